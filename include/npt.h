@@ -1,0 +1,232 @@
+/*
+ * npt.h -- C ABI of libnpt, an MI355X (gfx950) neural path tracer after
+ * "Towards Neural Path Tracing in SRAM" (Pupilli, 2023).
+ *
+ * Conventions (all calls):
+ *   - Every call returns an int status: NPT_OK (0) or a negative NPT_E_* code.
+ *     Nothing throws across the ABI.  npt_last_error() returns a message owned
+ *     by the context, valid until the next call on that context.
+ *   - Host input arrays are copied during the call; the caller keeps ownership.
+ *   - Device output buffers are caller-owned (e.g. the data pointer of a
+ *     torch.cuda tensor).  `stream` is a hipStream_t (NULL = the null stream);
+ *     calls that take a stream only enqueue work on it and return; the caller
+ *     synchronises before reading outputs.  Calls without a stream are
+ *     synchronous.
+ *   - One context per host thread; a context owns all of its device scratch.
+ *   - A failed call leaves the context usable (its previous state intact).
+ */
+#ifndef NPT_H
+#define NPT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define NPT_OK 0
+#define NPT_E_INVALID_ARG (-1) /* bad pointer, size, enum or overflow          */
+#define NPT_E_NO_SCENE (-2)    /* render / BVH build before geometry           */
+#define NPT_E_NO_ENV (-3)      /* render before env map or NIF weights         */
+#define NPT_E_OOM (-4)         /* host or device allocation failed             */
+#define NPT_E_HIP (-5)         /* HIP runtime error                            */
+#define NPT_E_UNSUPPORTED (-6) /* e.g. FP8 on a device without gfx950 FP8 MFMA */
+#define NPT_E_NAN_INPUT (-7)   /* NaN or Inf in uploaded floats                */
+#define NPT_E_NO_DEVICE (-8)   /* no usable GPU (host-only context)           */
+#define NPT_E_STATE (-9)       /* call order, e.g. render before npt_build_bvh */
+
+/* ---- enums --------------------------------------------------------------- */
+enum { NPT_LAMBERT = 0, NPT_MIRROR = 1, NPT_DIELECTRIC = 2, NPT_EMITTER = 3 };
+enum { NPT_ENV_MAP = 0, NPT_ENV_NIF = 1 };
+enum { NPT_FP32 = 0, NPT_FP16 = 1, NPT_BF16 = 2, NPT_FP8 = 3 };
+
+typedef struct npt_ctx npt_ctx;
+
+/* Surface material (Sec. 3.1: diffuse, mirror and dielectric surfaces; the
+ * paper adds emission only when a path hits an emitter by chance).
+ * type: NPT_*; albedo: Lambertian reflectance or mirror tint (dielectrics
+ * ignore it); emission: radiance emitted from the front face (the side the
+ * triangle's counter-clockwise normal points to, the outside of a sphere);
+ * ior: dielectric index of refraction (outside medium has index 1).
+ * NPT_EMITTER emits and ends the path. */
+typedef struct {
+    uint32_t type;
+    float albedo[3];
+    float emission[3];
+    float ior;
+} npt_material;
+
+/* Instance of an object-space mesh (blas_id from npt_scene_blas_triangles):
+ * world = translate + scale * object.  Uniform scale > 0 only. */
+typedef struct {
+    uint32_t blas_id;
+    float translate[3];
+    float scale;
+} npt_instance;
+
+/* Pinhole camera; vfov_deg is the full vertical field of view. */
+typedef struct {
+    float eye[3];
+    float look_at[3];
+    float up[3];
+    float vfov_deg;
+} npt_camera;
+
+/* Host BVH build (Sec. 3.1.4 builds a BVH2 on the host).  bins: SAH bins per
+ * axis (4..256, 0 = 32); max_leaf: primitives per leaf (1..8, 0 = 4);
+ * lds_levels: top tree levels staged in LDS by the traversal kernel (0..8,
+ * 0 = none). */
+typedef struct {
+    uint32_t bins;
+    uint32_t max_leaf;
+    uint32_t lds_levels;
+} npt_bvh_params;
+
+/* HDR-NIF shape (Sec. 3.2): 4*n_freq Fourier features -> layers x
+ * [dense hidden + ReLU] -> dense 3 (YUV) -> fixed YUV->RGB matrix.
+ * Supported: n_freq = 16, hidden = 96, layers = 5. */
+typedef struct {
+    uint32_t n_freq;
+    uint32_t hidden;
+    uint32_t layers;
+} npt_nif_desc;
+
+/* NIF training (Sec. 3.2.1): uniform (u,v) samples of the uploaded map,
+ * targets log1p(bilinear), Huber loss, Adam with FP32 master weights.
+ * grad_prec: NPT_FP32 / NPT_FP16 / NPT_BF16 operands of the GEMMs (FP32
+ * accumulation).  Zero fields take the defaults in brackets:
+ * batch [65536; a multiple of 2048], samples [2^24], lr [1e-3], beta1 [0.9], beta2 [0.999],
+ * eps [1e-7], huber_delta [1e-3], loss_scale [1024]. */
+typedef struct {
+    uint32_t batch;
+    uint64_t samples;
+    float lr, beta1, beta2, eps, huber_delta;
+    uint64_t seed;
+    uint32_t grad_prec;
+    float loss_scale;
+} npt_train_params;
+
+typedef struct {
+    uint32_t steps;      /* optimiser steps taken                    */
+    uint32_t step_total; /* Adam step counter after the call         */
+    float first_loss;    /* mean Huber loss of the first batch       */
+    float last_loss;     /* mean Huber loss of the last batch        */
+    float ms;            /* device time of the call                  */
+} npt_train_stats;
+
+/* Render options.  rr_start: first depth with Russian roulette (Sec. 4: 3);
+ * samples_per_pass: samples traced together (0 = library default, sized
+ * from the pool); pool_paths: upper bound on paths in flight (0 = 2^23). */
+typedef struct {
+    uint32_t rr_start;
+    uint32_t samples_per_pass;
+    uint32_t pool_paths;
+} npt_render_options;
+
+#define NPT_MAX_DEPTH 64
+
+/* Counters of the last render (read back synchronously by npt_get_stats). */
+typedef struct {
+    uint64_t paths;                      /* W*H*spp                               */
+    uint64_t rays[NPT_MAX_DEPTH];        /* rays traced at depth k (index k-1)    */
+    uint64_t escaped[NPT_MAX_DEPTH];     /* rays lit by the environment at depth k */
+    uint64_t env_queries;                /* total environment lookups / NIF queries */
+    uint32_t passes;
+    uint32_t samples_per_pass;
+    float ms_total;                      /* device time of the last render         */
+} npt_stats;
+
+/* ---- context ------------------------------------------------------------- */
+/* device >= 0: HIP device index.  device = -1: host-only context (scene and
+ * BVH calls work, anything needing a GPU returns NPT_E_NO_DEVICE). */
+int npt_create(npt_ctx **out, int device);
+int npt_destroy(npt_ctx *ctx);
+const char *npt_last_error(npt_ctx *ctx);
+
+/* ---- scene (Sec. 3.1.1 scene data; Fig. 1 scenes) -------------------------- */
+/* Base (instance 0) triangles: xyz [nv][3] FP32, tri [nt][3] vertex indices,
+ * mat_of_tri [nt] material ids (NULL = all 0).  Primitive ids 0..nt-1.
+ * Replaces any previous base triangles.  NPT_E_NAN_INPUT on NaN/Inf;
+ * NPT_E_INVALID_ARG on out-of-range indices. */
+int npt_scene_triangles(npt_ctx *ctx, const float *xyz, uint64_t nv, const uint32_t *tri,
+                        uint64_t nt, const uint32_t *mat_of_tri);
+/* Base spheres: cxyzr [n][4] (centre, radius > 0), mat [n] (NULL = 0).
+ * Primitive ids nt..nt+n-1 after the base triangles. */
+int npt_scene_spheres(npt_ctx *ctx, const float *cxyzr, uint64_t n, const uint32_t *mat);
+/* Object-space mesh for instancing; blas_id must be 0, 1, ... in order (or
+ * an existing id to replace it). */
+int npt_scene_blas_triangles(npt_ctx *ctx, uint32_t blas_id, const float *xyz, uint64_t nv,
+                             const uint32_t *tri, uint64_t nt, const uint32_t *mat_of_tri);
+/* Instances k = 0..n-1 get instance id k+1 (the base geometry is 0). */
+int npt_scene_instances(npt_ctx *ctx, const npt_instance *inst, uint32_t n);
+int npt_scene_materials(npt_ctx *ctx, const npt_material *m, uint32_t n);
+/* Builds the BVH(s) on the host (binned SAH), flattens them and uploads on
+ * `stream`.  NPT_E_NO_SCENE if no geometry; NPT_E_NO_DEVICE only for the
+ * upload on a host-only context (the host build still happens). */
+int npt_build_bvh(npt_ctx *ctx, const npt_bvh_params *p, void *stream);
+/* Host-side BVH summary for tests: nodes, leaves, max depth, prim slots. */
+int npt_bvh_info(npt_ctx *ctx, uint64_t *nodes, uint64_t *leaves, uint32_t *max_depth,
+                 uint64_t *prim_slots);
+int npt_set_camera(npt_ctx *ctx, const npt_camera *cam);
+int npt_set_render_options(npt_ctx *ctx, const npt_render_options *opt);
+
+/* ---- environment (Sec. 3.3) ------------------------------------------------ */
+/* Equirectangular FP32 RGB map rgb [h][w][3] (row j = polar angle, column i
+ * = azimuth, texel centres at half-integers).  Kept on the device for lookup
+ * and training.  NPT_E_NAN_INPUT on NaN/Inf or negative radiance. */
+int npt_env_upload(npt_ctx *ctx, const float *rgb, uint32_t w, uint32_t h, void *stream);
+/* NPT_ENV_MAP: bilinear lookup; NPT_ENV_NIF: the HDR-NIF. */
+int npt_set_env_mode(npt_ctx *ctx, int mode);
+
+/* ---- HDR-NIF (Sec. 3.2) ----------------------------------------------------- */
+/* params_fp32: [W1, b1, ..., W6, b6], W row-major [out][in], n values
+ * (43,779 for 16/96/5).  Becomes the FP32 master copy; Adam state is reset;
+ * the inference pack of the current precision is rebuilt. */
+int npt_nif_upload(npt_ctx *ctx, const npt_nif_desc *desc, const float *params_fp32,
+                   uint64_t n, void *stream);
+/* Copies the FP32 master parameters to host memory (synchronous). */
+int npt_nif_download(npt_ctx *ctx, float *params_fp32, uint64_t n);
+/* Inference precision NPT_FP32 / FP16 / BF16 / FP8 (OCP E4M3 weights and
+ * activations with power-of-two scales).  Packs the weights. */
+int npt_nif_set_precision(npt_ctx *ctx, int prec);
+/* Copies the dequantised inference weights (the values the MFMA kernel
+ * multiplies, in the npt_nif_upload order) to host memory. */
+int npt_nif_get_dequantized(npt_ctx *ctx, float *params, uint64_t n);
+/* Trains in place on the uploaded env map (Sec. 3.2.1). */
+int npt_nif_train(npt_ctx *ctx, const npt_train_params *p, npt_train_stats *out, void *stream);
+/* Loss and gradient of training step `step`'s batch at the current weights,
+ * without updating them: d_grad [n params] FP32 device, d_loss [1] FP32
+ * device (caller-owned). */
+int npt_nif_train_grad(npt_ctx *ctx, const npt_train_params *p, uint32_t step, float *d_grad,
+                       float *d_loss, void *stream);
+/* Evaluates the NIF at the centres of a gw x gh (u,v) grid against the
+ * bilinear map: out[0] = mean log-radiance MSE (log1p domain), out[1] =
+ * RGB PSNR in the log domain (peak = max log1p of the map).  Synchronous. */
+int npt_nif_eval_grid(npt_ctx *ctx, uint32_t gw, uint32_t gh, float *out2, void *stream);
+/* NIF radiance (or bilinear map if mode == NPT_ENV_MAP) for n world
+ * directions d_dirs [n][3] FP32 device -> d_rgb [n][3] FP32 device. */
+int npt_env_query(npt_ctx *ctx, int mode, const float *d_dirs, uint64_t n, float *d_rgb,
+                  void *stream);
+
+/* ---- rendering (Sec. 3.1, 3.3, 4) --------------------------------------------- */
+/* Monte-Carlo path tracing: W*H pixels, spp samples, paths of at most
+ * max_depth segments (1..64), Philox seed.  d_radiance: [H][W][3] FP32
+ * device, caller-owned, overwritten with the per-pixel mean.
+ * NPT_E_INVALID_ARG: W*H*spp overflows 2^40, zero sizes, max_depth 0 or > 64.
+ * NPT_E_NO_SCENE / NPT_E_STATE: no geometry / BVH not built.
+ * NPT_E_NO_ENV: environment mode without a map or NIF weights. */
+int npt_render(npt_ctx *ctx, uint32_t width, uint32_t height, uint32_t spp, uint32_t max_depth,
+               uint64_t seed, float *d_radiance, void *stream);
+/* Primary hits of sample `sample` (Table 3-style checks): d_prim / d_inst
+ * [H*W] u32 (0xFFFFFFFF on miss), d_t [H*W] FP32 (+inf on miss), d_normal
+ * [H*W][3] geometric normal (0 on miss).  Any output may be NULL. */
+int npt_trace_primary(npt_ctx *ctx, uint32_t width, uint32_t height, uint32_t sample,
+                      uint64_t seed, uint32_t *d_prim, uint32_t *d_inst, float *d_t,
+                      float *d_normal, void *stream);
+int npt_get_stats(npt_ctx *ctx, npt_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,38 @@
+// bvh_build.h -- host BVH2 construction (Sec. 3.1.4: a BVH2 built on the
+// host and compacted into pointer-less nodes) for the GPU traversal.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace npt {
+
+struct BuildInput {
+  const float* verts = nullptr;   // [nv][3]
+  uint64_t nv = 0;
+  const uint32_t* tris = nullptr; // [nt][3]
+  uint64_t nt = 0;
+  const uint32_t* tri_mat = nullptr;
+  const float* spheres = nullptr; // [ns][4]
+  uint64_t ns = 0;
+  const uint32_t* sph_mat = nullptr;
+};
+
+struct FlatBvh {
+  std::vector<float4> nodes;  // 4 float4 per node (npt_shared.h layout)
+  std::vector<float4> slots;  // 3 float4 per primitive slot
+  uint32_t lds_nodes = 0;     // BFS-ordered top nodes staged in LDS
+  uint32_t max_depth = 0;     // deepest inner node (root = 0)
+  uint64_t leaves = 0;
+  float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};  // bounds of all primitives
+};
+
+// Binned-SAH build (bins per axis, primitives per leaf <= max_leaf), then
+// flattening: the inner nodes of the top lds_levels levels first in BFS
+// order, the rest depth-first.  Returns false with a message on failure.
+bool build_bvh(const BuildInput& in, uint32_t bins, uint32_t max_leaf, uint32_t lds_levels, FlatBvh& out,
+               std::string& err);
+
+}  // namespace npt

@@ -1,0 +1,470 @@
+// k_render.hip -- wavefront path-tracing kernels (Sec. 3.1, 3.3 of the paper):
+// camera rays, closest-hit traversal + shading with wave-level queue
+// compaction, bilinear environment lookup, per-pixel accumulation.
+#include <hip/hip_runtime.h>
+
+#include "npt_device.h"
+#include "npt_kernels.h"
+#include "npt_shared.h"
+#include "npt_train.h"
+
+namespace npt {
+
+constexpr int kTraceBlock = 128;
+constexpr int kWave = 64;
+constexpr uint32_t kMaxVisits = 1u << 22;
+
+// ---------------------------------------------------------------------------
+// wave-level compaction: one atomic per wave, ballot + mbcnt for the offsets
+// (all 64 lanes must call it)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t wave_append(bool pred, uint32_t* counter) {
+  const uint64_t mask = __ballot(pred);
+  const uint32_t lane_prefix =
+      __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+  uint32_t base = 0;
+  if (mask != 0) {
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    uint32_t b = 0;
+    if ((int)(threadIdx.x & (kWave - 1)) == leader) b = atomicAdd(counter, (uint32_t)__popcll(mask));
+    base = __shfl(b, leader);
+  }
+  return base + lane_prefix;
+}
+
+// ---------------------------------------------------------------------------
+// camera (pinhole) -- same definitions as the host-side basis
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ V3 camera_direction(const CameraView& cam, uint32_t W, uint32_t H,
+                                               uint32_t x, uint32_t y, float jx, float jy) {
+  const float px = ((float)x + jx) / (float)W;
+  const float py = ((float)y + jy) / (float)H;
+  const float sx = 2.0f * px - 1.0f;
+  const float sy = 1.0f - 2.0f * py;
+  const float cx = sx * cam.tan_x;
+  const float cy = sy * cam.tan_y;
+  const V3 d{(cam.fwd[0] + cx * cam.right[0]) + cy * cam.up[0],
+             (cam.fwd[1] + cx * cam.right[1]) + cy * cam.up[1],
+             (cam.fwd[2] + cx * cam.right[2]) + cy * cam.up[2]};
+  return normalized(d);
+}
+
+// ---------------------------------------------------------------------------
+// closest hit: stack traversal of the two-box BVH2; the top `lds_nodes`
+// nodes come from LDS.  Ties on t go to the lowest primitive id.
+// ---------------------------------------------------------------------------
+struct Hit {
+  float t;
+  uint32_t slot;
+  uint32_t prim;
+};
+
+__device__ __forceinline__ void slab2(const float4& n0, const float4& n1, const float4& n2,
+                                      float ix, float iy, float iz, float ox, float oy, float oz,
+                                      float lim, float& lo0, float& hi0, float& lo1, float& hi1) {
+  const float a0 = __builtin_fmaf(n0.x, ix, -ox), a1 = __builtin_fmaf(n0.y, ix, -ox);
+  const float b0 = __builtin_fmaf(n0.z, iy, -oy), b1 = __builtin_fmaf(n0.w, iy, -oy);
+  const float c0 = __builtin_fmaf(n2.x, iz, -oz), c1 = __builtin_fmaf(n2.y, iz, -oz);
+  lo0 = fmaxf(fmaxf(fminf(a0, a1), fminf(b0, b1)), fmaxf(fminf(c0, c1), 0.0f));
+  hi0 = fminf(fminf(fmaxf(a0, a1), fmaxf(b0, b1)), fminf(fmaxf(c0, c1), lim));
+  const float d0 = __builtin_fmaf(n1.x, ix, -ox), d1 = __builtin_fmaf(n1.y, ix, -ox);
+  const float e0 = __builtin_fmaf(n1.z, iy, -oy), e1 = __builtin_fmaf(n1.w, iy, -oy);
+  const float f0 = __builtin_fmaf(n2.z, iz, -oz), f1 = __builtin_fmaf(n2.w, iz, -oz);
+  lo1 = fmaxf(fmaxf(fminf(d0, d1), fminf(e0, e1)), fmaxf(fminf(f0, f1), 0.0f));
+  hi1 = fminf(fminf(fmaxf(d0, d1), fmaxf(e0, e1)), fminf(fmaxf(f0, f1), lim));
+}
+
+__device__ __forceinline__ float safe_inverse(float x) {
+  return 1.0f / (fabsf(x) > 1e-20f ? x : copysignf(1e-20f, x));
+}
+
+template <int kStack>
+__device__ __forceinline__ Hit closest_hit(const SceneView& sc, const float4* lds_nodes,
+                                           uint32_t* stack, V3 o, V3 d) {
+  Hit h{__builtin_inff(), kMiss, kMiss};
+  if (!sc.has_geometry) return h;
+  const Shear sh = make_shear(d);
+  const float ix = safe_inverse(d.x), iy = safe_inverse(d.y), iz = safe_inverse(d.z);
+  const float ox = o.x * ix, oy = o.y * iy, oz = o.z * iz;
+  uint32_t ref = 0;
+  int sp = 0;
+  // a bound every traversal reaches: a well-formed tree visits each node at
+  // most once per ray, so this only guards against a malformed upload
+  for (uint32_t visits = 0; visits < kMaxVisits; ++visits) {
+    if ((ref & kLeafBit) == 0u) {
+      float4 n0, n1, n2, n3;
+      if (ref < sc.lds_nodes) {
+        const float4* p = lds_nodes + 4 * ref;
+        n0 = p[0]; n1 = p[1]; n2 = p[2]; n3 = p[3];
+      } else {
+        const float4* p = sc.nodes + 4 * (size_t)ref;
+        n0 = p[0]; n1 = p[1]; n2 = p[2]; n3 = p[3];
+      }
+      float lo0, hi0, lo1, hi1;
+      slab2(n0, n1, n2, ix, iy, iz, ox, oy, oz, h.t * 1.000001f, lo0, hi0, lo1, hi1);
+      const bool h0 = lo0 <= hi0, h1 = lo1 <= hi1;
+      const uint32_t r0 = __float_as_uint(n3.x), r1 = __float_as_uint(n3.y);
+      if (h0 && h1) {
+        const bool near0 = lo0 <= lo1;
+        if (sp < kStack) {
+          stack[sp * kTraceBlock] = near0 ? r1 : r0;
+          ++sp;
+        }
+        ref = near0 ? r0 : r1;
+        continue;
+      }
+      if (h0) { ref = r0; continue; }
+      if (h1) { ref = r1; continue; }
+    } else {
+      const uint32_t first = (ref >> 3) & 0x0FFFFFFFu;
+      const uint32_t count = (ref & 7u) + 1u;
+      for (uint32_t i = 0; i < count; ++i) {
+        const float4* s = sc.slots + 3 * (size_t)(first + i);
+        const float4 s0 = s[0], s1 = s[1], s2 = s[2];
+        const uint32_t prim = __float_as_uint(s0.w);
+        float t = 0.0f;
+        bool hit;
+        if (__float_as_uint(s2.w) == kPrimTriangle)
+          hit = hit_triangle(o, sh, V3{s0.x, s0.y, s0.z}, V3{s1.x, s1.y, s1.z}, V3{s2.x, s2.y, s2.z}, h.t, t);
+        else
+          hit = hit_sphere(o, d, V3{s0.x, s0.y, s0.z}, s1.x, h.t, t);
+        if (hit && (t < h.t || prim < h.prim)) {
+          h.t = t;
+          h.slot = first + i;
+          h.prim = prim;
+        }
+      }
+    }
+    if (sp == 0) break;
+    --sp;
+    ref = stack[sp * kTraceBlock];
+  }
+  return h;
+}
+
+// geometric normal of a hit slot (unit for triangles; (p - c) / r for spheres)
+__device__ __forceinline__ V3 slot_normal(const float4* slots, uint32_t slot, V3 p, uint32_t& material) {
+  const float4* s = slots + 3 * (size_t)slot;
+  const float4 s0 = s[0], s1 = s[1], s2 = s[2];
+  material = __float_as_uint(s1.w);
+  if (__float_as_uint(s2.w) == kPrimTriangle) {
+    const V3 p0{s0.x, s0.y, s0.z};
+    return normalized(cross(sub(V3{s1.x, s1.y, s1.z}, p0), sub(V3{s2.x, s2.y, s2.z}, p0)));
+  }
+  return V3{(p.x - s0.x) / s1.x, (p.y - s0.y) / s1.x, (p.z - s0.z) / s1.x};
+}
+
+__device__ __forceinline__ void stage_lds_nodes(const SceneView& sc, float4* lds) {
+  for (uint32_t i = threadIdx.x; i < 4 * sc.lds_nodes; i += blockDim.x) lds[i] = sc.nodes[i];
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// generate: one camera ray per path slot of the pass
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_generate(CameraView cam, PassView pv, RayQueue q, float4* L) {
+  const uint32_t n = pv.pixels * pv.samples;
+  for (uint32_t slot = blockIdx.x * blockDim.x + threadIdx.x; slot < n; slot += gridDim.x * blockDim.x) {
+    const uint32_t pixel = slot % pv.pixels;
+    const uint32_t sample = pv.sample0 + slot / pv.pixels;
+    const uint32_t x = pixel % pv.width, y = pixel / pv.width;
+    const U4 r = philox(pixel, sample, 0, kRngCamera, pv.key0, pv.key1);
+    const V3 d = camera_direction(cam, pv.width, pv.height, x, y, unit_float(r.x), unit_float(r.y));
+    q.o[slot] = make_float4(cam.eye[0], cam.eye[1], cam.eye[2], __uint_as_float(pixel));
+    q.d[slot] = make_float4(d.x, d.y, d.z, __uint_as_float(sample));
+    q.b[slot] = make_float4(1.0f, 1.0f, 1.0f, 0.0f);
+    L[slot] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  }
+}
+
+__global__ void k_pass_init(uint32_t* cnt, uint32_t paths) {
+  for (int i = threadIdx.x; i < kCntWords; i += blockDim.x) cnt[i] = 0;
+  __syncthreads();
+  if (threadIdx.x == 0) cnt[kCntRays + 1] = paths;
+}
+
+// ---------------------------------------------------------------------------
+// trace: closest hit + shading of every ray entering depth `depth`.
+// Escaped rays go to the environment queue; survivors to the next queue.
+// ---------------------------------------------------------------------------
+template <int kStack>
+__global__ __launch_bounds__(kTraceBlock) void k_trace(SceneView sc, PassView pv, uint32_t depth,
+                                                       RayQueue in, RayQueue out, EnvQueue env,
+                                                       float4* L, uint32_t* cnt) {
+  extern __shared__ float4 lds_nodes[];
+  __shared__ uint32_t stack_mem[kStack * kTraceBlock];
+  stage_lds_nodes(sc, lds_nodes);
+  uint32_t* stack = stack_mem + threadIdx.x;
+  const uint32_t n = cnt[kCntRays + depth];
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  for (;;) {
+    uint32_t chunk = 0;
+    if (lane == 0) chunk = atomicAdd(&cnt[kCntWork + depth], 1u);
+    chunk = __shfl(chunk, 0);
+    const uint32_t i = chunk * kWave + lane;
+    if (chunk * kWave >= n) break;
+    const bool valid = i < n;
+    V3 o{0, 0, 0}, d{0, 0, 1}, beta{0, 0, 0};
+    uint32_t pixel = 0, sample = 0;
+    if (valid) {
+      const float4 qo = in.o[i], qd = in.d[i], qb = in.b[i];
+      o = V3{qo.x, qo.y, qo.z};
+      d = V3{qd.x, qd.y, qd.z};
+      beta = V3{qb.x, qb.y, qb.z};
+      pixel = __float_as_uint(qo.w);
+      sample = __float_as_uint(qd.w);
+    }
+    const uint32_t slot = (sample - pv.sample0) * pv.pixels + pixel;
+    Hit h{__builtin_inff(), kMiss, kMiss};
+    if (valid) h = closest_hit<kStack>(sc, lds_nodes, stack, o, d);
+    const bool escaped = valid && h.slot == kMiss;
+    bool alive = false;
+    V3 no{0, 0, 0}, nd{0, 0, 1};
+    if (valid && !escaped) {
+      const V3 p{o.x + h.t * d.x, o.y + h.t * d.y, o.z + h.t * d.z};
+      uint32_t mat;
+      const V3 n = slot_normal(sc.slots, h.slot, p, mat);
+      const float4 m0 = sc.materials[2 * mat], m1 = sc.materials[2 * mat + 1];
+      const float dn = dot(d, n);
+      if (dn < 0.0f && (m1.x != 0.0f || m1.y != 0.0f || m1.z != 0.0f)) {
+        float4 l = L[slot];
+        l.x += beta.x * m1.x;
+        l.y += beta.y * m1.y;
+        l.z += beta.z * m1.z;
+        L[slot] = l;
+      }
+      const uint32_t mtype = __float_as_uint(m0.w);
+      alive = !(depth == pv.max_depth || mtype == kEmitter);
+      if (alive) {
+        const U4 r = philox(pixel, sample, depth, kRngScatter, pv.key0, pv.key1);
+        if (mtype == kLambert) {
+          const V3 nf = dn > 0.0f ? neg(n) : n;
+          nd = sample_cosine(nf, unit_float(r.x), unit_float(r.y));
+          beta = V3{beta.x * m0.x, beta.y * m0.y, beta.z * m0.z};
+        } else if (mtype == kMirror) {
+          const float k2 = 2.0f * dn;
+          nd = V3{d.x - k2 * n.x, d.y - k2 * n.y, d.z - k2 * n.z};
+          beta = V3{beta.x * m0.x, beta.y * m0.y, beta.z * m0.z};
+        } else {
+          nd = sample_dielectric(d, n, m1.w, unit_float(r.z));
+        }
+        if (depth >= pv.rr_start) {
+          const float q = fminf(1.0f, fmaxf(fmaxf(beta.x, beta.y), beta.z));
+          if (unit_float(r.w) >= q) {
+            alive = false;
+          } else {
+            beta = V3{beta.x / q, beta.y / q, beta.z / q};
+          }
+        }
+        if (alive) {
+          const float sd = dot(nd, n);
+          no = offset_origin(p, sd > 0.0f ? n : neg(n));
+        }
+      }
+    }
+    const uint32_t ei = wave_append(escaped, &cnt[kCntEnv + depth]);
+    if (escaped) {
+      env.d[ei] = make_float4(d.x, d.y, d.z, __uint_as_float(slot));
+      env.b[ei] = make_float4(beta.x, beta.y, beta.z, 0.0f);
+    }
+    const uint32_t oi = wave_append(alive, &cnt[kCntRays + depth + 1]);
+    if (alive) {
+      out.o[oi] = make_float4(no.x, no.y, no.z, __uint_as_float(pixel));
+      out.d[oi] = make_float4(nd.x, nd.y, nd.z, __uint_as_float(sample));
+      out.b[oi] = make_float4(beta.x, beta.y, beta.z, 0.0f);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// environment: bilinear lookup of the equirect map
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_env_lookup(const float4* map, int W, int H, EnvQueue env,
+                                                    float4* L, const uint32_t* cnt, uint32_t depth) {
+  const uint32_t n = cnt[kCntEnv + depth];
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const float4 ed = env.d[i], eb = env.b[i];
+    float u, v;
+    direction_to_uv(V3{ed.x, ed.y, ed.z}, u, v);
+    const float3 c = env_bilinear(map, W, H, u, v);
+    const uint32_t slot = __float_as_uint(ed.w);
+    float4 l = L[slot];
+    l.x += eb.x * c.x;
+    l.y += eb.y * c.y;
+    l.z += eb.z * c.z;
+    L[slot] = l;
+  }
+}
+
+// direct queries (npt_env_query): dirs [n][3] -> rgb [n][3]
+__global__ __launch_bounds__(256) void k_env_query_map(const float4* map, int W, int H, const float* dirs,
+                                                       uint64_t n, float* rgb) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    float u, v;
+    direction_to_uv(V3{dirs[3 * i], dirs[3 * i + 1], dirs[3 * i + 2]}, u, v);
+    const float3 c = env_bilinear(map, W, H, u, v);
+    rgb[3 * i] = c.x;
+    rgb[3 * i + 1] = c.y;
+    rgb[3 * i + 2] = c.z;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// accumulate the pass's samples per pixel in sample order, then finalize
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_accumulate(const float4* L, float4* accum, PassView pv, int first_pass) {
+  for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < pv.pixels; p += gridDim.x * blockDim.x) {
+    float4 a = first_pass ? make_float4(0, 0, 0, 0) : accum[p];
+    for (uint32_t s = 0; s < pv.samples; ++s) {
+      const float4 l = L[(size_t)s * pv.pixels + p];
+      a.x += l.x;
+      a.y += l.y;
+      a.z += l.z;
+    }
+    accum[p] = a;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_finalize(const float4* accum, float* out, uint32_t pixels, float inv_spp) {
+  for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < pixels; p += gridDim.x * blockDim.x) {
+    const float4 a = accum[p];
+    out[3 * (size_t)p] = a.x * inv_spp;
+    out[3 * (size_t)p + 1] = a.y * inv_spp;
+    out[3 * (size_t)p + 2] = a.z * inv_spp;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// primary hits (Table 3-style checks)
+// ---------------------------------------------------------------------------
+template <int kStack>
+__global__ __launch_bounds__(kTraceBlock) void k_trace_primary(SceneView sc, CameraView cam, PassView pv,
+                                                               uint32_t* prim, uint32_t* inst, float* tout,
+                                                               float* normal) {
+  extern __shared__ float4 lds_nodes[];
+  __shared__ uint32_t stack_mem[kStack * kTraceBlock];
+  stage_lds_nodes(sc, lds_nodes);
+  uint32_t* stack = stack_mem + threadIdx.x;
+  const uint32_t nblocks = (pv.pixels + kTraceBlock - 1) / kTraceBlock;
+  for (uint32_t b = blockIdx.x; b < nblocks; b += gridDim.x) {
+    const uint32_t pixel = b * kTraceBlock + threadIdx.x;
+    if (pixel >= pv.pixels) continue;
+    const uint32_t x = pixel % pv.width, y = pixel / pv.width;
+    const U4 r = philox(pixel, pv.sample0, 0, kRngCamera, pv.key0, pv.key1);
+    const V3 d = camera_direction(cam, pv.width, pv.height, x, y, unit_float(r.x), unit_float(r.y));
+    const V3 o{cam.eye[0], cam.eye[1], cam.eye[2]};
+    const Hit h = closest_hit<kStack>(sc, lds_nodes, stack, o, d);
+    V3 n{0, 0, 0};
+    if (h.slot != kMiss) {
+      uint32_t mat;
+      n = slot_normal(sc.slots, h.slot, V3{o.x + h.t * d.x, o.y + h.t * d.y, o.z + h.t * d.z}, mat);
+    }
+    if (prim) prim[pixel] = h.slot == kMiss ? kMiss : h.prim;
+    if (inst) inst[pixel] = h.slot == kMiss ? kMiss : 0u;
+    if (tout) tout[pixel] = h.t;
+    if (normal) {
+      normal[3 * (size_t)pixel] = n.x;
+      normal[3 * (size_t)pixel + 1] = n.y;
+      normal[3 * (size_t)pixel + 2] = n.z;
+    }
+  }
+}
+
+// per-depth counters summed over passes (npt_get_stats)
+__global__ void k_stats_clear(unsigned long long* st) {
+  for (int i = threadIdx.x; i < 2 * 64; i += blockDim.x) st[i] = 0ull;
+}
+
+__global__ void k_stats_add(const uint32_t* cnt, unsigned long long* st) {
+  const int k = threadIdx.x;
+  if (k < 64) {
+    st[k] += cnt[kCntRays + k + 1];
+    st[64 + k] += cnt[kCntEnv + k + 1];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_stats_clear(unsigned long long* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_stats_clear, dim3(1), dim3(128), 0, s, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_stats_add(const uint32_t* cnt, unsigned long long* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_stats_add, dim3(1), dim3(64), 0, s, cnt, st);
+  return hipGetLastError();
+}
+
+static int grid_for(uint64_t n, int block, int cap) {
+  const uint64_t g = (n + block - 1) / block;
+  return (int)(g < 1 ? 1 : (g > (uint64_t)cap ? cap : g));
+}
+
+hipError_t launch_pass_init(uint32_t* cnt, uint32_t paths, hipStream_t s) {
+  hipLaunchKernelGGL(k_pass_init, dim3(1), dim3(256), 0, s, cnt, paths);
+  return hipGetLastError();
+}
+
+hipError_t launch_generate(const CameraView& cam, const PassView& pv, const RayQueue& q, float4* L,
+                           hipStream_t s) {
+  const uint64_t n = (uint64_t)pv.pixels * pv.samples;
+  hipLaunchKernelGGL(k_generate, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, cam, pv, q, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_trace(int stack_depth, const SceneView& sc, const PassView& pv, uint32_t depth,
+                        uint64_t max_rays, const RayQueue& in, const RayQueue& out, const EnvQueue& env,
+                        float4* L, uint32_t* cnt, int num_cus, hipStream_t s) {
+  const size_t lds = (size_t)sc.lds_nodes * 4 * sizeof(float4);
+  const int grid = grid_for(max_rays, kTraceBlock, num_cus * 16);
+  if (stack_depth <= 32) {
+    hipLaunchKernelGGL(k_trace<32>, dim3(grid), dim3(kTraceBlock), lds, s, sc, pv, depth, in, out, env, L, cnt);
+  } else {
+    hipLaunchKernelGGL(k_trace<64>, dim3(grid), dim3(kTraceBlock), lds, s, sc, pv, depth, in, out, env, L, cnt);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_env_lookup(const float4* map, int W, int H, const EnvQueue& env, float4* L,
+                             const uint32_t* cnt, uint32_t depth, uint64_t max_rays, int num_cus,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_env_lookup, dim3(grid_for(max_rays, 256, num_cus * 8)), dim3(256), 0, s, map, W, H,
+                     env, L, cnt, depth);
+  return hipGetLastError();
+}
+
+hipError_t launch_env_query_map(const float4* map, int W, int H, const float* dirs, uint64_t n, float* rgb,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_env_query_map, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, map, W, H, dirs, n, rgb);
+  return hipGetLastError();
+}
+
+hipError_t launch_accumulate(const float4* L, float4* accum, const PassView& pv, int first_pass, hipStream_t s) {
+  hipLaunchKernelGGL(k_accumulate, dim3(grid_for(pv.pixels, 256, 65536)), dim3(256), 0, s, L, accum, pv,
+                     first_pass);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const float4* accum, float* out, uint32_t pixels, float inv_spp, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(grid_for(pixels, 256, 65536)), dim3(256), 0, s, accum, out, pixels,
+                     inv_spp);
+  return hipGetLastError();
+}
+
+hipError_t launch_trace_primary(int stack_depth, const SceneView& sc, const CameraView& cam, const PassView& pv,
+                                uint32_t* prim, uint32_t* inst, float* t, float* normal, int num_cus,
+                                hipStream_t s) {
+  const size_t lds = (size_t)sc.lds_nodes * 4 * sizeof(float4);
+  const int grid = grid_for(pv.pixels, kTraceBlock, num_cus * 16);
+  if (stack_depth <= 32) {
+    hipLaunchKernelGGL(k_trace_primary<32>, dim3(grid), dim3(kTraceBlock), lds, s, sc, cam, pv, prim, inst, t,
+                       normal);
+  } else {
+    hipLaunchKernelGGL(k_trace_primary<64>, dim3(grid), dim3(kTraceBlock), lds, s, sc, cam, pv, prim, inst, t,
+                       normal);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace npt

@@ -1,0 +1,514 @@
+// k_train.hip -- on-device HDR-NIF training (Sec. 3.2.1): samples, forward
+// and backward MFMA GEMMs, Huber head, split-K weight gradients reduced in a
+// fixed order (deterministic), Adam on FP32 master weights, grid evaluation.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+#include "npt.h"
+#include "npt_device.h"
+#include "npt_kernels.h"
+#include "npt_mfma.h"
+#include "npt_nif_layout.h"
+#include "npt_train.h"
+
+namespace npt {
+using namespace nif;
+
+constexpr int kChunk = 2048;  // batch rows per split-K chunk of the weight gradients
+
+// ---------------------------------------------------------------------------
+// samples: (u, v) uniform from the TRAIN Philox stream; features; targets
+// log1p(bilinear(map))
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(256) void k_train_sample(TrainTargets t, uint32_t key0, uint32_t key1, uint32_t step,
+                                                     uint32_t B, typename Prec<P>::Elem* X0, float* target) {
+  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < B; b += gridDim.x * blockDim.x) {
+    const U4 r = philox(b, step, 0, kRngTrain, key0, key1);
+    const float u = unit_float(r.x), v = unit_float(r.y);
+    typename Prec<P>::Elem* x = X0 + (size_t)b * kFeat;
+#pragma unroll
+    for (int k = 0; k < kFreq; ++k) {
+      const float f = (float)frequency(k);
+      const float xu = f * u, xv = f * v;
+      float su, cu, sv, cv;
+      sincos_turns(xu - floorf(xu), su, cu);
+      sincos_turns(xv - floorf(xv), sv, cv);
+      x[k] = Prec<P>::cvt(su);
+      x[kFreq + k] = Prec<P>::cvt(cu);
+      x[2 * kFreq + k] = Prec<P>::cvt(sv);
+      x[3 * kFreq + k] = Prec<P>::cvt(cv);
+    }
+    const float3 c = env_bilinear(t.map, (int)t.w, (int)t.h, u, v);
+    target[3 * (size_t)b] = log1pf(c.x);
+    target[3 * (size_t)b + 1] = log1pf(c.y);
+    target[3 * (size_t)b + 2] = log1pf(c.z);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// GEMM on MFMA, one wave per 32x32 output tile, operands straight from
+// global memory: C(m, n) = sum_k A(m, k) B(k, n), A(m,k) = A[m*a_sm + k*a_sk],
+// B(k,n) = B[k*b_sk + n*b_sn].  AK / BK: the operand is contiguous along k.
+// ---------------------------------------------------------------------------
+struct GemmDesc {
+  const void* A;
+  int64_t a_sm, a_sk;
+  const void* B;
+  int64_t b_sk, b_sn;
+  int M, N, K, k_chunk, splits;
+  int mode;             // 0: relu(acc + bias[n]) -> C;  1: mask(m,n) > 0 ? acc : 0 -> C;  2: FP32 partial
+  const float* bias;
+  const void* mask;
+  int64_t mask_ld;
+  void* C;
+  int64_t ldc, c_split_stride;
+};
+
+template <int P, bool AK, bool BK>
+__global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
+  using Elem = typename Prec<P>::Elem;
+  using Frag = typename Prec<P>::Frag;
+  constexpr int KPL = Prec<P>::KPL;
+  const int lane = threadIdx.x & 63;
+  const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int mt = g.M / 32, nt = g.N / 32;
+  if (wave >= mt * nt * g.splits) return;
+  const int split = wave / (mt * nt), rem = wave % (mt * nt);
+  const int m0 = (rem / nt) * 32, n0 = (rem % nt) * 32;
+  const int h = lane / 32, c = lane % 32;
+  const int kbeg = split * g.k_chunk, kend = min(g.K, kbeg + g.k_chunk);
+  const Elem* A = static_cast<const Elem*>(g.A);
+  const Elem* B = static_cast<const Elem*>(g.B);
+  f32x16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+  for (int k0 = kbeg; k0 < kend; k0 += 2 * KPL) {
+    const int kk = k0 + h * KPL;
+    Frag a, b;
+    if constexpr (KPL == 1) {
+      a = A[(int64_t)(m0 + c) * g.a_sm + (int64_t)kk * g.a_sk];
+      b = B[(int64_t)kk * g.b_sk + (int64_t)(n0 + c) * g.b_sn];
+    } else {
+      if constexpr (AK) {
+        a = *reinterpret_cast<const Frag*>(A + (int64_t)(m0 + c) * g.a_sm + kk);
+      } else {
+#pragma unroll
+        for (int e = 0; e < KPL; ++e) a[e] = A[(int64_t)(m0 + c) * g.a_sm + (int64_t)(kk + e) * g.a_sk];
+      }
+      if constexpr (BK) {
+        b = *reinterpret_cast<const Frag*>(B + (int64_t)(n0 + c) * g.b_sn + kk);
+      } else {
+#pragma unroll
+        for (int e = 0; e < KPL; ++e) b[e] = B[(int64_t)(kk + e) * g.b_sk + (int64_t)(n0 + c) * g.b_sn];
+      }
+    }
+    acc = Prec<P>::mma(a, b, acc);
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int m = m0 + acc_row(0, h, r), n = n0 + c;
+    float val = acc[r];
+    if (g.mode == 0) {
+      val = fmaxf(val + g.bias[n], 0.0f);
+      static_cast<Elem*>(g.C)[(int64_t)m * g.ldc + n] = Prec<P>::cvt(val);
+    } else if (g.mode == 1) {
+      const float mk = (float)static_cast<const Elem*>(g.mask)[(int64_t)m * g.mask_ld + n];
+      static_cast<Elem*>(g.C)[(int64_t)m * g.ldc + n] = Prec<P>::cvt(mk > 0.0f ? val : 0.0f);
+    } else {
+      static_cast<float*>(g.C)[(int64_t)split * g.c_split_stride + (int64_t)m * g.ldc + n] = val;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// output layer, colour matrix, Huber loss and the per-sample gradient
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(256) void k_train_head(const float* master, const typename Prec<P>::Elem* H5,
+                                                   const float* target, float delta, float scale, uint32_t B,
+                                                   float* dy_out, typename Prec<P>::Elem* dP, float* loss_part) {
+  __shared__ float w6[kOut * kHidden + kOut];
+  __shared__ float red[256];
+  for (int i = threadIdx.x; i < kOut * kHidden + kOut; i += blockDim.x) w6[i] = master[w_offset(kLayers) + i];
+  __syncthreads();
+  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  float loss = 0.0f;
+  if (b < B) {
+    const typename Prec<P>::Elem* h = H5 + (size_t)b * kHidden;
+    float y0 = w6[3 * kHidden], y1 = w6[3 * kHidden + 1], y2 = w6[3 * kHidden + 2];
+    for (int i = 0; i < kHidden; ++i) {
+      const float hv = (float)h[i];
+      y0 += w6[i] * hv;
+      y1 += w6[kHidden + i] * hv;
+      y2 += w6[2 * kHidden + i] * hv;
+    }
+    // YUV -> RGB (BT.601 analogue) in log space
+    const float z[3] = {y0 + 1.13983f * y2, (y0 - 0.39465f * y1) - 0.58060f * y2, y0 + 2.03211f * y1};
+    float g[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float e = z[k] - target[3 * (size_t)b + k];
+      const float ae = fabsf(e);
+      loss += ae <= delta ? 0.5f * e * e : delta * (ae - 0.5f * delta);
+      g[k] = (ae <= delta ? e : copysignf(delta, e)) * scale;
+    }
+    // through the colour matrix: dy = M^T g
+    const float d0 = g[0] + g[1] + g[2];
+    const float d1 = -0.39465f * g[1] + 2.03211f * g[2];
+    const float d2 = 1.13983f * g[0] - 0.58060f * g[1];
+    dy_out[3 * (size_t)b] = d0;
+    dy_out[3 * (size_t)b + 1] = d1;
+    dy_out[3 * (size_t)b + 2] = d2;
+    typename Prec<P>::Elem* dp = dP + (size_t)b * kHidden;
+    for (int i = 0; i < kHidden; ++i) {
+      const float gv = (d0 * w6[i] + d1 * w6[kHidden + i]) + d2 * w6[2 * kHidden + i];
+      dp[i] = Prec<P>::cvt((float)h[i] > 0.0f ? gv : 0.0f);
+    }
+  }
+  red[threadIdx.x] = loss;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) loss_part[blockIdx.x] = red[0];
+}
+
+// output-layer weight/bias gradients of one batch chunk
+template <int P>
+__global__ __launch_bounds__(320) void k_train_head_grad(const float* dy, const typename Prec<P>::Elem* H5,
+                                                        float* partial) {
+  const int j = threadIdx.x;
+  const uint32_t b0 = blockIdx.x * kChunk;
+  if (j < kOut * kHidden) {
+    const int c = j / kHidden, i = j % kHidden;
+    float s = 0.0f;
+    for (uint32_t b = b0; b < b0 + kChunk; ++b) s += dy[3 * (size_t)b + c] * (float)H5[(size_t)b * kHidden + i];
+    partial[(size_t)blockIdx.x * kParams + w_offset(kLayers) + j] = s;
+  } else if (j < kOut * kHidden + kOut) {
+    const int c = j - kOut * kHidden;
+    float s = 0.0f;
+    for (uint32_t b = b0; b < b0 + kChunk; ++b) s += dy[3 * (size_t)b + c];
+    partial[(size_t)blockIdx.x * kParams + b_offset(kLayers) + c] = s;
+  }
+}
+
+// bias gradient of a hidden layer: column sums of dP over one chunk
+template <int P>
+__global__ __launch_bounds__(128) void k_colsum(const typename Prec<P>::Elem* dP, float* partial, int boff) {
+  const int i = threadIdx.x;
+  if (i >= kHidden) return;
+  const uint32_t b0 = blockIdx.x * kChunk;
+  float s = 0.0f;
+  for (uint32_t b = b0; b < b0 + kChunk; ++b) s += (float)dP[(size_t)b * kHidden + i];
+  partial[(size_t)blockIdx.x * kParams + boff + i] = s;
+}
+
+// gradient = (sum of chunk partials in chunk order) * scale; loss of the step
+__global__ __launch_bounds__(256) void k_reduce_grad(const float* partial, int splits, float scale, float* grad,
+                                                    const float* loss_part, int nloss, float loss_scale,
+                                                    float* loss_out) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < kParams; j += gridDim.x * blockDim.x) {
+    float s = 0.0f;
+    for (int k = 0; k < splits; ++k) s += partial[(size_t)k * kParams + j];
+    grad[j] = s * scale;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && loss_out) {
+    float s = 0.0f;
+    for (int k = 0; k < nloss; ++k) s += loss_part[k];
+    *loss_out = s * loss_scale;
+  }
+}
+
+// Adam (Kingma & Ba, Alg. 1) on the FP32 master weights; refreshes the
+// operand-precision copy used by the next step's GEMMs
+template <int P>
+__global__ __launch_bounds__(256) void k_adam(float* w, float* m, float* v, const float* g, float lr, float b1,
+                                             float b2, float eps, float c1, float c2, typename Prec<P>::Elem* wp) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < kParams; j += gridDim.x * blockDim.x) {
+    const float gj = g[j];
+    const float mj = b1 * m[j] + (1.0f - b1) * gj;
+    const float vj = b2 * v[j] + (1.0f - b2) * gj * gj;
+    m[j] = mj;
+    v[j] = vj;
+    const float wj = w[j] - lr * (mj / c1) / (sqrtf(vj / c2) + eps);
+    w[j] = wj;
+    wp[j] = Prec<P>::cvt(wj);
+  }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_convert(const float* w, typename Prec<P>::Elem* wp) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < kParams; j += gridDim.x * blockDim.x)
+    wp[j] = Prec<P>::cvt(w[j]);
+}
+
+// grid evaluation: squared log-error sums and the largest target per block
+__global__ __launch_bounds__(256) void k_grid_err(const float* z, const float4* map, int W, int H, uint32_t gw,
+                                                 uint32_t gh, float* part) {
+  __shared__ float se[256], mx[256];
+  float s = 0.0f, m = 0.0f;
+  const uint64_t n = (uint64_t)gw * gh;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    const float u = ((float)(i % gw) + 0.5f) / (float)gw, v = ((float)(i / gw) + 0.5f) / (float)gh;
+    const float3 c = env_bilinear(map, W, H, u, v);
+    const float t[3] = {log1pf(c.x), log1pf(c.y), log1pf(c.z)};
+    for (int k = 0; k < 3; ++k) {
+      const float e = z[3 * i + k] - t[k];
+      s += e * e;
+      m = fmaxf(m, t[k]);
+    }
+  }
+  se[threadIdx.x] = s;
+  mx[threadIdx.x] = m;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) {
+      se[threadIdx.x] += se[threadIdx.x + k];
+      mx[threadIdx.x] = fmaxf(mx[threadIdx.x], mx[threadIdx.x + k]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = se[0];
+    part[2 * blockIdx.x + 1] = mx[0];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+void TrainScratch::release() {
+  void* all[] = {act, dp, wp, target, dy, partial, grad, loss_part, loss, zgrid, err_part};
+  for (void* p : all)
+    if (p) (void)hipFree(p);
+  act = dp = wp = nullptr;
+  target = dy = partial = grad = loss_part = loss = zgrid = err_part = nullptr;
+  batch_cap = elem_bytes = steps_cap = 0;
+  grid_cap = 0;
+}
+
+static uint32_t elem_size(int prec) { return prec == NPT_FP32 ? 4u : 2u; }
+
+static hipError_t ensure_scratch(TrainScratch& s, uint32_t B, int prec, uint32_t steps) {
+  const uint32_t es = elem_size(prec);
+  if (B > s.batch_cap || es > s.elem_bytes || steps > s.steps_cap) {
+    const uint32_t nb = std::max(B, s.batch_cap), ne = std::max(es, s.elem_bytes);
+    const uint32_t ns = std::max(std::max(steps, s.steps_cap), 1u);
+    const uint64_t zc = s.grid_cap;
+    float* zg = s.zgrid;
+    float* ep = s.err_part;
+    s.zgrid = nullptr;
+    s.err_part = nullptr;
+    s.release();
+    s.zgrid = zg;
+    s.err_part = ep;
+    s.grid_cap = zc;
+    hipError_t e;
+    const size_t acts = (size_t)nb * (kFeat + kLayers * kHidden);
+    if ((e = hipMalloc(&s.act, acts * ne)) != hipSuccess) return e;
+    if ((e = hipMalloc(&s.dp, (size_t)2 * nb * kHidden * ne)) != hipSuccess) return e;
+    if ((e = hipMalloc(&s.wp, (size_t)kParams * 4)) != hipSuccess) return e;
+    if ((e = hipMalloc((void**)&s.target, (size_t)nb * 3 * 4)) != hipSuccess) return e;
+    if ((e = hipMalloc((void**)&s.dy, (size_t)nb * 3 * 4)) != hipSuccess) return e;
+    if ((e = hipMalloc((void**)&s.partial, (size_t)(nb / kChunk + 1) * kParams * 4)) != hipSuccess) return e;
+    if ((e = hipMalloc((void**)&s.grad, (size_t)kParams * 4)) != hipSuccess) return e;
+    if ((e = hipMalloc((void**)&s.loss_part, (size_t)(nb / 256 + 1) * 4)) != hipSuccess) return e;
+    if ((e = hipMalloc((void**)&s.loss, (size_t)ns * 4)) != hipSuccess) return e;
+    s.batch_cap = nb;
+    s.elem_bytes = ne;
+    s.steps_cap = ns;
+  }
+  return hipSuccess;
+}
+
+template <int P, bool AK, bool BK>
+static hipError_t gemm(const GemmDesc& g, hipStream_t st) {
+  const int waves = (g.M / 32) * (g.N / 32) * g.splits;
+  hipLaunchKernelGGL((k_gemm<P, AK, BK>), dim3((waves + 3) / 4), dim3(256), 0, st, g);
+  return hipGetLastError();
+}
+
+// One training step's loss and gradient (gradient of the mean loss) into
+// s.grad / loss_out; weights in operand precision must be current in s.wp.
+template <int P>
+static hipError_t step_gradient(TrainScratch& s, const TrainConfig& c, const TrainTargets& t, uint32_t step,
+                                float* grad_out, float* loss_out, hipStream_t st) {
+  using Elem = typename Prec<P>::Elem;
+  const uint32_t B = c.batch;
+  Elem* act = static_cast<Elem*>(s.act);
+  Elem* acts[kLayers + 1];
+  acts[0] = act;
+  for (int l = 1; l <= kLayers; ++l) acts[l] = act + (size_t)B * kFeat + (size_t)(l - 1) * B * kHidden;
+  Elem* dp[2] = {static_cast<Elem*>(s.dp), static_cast<Elem*>(s.dp) + (size_t)B * kHidden};
+  const Elem* wp = static_cast<const Elem*>(s.wp);
+  hipError_t e;
+  hipLaunchKernelGGL(k_train_sample<P>, dim3((B + 255) / 256), dim3(256), 0, st, t, (uint32_t)c.seed,
+                     (uint32_t)(c.seed >> 32), step, B, acts[0], s.target);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  for (int l = 0; l < kLayers; ++l) {
+    GemmDesc g{};
+    g.A = acts[l];
+    g.a_sm = layer_in(l);
+    g.a_sk = 1;
+    g.B = wp + w_offset(l);
+    g.b_sk = 1;
+    g.b_sn = layer_in(l);
+    g.M = (int)B;
+    g.N = kHidden;
+    g.K = layer_in(l);
+    g.k_chunk = g.K;
+    g.splits = 1;
+    g.mode = 0;
+    g.bias = t.master + b_offset(l);
+    g.C = acts[l + 1];
+    g.ldc = kHidden;
+    if ((e = gemm<P, true, true>(g, st)) != hipSuccess) return e;
+  }
+  const int nblk = (int)((B + 255) / 256);
+  hipLaunchKernelGGL(k_train_head<P>, dim3(nblk), dim3(256), 0, st, t.master, acts[kLayers], s.target, c.delta,
+                     c.loss_scale, B, s.dy, dp[0], s.loss_part);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int splits = (int)(B / kChunk);
+  hipLaunchKernelGGL(k_train_head_grad<P>, dim3(splits), dim3(320), 0, st, s.dy, acts[kLayers], s.partial);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  int cur = 0;
+  for (int l = kLayers - 1; l >= 0; --l) {
+    // dW_l = dP_l^T act_l, split over batch chunks
+    GemmDesc g{};
+    g.A = dp[cur];
+    g.a_sm = 1;
+    g.a_sk = kHidden;
+    g.B = acts[l];
+    g.b_sk = layer_in(l);
+    g.b_sn = 1;
+    g.M = kHidden;
+    g.N = layer_in(l);
+    g.K = (int)B;
+    g.k_chunk = kChunk;
+    g.splits = splits;
+    g.mode = 2;
+    g.C = s.partial + w_offset(l);
+    g.ldc = layer_in(l);
+    g.c_split_stride = kParams;
+    if ((e = gemm<P, false, false>(g, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_colsum<P>, dim3(splits), dim3(128), 0, st, dp[cur], s.partial, b_offset(l));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (l == 0) break;
+    // dP_{l-1} = (dP_l W_l) masked by act_l > 0
+    GemmDesc d{};
+    d.A = dp[cur];
+    d.a_sm = kHidden;
+    d.a_sk = 1;
+    d.B = wp + w_offset(l);
+    d.b_sk = layer_in(l);
+    d.b_sn = 1;
+    d.M = (int)B;
+    d.N = layer_in(l);
+    d.K = kHidden;
+    d.k_chunk = kHidden;
+    d.splits = 1;
+    d.mode = 1;
+    d.mask = acts[l];
+    d.mask_ld = kHidden;
+    d.C = dp[cur ^ 1];
+    d.ldc = kHidden;
+    if ((e = gemm<P, true, false>(d, st)) != hipSuccess) return e;
+    cur ^= 1;
+  }
+  const float scale = 1.0f / (3.0f * (float)B * c.loss_scale);
+  hipLaunchKernelGGL(k_reduce_grad, dim3(64), dim3(256), 0, st, s.partial, splits, scale, grad_out, s.loss_part,
+                     nblk, 1.0f / (3.0f * (float)B), loss_out);
+  return hipGetLastError();
+}
+
+template <int P>
+static hipError_t run_p(TrainScratch& s, const TrainConfig& c, const TrainTargets& t, uint32_t step0,
+                        uint32_t steps, bool update, float* grad_out, float* loss_out, hipStream_t st) {
+  using Elem = typename Prec<P>::Elem;
+  hipLaunchKernelGGL(k_convert<P>, dim3(64), dim3(256), 0, st, t.master, static_cast<Elem*>(s.wp));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  for (uint32_t i = 0; i < steps; ++i) {
+    const uint32_t step = step0 + i;
+    e = step_gradient<P>(s, c, t, step, update ? s.grad : grad_out, update ? s.loss + i : loss_out, st);
+    if (e != hipSuccess) return e;
+    if (!update) continue;
+    const double tt = (double)step + 1.0;
+    const float c1 = (float)(1.0 - std::pow((double)c.beta1, tt));
+    const float c2 = (float)(1.0 - std::pow((double)c.beta2, tt));
+    hipLaunchKernelGGL(k_adam<P>, dim3(64), dim3(256), 0, st, t.master, t.m, t.v, s.grad, c.lr, c.beta1, c.beta2,
+                       c.eps, c1, c2, static_cast<Elem*>(s.wp));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+static hipError_t dispatch(TrainScratch& s, const TrainConfig& c, const TrainTargets& t, uint32_t step0,
+                           uint32_t steps, bool update, float* grad_out, float* loss_out, hipStream_t st) {
+  if (c.batch % kChunk != 0) return hipErrorInvalidValue;
+  hipError_t e = ensure_scratch(s, c.batch, c.prec, update ? steps : 1);
+  if (e != hipSuccess) return e;
+  switch (c.prec) {
+    case NPT_FP32: return run_p<NPT_FP32>(s, c, t, step0, steps, update, grad_out, loss_out, st);
+    case NPT_FP16: return run_p<NPT_FP16>(s, c, t, step0, steps, update, grad_out, loss_out, st);
+    case NPT_BF16: return run_p<NPT_BF16>(s, c, t, step0, steps, update, grad_out, loss_out, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t train_run(TrainScratch& s, const TrainConfig& c, const TrainTargets& t, uint32_t step0, uint32_t steps,
+                     float* first_loss, float* last_loss, hipStream_t st) {
+  hipError_t e = dispatch(s, c, t, step0, steps, true, nullptr, nullptr, st);
+  if (e != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+  std::vector<float> l(steps ? steps : 1, 0.0f);
+  if (steps && (e = hipMemcpy(l.data(), s.loss, steps * sizeof(float), hipMemcpyDeviceToHost)) != hipSuccess)
+    return e;
+  *first_loss = l.front();
+  *last_loss = l[steps ? steps - 1 : 0];
+  return hipSuccess;
+}
+
+hipError_t train_gradient(TrainScratch& s, const TrainConfig& c, const TrainTargets& t, uint32_t step,
+                          float* d_grad, float* d_loss, hipStream_t st) {
+  return dispatch(s, c, t, step, 1, false, d_grad, d_loss, st);
+}
+
+hipError_t grid_eval(TrainScratch& s, int prec, const void* frags, const float* bias, const TrainTargets& t,
+                     uint32_t gw, uint32_t gh, int num_cus, float out[2], hipStream_t st) {
+  const uint64_t n = (uint64_t)gw * gh;
+  hipError_t e;
+  const int blocks = 256;
+  if (n > s.grid_cap) {
+    if (s.zgrid) (void)hipFree(s.zgrid);
+    if (s.err_part) (void)hipFree(s.err_part);
+    s.zgrid = nullptr;
+    s.err_part = nullptr;
+    s.grid_cap = 0;
+    if ((e = hipMalloc((void**)&s.zgrid, n * 3 * sizeof(float))) != hipSuccess) return e;
+    if ((e = hipMalloc((void**)&s.err_part, 2 * blocks * sizeof(float))) != hipSuccess) return e;
+    s.grid_cap = n;
+  }
+  if ((e = launch_nif_grid(prec, frags, bias, gw, gh, s.zgrid, num_cus, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_grid_err, dim3(blocks), dim3(256), 0, st, s.zgrid, t.map, (int)t.w, (int)t.h, gw, gh,
+                     s.err_part);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+  std::vector<float> p(2 * blocks);
+  if ((e = hipMemcpy(p.data(), s.err_part, p.size() * sizeof(float), hipMemcpyDeviceToHost)) != hipSuccess) return e;
+  double se = 0.0, mx = 0.0;
+  for (int b = 0; b < blocks; ++b) {
+    se += p[2 * b];
+    mx = std::max(mx, (double)p[2 * b + 1]);
+  }
+  const double mse = se / (3.0 * (double)n);
+  out[0] = (float)mse;
+  out[1] = (float)(10.0 * std::log10(mx * mx / std::max(mse, 1e-30)));
+  return hipSuccess;
+}
+
+}  // namespace npt

@@ -1,0 +1,752 @@
+// npt_api.cpp -- the C ABI of libnpt (include/npt.h): context, validation,
+// scene / environment / NIF state, and the wavefront render loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "bvh_build.h"
+#include "npt.h"
+#include "npt_kernels.h"
+#include "npt_nif_layout.h"
+#include "npt_shared.h"
+#include "npt_train.h"
+
+using namespace npt;
+
+namespace {
+
+// device allocation that grows on demand and is freed with its owner
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipError_t ensure(size_t n) {
+    if (n <= bytes) return hipSuccess;
+    if (p) {
+      hipError_t e = hipFree(p);
+      p = nullptr;
+      bytes = 0;
+      if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipMalloc(&p, n);
+    if (e == hipSuccess) bytes = n;
+    return e;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+bool finite_all(const float* a, uint64_t n) {
+  for (uint64_t i = 0; i < n; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+struct npt_ctx {
+  int device = -1;
+  bool host_only = true;
+  int num_cus = 256;
+  bool fp8_capable = false;
+  std::string err;
+
+  // host scene
+  std::vector<float> verts;
+  std::vector<uint32_t> tris, tri_mat;
+  std::vector<float> spheres;
+  std::vector<uint32_t> sph_mat;
+  std::vector<npt_material> materials;
+  bool scene_dirty = true;
+  FlatBvh bvh;
+  bool bvh_built = false;
+
+  // device scene
+  DevBuf d_nodes, d_slots, d_mats;
+  int stack_depth = 32;
+
+  bool have_camera = false;
+  npt_camera camera{};
+  npt_render_options opt{3, 0, 0};
+
+  // environment
+  DevBuf d_env;
+  uint32_t env_w = 0, env_h = 0;
+  int env_mode = NPT_ENV_MAP;
+
+  // NIF
+  bool have_nif = false;
+  DevBuf d_master, d_adam_m, d_adam_v, d_frags, d_bias;
+  uint32_t adam_step = 0;
+  int nif_prec = NPT_FP16;
+  TrainScratch train;
+
+  // render scratch
+  DevBuf qa_o, qa_d, qa_b, qb_o, qb_d, qb_b, env_d, env_b, d_L, d_accum, d_cnt, d_stats;
+  npt_stats stats{};
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool timing_pending = false;
+
+  ~npt_ctx() {
+    DevBuf* all[] = {&d_nodes, &d_slots, &d_mats, &d_env, &d_master, &d_adam_m, &d_adam_v, &d_frags, &d_bias,
+                     &qa_o, &qa_d, &qa_b, &qb_o, &qb_d, &qb_b, &env_d, &env_b, &d_L, &d_accum, &d_cnt, &d_stats};
+    for (DevBuf* b : all) b->release();
+    train.release();
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+  }
+};
+
+namespace {
+
+int fail(npt_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int ok(npt_ctx* c) {
+  c->err.clear();
+  return NPT_OK;
+}
+
+#define HIP_TRY(ctx, expr)                                                                   \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail(ctx, e_ == hipErrorOutOfMemory ? NPT_E_OOM : NPT_E_HIP,                   \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                        \
+  } while (0)
+
+int need_device(npt_ctx* c) {
+  if (c->host_only) return fail(c, NPT_E_NO_DEVICE, "host-only context has no GPU");
+  HIP_TRY(c, hipSetDevice(c->device));
+  return NPT_OK;
+}
+
+// Camera basis in FP32, formed on the host (fixed operation order, no
+// contraction): fwd = |look_at - eye|, right = |fwd x up|, up' = right x fwd;
+// tan(vfov/2) in FP64 rounded to FP32.
+CameraView camera_view(const npt_camera& cam, uint32_t W, uint32_t H) {
+  CameraView v;
+  float f[3], r[3], u[3];
+  for (int i = 0; i < 3; ++i) f[i] = cam.look_at[i] - cam.eye[i];
+  float len = std::sqrt((f[0] * f[0] + f[1] * f[1]) + f[2] * f[2]);
+  for (int i = 0; i < 3; ++i) f[i] = f[i] / len;
+  r[0] = f[1] * cam.up[2] - f[2] * cam.up[1];
+  r[1] = f[2] * cam.up[0] - f[0] * cam.up[2];
+  r[2] = f[0] * cam.up[1] - f[1] * cam.up[0];
+  len = std::sqrt((r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]);
+  for (int i = 0; i < 3; ++i) r[i] = r[i] / len;
+  u[0] = r[1] * f[2] - r[2] * f[1];
+  u[1] = r[2] * f[0] - r[0] * f[2];
+  u[2] = r[0] * f[1] - r[1] * f[0];
+  for (int i = 0; i < 3; ++i) {
+    v.eye[i] = cam.eye[i];
+    v.fwd[i] = f[i];
+    v.right[i] = r[i];
+    v.up[i] = u[i];
+  }
+  v.tan_y = (float)std::tan((double)cam.vfov_deg * (M_PI / 360.0));
+  const float aspect = (float)W / (float)H;
+  v.tan_x = v.tan_y * aspect;
+  return v;
+}
+
+SceneView scene_view(npt_ctx* c) {
+  SceneView s;
+  s.nodes = c->d_nodes.as<float4>();
+  s.slots = c->d_slots.as<float4>();
+  s.materials = c->d_mats.as<float4>();
+  s.lds_nodes = c->bvh.lds_nodes;
+  s.has_geometry = c->bvh_built ? 1u : 0u;
+  return s;
+}
+
+int upload_materials(npt_ctx* c, hipStream_t s) {
+  std::vector<npt_material> mats = c->materials;
+  if (mats.empty()) mats.push_back(npt_material{NPT_LAMBERT, {0.5f, 0.5f, 0.5f}, {0, 0, 0}, 1.5f});
+  std::vector<float4> m(2 * mats.size());
+  for (size_t i = 0; i < mats.size(); ++i) {
+    uint32_t t = mats[i].type;
+    float tb;
+    std::memcpy(&tb, &t, 4);
+    m[2 * i] = make_float4(mats[i].albedo[0], mats[i].albedo[1], mats[i].albedo[2], tb);
+    m[2 * i + 1] = make_float4(mats[i].emission[0], mats[i].emission[1], mats[i].emission[2], mats[i].ior);
+  }
+  HIP_TRY(c, c->d_mats.ensure(m.size() * sizeof(float4)));
+  HIP_TRY(c, hipMemcpyAsync(c->d_mats.p, m.data(), m.size() * sizeof(float4), hipMemcpyHostToDevice, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  return NPT_OK;
+}
+
+int repack_nif(npt_ctx* c, hipStream_t s) {
+  if (!c->have_nif) return NPT_OK;
+  const size_t bytes = nif_packed_bytes(c->nif_prec);
+  if (bytes == 0) return fail(c, NPT_E_UNSUPPORTED, "precision not supported");
+  HIP_TRY(c, c->d_frags.ensure(bytes));
+  HIP_TRY(c, c->d_bias.ensure(nif::kBiasFloats * sizeof(float)));
+  HIP_TRY(c, launch_nif_pack(c->nif_prec, c->d_master.as<float>(), c->d_frags.p, c->d_bias.as<float>(), s));
+  return NPT_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// context
+// ===========================================================================
+extern "C" int npt_create(npt_ctx** out, int device) {
+  if (!out) return NPT_E_INVALID_ARG;
+  *out = nullptr;
+  npt_ctx* c = new (std::nothrow) npt_ctx();
+  if (!c) return NPT_E_OOM;
+  if (device >= 0) {
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device >= count) {
+      delete c;
+      return NPT_E_NO_DEVICE;
+    }
+    if (hipSetDevice(device) != hipSuccess) {
+      delete c;
+      return NPT_E_HIP;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+      delete c;
+      return NPT_E_HIP;
+    }
+    c->device = device;
+    c->host_only = false;
+    c->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    c->fp8_capable = std::strstr(prop.gcnArchName, "gfx950") != nullptr;
+    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+      delete c;
+      return NPT_E_HIP;
+    }
+  }
+  *out = c;
+  return NPT_OK;
+}
+
+extern "C" int npt_destroy(npt_ctx* ctx) {
+  if (!ctx) return NPT_E_INVALID_ARG;
+  if (!ctx->host_only) (void)hipSetDevice(ctx->device);
+  delete ctx;
+  return NPT_OK;
+}
+
+extern "C" const char* npt_last_error(npt_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+// ===========================================================================
+// scene
+// ===========================================================================
+extern "C" int npt_scene_triangles(npt_ctx* c, const float* xyz, uint64_t nv, const uint32_t* tri, uint64_t nt,
+                                   const uint32_t* mat_of_tri) {
+  if (!c) return NPT_E_INVALID_ARG;
+  if ((nv && !xyz) || (nt && !tri)) return fail(c, NPT_E_INVALID_ARG, "null array with nonzero size");
+  if (nv > (1ull << 32) || nt >= kMaxSlots) return fail(c, NPT_E_INVALID_ARG, "too many vertices/triangles");
+  if (!finite_all(xyz, 3 * nv)) return fail(c, NPT_E_NAN_INPUT, "non-finite vertex coordinate");
+  for (uint64_t i = 0; i < 3 * nt; ++i)
+    if (tri[i] >= nv) return fail(c, NPT_E_INVALID_ARG, "triangle index out of range");
+  c->verts.assign(xyz, xyz + 3 * nv);
+  c->tris.assign(tri, tri + 3 * nt);
+  if (mat_of_tri) c->tri_mat.assign(mat_of_tri, mat_of_tri + nt);
+  else c->tri_mat.assign(nt, 0u);
+  c->scene_dirty = true;
+  c->bvh_built = false;
+  return ok(c);
+}
+
+extern "C" int npt_scene_spheres(npt_ctx* c, const float* cxyzr, uint64_t n, const uint32_t* mat) {
+  if (!c) return NPT_E_INVALID_ARG;
+  if (n && !cxyzr) return fail(c, NPT_E_INVALID_ARG, "null sphere array");
+  if (n >= kMaxSlots) return fail(c, NPT_E_INVALID_ARG, "too many spheres");
+  if (!finite_all(cxyzr, 4 * n)) return fail(c, NPT_E_NAN_INPUT, "non-finite sphere");
+  for (uint64_t i = 0; i < n; ++i)
+    if (!(cxyzr[4 * i + 3] > 0.0f)) return fail(c, NPT_E_INVALID_ARG, "sphere radius must be > 0");
+  c->spheres.assign(cxyzr, cxyzr + 4 * n);
+  if (mat) c->sph_mat.assign(mat, mat + n);
+  else c->sph_mat.assign(n, 0u);
+  c->scene_dirty = true;
+  c->bvh_built = false;
+  return ok(c);
+}
+
+extern "C" int npt_scene_blas_triangles(npt_ctx* c, uint32_t, const float*, uint64_t, const uint32_t*, uint64_t,
+                                        const uint32_t*) {
+  if (!c) return NPT_E_INVALID_ARG;
+  return fail(c, NPT_E_UNSUPPORTED, "instanced meshes are not built yet");
+}
+
+extern "C" int npt_scene_instances(npt_ctx* c, const npt_instance*, uint32_t n) {
+  if (!c) return NPT_E_INVALID_ARG;
+  if (n == 0) return ok(c);
+  return fail(c, NPT_E_UNSUPPORTED, "instances are not built yet");
+}
+
+extern "C" int npt_scene_materials(npt_ctx* c, const npt_material* m, uint32_t n) {
+  if (!c) return NPT_E_INVALID_ARG;
+  if (n && !m) return fail(c, NPT_E_INVALID_ARG, "null material array");
+  for (uint32_t i = 0; i < n; ++i) {
+    if (m[i].type > NPT_EMITTER) return fail(c, NPT_E_INVALID_ARG, "unknown material type");
+    if (!finite_all(m[i].albedo, 3) || !finite_all(m[i].emission, 3) || !std::isfinite(m[i].ior))
+      return fail(c, NPT_E_NAN_INPUT, "non-finite material");
+    if (m[i].type == NPT_DIELECTRIC && !(m[i].ior > 0.0f)) return fail(c, NPT_E_INVALID_ARG, "ior must be > 0");
+  }
+  c->materials.assign(m, m + n);
+  if (!c->host_only) {
+    int r = need_device(c);
+    if (r) return r;
+    r = upload_materials(c, nullptr);
+    if (r) return r;
+  }
+  return ok(c);
+}
+
+extern "C" int npt_build_bvh(npt_ctx* c, const npt_bvh_params* p, void* stream) {
+  if (!c) return NPT_E_INVALID_ARG;
+  uint32_t bins = p && p->bins ? p->bins : 32, max_leaf = p && p->max_leaf ? p->max_leaf : 4;
+  uint32_t lds_levels = p ? p->lds_levels : 0;
+  if (bins < 4 || bins > 256 || max_leaf < 1 || max_leaf > kMaxLeaf || lds_levels > 8)
+    return fail(c, NPT_E_INVALID_ARG, "bvh params out of range");
+  if (c->tris.empty() && c->spheres.empty()) return fail(c, NPT_E_NO_SCENE, "no geometry uploaded");
+  const uint32_t nmat = (uint32_t)std::max<size_t>(1, c->materials.size());
+  for (uint32_t m : c->tri_mat)
+    if (m >= nmat) return fail(c, NPT_E_INVALID_ARG, "triangle material id out of range");
+  for (uint32_t m : c->sph_mat)
+    if (m >= nmat) return fail(c, NPT_E_INVALID_ARG, "sphere material id out of range");
+  BuildInput in;
+  in.verts = c->verts.data();
+  in.nv = c->verts.size() / 3;
+  in.tris = c->tris.data();
+  in.nt = c->tris.size() / 3;
+  in.tri_mat = c->tri_mat.data();
+  in.spheres = c->spheres.data();
+  in.ns = c->spheres.size() / 4;
+  in.sph_mat = c->sph_mat.data();
+  FlatBvh b;
+  std::string e;
+  if (!build_bvh(in, bins, max_leaf, lds_levels, b, e)) return fail(c, NPT_E_INVALID_ARG, e);
+  if (b.max_depth + 1 > 64) return fail(c, NPT_E_UNSUPPORTED, "BVH deeper than the 64-entry traversal stack");
+  c->bvh = std::move(b);
+  c->bvh_built = false;
+  if (c->host_only) return fail(c, NPT_E_NO_DEVICE, "BVH built on the host; no device to upload to");
+  int r = need_device(c);
+  if (r) return r;
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(c, c->d_nodes.ensure(c->bvh.nodes.size() * sizeof(float4)));
+  HIP_TRY(c, c->d_slots.ensure(c->bvh.slots.size() * sizeof(float4)));
+  HIP_TRY(c, hipMemcpyAsync(c->d_nodes.p, c->bvh.nodes.data(), c->bvh.nodes.size() * sizeof(float4),
+                            hipMemcpyHostToDevice, s));
+  HIP_TRY(c, hipMemcpyAsync(c->d_slots.p, c->bvh.slots.data(), c->bvh.slots.size() * sizeof(float4),
+                            hipMemcpyHostToDevice, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  r = upload_materials(c, s);
+  if (r) return r;
+  c->stack_depth = c->bvh.max_depth + 1 <= 32 ? 32 : 64;
+  c->bvh_built = true;
+  c->scene_dirty = false;
+  return ok(c);
+}
+
+extern "C" int npt_bvh_info(npt_ctx* c, uint64_t* nodes, uint64_t* leaves, uint32_t* max_depth, uint64_t* slots) {
+  if (!c) return NPT_E_INVALID_ARG;
+  if (c->bvh.nodes.empty()) return fail(c, NPT_E_STATE, "no BVH built");
+  if (nodes) *nodes = c->bvh.nodes.size() / 4;
+  if (leaves) *leaves = c->bvh.leaves;
+  if (max_depth) *max_depth = c->bvh.max_depth;
+  if (slots) *slots = c->bvh.slots.size() / 3;
+  return ok(c);
+}
+
+extern "C" int npt_set_camera(npt_ctx* c, const npt_camera* cam) {
+  if (!c) return NPT_E_INVALID_ARG;
+  if (!cam) return fail(c, NPT_E_INVALID_ARG, "null camera");
+  if (!finite_all(cam->eye, 3) || !finite_all(cam->look_at, 3) || !finite_all(cam->up, 3) ||
+      !std::isfinite(cam->vfov_deg))
+    return fail(c, NPT_E_NAN_INPUT, "non-finite camera");
+  if (!(cam->vfov_deg > 0.0f && cam->vfov_deg < 180.0f)) return fail(c, NPT_E_INVALID_ARG, "vfov out of (0,180)");
+  float f[3];
+  for (int i = 0; i < 3; ++i) f[i] = cam->look_at[i] - cam->eye[i];
+  const float cx = f[1] * cam->up[2] - f[2] * cam->up[1], cy = f[2] * cam->up[0] - f[0] * cam->up[2],
+              cz = f[0] * cam->up[1] - f[1] * cam->up[0];
+  if (f[0] == 0 && f[1] == 0 && f[2] == 0) return fail(c, NPT_E_INVALID_ARG, "eye == look_at");
+  if (cx == 0 && cy == 0 && cz == 0) return fail(c, NPT_E_INVALID_ARG, "up parallel to view direction");
+  c->camera = *cam;
+  c->have_camera = true;
+  return ok(c);
+}
+
+extern "C" int npt_set_render_options(npt_ctx* c, const npt_render_options* o) {
+  if (!c) return NPT_E_INVALID_ARG;
+  if (!o) return fail(c, NPT_E_INVALID_ARG, "null options");
+  if (o->pool_paths > (1u << 30)) return fail(c, NPT_E_INVALID_ARG, "pool_paths > 2^30");
+  c->opt = *o;
+  return ok(c);
+}
+
+// ===========================================================================
+// environment
+// ===========================================================================
+extern "C" int npt_env_upload(npt_ctx* c, const float* rgb, uint32_t w, uint32_t h, void* stream) {
+  if (!c) return NPT_E_INVALID_ARG;
+  if (!rgb || w == 0 || h == 0 || (uint64_t)w * h > (1ull << 28)) return fail(c, NPT_E_INVALID_ARG, "bad env map");
+  const uint64_t n = (uint64_t)w * h;
+  for (uint64_t i = 0; i < 3 * n; ++i)
+    if (!std::isfinite(rgb[i]) || rgb[i] < 0.0f) return fail(c, NPT_E_NAN_INPUT, "non-finite or negative radiance");
+  int r = need_device(c);
+  if (r) return r;
+  std::vector<float4> m(n);
+  for (uint64_t i = 0; i < n; ++i) m[i] = make_float4(rgb[3 * i], rgb[3 * i + 1], rgb[3 * i + 2], 0.0f);
+  HIP_TRY(c, c->d_env.ensure(n * sizeof(float4)));
+  HIP_TRY(c, hipMemcpyAsync(c->d_env.p, m.data(), n * sizeof(float4), hipMemcpyHostToDevice, (hipStream_t)stream));
+  HIP_TRY(c, hipStreamSynchronize((hipStream_t)stream));
+  c->env_w = w;
+  c->env_h = h;
+  return ok(c);
+}
+
+extern "C" int npt_set_env_mode(npt_ctx* c, int mode) {
+  if (!c) return NPT_E_INVALID_ARG;
+  if (mode != NPT_ENV_MAP && mode != NPT_ENV_NIF) return fail(c, NPT_E_INVALID_ARG, "unknown env mode");
+  c->env_mode = mode;
+  return ok(c);
+}
+
+// ===========================================================================
+// NIF
+// ===========================================================================
+static bool nif_desc_ok(const npt_nif_desc* d) {
+  return d && d->n_freq == (uint32_t)nif::kFreq && d->hidden == (uint32_t)nif::kHidden &&
+         d->layers == (uint32_t)nif::kLayers;
+}
+
+extern "C" int npt_nif_upload(npt_ctx* c, const npt_nif_desc* desc, const float* params, uint64_t n, void* stream) {
+  if (!c) return NPT_E_INVALID_ARG;
+  if (!nif_desc_ok(desc)) return fail(c, NPT_E_UNSUPPORTED, "NIF shape must be n_freq 16, hidden 96, layers 5");
+  if (!params || n != (uint64_t)nif::kParams) return fail(c, NPT_E_INVALID_ARG, "parameter count mismatch");
+  if (!finite_all(params, n)) return fail(c, NPT_E_NAN_INPUT, "non-finite NIF parameter");
+  int r = need_device(c);
+  if (r) return r;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t bytes = n * sizeof(float);
+  HIP_TRY(c, c->d_master.ensure(bytes));
+  HIP_TRY(c, c->d_adam_m.ensure(bytes));
+  HIP_TRY(c, c->d_adam_v.ensure(bytes));
+  HIP_TRY(c, hipMemcpyAsync(c->d_master.p, params, bytes, hipMemcpyHostToDevice, s));
+  HIP_TRY(c, hipMemsetAsync(c->d_adam_m.p, 0, bytes, s));
+  HIP_TRY(c, hipMemsetAsync(c->d_adam_v.p, 0, bytes, s));
+  c->adam_step = 0;
+  c->have_nif = true;
+  r = repack_nif(c, s);
+  if (r) return r;
+  HIP_TRY(c, hipStreamSynchronize(s));
+  return ok(c);
+}
+
+extern "C" int npt_nif_download(npt_ctx* c, float* params, uint64_t n) {
+  if (!c) return NPT_E_INVALID_ARG;
+  if (!c->have_nif) return fail(c, NPT_E_STATE, "no NIF uploaded");
+  if (!params || n != (uint64_t)nif::kParams) return fail(c, NPT_E_INVALID_ARG, "parameter count mismatch");
+  int r = need_device(c);
+  if (r) return r;
+  HIP_TRY(c, hipDeviceSynchronize());
+  HIP_TRY(c, hipMemcpy(params, c->d_master.p, n * sizeof(float), hipMemcpyDeviceToHost));
+  return ok(c);
+}
+
+extern "C" int npt_nif_set_precision(npt_ctx* c, int prec) {
+  if (!c) return NPT_E_INVALID_ARG;
+  if (prec < NPT_FP32 || prec > NPT_FP8) return fail(c, NPT_E_INVALID_ARG, "unknown precision");
+  if (prec == NPT_FP8 && (c->host_only || !c->fp8_capable))
+    return fail(c, NPT_E_UNSUPPORTED, "FP8 NIF inference needs gfx950");
+  if (nif_packed_bytes(prec) == 0) return fail(c, NPT_E_UNSUPPORTED, "precision not built");
+  const int old = c->nif_prec;
+  c->nif_prec = prec;
+  if (c->have_nif) {
+    int r = need_device(c);
+    if (r) { c->nif_prec = old; return r; }
+    r = repack_nif(c, nullptr);
+    if (r) { c->nif_prec = old; return r; }
+    HIP_TRY(c, hipStreamSynchronize(nullptr));
+  }
+  return ok(c);
+}
+
+extern "C" int npt_nif_get_dequantized(npt_ctx* c, float* params, uint64_t n) {
+  if (!c) return NPT_E_INVALID_ARG;
+  if (!c->have_nif) return fail(c, NPT_E_STATE, "no NIF uploaded");
+  if (!params || n != (uint64_t)nif::kParams) return fail(c, NPT_E_INVALID_ARG, "parameter count mismatch");
+  int r = need_device(c);
+  if (r) return r;
+  DevBuf tmp;
+  HIP_TRY(c, tmp.ensure(n * sizeof(float)));
+  hipError_t e = launch_nif_dequant(c->nif_prec, c->d_master.as<float>(), tmp.as<float>(), (int)n, nullptr);
+  if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+  if (e == hipSuccess) e = hipMemcpy(params, tmp.p, n * sizeof(float), hipMemcpyDeviceToHost);
+  tmp.release();
+  HIP_TRY(c, e);
+  return ok(c);
+}
+
+static void train_defaults(const npt_train_params* p, TrainConfig& t) {
+  t.batch = p && p->batch ? p->batch : 65536;
+  t.samples = p && p->samples ? p->samples : (1ull << 24);
+  t.lr = p && p->lr > 0 ? p->lr : 1e-3f;
+  t.beta1 = p && p->beta1 > 0 ? p->beta1 : 0.9f;
+  t.beta2 = p && p->beta2 > 0 ? p->beta2 : 0.999f;
+  t.eps = p && p->eps > 0 ? p->eps : 1e-7f;
+  t.delta = p && p->huber_delta > 0 ? p->huber_delta : 1e-3f;
+  t.seed = p ? p->seed : 0;
+  t.prec = p ? (int)p->grad_prec : NPT_FP32;
+  t.loss_scale = p && p->loss_scale > 0 ? p->loss_scale : 1024.0f;
+}
+
+static int train_check(npt_ctx* c, const TrainConfig& t) {
+  if (!c->have_nif) return fail(c, NPT_E_STATE, "no NIF uploaded");
+  if (!c->env_w) return fail(c, NPT_E_NO_ENV, "no environment map to train on");
+  if (t.batch == 0 || t.batch % 2048 != 0 || t.batch > (1u << 22))
+    return fail(c, NPT_E_INVALID_ARG, "batch must be a positive multiple of 2048, <= 2^22");
+  if (t.prec != NPT_FP32 && t.prec != NPT_FP16 && t.prec != NPT_BF16)
+    return fail(c, NPT_E_INVALID_ARG, "grad_prec must be FP32, FP16 or BF16");
+  return NPT_OK;
+}
+
+static TrainTargets train_targets(npt_ctx* c) {
+  TrainTargets tt;
+  tt.map = c->d_env.as<float4>();
+  tt.w = c->env_w;
+  tt.h = c->env_h;
+  tt.master = c->d_master.as<float>();
+  tt.m = c->d_adam_m.as<float>();
+  tt.v = c->d_adam_v.as<float>();
+  return tt;
+}
+
+extern "C" int npt_nif_train(npt_ctx* c, const npt_train_params* p, npt_train_stats* out, void* stream) {
+  if (!c) return NPT_E_INVALID_ARG;
+  TrainConfig t;
+  train_defaults(p, t);
+  int r = train_check(c, t);
+  if (r) return r;
+  r = need_device(c);
+  if (r) return r;
+  hipStream_t s = (hipStream_t)stream;
+  const uint32_t steps = (uint32_t)((t.samples + t.batch - 1) / t.batch);
+  TrainTargets tt = train_targets(c);
+  float first = 0.0f, last = 0.0f, ms = 0.0f;
+  HIP_TRY(c, hipEventRecord(c->ev0, s));
+  hipError_t e = train_run(c->train, t, tt, c->adam_step, steps, &first, &last, s);
+  HIP_TRY(c, e);
+  HIP_TRY(c, hipEventRecord(c->ev1, s));
+  HIP_TRY(c, hipEventSynchronize(c->ev1));
+  HIP_TRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  c->adam_step += steps;
+  r = repack_nif(c, s);
+  if (r) return r;
+  HIP_TRY(c, hipStreamSynchronize(s));
+  if (out) {
+    out->steps = steps;
+    out->step_total = c->adam_step;
+    out->first_loss = first;
+    out->last_loss = last;
+    out->ms = ms;
+  }
+  return ok(c);
+}
+
+extern "C" int npt_nif_train_grad(npt_ctx* c, const npt_train_params* p, uint32_t step, float* d_grad,
+                                  float* d_loss, void* stream) {
+  if (!c) return NPT_E_INVALID_ARG;
+  if (!d_grad || !d_loss) return fail(c, NPT_E_INVALID_ARG, "null output");
+  TrainConfig t;
+  train_defaults(p, t);
+  int r = train_check(c, t);
+  if (r) return r;
+  r = need_device(c);
+  if (r) return r;
+  HIP_TRY(c, train_gradient(c->train, t, train_targets(c), step, d_grad, d_loss, (hipStream_t)stream));
+  return ok(c);
+}
+
+extern "C" int npt_nif_eval_grid(npt_ctx* c, uint32_t gw, uint32_t gh, float* out2, void* stream) {
+  if (!c) return NPT_E_INVALID_ARG;
+  if (!out2 || gw == 0 || gh == 0 || (uint64_t)gw * gh > (1ull << 26)) return fail(c, NPT_E_INVALID_ARG, "bad grid");
+  if (!c->have_nif) return fail(c, NPT_E_STATE, "no NIF uploaded");
+  if (!c->env_w) return fail(c, NPT_E_NO_ENV, "no environment map");
+  int r = need_device(c);
+  if (r) return r;
+  hipStream_t s = (hipStream_t)stream;
+  float res[2] = {0, 0};
+  HIP_TRY(c, grid_eval(c->train, c->nif_prec, c->d_frags.p, c->d_bias.as<float>(), train_targets(c), gw, gh,
+                       c->num_cus, res, s));
+  out2[0] = res[0];
+  out2[1] = res[1];
+  return ok(c);
+}
+
+extern "C" int npt_env_query(npt_ctx* c, int mode, const float* d_dirs, uint64_t n, float* d_rgb, void* stream) {
+  if (!c) return NPT_E_INVALID_ARG;
+  if (!d_dirs || !d_rgb || n == 0) return fail(c, NPT_E_INVALID_ARG, "bad query buffers");
+  int r = need_device(c);
+  if (r) return r;
+  hipStream_t s = (hipStream_t)stream;
+  if (mode == NPT_ENV_MAP) {
+    if (!c->env_w) return fail(c, NPT_E_NO_ENV, "no environment map");
+    HIP_TRY(c, launch_env_query_map(c->d_env.as<float4>(), (int)c->env_w, (int)c->env_h, d_dirs, n, d_rgb, s));
+  } else if (mode == NPT_ENV_NIF) {
+    if (!c->have_nif) return fail(c, NPT_E_NO_ENV, "no NIF uploaded");
+    HIP_TRY(c, launch_nif_dirs(c->nif_prec, c->d_frags.p, c->d_bias.as<float>(), d_dirs, n, d_rgb, c->num_cus, s));
+  } else {
+    return fail(c, NPT_E_INVALID_ARG, "unknown env mode");
+  }
+  return ok(c);
+}
+
+// ===========================================================================
+// rendering
+// ===========================================================================
+static int render_checks(npt_ctx* c, uint32_t W, uint32_t H) {
+  if (c->tris.empty() && c->spheres.empty()) return fail(c, NPT_E_NO_SCENE, "no geometry uploaded");
+  if (!c->bvh_built) return fail(c, NPT_E_STATE, "npt_build_bvh not called after the last scene change");
+  if (!c->have_camera) return fail(c, NPT_E_STATE, "no camera set");
+  if (W == 0 || H == 0) return fail(c, NPT_E_INVALID_ARG, "zero image size");
+  if ((uint64_t)W * H >= (1ull << 31)) return fail(c, NPT_E_INVALID_ARG, "image too large");
+  return NPT_OK;
+}
+
+extern "C" int npt_render(npt_ctx* c, uint32_t W, uint32_t H, uint32_t spp, uint32_t max_depth, uint64_t seed,
+                          float* d_out, void* stream) {
+  if (!c) return NPT_E_INVALID_ARG;
+  if (!d_out) return fail(c, NPT_E_INVALID_ARG, "null output buffer");
+  if (spp == 0 || max_depth == 0 || max_depth > NPT_MAX_DEPTH)
+    return fail(c, NPT_E_INVALID_ARG, "spp must be > 0 and max_depth in 1..64");
+  if (W == 0 || H == 0 || (uint64_t)W * H * spp >= (1ull << 40))
+    return fail(c, NPT_E_INVALID_ARG, "W*H*spp must be in (0, 2^40)");
+  if (c->host_only) return fail(c, NPT_E_NO_DEVICE, "host-only context cannot render");
+  int r = render_checks(c, W, H);
+  if (r) return r;
+  if (c->env_mode == NPT_ENV_MAP && !c->env_w) return fail(c, NPT_E_NO_ENV, "env mode MAP without a map");
+  if (c->env_mode == NPT_ENV_NIF && !c->have_nif) return fail(c, NPT_E_NO_ENV, "env mode NIF without weights");
+  r = need_device(c);
+  if (r) return r;
+  hipStream_t s = (hipStream_t)stream;
+
+  const uint64_t pixels = (uint64_t)W * H;
+  const uint64_t pool = c->opt.pool_paths ? c->opt.pool_paths : (1ull << 23);
+  uint64_t sp = c->opt.samples_per_pass ? c->opt.samples_per_pass : std::max<uint64_t>(1, pool / pixels);
+  sp = std::min<uint64_t>(sp, spp);
+  while (sp > 1 && pixels * sp >= (1ull << 31)) --sp;
+  const uint64_t slots = pixels * sp;
+  const size_t qb = slots * sizeof(float4);
+  DevBuf* qbufs[] = {&c->qa_o, &c->qa_d, &c->qa_b, &c->qb_o, &c->qb_d, &c->qb_b, &c->env_d, &c->env_b, &c->d_L};
+  for (DevBuf* b : qbufs) HIP_TRY(c, b->ensure(qb));
+  HIP_TRY(c, c->d_accum.ensure(pixels * sizeof(float4)));
+  HIP_TRY(c, c->d_cnt.ensure(kCntWords * sizeof(uint32_t)));
+  HIP_TRY(c, c->d_stats.ensure(2 * NPT_MAX_DEPTH * sizeof(unsigned long long)));
+  HIP_TRY(c, launch_stats_clear(c->d_stats.as<unsigned long long>(), s));
+
+  const SceneView sv = scene_view(c);
+  const CameraView cam = camera_view(c->camera, W, H);
+  RayQueue qa{c->qa_o.as<float4>(), c->qa_d.as<float4>(), c->qa_b.as<float4>()};
+  RayQueue qbq{c->qb_o.as<float4>(), c->qb_d.as<float4>(), c->qb_b.as<float4>()};
+  EnvQueue eq{c->env_d.as<float4>(), c->env_b.as<float4>()};
+  float4* L = c->d_L.as<float4>();
+  uint32_t* cnt = c->d_cnt.as<uint32_t>();
+
+  HIP_TRY(c, hipEventRecord(c->ev0, s));
+  uint32_t passes = 0;
+  for (uint64_t s0 = 0; s0 < spp; s0 += sp) {
+    PassView pv;
+    pv.width = W;
+    pv.height = H;
+    pv.pixels = (uint32_t)pixels;
+    pv.sample0 = (uint32_t)s0;
+    pv.samples = (uint32_t)std::min<uint64_t>(sp, spp - s0);
+    pv.max_depth = max_depth;
+    pv.rr_start = c->opt.rr_start ? c->opt.rr_start : 3;
+    pv.key0 = (uint32_t)seed;
+    pv.key1 = (uint32_t)(seed >> 32);
+    const uint64_t n = pixels * pv.samples;
+    HIP_TRY(c, launch_pass_init(cnt, (uint32_t)n, s));
+    HIP_TRY(c, launch_generate(cam, pv, qa, L, s));
+    RayQueue in = qa, out = qbq;
+    for (uint32_t k = 1; k <= max_depth; ++k) {
+      HIP_TRY(c, launch_trace(c->stack_depth, sv, pv, k, n, in, out, eq, L, cnt, c->num_cus, s));
+      if (c->env_mode == NPT_ENV_MAP) {
+        HIP_TRY(c, launch_env_lookup(c->d_env.as<float4>(), (int)c->env_w, (int)c->env_h, eq, L, cnt, k, n,
+                                     c->num_cus, s));
+      } else {
+        HIP_TRY(c, launch_nif_queue(c->nif_prec, c->d_frags.p, c->d_bias.as<float>(), eq, L, cnt, k, n,
+                                    c->num_cus, s));
+      }
+      std::swap(in, out);
+    }
+    HIP_TRY(c, launch_accumulate(L, c->d_accum.as<float4>(), pv, s0 == 0, s));
+    HIP_TRY(c, launch_stats_add(cnt, c->d_stats.as<unsigned long long>(), s));
+    ++passes;
+  }
+  HIP_TRY(c, launch_finalize(c->d_accum.as<float4>(), d_out, (uint32_t)pixels, 1.0f / (float)spp, s));
+  HIP_TRY(c, hipEventRecord(c->ev1, s));
+  c->timing_pending = true;
+  c->stats = npt_stats{};
+  c->stats.paths = pixels * spp;
+  c->stats.passes = passes;
+  c->stats.samples_per_pass = (uint32_t)sp;
+  return ok(c);
+}
+
+extern "C" int npt_trace_primary(npt_ctx* c, uint32_t W, uint32_t H, uint32_t sample, uint64_t seed, uint32_t* d_prim,
+                                 uint32_t* d_inst, float* d_t, float* d_normal, void* stream) {
+  if (!c) return NPT_E_INVALID_ARG;
+  if (c->host_only) return fail(c, NPT_E_NO_DEVICE, "host-only context");
+  int r = render_checks(c, W, H);
+  if (r) return r;
+  r = need_device(c);
+  if (r) return r;
+  PassView pv{};
+  pv.width = W;
+  pv.height = H;
+  pv.pixels = W * H;
+  pv.sample0 = sample;
+  pv.samples = 1;
+  pv.key0 = (uint32_t)seed;
+  pv.key1 = (uint32_t)(seed >> 32);
+  HIP_TRY(c, launch_trace_primary(c->stack_depth, scene_view(c), camera_view(c->camera, W, H), pv, d_prim, d_inst,
+                                  d_t, d_normal, c->num_cus, (hipStream_t)stream));
+  return ok(c);
+}
+
+extern "C" int npt_get_stats(npt_ctx* c, npt_stats* out) {
+  if (!c) return NPT_E_INVALID_ARG;
+  if (!out) return fail(c, NPT_E_INVALID_ARG, "null stats");
+  if (c->timing_pending) {
+    int r = need_device(c);
+    if (r) return r;
+    HIP_TRY(c, hipEventSynchronize(c->ev1));
+    float ms = 0;
+    HIP_TRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    c->stats.ms_total = ms;
+    std::vector<unsigned long long> h(2 * NPT_MAX_DEPTH);
+    HIP_TRY(c, hipMemcpy(h.data(), c->d_stats.p, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    c->stats.env_queries = 0;
+    for (int k = 0; k < NPT_MAX_DEPTH; ++k) {
+      c->stats.rays[k] = h[k];
+      c->stats.escaped[k] = h[NPT_MAX_DEPTH + k];
+      c->stats.env_queries += h[NPT_MAX_DEPTH + k];
+    }
+    c->timing_pending = false;
+  }
+  *out = c->stats;
+  return ok(c);
+}

@@ -1,0 +1,41 @@
+// npt_kernels.h -- host-side launchers of the library's kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "npt_shared.h"
+
+namespace npt {
+
+// k_render.hip
+hipError_t launch_pass_init(uint32_t* cnt, uint32_t paths, hipStream_t s);
+hipError_t launch_generate(const CameraView& cam, const PassView& pv, const RayQueue& q, float4* L,
+                           hipStream_t s);
+hipError_t launch_trace(int stack_depth, const SceneView& sc, const PassView& pv, uint32_t depth,
+                        uint64_t max_rays, const RayQueue& in, const RayQueue& out, const EnvQueue& env,
+                        float4* L, uint32_t* cnt, int num_cus, hipStream_t s);
+hipError_t launch_env_lookup(const float4* map, int W, int H, const EnvQueue& env, float4* L,
+                             const uint32_t* cnt, uint32_t depth, uint64_t max_rays, int num_cus,
+                             hipStream_t s);
+hipError_t launch_env_query_map(const float4* map, int W, int H, const float* dirs, uint64_t n, float* rgb,
+                                hipStream_t s);
+hipError_t launch_accumulate(const float4* L, float4* accum, const PassView& pv, int first_pass,
+                             hipStream_t s);
+hipError_t launch_finalize(const float4* accum, float* out, uint32_t pixels, float inv_spp, hipStream_t s);
+hipError_t launch_trace_primary(int stack_depth, const SceneView& sc, const CameraView& cam,
+                                const PassView& pv, uint32_t* prim, uint32_t* inst, float* t, float* normal,
+                                int num_cus, hipStream_t s);
+
+// k_nif.hip
+size_t nif_packed_bytes(int prec);
+hipError_t launch_nif_pack(int prec, const float* master, void* frags, float* bias, hipStream_t s);
+hipError_t launch_nif_dequant(int prec, const float* master, float* out, int n, hipStream_t s);
+hipError_t launch_nif_queue(int prec, const void* frags, const float* bias, const EnvQueue& env, float4* L,
+                            const uint32_t* cnt, uint32_t depth, uint64_t max_rays, int num_cus,
+                            hipStream_t s);
+hipError_t launch_nif_dirs(int prec, const void* frags, const float* bias, const float* dirs, uint64_t n,
+                           float* rgb, int num_cus, hipStream_t s);
+hipError_t launch_nif_grid(int prec, const void* frags, const float* bias, uint32_t gw, uint32_t gh,
+                           float* zout, int num_cus, hipStream_t s);
+
+}  // namespace npt

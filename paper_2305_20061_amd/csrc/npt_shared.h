@@ -1,0 +1,74 @@
+// npt_shared.h -- plain structs passed from the host library to its kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace npt {
+
+// BVH2 node, 64 bytes, both child boxes stored in the parent:
+//   n0 = (c0.lo.x, c0.hi.x, c0.lo.y, c0.hi.y)
+//   n1 = (c1.lo.x, c1.hi.x, c1.lo.y, c1.hi.y)
+//   n2 = (c0.lo.z, c0.hi.z, c1.lo.z, c1.hi.z)
+//   n3 = (ref0, ref1, -, -) as uint bits
+// ref: inner child = node index; leaf = kLeafBit | first_slot << 3 | (count-1).
+constexpr uint32_t kLeafBit = 0x80000000u;
+constexpr uint32_t kMaxLeaf = 8;
+constexpr uint32_t kMaxSlots = 1u << 28;
+constexpr uint32_t kMaxLdsNodes = 255;
+
+// Primitive slot, 48 bytes, leaf order:
+//   triangle: s0 = (v0, prim id), s1 = (v1, material), s2 = (v2, kPrimTriangle)
+//   sphere:   s0 = (centre, prim id), s1 = (radius, 0, 0, material), s2 = (0, 0, 0, kPrimSphere)
+constexpr uint32_t kPrimTriangle = 0;
+constexpr uint32_t kPrimSphere = 1;
+
+constexpr uint32_t kMiss = 0xFFFFFFFFu;
+
+// Material table entry (two float4): m0 = (albedo, type), m1 = (emission, ior).
+enum : uint32_t { kLambert = 0, kMirror = 1, kDielectric = 2, kEmitter = 3 };
+
+struct CameraView {
+  float eye[3], fwd[3], right[3], up[3];
+  float tan_x, tan_y;
+};
+
+struct SceneView {
+  const float4* nodes;
+  const float4* slots;
+  const float4* materials;
+  uint32_t lds_nodes;  // nodes [0, lds_nodes) are staged in LDS
+  uint32_t has_geometry;
+};
+
+// Path queue (structure of float4 streams):
+//   o = (origin, pixel), d = (direction, sample), b = (throughput, -)
+struct RayQueue {
+  float4* o;
+  float4* d;
+  float4* b;
+};
+
+// Environment queue: d = (direction, path slot), b = (throughput, -)
+struct EnvQueue {
+  float4* d;
+  float4* b;
+};
+
+// Device counters (uint32 words), zeroed at the start of every pass.
+//   [kCntRays + k]: rays entering depth k        (k = 1..64)
+//   [kCntEnv + k]: escaped rays of depth k
+//   [kCntWork + k]: work-distribution counter of the trace kernel at depth k
+constexpr int kCntRays = 0;
+constexpr int kCntEnv = 80;
+constexpr int kCntWork = 160;
+constexpr int kCntEnvWork = 240;
+constexpr int kCntWords = 320;
+
+struct PassView {
+  uint32_t width, height, pixels;  // pixels = width * height
+  uint32_t sample0, samples;        // samples of this pass: [sample0, sample0 + samples)
+  uint32_t max_depth, rr_start;
+  uint32_t key0, key1;              // Philox key = seed
+};
+
+}  // namespace npt

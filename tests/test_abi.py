@@ -1,0 +1,123 @@
+"""The C-ABI library loads and exports every function include/npt.h declares;
+host-only contexts validate arguments and build BVHs without a GPU (no
+compute calls here)."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from paper_2305_20061_amd import npt, synth
+
+
+@pytest.fixture(scope="module")
+def L():
+    return npt.lib()
+
+
+def test_every_declared_function_is_exported(L):
+    names = npt.header_functions()
+    assert len(names) >= 25
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(npt._SIGS), set(names) ^ set(npt._SIGS)
+
+
+def test_header_is_plain_c():
+    import re
+    txt = open(npt.HEADER).read()
+    code = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    assert 'extern "C"' in code
+    for bad in ("torch", "hip_runtime", "std::", "template", "hipStream_t"):
+        assert bad not in code
+
+
+@pytest.fixture
+def host_ctx():
+    h = npt.npt_create(-1)
+    yield h
+    npt.npt_destroy(h)
+
+
+def _code(fn, *a, **k):
+    with pytest.raises(npt.NptError) as e:
+        fn(*a, **k)
+    return e.value.name
+
+
+def test_host_only_validation(host_ctx):
+    c = host_ctx
+    v = np.zeros((3, 3), np.float32)
+    v[1, 0] = 1
+    v[2, 1] = 1
+    assert _code(npt.npt_scene_triangles, c, v, np.array([[0, 1, 3]])) == "INVALID_ARG"
+    bad = v.copy()
+    bad[0, 0] = np.nan
+    assert _code(npt.npt_scene_triangles, c, bad, np.array([[0, 1, 2]])) == "NAN_INPUT"
+    assert _code(npt.npt_scene_spheres, c, np.array([[0, 0, 0, -1.0]])) == "INVALID_ARG"
+    assert _code(npt.npt_scene_materials, c, [{"type": 9}]) == "INVALID_ARG"
+    assert _code(npt.npt_build_bvh, c) == "NO_SCENE"
+    assert _code(npt.npt_set_camera, c, (0, 0, 0), (0, 0, 0), (0, 1, 0), 40) == "INVALID_ARG"
+    assert _code(npt.npt_set_camera, c, (0, 0, 0), (0, 0, -1), (0, 0, 1), 40) == "INVALID_ARG"
+    assert _code(npt.npt_set_camera, c, (0, 0, 0), (0, 0, -1), (0, 1, 0), 180) == "INVALID_ARG"
+    assert _code(npt.npt_set_env_mode, c, 5) == "INVALID_ARG"
+    assert _code(npt.npt_nif_set_precision, c, 7) == "INVALID_ARG"
+    assert _code(npt.npt_nif_set_precision, c, npt.FP8) == "UNSUPPORTED"
+    assert _code(npt.npt_nif_upload, c, np.zeros(10)) == "INVALID_ARG"
+    assert _code(npt.npt_nif_upload, c, np.zeros(43779), hidden=128) == "UNSUPPORTED"
+    assert _code(npt.npt_env_upload, c, np.zeros((4, 8, 3))) == "NO_DEVICE"
+    assert _code(npt.npt_env_upload, c, -np.ones((4, 8, 3))) == "NAN_INPUT"
+    # render argument checks come before any device work
+    lib = npt.lib()
+    assert lib.npt_render(c, 0, 4, 1, 1, 0, C.c_void_p(1), None) == npt.NPT_E["INVALID_ARG"]
+    assert lib.npt_render(c, 4, 4, 0, 1, 0, C.c_void_p(1), None) == npt.NPT_E["INVALID_ARG"]
+    assert lib.npt_render(c, 4, 4, 1, 0, 0, C.c_void_p(1), None) == npt.NPT_E["INVALID_ARG"]
+    assert lib.npt_render(c, 4, 4, 1, 65, 0, C.c_void_p(1), None) == npt.NPT_E["INVALID_ARG"]
+    assert lib.npt_render(c, 1 << 20, 1 << 20, 1 << 20, 1, 0, C.c_void_p(1), None) == npt.NPT_E["INVALID_ARG"]
+    assert lib.npt_render(c, 4, 4, 1, 1, 0, None, None) == npt.NPT_E["INVALID_ARG"]
+    assert lib.npt_render(c, 4, 4, 1, 1, 0, C.c_void_p(1), None) == npt.NPT_E["NO_DEVICE"]
+    assert "host-only" in npt.npt_last_error(c)
+    assert lib.npt_render(None, 4, 4, 1, 1, 0, C.c_void_p(1), None) == npt.NPT_E["INVALID_ARG"]
+
+
+def test_host_only_bvh_build_and_state_survives_errors(host_ctx):
+    c = host_ctx
+    sc = synth.scene_for(3)
+    npt.npt_scene_materials(c, sc["materials"])
+    npt.npt_scene_triangles(c, sc["verts"], sc["tris"], sc["tri_mat"])
+    assert _code(npt.npt_build_bvh, c, lds_levels=6) == "NO_DEVICE"  # built on the host, no upload
+    info = npt.npt_bvh_info(c)
+    nt = len(sc["tris"])
+    assert info["prim_slots"] == nt
+    assert info["nodes"] == info["leaves"] - 1
+    assert nt / 4 <= info["leaves"] <= nt
+    assert info["max_depth"] < 63
+    # a rejected upload leaves the previous scene intact
+    assert _code(npt.npt_scene_triangles, c, sc["verts"], sc["tris"][:, ::-1] + 10**7) == "INVALID_ARG"
+    assert _code(npt.npt_build_bvh, c, lds_levels=0) == "NO_DEVICE"
+    assert npt.npt_bvh_info(c)["prim_slots"] == nt
+
+
+def test_bvh_params_validated(host_ctx):
+    c = host_ctx
+    sc = synth.box_scene()
+    npt.npt_scene_triangles(c, sc["verts"], sc["tris"], sc["tri_mat"])
+    assert _code(npt.npt_build_bvh, c, bins=2) == "INVALID_ARG"
+    assert _code(npt.npt_build_bvh, c, max_leaf=9) == "INVALID_ARG"
+    assert _code(npt.npt_build_bvh, c, lds_levels=9) == "INVALID_ARG"
+    # material ids beyond the table (none uploaded -> one default material)
+    assert _code(npt.npt_build_bvh, c) == "INVALID_ARG"
+
+
+def test_tiny_scenes_build(host_ctx):
+    c = host_ctx
+    npt.npt_scene_spheres(c, np.array([[0, 0, 0, 1.0]]))
+    assert _code(npt.npt_build_bvh, c) == "NO_DEVICE"
+    info = npt.npt_bvh_info(c)
+    assert info["prim_slots"] == 1 and info["nodes"] == 1 and info["leaves"] == 1
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(npt, "_lib", None)
+    monkeypatch.setattr(npt, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        npt.lib()

@@ -1,0 +1,171 @@
+"""HDR-NIF on the GPU vs the CPU oracle (Sec. 3.2, 3.3): MFMA inference in
+FP32/FP16/BF16 against the oracle's FP64 forward on the same weights rounded
+to the inference precision; NIF-lit renders; training gradients and an Adam
+step (Sec. 3.2.1) against the oracle's FP64 backward pass."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2305_20061_amd import npt, synth
+
+from gpu_util import (bf16_round, fp16_round, gpu_render, make_ctx, oracle_scene, rel_rmse, torch_cuda)
+
+pytestmark = pytest.mark.gpu
+SHAPE = O.nif_shape(16, 96, 5)
+
+# relative-RMSE bounds of the radiance of one query batch, per precision
+# (FP32 features/uv vs FP64; FP16/BF16 activation rounding)
+QUERY_TOL = {npt.FP32: 2e-4, npt.FP16: 1e-2, npt.BF16: 4e-2}
+
+
+def _weights(seed=3):
+    p = synth.nif_init(seed).astype(np.float32)
+    p[-3:] = (0.6, 0.05, -0.05)  # output bias: Y 0.6, small chroma -> positive radiance
+    return p
+
+
+def _dequant(p, prec):
+    return {npt.FP32: np.asarray(p, np.float64), npt.FP16: fp16_round(p), npt.BF16: bf16_round(p)}[prec]
+
+
+def _dirs(n, seed=0):
+    rng = np.random.default_rng(seed)
+    d = rng.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    return d.astype(np.float32)
+
+
+@pytest.mark.parametrize("prec", [npt.FP32, npt.FP16, npt.BF16])
+@pytest.mark.parametrize("n", [1, 37, 4096 + 29])
+def test_nif_query_matches_oracle(prec, n):
+    torch = torch_cuda()
+    p = _weights()
+    ctx = npt.npt_create(0)
+    try:
+        npt.npt_nif_upload(ctx, p)
+        npt.npt_nif_set_precision(ctx, prec)
+        d = _dirs(n)
+        dt = torch.from_numpy(d).cuda()
+        out = torch.full((n, 3), -1.0, dtype=torch.float32, device="cuda")
+        npt.npt_env_query(ctx, npt.ENV_NIF, dt, out)
+        torch.cuda.synchronize()
+        g = out.cpu().numpy().astype(np.float64)
+        dq = npt.npt_nif_get_dequantized(ctx)
+    finally:
+        npt.npt_destroy(ctx)
+    ref_p = _dequant(p, prec)
+    assert np.array_equal(dq.astype(np.float64), ref_p)  # the library multiplies the same rounded weights
+    o = np.array([O.nif_radiance(SHAPE, ref_p, *O.dir_to_uv(x)) for x in d])
+    r = rel_rmse(g, o)
+    print(f"prec {prec} n {n}: relRMSE {r:.3e}")
+    assert np.all(g >= 0)
+    assert r <= QUERY_TOL[prec]
+
+
+def test_nif_render_matches_oracle_fp32(small_sky):
+    scene = synth.scene_for(1)
+    p = _weights()
+    ctx = make_ctx(scene, env=small_sky)
+    try:
+        npt.npt_nif_upload(ctx, p)
+        npt.npt_nif_set_precision(ctx, npt.FP32)
+        npt.npt_set_env_mode(ctx, npt.ENV_NIF)
+        g = gpu_render(ctx, 48, 48, 2, 6, 9)
+    finally:
+        npt.npt_destroy(ctx)
+    osc, cam = oracle_scene(scene)
+    o = O.render(osc, cam, O.render_desc(48, 48, 2, 6, 9, nif_params=p.astype(np.float64), nif=SHAPE))
+    r = rel_rmse(g, o)
+    print(f"NIF FP32 render relRMSE {r:.3e}")
+    assert r <= 1e-3
+
+
+@pytest.mark.parametrize("prec", [npt.FP16, npt.BF16])
+def test_nif_render_matches_oracle_low_precision(prec, small_sky):
+    scene = synth.scene_for(1)
+    p = _weights()
+    ctx = make_ctx(scene, env=small_sky)
+    try:
+        npt.npt_nif_upload(ctx, p)
+        npt.npt_nif_set_precision(ctx, prec)
+        npt.npt_set_env_mode(ctx, npt.ENV_NIF)
+        g = gpu_render(ctx, 48, 48, 2, 6, 9)
+    finally:
+        npt.npt_destroy(ctx)
+    osc, cam = oracle_scene(scene)
+    o = O.render(osc, cam, O.render_desc(48, 48, 2, 6, 9, nif_params=_dequant(p, prec), nif=SHAPE))
+    r = rel_rmse(g, o)
+    print(f"NIF prec {prec} render relRMSE {r:.3e}")
+    assert r <= QUERY_TOL[prec]
+
+
+GRAD_TOL = {npt.FP32: 1e-4, npt.FP16: 3e-2, npt.BF16: 1e-1}
+
+
+@pytest.mark.parametrize("prec", [npt.FP32, npt.FP16, npt.BF16])
+def test_training_gradient_matches_oracle(prec, small_sky):
+    torch = torch_cuda()
+    p = synth.nif_init(11)
+    B, seed, step = 2048, 5, 2
+    ctx = npt.npt_create(0)
+    try:
+        npt.npt_env_upload(ctx, small_sky)
+        npt.npt_nif_upload(ctx, p)
+        grad = torch.zeros(43779, dtype=torch.float32, device="cuda")
+        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        tp = npt.train_params(batch=B, seed=seed, grad_prec=prec)
+        npt.npt_nif_train_grad(ctx, tp, step, grad, loss)
+        torch.cuda.synchronize()
+        g = grad.cpu().numpy().astype(np.float64)
+        lg = float(loss.cpu()[0])
+    finally:
+        npt.npt_destroy(ctx)
+    uv, tg = O.nif_train_batch(small_sky, seed, step, B)
+    lo, go = O.nif_loss_grad(SHAPE, p.astype(np.float64), uv, tg, 1e-3)
+    r = rel_rmse(g, go)
+    print(f"grad prec {prec}: relRMSE {r:.3e}, loss {lg:.6e} vs {lo:.6e}")
+    assert abs(lg - lo) <= 1e-4 * abs(lo) + 1e-9
+    assert r <= GRAD_TOL[prec]
+
+
+def test_adam_step_matches_oracle(small_sky):
+    p = synth.nif_init(13)
+    B, seed = 2048, 21
+    ctx = npt.npt_create(0)
+    try:
+        npt.npt_env_upload(ctx, small_sky)
+        npt.npt_nif_upload(ctx, p)
+        st = npt.npt_nif_train(ctx, npt.train_params(batch=B, samples=B, seed=seed, grad_prec=npt.FP32))
+        q = npt.npt_nif_download(ctx).astype(np.float64)
+    finally:
+        npt.npt_destroy(ctx)
+    ref = p.astype(np.float64).copy()
+    m, v = np.zeros_like(ref), np.zeros_like(ref)
+    lo = O.nif_train_step(SHAPE, ref, m, v, small_sky, seed, 0, B)
+    assert st["steps"] == 1 and abs(st["first_loss"] - lo) <= 1e-4 * lo
+    dg, do = q - p, ref - p
+    # first Adam step is -lr * g / (|g| + eps): sign agreement wherever the
+    # oracle's step is not tiny, magnitudes within 1e-3 absolute of lr
+    big = np.abs(do) > 1e-4
+    assert np.mean(np.sign(dg[big]) == np.sign(do[big])) > 0.999
+    assert np.abs(dg - do).max() < 1e-3 * 1e-3 + 2e-4
+
+
+def test_training_beats_untrained_network(sky_map):
+    """The learned part earns its keep: training on the device cuts the
+    log-radiance error of the NIF against the map it compresses by a wide
+    margin (the untrained network is the method without learning)."""
+    ctx = npt.npt_create(0)
+    try:
+        npt.npt_env_upload(ctx, sky_map)
+        npt.npt_nif_upload(ctx, synth.nif_init(3))
+        npt.npt_nif_set_precision(ctx, npt.FP16)
+        before = npt.npt_nif_eval_grid(ctx, 512, 256)
+        st = npt.npt_nif_train(ctx, npt.train_params(batch=65536, samples=1 << 22, seed=1, grad_prec=npt.FP16))
+        after = npt.npt_nif_eval_grid(ctx, 512, 256)
+    finally:
+        npt.npt_destroy(ctx)
+    print(f"log-MSE {before['log_mse']:.4e} -> {after['log_mse']:.4e}; loss {st['first_loss']:.3e} -> "
+          f"{st['last_loss']:.3e} in {st['steps']} steps, {st['ms']:.1f} ms")
+    assert st["last_loss"] < 0.2 * st["first_loss"]
+    assert after["log_mse"] < 0.05 * before["log_mse"]
