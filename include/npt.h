@@ -38,7 +38,7 @@ extern "C" {
 
 /* ---- enums --------------------------------------------------------------- */
 enum { NPT_LAMBERT = 0, NPT_MIRROR = 1, NPT_DIELECTRIC = 2, NPT_EMITTER = 3 };
-enum { NPT_ENV_MAP = 0, NPT_ENV_NIF = 1 };
+enum { NPT_ENV_MAP = 0, NPT_ENV_NIF = 1, NPT_ENV_NONE = 2 };
 enum { NPT_FP32 = 0, NPT_FP16 = 1, NPT_BF16 = 2, NPT_FP8 = 3 };
 
 typedef struct npt_ctx npt_ctx;
@@ -117,11 +117,17 @@ typedef struct {
 
 /* Render options.  rr_start: first depth with Russian roulette (Sec. 4: 3);
  * samples_per_pass: samples traced together (0 = library default, sized
- * from the pool); pool_paths: upper bound on paths in flight (0 = 2^23). */
+ * from the pool); pool_paths: upper bound on paths in flight (0 = 2^23);
+ * kernel_timing: 1 = time every trace and environment launch with HIP
+ * events on the render stream (npt_stats.ms_trace / ms_env);
+ * count_visits: 1 = use the counting variant of the trace kernel
+ * (npt_stats.node_visits / prim_tests; slower, for byte accounting only). */
 typedef struct {
     uint32_t rr_start;
     uint32_t samples_per_pass;
     uint32_t pool_paths;
+    uint32_t kernel_timing;
+    uint32_t count_visits;
 } npt_render_options;
 
 #define NPT_MAX_DEPTH 64
@@ -135,6 +141,12 @@ typedef struct {
     uint32_t passes;
     uint32_t samples_per_pass;
     float ms_total;                      /* device time of the last render         */
+    /* kernel_timing: summed event time and launch counts */
+    float ms_trace, ms_env;
+    uint32_t trace_launches, env_launches;
+    /* count_visits: BVH nodes fetched / primitives tested at depth k */
+    uint64_t node_visits[NPT_MAX_DEPTH];
+    uint64_t prim_tests[NPT_MAX_DEPTH];
 } npt_stats;
 
 /* ---- context ------------------------------------------------------------- */
@@ -176,7 +188,8 @@ int npt_set_render_options(npt_ctx *ctx, const npt_render_options *opt);
  * = azimuth, texel centres at half-integers).  Kept on the device for lookup
  * and training.  NPT_E_NAN_INPUT on NaN/Inf or negative radiance. */
 int npt_env_upload(npt_ctx *ctx, const float *rgb, uint32_t w, uint32_t h, void *stream);
-/* NPT_ENV_MAP: bilinear lookup; NPT_ENV_NIF: the HDR-NIF. */
+/* NPT_ENV_MAP: bilinear lookup; NPT_ENV_NIF: the HDR-NIF; NPT_ENV_NONE: no
+ * environment light (escaped paths add nothing; closed scenes). */
 int npt_set_env_mode(npt_ctx *ctx, int mode);
 
 /* ---- HDR-NIF (Sec. 3.2) ----------------------------------------------------- */

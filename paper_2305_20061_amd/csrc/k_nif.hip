@@ -94,8 +94,7 @@ template <int P, bool kAccurateSin>
 __device__ __forceinline__ float feature(int f, float u, float v) {
   const int blk = f >> 4;
   const float arg = blk < 2 ? u : v;
-  const float x = (float)frequency(f & 15) * arg;
-  const float ph = x - floorf(x);
+  const float ph = frac_product((float)frequency(f & 15), arg);
   if (kAccurateSin) {
     float s, c;
     sincos_turns(ph, s, c);

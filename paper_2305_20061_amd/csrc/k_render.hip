@@ -78,9 +78,11 @@ __device__ __forceinline__ float safe_inverse(float x) {
   return 1.0f / (fabsf(x) > 1e-20f ? x : copysignf(1e-20f, x));
 }
 
-template <int kStack>
+// kCount: also count inner-node fetches (n_nodes) and primitive tests (n_prims)
+template <int kStack, bool kCount = false>
 __device__ __forceinline__ Hit closest_hit(const SceneView& sc, const float4* lds_nodes,
-                                           uint32_t* stack, V3 o, V3 d) {
+                                           uint32_t* stack, V3 o, V3 d, uint32_t* n_nodes = nullptr,
+                                           uint32_t* n_prims = nullptr) {
   Hit h{__builtin_inff(), kMiss, kMiss};
   if (!sc.has_geometry) return h;
   const Shear sh = make_shear(d);
@@ -100,6 +102,7 @@ __device__ __forceinline__ Hit closest_hit(const SceneView& sc, const float4* ld
         const float4* p = sc.nodes + 4 * (size_t)ref;
         n0 = p[0]; n1 = p[1]; n2 = p[2]; n3 = p[3];
       }
+      if constexpr (kCount) ++*n_nodes;
       float lo0, hi0, lo1, hi1;
       slab2(n0, n1, n2, ix, iy, iz, ox, oy, oz, h.t * 1.000001f, lo0, hi0, lo1, hi1);
       const bool h0 = lo0 <= hi0, h1 = lo1 <= hi1;
@@ -118,6 +121,7 @@ __device__ __forceinline__ Hit closest_hit(const SceneView& sc, const float4* ld
     } else {
       const uint32_t first = (ref >> 3) & 0x0FFFFFFFu;
       const uint32_t count = (ref & 7u) + 1u;
+      if constexpr (kCount) *n_prims += count;
       for (uint32_t i = 0; i < count; ++i) {
         const float4* s = sc.slots + 3 * (size_t)(first + i);
         const float4 s0 = s[0], s1 = s[1], s2 = s[2];
@@ -187,16 +191,17 @@ __global__ void k_pass_init(uint32_t* cnt, uint32_t paths) {
 // trace: closest hit + shading of every ray entering depth `depth`.
 // Escaped rays go to the environment queue; survivors to the next queue.
 // ---------------------------------------------------------------------------
-template <int kStack>
+template <int kStack, bool kCount>
 __global__ __launch_bounds__(kTraceBlock) void k_trace(SceneView sc, PassView pv, uint32_t depth,
                                                        RayQueue in, RayQueue out, EnvQueue env,
-                                                       float4* L, uint32_t* cnt) {
+                                                       float4* L, uint32_t* cnt, unsigned long long* visit_cnt) {
   extern __shared__ float4 lds_nodes[];
   __shared__ uint32_t stack_mem[kStack * kTraceBlock];
   stage_lds_nodes(sc, lds_nodes);
   uint32_t* stack = stack_mem + threadIdx.x;
   const uint32_t n = cnt[kCntRays + depth];
   const uint32_t lane = threadIdx.x & (kWave - 1);
+  uint32_t n_nodes = 0, n_prims = 0;
   for (;;) {
     uint32_t chunk = 0;
     if (lane == 0) chunk = atomicAdd(&cnt[kCntWork + depth], 1u);
@@ -216,7 +221,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(SceneView sc, PassView pv
     }
     const uint32_t slot = (sample - pv.sample0) * pv.pixels + pixel;
     Hit h{__builtin_inff(), kMiss, kMiss};
-    if (valid) h = closest_hit<kStack>(sc, lds_nodes, stack, o, d);
+    if (valid) h = closest_hit<kStack, kCount>(sc, lds_nodes, stack, o, d, &n_nodes, &n_prims);
     const bool escaped = valid && h.slot == kMiss;
     bool alive = false;
     V3 no{0, 0, 0}, nd{0, 0, 1};
@@ -273,6 +278,10 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(SceneView sc, PassView pv
       out.d[oi] = make_float4(nd.x, nd.y, nd.z, __uint_as_float(sample));
       out.b[oi] = make_float4(beta.x, beta.y, beta.z, 0.0f);
     }
+  }
+  if constexpr (kCount) {
+    atomicAdd(&visit_cnt[depth - 1], (unsigned long long)n_nodes);
+    atomicAdd(&visit_cnt[64 + depth - 1], (unsigned long long)n_prims);
   }
 }
 
@@ -372,7 +381,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_primary(SceneView sc, Cam
 
 // per-depth counters summed over passes (npt_get_stats)
 __global__ void k_stats_clear(unsigned long long* st) {
-  for (int i = threadIdx.x; i < 2 * 64; i += blockDim.x) st[i] = 0ull;
+  for (int i = threadIdx.x; i < 4 * 64; i += blockDim.x) st[i] = 0ull;
 }
 
 __global__ void k_stats_add(const uint32_t* cnt, unsigned long long* st) {
@@ -415,13 +424,23 @@ hipError_t launch_generate(const CameraView& cam, const PassView& pv, const RayQ
 
 hipError_t launch_trace(int stack_depth, const SceneView& sc, const PassView& pv, uint32_t depth,
                         uint64_t max_rays, const RayQueue& in, const RayQueue& out, const EnvQueue& env,
-                        float4* L, uint32_t* cnt, int num_cus, hipStream_t s) {
+                        float4* L, uint32_t* cnt, unsigned long long* visit_cnt, int num_cus, hipStream_t s) {
   const size_t lds = (size_t)sc.lds_nodes * 4 * sizeof(float4);
   const int grid = grid_for(max_rays, kTraceBlock, num_cus * 16);
-  if (stack_depth <= 32) {
-    hipLaunchKernelGGL(k_trace<32>, dim3(grid), dim3(kTraceBlock), lds, s, sc, pv, depth, in, out, env, L, cnt);
+  if (visit_cnt) {
+    if (stack_depth <= 32)
+      hipLaunchKernelGGL((k_trace<32, true>), dim3(grid), dim3(kTraceBlock), lds, s, sc, pv, depth, in, out, env, L,
+                         cnt, visit_cnt);
+    else
+      hipLaunchKernelGGL((k_trace<64, true>), dim3(grid), dim3(kTraceBlock), lds, s, sc, pv, depth, in, out, env, L,
+                         cnt, visit_cnt);
   } else {
-    hipLaunchKernelGGL(k_trace<64>, dim3(grid), dim3(kTraceBlock), lds, s, sc, pv, depth, in, out, env, L, cnt);
+    if (stack_depth <= 32)
+      hipLaunchKernelGGL((k_trace<32, false>), dim3(grid), dim3(kTraceBlock), lds, s, sc, pv, depth, in, out, env, L,
+                         cnt, visit_cnt);
+    else
+      hipLaunchKernelGGL((k_trace<64, false>), dim3(grid), dim3(kTraceBlock), lds, s, sc, pv, depth, in, out, env, L,
+                         cnt, visit_cnt);
   }
   return hipGetLastError();
 }

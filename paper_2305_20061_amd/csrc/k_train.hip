@@ -32,10 +32,9 @@ __global__ __launch_bounds__(256) void k_train_sample(TrainTargets t, uint32_t k
 #pragma unroll
     for (int k = 0; k < kFreq; ++k) {
       const float f = (float)frequency(k);
-      const float xu = f * u, xv = f * v;
       float su, cu, sv, cv;
-      sincos_turns(xu - floorf(xu), su, cu);
-      sincos_turns(xv - floorf(xv), sv, cv);
+      sincos_turns(frac_product(f, u), su, cu);
+      sincos_turns(frac_product(f, v), sv, cv);
       x[k] = Prec<P>::cvt(su);
       x[kFreq + k] = Prec<P>::cvt(cu);
       x[2 * kFreq + k] = Prec<P>::cvt(sv);

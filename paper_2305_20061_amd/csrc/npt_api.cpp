@@ -96,6 +96,7 @@ struct npt_ctx {
   DevBuf qa_o, qa_d, qa_b, qb_o, qb_d, qb_b, env_d, env_b, d_L, d_accum, d_cnt, d_stats;
   npt_stats stats{};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::vector<hipEvent_t> event_pool, trace_events, env_events;
   bool timing_pending = false;
 
   ~npt_ctx() {
@@ -103,6 +104,7 @@ struct npt_ctx {
                      &qa_o, &qa_d, &qa_b, &qb_o, &qb_d, &qb_b, &env_d, &env_b, &d_L, &d_accum, &d_cnt, &d_stats};
     for (DevBuf* b : all) b->release();
     train.release();
+    for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
   }
@@ -418,7 +420,8 @@ extern "C" int npt_env_upload(npt_ctx* c, const float* rgb, uint32_t w, uint32_t
 
 extern "C" int npt_set_env_mode(npt_ctx* c, int mode) {
   if (!c) return NPT_E_INVALID_ARG;
-  if (mode != NPT_ENV_MAP && mode != NPT_ENV_NIF) return fail(c, NPT_E_INVALID_ARG, "unknown env mode");
+  if (mode != NPT_ENV_MAP && mode != NPT_ENV_NIF && mode != NPT_ENV_NONE)
+    return fail(c, NPT_E_INVALID_ARG, "unknown env mode");
   c->env_mode = mode;
   return ok(c);
 }
@@ -653,8 +656,26 @@ extern "C" int npt_render(npt_ctx* c, uint32_t W, uint32_t H, uint32_t spp, uint
   for (DevBuf* b : qbufs) HIP_TRY(c, b->ensure(qb));
   HIP_TRY(c, c->d_accum.ensure(pixels * sizeof(float4)));
   HIP_TRY(c, c->d_cnt.ensure(kCntWords * sizeof(uint32_t)));
-  HIP_TRY(c, c->d_stats.ensure(2 * NPT_MAX_DEPTH * sizeof(unsigned long long)));
+  HIP_TRY(c, c->d_stats.ensure(4 * NPT_MAX_DEPTH * sizeof(unsigned long long)));
   HIP_TRY(c, launch_stats_clear(c->d_stats.as<unsigned long long>(), s));
+  unsigned long long* visit_cnt = c->opt.count_visits ? c->d_stats.as<unsigned long long>() + 2 * NPT_MAX_DEPTH
+                                                      : nullptr;
+  const bool timing = c->opt.kernel_timing != 0;
+  c->trace_events.clear();
+  c->env_events.clear();
+  auto event_pair = [&](std::vector<hipEvent_t>& v) -> hipError_t {
+    // events are pooled per context and reused across renders
+    const size_t need = c->trace_events.size() + c->env_events.size() + 2;
+    while (c->event_pool.size() < need) {
+      hipEvent_t e;
+      hipError_t err = hipEventCreate(&e);
+      if (err != hipSuccess) return err;
+      c->event_pool.push_back(e);
+    }
+    v.push_back(c->event_pool[need - 2]);
+    v.push_back(c->event_pool[need - 1]);
+    return hipSuccess;
+  };
 
   const SceneView sv = scene_view(c);
   const CameraView cam = camera_view(c->camera, W, H);
@@ -682,13 +703,25 @@ extern "C" int npt_render(npt_ctx* c, uint32_t W, uint32_t H, uint32_t spp, uint
     HIP_TRY(c, launch_generate(cam, pv, qa, L, s));
     RayQueue in = qa, out = qbq;
     for (uint32_t k = 1; k <= max_depth; ++k) {
-      HIP_TRY(c, launch_trace(c->stack_depth, sv, pv, k, n, in, out, eq, L, cnt, c->num_cus, s));
-      if (c->env_mode == NPT_ENV_MAP) {
-        HIP_TRY(c, launch_env_lookup(c->d_env.as<float4>(), (int)c->env_w, (int)c->env_h, eq, L, cnt, k, n,
-                                     c->num_cus, s));
-      } else {
-        HIP_TRY(c, launch_nif_queue(c->nif_prec, c->d_frags.p, c->d_bias.as<float>(), eq, L, cnt, k, n,
-                                    c->num_cus, s));
+      if (timing) {
+        HIP_TRY(c, event_pair(c->trace_events));
+        HIP_TRY(c, hipEventRecord(c->trace_events[c->trace_events.size() - 2], s));
+      }
+      HIP_TRY(c, launch_trace(c->stack_depth, sv, pv, k, n, in, out, eq, L, cnt, visit_cnt, c->num_cus, s));
+      if (timing) HIP_TRY(c, hipEventRecord(c->trace_events.back(), s));
+      if (c->env_mode != NPT_ENV_NONE) {  // NONE: escaped paths carry no radiance
+        if (timing) {
+          HIP_TRY(c, event_pair(c->env_events));
+          HIP_TRY(c, hipEventRecord(c->env_events[c->env_events.size() - 2], s));
+        }
+        if (c->env_mode == NPT_ENV_MAP) {
+          HIP_TRY(c, launch_env_lookup(c->d_env.as<float4>(), (int)c->env_w, (int)c->env_h, eq, L, cnt, k, n,
+                                       c->num_cus, s));
+        } else {
+          HIP_TRY(c, launch_nif_queue(c->nif_prec, c->d_frags.p, c->d_bias.as<float>(), eq, L, cnt, k, n,
+                                      c->num_cus, s));
+        }
+        if (timing) HIP_TRY(c, hipEventRecord(c->env_events.back(), s));
       }
       std::swap(in, out);
     }
@@ -737,14 +770,30 @@ extern "C" int npt_get_stats(npt_ctx* c, npt_stats* out) {
     float ms = 0;
     HIP_TRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
     c->stats.ms_total = ms;
-    std::vector<unsigned long long> h(2 * NPT_MAX_DEPTH);
+    std::vector<unsigned long long> h(4 * NPT_MAX_DEPTH);
     HIP_TRY(c, hipMemcpy(h.data(), c->d_stats.p, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
     c->stats.env_queries = 0;
     for (int k = 0; k < NPT_MAX_DEPTH; ++k) {
       c->stats.rays[k] = h[k];
       c->stats.escaped[k] = h[NPT_MAX_DEPTH + k];
       c->stats.env_queries += h[NPT_MAX_DEPTH + k];
+      c->stats.node_visits[k] = h[2 * NPT_MAX_DEPTH + k];
+      c->stats.prim_tests[k] = h[3 * NPT_MAX_DEPTH + k];
     }
+    float sum = 0.0f;
+    for (size_t i = 0; i + 1 < c->trace_events.size(); i += 2) {
+      HIP_TRY(c, hipEventElapsedTime(&ms, c->trace_events[i], c->trace_events[i + 1]));
+      sum += ms;
+    }
+    c->stats.ms_trace = sum;
+    c->stats.trace_launches = (uint32_t)(c->trace_events.size() / 2);
+    sum = 0.0f;
+    for (size_t i = 0; i + 1 < c->env_events.size(); i += 2) {
+      HIP_TRY(c, hipEventElapsedTime(&ms, c->env_events[i], c->env_events[i + 1]));
+      sum += ms;
+    }
+    c->stats.ms_env = sum;
+    c->stats.env_launches = (uint32_t)(c->env_events.size() / 2);
     c->timing_pending = false;
   }
   *out = c->stats;

@@ -75,6 +75,17 @@ __device__ __forceinline__ void sincos_turns(float u, float& s, float& c) {
   }
 }
 
+// Fractional part of f * x for an integer-valued f, to full FP32 accuracy:
+// the product's rounding error is recovered exactly with an FMA (two-product),
+// so high Fourier frequencies keep their phase.
+__device__ __forceinline__ float frac_product(float f, float x) {
+  const float p = f * x;
+  const float err = __builtin_fmaf(f, x, -p);
+  float r = (p - floorf(p)) + err;
+  r = r < 0.0f ? r + 1.0f : (r >= 1.0f ? r - 1.0f : r);
+  return r;
+}
+
 // ---------------------------------------------------------------------------
 // small FP32 vector type with explicit, fixed-order arithmetic
 // ---------------------------------------------------------------------------

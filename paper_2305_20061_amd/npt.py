@@ -23,7 +23,7 @@ ERRORS = {-1: "INVALID_ARG", -2: "NO_SCENE", -3: "NO_ENV", -4: "OOM", -5: "HIP",
           -7: "NAN_INPUT", -8: "NO_DEVICE", -9: "STATE"}
 NPT_E = {v: k for k, v in ERRORS.items()}
 LAMBERT, MIRROR, DIELECTRIC, EMITTER = 0, 1, 2, 3
-ENV_MAP, ENV_NIF = 0, 1
+ENV_MAP, ENV_NIF, ENV_NONE = 0, 1, 2
 FP32, FP16, BF16, FP8 = 0, 1, 2, 3
 MAX_DEPTH = 64
 MISS = 0xFFFFFFFF
@@ -70,13 +70,16 @@ class npt_train_stats(C.Structure):
 
 
 class npt_render_options(C.Structure):
-    _fields_ = [("rr_start", C.c_uint32), ("samples_per_pass", C.c_uint32), ("pool_paths", C.c_uint32)]
+    _fields_ = [("rr_start", C.c_uint32), ("samples_per_pass", C.c_uint32), ("pool_paths", C.c_uint32),
+                ("kernel_timing", C.c_uint32), ("count_visits", C.c_uint32)]
 
 
 class npt_stats(C.Structure):
     _fields_ = [("paths", C.c_uint64), ("rays", C.c_uint64 * MAX_DEPTH), ("escaped", C.c_uint64 * MAX_DEPTH),
                 ("env_queries", C.c_uint64), ("passes", C.c_uint32), ("samples_per_pass", C.c_uint32),
-                ("ms_total", C.c_float)]
+                ("ms_total", C.c_float), ("ms_trace", C.c_float), ("ms_env", C.c_float),
+                ("trace_launches", C.c_uint32), ("env_launches", C.c_uint32),
+                ("node_visits", C.c_uint64 * MAX_DEPTH), ("prim_tests", C.c_uint64 * MAX_DEPTH)]
 
 
 _P = C.c_void_p
@@ -123,6 +126,13 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() (hipcc, gfx950)")
+        # torch ships its own HIP runtime under the same soname; load it first
+        # so that libnpt and torch share one runtime (and one device context)
+        try:
+            import torch
+            torch.cuda.is_available()
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         for name, args in _SIGS.items():
             fn = getattr(L, name)
@@ -247,8 +257,8 @@ def npt_set_camera(ctx, eye, look_at, up, vfov_deg):
     _check(ctx, lib().npt_set_camera(ctx, C.byref(cam)))
 
 
-def npt_set_render_options(ctx, rr_start=3, samples_per_pass=0, pool_paths=0):
-    o = npt_render_options(rr_start, samples_per_pass, pool_paths)
+def npt_set_render_options(ctx, rr_start=3, samples_per_pass=0, pool_paths=0, kernel_timing=0, count_visits=0):
+    o = npt_render_options(rr_start, samples_per_pass, pool_paths, kernel_timing, count_visits)
     _check(ctx, lib().npt_set_render_options(ctx, C.byref(o)))
 
 
@@ -337,7 +347,9 @@ def npt_get_stats(ctx):
     s = npt_stats()
     _check(ctx, lib().npt_get_stats(ctx, C.byref(s)))
     return {"paths": s.paths, "rays": list(s.rays), "escaped": list(s.escaped), "env_queries": s.env_queries,
-            "passes": s.passes, "samples_per_pass": s.samples_per_pass, "ms_total": s.ms_total}
+            "passes": s.passes, "samples_per_pass": s.samples_per_pass, "ms_total": s.ms_total,
+            "ms_trace": s.ms_trace, "ms_env": s.ms_env, "trace_launches": s.trace_launches,
+            "env_launches": s.env_launches, "node_visits": list(s.node_visits), "prim_tests": list(s.prim_tests)}
 
 
 # ------------------------------------------------------------ conveniences

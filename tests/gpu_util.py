@@ -17,6 +17,8 @@ def make_ctx(scene, env=None, lds_levels=6, max_leaf=4):
     npt.npt_load_scene(ctx, scene, lds_levels=lds_levels, max_leaf=max_leaf)
     if env is not None:
         npt.npt_env_upload(ctx, env)
+    else:
+        npt.npt_set_env_mode(ctx, npt.ENV_NONE)
     return ctx
 
 

@@ -100,6 +100,9 @@ def test_nif_render_matches_oracle_low_precision(prec, small_sky):
 
 
 GRAD_TOL = {npt.FP32: 1e-4, npt.FP16: 3e-2, npt.BF16: 1e-1}
+# relative loss error: FP32 rounding only; FP16 / BF16 activations carry
+# 2^-11 / 2^-8 relative rounding into the outputs
+LOSS_TOL = {npt.FP32: 1e-5, npt.FP16: 1e-3, npt.BF16: 1e-2}
 
 
 @pytest.mark.parametrize("prec", [npt.FP32, npt.FP16, npt.BF16])
@@ -124,7 +127,7 @@ def test_training_gradient_matches_oracle(prec, small_sky):
     lo, go = O.nif_loss_grad(SHAPE, p.astype(np.float64), uv, tg, 1e-3)
     r = rel_rmse(g, go)
     print(f"grad prec {prec}: relRMSE {r:.3e}, loss {lg:.6e} vs {lo:.6e}")
-    assert abs(lg - lo) <= 1e-4 * abs(lo) + 1e-9
+    assert abs(lg - lo) <= LOSS_TOL[prec] * abs(lo)
     assert r <= GRAD_TOL[prec]
 
 
