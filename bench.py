@@ -147,11 +147,14 @@ def main():
         out = torch.empty(H, W, 3, dtype=torch.float32, device="cuda")
 
         if args.calibrate_copy:
-            a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+            # one elementwise kernel reading 1 GiB and writing 1 GiB: the scale
+            # for the FETCH_SIZE / WRITE_SIZE counters of the same run
+            a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
             b = torch.empty_like(a)
-            b.copy_(a)
+            torch.mul(a, 1.0, out=b)
             torch.cuda.synchronize()
-            extra["copy_calibration_bytes"] = 2 * a.numel() * 4
+            extra["copy_calibration"] = {"read_bytes": a.numel() * 4, "write_bytes": b.numel() * 4}
+            del a, b
 
         # counting render (outside the timed region): algorithmic bytes
         npt.npt_set_render_options(ctx, rr_start=3, count_visits=1)
