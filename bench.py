@@ -133,7 +133,8 @@ def main():
     extra = {}
     try:
         t0 = time.perf_counter()
-        npt.npt_load_scene(ctx, scene, lds_levels=6)
+        # leaf size 2, no LDS-staged levels: fastest in the trace-kernel sweep
+        npt.npt_load_scene(ctx, scene, max_leaf=2, lds_levels=0)
         extra["bvh_build_ms"] = 1e3 * (time.perf_counter() - t0)
         extra["bvh"] = npt.npt_bvh_info(ctx)
         npt.npt_env_upload(ctx, env)

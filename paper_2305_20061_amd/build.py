@@ -21,34 +21,37 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-Wno-unus
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
-def _compile(src: str) -> str:
+def _compile(src: str, build_dir: str, defines: tuple) -> str:
     path = os.path.join(CSRC, src)
-    obj = os.path.join(BUILD, src + ".o")
+    obj = os.path.join(build_dir, src + ".o")
+    dflags = [f"-D{d}" for d in defines]
     if src.endswith(".hip"):
-        cmd = ["hipcc", "-x", "hip", *DEVICE, *COMMON, "-c", path, "-o", obj]
+        cmd = ["hipcc", "-x", "hip", *DEVICE, *COMMON, *dflags, "-c", path, "-o", obj]
     else:
         rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
-        cmd = ["hipcc", "-x", "c++", "-D__HIP_PLATFORM_AMD__", f"-I{rocm}/include", *COMMON, "-c", path,
-               "-o", obj]
+        cmd = ["hipcc", "-x", "c++", "-D__HIP_PLATFORM_AMD__", f"-I{rocm}/include", *COMMON, *dflags, "-c",
+               path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose: bool = False, defines: tuple = (), out: str = LIB, build_dir: str = BUILD) -> str:
+    """Compiles every source for gfx950 and links `out` (default: the in-tree
+    libnpt.so); `defines` are extra preprocessor definitions (NAME=VALUE)."""
+    os.makedirs(build_dir, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, build_dir, tuple(defines)), SOURCES))
+    tmp = out + ".tmp"
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
     if verbose:
-        print(f"built {LIB}")
-    return LIB
+        print(f"built {out}")
+    return out
 
 
 if __name__ == "__main__":

@@ -2,8 +2,8 @@
 // queries of escaped rays) and the weight packing it reads.
 //
 // One workgroup per CU keeps the whole packed network in LDS (FP16/BF16:
-// 94 KB); each wave pushes 64 rays (two 32-column tiles) through all layers
-// with activations held in registers (see npt_nif_layout.h).  FP32 operands
+// 94 KB); each wave pushes 32-ray column tiles through all layers with
+// activations held in registers (see npt_nif_layout.h).  FP32 operands
 // (v_mfma_f32_32x32x2f32) keep the 4 hidden 96x96 layers in LDS and read the
 // first and last layer from L2.
 #include <hip/hip_runtime.h>
@@ -73,7 +73,15 @@ __global__ void k_nif_dequant(const float* master, float* out, int n) {
 // ---------------------------------------------------------------------------
 // inference
 // ---------------------------------------------------------------------------
-constexpr int kNifWaves = 4;  // one wave per SIMD: up to 512 VGPR+AGPR per wave, no spills
+// 8 waves (two per SIMD) x one 32-ray tile per wave measured fastest: the
+// second wave hides MFMA/LDS latency; more tiles per wave spill registers.
+#ifndef NPT_NIF_WAVES
+#define NPT_NIF_WAVES 8
+#endif
+#ifndef NPT_NIF_TILES
+#define NPT_NIF_TILES 1  // 32-ray column tiles per wave for FP16/BF16 operands
+#endif
+constexpr int kNifWaves = NPT_NIF_WAVES;
 constexpr int kNifBlock = 64 * kNifWaves;
 
 enum : int { kSrcQueue = 0, kSrcDirs = 1, kSrcGrid = 2 };
@@ -149,7 +157,7 @@ __global__ __launch_bounds__(kNifBlock, 1) void k_nif_infer(const typename Prec<
   using G = Geometry<KPL>;
   using Frag = typename Prec<P>::Frag;
   constexpr bool kAccurate = (P == NPT_FP32);
-  constexpr int NT = (P == NPT_FP32) ? 1 : 2;  // 32-ray column tiles per wave
+  constexpr int NT = (P == NPT_FP32) ? 1 : NPT_NIF_TILES;  // 32-ray column tiles per wave
   constexpr int kRays = 32 * NT;
   extern __shared__ float4 smem4[];
   Frag* lfrags = reinterpret_cast<Frag*>(smem4);

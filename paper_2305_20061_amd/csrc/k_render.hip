@@ -10,7 +10,13 @@
 
 namespace npt {
 
-constexpr int kTraceBlock = 128;
+#ifndef NPT_TRACE_BLOCK
+#define NPT_TRACE_BLOCK 64  // one wave per workgroup: measured fastest (64 < 128 < 256)
+#endif
+#ifndef NPT_STACK_IN_SCRATCH
+#define NPT_STACK_IN_SCRATCH 0
+#endif
+constexpr int kTraceBlock = NPT_TRACE_BLOCK;
 constexpr int kWave = 64;
 constexpr uint32_t kMaxVisits = 1u << 22;
 
@@ -78,8 +84,9 @@ __device__ __forceinline__ float safe_inverse(float x) {
   return 1.0f / (fabsf(x) > 1e-20f ? x : copysignf(1e-20f, x));
 }
 
-// kCount: also count inner-node fetches (n_nodes) and primitive tests (n_prims)
-template <int kStack, bool kCount = false>
+// Per-lane stack entry i lives at stack[i * kStride]; kCount: also count
+// inner-node fetches (n_nodes) and primitive tests (n_prims)
+template <int kStack, int kStride, bool kCount = false>
 __device__ __forceinline__ Hit closest_hit(const SceneView& sc, const float4* lds_nodes,
                                            uint32_t* stack, V3 o, V3 d, uint32_t* n_nodes = nullptr,
                                            uint32_t* n_prims = nullptr) {
@@ -110,7 +117,7 @@ __device__ __forceinline__ Hit closest_hit(const SceneView& sc, const float4* ld
       if (h0 && h1) {
         const bool near0 = lo0 <= lo1;
         if (sp < kStack) {
-          stack[sp * kTraceBlock] = near0 ? r1 : r0;
+          stack[sp * kStride] = near0 ? r1 : r0;
           ++sp;
         }
         ref = near0 ? r0 : r1;
@@ -141,7 +148,7 @@ __device__ __forceinline__ Hit closest_hit(const SceneView& sc, const float4* ld
     }
     if (sp == 0) break;
     --sp;
-    ref = stack[sp * kTraceBlock];
+    ref = stack[sp * kStride];
   }
   return h;
 }
@@ -196,9 +203,15 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(SceneView sc, PassView pv
                                                        RayQueue in, RayQueue out, EnvQueue env,
                                                        float4* L, uint32_t* cnt, unsigned long long* visit_cnt) {
   extern __shared__ float4 lds_nodes[];
+#if NPT_STACK_IN_SCRATCH
+  uint32_t stack[kStack];
+  constexpr int kStride = 1;
+#else
   __shared__ uint32_t stack_mem[kStack * kTraceBlock];
-  stage_lds_nodes(sc, lds_nodes);
   uint32_t* stack = stack_mem + threadIdx.x;
+  constexpr int kStride = kTraceBlock;
+#endif
+  stage_lds_nodes(sc, lds_nodes);
   const uint32_t n = cnt[kCntRays + depth];
   const uint32_t lane = threadIdx.x & (kWave - 1);
   uint32_t n_nodes = 0, n_prims = 0;
@@ -221,7 +234,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(SceneView sc, PassView pv
     }
     const uint32_t slot = (sample - pv.sample0) * pv.pixels + pixel;
     Hit h{__builtin_inff(), kMiss, kMiss};
-    if (valid) h = closest_hit<kStack, kCount>(sc, lds_nodes, stack, o, d, &n_nodes, &n_prims);
+    if (valid) h = closest_hit<kStack, kStride, kCount>(sc, lds_nodes, stack, o, d, &n_nodes, &n_prims);
     const bool escaped = valid && h.slot == kMiss;
     bool alive = false;
     V3 no{0, 0, 0}, nd{0, 0, 1};
@@ -362,7 +375,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_primary(SceneView sc, Cam
     const U4 r = philox(pixel, pv.sample0, 0, kRngCamera, pv.key0, pv.key1);
     const V3 d = camera_direction(cam, pv.width, pv.height, x, y, unit_float(r.x), unit_float(r.y));
     const V3 o{cam.eye[0], cam.eye[1], cam.eye[2]};
-    const Hit h = closest_hit<kStack>(sc, lds_nodes, stack, o, d);
+    const Hit h = closest_hit<kStack, kTraceBlock>(sc, lds_nodes, stack, o, d);
     V3 n{0, 0, 0};
     if (h.slot != kMiss) {
       uint32_t mat;
@@ -426,23 +439,29 @@ hipError_t launch_trace(int stack_depth, const SceneView& sc, const PassView& pv
                         uint64_t max_rays, const RayQueue& in, const RayQueue& out, const EnvQueue& env,
                         float4* L, uint32_t* cnt, unsigned long long* visit_cnt, int num_cus, hipStream_t s) {
   const size_t lds = (size_t)sc.lds_nodes * 4 * sizeof(float4);
-  const int grid = grid_for(max_rays, kTraceBlock, num_cus * 16);
-  if (visit_cnt) {
-    if (stack_depth <= 32)
-      hipLaunchKernelGGL((k_trace<32, true>), dim3(grid), dim3(kTraceBlock), lds, s, sc, pv, depth, in, out, env, L,
-                         cnt, visit_cnt);
-    else
-      hipLaunchKernelGGL((k_trace<64, true>), dim3(grid), dim3(kTraceBlock), lds, s, sc, pv, depth, in, out, env, L,
-                         cnt, visit_cnt);
-  } else {
-    if (stack_depth <= 32)
-      hipLaunchKernelGGL((k_trace<32, false>), dim3(grid), dim3(kTraceBlock), lds, s, sc, pv, depth, in, out, env, L,
-                         cnt, visit_cnt);
-    else
-      hipLaunchKernelGGL((k_trace<64, false>), dim3(grid), dim3(kTraceBlock), lds, s, sc, pv, depth, in, out, env, L,
-                         cnt, visit_cnt);
+  const int grid = grid_for(max_rays, kTraceBlock, num_cus * 32);
+#define NPT_LAUNCH_TRACE(S, C)                                                                               \
+  hipLaunchKernelGGL((k_trace<S, C>), dim3(grid), dim3(kTraceBlock), lds, s, sc, pv, depth, in, out, env, L, \
+                     cnt, visit_cnt)
+  const bool c = visit_cnt != nullptr;
+  switch (stack_depth) {
+    case 16: if (c) NPT_LAUNCH_TRACE(16, true); else NPT_LAUNCH_TRACE(16, false); break;
+    case 24: if (c) NPT_LAUNCH_TRACE(24, true); else NPT_LAUNCH_TRACE(24, false); break;
+    case 32: if (c) NPT_LAUNCH_TRACE(32, true); else NPT_LAUNCH_TRACE(32, false); break;
+    case 48: if (c) NPT_LAUNCH_TRACE(48, true); else NPT_LAUNCH_TRACE(48, false); break;
+    case 64: if (c) NPT_LAUNCH_TRACE(64, true); else NPT_LAUNCH_TRACE(64, false); break;
+    default: return hipErrorInvalidValue;
   }
+#undef NPT_LAUNCH_TRACE
   return hipGetLastError();
+}
+
+// smallest supported traversal stack holding `entries`
+int trace_stack_size(uint32_t entries) {
+  const int sizes[] = {16, 24, 32, 48, 64};
+  for (int v : sizes)
+    if ((uint32_t)v >= entries) return v;
+  return 0;
 }
 
 hipError_t launch_env_lookup(const float4* map, int W, int H, const EnvQueue& env, float4* L,
@@ -476,6 +495,7 @@ hipError_t launch_trace_primary(int stack_depth, const SceneView& sc, const Came
                                 hipStream_t s) {
   const size_t lds = (size_t)sc.lds_nodes * 4 * sizeof(float4);
   const int grid = grid_for(pv.pixels, kTraceBlock, num_cus * 16);
+  // primary rays of a well-formed tree never need more than the full stack
   if (stack_depth <= 32) {
     hipLaunchKernelGGL(k_trace_primary<32>, dim3(grid), dim3(kTraceBlock), lds, s, sc, cam, pv, prim, inst, t,
                        normal);

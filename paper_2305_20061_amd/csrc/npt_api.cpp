@@ -355,7 +355,7 @@ extern "C" int npt_build_bvh(npt_ctx* c, const npt_bvh_params* p, void* stream) 
   HIP_TRY(c, hipStreamSynchronize(s));
   r = upload_materials(c, s);
   if (r) return r;
-  c->stack_depth = c->bvh.max_depth + 1 <= 32 ? 32 : 64;
+  c->stack_depth = trace_stack_size(c->bvh.max_depth + 1);
   c->bvh_built = true;
   c->scene_dirty = false;
   return ok(c);
