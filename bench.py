@@ -29,10 +29,12 @@ METRIC = "path samples/s at 1080p; NIF rays/s + MFMA util vs env-map lookup at e
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"fp16": 2500.0, "bf16": 2500.0, "fp8": 5000.0, "fp32": 157.3}
 NIF_FLOP_PER_QUERY = 2 * (64 * 96 + 4 * 96 * 96 + 96 * 3)  # 86,592
-# algorithmic bytes of the trace kernel: ray in 48 B, 64 B per
-# BVH node fetched, 48 B per primitive slot tested, 80 B per hit (slot re-read
-# + material), 32 B per escaped ray (environment queue), 48 B per survivor
-B_RAY, B_NODE, B_PRIM, B_HIT, B_ESC, B_OUT = 48, 64, 48, 80, 32, 48
+# algorithmic bytes of the trace kernel: ray in 48 B, one node
+# per BVH node fetched (64 B two-wide, 112 B four-wide), 48 B per primitive
+# slot tested, 80 B per hit (slot re-read + material), 32 B per escaped ray
+# (environment queue), 48 B per survivor
+B_RAY, B_PRIM, B_HIT, B_ESC, B_OUT = 48, 48, 80, 32, 48
+B_NODE = {2: 64, 4: 112}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_trace_small_bvh_1080p_traffic.json")
 
 
@@ -133,8 +135,8 @@ def main():
     extra = {}
     try:
         t0 = time.perf_counter()
-        # leaf size 2, no LDS-staged levels: fastest in the trace-kernel sweep
-        npt.npt_load_scene(ctx, scene, max_leaf=2, lds_levels=0)
+        # 4-wide BVH, leaf size 2, no LDS-staged levels: fastest in the sweep
+        npt.npt_load_scene(ctx, scene, max_leaf=2, lds_levels=0, width=4)
         extra["bvh_build_ms"] = 1e3 * (time.perf_counter() - t0)
         extra["bvh"] = npt.npt_bvh_info(ctx)
         npt.npt_env_upload(ctx, env)
@@ -167,7 +169,7 @@ def main():
         tests = np.array(cs["prim_tests"], np.float64)
         survivors = np.concatenate([rays[1:], [0.0]])
         hits = rays - esc
-        alg_bytes = float(np.sum(B_RAY * rays + B_NODE * visits + B_PRIM * tests + B_HIT * hits
+        alg_bytes = float(np.sum(B_RAY * rays + B_NODE[extra["bvh"]["width"]] * visits + B_PRIM * tests + B_HIT * hits
                                  + B_ESC * esc + B_OUT * survivors))
         extra["per_ray"] = {"node_visits": float(visits.sum() / rays.sum()),
                             "prim_tests": float(tests.sum() / rays.sum()),

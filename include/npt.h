@@ -76,11 +76,13 @@ typedef struct {
 /* Host BVH build (Sec. 3.1.4 builds a BVH2 on the host).  bins: SAH bins per
  * axis (4..256, 0 = 32); max_leaf: primitives per leaf (1..8, 0 = 4);
  * lds_levels: top tree levels staged in LDS by the traversal kernel (0..8,
- * 0 = none). */
+ * 0 = none); width: children per node, 2 (the paper's BVH2) or 4 (the
+ * binary SAH tree collapsed to 4-wide nodes), 0 = 4. */
 typedef struct {
     uint32_t bins;
     uint32_t max_leaf;
     uint32_t lds_levels;
+    uint32_t width;
 } npt_bvh_params;
 
 /* HDR-NIF shape (Sec. 3.2): 4*n_freq Fourier features -> layers x
@@ -117,7 +119,8 @@ typedef struct {
 
 /* Render options.  rr_start: first depth with Russian roulette (Sec. 4: 3);
  * samples_per_pass: samples traced together (0 = library default, sized
- * from the pool); pool_paths: upper bound on paths in flight (0 = 2^23);
+ * from the pool); pool_paths: upper bound on paths in flight (0 = 2^26,
+ * 144 bytes of device queues per path);
  * kernel_timing: 1 = time every trace and environment launch with HIP
  * events on the render stream (npt_stats.ms_trace / ms_env);
  * count_visits: 1 = use the counting variant of the trace kernel
@@ -177,9 +180,10 @@ int npt_scene_materials(npt_ctx *ctx, const npt_material *m, uint32_t n);
  * `stream`.  NPT_E_NO_SCENE if no geometry; NPT_E_NO_DEVICE only for the
  * upload on a host-only context (the host build still happens). */
 int npt_build_bvh(npt_ctx *ctx, const npt_bvh_params *p, void *stream);
-/* Host-side BVH summary for tests: nodes, leaves, max depth, prim slots. */
+/* Host-side BVH summary: nodes, leaves, max depth (root = 0), primitive
+ * slots, children per node.  Any output may be NULL. */
 int npt_bvh_info(npt_ctx *ctx, uint64_t *nodes, uint64_t *leaves, uint32_t *max_depth,
-                 uint64_t *prim_slots);
+                 uint64_t *prim_slots, uint32_t *width);
 int npt_set_camera(npt_ctx *ctx, const npt_camera *cam);
 int npt_set_render_options(npt_ctx *ctx, const npt_render_options *opt);
 

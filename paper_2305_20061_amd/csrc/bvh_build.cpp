@@ -156,9 +156,79 @@ inline float bits(uint32_t u) {
   return f;
 }
 
+inline uint32_t ubits(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  return u;
+}
+
+// Structural check of a flattened tree before it is uploaded: every ref in
+// range, every node reached exactly once from the root, every primitive slot
+// covered by exactly one leaf, depth within max_depth.
+bool check_flat(const FlatBvh& b, std::string& err) {
+  const size_t nn = b.nodes.size() / b.node_float4s, ns = b.slots.size() / 3;
+  std::vector<uint8_t> seen(nn, 0), covered(ns, 0);
+  std::vector<std::pair<uint32_t, uint32_t>> st{{0u, 0u}};
+  while (!st.empty()) {
+    const auto [id, depth] = st.back();
+    st.pop_back();
+    if (id >= nn || seen[id]) {
+      err = "flattened BVH: node reached twice or out of range";
+      return false;
+    }
+    if (depth > b.max_depth) {
+      err = "flattened BVH: depth exceeds max_depth";
+      return false;
+    }
+    seen[id] = 1;
+    const float4* o = &b.nodes[(size_t)id * b.node_float4s];
+    uint32_t refs[4];
+    int nref = 0;
+    if (b.width == 2) {
+      refs[nref++] = ubits(o[3].x);
+      if (ubits(o[3].y) != ubits(o[3].x)) refs[nref++] = ubits(o[3].y);
+    } else {
+      const uint32_t r[4] = {ubits(o[6].x), ubits(o[6].y), ubits(o[6].z), ubits(o[6].w)};
+      for (uint32_t x : r)
+        if (x != kEmptyChild) refs[nref++] = x;
+    }
+    for (int k = 0; k < nref; ++k) {
+      const uint32_t r = refs[k];
+      if (r & kLeafBit) {
+        const uint32_t first = (r >> 3) & 0x0FFFFFFFu, count = (r & 7u) + 1u;
+        if ((uint64_t)first + count > ns) {
+          err = "flattened BVH: leaf beyond the primitive slots";
+          return false;
+        }
+        for (uint32_t i = first; i < first + count; ++i) {
+          if (covered[i]) {
+            err = "flattened BVH: primitive slot in two leaves";
+            return false;
+          }
+          covered[i] = 1;
+        }
+      } else {
+        st.push_back({r, depth + 1});
+      }
+    }
+  }
+  for (size_t i = 0; i < nn; ++i)
+    if (!seen[i]) {
+      err = "flattened BVH: unreachable node";
+      return false;
+    }
+  for (size_t i = 0; i < ns; ++i)
+    if (!covered[i]) {
+      err = "flattened BVH: primitive slot in no leaf";
+      return false;
+    }
+  return true;
+}
+
 }  // namespace
 
-bool build_bvh(const BuildInput& in, uint32_t bins, uint32_t max_leaf, uint32_t lds_levels, FlatBvh& out,
+bool build_bvh(const BuildInput& in, uint32_t bins, uint32_t max_leaf, uint32_t lds_levels, uint32_t width,
+               FlatBvh& out,
                std::string& err) {
   out = FlatBvh();
   const uint64_t n = in.nt + in.ns;
@@ -207,7 +277,44 @@ bool build_bvh(const BuildInput& in, uint32_t bins, uint32_t max_leaf, uint32_t 
     B.nodes[0].child[0] = B.nodes[0].child[1] = (int32_t)B.nodes.size() - 1;
   }
 
-  // flat index of every inner node: BFS for depth < lds_levels, then DFS
+  // wide nodes: the children of a binary inner node, widened (for width 4) by
+  // repeatedly opening the inner child with the largest surface area
+  std::vector<std::vector<int>> kids(B.nodes.size());
+  std::vector<uint32_t> wdepth(B.nodes.size(), 0);
+  std::vector<int> wide;  // binary ids that become wide nodes, parents first
+  {
+    std::vector<int> st{0};
+    while (!st.empty()) {
+      const int id = st.back();
+      st.pop_back();
+      wide.push_back(id);
+      std::vector<int> ch{B.nodes[id].child[0], B.nodes[id].child[1]};
+      if (ch[0] == ch[1]) ch.pop_back();  // leaf root
+      while ((int)ch.size() < (int)width) {
+        int best = -1;
+        double area = -1.0;
+        for (size_t i = 0; i < ch.size(); ++i) {
+          const Node& c = B.nodes[ch[i]];
+          if (!c.leaf() && c.box.half_area() > area) {
+            area = c.box.half_area();
+            best = (int)i;
+          }
+        }
+        if (best < 0) break;
+        const int open = ch[best];
+        ch.erase(ch.begin() + best);
+        ch.push_back(B.nodes[open].child[0]);
+        ch.push_back(B.nodes[open].child[1]);
+      }
+      for (int c : ch) {
+        if (B.nodes[c].leaf()) continue;
+        wdepth[c] = wdepth[id] + 1;
+        st.push_back(c);
+      }
+      kids[id] = std::move(ch);
+    }
+  }
+  // flat index of every wide node: BFS for depth < lds_levels, then DFS
   std::vector<int64_t> flat(B.nodes.size(), -1);
   uint32_t next = 0;
   {
@@ -216,11 +323,9 @@ bool build_bvh(const BuildInput& in, uint32_t bins, uint32_t max_leaf, uint32_t 
     while (!q.empty()) {
       const int id = q.front();
       q.pop_front();
-      const Node& nd = B.nodes[id];
-      if (nd.leaf() || nd.depth >= lds_levels || next >= kMaxLdsNodes) continue;
+      if (B.nodes[id].leaf() || wdepth[id] >= lds_levels || next >= kMaxLdsNodes) continue;
       flat[id] = next++;
-      q.push_back(nd.child[0]);
-      q.push_back(nd.child[1]);
+      for (int c : kids[id]) q.push_back(c);
     }
     out.lds_nodes = next;
   }
@@ -229,34 +334,52 @@ bool build_bvh(const BuildInput& in, uint32_t bins, uint32_t max_leaf, uint32_t 
     while (!st.empty()) {
       const int id = st.back();
       st.pop_back();
-      const Node& nd = B.nodes[id];
-      if (nd.leaf()) continue;
+      if (B.nodes[id].leaf()) continue;
       if (flat[id] < 0) flat[id] = next++;
-      out.max_depth = std::max(out.max_depth, nd.depth);
-      st.push_back(nd.child[1]);
-      st.push_back(nd.child[0]);
+      out.max_depth = std::max(out.max_depth, wdepth[id]);
+      for (auto it = kids[id].rbegin(); it != kids[id].rend(); ++it) st.push_back(*it);
     }
   }
-  out.nodes.assign((size_t)next * 4, make_float4(0, 0, 0, 0));
-  for (size_t id = 0; id < B.nodes.size(); ++id) {
-    const Node& nd = B.nodes[id];
-    if (nd.leaf() || flat[id] < 0) continue;
-    float lo[2][3], hi[2][3];
-    uint32_t ref[2];
-    for (int c = 0; c < 2; ++c) {
-      const Node& ch = B.nodes[nd.child[c]];
-      padded(ch.box, lo[c], hi[c]);
-      if (ch.leaf()) {
-        ref[c] = kLeafBit | (ch.first << 3) | (ch.count - 1);
+  out.width = width;
+  out.node_float4s = width == 2 ? 4 : 7;
+  out.nodes.assign((size_t)next * out.node_float4s, make_float4(0, 0, 0, 0));
+  for (int id : wide) {
+    const std::vector<int>& ch = kids[id];
+    float lo[4][3], hi[4][3];
+    uint32_t ref[4];
+    for (int c = 0; c < 4; ++c) {
+      if (c < (int)ch.size()) {
+        const Node& k = B.nodes[ch[c]];
+        padded(k.box, lo[c], hi[c]);
+        ref[c] = k.leaf() ? (kLeafBit | (k.first << 3) | (k.count - 1)) : (uint32_t)flat[ch[c]];
       } else {
-        ref[c] = (uint32_t)flat[nd.child[c]];
+        for (int a = 0; a < 3; ++a) {
+          lo[c][a] = INFINITY;
+          hi[c][a] = -INFINITY;
+        }
+        ref[c] = kEmptyChild;
       }
     }
-    float4* o = &out.nodes[(size_t)flat[id] * 4];
-    o[0] = make_float4(lo[0][0], hi[0][0], lo[0][1], hi[0][1]);
-    o[1] = make_float4(lo[1][0], hi[1][0], lo[1][1], hi[1][1]);
-    o[2] = make_float4(lo[0][2], hi[0][2], lo[1][2], hi[1][2]);
-    o[3] = make_float4(bits(ref[0]), bits(ref[1]), 0.0f, 0.0f);
+    float4* o = &out.nodes[(size_t)flat[id] * out.node_float4s];
+    if (width == 2) {
+      if (ch.size() == 1) {  // single-leaf scene: the leaf as both children
+        for (int a = 0; a < 3; ++a) {
+          lo[1][a] = lo[0][a];
+          hi[1][a] = hi[0][a];
+        }
+        ref[1] = ref[0];
+      }
+      o[0] = make_float4(lo[0][0], hi[0][0], lo[0][1], hi[0][1]);
+      o[1] = make_float4(lo[1][0], hi[1][0], lo[1][1], hi[1][1]);
+      o[2] = make_float4(lo[0][2], hi[0][2], lo[1][2], hi[1][2]);
+      o[3] = make_float4(bits(ref[0]), bits(ref[1]), 0.0f, 0.0f);
+    } else {
+      for (int a = 0; a < 3; ++a) {
+        o[2 * a] = make_float4(lo[0][a], lo[1][a], lo[2][a], lo[3][a]);
+        o[2 * a + 1] = make_float4(hi[0][a], hi[1][a], hi[2][a], hi[3][a]);
+      }
+      o[6] = make_float4(bits(ref[0]), bits(ref[1]), bits(ref[2]), bits(ref[3]));
+    }
   }
   for (const Node& nd : B.nodes)
     if (nd.leaf()) ++out.leaves;
@@ -284,7 +407,7 @@ bool build_bvh(const BuildInput& in, uint32_t bins, uint32_t max_leaf, uint32_t 
       s[2] = make_float4(0.0f, 0.0f, 0.0f, bits(kPrimSphere));
     }
   }
-  return true;
+  return check_flat(out, err);
 }
 
 }  // namespace npt

@@ -23,16 +23,20 @@ struct BuildInput {
 struct FlatBvh {
   std::vector<float4> nodes;  // 4 float4 per node (npt_shared.h layout)
   std::vector<float4> slots;  // 3 float4 per primitive slot
+  uint32_t width = 2;         // children per node (2 or 4)
+  uint32_t node_float4s = 4;  // float4s per node (4 for width 2, 7 for width 4)
   uint32_t lds_nodes = 0;     // BFS-ordered top nodes staged in LDS
   uint32_t max_depth = 0;     // deepest inner node (root = 0)
   uint64_t leaves = 0;
   float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};  // bounds of all primitives
 };
 
-// Binned-SAH build (bins per axis, primitives per leaf <= max_leaf), then
-// flattening: the inner nodes of the top lds_levels levels first in BFS
-// order, the rest depth-first.  Returns false with a message on failure.
-bool build_bvh(const BuildInput& in, uint32_t bins, uint32_t max_leaf, uint32_t lds_levels, FlatBvh& out,
+// Binned-SAH build of a binary tree (bins per axis, primitives per leaf <=
+// max_leaf), collapsed to `width` children per node (2 or 4), then
+// flattening: the nodes of the top lds_levels levels first in BFS order, the
+// rest depth-first.  Returns false with a message on failure.
+bool build_bvh(const BuildInput& in, uint32_t bins, uint32_t max_leaf, uint32_t lds_levels, uint32_t width,
+               FlatBvh& out,
                std::string& err);
 
 }  // namespace npt

@@ -162,6 +162,11 @@ __global__ __launch_bounds__(kNifBlock, 1) void k_nif_infer(const typename Prec<
   extern __shared__ float4 smem4[];
   Frag* lfrags = reinterpret_cast<Frag*>(smem4);
   float* lbias = reinterpret_cast<float*>(lfrags + (size_t)lds_frag_offset<P>(kLayers + 1) * 64);
+  uint64_t n;
+  if (io.source == kSrcQueue) n = io.cnt[kCntEnv + io.depth];
+  else n = io.n;
+  // workgroups without a tile leave before staging the weights
+  if ((uint64_t)blockIdx.x * kNifWaves * kRays >= n) return;
 
   // stage the resident layers and the biases
   for (int l = 0; l <= kLayers; ++l) {
@@ -175,9 +180,6 @@ __global__ __launch_bounds__(kNifBlock, 1) void k_nif_infer(const typename Prec<
 
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int h = lane / 32, col = lane % 32;
-  uint64_t n;
-  if (io.source == kSrcQueue) n = io.cnt[kCntEnv + io.depth];
-  else n = io.n;
   const uint64_t waves_total = (uint64_t)gridDim.x * kNifWaves;
 
   for (uint64_t tile = (uint64_t)blockIdx.x * kNifWaves + wave; tile * kRays < n; tile += waves_total) {

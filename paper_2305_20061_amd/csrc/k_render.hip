@@ -153,6 +153,104 @@ __device__ __forceinline__ Hit closest_hit(const SceneView& sc, const float4* ld
   return h;
 }
 
+// compare-exchange of (entry distance, ref) pairs, ascending by distance
+__device__ __forceinline__ void order2(float& ka, uint32_t& ra, float& kb, uint32_t& rb) {
+  const bool sw = kb < ka;
+  const float k = sw ? kb : ka;
+  const uint32_t r = sw ? rb : ra;
+  kb = sw ? ka : kb;
+  rb = sw ? ra : rb;
+  ka = k;
+  ra = r;
+}
+
+// one child of a 4-wide node: entry distance, or +inf when missed or empty
+__device__ __forceinline__ float child_entry(float lx, float hx, float ly, float hy, float lz, float hz, float ix,
+                                             float iy, float iz, float ox, float oy, float oz, float lim,
+                                             uint32_t ref) {
+  const float a0 = __builtin_fmaf(lx, ix, -ox), a1 = __builtin_fmaf(hx, ix, -ox);
+  const float b0 = __builtin_fmaf(ly, iy, -oy), b1 = __builtin_fmaf(hy, iy, -oy);
+  const float c0 = __builtin_fmaf(lz, iz, -oz), c1 = __builtin_fmaf(hz, iz, -oz);
+  const float tn = fmaxf(fmaxf(fminf(a0, a1), fminf(b0, b1)), fmaxf(fminf(c0, c1), 0.0f));
+  const float tf = fminf(fminf(fmaxf(a0, a1), fmaxf(b0, b1)), fminf(fmaxf(c0, c1), lim));
+  return (tn <= tf && ref != kEmptyChild) ? tn : __builtin_inff();
+}
+
+// Closest hit on the 4-wide BVH: the children a ray enters are visited
+// nearest first (sorting network on entry distance), the rest pushed far to
+// near.  Same primitive tests and tie rule as the binary traversal.
+template <int kStack, int kStride, bool kCount = false>
+__device__ __forceinline__ Hit closest_hit4(const SceneView& sc, const float4* lds_nodes, uint32_t* stack, V3 o,
+                                            V3 d, uint32_t* n_nodes = nullptr, uint32_t* n_prims = nullptr) {
+  Hit h{__builtin_inff(), kMiss, kMiss};
+  if (!sc.has_geometry) return h;
+  const Shear sh = make_shear(d);
+  const float ix = safe_inverse(d.x), iy = safe_inverse(d.y), iz = safe_inverse(d.z);
+  const float ox = o.x * ix, oy = o.y * iy, oz = o.z * iz;
+  const float inf = __builtin_inff();
+  uint32_t ref = 0;
+  int sp = 0;
+  for (uint32_t visits = 0; visits < kMaxVisits; ++visits) {
+    if ((ref & kLeafBit) == 0u) {
+      const float4* p = ref < sc.lds_nodes ? lds_nodes + 7 * ref : sc.nodes + 7 * (size_t)ref;
+      const float4 lx = p[0], hx = p[1], ly = p[2], hy = p[3], lz = p[4], hz = p[5], rf = p[6];
+      if constexpr (kCount) ++*n_nodes;
+      const float lim = h.t * 1.000001f;
+      uint32_t r0 = __float_as_uint(rf.x), r1 = __float_as_uint(rf.y), r2 = __float_as_uint(rf.z),
+               r3 = __float_as_uint(rf.w);
+      float k0 = child_entry(lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, ix, iy, iz, ox, oy, oz, lim, r0);
+      float k1 = child_entry(lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, ix, iy, iz, ox, oy, oz, lim, r1);
+      float k2 = child_entry(lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, ix, iy, iz, ox, oy, oz, lim, r2);
+      float k3 = child_entry(lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, ix, iy, iz, ox, oy, oz, lim, r3);
+      order2(k0, r0, k1, r1);
+      order2(k2, r2, k3, r3);
+      order2(k0, r0, k2, r2);
+      order2(k1, r1, k3, r3);
+      order2(k1, r1, k2, r2);
+      if (k0 < inf) {
+        if (k3 < inf && sp < kStack) stack[(sp++) * kStride] = r3;
+        if (k2 < inf && sp < kStack) stack[(sp++) * kStride] = r2;
+        if (k1 < inf && sp < kStack) stack[(sp++) * kStride] = r1;
+        ref = r0;
+        continue;
+      }
+    } else {
+      const uint32_t first = (ref >> 3) & 0x0FFFFFFFu;
+      const uint32_t count = (ref & 7u) + 1u;
+      if constexpr (kCount) *n_prims += count;
+      for (uint32_t i = 0; i < count; ++i) {
+        const float4* s = sc.slots + 3 * (size_t)(first + i);
+        const float4 s0 = s[0], s1 = s[1], s2 = s[2];
+        const uint32_t prim = __float_as_uint(s0.w);
+        float t = 0.0f;
+        bool hit;
+        if (__float_as_uint(s2.w) == kPrimTriangle)
+          hit = hit_triangle(o, sh, V3{s0.x, s0.y, s0.z}, V3{s1.x, s1.y, s1.z}, V3{s2.x, s2.y, s2.z}, h.t, t);
+        else
+          hit = hit_sphere(o, d, V3{s0.x, s0.y, s0.z}, s1.x, h.t, t);
+        if (hit && (t < h.t || prim < h.prim)) {
+          h.t = t;
+          h.slot = first + i;
+          h.prim = prim;
+        }
+      }
+    }
+    if (sp == 0) break;
+    --sp;
+    ref = stack[sp * kStride];
+  }
+  return h;
+}
+
+template <int kWidth, int kStack, int kStride, bool kCount = false>
+__device__ __forceinline__ Hit trace_closest(const SceneView& sc, const float4* lds_nodes, uint32_t* stack, V3 o,
+                                             V3 d, uint32_t* n_nodes = nullptr, uint32_t* n_prims = nullptr) {
+  if constexpr (kWidth == 4)
+    return closest_hit4<kStack, kStride, kCount>(sc, lds_nodes, stack, o, d, n_nodes, n_prims);
+  else
+    return closest_hit<kStack, kStride, kCount>(sc, lds_nodes, stack, o, d, n_nodes, n_prims);
+}
+
 // geometric normal of a hit slot (unit for triangles; (p - c) / r for spheres)
 __device__ __forceinline__ V3 slot_normal(const float4* slots, uint32_t slot, V3 p, uint32_t& material) {
   const float4* s = slots + 3 * (size_t)slot;
@@ -166,7 +264,7 @@ __device__ __forceinline__ V3 slot_normal(const float4* slots, uint32_t slot, V3
 }
 
 __device__ __forceinline__ void stage_lds_nodes(const SceneView& sc, float4* lds) {
-  for (uint32_t i = threadIdx.x; i < 4 * sc.lds_nodes; i += blockDim.x) lds[i] = sc.nodes[i];
+  for (uint32_t i = threadIdx.x; i < sc.node_float4s * sc.lds_nodes; i += blockDim.x) lds[i] = sc.nodes[i];
   __syncthreads();
 }
 
@@ -198,7 +296,7 @@ __global__ void k_pass_init(uint32_t* cnt, uint32_t paths) {
 // trace: closest hit + shading of every ray entering depth `depth`.
 // Escaped rays go to the environment queue; survivors to the next queue.
 // ---------------------------------------------------------------------------
-template <int kStack, bool kCount>
+template <int kWidth, int kStack, bool kCount>
 __global__ __launch_bounds__(kTraceBlock) void k_trace(SceneView sc, PassView pv, uint32_t depth,
                                                        RayQueue in, RayQueue out, EnvQueue env,
                                                        float4* L, uint32_t* cnt, unsigned long long* visit_cnt) {
@@ -211,14 +309,17 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(SceneView sc, PassView pv
   uint32_t* stack = stack_mem + threadIdx.x;
   constexpr int kStride = kTraceBlock;
 #endif
-  stage_lds_nodes(sc, lds_nodes);
+  // the grid is sized for the largest possible queue; workgroups beyond the
+  // actual ray count leave before any staging or atomic
   const uint32_t n = cnt[kCntRays + depth];
+  if ((uint64_t)blockIdx.x * kTraceBlock >= n) return;
+  stage_lds_nodes(sc, lds_nodes);
   const uint32_t lane = threadIdx.x & (kWave - 1);
+  constexpr uint32_t kWavesPerBlock = kTraceBlock / kWave;
   uint32_t n_nodes = 0, n_prims = 0;
-  for (;;) {
-    uint32_t chunk = 0;
-    if (lane == 0) chunk = atomicAdd(&cnt[kCntWork + depth], 1u);
-    chunk = __shfl(chunk, 0);
+  // first chunk static (one per wave of the grid), then work stealing
+  uint32_t chunk = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+  for (;; ) {
     const uint32_t i = chunk * kWave + lane;
     if (chunk * kWave >= n) break;
     const bool valid = i < n;
@@ -234,7 +335,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(SceneView sc, PassView pv
     }
     const uint32_t slot = (sample - pv.sample0) * pv.pixels + pixel;
     Hit h{__builtin_inff(), kMiss, kMiss};
-    if (valid) h = closest_hit<kStack, kStride, kCount>(sc, lds_nodes, stack, o, d, &n_nodes, &n_prims);
+    if (valid) h = trace_closest<kWidth, kStack, kStride, kCount>(sc, lds_nodes, stack, o, d, &n_nodes, &n_prims);
     const bool escaped = valid && h.slot == kMiss;
     bool alive = false;
     V3 no{0, 0, 0}, nd{0, 0, 1};
@@ -291,6 +392,9 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(SceneView sc, PassView pv
       out.d[oi] = make_float4(nd.x, nd.y, nd.z, __uint_as_float(sample));
       out.b[oi] = make_float4(beta.x, beta.y, beta.z, 0.0f);
     }
+    uint32_t next = 0;
+    if (lane == 0) next = gridDim.x * kWavesPerBlock + atomicAdd(&cnt[kCntWork + depth], 1u);
+    chunk = __shfl(next, 0);
   }
   if constexpr (kCount) {
     atomicAdd(&visit_cnt[depth - 1], (unsigned long long)n_nodes);
@@ -359,7 +463,7 @@ __global__ __launch_bounds__(256) void k_finalize(const float4* accum, float* ou
 // ---------------------------------------------------------------------------
 // primary hits (Table 3-style checks)
 // ---------------------------------------------------------------------------
-template <int kStack>
+template <int kWidth, int kStack>
 __global__ __launch_bounds__(kTraceBlock) void k_trace_primary(SceneView sc, CameraView cam, PassView pv,
                                                                uint32_t* prim, uint32_t* inst, float* tout,
                                                                float* normal) {
@@ -375,7 +479,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_primary(SceneView sc, Cam
     const U4 r = philox(pixel, pv.sample0, 0, kRngCamera, pv.key0, pv.key1);
     const V3 d = camera_direction(cam, pv.width, pv.height, x, y, unit_float(r.x), unit_float(r.y));
     const V3 o{cam.eye[0], cam.eye[1], cam.eye[2]};
-    const Hit h = closest_hit<kStack, kTraceBlock>(sc, lds_nodes, stack, o, d);
+    const Hit h = trace_closest<kWidth, kStack, kTraceBlock>(sc, lds_nodes, stack, o, d);
     V3 n{0, 0, 0};
     if (h.slot != kMiss) {
       uint32_t mat;
@@ -438,20 +542,27 @@ hipError_t launch_generate(const CameraView& cam, const PassView& pv, const RayQ
 hipError_t launch_trace(int stack_depth, const SceneView& sc, const PassView& pv, uint32_t depth,
                         uint64_t max_rays, const RayQueue& in, const RayQueue& out, const EnvQueue& env,
                         float4* L, uint32_t* cnt, unsigned long long* visit_cnt, int num_cus, hipStream_t s) {
-  const size_t lds = (size_t)sc.lds_nodes * 4 * sizeof(float4);
+  const size_t lds = (size_t)sc.lds_nodes * sc.node_float4s * sizeof(float4);
   const int grid = grid_for(max_rays, kTraceBlock, num_cus * 32);
-#define NPT_LAUNCH_TRACE(S, C)                                                                               \
-  hipLaunchKernelGGL((k_trace<S, C>), dim3(grid), dim3(kTraceBlock), lds, s, sc, pv, depth, in, out, env, L, \
+#define NPT_LAUNCH_TRACE(W, S, C)                                                                               \
+  hipLaunchKernelGGL((k_trace<W, S, C>), dim3(grid), dim3(kTraceBlock), lds, s, sc, pv, depth, in, out, env, L, \
                      cnt, visit_cnt)
-  const bool c = visit_cnt != nullptr;
-  switch (stack_depth) {
-    case 16: if (c) NPT_LAUNCH_TRACE(16, true); else NPT_LAUNCH_TRACE(16, false); break;
-    case 24: if (c) NPT_LAUNCH_TRACE(24, true); else NPT_LAUNCH_TRACE(24, false); break;
-    case 32: if (c) NPT_LAUNCH_TRACE(32, true); else NPT_LAUNCH_TRACE(32, false); break;
-    case 48: if (c) NPT_LAUNCH_TRACE(48, true); else NPT_LAUNCH_TRACE(48, false); break;
-    case 64: if (c) NPT_LAUNCH_TRACE(64, true); else NPT_LAUNCH_TRACE(64, false); break;
-    default: return hipErrorInvalidValue;
+#define NPT_LAUNCH_TRACE_S(W)                                                                   \
+  switch (stack_depth) {                                                                       \
+    case 16: if (c) NPT_LAUNCH_TRACE(W, 16, true); else NPT_LAUNCH_TRACE(W, 16, false); break; \
+    case 24: if (c) NPT_LAUNCH_TRACE(W, 24, true); else NPT_LAUNCH_TRACE(W, 24, false); break; \
+    case 32: if (c) NPT_LAUNCH_TRACE(W, 32, true); else NPT_LAUNCH_TRACE(W, 32, false); break; \
+    case 48: if (c) NPT_LAUNCH_TRACE(W, 48, true); else NPT_LAUNCH_TRACE(W, 48, false); break; \
+    case 64: if (c) NPT_LAUNCH_TRACE(W, 64, true); else NPT_LAUNCH_TRACE(W, 64, false); break; \
+    default: return hipErrorInvalidValue;                                                      \
   }
+  const bool c = visit_cnt != nullptr;
+  if (sc.width == 4) {
+    NPT_LAUNCH_TRACE_S(4)
+  } else {
+    NPT_LAUNCH_TRACE_S(2)
+  }
+#undef NPT_LAUNCH_TRACE_S
 #undef NPT_LAUNCH_TRACE
   return hipGetLastError();
 }
@@ -493,16 +604,17 @@ hipError_t launch_finalize(const float4* accum, float* out, uint32_t pixels, flo
 hipError_t launch_trace_primary(int stack_depth, const SceneView& sc, const CameraView& cam, const PassView& pv,
                                 uint32_t* prim, uint32_t* inst, float* t, float* normal, int num_cus,
                                 hipStream_t s) {
-  const size_t lds = (size_t)sc.lds_nodes * 4 * sizeof(float4);
+  const size_t lds = (size_t)sc.lds_nodes * sc.node_float4s * sizeof(float4);
   const int grid = grid_for(pv.pixels, kTraceBlock, num_cus * 16);
-  // primary rays of a well-formed tree never need more than the full stack
-  if (stack_depth <= 32) {
-    hipLaunchKernelGGL(k_trace_primary<32>, dim3(grid), dim3(kTraceBlock), lds, s, sc, cam, pv, prim, inst, t,
-                       normal);
+#define NPT_LAUNCH_PRIMARY(W, S)                                                                                   \
+  hipLaunchKernelGGL((k_trace_primary<W, S>), dim3(grid), dim3(kTraceBlock), lds, s, sc, cam, pv, prim, inst, t, \
+                     normal)
+  if (sc.width == 4) {
+    if (stack_depth <= 32) NPT_LAUNCH_PRIMARY(4, 32); else NPT_LAUNCH_PRIMARY(4, 64);
   } else {
-    hipLaunchKernelGGL(k_trace_primary<64>, dim3(grid), dim3(kTraceBlock), lds, s, sc, cam, pv, prim, inst, t,
-                       normal);
+    if (stack_depth <= 32) NPT_LAUNCH_PRIMARY(2, 32); else NPT_LAUNCH_PRIMARY(2, 64);
   }
+#undef NPT_LAUNCH_PRIMARY
   return hipGetLastError();
 }
 

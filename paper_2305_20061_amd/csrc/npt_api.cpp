@@ -172,6 +172,8 @@ SceneView scene_view(npt_ctx* c) {
   s.materials = c->d_mats.as<float4>();
   s.lds_nodes = c->bvh.lds_nodes;
   s.has_geometry = c->bvh_built ? 1u : 0u;
+  s.width = c->bvh.width;
+  s.node_float4s = c->bvh.node_float4s;
   return s;
 }
 
@@ -319,6 +321,8 @@ extern "C" int npt_build_bvh(npt_ctx* c, const npt_bvh_params* p, void* stream) 
   if (!c) return NPT_E_INVALID_ARG;
   uint32_t bins = p && p->bins ? p->bins : 32, max_leaf = p && p->max_leaf ? p->max_leaf : 4;
   uint32_t lds_levels = p ? p->lds_levels : 0;
+  const uint32_t width = p && p->width ? p->width : 4;
+  if (width != 2 && width != 4) return fail(c, NPT_E_INVALID_ARG, "BVH width must be 2 or 4");
   if (bins < 4 || bins > 256 || max_leaf < 1 || max_leaf > kMaxLeaf || lds_levels > 8)
     return fail(c, NPT_E_INVALID_ARG, "bvh params out of range");
   if (c->tris.empty() && c->spheres.empty()) return fail(c, NPT_E_NO_SCENE, "no geometry uploaded");
@@ -338,8 +342,11 @@ extern "C" int npt_build_bvh(npt_ctx* c, const npt_bvh_params* p, void* stream) 
   in.sph_mat = c->sph_mat.data();
   FlatBvh b;
   std::string e;
-  if (!build_bvh(in, bins, max_leaf, lds_levels, b, e)) return fail(c, NPT_E_INVALID_ARG, e);
-  if (b.max_depth + 1 > 64) return fail(c, NPT_E_UNSUPPORTED, "BVH deeper than the 64-entry traversal stack");
+  if (!build_bvh(in, bins, max_leaf, lds_levels, width, b, e)) return fail(c, NPT_E_INVALID_ARG, e);
+  // traversal stack: one deferred child per level (width 2), up to three (width 4)
+  const uint32_t stack_need = (width == 2 ? 1 : 3) * b.max_depth + 1;
+  if (trace_stack_size(stack_need) == 0)
+    return fail(c, NPT_E_UNSUPPORTED, "BVH deeper than the 64-entry traversal stack");
   c->bvh = std::move(b);
   c->bvh_built = false;
   if (c->host_only) return fail(c, NPT_E_NO_DEVICE, "BVH built on the host; no device to upload to");
@@ -355,19 +362,21 @@ extern "C" int npt_build_bvh(npt_ctx* c, const npt_bvh_params* p, void* stream) 
   HIP_TRY(c, hipStreamSynchronize(s));
   r = upload_materials(c, s);
   if (r) return r;
-  c->stack_depth = trace_stack_size(c->bvh.max_depth + 1);
+  c->stack_depth = trace_stack_size((c->bvh.width == 2 ? 1 : 3) * c->bvh.max_depth + 1);
   c->bvh_built = true;
   c->scene_dirty = false;
   return ok(c);
 }
 
-extern "C" int npt_bvh_info(npt_ctx* c, uint64_t* nodes, uint64_t* leaves, uint32_t* max_depth, uint64_t* slots) {
+extern "C" int npt_bvh_info(npt_ctx* c, uint64_t* nodes, uint64_t* leaves, uint32_t* max_depth, uint64_t* slots,
+                            uint32_t* width) {
   if (!c) return NPT_E_INVALID_ARG;
   if (c->bvh.nodes.empty()) return fail(c, NPT_E_STATE, "no BVH built");
-  if (nodes) *nodes = c->bvh.nodes.size() / 4;
+  if (nodes) *nodes = c->bvh.nodes.size() / c->bvh.node_float4s;
   if (leaves) *leaves = c->bvh.leaves;
   if (max_depth) *max_depth = c->bvh.max_depth;
   if (slots) *slots = c->bvh.slots.size() / 3;
+  if (width) *width = c->bvh.width;
   return ok(c);
 }
 
@@ -646,7 +655,9 @@ extern "C" int npt_render(npt_ctx* c, uint32_t W, uint32_t H, uint32_t spp, uint
   hipStream_t s = (hipStream_t)stream;
 
   const uint64_t pixels = (uint64_t)W * H;
-  const uint64_t pool = c->opt.pool_paths ? c->opt.pool_paths : (1ull << 23);
+  // default pool: 2^26 paths in flight (a whole 1080p x 32 spp frame per
+  // pass; 144 B of queues per path = 9.7 GB of the 288 GB of HBM)
+  const uint64_t pool = c->opt.pool_paths ? c->opt.pool_paths : (1ull << 26);
   uint64_t sp = c->opt.samples_per_pass ? c->opt.samples_per_pass : std::max<uint64_t>(1, pool / pixels);
   sp = std::min<uint64_t>(sp, spp);
   while (sp > 1 && pixels * sp >= (1ull << 31)) --sp;

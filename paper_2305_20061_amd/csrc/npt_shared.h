@@ -15,6 +15,12 @@ constexpr uint32_t kLeafBit = 0x80000000u;
 constexpr uint32_t kMaxLeaf = 8;
 constexpr uint32_t kMaxSlots = 1u << 28;
 constexpr uint32_t kMaxLdsNodes = 255;
+constexpr uint32_t kEmptyChild = 0x7FFFFFFFu;  // unused child of a 4-wide node
+
+// BVH4 node, 112 bytes (7 float4), child boxes as structure of arrays:
+//   n0 = lo.x of children 0..3, n1 = hi.x, n2 = lo.y, n3 = hi.y, n4 = lo.z,
+//   n5 = hi.z, n6 = (ref0, ref1, ref2, ref3); empty children have ref
+//   kEmptyChild and an inverted (+inf, -inf) box.
 
 // Primitive slot, 48 bytes, leaf order:
 //   triangle: s0 = (v0, prim id), s1 = (v1, material), s2 = (v2, kPrimTriangle)
@@ -38,6 +44,8 @@ struct SceneView {
   const float4* materials;
   uint32_t lds_nodes;  // nodes [0, lds_nodes) are staged in LDS
   uint32_t has_geometry;
+  uint32_t width;       // 2 or 4 children per node
+  uint32_t node_float4s;
 };
 
 // Path queue (structure of float4 streams):

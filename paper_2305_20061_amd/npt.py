@@ -51,7 +51,7 @@ class npt_camera(C.Structure):
 
 
 class npt_bvh_params(C.Structure):
-    _fields_ = [("bins", C.c_uint32), ("max_leaf", C.c_uint32), ("lds_levels", C.c_uint32)]
+    _fields_ = [("bins", C.c_uint32), ("max_leaf", C.c_uint32), ("lds_levels", C.c_uint32), ("width", C.c_uint32)]
 
 
 class npt_nif_desc(C.Structure):
@@ -93,7 +93,7 @@ _SIGS = {
     "npt_scene_instances": [_P, _P, C.c_uint32],
     "npt_scene_materials": [_P, _P, C.c_uint32],
     "npt_build_bvh": [_P, _P, _P],
-    "npt_bvh_info": [_P, _P, _P, _P, _P],
+    "npt_bvh_info": [_P, _P, _P, _P, _P, _P],
     "npt_set_camera": [_P, _P],
     "npt_set_render_options": [_P, _P],
     "npt_env_upload": [_P, _P, C.c_uint32, C.c_uint32, _P],
@@ -236,16 +236,17 @@ def npt_scene_materials(ctx, materials):
     _check(ctx, lib().npt_scene_materials(ctx, arr, len(materials)))
 
 
-def npt_build_bvh(ctx, bins=32, max_leaf=4, lds_levels=6, stream=None):
-    p = npt_bvh_params(bins, max_leaf, lds_levels)
+def npt_build_bvh(ctx, bins=32, max_leaf=4, lds_levels=6, stream=None, width=0):
+    p = npt_bvh_params(bins, max_leaf, lds_levels, width)
     _check(ctx, lib().npt_build_bvh(ctx, C.byref(p), _stream(stream)))
 
 
 def npt_bvh_info(ctx):
     n, lv, s = C.c_uint64(), C.c_uint64(), C.c_uint64()
     d = C.c_uint32()
-    _check(ctx, lib().npt_bvh_info(ctx, C.byref(n), C.byref(lv), C.byref(d), C.byref(s)))
-    return {"nodes": n.value, "leaves": lv.value, "max_depth": d.value, "prim_slots": s.value}
+    w = C.c_uint32()
+    _check(ctx, lib().npt_bvh_info(ctx, C.byref(n), C.byref(lv), C.byref(d), C.byref(s), C.byref(w)))
+    return {"nodes": n.value, "leaves": lv.value, "max_depth": d.value, "prim_slots": s.value, "width": w.value}
 
 
 def npt_set_camera(ctx, eye, look_at, up, vfov_deg):
@@ -353,7 +354,7 @@ def npt_get_stats(ctx):
 
 
 # ------------------------------------------------------------ conveniences
-def npt_load_scene(ctx, scene: dict, bins=32, max_leaf=4, lds_levels=6, stream=None):
+def npt_load_scene(ctx, scene: dict, bins=32, max_leaf=4, lds_levels=6, stream=None, width=0):
     """Uploads a scene dict (paper_2305_20061_amd.synth layout) and builds its BVH."""
     npt_scene_materials(ctx, scene["materials"])
     if len(scene.get("tris", [])):
@@ -366,4 +367,4 @@ def npt_load_scene(ctx, scene: dict, bins=32, max_leaf=4, lds_levels=6, stream=N
         npt_scene_instances(ctx, scene["instances"])
     cam = scene["camera"]
     npt_set_camera(ctx, cam["eye"], cam["look_at"], cam["up"], cam["vfov_deg"])
-    npt_build_bvh(ctx, bins, max_leaf, lds_levels, stream)
+    npt_build_bvh(ctx, bins, max_leaf, lds_levels, stream, width)

@@ -84,13 +84,20 @@ def test_host_only_bvh_build_and_state_survives_errors(host_ctx):
     sc = synth.scene_for(3)
     npt.npt_scene_materials(c, sc["materials"])
     npt.npt_scene_triangles(c, sc["verts"], sc["tris"], sc["tri_mat"])
-    assert _code(npt.npt_build_bvh, c, lds_levels=6) == "NO_DEVICE"  # built on the host, no upload
-    info = npt.npt_bvh_info(c)
     nt = len(sc["tris"])
-    assert info["prim_slots"] == nt
-    assert info["nodes"] == info["leaves"] - 1
-    assert nt / 4 <= info["leaves"] <= nt
-    assert info["max_depth"] < 63
+    for width in (2, 4):
+        # built and structurally checked on the host, then no device to upload to
+        assert _code(npt.npt_build_bvh, c, lds_levels=6, width=width) == "NO_DEVICE"
+        info = npt.npt_bvh_info(c)
+        assert info["prim_slots"] == nt and info["width"] == width
+        assert nt / 4 <= info["leaves"] <= nt
+        if width == 2:
+            assert info["nodes"] == info["leaves"] - 1
+            assert info["max_depth"] < 63
+        else:
+            assert (info["leaves"] - 1) / 3 <= info["nodes"] < info["leaves"]
+            assert info["max_depth"] <= 21
+    assert _code(npt.npt_build_bvh, c, width=3) == "INVALID_ARG"
     # a rejected upload leaves the previous scene intact
     assert _code(npt.npt_scene_triangles, c, sc["verts"], sc["tris"][:, ::-1] + 10**7) == "INVALID_ARG"
     assert _code(npt.npt_build_bvh, c, lds_levels=0) == "NO_DEVICE"

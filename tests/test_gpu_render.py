@@ -111,3 +111,25 @@ def test_lds_levels_do_not_change_hits():
         finally:
             npt.npt_destroy(ctx)
     assert np.array_equal(res[0], res[1]) and np.array_equal(res[0], res[2])
+
+
+@pytest.mark.parametrize("cfg", [0, 2, 3])
+def test_bvh_width_and_leaf_size_do_not_change_images(cfg, small_sky):
+    # the closest hit is defined over all primitives (ties to the lowest id),
+    # so every tree shape gives bit-identical paths
+    scene = synth.scene_for(cfg)
+    env = None if cfg == 0 else small_sky
+    imgs = []
+    for width, leaf, lv in ((2, 4, 0), (4, 1, 0), (4, 2, 3), (4, 8, 0), (2, 1, 6)):
+        ctx = npt.npt_create(0)
+        try:
+            npt.npt_load_scene(ctx, scene, max_leaf=leaf, lds_levels=lv, width=width)
+            if env is None:
+                npt.npt_set_env_mode(ctx, npt.ENV_NONE)
+            else:
+                npt.npt_env_upload(ctx, env)
+            imgs.append(gpu_render(ctx, 80, 60, 4, 6, 11))
+        finally:
+            npt.npt_destroy(ctx)
+    for im in imgs[1:]:
+        assert np.array_equal(im, imgs[0])
