@@ -169,11 +169,21 @@ int npt_scene_triangles(npt_ctx *ctx, const float *xyz, uint64_t nv, const uint3
 /* Base spheres: cxyzr [n][4] (centre, radius > 0), mat [n] (NULL = 0).
  * Primitive ids nt..nt+n-1 after the base triangles. */
 int npt_scene_spheres(npt_ctx *ctx, const float *cxyzr, uint64_t n, const uint32_t *mat);
-/* Object-space mesh for instancing; blas_id must be 0, 1, ... in order (or
- * an existing id to replace it). */
+/* Object-space mesh for instancing (Sec. 3.1.4 scenes; the large-BVH
+ * scene of Fig. 1 places copies of one mesh): xyz [nv][3], tri [nt][3],
+ * mat_of_tri [nt] (NULL = 0).  blas_id must be an existing id (replaced) or
+ * the next one (appended); nt > 0.  Hits on instance k report primitive ids
+ * 0..nt-1 of its mesh.  Copied; the caller keeps its arrays. */
 int npt_scene_blas_triangles(npt_ctx *ctx, uint32_t blas_id, const float *xyz, uint64_t nv,
                              const uint32_t *tri, uint64_t nt, const uint32_t *mat_of_tri);
-/* Instances k = 0..n-1 get instance id k+1 (the base geometry is 0). */
+/* Instances k = 0..n-1 get instance id k+1 (the base geometry is 0).
+ * world = translate + scale * object, scale > 0 (NPT_E_INVALID_ARG
+ * otherwise or for an unknown blas_id; NPT_E_NAN_INPUT on NaN/Inf).  A scene
+ * with instances is traced through a two-level BVH (4-wide top tree over
+ * object boxes, one 4-wide tree per mesh; the object-space ray is
+ * ((o - translate) / scale, d / scale), so t is shared by both spaces);
+ * npt_build_bvh then requires width 4 (or 0) and lds_levels 0.  n = 0
+ * removes all instances. */
 int npt_scene_instances(npt_ctx *ctx, const npt_instance *inst, uint32_t n);
 int npt_scene_materials(npt_ctx *ctx, const npt_material *m, uint32_t n);
 /* Builds the BVH(s) on the host (binned SAH), flattens them and uploads on

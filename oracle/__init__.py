@@ -120,6 +120,8 @@ def lib():
                                       C.c_uint32, C.c_uint32, _f64p]),
             "or_trace_primary": (None, [_P, C.POINTER(Camera), C.c_uint32, C.c_uint32, C.c_uint32,
                                         C.c_uint64, _u32p, _u32p, _f32p, _f32p]),
+            "or_trace_pixels": (None, [_P, C.POINTER(Camera), C.c_uint32, C.c_uint32, C.c_uint32,
+                                       C.c_uint64, _u32p, C.c_uint64, _u32p, _u32p, _f32p, _f32p]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -431,3 +433,17 @@ def trace_primary(scene: Scene, cam: Camera, W, H, sample, seed):
     lib().or_trace_primary(scene.h, C.byref(cam), W, H, sample, seed, _ptr(prim, C.c_uint32),
                            _ptr(inst, C.c_uint32), _ptr(t, C.c_float), _ptr(n, C.c_float))
     return prim, inst, t, n
+
+
+def trace_pixels(scene: Scene, cam: Camera, W, H, sample, seed, pixels):
+    """trace_primary restricted to the listed pixel indices (y * W + x)."""
+    px = u32(pixels)
+    n = len(px)
+    prim = np.zeros(n, np.uint32)
+    inst = np.zeros(n, np.uint32)
+    t = np.zeros(n, np.float32)
+    nrm = np.zeros((n, 3), np.float32)
+    lib().or_trace_pixels(scene.h, C.byref(cam), W, H, sample, seed, _ptr(px, C.c_uint32), n,
+                          _ptr(prim, C.c_uint32), _ptr(inst, C.c_uint32), _ptr(t, C.c_float),
+                          _ptr(nrm, C.c_float))
+    return prim, inst, t, nrm

@@ -1148,30 +1148,43 @@ uint64_t or_render_rows(const or_scene *sc, const or_camera *cam, const or_rende
     return paths;
 }
 
+/* First hit of the camera ray of one pixel (sample s); outputs at index i. */
+static void primary_one(const or_scene *sc, const cam_basis *cb, uint32_t W, uint32_t H, uint32_t pix,
+                        uint32_t s, uint64_t seed, size_t i, uint32_t *prim, uint32_t *inst, float *t,
+                        float *normal)
+{
+    uint32_t r[4];
+    rng4(pix, s, 0, OR_RNG_CAM, seed, r);
+    float o[3], d[3], n[3], th;
+    uint32_t pr, in;
+    basis_ray(cb, W, H, pix % W, pix / W, or_u01(r[0]), or_u01(r[1]), o, d);
+    if (or_closest_hit(sc, o, d, INFINITY, &th, &pr, &in, n)) {
+        prim[i] = pr;
+        inst[i] = in;
+        t[i] = th;
+        for (int a = 0; a < 3; ++a) normal[3 * i + a] = n[a];
+    } else {
+        prim[i] = 0xffffffffu;
+        inst[i] = 0xffffffffu;
+        t[i] = INFINITY;
+        for (int a = 0; a < 3; ++a) normal[3 * i + a] = 0.0f;
+    }
+}
+
 void or_trace_primary(const or_scene *sc, const or_camera *cam, uint32_t W, uint32_t H,
                       uint32_t s, uint64_t seed, uint32_t *prim, uint32_t *inst, float *t,
                       float *normal)
 {
     cam_basis cb;
     camera_basis(cam, W, H, &cb);
-    for (uint32_t y = 0; y < H; ++y)
-        for (uint32_t x = 0; x < W; ++x) {
-            uint32_t pix = y * W + x;
-            uint32_t r[4];
-            rng4(pix, s, 0, OR_RNG_CAM, seed, r);
-            float o[3], d[3], n[3], th;
-            uint32_t pr, in;
-            basis_ray(&cb, W, H, x, y, or_u01(r[0]), or_u01(r[1]), o, d);
-            if (or_closest_hit(sc, o, d, INFINITY, &th, &pr, &in, n)) {
-                prim[pix] = pr;
-                inst[pix] = in;
-                t[pix] = th;
-                for (int a = 0; a < 3; ++a) normal[3 * (size_t)pix + a] = n[a];
-            } else {
-                prim[pix] = 0xffffffffu;
-                inst[pix] = 0xffffffffu;
-                t[pix] = INFINITY;
-                for (int a = 0; a < 3; ++a) normal[3 * (size_t)pix + a] = 0.0f;
-            }
-        }
+    for (uint32_t pix = 0; pix < W * H; ++pix) primary_one(sc, &cb, W, H, pix, s, seed, pix, prim, inst, t, normal);
+}
+
+void or_trace_pixels(const or_scene *sc, const or_camera *cam, uint32_t W, uint32_t H, uint32_t s,
+                     uint64_t seed, const uint32_t *pixels, uint64_t n, uint32_t *prim, uint32_t *inst,
+                     float *t, float *normal)
+{
+    cam_basis cb;
+    camera_basis(cam, W, H, &cb);
+    for (uint64_t i = 0; i < n; ++i) primary_one(sc, &cb, W, H, pixels[i], s, seed, (size_t)i, prim, inst, t, normal);
 }

@@ -169,6 +169,10 @@ void or_path_sample(const or_scene *sc, const or_camera *cam, const or_render_de
 void or_trace_primary(const or_scene *sc, const or_camera *cam, uint32_t W, uint32_t H,
                       uint32_t s, uint64_t seed, uint32_t *prim, uint32_t *inst, float *t,
                       float *normal);
+/* or_trace_primary for a list of pixel indices (y * W + x); outputs [n]. */
+void or_trace_pixels(const or_scene *sc, const or_camera *cam, uint32_t W, uint32_t H, uint32_t s,
+                     uint64_t seed, const uint32_t *pixels, uint64_t n, uint32_t *prim, uint32_t *inst,
+                     float *t, float *normal);
 
 #ifdef __cplusplus
 }

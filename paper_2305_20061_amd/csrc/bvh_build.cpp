@@ -231,7 +231,7 @@ bool build_bvh(const BuildInput& in, uint32_t bins, uint32_t max_leaf, uint32_t 
                FlatBvh& out,
                std::string& err) {
   out = FlatBvh();
-  const uint64_t n = in.nt + in.ns;
+  const uint64_t n = in.nboxes ? in.nboxes : in.nt + in.ns;
   if (n == 0) {
     err = "no primitives";
     return false;
@@ -248,7 +248,10 @@ bool build_bvh(const BuildInput& in, uint32_t bins, uint32_t max_leaf, uint32_t 
   B.order.resize(n);
   for (uint64_t p = 0; p < n; ++p) {
     Box b;
-    if (p < in.nt) {
+    if (in.nboxes) {
+      b.grow(&in.boxes[6 * p]);
+      b.grow(&in.boxes[6 * p + 3]);
+    } else if (p < in.nt) {
       for (int k = 0; k < 3; ++k) b.grow(&in.verts[3 * (size_t)in.tris[3 * p + k]]);
     } else {
       const float* s = &in.spheres[4 * (p - in.nt)];
@@ -390,7 +393,11 @@ bool build_bvh(const BuildInput& in, uint32_t bins, uint32_t max_leaf, uint32_t 
   for (uint64_t i = 0; i < n; ++i) {
     const uint32_t p = B.order[i];
     float4* s = &out.slots[3 * i];
-    if (p < in.nt) {
+    if (in.nboxes) {
+      // box mode: the slot only names the input box it holds
+      s[0] = make_float4(0.0f, 0.0f, 0.0f, bits(p));
+      s[1] = s[2] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    } else if (p < in.nt) {
       const uint32_t* t = &in.tris[3 * (size_t)p];
       const float* v0 = &in.verts[3 * (size_t)t[0]];
       const float* v1 = &in.verts[3 * (size_t)t[1]];
@@ -408,6 +415,100 @@ bool build_bvh(const BuildInput& in, uint32_t bins, uint32_t max_leaf, uint32_t 
     }
   }
   return check_flat(out, err);
+}
+
+bool build_two_level(const std::vector<FlatBvh>& bottoms, const std::vector<Placement>& objects, uint32_t bins,
+                     FlatBvh& out, std::vector<float4>& records, uint32_t& stack_entries, std::string& err) {
+  out = FlatBvh();
+  records.clear();
+  if (objects.empty()) {
+    err = "no objects";
+    return false;
+  }
+  // world box of every object: the bottom tree's bounds, scaled and moved
+  std::vector<float> boxes(6 * objects.size());
+  for (size_t i = 0; i < objects.size(); ++i) {
+    const Placement& o = objects[i];
+    if (o.tree >= bottoms.size() || bottoms[o.tree].width != 4 || !(o.scale > 0.0f)) {
+      err = "two-level layout: bad placement";
+      return false;
+    }
+    const FlatBvh& b = bottoms[o.tree];
+    for (int a = 0; a < 3; ++a) {
+      boxes[6 * i + a] = b.lo[a] * o.scale + o.translate[a];
+      boxes[6 * i + 3 + a] = b.hi[a] * o.scale + o.translate[a];
+    }
+  }
+  BuildInput tin;
+  tin.boxes = boxes.data();
+  tin.nboxes = objects.size();
+  FlatBvh top;
+  if (!build_bvh(tin, bins, 1, 0, 4, top, err)) return false;
+
+  out.width = 4;
+  out.node_float4s = 7;
+  out.nodes = top.nodes;
+  out.leaves = top.leaves;
+  for (int a = 0; a < 3; ++a) {
+    out.lo[a] = top.lo[a];
+    out.hi[a] = top.hi[a];
+  }
+  std::vector<uint32_t> root(bottoms.size());
+  uint32_t deepest = 0;
+  for (size_t t = 0; t < bottoms.size(); ++t) {
+    const FlatBvh& b = bottoms[t];
+    const uint64_t node_off = out.nodes.size() / 7, slot_off = out.slots.size() / 3;
+    if (node_off + b.nodes.size() / 7 >= kEmptyChild || slot_off + b.slots.size() / 3 > kMaxSlots) {
+      err = "two-level layout: too many nodes or primitive slots";
+      return false;
+    }
+    root[t] = (uint32_t)node_off;
+    for (size_t i = 0; i < b.nodes.size(); i += 7) {
+      float4 rf = b.nodes[i + 6];
+      float* r4[4] = {&rf.x, &rf.y, &rf.z, &rf.w};
+      for (float* f : r4) {
+        uint32_t r = ubits(*f);
+        if (r == kEmptyChild) continue;
+        if (r & kLeafBit) {
+          const uint32_t first = ((r >> 3) & 0x0FFFFFFFu) + (uint32_t)slot_off;
+          r = kLeafBit | (first << 3) | (r & 7u);
+        } else {
+          r += (uint32_t)node_off;
+        }
+        *f = bits(r);
+      }
+      out.nodes.insert(out.nodes.end(), b.nodes.begin() + i, b.nodes.begin() + i + 6);
+      out.nodes.push_back(rf);
+    }
+    out.slots.insert(out.slots.end(), b.slots.begin(), b.slots.end());
+    out.leaves += b.leaves;
+    deepest = std::max(deepest, b.max_depth);
+  }
+  // one record per top-tree leaf, in the top tree's slot order
+  const size_t nrec = top.slots.size() / 3;
+  records.resize(2 * nrec);
+  for (size_t i = 0; i < nrec; ++i) {
+    const uint32_t p = ubits(top.slots[3 * i].w);
+    const Placement& o = objects[p];
+    records[2 * i] = make_float4(o.translate[0], o.translate[1], o.translate[2], o.scale);
+    records[2 * i + 1] = make_float4(bits(root[o.tree]), bits(o.id), 0.0f, 0.0f);
+  }
+  // top leaves hold one object each (leaf size 1)
+  for (size_t i = 0; i < top.nodes.size(); i += 7) {
+    const float4 rf = top.nodes[i + 6];
+    for (float f : {rf.x, rf.y, rf.z, rf.w}) {
+      const uint32_t r = ubits(f);
+      if (r != kEmptyChild && (r & kLeafBit) && ((r & 7u) != 0u || ((r >> 3) & 0x0FFFFFFFu) >= nrec)) {
+        err = "two-level layout: top leaf with more than one object";
+        return false;
+      }
+    }
+  }
+  out.max_depth = top.max_depth + 1 + deepest;
+  // at most three deferred children per 4-wide level, plus the three of the
+  // deepest node, in each of the two trees
+  stack_entries = 3 * (top.max_depth + 1) + 3 * (deepest + 1);
+  return true;
 }
 
 }  // namespace npt

@@ -18,6 +18,11 @@ struct BuildInput {
   const float* spheres = nullptr; // [ns][4]
   uint64_t ns = 0;
   const uint32_t* sph_mat = nullptr;
+  // box mode (a top-level tree over instances): when nboxes > 0 the tree is
+  // built over these boxes [nboxes][lo xyz, hi xyz] instead, and slot i
+  // holds the input box index in the .w of its first float4
+  const float* boxes = nullptr;
+  uint64_t nboxes = 0;
 };
 
 struct FlatBvh {
@@ -38,5 +43,22 @@ struct FlatBvh {
 bool build_bvh(const BuildInput& in, uint32_t bins, uint32_t max_leaf, uint32_t lds_levels, uint32_t width,
                FlatBvh& out,
                std::string& err);
+
+// One object of a two-level scene: bottom tree `tree` placed in the world at
+// translate + scale * x (scale > 0), hits reported with instance id `id`.
+struct Placement {
+  uint32_t tree;
+  float translate[3];
+  float scale;
+  uint32_t id;
+};
+
+// Two-level layout for instancing: a 4-wide top tree (one object per leaf)
+// over the world boxes of `objects`, followed in one node array and one slot
+// array by the 4-wide bottom trees with their refs moved by their offsets.
+// records receives two float4 per top-tree leaf (translate, scale) and
+// (bottom root, id); stack_entries the traversal stack the layout needs.
+bool build_two_level(const std::vector<FlatBvh>& bottoms, const std::vector<Placement>& objects, uint32_t bins,
+                     FlatBvh& out, std::vector<float4>& records, uint32_t& stack_entries, std::string& err);
 
 }  // namespace npt

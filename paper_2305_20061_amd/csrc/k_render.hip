@@ -56,45 +56,112 @@ __device__ __forceinline__ V3 camera_direction(const CameraView& cam, uint32_t W
 }
 
 // ---------------------------------------------------------------------------
-// closest hit: stack traversal of the two-box BVH2; the top `lds_nodes`
-// nodes come from LDS.  Ties on t go to the lowest primitive id.
+// closest hit: stack traversal of the BVH (binary, 4-wide, or two-level over
+// instances); the top `lds_nodes` nodes of a one-level tree come from LDS.
+// Ties on t go to the lowest (instance, primitive).
 // ---------------------------------------------------------------------------
 struct Hit {
   float t;
   uint32_t slot;
   uint32_t prim;
+  uint32_t inst;  // 0 for the base geometry, k + 1 for instance k
 };
-
-__device__ __forceinline__ void slab2(const float4& n0, const float4& n1, const float4& n2,
-                                      float ix, float iy, float iz, float ox, float oy, float oz,
-                                      float lim, float& lo0, float& hi0, float& lo1, float& hi1) {
-  const float a0 = __builtin_fmaf(n0.x, ix, -ox), a1 = __builtin_fmaf(n0.y, ix, -ox);
-  const float b0 = __builtin_fmaf(n0.z, iy, -oy), b1 = __builtin_fmaf(n0.w, iy, -oy);
-  const float c0 = __builtin_fmaf(n2.x, iz, -oz), c1 = __builtin_fmaf(n2.y, iz, -oz);
-  lo0 = fmaxf(fmaxf(fminf(a0, a1), fminf(b0, b1)), fmaxf(fminf(c0, c1), 0.0f));
-  hi0 = fminf(fminf(fmaxf(a0, a1), fmaxf(b0, b1)), fminf(fmaxf(c0, c1), lim));
-  const float d0 = __builtin_fmaf(n1.x, ix, -ox), d1 = __builtin_fmaf(n1.y, ix, -ox);
-  const float e0 = __builtin_fmaf(n1.z, iy, -oy), e1 = __builtin_fmaf(n1.w, iy, -oy);
-  const float f0 = __builtin_fmaf(n2.z, iz, -oz), f1 = __builtin_fmaf(n2.w, iz, -oz);
-  lo1 = fmaxf(fmaxf(fminf(d0, d1), fminf(e0, e1)), fmaxf(fminf(f0, f1), 0.0f));
-  hi1 = fminf(fminf(fmaxf(d0, d1), fmaxf(e0, e1)), fminf(fmaxf(f0, f1), lim));
-}
 
 __device__ __forceinline__ float safe_inverse(float x) {
   return 1.0f / (fabsf(x) > 1e-20f ? x : copysignf(1e-20f, x));
 }
 
-// Per-lane stack entry i lives at stack[i * kStride]; kCount: also count
-// inner-node fetches (n_nodes) and primitive tests (n_prims)
+// Ray in the frame a tree is traversed in: origin, direction, the shear of
+// the watertight triangle test and the slab-test terms.
+//
+// A slab distance is formed as fma(plane, ix, -o * ix).  Against the exact
+// (plane - o) / d it errs by a part relative to the distance itself (from
+// the rounded reciprocal and the fma) and a part of up to one rounding of
+// o * ix, which does not shrink with the distance.  The second part is taken
+// out per ray: the origin term of the entry plane of each axis is moved up
+// by 4 ulp-units of |o * ix| and that of the exit plane down, so the
+// computed interval of every axis contains the exact one up to the relative
+// part, which kSlabSlack covers.  Boxes are then never missed by a ray that
+// enters them, whatever the distance between origin and box.
+struct RayFrame {
+  V3 o, d;
+  Shear sh;
+  float ix, iy, iz;
+  float ox_lo, oy_lo, oz_lo;  // origin terms for the low and high planes
+  float ox_hi, oy_hi, oz_hi;
+};
+
+constexpr float kSlabSlack = 1.0f + 0x1p-20f;
+
+__device__ __forceinline__ void origin_terms(float o, float inv, float& lo, float& hi) {
+  const float oi = o * inv;
+  const float e = fabsf(oi) * 0x1p-22f;
+  const float near_t = oi + e, far_t = oi - e;  // entry plane: smaller distance
+  lo = inv >= 0.0f ? near_t : far_t;
+  hi = inv >= 0.0f ? far_t : near_t;
+}
+
+__device__ __forceinline__ RayFrame make_frame(V3 o, V3 d) {
+  RayFrame f;
+  f.o = o;
+  f.d = d;
+  f.sh = make_shear(d);
+  f.ix = safe_inverse(d.x);
+  f.iy = safe_inverse(d.y);
+  f.iz = safe_inverse(d.z);
+  origin_terms(o.x, f.ix, f.ox_lo, f.ox_hi);
+  origin_terms(o.y, f.iy, f.oy_lo, f.oy_hi);
+  origin_terms(o.z, f.iz, f.oz_lo, f.oz_hi);
+  return f;
+}
+
+// entry and exit distance of one box against [0, lim]
+__device__ __forceinline__ void slab(const RayFrame& f, float lx, float hx, float ly, float hy, float lz, float hz,
+                                     float lim, float& tn, float& tf) {
+  const float a0 = __builtin_fmaf(lx, f.ix, -f.ox_lo), a1 = __builtin_fmaf(hx, f.ix, -f.ox_hi);
+  const float b0 = __builtin_fmaf(ly, f.iy, -f.oy_lo), b1 = __builtin_fmaf(hy, f.iy, -f.oy_hi);
+  const float c0 = __builtin_fmaf(lz, f.iz, -f.oz_lo), c1 = __builtin_fmaf(hz, f.iz, -f.oz_hi);
+  tn = fmaxf(fmaxf(fminf(a0, a1), fminf(b0, b1)), fmaxf(fminf(c0, c1), 0.0f));
+  tf = fminf(fminf(fmaxf(a0, a1), fmaxf(b0, b1)), fminf(fmaxf(c0, c1), lim)) * kSlabSlack;
+}
+
+// primitive tests of one leaf; the hit is kept on a smaller t, or on equal t
+// with a smaller (instance, primitive)
+template <bool kCount>
+__device__ __forceinline__ void test_leaf(const SceneView& sc, const RayFrame& f, uint32_t ref, uint32_t inst,
+                                          Hit& h, uint32_t* n_prims) {
+  const uint32_t first = (ref >> 3) & 0x0FFFFFFFu;
+  const uint32_t count = (ref & 7u) + 1u;
+  if constexpr (kCount) *n_prims += count;
+  for (uint32_t i = 0; i < count; ++i) {
+    const float4* s = sc.slots + 3 * (size_t)(first + i);
+    const float4 s0 = s[0], s1 = s[1], s2 = s[2];
+    const uint32_t prim = __float_as_uint(s0.w);
+    float t = 0.0f;
+    bool hit;
+    if (__float_as_uint(s2.w) == kPrimTriangle)
+      hit = hit_triangle(f.o, f.sh, V3{s0.x, s0.y, s0.z}, V3{s1.x, s1.y, s1.z}, V3{s2.x, s2.y, s2.z}, h.t, t);
+    else
+      hit = hit_sphere(f.o, f.d, V3{s0.x, s0.y, s0.z}, s1.x, h.t, t);
+    // a hit has t <= h.t, so "t < h.t or a smaller key" is the tie rule
+    if (hit && (t < h.t || inst < h.inst || (inst == h.inst && prim < h.prim))) {
+      h.t = t;
+      h.slot = first + i;
+      h.prim = prim;
+      h.inst = inst;
+    }
+  }
+}
+
+// Binary tree.  Per-lane stack entry i lives at stack[i * kStride]; kCount:
+// also count inner-node fetches (n_nodes) and primitive tests (n_prims).
 template <int kStack, int kStride, bool kCount = false>
 __device__ __forceinline__ Hit closest_hit(const SceneView& sc, const float4* lds_nodes,
                                            uint32_t* stack, V3 o, V3 d, uint32_t* n_nodes = nullptr,
                                            uint32_t* n_prims = nullptr) {
-  Hit h{__builtin_inff(), kMiss, kMiss};
+  Hit h{__builtin_inff(), kMiss, kMiss, kMiss};
   if (!sc.has_geometry) return h;
-  const Shear sh = make_shear(d);
-  const float ix = safe_inverse(d.x), iy = safe_inverse(d.y), iz = safe_inverse(d.z);
-  const float ox = o.x * ix, oy = o.y * iy, oz = o.z * iz;
+  const RayFrame f = make_frame(o, d);
   uint32_t ref = 0;
   int sp = 0;
   // a bound every traversal reaches: a well-formed tree visits each node at
@@ -110,8 +177,10 @@ __device__ __forceinline__ Hit closest_hit(const SceneView& sc, const float4* ld
         n0 = p[0]; n1 = p[1]; n2 = p[2]; n3 = p[3];
       }
       if constexpr (kCount) ++*n_nodes;
+      const float lim = h.t * 1.000001f;
       float lo0, hi0, lo1, hi1;
-      slab2(n0, n1, n2, ix, iy, iz, ox, oy, oz, h.t * 1.000001f, lo0, hi0, lo1, hi1);
+      slab(f, n0.x, n0.y, n0.z, n0.w, n2.x, n2.y, lim, lo0, hi0);
+      slab(f, n1.x, n1.y, n1.z, n1.w, n2.z, n2.w, lim, lo1, hi1);
       const bool h0 = lo0 <= hi0, h1 = lo1 <= hi1;
       const uint32_t r0 = __float_as_uint(n3.x), r1 = __float_as_uint(n3.y);
       if (h0 && h1) {
@@ -126,25 +195,7 @@ __device__ __forceinline__ Hit closest_hit(const SceneView& sc, const float4* ld
       if (h0) { ref = r0; continue; }
       if (h1) { ref = r1; continue; }
     } else {
-      const uint32_t first = (ref >> 3) & 0x0FFFFFFFu;
-      const uint32_t count = (ref & 7u) + 1u;
-      if constexpr (kCount) *n_prims += count;
-      for (uint32_t i = 0; i < count; ++i) {
-        const float4* s = sc.slots + 3 * (size_t)(first + i);
-        const float4 s0 = s[0], s1 = s[1], s2 = s[2];
-        const uint32_t prim = __float_as_uint(s0.w);
-        float t = 0.0f;
-        bool hit;
-        if (__float_as_uint(s2.w) == kPrimTriangle)
-          hit = hit_triangle(o, sh, V3{s0.x, s0.y, s0.z}, V3{s1.x, s1.y, s1.z}, V3{s2.x, s2.y, s2.z}, h.t, t);
-        else
-          hit = hit_sphere(o, d, V3{s0.x, s0.y, s0.z}, s1.x, h.t, t);
-        if (hit && (t < h.t || prim < h.prim)) {
-          h.t = t;
-          h.slot = first + i;
-          h.prim = prim;
-        }
-      }
+      test_leaf<kCount>(sc, f, ref, 0u, h, n_prims);
     }
     if (sp == 0) break;
     --sp;
@@ -165,75 +216,99 @@ __device__ __forceinline__ void order2(float& ka, uint32_t& ra, float& kb, uint3
 }
 
 // one child of a 4-wide node: entry distance, or +inf when missed or empty
-__device__ __forceinline__ float child_entry(float lx, float hx, float ly, float hy, float lz, float hz, float ix,
-                                             float iy, float iz, float ox, float oy, float oz, float lim,
-                                             uint32_t ref) {
-  const float a0 = __builtin_fmaf(lx, ix, -ox), a1 = __builtin_fmaf(hx, ix, -ox);
-  const float b0 = __builtin_fmaf(ly, iy, -oy), b1 = __builtin_fmaf(hy, iy, -oy);
-  const float c0 = __builtin_fmaf(lz, iz, -oz), c1 = __builtin_fmaf(hz, iz, -oz);
-  const float tn = fmaxf(fmaxf(fminf(a0, a1), fminf(b0, b1)), fmaxf(fminf(c0, c1), 0.0f));
-  const float tf = fminf(fminf(fmaxf(a0, a1), fmaxf(b0, b1)), fminf(fmaxf(c0, c1), lim));
+__device__ __forceinline__ float child_entry(const RayFrame& f, float lx, float hx, float ly, float hy, float lz,
+                                             float hz, float lim, uint32_t ref) {
+  float tn, tf;
+  slab(f, lx, hx, ly, hy, lz, hz, lim, tn, tf);
   return (tn <= tf && ref != kEmptyChild) ? tn : __builtin_inff();
 }
 
-// Closest hit on the 4-wide BVH: the children a ray enters are visited
-// nearest first (sorting network on entry distance), the rest pushed far to
-// near.  Same primitive tests and tie rule as the binary traversal.
+// One 4-wide node: the children the ray enters, nearest first in `ref`, the
+// others pushed far to near.  Returns false when no child is entered.
+template <int kStack, int kStride>
+__device__ __forceinline__ bool visit4(const float4* p, const RayFrame& f, float lim, uint32_t* stack, int& sp,
+                                       uint32_t& ref) {
+  const float4 lx = p[0], hx = p[1], ly = p[2], hy = p[3], lz = p[4], hz = p[5], rf = p[6];
+  uint32_t r0 = __float_as_uint(rf.x), r1 = __float_as_uint(rf.y), r2 = __float_as_uint(rf.z),
+           r3 = __float_as_uint(rf.w);
+  float k0 = child_entry(f, lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, lim, r0);
+  float k1 = child_entry(f, lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, lim, r1);
+  float k2 = child_entry(f, lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, lim, r2);
+  float k3 = child_entry(f, lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, lim, r3);
+  order2(k0, r0, k1, r1);
+  order2(k2, r2, k3, r3);
+  order2(k0, r0, k2, r2);
+  order2(k1, r1, k3, r3);
+  order2(k1, r1, k2, r2);
+  const float inf = __builtin_inff();
+  if (!(k0 < inf)) return false;
+  if (k3 < inf && sp < kStack) stack[(sp++) * kStride] = r3;
+  if (k2 < inf && sp < kStack) stack[(sp++) * kStride] = r2;
+  if (k1 < inf && sp < kStack) stack[(sp++) * kStride] = r1;
+  ref = r0;
+  return true;
+}
+
+// 4-wide tree: same primitive tests and tie rule as the binary traversal.
 template <int kStack, int kStride, bool kCount = false>
 __device__ __forceinline__ Hit closest_hit4(const SceneView& sc, const float4* lds_nodes, uint32_t* stack, V3 o,
                                             V3 d, uint32_t* n_nodes = nullptr, uint32_t* n_prims = nullptr) {
-  Hit h{__builtin_inff(), kMiss, kMiss};
+  Hit h{__builtin_inff(), kMiss, kMiss, kMiss};
   if (!sc.has_geometry) return h;
-  const Shear sh = make_shear(d);
-  const float ix = safe_inverse(d.x), iy = safe_inverse(d.y), iz = safe_inverse(d.z);
-  const float ox = o.x * ix, oy = o.y * iy, oz = o.z * iz;
-  const float inf = __builtin_inff();
+  const RayFrame f = make_frame(o, d);
   uint32_t ref = 0;
   int sp = 0;
   for (uint32_t visits = 0; visits < kMaxVisits; ++visits) {
     if ((ref & kLeafBit) == 0u) {
       const float4* p = ref < sc.lds_nodes ? lds_nodes + 7 * ref : sc.nodes + 7 * (size_t)ref;
-      const float4 lx = p[0], hx = p[1], ly = p[2], hy = p[3], lz = p[4], hz = p[5], rf = p[6];
       if constexpr (kCount) ++*n_nodes;
-      const float lim = h.t * 1.000001f;
-      uint32_t r0 = __float_as_uint(rf.x), r1 = __float_as_uint(rf.y), r2 = __float_as_uint(rf.z),
-               r3 = __float_as_uint(rf.w);
-      float k0 = child_entry(lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, ix, iy, iz, ox, oy, oz, lim, r0);
-      float k1 = child_entry(lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, ix, iy, iz, ox, oy, oz, lim, r1);
-      float k2 = child_entry(lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, ix, iy, iz, ox, oy, oz, lim, r2);
-      float k3 = child_entry(lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, ix, iy, iz, ox, oy, oz, lim, r3);
-      order2(k0, r0, k1, r1);
-      order2(k2, r2, k3, r3);
-      order2(k0, r0, k2, r2);
-      order2(k1, r1, k3, r3);
-      order2(k1, r1, k2, r2);
-      if (k0 < inf) {
-        if (k3 < inf && sp < kStack) stack[(sp++) * kStride] = r3;
-        if (k2 < inf && sp < kStack) stack[(sp++) * kStride] = r2;
-        if (k1 < inf && sp < kStack) stack[(sp++) * kStride] = r1;
-        ref = r0;
-        continue;
-      }
+      if (visit4<kStack, kStride>(p, f, h.t * 1.000001f, stack, sp, ref)) continue;
     } else {
-      const uint32_t first = (ref >> 3) & 0x0FFFFFFFu;
-      const uint32_t count = (ref & 7u) + 1u;
-      if constexpr (kCount) *n_prims += count;
-      for (uint32_t i = 0; i < count; ++i) {
-        const float4* s = sc.slots + 3 * (size_t)(first + i);
-        const float4 s0 = s[0], s1 = s[1], s2 = s[2];
-        const uint32_t prim = __float_as_uint(s0.w);
-        float t = 0.0f;
-        bool hit;
-        if (__float_as_uint(s2.w) == kPrimTriangle)
-          hit = hit_triangle(o, sh, V3{s0.x, s0.y, s0.z}, V3{s1.x, s1.y, s1.z}, V3{s2.x, s2.y, s2.z}, h.t, t);
-        else
-          hit = hit_sphere(o, d, V3{s0.x, s0.y, s0.z}, s1.x, h.t, t);
-        if (hit && (t < h.t || prim < h.prim)) {
-          h.t = t;
-          h.slot = first + i;
-          h.prim = prim;
-        }
-      }
+      test_leaf<kCount>(sc, f, ref, 0u, h, n_prims);
+    }
+    if (sp == 0) break;
+    --sp;
+    ref = stack[sp * kStride];
+  }
+  return h;
+}
+
+// Tree kind of the instanced (two-level, 4-wide) traversal, next to the
+// widths 2 and 4 of the one-level traversals.
+constexpr int kTwoLevel = 1;
+
+// Two-level scene.  Top-tree leaves are instances: entering one moves the
+// ray into object space and records the stack height; once the stack is
+// back at that height the bottom tree is done and the world ray returns.
+template <int kStack, int kStride, bool kCount = false>
+__device__ __forceinline__ Hit closest_hit_two_level(const SceneView& sc, uint32_t* stack, V3 ow, V3 dw,
+                                                     uint32_t* n_nodes = nullptr, uint32_t* n_prims = nullptr) {
+  Hit h{__builtin_inff(), kMiss, kMiss, kMiss};
+  if (!sc.has_geometry) return h;
+  RayFrame f = make_frame(ow, dw);
+  uint32_t ref = 0, inst = 0;
+  int sp = 0, mark = -1;
+  for (uint32_t visits = 0; visits < kMaxVisits; ++visits) {
+    if ((ref & kLeafBit) == 0u) {
+      if constexpr (kCount) ++*n_nodes;
+      if (visit4<kStack, kStride>(sc.nodes + 7 * (size_t)ref, f, h.t * 1.000001f, stack, sp, ref)) continue;
+    } else if (mark < 0) {
+      // top-tree leaf: enter the instance's bottom tree in object space
+      const uint32_t k = (ref >> 3) & 0x0FFFFFFFu;
+      const float4 r0 = sc.instances[2 * (size_t)k], r1 = sc.instances[2 * (size_t)k + 1];
+      const V3 o{(ow.x - r0.x) / r0.w, (ow.y - r0.y) / r0.w, (ow.z - r0.z) / r0.w};
+      const V3 d{dw.x / r0.w, dw.y / r0.w, dw.z / r0.w};
+      f = make_frame(o, d);
+      inst = __float_as_uint(r1.y);
+      ref = __float_as_uint(r1.x);
+      mark = sp;
+      continue;
+    } else {
+      test_leaf<kCount>(sc, f, ref, inst, h, n_prims);
+    }
+    if (sp == mark) {
+      f = make_frame(ow, dw);
+      mark = -1;
     }
     if (sp == 0) break;
     --sp;
@@ -245,7 +320,9 @@ __device__ __forceinline__ Hit closest_hit4(const SceneView& sc, const float4* l
 template <int kWidth, int kStack, int kStride, bool kCount = false>
 __device__ __forceinline__ Hit trace_closest(const SceneView& sc, const float4* lds_nodes, uint32_t* stack, V3 o,
                                              V3 d, uint32_t* n_nodes = nullptr, uint32_t* n_prims = nullptr) {
-  if constexpr (kWidth == 4)
+  if constexpr (kWidth == kTwoLevel)
+    return closest_hit_two_level<kStack, kStride, kCount>(sc, stack, o, d, n_nodes, n_prims);
+  else if constexpr (kWidth == 4)
     return closest_hit4<kStack, kStride, kCount>(sc, lds_nodes, stack, o, d, n_nodes, n_prims);
   else
     return closest_hit<kStack, kStride, kCount>(sc, lds_nodes, stack, o, d, n_nodes, n_prims);
@@ -334,7 +411,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(SceneView sc, PassView pv
       sample = __float_as_uint(qd.w);
     }
     const uint32_t slot = (sample - pv.sample0) * pv.pixels + pixel;
-    Hit h{__builtin_inff(), kMiss, kMiss};
+    Hit h{__builtin_inff(), kMiss, kMiss, 0u};
     if (valid) h = trace_closest<kWidth, kStack, kStride, kCount>(sc, lds_nodes, stack, o, d, &n_nodes, &n_prims);
     const bool escaped = valid && h.slot == kMiss;
     bool alive = false;
@@ -486,7 +563,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_primary(SceneView sc, Cam
       n = slot_normal(sc.slots, h.slot, V3{o.x + h.t * d.x, o.y + h.t * d.y, o.z + h.t * d.z}, mat);
     }
     if (prim) prim[pixel] = h.slot == kMiss ? kMiss : h.prim;
-    if (inst) inst[pixel] = h.slot == kMiss ? kMiss : 0u;
+    if (inst) inst[pixel] = h.slot == kMiss ? kMiss : h.inst;
     if (tout) tout[pixel] = h.t;
     if (normal) {
       normal[3 * (size_t)pixel] = n.x;
@@ -557,7 +634,9 @@ hipError_t launch_trace(int stack_depth, const SceneView& sc, const PassView& pv
     default: return hipErrorInvalidValue;                                                      \
   }
   const bool c = visit_cnt != nullptr;
-  if (sc.width == 4) {
+  if (sc.two_level) {
+    NPT_LAUNCH_TRACE_S(kTwoLevel)
+  } else if (sc.width == 4) {
     NPT_LAUNCH_TRACE_S(4)
   } else {
     NPT_LAUNCH_TRACE_S(2)
@@ -609,7 +688,9 @@ hipError_t launch_trace_primary(int stack_depth, const SceneView& sc, const Came
 #define NPT_LAUNCH_PRIMARY(W, S)                                                                                   \
   hipLaunchKernelGGL((k_trace_primary<W, S>), dim3(grid), dim3(kTraceBlock), lds, s, sc, cam, pv, prim, inst, t, \
                      normal)
-  if (sc.width == 4) {
+  if (sc.two_level) {
+    if (stack_depth <= 32) NPT_LAUNCH_PRIMARY(kTwoLevel, 32); else NPT_LAUNCH_PRIMARY(kTwoLevel, 64);
+  } else if (sc.width == 4) {
     if (stack_depth <= 32) NPT_LAUNCH_PRIMARY(4, 32); else NPT_LAUNCH_PRIMARY(4, 64);
   } else {
     if (stack_depth <= 32) NPT_LAUNCH_PRIMARY(2, 32); else NPT_LAUNCH_PRIMARY(2, 64);

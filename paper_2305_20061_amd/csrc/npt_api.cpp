@@ -71,9 +71,18 @@ struct npt_ctx {
   bool scene_dirty = true;
   FlatBvh bvh;
   bool bvh_built = false;
+  // instancing: object-space meshes and their instances
+  struct Mesh {
+    std::vector<float> verts;
+    std::vector<uint32_t> tris, mat;
+  };
+  std::vector<Mesh> blas;
+  std::vector<npt_instance> instances;
+  std::vector<float4> inst_records;  // two float4 per top-tree leaf
+  bool two_level = false;
 
   // device scene
-  DevBuf d_nodes, d_slots, d_mats;
+  DevBuf d_nodes, d_slots, d_mats, d_inst;
   int stack_depth = 32;
 
   bool have_camera = false;
@@ -100,7 +109,7 @@ struct npt_ctx {
   bool timing_pending = false;
 
   ~npt_ctx() {
-    DevBuf* all[] = {&d_nodes, &d_slots, &d_mats, &d_env, &d_master, &d_adam_m, &d_adam_v, &d_frags, &d_bias,
+    DevBuf* all[] = {&d_nodes, &d_slots, &d_mats, &d_inst, &d_env, &d_master, &d_adam_m, &d_adam_v, &d_frags, &d_bias,
                      &qa_o, &qa_d, &qa_b, &qb_o, &qb_d, &qb_b, &env_d, &env_b, &d_L, &d_accum, &d_cnt, &d_stats};
     for (DevBuf* b : all) b->release();
     train.release();
@@ -174,6 +183,8 @@ SceneView scene_view(npt_ctx* c) {
   s.has_geometry = c->bvh_built ? 1u : 0u;
   s.width = c->bvh.width;
   s.node_float4s = c->bvh.node_float4s;
+  s.instances = c->d_inst.as<float4>();
+  s.two_level = c->two_level ? 1u : 0u;
   return s;
 }
 
@@ -286,16 +297,41 @@ extern "C" int npt_scene_spheres(npt_ctx* c, const float* cxyzr, uint64_t n, con
   return ok(c);
 }
 
-extern "C" int npt_scene_blas_triangles(npt_ctx* c, uint32_t, const float*, uint64_t, const uint32_t*, uint64_t,
-                                        const uint32_t*) {
+extern "C" int npt_scene_blas_triangles(npt_ctx* c, uint32_t blas_id, const float* xyz, uint64_t nv,
+                                        const uint32_t* tri, uint64_t nt, const uint32_t* mat_of_tri) {
   if (!c) return NPT_E_INVALID_ARG;
-  return fail(c, NPT_E_UNSUPPORTED, "instanced meshes are not built yet");
+  if (blas_id > c->blas.size()) return fail(c, NPT_E_INVALID_ARG, "blas_id must be an existing id or the next one");
+  if (nt == 0 || !xyz || !tri) return fail(c, NPT_E_INVALID_ARG, "an instanced mesh needs triangles");
+  if (nv > (1ull << 32) || nt >= kMaxSlots) return fail(c, NPT_E_INVALID_ARG, "too many vertices/triangles");
+  if (!finite_all(xyz, 3 * nv)) return fail(c, NPT_E_NAN_INPUT, "non-finite vertex coordinate");
+  for (uint64_t i = 0; i < 3 * nt; ++i)
+    if (tri[i] >= nv) return fail(c, NPT_E_INVALID_ARG, "triangle index out of range");
+  npt_ctx::Mesh m;
+  m.verts.assign(xyz, xyz + 3 * nv);
+  m.tris.assign(tri, tri + 3 * nt);
+  if (mat_of_tri) m.mat.assign(mat_of_tri, mat_of_tri + nt);
+  else m.mat.assign(nt, 0u);
+  if (blas_id == c->blas.size()) c->blas.push_back(std::move(m));
+  else c->blas[blas_id] = std::move(m);
+  c->scene_dirty = true;
+  c->bvh_built = false;
+  return ok(c);
 }
 
-extern "C" int npt_scene_instances(npt_ctx* c, const npt_instance*, uint32_t n) {
+extern "C" int npt_scene_instances(npt_ctx* c, const npt_instance* inst, uint32_t n) {
   if (!c) return NPT_E_INVALID_ARG;
-  if (n == 0) return ok(c);
-  return fail(c, NPT_E_UNSUPPORTED, "instances are not built yet");
+  if (n && !inst) return fail(c, NPT_E_INVALID_ARG, "null instance array");
+  if (n >= (1u << 24)) return fail(c, NPT_E_INVALID_ARG, "too many instances");
+  for (uint32_t i = 0; i < n; ++i) {
+    if (inst[i].blas_id >= c->blas.size()) return fail(c, NPT_E_INVALID_ARG, "instance of an unknown blas_id");
+    if (!finite_all(inst[i].translate, 3) || !std::isfinite(inst[i].scale))
+      return fail(c, NPT_E_NAN_INPUT, "non-finite instance transform");
+    if (!(inst[i].scale > 0.0f)) return fail(c, NPT_E_INVALID_ARG, "instance scale must be > 0");
+  }
+  c->instances.assign(inst, inst + n);
+  c->scene_dirty = true;
+  c->bvh_built = false;
+  return ok(c);
 }
 
 extern "C" int npt_scene_materials(npt_ctx* c, const npt_material* m, uint32_t n) {
@@ -325,12 +361,21 @@ extern "C" int npt_build_bvh(npt_ctx* c, const npt_bvh_params* p, void* stream) 
   if (width != 2 && width != 4) return fail(c, NPT_E_INVALID_ARG, "BVH width must be 2 or 4");
   if (bins < 4 || bins > 256 || max_leaf < 1 || max_leaf > kMaxLeaf || lds_levels > 8)
     return fail(c, NPT_E_INVALID_ARG, "bvh params out of range");
-  if (c->tris.empty() && c->spheres.empty()) return fail(c, NPT_E_NO_SCENE, "no geometry uploaded");
+  const bool has_base = !c->tris.empty() || !c->spheres.empty();
+  const bool two_level = !c->instances.empty();
+  if (!has_base && !two_level) return fail(c, NPT_E_NO_SCENE, "no geometry uploaded");
+  if (two_level && (width != 4 || lds_levels != 0))
+    return fail(c, NPT_E_UNSUPPORTED, "instanced scenes use width 4 without LDS levels");
   const uint32_t nmat = (uint32_t)std::max<size_t>(1, c->materials.size());
   for (uint32_t m : c->tri_mat)
     if (m >= nmat) return fail(c, NPT_E_INVALID_ARG, "triangle material id out of range");
   for (uint32_t m : c->sph_mat)
     if (m >= nmat) return fail(c, NPT_E_INVALID_ARG, "sphere material id out of range");
+  for (const npt_instance& k : c->instances) {
+    if (k.blas_id >= c->blas.size()) return fail(c, NPT_E_INVALID_ARG, "instance of an unknown blas_id");
+    for (uint32_t m : c->blas[k.blas_id].mat)
+      if (m >= nmat) return fail(c, NPT_E_INVALID_ARG, "instanced triangle material id out of range");
+  }
   BuildInput in;
   in.verts = c->verts.data();
   in.nv = c->verts.size() / 3;
@@ -341,13 +386,50 @@ extern "C" int npt_build_bvh(npt_ctx* c, const npt_bvh_params* p, void* stream) 
   in.ns = c->spheres.size() / 4;
   in.sph_mat = c->sph_mat.data();
   FlatBvh b;
+  std::vector<float4> records;
   std::string e;
-  if (!build_bvh(in, bins, max_leaf, lds_levels, width, b, e)) return fail(c, NPT_E_INVALID_ARG, e);
-  // traversal stack: one deferred child per level (width 2), up to three (width 4)
-  const uint32_t stack_need = (width == 2 ? 1 : 3) * b.max_depth + 1;
+  uint32_t stack_need = 0;
+  if (!two_level) {
+    if (!build_bvh(in, bins, max_leaf, lds_levels, width, b, e)) return fail(c, NPT_E_INVALID_ARG, e);
+    // deferred children: one per level (width 2); up to three per level,
+    // plus the three of the deepest node (width 4)
+    stack_need = width == 2 ? b.max_depth + 1 : 3 * b.max_depth + 3;
+  } else {
+    // bottom trees: the base geometry (instance 0) and each instanced mesh
+    std::vector<FlatBvh> bottoms;
+    std::vector<Placement> objects;
+    if (has_base) {
+      bottoms.emplace_back();
+      if (!build_bvh(in, bins, max_leaf, 0, 4, bottoms.back(), e)) return fail(c, NPT_E_INVALID_ARG, e);
+      objects.push_back(Placement{0u, {0.0f, 0.0f, 0.0f}, 1.0f, 0u});
+    }
+    std::vector<int64_t> tree_of(c->blas.size(), -1);
+    for (size_t k = 0; k < c->instances.size(); ++k) {
+      const npt_instance& x = c->instances[k];
+      if (tree_of[x.blas_id] < 0) {
+        const npt_ctx::Mesh& m = c->blas[x.blas_id];
+        BuildInput bi;
+        bi.verts = m.verts.data();
+        bi.nv = m.verts.size() / 3;
+        bi.tris = m.tris.data();
+        bi.nt = m.tris.size() / 3;
+        bi.tri_mat = m.mat.data();
+        bottoms.emplace_back();
+        if (!build_bvh(bi, bins, max_leaf, 0, 4, bottoms.back(), e)) return fail(c, NPT_E_INVALID_ARG, e);
+        tree_of[x.blas_id] = (int64_t)bottoms.size() - 1;
+      }
+      objects.push_back(Placement{(uint32_t)tree_of[x.blas_id],
+                                  {x.translate[0], x.translate[1], x.translate[2]},
+                                  x.scale,
+                                  (uint32_t)(k + 1)});
+    }
+    if (!build_two_level(bottoms, objects, bins, b, records, stack_need, e)) return fail(c, NPT_E_INVALID_ARG, e);
+  }
   if (trace_stack_size(stack_need) == 0)
     return fail(c, NPT_E_UNSUPPORTED, "BVH deeper than the 64-entry traversal stack");
   c->bvh = std::move(b);
+  c->inst_records = std::move(records);
+  c->two_level = two_level;
   c->bvh_built = false;
   if (c->host_only) return fail(c, NPT_E_NO_DEVICE, "BVH built on the host; no device to upload to");
   int r = need_device(c);
@@ -359,10 +441,15 @@ extern "C" int npt_build_bvh(npt_ctx* c, const npt_bvh_params* p, void* stream) 
                             hipMemcpyHostToDevice, s));
   HIP_TRY(c, hipMemcpyAsync(c->d_slots.p, c->bvh.slots.data(), c->bvh.slots.size() * sizeof(float4),
                             hipMemcpyHostToDevice, s));
+  if (two_level) {
+    HIP_TRY(c, c->d_inst.ensure(c->inst_records.size() * sizeof(float4)));
+    HIP_TRY(c, hipMemcpyAsync(c->d_inst.p, c->inst_records.data(), c->inst_records.size() * sizeof(float4),
+                              hipMemcpyHostToDevice, s));
+  }
   HIP_TRY(c, hipStreamSynchronize(s));
   r = upload_materials(c, s);
   if (r) return r;
-  c->stack_depth = trace_stack_size((c->bvh.width == 2 ? 1 : 3) * c->bvh.max_depth + 1);
+  c->stack_depth = trace_stack_size(stack_need);
   c->bvh_built = true;
   c->scene_dirty = false;
   return ok(c);
@@ -629,7 +716,8 @@ extern "C" int npt_env_query(npt_ctx* c, int mode, const float* d_dirs, uint64_t
 // rendering
 // ===========================================================================
 static int render_checks(npt_ctx* c, uint32_t W, uint32_t H) {
-  if (c->tris.empty() && c->spheres.empty()) return fail(c, NPT_E_NO_SCENE, "no geometry uploaded");
+  if (c->tris.empty() && c->spheres.empty() && c->instances.empty())
+    return fail(c, NPT_E_NO_SCENE, "no geometry uploaded");
   if (!c->bvh_built) return fail(c, NPT_E_STATE, "npt_build_bvh not called after the last scene change");
   if (!c->have_camera) return fail(c, NPT_E_STATE, "no camera set");
   if (W == 0 || H == 0) return fail(c, NPT_E_INVALID_ARG, "zero image size");

@@ -38,14 +38,24 @@ struct CameraView {
   float tan_x, tan_y;
 };
 
+// Two-level scenes (instancing): the top tree is a BVH4 over object boxes
+// whose leaf refs (count 1) index instance records, two float4 each:
+//   r0 = (translate.xyz, scale), r1 = (bottom root node, instance id, -, -)
+// The base geometry is the record with translate 0, scale 1 and id 0.  The
+// bottom trees follow the top tree in the node array, their primitive slots
+// share one slot array, and a bottom slot's id is the primitive index within
+// its own mesh.  An object ray is ((o - translate) / scale, d / scale): the
+// ray parameter t, and hence the order of hits, is the same in both spaces.
 struct SceneView {
   const float4* nodes;
   const float4* slots;
   const float4* materials;
+  const float4* instances;  // instance records (two-level scenes only)
   uint32_t lds_nodes;  // nodes [0, lds_nodes) are staged in LDS
   uint32_t has_geometry;
   uint32_t width;       // 2 or 4 children per node
   uint32_t node_float4s;
+  uint32_t two_level;   // 1: top tree over instances (width 4)
 };
 
 // Path queue (structure of float4 streams):

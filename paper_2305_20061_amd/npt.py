@@ -367,4 +367,6 @@ def npt_load_scene(ctx, scene: dict, bins=32, max_leaf=4, lds_levels=6, stream=N
         npt_scene_instances(ctx, scene["instances"])
     cam = scene["camera"]
     npt_set_camera(ctx, cam["eye"], cam["look_at"], cam["up"], cam["vfov_deg"])
+    if scene.get("instances"):
+        lds_levels = 0  # the two-level traversal reads every node from memory
     npt_build_bvh(ctx, bins, max_leaf, lds_levels, stream, width)

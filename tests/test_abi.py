@@ -123,6 +123,37 @@ def test_tiny_scenes_build(host_ctx):
     assert info["prim_slots"] == 1 and info["nodes"] == 1 and info["leaves"] == 1
 
 
+def test_instances_validated_and_two_level_layout_built(host_ctx):
+    c = host_ctx
+    sc = synth.large_bvh_scene(grid=65, n_inst=12, ico_level=3, size=30.0, amp=4.0)
+    npt.npt_scene_materials(c, sc["materials"])
+    npt.npt_scene_triangles(c, sc["verts"], sc["tris"], sc["tri_mat"])
+    b = sc["blas"][0]
+    # ids are appended in order or replaced; instances name existing meshes
+    assert _code(npt.npt_scene_blas_triangles, c, 1, b["verts"], b["tris"]) == "INVALID_ARG"
+    npt.npt_scene_blas_triangles(c, 0, b["verts"], b["tris"], b["tri_mat"])
+    assert _code(npt.npt_scene_instances, c, [{"blas": 1, "translate": (0, 0, 0), "scale": 1.0}]) == "INVALID_ARG"
+    assert _code(npt.npt_scene_instances, c, [{"blas": 0, "translate": (0, 0, 0), "scale": 0.0}]) == "INVALID_ARG"
+    assert _code(npt.npt_scene_instances, c,
+                 [{"blas": 0, "translate": (0, float("nan"), 0), "scale": 1.0}]) == "NAN_INPUT"
+    npt.npt_scene_instances(c, sc["instances"])
+    # the two-level traversal is 4-wide and reads its nodes from memory
+    assert _code(npt.npt_build_bvh, c, width=2, lds_levels=0) == "UNSUPPORTED"
+    assert _code(npt.npt_build_bvh, c, width=4, lds_levels=3) == "UNSUPPORTED"
+    assert _code(npt.npt_build_bvh, c, max_leaf=2, lds_levels=0) == "NO_DEVICE"
+    info = npt.npt_bvh_info(c)
+    nt, nb, ni = len(sc["tris"]), len(b["tris"]), len(sc["instances"])
+    # one copy of each mesh's slots, however many instances place it
+    assert info["prim_slots"] == nt + nb
+    assert info["width"] == 4
+    # leaves: the top tree's (one per object) plus each bottom tree's
+    assert ni + 1 + (nt + nb) / 2 <= info["leaves"] <= ni + 1 + nt + nb
+    # removing the instances returns to the one-level tree
+    npt.npt_scene_instances(c, [])
+    assert _code(npt.npt_build_bvh, c, max_leaf=2, lds_levels=0) == "NO_DEVICE"
+    assert npt.npt_bvh_info(c)["prim_slots"] == nt
+
+
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(npt, "_lib", None)
     monkeypatch.setattr(npt, "LIB_PATH", str(tmp_path / "missing.so"))

@@ -139,3 +139,15 @@ def test_row_subset_equals_full_render():
     sub = O.render(S, cam, rd, y0=3, ystep=8)
     assert np.array_equal(full[3::8], sub[3::8])
     assert np.isnan(sub[4]).all()
+
+
+def test_pixel_list_equals_full_primary_trace():
+    sc = synth.large_bvh_scene(grid=33, n_inst=6, ico_level=2, size=20.0, amp=2.0)
+    S = O.Scene(sc)
+    cam = O.make_camera(**sc["camera"])
+    full = O.trace_primary(S, cam, 48, 32, 2, 9)
+    px = np.array([0, 5, 47, 48, 700, 1535, 5], np.uint32)
+    part = O.trace_pixels(S, cam, 48, 32, 2, 9, px)
+    for a, b in zip(full, part):
+        assert np.array_equal(a[px], b)
+    assert np.any(full[1][full[0] != O.MISS] > 0)  # some instance hits
