@@ -57,7 +57,7 @@ class RenderDesc(C.Structure):
                 ("env_mode", C.c_uint32), ("env_map", C.POINTER(C.c_float)),
                 ("env_w", C.c_uint32), ("env_h", C.c_uint32),
                 ("nif_params", C.POINTER(C.c_double)), ("nif", NifShape),
-                ("env_const", C.c_double * 3)]
+                ("env_const", C.c_double * 3), ("nif_prec", C.c_uint32)]
 
 
 _P = C.c_void_p
@@ -120,6 +120,12 @@ def lib():
                                       C.c_uint32, C.c_uint32, _f64p]),
             "or_trace_primary": (None, [_P, C.POINTER(Camera), C.c_uint32, C.c_uint32, C.c_uint32,
                                         C.c_uint64, _u32p, _u32p, _f32p, _f32p]),
+            "or_round_to": (C.c_double, [C.c_double, C.c_int]),
+            "or_round_array": (None, [_f64p, _f64p, C.c_uint64, C.c_int]),
+            "or_nif_fp8_scale_exp": (C.c_int, [C.c_double]),
+            "or_nif_dequantize": (None, [C.POINTER(NifShape), _f64p, C.c_int, _f64p]),
+            "or_nif_forward_q": (None, [C.POINTER(NifShape), _f64p, C.c_int, C.c_double, C.c_double, _f64p]),
+            "or_nif_radiance_q": (None, [C.POINTER(NifShape), _f64p, C.c_int, C.c_double, C.c_double, _f64p]),
             "or_trace_pixels": (None, [_P, C.POINTER(Camera), C.c_uint32, C.c_uint32, C.c_uint32,
                                        C.c_uint64, _u32p, C.c_uint64, _u32p, _u32p, _f32p, _f32p]),
         }
@@ -283,6 +289,43 @@ def nif_radiance(shape, params, u, v):
     return z
 
 
+PREC_FP32, PREC_FP16, PREC_BF16, PREC_FP8 = 0, 1, 2, 3
+FMT_NONE, FMT_F16, FMT_BF16, FMT_E4M3 = 0, 1, 2, 3
+
+
+def round_to(x, fmt):
+    """Round every value to FMT_* (nearest, ties to even; E4M3 saturates)."""
+    a = f64(np.atleast_1d(x))
+    out = np.zeros_like(a)
+    lib().or_round_array(_ptr(a, C.c_double), _ptr(out, C.c_double), a.size, int(fmt))
+    return out.reshape(np.shape(x))
+
+
+def nif_fp8_scale_exp(maxabs):
+    return int(lib().or_nif_fp8_scale_exp(float(maxabs)))
+
+
+def nif_dequantize(shape, params, prec):
+    p = f64(params)
+    out = np.zeros_like(p)
+    lib().or_nif_dequantize(C.byref(shape), _ptr(p, C.c_double), int(prec), _ptr(out, C.c_double))
+    return out
+
+
+def nif_forward_q(shape, deq, prec, u, v):
+    p, z = f64(deq), np.zeros(3, np.float64)
+    lib().or_nif_forward_q(C.byref(shape), _ptr(p, C.c_double), int(prec), float(u), float(v),
+                           _ptr(z, C.c_double))
+    return z
+
+
+def nif_radiance_q(shape, deq, prec, u, v):
+    p, z = f64(deq), np.zeros(3, np.float64)
+    lib().or_nif_radiance_q(C.byref(shape), _ptr(p, C.c_double), int(prec), float(u), float(v),
+                            _ptr(z, C.c_double))
+    return z
+
+
 def huber(e, delta):
     return lib().or_huber(float(e), float(delta))
 
@@ -388,7 +431,9 @@ class Scene:
 
 
 def render_desc(width, height, spp, max_depth, seed, rr_start=3, env=None, nif_params=None,
-                nif=None, env_const=None):
+                nif=None, env_const=None, nif_prec=0):
+    """nif_params: the dequantised parameters (nif_dequantize) of precision
+    nif_prec (PREC_*), whose operand rounding the environment queries follow."""
     rd = RenderDesc()
     rd.width, rd.height, rd.spp, rd.max_depth, rd.rr_start, rd.seed = (
         width, height, spp, max_depth, rr_start, seed)
@@ -402,6 +447,7 @@ def render_desc(width, height, spp, max_depth, seed, rr_start=3, env=None, nif_p
         keep.append(p)
         rd.nif_params = _ptr(p, C.c_double)
         rd.nif = nif if nif is not None else nif_shape()
+        rd.nif_prec = int(nif_prec)
     else:
         rd.env_mode = ENV_MAP
         e = f32(env)

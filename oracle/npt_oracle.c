@@ -499,6 +499,128 @@ void or_nif_radiance(const or_nif_shape *s, const double *params, double u, doub
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Reduced-precision NIF inference.  The network is unchanged; what changes  */
+/* is where values are rounded: every weight once, and the input vector of   */
+/* every layer, each to the format of its matrix-core operands.  Biases stay */
+/* exact, and products and sums are exact here (FP64), which the FP32        */
+/* accumulation of the device approximates.  Per precision:                  */
+/*   FP16 / BF16: weights and layer inputs in binary16 / bfloat16.           */
+/*   FP8: the first layer and the output layer as in FP16; the hidden-to-    */
+/*        hidden layers with OCP E4M3 weights W * 2^s (s the largest integer */
+/*        with max|W| * 2^s <= 448, one per layer), E4M3 inputs (saturating  */
+/*        at 448), and the sums taken back by 2^-s.                           */
+/* ------------------------------------------------------------------------ */
+double or_round_format(double x, int frac_bits, int emin, double maxv, int saturate)
+{
+    if (x == 0.0 || isnan(x)) return x;
+    if (isinf(x)) return saturate ? copysign(maxv, x) : x;
+    int e;
+    (void)frexp(x, &e); /* |x| in [2^(e-1), 2^e) */
+    int lead = e - 1 < emin ? emin : e - 1;
+    /* spacing of the format around x is 2^(lead - frac_bits); nearbyint rounds */
+    /* to nearest, ties to even, in the default rounding mode                   */
+    double q = ldexp(nearbyint(ldexp(x, frac_bits - lead)), lead - frac_bits);
+    if (fabs(q) > maxv) q = saturate ? copysign(maxv, x) : copysign(INFINITY, x);
+    return q;
+}
+
+double or_round_to(double x, int fmt)
+{
+    switch (fmt) {
+    case OR_FMT_F16: return or_round_format(x, 10, -14, 65504.0, 0);
+    case OR_FMT_BF16: return or_round_format(x, 7, -126, ldexp(255.0, 120), 0);
+    case OR_FMT_E4M3: return or_round_format(x, 3, -6, 448.0, 1);
+    default: return x;
+    }
+}
+
+void or_round_array(const double *in, double *out, uint64_t n, int fmt)
+{
+    for (uint64_t i = 0; i < n; ++i) out[i] = or_round_to(in[i], fmt);
+}
+
+int or_nif_fp8_scale_exp(double maxabs)
+{
+    if (!(maxabs > 0.0)) return 0;
+    int e;
+    (void)frexp(maxabs, &e);
+    int s = 9 - e; /* maxabs * 2^s in [256, 512) */
+    if (ldexp(maxabs, s) > 448.0) s -= 1;
+    return s;
+}
+
+/* format of the weights and of the input vector of layer l at precision prec */
+static int nif_operand_format(const or_nif_shape *s, int prec, uint32_t l)
+{
+    switch (prec) {
+    case OR_PREC_FP16: return OR_FMT_F16;
+    case OR_PREC_BF16: return OR_FMT_BF16;
+    case OR_PREC_FP8: return (l == 0 || l == s->layers) ? OR_FMT_F16 : OR_FMT_E4M3;
+    default: return OR_FMT_NONE;
+    }
+}
+
+void or_nif_dequantize(const or_nif_shape *s, const double *params, int prec, double *out)
+{
+    const double *p = params;
+    double *q = out;
+    for (uint32_t l = 0; l <= s->layers; ++l) {
+        uint64_t nw = (uint64_t)layer_out(s, l) * layer_in(s, l), nb = layer_out(s, l);
+        int fmt = nif_operand_format(s, prec, l);
+        if (fmt == OR_FMT_E4M3) {
+            double m = 0.0;
+            for (uint64_t i = 0; i < nw; ++i) m = fabs(p[i]) > m ? fabs(p[i]) : m;
+            int sc = or_nif_fp8_scale_exp(m);
+            for (uint64_t i = 0; i < nw; ++i) q[i] = ldexp(or_round_to(ldexp(p[i], sc), fmt), -sc);
+        } else {
+            for (uint64_t i = 0; i < nw; ++i) q[i] = or_round_to(p[i], fmt);
+        }
+        for (uint64_t i = 0; i < nb; ++i) q[nw + i] = p[nw + i];
+        p += nw + nb;
+        q += nw + nb;
+    }
+}
+
+void or_nif_forward_q(const or_nif_shape *s, const double *deq, int prec, double u, double v, double z[3])
+{
+    uint32_t width = 4 * s->n_freq > s->hidden ? 4 * s->n_freq : s->hidden;
+    double *x = (double *)malloc(sizeof(double) * width);
+    double *h = (double *)malloc(sizeof(double) * width);
+    double y[3];
+    or_nif_features(s, u, v, x);
+    const double *p = deq;
+    for (uint32_t l = 0; l <= s->layers; ++l) {
+        uint32_t ni = layer_in(s, l), no = layer_out(s, l);
+        int fmt = nif_operand_format(s, prec, l);
+        for (uint32_t i = 0; i < ni; ++i) x[i] = or_round_to(x[i], fmt);
+        const double *W = p, *b = p + (size_t)no * ni;
+        double *out = l == s->layers ? y : h;
+        for (uint32_t j = 0; j < no; ++j) {
+            double acc = b[j];
+            for (uint32_t i = 0; i < ni; ++i) acc += W[(size_t)j * ni + i] * x[i];
+            out[j] = (l == s->layers) ? acc : (acc > 0.0 ? acc : 0.0);
+        }
+        if (l < s->layers) memcpy(x, h, sizeof(double) * no);
+        p += (size_t)no * ni + no;
+    }
+    double m[9];
+    or_yuv_to_rgb_matrix(m);
+    for (int r = 0; r < 3; ++r) z[r] = m[3 * r] * y[0] + m[3 * r + 1] * y[1] + m[3 * r + 2] * y[2];
+    free(x);
+    free(h);
+}
+
+void or_nif_radiance_q(const or_nif_shape *s, const double *deq, int prec, double u, double v, double rgb[3])
+{
+    double z[3];
+    or_nif_forward_q(s, deq, prec, u, v, z);
+    for (int c = 0; c < 3; ++c) {
+        double e = expm1(z[c]);
+        rgb[c] = e > 0.0 ? e : 0.0;
+    }
+}
+
 /* Huber loss with threshold delta (Sec. 3.2.1 uses delta = 0.001). */
 double or_huber(double e, double delta)
 {
@@ -1045,7 +1167,7 @@ static void env_radiance(const or_render_desc *rd, const float d[3], double out[
     if (rd->env_mode == OR_ENV_MAP) {
         or_env_bilinear(rd->env_map, rd->env_w, rd->env_h, u, v, out);
     } else {
-        or_nif_radiance(&rd->nif, rd->nif_params, u, v, out);
+        or_nif_radiance_q(&rd->nif, rd->nif_params, (int)rd->nif_prec, u, v, out);
     }
 }
 

@@ -112,6 +112,23 @@ void or_yuv_to_rgb_matrix(double m[9]);
 void or_nif_forward(const or_nif_shape *s, const double *params, double u, double v, double z[3]);
 /* Radiance = max(0, expm1(z)). */
 void or_nif_radiance(const or_nif_shape *s, const double *params, double u, double v, double rgb[3]);
+/* Reduced-precision inference (FP16 / BF16 / FP8 operands, exact sums). */
+enum { OR_PREC_FP32 = 0, OR_PREC_FP16 = 1, OR_PREC_BF16 = 2, OR_PREC_FP8 = 3 };
+enum { OR_FMT_NONE = 0, OR_FMT_F16 = 1, OR_FMT_BF16 = 2, OR_FMT_E4M3 = 3 };
+/* Nearest value with ties to even in a binary format with frac_bits fraction
+ * bits, minimum normal exponent emin and largest finite maxv; beyond maxv
+ * the result saturates (saturate != 0) or is infinite. */
+double or_round_format(double x, int frac_bits, int emin, double maxv, int saturate);
+double or_round_to(double x, int fmt); /* OR_FMT_*: binary16, bfloat16, E4M3 (saturating) */
+void or_round_array(const double *in, double *out, uint64_t n, int fmt);
+/* FP8 weight scale: the largest s with maxabs * 2^s <= 448 (0 for maxabs 0). */
+int or_nif_fp8_scale_exp(double maxabs);
+/* The weights as rounded for inference at `prec` (biases unchanged). */
+void or_nif_dequantize(const or_nif_shape *s, const double *params, int prec, double *out);
+/* Forward pass with every layer input rounded to its operand format; deq
+ * from or_nif_dequantize.  OR_PREC_FP32 is or_nif_forward. */
+void or_nif_forward_q(const or_nif_shape *s, const double *deq, int prec, double u, double v, double z[3]);
+void or_nif_radiance_q(const or_nif_shape *s, const double *deq, int prec, double u, double v, double rgb[3]);
 double or_huber(double e, double delta);
 double or_huber_grad(double e, double delta);
 /* Mean Huber loss over n samples x 3 channels and its gradient w.r.t. params
@@ -156,6 +173,7 @@ typedef struct {
     const double *nif_params; /* OR_ENV_NIF: dequantised parameters */
     or_nif_shape nif;
     double env_const[3];      /* OR_ENV_CONST */
+    uint32_t nif_prec;        /* OR_ENV_NIF: OR_PREC_* of or_nif_forward_q */
 } or_render_desc;
 
 /* Renders rows y0, y0+ystep, ... into out (full W*H*3 FP64 image; other rows
