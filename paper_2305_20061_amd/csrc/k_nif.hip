@@ -18,44 +18,39 @@
 namespace npt {
 using namespace nif;
 
+// Bytes of layer l's weight fragments, and their offsets in the packed
+// buffer (all layers) and in LDS (the resident layers).
 template <int P>
-__host__ __device__ constexpr int lds_frag_offset(int l) {
-  using G = Geometry<Prec<P>::KPL>;
-  int o = 0;
+__host__ __device__ constexpr size_t layer_bytes(int l) {
+  if (P == NPT_FP8 && fp8_layer(l)) return (size_t)kFp8LayerBytes;
+  return (size_t)Geometry<Prec<P>::KPL>::frags(l) * 64 * sizeof(typename Prec<P>::Frag);
+}
+
+template <int P>
+__host__ __device__ constexpr size_t global_offset(int l) {
+  size_t o = 0;
+  for (int i = 0; i < l; ++i) o += layer_bytes<P>(i);
+  return o;
+}
+
+template <int P>
+__host__ __device__ constexpr size_t lds_offset(int l) {
+  size_t o = 0;
   for (int i = 0; i < l; ++i)
-    if (Prec<P>::kResident[i]) o += G::frags(i);
+    if (Prec<P>::kResident[i]) o += layer_bytes<P>(i);
   return o;
 }
 
 template <int P>
 size_t nif_lds_bytes() {
-  return (size_t)lds_frag_offset<P>(kLayers + 1) * 64 * sizeof(typename Prec<P>::Frag) +
-         kBiasFloats * sizeof(float);
+  return lds_offset<P>(kLayers + 1) + (kBiasFloats + kScaleWords) * sizeof(float);
 }
 
 // ---------------------------------------------------------------------------
 // packing: master FP32 parameters -> MFMA fragments + bias table
 // ---------------------------------------------------------------------------
-template <int P>
-__global__ void k_nif_pack(const float* master, typename Prec<P>::Elem* frags, float* bias) {
-  constexpr int KPL = Prec<P>::KPL;
-  using G = Geometry<KPL>;
-  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-  for (int i = tid; i < G::kElems; i += gridDim.x * blockDim.x) {
-    const int q = i / (64 * KPL);
-    const int lane = (i / KPL) % 64;
-    const int e = i % KPL;
-    int l = 0;
-    while (l < kLayers && q >= G::frag_offset(l + 1)) ++l;
-    const int local = q - G::frag_offset(l);
-    const int nkb = l == 0 ? G::kKBFeat : G::kKBHidden;
-    const int mb = local / nkb, kb = local % nkb;
-    const int row = 32 * mb + lane % 32;
-    const int col = input_index<KPL>(l, kb, lane / 32, e);
-    const float w = row < layer_out(l) ? master[w_offset(l) + row * layer_in(l) + col] : 0.0f;
-    frags[i] = Prec<P>::cvt(w);
-  }
-  for (int j = tid; j < kBiasFloats; j += gridDim.x * blockDim.x) {
+__device__ __forceinline__ void fill_bias(const float* master, float* bias, int tid, int stride) {
+  for (int j = tid; j < kBiasFloats; j += stride) {
     float b = 0.0f;
     if (j < kLayers * kHidden) b = master[b_offset(j / kHidden) + j % kHidden];
     else if (j - kLayers * kHidden < kOut) b = master[b_offset(kLayers) + (j - kLayers * kHidden)];
@@ -63,11 +58,105 @@ __global__ void k_nif_pack(const float* master, typename Prec<P>::Elem* frags, f
   }
 }
 
-// the weights the kernel multiplies, back in FP32 (npt_nif_get_dequantized)
+// FP16/BF16/FP32 fragment element i (over all layers) of the packed buffer
+template <int KPL>
+__device__ __forceinline__ float packed_weight(const float* master, int i) {
+  using G = Geometry<KPL>;
+  const int q = i / (64 * KPL);
+  const int lane = (i / KPL) % 64;
+  const int e = i % KPL;
+  int l = 0;
+  while (l < kLayers && q >= G::frag_offset(l + 1)) ++l;
+  const int local = q - G::frag_offset(l);
+  const int nkb = l == 0 ? G::kKBFeat : G::kKBHidden;
+  const int mb = local / nkb, kb = local % nkb;
+  const int row = 32 * mb + lane % 32;
+  const int col = input_index<KPL>(l, kb, lane / 32, e);
+  return row < layer_out(l) ? master[w_offset(l) + row * layer_in(l) + col] : 0.0f;
+}
+
 template <int P>
-__global__ void k_nif_dequant(const float* master, float* out, int n) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    out[i] = (float)Prec<P>::cvt(master[i]);
+__global__ void k_nif_pack(const float* master, typename Prec<P>::Elem* frags, float* bias) {
+  constexpr int KPL = Prec<P>::KPL;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  for (int i = tid; i < Geometry<KPL>::kElems; i += gridDim.x * blockDim.x)
+    frags[i] = Prec<P>::cvt(packed_weight<KPL>(master, i));
+  fill_bias(master, bias, tid, gridDim.x * blockDim.x);
+  for (int j = tid; j < kScaleWords; j += gridDim.x * blockDim.x) reinterpret_cast<int*>(bias + kBiasFloats)[j] = 0;
+}
+
+// FP8 weight scale: the largest s with m * 2^s <= 448 (0 for m = 0)
+__device__ __forceinline__ int fp8_scale_exp(float m) {
+  if (!(m > 0.0f)) return 0;
+  int e;
+  (void)frexpf(m, &e);  // m in [2^(e-1), 2^e)
+  int s = 9 - e;
+  if (ldexpf(m, s) > 448.0f) s -= 1;
+  return s;
+}
+
+// FP8 mode: one workgroup of 256 per layer.  Layers 1..4 become E4M3
+// fragments of W * 2^s (s from the layer's largest |w|, stored after the
+// bias table); layers 0 and 5 FP16 fragments as in FP16 mode.
+__global__ __launch_bounds__(256) void k_nif_pack_fp8(const float* master, uint8_t* packed, float* bias) {
+  const int l = blockIdx.x;
+  __shared__ float red[256];
+  int* scales = reinterpret_cast<int*>(bias + kBiasFloats);
+  if (fp8_layer(l)) {
+    float m = 0.0f;
+    for (int i = threadIdx.x; i < kHidden * kHidden; i += 256) m = fmaxf(m, fabsf(master[w_offset(l) + i]));
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+      if (threadIdx.x < k) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + k]);
+      __syncthreads();
+    }
+    const int s = fp8_scale_exp(red[0]);
+    if (threadIdx.x == 0) scales[l] = s;
+    int* dst = reinterpret_cast<int*>(packed + global_offset<NPT_FP8>(l));
+    // dword wd: fragment q = (M-block, K-block), lane, bytes 4 (wd % 8) .. +3
+    for (int wd = threadIdx.x; wd < kFp8LayerBytes / 4; wd += 256) {
+      const int q = wd / (64 * 8), lane = (wd / 8) % 64, e0 = (wd % 8) * 4;
+      const int mb = q / kKB8, kb = q % kKB8;
+      const int row = 32 * mb + lane % 32;
+      float v[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int col = input_index_fp8(kb, lane / 32, e0 + k);
+        v[k] = col < 0 ? 0.0f : ldexpf(master[w_offset(l) + row * kHidden + col], s);
+      }
+      dst[wd] = pack_e4m3<true>(v[2], v[3], pack_e4m3<false>(v[0], v[1], 0));
+    }
+  } else {
+    using G = Geometry<8>;
+    _Float16* dst = reinterpret_cast<_Float16*>(packed + global_offset<NPT_FP8>(l));
+    const int base = G::frag_offset(l) * 64 * 8;
+    for (int i = threadIdx.x; i < G::frags(l) * 64 * 8; i += 256) dst[i] = (_Float16)packed_weight<8>(master, base + i);
+    if (threadIdx.x == 0) scales[l] = 0;
+  }
+  if (l == 0) {
+    fill_bias(master, bias, threadIdx.x, 256);
+    for (int j = kLayers + 1 + threadIdx.x; j < kScaleWords; j += 256) scales[j] = 0;
+  }
+}
+
+// the values the kernel multiplies, back in FP32 (npt_nif_get_dequantized):
+// weights rounded as packed, biases unchanged (they are added in FP32)
+template <int P>
+__global__ void k_nif_dequant(const float* master, const float* bias_tab, float* out, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    int l = 0;
+    while (l < kLayers && i >= w_offset(l + 1)) ++l;
+    const float w = master[i];
+    if (i >= b_offset(l)) {
+      out[i] = w;
+    } else if (P == NPT_FP8 && fp8_layer(l)) {
+      const int s = reinterpret_cast<const int*>(bias_tab + kBiasFloats)[l];
+      out[i] = ldexpf(__builtin_amdgcn_cvt_f32_fp8(pack_e4m3<false>(ldexpf(w, s), 0.0f, 0), 0), -s);
+    } else {
+      out[i] = (float)Prec<P>::cvt(w);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -111,15 +200,9 @@ __device__ __forceinline__ float feature(int f, float u, float v) {
   return (blk & 1) ? __builtin_amdgcn_cosf(ph) : __builtin_amdgcn_sinf(ph);
 }
 
-// one dense layer + ReLU over NT 32-ray column tiles: x (K-blocks of the
-// layer input) -> x (K-blocks of the next layer), weights fr, biases lb
-template <int P, int NT, int NKB>
-__device__ __forceinline__ void dense_relu(const typename Prec<P>::Frag* fr, const float* lb, int lane, int h,
-                                           typename Prec<P>::Frag (&x)[NT][Geometry<Prec<P>::KPL>::kKBHidden]) {
-  constexpr int KPL = Prec<P>::KPL;
-  using G = Geometry<KPL>;
-  using Frag = typename Prec<P>::Frag;
-  f32x16 acc[NT][kMB];
+// bias-initialised accumulators of one layer over NT 32-ray column tiles
+template <int NT>
+__device__ __forceinline__ void init_acc(const float* lb, int h, f32x16 (&acc)[NT][kMB]) {
 #pragma unroll
   for (int mb = 0; mb < kMB; ++mb) {
     f32x16 b;
@@ -128,14 +211,29 @@ __device__ __forceinline__ void dense_relu(const typename Prec<P>::Frag* fr, con
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t][mb] = b;
   }
+}
+
+// acc += W x for Prec<P> operands: x holds the layer input as NKB K-blocks
+template <int P, int NT, int NKB>
+__device__ __forceinline__ void mma_layer(const typename Prec<P>::Frag* fr, int lane,
+                                          const typename Prec<P>::Frag (&x)[NT][Geometry<Prec<P>::KPL>::kKBHidden],
+                                          f32x16 (&acc)[NT][kMB]) {
 #pragma unroll
   for (int kb = 0; kb < NKB; ++kb)
 #pragma unroll
     for (int mb = 0; mb < kMB; ++mb) {
-      const Frag a = fr[(mb * NKB + kb) * 64 + lane];
+      const typename Prec<P>::Frag a = fr[(mb * NKB + kb) * 64 + lane];
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[t][mb] = Prec<P>::mma(a, x[t][kb], acc[t][mb]);
     }
+}
+
+// ReLU of the accumulators into the Prec<P> K-blocks of the next layer
+template <int P, int NT>
+__device__ __forceinline__ void relu_to_frags(const f32x16 (&acc)[NT][kMB],
+                                              typename Prec<P>::Frag (&x)[NT][Geometry<Prec<P>::KPL>::kKBHidden]) {
+  constexpr int KPL = Prec<P>::KPL;
+  using G = Geometry<KPL>;
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -150,9 +248,55 @@ __device__ __forceinline__ void dense_relu(const typename Prec<P>::Frag* fr, con
     }
 }
 
+// one dense layer + ReLU: x (K-blocks of the layer input) -> x (K-blocks of
+// the next layer), weights fr, biases lb
+template <int P, int NT, int NKB>
+__device__ __forceinline__ void dense_relu(const typename Prec<P>::Frag* fr, const float* lb, int lane, int h,
+                                           typename Prec<P>::Frag (&x)[NT][Geometry<Prec<P>::KPL>::kKBHidden]) {
+  f32x16 acc[NT][kMB];
+  init_acc<NT>(lb, h, acc);
+  mma_layer<P, NT, NKB>(fr, lane, x, acc);
+  relu_to_frags<P, NT>(acc, x);
+}
+
+// FP8 hidden-to-hidden layer: acc += 2^-s (W 2^s) x with E4M3 operands
+template <int NT>
+__device__ __forceinline__ void mma_layer_e4m3(const i32x8* fr, int lane, int scale_a, const i32x8 (&x)[NT][kKB8],
+                                               f32x16 (&acc)[NT][kMB]) {
+#pragma unroll
+  for (int kb = 0; kb < kKB8; ++kb)
+#pragma unroll
+    for (int mb = 0; mb < kMB; ++mb) {
+      const i32x8 a = fr[(mb * kKB8 + kb) * 64 + lane];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[t][mb] = mma_e4m3(a, x[t][kb], acc[t][mb], scale_a);
+    }
+}
+
+__device__ __forceinline__ float relu448(float v) { return fminf(fmaxf(v, 0.0f), 448.0f); }
+
+__device__ __forceinline__ int pack4_e4m3(const f32x16& a, int r) {
+  return pack_e4m3<true>(relu448(a[r + 2]), relu448(a[r + 3]), pack_e4m3<false>(relu448(a[r]), relu448(a[r + 1]), 0));
+}
+
+// ReLU of the accumulators, saturated at 448, into the two E4M3 K-blocks of
+// the next layer (byte e of K-block 0: M-block e / 16, register e % 16;
+// K-block 1: M-block 2, then zero padding)
+template <int NT>
+__device__ __forceinline__ void relu_to_e4m3(const f32x16 (&acc)[NT][kMB], i32x8 (&x)[NT][kKB8]) {
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+#pragma unroll
+    for (int d = 0; d < 8; ++d) x[t][0][d] = pack4_e4m3(acc[t][d / 4], 4 * (d % 4));
+#pragma unroll
+    for (int d = 0; d < 4; ++d) x[t][1][d] = pack4_e4m3(acc[t][2], 4 * d);
+#pragma unroll
+    for (int d = 4; d < 8; ++d) x[t][1][d] = 0;
+  }
+}
+
 template <int P>
-__global__ __launch_bounds__(kNifBlock, 1) void k_nif_infer(const typename Prec<P>::Frag* gfrags,
-                                                            const float* gbias, NifIO io) {
+__global__ __launch_bounds__(kNifBlock, 1) void k_nif_infer(const uint8_t* gpack, const float* gbias, NifIO io) {
   constexpr int KPL = Prec<P>::KPL;
   using G = Geometry<KPL>;
   using Frag = typename Prec<P>::Frag;
@@ -160,23 +304,34 @@ __global__ __launch_bounds__(kNifBlock, 1) void k_nif_infer(const typename Prec<
   constexpr int NT = (P == NPT_FP32) ? 1 : NPT_NIF_TILES;  // 32-ray column tiles per wave
   constexpr int kRays = 32 * NT;
   extern __shared__ float4 smem4[];
-  Frag* lfrags = reinterpret_cast<Frag*>(smem4);
-  float* lbias = reinterpret_cast<float*>(lfrags + (size_t)lds_frag_offset<P>(kLayers + 1) * 64);
+  uint8_t* lds = reinterpret_cast<uint8_t*>(smem4);
+  float* lbias = reinterpret_cast<float*>(lds + lds_offset<P>(kLayers + 1));
+  const int* lscale = reinterpret_cast<const int*>(lbias + kBiasFloats);
   uint64_t n;
   if (io.source == kSrcQueue) n = io.cnt[kCntEnv + io.depth];
   else n = io.n;
   // workgroups without a tile leave before staging the weights
   if ((uint64_t)blockIdx.x * kNifWaves * kRays >= n) return;
 
-  // stage the resident layers and the biases
+  // stage the resident layers, the biases and the FP8 scale exponents
+#pragma unroll
   for (int l = 0; l <= kLayers; ++l) {
     if (!Prec<P>::kResident[l]) continue;
-    const Frag* src = gfrags + (size_t)G::frag_offset(l) * 64;
-    Frag* dst = lfrags + (size_t)lds_frag_offset<P>(l) * 64;
-    for (int i = threadIdx.x; i < G::frags(l) * 64; i += kNifBlock) dst[i] = src[i];
+    const uint4* src = reinterpret_cast<const uint4*>(gpack + global_offset<P>(l));
+    uint4* dst = reinterpret_cast<uint4*>(lds + lds_offset<P>(l));
+    for (int i = threadIdx.x; i < (int)(layer_bytes<P>(l) / 16); i += kNifBlock) dst[i] = src[i];
   }
-  for (int i = threadIdx.x; i < kBiasFloats; i += kNifBlock) lbias[i] = gbias[i];
+  {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(gbias);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(lbias);
+    for (int i = threadIdx.x; i < kBiasFloats + kScaleWords; i += kNifBlock) dst[i] = src[i];
+  }
   __syncthreads();
+  // weights of layer l: from LDS when resident, else from the packed buffer
+  auto frags = [&](int l) -> const Frag* {
+    return Prec<P>::kResident[l] ? reinterpret_cast<const Frag*>(lds + lds_offset<P>(l))
+                                 : reinterpret_cast<const Frag*>(gpack + global_offset<P>(l));
+  };
 
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int h = lane / 32, col = lane % 32;
@@ -226,19 +381,29 @@ __global__ __launch_bounds__(kNifBlock, 1) void k_nif_infer(const typename Prec<
         }
       }
 
-    // hidden layers: layer 0 (64 -> 96), then 1..4 (96 -> 96, all in LDS)
-    if constexpr (Prec<P>::kResident[0])
-      dense_relu<P, NT, G::kKBFeat>(lfrags + (size_t)lds_frag_offset<P>(0) * 64, lbias, lane, h, x);
-    else
-      dense_relu<P, NT, G::kKBFeat>(gfrags + (size_t)G::frag_offset(0) * 64, lbias, lane, h, x);
+    if constexpr (P == NPT_FP8) {
+      // layer 0 on FP16 operands, layers 1..4 on E4M3, FP16 input to the output layer
+      f32x16 acc[NT][kMB];
+      i32x8 x8[NT][kKB8];
+      init_acc<NT>(lbias, h, acc);
+      mma_layer<P, NT, G::kKBFeat>(frags(0), lane, x, acc);
+      relu_to_e4m3<NT>(acc, x8);
 #pragma unroll 1
-    for (int l = 1; l < kLayers; ++l)
-      dense_relu<P, NT, G::kKBHidden>(lfrags + (size_t)lds_frag_offset<P>(l) * 64, lbias + l * kHidden, lane, h, x);
+      for (int l = 1; l < kLayers; ++l) {
+        init_acc<NT>(lbias + l * kHidden, h, acc);
+        mma_layer_e4m3<NT>(reinterpret_cast<const i32x8*>(lds + lds_offset<P>(l)), lane, 127 - lscale[l], x8, acc);
+        if (l + 1 < kLayers) relu_to_e4m3<NT>(acc, x8);
+      }
+      relu_to_frags<P, NT>(acc, x);
+    } else {
+      // layer 0 (64 -> 96), then 1..4 (96 -> 96, all in LDS)
+      dense_relu<P, NT, G::kKBFeat>(frags(0), lbias, lane, h, x);
+#pragma unroll 1
+      for (int l = 1; l < kLayers; ++l) dense_relu<P, NT, G::kKBHidden>(frags(l), lbias + l * kHidden, lane, h, x);
+    }
 
     // output layer (rows 0..2 of one padded M-block) and the colour matrix
-    const Frag* fr;
-    if constexpr (Prec<P>::kResident[kLayers]) fr = lfrags + (size_t)lds_frag_offset<P>(kLayers) * 64;
-    else fr = gfrags + (size_t)G::frag_offset(kLayers) * 64;
+    const Frag* fr = frags(kLayers);
     f32x16 o[NT];
     {
       f32x16 b;
@@ -291,28 +456,33 @@ __global__ __launch_bounds__(kNifBlock, 1) void k_nif_infer(const typename Prec<
 // ---------------------------------------------------------------------------
 size_t nif_packed_bytes(int prec) {
   switch (prec) {
-    case NPT_FP32: return (size_t)Geometry<1>::kElems * sizeof(float);
-    case NPT_FP16: return (size_t)Geometry<8>::kElems * 2;
-    case NPT_BF16: return (size_t)Geometry<8>::kElems * 2;
+    case NPT_FP32: return global_offset<NPT_FP32>(kLayers + 1);
+    case NPT_FP16: return global_offset<NPT_FP16>(kLayers + 1);
+    case NPT_BF16: return global_offset<NPT_BF16>(kLayers + 1);
+    case NPT_FP8: return global_offset<NPT_FP8>(kLayers + 1);
     default: return 0;
   }
 }
+
+size_t nif_bias_bytes() { return (kBiasFloats + kScaleWords) * sizeof(float); }
 
 hipError_t launch_nif_pack(int prec, const float* master, void* frags, float* bias, hipStream_t s) {
   switch (prec) {
     case NPT_FP32: hipLaunchKernelGGL(k_nif_pack<NPT_FP32>, dim3(64), dim3(256), 0, s, master, (float*)frags, bias); break;
     case NPT_FP16: hipLaunchKernelGGL(k_nif_pack<NPT_FP16>, dim3(64), dim3(256), 0, s, master, (_Float16*)frags, bias); break;
     case NPT_BF16: hipLaunchKernelGGL(k_nif_pack<NPT_BF16>, dim3(64), dim3(256), 0, s, master, (__bf16*)frags, bias); break;
+    case NPT_FP8: hipLaunchKernelGGL(k_nif_pack_fp8, dim3(kLayers + 1), dim3(256), 0, s, master, (uint8_t*)frags, bias); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_nif_dequant(int prec, const float* master, float* out, int n, hipStream_t s) {
+hipError_t launch_nif_dequant(int prec, const float* master, const float* bias, float* out, int n, hipStream_t s) {
   switch (prec) {
-    case NPT_FP32: hipLaunchKernelGGL(k_nif_dequant<NPT_FP32>, dim3(64), dim3(256), 0, s, master, out, n); break;
-    case NPT_FP16: hipLaunchKernelGGL(k_nif_dequant<NPT_FP16>, dim3(64), dim3(256), 0, s, master, out, n); break;
-    case NPT_BF16: hipLaunchKernelGGL(k_nif_dequant<NPT_BF16>, dim3(64), dim3(256), 0, s, master, out, n); break;
+    case NPT_FP32: hipLaunchKernelGGL(k_nif_dequant<NPT_FP32>, dim3(64), dim3(256), 0, s, master, bias, out, n); break;
+    case NPT_FP16: hipLaunchKernelGGL(k_nif_dequant<NPT_FP16>, dim3(64), dim3(256), 0, s, master, bias, out, n); break;
+    case NPT_BF16: hipLaunchKernelGGL(k_nif_dequant<NPT_BF16>, dim3(64), dim3(256), 0, s, master, bias, out, n); break;
+    case NPT_FP8: hipLaunchKernelGGL(k_nif_dequant<NPT_FP8>, dim3(64), dim3(256), 0, s, master, bias, out, n); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -323,8 +493,7 @@ static hipError_t launch_infer_p(const void* frags, const float* bias, const Nif
   const size_t lds = nif_lds_bytes<P>();
   hipError_t e = hipFuncSetAttribute((const void*)k_nif_infer<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_nif_infer<P>, dim3(grid), dim3(kNifBlock), lds, s,
-                     (const typename Prec<P>::Frag*)frags, bias, io);
+  hipLaunchKernelGGL(k_nif_infer<P>, dim3(grid), dim3(kNifBlock), lds, s, (const uint8_t*)frags, bias, io);
   return hipGetLastError();
 }
 
@@ -334,6 +503,7 @@ static hipError_t launch_infer(int prec, const void* frags, const float* bias, c
     case NPT_FP32: return launch_infer_p<NPT_FP32>(frags, bias, io, grid, s);
     case NPT_FP16: return launch_infer_p<NPT_FP16>(frags, bias, io, grid, s);
     case NPT_BF16: return launch_infer_p<NPT_BF16>(frags, bias, io, grid, s);
+    case NPT_FP8: return launch_infer_p<NPT_FP8>(frags, bias, io, grid, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -210,7 +210,7 @@ int repack_nif(npt_ctx* c, hipStream_t s) {
   const size_t bytes = nif_packed_bytes(c->nif_prec);
   if (bytes == 0) return fail(c, NPT_E_UNSUPPORTED, "precision not supported");
   HIP_TRY(c, c->d_frags.ensure(bytes));
-  HIP_TRY(c, c->d_bias.ensure(nif::kBiasFloats * sizeof(float)));
+  HIP_TRY(c, c->d_bias.ensure(nif_bias_bytes()));
   HIP_TRY(c, launch_nif_pack(c->nif_prec, c->d_master.as<float>(), c->d_frags.p, c->d_bias.as<float>(), s));
   return NPT_OK;
 }
@@ -590,7 +590,8 @@ extern "C" int npt_nif_get_dequantized(npt_ctx* c, float* params, uint64_t n) {
   if (r) return r;
   DevBuf tmp;
   HIP_TRY(c, tmp.ensure(n * sizeof(float)));
-  hipError_t e = launch_nif_dequant(c->nif_prec, c->d_master.as<float>(), tmp.as<float>(), (int)n, nullptr);
+  hipError_t e = launch_nif_dequant(c->nif_prec, c->d_master.as<float>(), c->d_bias.as<float>(), tmp.as<float>(),
+                                    (int)n, nullptr);
   if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
   if (e == hipSuccess) e = hipMemcpy(params, tmp.p, n * sizeof(float), hipMemcpyDeviceToHost);
   tmp.release();

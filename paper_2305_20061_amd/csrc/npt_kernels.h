@@ -30,7 +30,8 @@ hipError_t launch_trace_primary(int stack_depth, const SceneView& sc, const Came
 // k_nif.hip
 size_t nif_packed_bytes(int prec);
 hipError_t launch_nif_pack(int prec, const float* master, void* frags, float* bias, hipStream_t s);
-hipError_t launch_nif_dequant(int prec, const float* master, float* out, int n, hipStream_t s);
+hipError_t launch_nif_dequant(int prec, const float* master, const float* bias, float* out, int n, hipStream_t s);
+size_t nif_bias_bytes();
 hipError_t launch_nif_queue(int prec, const void* frags, const float* bias, const EnvQueue& env, float4* L,
                             const uint32_t* cnt, uint32_t depth, uint64_t max_rays, int num_cus,
                             hipStream_t s);

@@ -79,7 +79,23 @@ __host__ __device__ constexpr int input_index(int l, int kb, int h, int e) {
 __host__ __device__ constexpr int acc_row(int mb, int h, int r) { return 32 * mb + 8 * (r / 4) + 4 * h + (r % 4); }
 
 // Bias table in LDS: 5 hidden layers x 96, then 32 for the output layer.
+// In device memory it is followed by kScaleWords words: the FP8 weight scale
+// exponent s of each layer (used by layers 1..4 in FP8 mode).
 constexpr int kBiasFloats = kLayers * kHidden + 32;
+constexpr int kScaleWords = 8;
+
+// FP8 hidden-to-hidden layers (1..4) on MFMA 32x32x64: 32 E4M3 values per
+// lane per K-block; the 96 inputs pad to two K-blocks.  K-block 0 holds
+// M-blocks 0 and 1 of the previous layer's accumulator (byte e -> M-block
+// e / 16, register e % 16), K-block 1 M-block 2 (bytes 0..15) and 16 zero
+// bytes.  Input index fed by byte e of lane half h, or -1 for padding:
+constexpr int kKB8 = 2;
+constexpr int kFp8Frags = kMB * kKB8;         // A fragments per FP8 layer
+constexpr int kFp8LayerBytes = kFp8Frags * 64 * 32;
+__host__ __device__ constexpr int input_index_fp8(int kb, int h, int e) {
+  return kb == 0 ? acc_row(e / 16, h, e % 16) : (e < 16 ? acc_row(2, h, e) : -1);
+}
+__host__ __device__ constexpr bool fp8_layer(int l) { return l >= 1 && l < kLayers; }
 
 }  // namespace nif
 }  // namespace npt

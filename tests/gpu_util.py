@@ -50,14 +50,3 @@ def rel_rmse(g, o):
     g = np.asarray(g, np.float64)
     o = np.asarray(o, np.float64)
     return float(np.sqrt(np.sum((g - o) ** 2)) / np.sqrt(np.sum(o ** 2)))
-
-
-def fp16_round(p):
-    return np.asarray(p, np.float32).astype(np.float16).astype(np.float64)
-
-
-def bf16_round(p):
-    """Round-to-nearest-even to bfloat16 (finite inputs), as float64."""
-    b = np.asarray(p, np.float32).view(np.uint32).astype(np.uint64)
-    b = ((b + 0x7FFF + ((b >> 16) & 1)) >> 16) << 16
-    return b.astype(np.uint32).view(np.float32).astype(np.float64)

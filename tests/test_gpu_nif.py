@@ -1,21 +1,27 @@
 """HDR-NIF on the GPU vs the CPU oracle (Sec. 3.2, 3.3): MFMA inference in
-FP32/FP16/BF16 against the oracle's FP64 forward on the same weights rounded
-to the inference precision; NIF-lit renders; training gradients and an Adam
-step (Sec. 3.2.1) against the oracle's FP64 backward pass."""
+FP32/FP16/BF16/FP8 against the oracle's forward pass with the same operand
+rounding (weights rounded once, each layer input rounded to its operand
+format, exact sums); NIF-lit renders; training gradients and an Adam step
+(Sec. 3.2.1) against the oracle's FP64 backward pass."""
 import numpy as np
 import pytest
 
 import oracle as O
 from paper_2305_20061_amd import npt, synth
 
-from gpu_util import (bf16_round, fp16_round, gpu_render, make_ctx, oracle_scene, rel_rmse, torch_cuda)
+from gpu_util import gpu_render, make_ctx, oracle_scene, rel_rmse, torch_cuda
 
 pytestmark = pytest.mark.gpu
 SHAPE = O.nif_shape(16, 96, 5)
+PRECS = [npt.FP32, npt.FP16, npt.BF16, npt.FP8]
+# oracle precision codes are the library's
+assert (O.PREC_FP32, O.PREC_FP16, O.PREC_BF16, O.PREC_FP8) == (npt.FP32, npt.FP16, npt.BF16, npt.FP8)
 
-# relative-RMSE bounds of the radiance of one query batch, per precision
-# (FP32 features/uv vs FP64; FP16/BF16 activation rounding)
-QUERY_TOL = {npt.FP32: 2e-4, npt.FP16: 1e-2, npt.BF16: 4e-2}
+# relative-RMSE bounds of the radiance of one query batch against the oracle
+# with the same operand rounding: what is left is FP32 accumulation order
+# and the FP32 features, which move an operand across a rounding boundary now
+# and then (one unit in its last place: 2^-11 FP16, 2^-8 BF16, 2^-4 E4M3)
+QUERY_TOL = {npt.FP32: 2e-4, npt.FP16: 2e-3, npt.BF16: 1e-2, npt.FP8: 2e-2}
 
 
 def _weights(seed=3):
@@ -25,7 +31,7 @@ def _weights(seed=3):
 
 
 def _dequant(p, prec):
-    return {npt.FP32: np.asarray(p, np.float64), npt.FP16: fp16_round(p), npt.BF16: bf16_round(p)}[prec]
+    return O.nif_dequantize(SHAPE, np.asarray(p, np.float64), prec)
 
 
 def _dirs(n, seed=0):
@@ -35,7 +41,7 @@ def _dirs(n, seed=0):
     return d.astype(np.float32)
 
 
-@pytest.mark.parametrize("prec", [npt.FP32, npt.FP16, npt.BF16])
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("n", [1, 37, 4096 + 29])
 def test_nif_query_matches_oracle(prec, n):
     torch = torch_cuda()
@@ -55,7 +61,7 @@ def test_nif_query_matches_oracle(prec, n):
         npt.npt_destroy(ctx)
     ref_p = _dequant(p, prec)
     assert np.array_equal(dq.astype(np.float64), ref_p)  # the library multiplies the same rounded weights
-    o = np.array([O.nif_radiance(SHAPE, ref_p, *O.dir_to_uv(x)) for x in d])
+    o = np.array([O.nif_radiance_q(SHAPE, ref_p, prec, *O.dir_to_uv(x)) for x in d])
     r = rel_rmse(g, o)
     print(f"prec {prec} n {n}: relRMSE {r:.3e}")
     assert np.all(g >= 0)
@@ -80,7 +86,7 @@ def test_nif_render_matches_oracle_fp32(small_sky):
     assert r <= 1e-3
 
 
-@pytest.mark.parametrize("prec", [npt.FP16, npt.BF16])
+@pytest.mark.parametrize("prec", [npt.FP16, npt.BF16, npt.FP8])
 def test_nif_render_matches_oracle_low_precision(prec, small_sky):
     scene = synth.scene_for(1)
     p = _weights()
@@ -93,7 +99,8 @@ def test_nif_render_matches_oracle_low_precision(prec, small_sky):
     finally:
         npt.npt_destroy(ctx)
     osc, cam = oracle_scene(scene)
-    o = O.render(osc, cam, O.render_desc(48, 48, 2, 6, 9, nif_params=_dequant(p, prec), nif=SHAPE))
+    o = O.render(osc, cam, O.render_desc(48, 48, 2, 6, 9, nif_params=_dequant(p, prec), nif=SHAPE,
+                                         nif_prec=prec))
     r = rel_rmse(g, o)
     print(f"NIF prec {prec} render relRMSE {r:.3e}")
     assert r <= QUERY_TOL[prec]
@@ -172,3 +179,24 @@ def test_training_beats_untrained_network(sky_map):
           f"{st['last_loss']:.3e} in {st['steps']} steps, {st['ms']:.1f} ms")
     assert st["last_loss"] < 0.2 * st["first_loss"]
     assert after["log_mse"] < 0.05 * before["log_mse"]
+
+
+def test_fp8_weight_scales_follow_each_layer():
+    # scaling one hidden layer by 2^k moves its E4M3 codes by exactly k in
+    # the exponent: the dequantised weights scale by 2^k as well
+    p = _weights()
+    q = p.copy()
+    lo = 64 * 96 + 96 + 96 * 96 + 96  # layer 2 (hidden-to-hidden)
+    q[lo:lo + 96 * 96] *= 2.0 ** -7
+    outs = []
+    for w in (p, q):
+        ctx = npt.npt_create(0)
+        try:
+            npt.npt_nif_upload(ctx, w)
+            npt.npt_nif_set_precision(ctx, npt.FP8)
+            outs.append(npt.npt_nif_get_dequantized(ctx).astype(np.float64))
+        finally:
+            npt.npt_destroy(ctx)
+    a, b = outs
+    assert np.array_equal(b[lo:lo + 96 * 96], a[lo:lo + 96 * 96] * 2.0 ** -7)
+    assert np.array_equal(np.delete(a, np.s_[lo:lo + 96 * 96]), np.delete(b, np.s_[lo:lo + 96 * 96]))
