@@ -816,13 +816,7 @@ static void prim_bounds(const mesh *m, uint32_t prim, double lo[3], double hi[3]
     }
 }
 
-static double prim_centroid(const mesh *m, uint32_t prim, int axis)
-{
-    double lo[3], hi[3];
-    prim_bounds(m, prim, lo, hi);
-    return 0.5 * (lo[axis] + hi[axis]);
-}
-
+/* Outward padding: 1e-5 of the largest coordinate magnitude. */
 static void pad_box(double lo[3], double hi[3])
 {
     double mag = 0.0;
@@ -837,22 +831,46 @@ static void pad_box(double lo[3], double hi[3])
     }
 }
 
-/* nth_element on order[lo, hi) by centroid along axis: three-way partition
- * (< pivot | == pivot | > pivot) around the middle element, so every round
- * shrinks the range. */
-static void select_nth(const mesh *m, uint32_t *order, uint32_t lo, uint32_t hi, uint32_t nth, int axis)
+/* Build-time copy of the primitive bounds in `order` position: ob[6 i ..]  */
+/* = (lo, hi) of primitive order[i], permuted together with order, so the  */
+/* median splits below read memory in sequence.                            */
+static double slot_centroid(const double *ob, uint32_t i, int axis)
 {
+    return 0.5 * (ob[6 * (size_t)i + axis] + ob[6 * (size_t)i + 3 + axis]);
+}
+
+static void swap_slots(uint32_t *order, double *ob, uint32_t i, uint32_t j)
+{
+    uint32_t t = order[i]; order[i] = order[j]; order[j] = t;
+    for (int k = 0; k < 6; ++k) {
+        double x = ob[6 * (size_t)i + k];
+        ob[6 * (size_t)i + k] = ob[6 * (size_t)j + k];
+        ob[6 * (size_t)j + k] = x;
+    }
+}
+
+/* Quickselect with a three-way partition on the centroid along `axis`: */
+/* afterwards order[nth] holds the nth smallest and is a median split.  */
+/* Pivots come from a fixed pseudo-random sequence (xorshift64), which   */
+/* keeps the expected work linear also on grid-ordered meshes, where the */
+/* middle element of a range is often near one end of its key range.    */
+static void select_nth(uint32_t *order, double *ob, uint32_t lo, uint32_t hi, uint32_t nth, int axis)
+{
+    uint64_t r = 0x9E3779B97F4A7C15ull ^ ((uint64_t)lo << 32 | hi);
     while (hi - lo > 1) {
-        double pivot = prim_centroid(m, order[lo + (hi - lo) / 2], axis);
+        r ^= r << 13;
+        r ^= r >> 7;
+        r ^= r << 17;
+        double pivot = slot_centroid(ob, lo + (uint32_t)(r % (hi - lo)), axis);
         uint32_t lt = lo, i = lo, gt = hi;
         while (i < gt) {
-            double c = prim_centroid(m, order[i], axis);
+            double c = slot_centroid(ob, i, axis);
             if (c < pivot) {
-                uint32_t t = order[lt]; order[lt] = order[i]; order[i] = t;
+                swap_slots(order, ob, lt, i);
                 ++lt; ++i;
             } else if (c > pivot) {
                 --gt;
-                uint32_t t = order[gt]; order[gt] = order[i]; order[i] = t;
+                swap_slots(order, ob, gt, i);
             } else {
                 ++i;
             }
@@ -863,15 +881,14 @@ static void select_nth(const mesh *m, uint32_t *order, uint32_t lo, uint32_t hi,
     }
 }
 
-static uint32_t build_node(mesh *m, uint32_t lo, uint32_t hi)
+static uint32_t build_node(mesh *m, double *ob, uint32_t lo, uint32_t hi)
 {
     uint32_t id = m->nnodes++;
     bvh_node *n = &m->nodes[id];
     double blo[3] = {INFINITY, INFINITY, INFINITY}, bhi[3] = {-INFINITY, -INFINITY, -INFINITY};
     double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (uint32_t i = lo; i < hi; ++i) {
-        double pl[3], ph[3];
-        prim_bounds(m, m->order[i], pl, ph);
+        const double *pl = ob + 6 * (size_t)i, *ph = pl + 3;
         for (int a = 0; a < 3; ++a) {
             if (pl[a] < blo[a]) blo[a] = pl[a];
             if (ph[a] > bhi[a]) bhi[a] = ph[a];
@@ -895,11 +912,11 @@ static uint32_t build_node(mesh *m, uint32_t lo, uint32_t hi)
     for (int a = 1; a < 3; ++a)
         if (chi[a] - clo[a] > chi[axis] - clo[axis]) axis = a;
     uint32_t mid = lo + (hi - lo) / 2;
-    select_nth(m, m->order, lo, hi, mid, axis);
+    select_nth(m->order, ob, lo, hi, mid, axis);
     n->count = 0;
     n->first = 0;
-    uint32_t l = build_node(m, lo, mid);
-    uint32_t r = build_node(m, mid, hi);
+    uint32_t l = build_node(m, ob, lo, mid);
+    uint32_t r = build_node(m, ob, mid, hi);
     m->nodes[id].left = l;
     m->nodes[id].right = r;
     return id;
@@ -940,9 +957,12 @@ static void mesh_init(mesh *m, const float *verts, uint64_t nv, const uint32_t *
     m->order = (uint32_t *)malloc(sizeof(uint32_t) * (np ? np : 1));
     for (uint64_t p = 0; p < np; ++p) m->order[p] = (uint32_t)p;
     if (accel && np > 0) {
+        double *ob = (double *)malloc(sizeof(double) * 6 * np);
+        for (uint64_t p = 0; p < np; ++p) prim_bounds(m, (uint32_t)p, ob + 6 * p, ob + 6 * p + 3);
         m->nodes = (bvh_node *)malloc(sizeof(bvh_node) * (2 * np + 1));
         m->nnodes = 0;
-        build_node(m, 0, (uint32_t)np);
+        build_node(m, ob, 0, (uint32_t)np);
+        free(ob);
     }
 }
 
