@@ -1,14 +1,20 @@
 """Benchmark: path samples/s at 1080p with HDR-NIF lighting on one MI355X.
 
-Workload: the small-BVH scene (displaced icosphere, 81,920 + 2 triangles) at
-1920x1080, 32 spp, max depth 6, lit by the HDR-NIF in FP16 on MFMA after
-on-device training (batch 65,536, 2^24 samples).  A step is one full render
-(camera rays, traversal + shading, NIF on every escaped ray, accumulation).
-Prints one JSON line.  Also reported: the same render with the plain
-environment-map lookup (rate and image difference at equal seeds), NIF
-queries/s and MFMA utilisation, the trace kernel's roofline from live HIP
-events and counted algorithmic bytes, and the CPU oracle timed on a row
-sample of the same workload.
+Workload (default): the large-BVH scene, a 2048 x 2048 fractal terrain
+(8,380,418 triangles) plus 256 instanced copies of the displaced icosphere
+(81,920 triangles each) through the two-level BVH, at 1920x1080, 64 spp, max
+depth 8, every escaped ray lit by the HDR-NIF with FP8 inference on MFMA
+after on-device training (batch 65,536, 2^24 samples, FP16 gradients).  A
+step is one full render (camera rays, traversal + shading, NIF on every
+escaped ray, accumulation).  Prints one JSON line.
+
+Also reported, on the same scene, camera and seeds: the FP16 NIF and the
+plain environment-map lookup (path rate, NIF/lookup queries/s, image
+difference), NIF throughput at a fixed 2^21-query batch, the trace kernel's
+roofline from live HIP events and counted algorithmic bytes, the small-BVH
+scene (FP16 NIF, 32 spp, depth 6) rate, and the CPU oracle timed on a row
+sample of the same workload.  --config 3 makes the small-BVH scene the
+timed workload instead.
 """
 from __future__ import annotations
 
@@ -29,13 +35,23 @@ METRIC = "path samples/s at 1080p; NIF rays/s + MFMA util vs env-map lookup at e
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"fp16": 2500.0, "bf16": 2500.0, "fp8": 5000.0, "fp32": 157.3}
 NIF_FLOP_PER_QUERY = 2 * (64 * 96 + 4 * 96 * 96 + 96 * 3)  # 86,592
-# algorithmic bytes of the trace kernel: ray in 48 B, one node
-# per BVH node fetched (64 B two-wide, 112 B four-wide), 48 B per primitive
-# slot tested, 80 B per hit (slot re-read + material), 32 B per escaped ray
-# (environment queue), 48 B per survivor
+# algorithmic bytes of the trace kernel: ray in 48 B, one node per BVH node
+# fetched (64 B two-wide, 112 B four-wide), 48 B per primitive slot tested,
+# 80 B per hit (slot re-read + material), 32 B per escaped ray (environment
+# queue), 48 B per survivor; instance records (32 B per instance entered) are
+# not counted
 B_RAY, B_PRIM, B_HIT, B_ESC, B_OUT = 48, 48, 80, 32, 48
 B_NODE = {2: 64, 4: 112}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_trace_small_bvh_1080p_traffic.json")
+WORKLOADS = {
+    4: dict(name="large-BVH", spp=64, depth=8, prec="fp8",
+            desc="large-BVH+NIF: 2048^2 terrain 8,380,418 tris + 256 instances x 81,920 tris (two-level BVH4), "
+                 "{W}x{H}, {spp} spp, max depth {depth}, FP8 NIF (64-96x5-3) trained on device, seed {seed}",
+            traffic="k_trace_large_bvh_1080p_traffic.json"),
+    3: dict(name="small-BVH", spp=32, depth=6, prec="fp16",
+            desc="small-BVH+NIF: displaced icosphere 81,922 tris, {W}x{H}, {spp} spp, max depth {depth}, "
+                 "FP16 NIF (64-96x5-3) trained on device, seed {seed}",
+            traffic="k_trace_small_bvh_1080p_traffic.json"),
+}
 
 
 def _parse():
@@ -43,13 +59,13 @@ def _parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--config", type=int, default=4, choices=(3, 4))
     p.add_argument("--width", type=int, default=1920)
     p.add_argument("--height", type=int, default=1080)
-    p.add_argument("--spp", type=int, default=32)
-    p.add_argument("--depth", type=int, default=6)
     p.add_argument("--train-samples", type=int, default=1 << 24)
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--no-envmap", action="store_true")
+    p.add_argument("--no-envmap", action="store_true", help="skip the FP16-NIF and env-map comparison renders")
+    p.add_argument("--no-small", action="store_true", help="skip the small-BVH rate")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="run one 1 GiB device copy (rocprof counter calibration)")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -63,11 +79,11 @@ def _kernel_sha():
     return h.hexdigest()[:16]
 
 
-def _traffic_per_launch():
+def _traffic_per_launch(name):
     """HBM bytes per trace launch from committed rocprofv3 counters, if they
     were taken on the current kernel source."""
     try:
-        t = json.load(open(TRAFFIC_FILE))
+        t = json.load(open(os.path.join(ROOT, "profiles", name)))
     except (OSError, ValueError):
         return None
     if t.get("kernel_sha") != _kernel_sha():
@@ -77,13 +93,15 @@ def _traffic_per_launch():
 
 def _oracle_rows(args):
     """Worker: oracle render of a row subset; returns path samples traced."""
-    scene_cfg, rows, W, H, spp, depth, seed, params = args
+    cfg, rows, W, H, spp, depth, seed, prec = args
     import oracle as O
     from paper_2305_20061_amd import synth
-    sc = synth.scene_for(scene_cfg)
+    sc = synth.scene_for(cfg)
     S = O.Scene(sc, accel=1)
     cam = O.make_camera(**sc["camera"])
-    rd = O.render_desc(W, H, spp, depth, seed, nif_params=params, nif=O.nif_shape())
+    shape = O.nif_shape()
+    params = O.nif_dequantize(shape, synth.nif_init(3).astype(np.float32).astype(np.float64), prec)
+    rd = O.render_desc(W, H, spp, depth, seed, nif_params=params, nif=shape, nif_prec=prec)
     out = np.zeros((H, W, 3))
     n = 0
     t0 = time.perf_counter()
@@ -93,28 +111,56 @@ def _oracle_rows(args):
     return n, time.perf_counter() - t0
 
 
-def cpu_baseline(W, H, spp, depth, seed, seconds):
-    """The oracle (single-threaded C, FP64 NIF) on a bounded row sample, run as
-    one process per host core over disjoint rows."""
-    from paper_2305_20061_amd import synth
-    params = synth.nif_init(3).astype(np.float32).astype(np.float16).astype(np.float64)
+def cpu_baseline(cfg, W, H, spp, depth, seed, prec, seconds):
+    """The oracle (single-threaded C, FP64 sums) on a bounded row sample, run
+    as one process per host core over disjoint rows."""
     cores = max(1, min(16, os.cpu_count() or 1))
-    # calibrate one row on one core
-    n1, t1 = _oracle_rows((3, [H // 2], W, H, spp, depth, seed, params))
-    per_row = t1
-    rows_total = max(cores, int(seconds * cores / max(per_row, 1e-3)))
-    rows_total = min(rows_total, H)
+    with mp.get_context("spawn").Pool(1) as pool:  # one row on one core
+        _, per_row = pool.map(_oracle_rows, [(cfg, [H // 2], W, H, spp, depth, seed, prec)])[0]
+    rows_total = min(H, max(cores, int(seconds * cores / max(per_row, 1e-3))))
     step = max(1, H // rows_total)
     rows = list(range(0, H, step))[:rows_total]
     chunks = [rows[i::cores] for i in range(cores)]
-    t0 = time.perf_counter()
     with mp.get_context("spawn").Pool(cores) as pool:
-        res = pool.map(_oracle_rows, [(3, c, W, H, spp, depth, seed, params) for c in chunks if c])
-    wall = time.perf_counter() - t0
+        res = pool.map(_oracle_rows, [(cfg, c, W, H, spp, depth, seed, prec) for c in chunks if c])
     paths = sum(r[0] for r in res)
+    wall = max(r[1] for r in res)  # render time of the slowest worker (scene setup excluded)
     return {"value": paths / wall, "unit": "path samples/s", "cores": cores, "kind": "oracle",
-            "sample": f"{len(rows)} of {H} rows (every {step}th), {W} px x {spp} spp each, "
-                      f"depth {depth}, FP64 NIF; {paths} path samples in {wall:.1f} s"}
+            "sample": f"{len(rows)} of {H} rows (every {step}th), {W} px x {spp} spp each, depth {depth}, "
+                      f"{['FP32', 'FP16', 'BF16', 'FP8'][prec]}-rounded NIF operands with FP64 sums; "
+                      f"{paths} path samples, slowest worker {wall:.1f} s"}
+
+
+def _timed_renders(npt, torch, ctx, W, H, spp, depth, seed, out, steps, warmup):
+    for _ in range(warmup):
+        npt.npt_render(ctx, W, H, spp, depth, seed, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        npt.npt_render(ctx, W, H, spp, depth, seed, out)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, npt.npt_get_stats(ctx)
+
+
+def _query_rate(npt, torch, ctx, mode, n=1 << 21, reps=20):
+    """env queries/s of one mode at a fixed batch (events on the stream the
+    library launches on: the null stream, torch's default)."""
+    g = torch.Generator(device="cpu").manual_seed(0)
+    d = torch.randn(n, 3, generator=g)
+    d = (d / d.norm(dim=1, keepdim=True)).cuda()
+    out = torch.empty(n, 3, device="cuda")
+    npt.npt_env_query(ctx, mode, d, out)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        npt.npt_env_query(ctx, mode, d, out)
+    e1.record()
+    torch.cuda.synchronize()
+    return n * reps / (e0.elapsed_time(e1) * 1e-3)
+
+
+def _rel(a, b):
+    return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b ** 2)))
 
 
 def main():
@@ -128,24 +174,32 @@ def main():
     from paper_2305_20061_amd import npt, synth
 
     torch.cuda.set_device(0)
-    W, H, spp, depth, seed = args.width, args.height, args.spp, args.depth, 1
-    scene = synth.scene_for(3)
+    wl = WORKLOADS[args.config]
+    W, H, spp, depth, seed = args.width, args.height, wl["spp"], wl["depth"], 1
+    prec_name = wl["prec"]
+    prec = {"fp8": npt.FP8, "fp16": npt.FP16}[prec_name]
     env = synth.env_map()
-    ctx = npt.npt_create(0)
     extra = {}
+    t0 = time.perf_counter()
+    scene = synth.scene_for(args.config)
+    extra["scene_gen_ms"] = 1e3 * (time.perf_counter() - t0)
+    ctx = npt.npt_create(0)
     try:
         t0 = time.perf_counter()
         # 4-wide BVH, leaf size 2, no LDS-staged levels: fastest in the sweep
         npt.npt_load_scene(ctx, scene, max_leaf=2, lds_levels=0, width=4)
         extra["bvh_build_ms"] = 1e3 * (time.perf_counter() - t0)
         extra["bvh"] = npt.npt_bvh_info(ctx)
+        del scene
         npt.npt_env_upload(ctx, env)
         npt.npt_nif_upload(ctx, synth.nif_init(3))
-        npt.npt_nif_set_precision(ctx, npt.FP16)
         tr = npt.npt_nif_train(ctx, npt.train_params(batch=65536, samples=args.train_samples, seed=1,
                                                      grad_prec=npt.FP16))
+        npt.npt_nif_set_precision(ctx, prec)
         extra["train"] = {"ms": tr["ms"], "steps": tr["steps"], "first_loss": tr["first_loss"],
-                          "last_loss": tr["last_loss"], "grid_eval": npt.npt_nif_eval_grid(ctx, 1024, 512)}
+                          "last_loss": tr["last_loss"],
+                          "grid_eval": npt.npt_nif_eval_grid(ctx, 1024, 512)}
+        trained = npt.npt_nif_download(ctx)
         npt.npt_set_env_mode(ctx, npt.ENV_NIF)
         out = torch.empty(H, W, 3, dtype=torch.float32, device="cuda")
 
@@ -169,66 +223,85 @@ def main():
         tests = np.array(cs["prim_tests"], np.float64)
         survivors = np.concatenate([rays[1:], [0.0]])
         hits = rays - esc
-        alg_bytes = float(np.sum(B_RAY * rays + B_NODE[extra["bvh"]["width"]] * visits + B_PRIM * tests + B_HIT * hits
-                                 + B_ESC * esc + B_OUT * survivors))
+        alg_bytes = float(np.sum(B_RAY * rays + B_NODE[extra["bvh"]["width"]] * visits + B_PRIM * tests
+                                 + B_HIT * hits + B_ESC * esc + B_OUT * survivors))
         extra["per_ray"] = {"node_visits": float(visits.sum() / rays.sum()),
                             "prim_tests": float(tests.sum() / rays.sum()),
                             "rays_per_path": float(rays.sum() / cs["paths"]),
                             "escaped_per_path": float(esc.sum() / cs["paths"])}
 
-        # timed renders with per-kernel events
+        # the timed workload, with per-kernel events
         npt.npt_set_render_options(ctx, rr_start=3, kernel_timing=1)
-        for _ in range(args.warmup):
-            npt.npt_render(ctx, W, H, spp, depth, seed, out)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            npt.npt_render(ctx, W, H, spp, depth, seed, out)
-        torch.cuda.synchronize()
-        elapsed = time.perf_counter() - t0
-        st = npt.npt_get_stats(ctx)  # events of the last timed render
-        img_nif = out.cpu().numpy().astype(np.float64)
+        elapsed, st = _timed_renders(npt, torch, ctx, W, H, spp, depth, seed, out, args.steps, args.warmup)
+        img = {prec_name: out.cpu().numpy().astype(np.float64)}
         ms_step = 1e3 * elapsed / args.steps
         value = W * H * spp * args.steps / elapsed
 
         trace_launch_ms = st["ms_trace"] / max(1, st["trace_launches"])
         achieved = alg_bytes / st["trace_launches"] / (trace_launch_ms * 1e-3) / 1e9
-        traffic = _traffic_per_launch()
-        nif_tflops = st["env_queries"] * NIF_FLOP_PER_QUERY / (st["ms_env"] * 1e-3) / 1e12
+        traffic = _traffic_per_launch(wl["traffic"])
+
+        def nif_stats(s, name):
+            tf = s["env_queries"] * NIF_FLOP_PER_QUERY / (s["ms_env"] * 1e-3) / 1e12
+            return {"precision": name, "queries_per_render": s["env_queries"],
+                    "queries_per_s": s["env_queries"] / (s["ms_env"] * 1e-3), "ms_per_render": s["ms_env"],
+                    "launches": s["env_launches"], "tflops": tf, "mfma_util": tf / MFMA_PEAK_TFLOPS[name],
+                    "flop_per_query": NIF_FLOP_PER_QUERY}
+
         extra["kernels"] = {"trace_ms_per_render": st["ms_trace"], "trace_launches": st["trace_launches"],
                             "trace_ms_per_launch": trace_launch_ms, "nif_ms_per_render": st["ms_env"],
-                            "nif_launches": st["env_launches"], "render_ms_device": st["ms_total"]}
-        extra["nif"] = {"precision": "fp16", "queries_per_render": st["env_queries"],
-                        "queries_per_s": st["env_queries"] / (st["ms_env"] * 1e-3),
-                        "tflops": nif_tflops, "mfma_util": nif_tflops / MFMA_PEAK_TFLOPS["fp16"],
-                        "flop_per_query": NIF_FLOP_PER_QUERY}
+                            "render_ms_device": st["ms_total"]}
+        extra["nif"] = nif_stats(st, prec_name)
+        extra["nif"]["fixed_batch_2^21_queries_per_s"] = _query_rate(npt, torch, ctx, npt.ENV_NIF)
 
         if not args.no_envmap:
+            modes = {}
+            if prec_name != "fp16":
+                npt.npt_nif_set_precision(ctx, npt.FP16)
+                el, s16 = _timed_renders(npt, torch, ctx, W, H, spp, depth, seed, out, args.steps, 1)
+                img["fp16"] = out.cpu().numpy().astype(np.float64)
+                modes["nif_fp16"] = {"path_samples_per_s": W * H * spp * args.steps / el,
+                                     **nif_stats(s16, "fp16"),
+                                     "fixed_batch_2^21_queries_per_s": _query_rate(npt, torch, ctx, npt.ENV_NIF)}
+                npt.npt_nif_set_precision(ctx, prec)
             npt.npt_set_env_mode(ctx, npt.ENV_MAP)
-            npt.npt_render(ctx, W, H, spp, depth, seed, out)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            for _ in range(args.steps):
-                npt.npt_render(ctx, W, H, spp, depth, seed, out)
-            torch.cuda.synchronize()
-            e_el = time.perf_counter() - t1
-            se = npt.npt_get_stats(ctx)
-            img_map = out.cpu().numpy().astype(np.float64)
-            rel = float(np.sqrt(np.sum((img_nif - img_map) ** 2) / np.sum(img_map ** 2)))
-            extra["env_map"] = {"path_samples_per_s": W * H * spp * args.steps / e_el,
+            el, se = _timed_renders(npt, torch, ctx, W, H, spp, depth, seed, out, args.steps, 1)
+            img["map"] = out.cpu().numpy().astype(np.float64)
+            modes["env_map"] = {"path_samples_per_s": W * H * spp * args.steps / el,
                                 "lookup_queries_per_s": se["env_queries"] / (se["ms_env"] * 1e-3),
                                 "lookup_ms_per_render": se["ms_env"],
-                                "nif_vs_envmap_image_rel_rmse": rel}
+                                "fixed_batch_2^21_queries_per_s": _query_rate(npt, torch, ctx, npt.ENV_MAP)}
+            # image error of each NIF precision against the map render at equal seeds
+            modes["image_rel_rmse_vs_env_map"] = {k: _rel(v, img["map"]) for k, v in img.items() if k != "map"}
+            if "fp16" in img and prec_name != "fp16":
+                modes["image_rel_rmse_fp8_vs_fp16"] = _rel(img[prec_name], img["fp16"])
+            extra["compare"] = modes
             npt.npt_set_env_mode(ctx, npt.ENV_NIF)
     finally:
         npt.npt_destroy(ctx)
 
+    if args.config == 4 and not args.no_small:
+        # the small-BVH scene with the same trained network in FP16
+        c3 = WORKLOADS[3]
+        ctx = npt.npt_create(0)
+        try:
+            npt.npt_load_scene(ctx, synth.scene_for(3), max_leaf=2, lds_levels=0, width=4)
+            npt.npt_nif_upload(ctx, trained)
+            npt.npt_nif_set_precision(ctx, npt.FP16)
+            npt.npt_set_env_mode(ctx, npt.ENV_NIF)
+            npt.npt_set_render_options(ctx, rr_start=3, kernel_timing=1)
+            el, s3 = _timed_renders(npt, torch, ctx, W, H, c3["spp"], c3["depth"], seed, out, args.steps, 1)
+            extra["small_bvh_fp16"] = {"path_samples_per_s": W * H * c3["spp"] * args.steps / el,
+                                       "ms_per_render": 1e3 * el / args.steps, "trace_ms_per_render": s3["ms_trace"],
+                                       "nif_ms_per_render": s3["ms_env"], "spp": c3["spp"], "max_depth": c3["depth"]}
+        finally:
+            npt.npt_destroy(ctx)
+
     line = {
         "metric": METRIC, "value": value, "unit": "path samples/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32 rays / f16 NIF", "data": "synthetic",
-        "config": {"workload": f"small-BVH+NIF: displaced icosphere 81,922 tris, {W}x{H}, {spp} spp, "
-                               f"max depth {depth}, FP16 NIF (64-96x5-3) trained on device, seed {seed}",
+        "vs_baseline": None, "dtype": f"f32 rays / {prec_name} NIF", "data": "synthetic",
+        "config": {"workload": wl["desc"].format(W=W, H=H, spp=spp, depth=depth, seed=seed),
                    "paths_per_step": W * H * spp},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
@@ -237,7 +310,7 @@ def main():
     }
     line.update(extra)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(W, H, spp, depth, seed, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(args.config, W, H, spp, depth, seed, prec, args.cpu_seconds)
     print(json.dumps(line), flush=True)
 
 
