@@ -120,10 +120,11 @@ typedef struct {
 /* Render options.  rr_start: first depth with Russian roulette (Sec. 4: 3);
  * samples_per_pass: samples traced together (0 = library default, sized
  * from the pool); pool_paths: upper bound on paths in flight (0 = 2^26,
- * 144 bytes of device queues per path);
- * kernel_timing: 1 = time every trace and environment launch with HIP
- * events on the render stream (npt_stats.ms_trace / ms_env);
- * count_visits: 1 = use the counting variant of the trace kernel
+ * 160 bytes of device queues per path);
+ * kernel_timing: 1 = time every extend (closest hit), shade and
+ * environment launch with HIP events on the render stream
+ * (npt_stats.ms_trace / ms_shade / ms_env);
+ * count_visits: 1 = use the counting variant of the extend kernel
  * (npt_stats.node_visits / prim_tests; slower, for byte accounting only). */
 typedef struct {
     uint32_t rr_start;
@@ -144,12 +145,16 @@ typedef struct {
     uint32_t passes;
     uint32_t samples_per_pass;
     float ms_total;                      /* device time of the last render         */
-    /* kernel_timing: summed event time and launch counts */
+    /* kernel_timing: summed event time and launch counts (trace = the
+     * extend kernel: BVH traversal and primitive tests) */
     float ms_trace, ms_env;
     uint32_t trace_launches, env_launches;
     /* count_visits: BVH nodes fetched / primitives tested at depth k */
     uint64_t node_visits[NPT_MAX_DEPTH];
     uint64_t prim_tests[NPT_MAX_DEPTH];
+    /* kernel_timing: the shade kernel (emission, BSDF sampling, roulette) */
+    float ms_shade;
+    uint32_t shade_launches;
 } npt_stats;
 
 /* ---- context ------------------------------------------------------------- */

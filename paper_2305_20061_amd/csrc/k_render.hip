@@ -13,30 +13,16 @@ namespace npt {
 #ifndef NPT_TRACE_BLOCK
 #define NPT_TRACE_BLOCK 64  // one wave per workgroup: measured fastest (64 < 128 < 256)
 #endif
-#ifndef NPT_STACK_IN_SCRATCH
-#define NPT_STACK_IN_SCRATCH 0
+#ifndef NPT_SHORT_STACK
+#define NPT_SHORT_STACK 16  // traversal stack entries per lane kept in LDS
 #endif
 constexpr int kTraceBlock = NPT_TRACE_BLOCK;
 constexpr int kWave = 64;
 constexpr uint32_t kMaxVisits = 1u << 22;
-
-// ---------------------------------------------------------------------------
-// wave-level compaction: one atomic per wave, ballot + mbcnt for the offsets
-// (all 64 lanes must call it)
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t wave_append(bool pred, uint32_t* counter) {
-  const uint64_t mask = __ballot(pred);
-  const uint32_t lane_prefix =
-      __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-  uint32_t base = 0;
-  if (mask != 0) {
-    const int leader = __ffsll((unsigned long long)mask) - 1;
-    uint32_t b = 0;
-    if ((int)(threadIdx.x & (kWave - 1)) == leader) b = atomicAdd(counter, (uint32_t)__popcll(mask));
-    base = __shfl(b, leader);
-  }
-  return base + lane_prefix;
-}
+#ifndef NPT_REFILL_AT
+#define NPT_REFILL_AT 48  // lanes still traversing at which a wave takes new rays
+#endif
+constexpr int kRefillAt = NPT_REFILL_AT;
 
 // ---------------------------------------------------------------------------
 // camera (pinhole) -- same definitions as the host-side basis
@@ -62,9 +48,40 @@ __device__ __forceinline__ V3 camera_direction(const CameraView& cam, uint32_t W
 // ---------------------------------------------------------------------------
 struct Hit {
   float t;
-  uint32_t slot;
-  uint32_t prim;
+  uint32_t slot;  // primitive slot (its id in the slot's first .w)
   uint32_t inst;  // 0 for the base geometry, k + 1 for instance k
+};
+
+__device__ __forceinline__ uint32_t slot_prim(const float4* slots, uint32_t slot) {
+  return __float_as_uint(slots[3 * (size_t)slot].w);
+}
+
+// Per-lane traversal stack of kCap entries: the first kShort live in LDS at
+// lds[i * kStride], deeper ones in a private array that only deep
+// traversals reach.  The LDS part is what bounds the occupancy of the trace
+// kernels.  A push beyond kCap is dropped; kCap is sized from the tree depth
+// so that it never is.
+template <int kCap, int kStride>
+struct LaneStack {
+  static constexpr int kShort = kCap < NPT_SHORT_STACK ? kCap : NPT_SHORT_STACK;
+  static constexpr int kDeep = kCap - kShort;
+  uint32_t* lds;
+  uint32_t deep[kDeep > 0 ? kDeep : 1];
+  __device__ __forceinline__ void push(int& sp, uint32_t v) {
+    if (sp < kShort) {
+      lds[sp * kStride] = v;
+    } else if (kDeep > 0 && sp < kCap) {
+      deep[sp - kShort] = v;
+    } else {
+      return;
+    }
+    ++sp;
+  }
+  __device__ __forceinline__ uint32_t pop(int& sp) {
+    --sp;
+    if (kDeep == 0 || sp < kShort) return lds[sp * kStride];
+    return deep[sp - kShort];
+  }
 };
 
 __device__ __forceinline__ float safe_inverse(float x) {
@@ -143,65 +160,18 @@ __device__ __forceinline__ void test_leaf(const SceneView& sc, const RayFrame& f
       hit = hit_triangle(f.o, f.sh, V3{s0.x, s0.y, s0.z}, V3{s1.x, s1.y, s1.z}, V3{s2.x, s2.y, s2.z}, h.t, t);
     else
       hit = hit_sphere(f.o, f.d, V3{s0.x, s0.y, s0.z}, s1.x, h.t, t);
-    // a hit has t <= h.t, so "t < h.t or a smaller key" is the tie rule
-    if (hit && (t < h.t || inst < h.inst || (inst == h.inst && prim < h.prim))) {
-      h.t = t;
-      h.slot = first + i;
-      h.prim = prim;
-      h.inst = inst;
+    // a hit has t <= h.t, so "t < h.t or a smaller key" is the tie rule;
+    // the kept hit's primitive id is read back only on a tie
+    if (hit) {
+      bool take = t < h.t || inst < h.inst;
+      if (!take && inst == h.inst) take = prim < slot_prim(sc.slots, h.slot);
+      if (take) {
+        h.t = t;
+        h.slot = first + i;
+        h.inst = inst;
+      }
     }
   }
-}
-
-// Binary tree.  Per-lane stack entry i lives at stack[i * kStride]; kCount:
-// also count inner-node fetches (n_nodes) and primitive tests (n_prims).
-template <int kStack, int kStride, bool kCount = false>
-__device__ __forceinline__ Hit closest_hit(const SceneView& sc, const float4* lds_nodes,
-                                           uint32_t* stack, V3 o, V3 d, uint32_t* n_nodes = nullptr,
-                                           uint32_t* n_prims = nullptr) {
-  Hit h{__builtin_inff(), kMiss, kMiss, kMiss};
-  if (!sc.has_geometry) return h;
-  const RayFrame f = make_frame(o, d);
-  uint32_t ref = 0;
-  int sp = 0;
-  // a bound every traversal reaches: a well-formed tree visits each node at
-  // most once per ray, so this only guards against a malformed upload
-  for (uint32_t visits = 0; visits < kMaxVisits; ++visits) {
-    if ((ref & kLeafBit) == 0u) {
-      float4 n0, n1, n2, n3;
-      if (ref < sc.lds_nodes) {
-        const float4* p = lds_nodes + 4 * ref;
-        n0 = p[0]; n1 = p[1]; n2 = p[2]; n3 = p[3];
-      } else {
-        const float4* p = sc.nodes + 4 * (size_t)ref;
-        n0 = p[0]; n1 = p[1]; n2 = p[2]; n3 = p[3];
-      }
-      if constexpr (kCount) ++*n_nodes;
-      const float lim = h.t * 1.000001f;
-      float lo0, hi0, lo1, hi1;
-      slab(f, n0.x, n0.y, n0.z, n0.w, n2.x, n2.y, lim, lo0, hi0);
-      slab(f, n1.x, n1.y, n1.z, n1.w, n2.z, n2.w, lim, lo1, hi1);
-      const bool h0 = lo0 <= hi0, h1 = lo1 <= hi1;
-      const uint32_t r0 = __float_as_uint(n3.x), r1 = __float_as_uint(n3.y);
-      if (h0 && h1) {
-        const bool near0 = lo0 <= lo1;
-        if (sp < kStack) {
-          stack[sp * kStride] = near0 ? r1 : r0;
-          ++sp;
-        }
-        ref = near0 ? r0 : r1;
-        continue;
-      }
-      if (h0) { ref = r0; continue; }
-      if (h1) { ref = r1; continue; }
-    } else {
-      test_leaf<kCount>(sc, f, ref, 0u, h, n_prims);
-    }
-    if (sp == 0) break;
-    --sp;
-    ref = stack[sp * kStride];
-  }
-  return h;
 }
 
 // compare-exchange of (entry distance, ref) pairs, ascending by distance
@@ -225,8 +195,8 @@ __device__ __forceinline__ float child_entry(const RayFrame& f, float lx, float 
 
 // One 4-wide node: the children the ray enters, nearest first in `ref`, the
 // others pushed far to near.  Returns false when no child is entered.
-template <int kStack, int kStride>
-__device__ __forceinline__ bool visit4(const float4* p, const RayFrame& f, float lim, uint32_t* stack, int& sp,
+template <class S>
+__device__ __forceinline__ bool visit4(const float4* p, const RayFrame& f, float lim, S& st, int& sp,
                                        uint32_t& ref) {
   const float4 lx = p[0], hx = p[1], ly = p[2], hy = p[3], lz = p[4], hz = p[5], rf = p[6];
   uint32_t r0 = __float_as_uint(rf.x), r1 = __float_as_uint(rf.y), r2 = __float_as_uint(rf.z),
@@ -242,90 +212,141 @@ __device__ __forceinline__ bool visit4(const float4* p, const RayFrame& f, float
   order2(k1, r1, k2, r2);
   const float inf = __builtin_inff();
   if (!(k0 < inf)) return false;
-  if (k3 < inf && sp < kStack) stack[(sp++) * kStride] = r3;
-  if (k2 < inf && sp < kStack) stack[(sp++) * kStride] = r2;
-  if (k1 < inf && sp < kStack) stack[(sp++) * kStride] = r1;
+  if (k3 < inf) st.push(sp, r3);
+  if (k2 < inf) st.push(sp, r2);
+  if (k1 < inf) st.push(sp, r1);
   ref = r0;
   return true;
-}
-
-// 4-wide tree: same primitive tests and tie rule as the binary traversal.
-template <int kStack, int kStride, bool kCount = false>
-__device__ __forceinline__ Hit closest_hit4(const SceneView& sc, const float4* lds_nodes, uint32_t* stack, V3 o,
-                                            V3 d, uint32_t* n_nodes = nullptr, uint32_t* n_prims = nullptr) {
-  Hit h{__builtin_inff(), kMiss, kMiss, kMiss};
-  if (!sc.has_geometry) return h;
-  const RayFrame f = make_frame(o, d);
-  uint32_t ref = 0;
-  int sp = 0;
-  for (uint32_t visits = 0; visits < kMaxVisits; ++visits) {
-    if ((ref & kLeafBit) == 0u) {
-      const float4* p = ref < sc.lds_nodes ? lds_nodes + 7 * ref : sc.nodes + 7 * (size_t)ref;
-      if constexpr (kCount) ++*n_nodes;
-      if (visit4<kStack, kStride>(p, f, h.t * 1.000001f, stack, sp, ref)) continue;
-    } else {
-      test_leaf<kCount>(sc, f, ref, 0u, h, n_prims);
-    }
-    if (sp == 0) break;
-    --sp;
-    ref = stack[sp * kStride];
-  }
-  return h;
 }
 
 // Tree kind of the instanced (two-level, 4-wide) traversal, next to the
 // widths 2 and 4 of the one-level traversals.
 constexpr int kTwoLevel = 1;
 
-// Two-level scene.  Top-tree leaves are instances: entering one moves the
-// ray into object space and records the stack height; once the stack is
-// back at that height the bottom tree is done and the world ray returns.
-template <int kStack, int kStride, bool kCount = false>
-__device__ __forceinline__ Hit closest_hit_two_level(const SceneView& sc, uint32_t* stack, V3 ow, V3 dw,
-                                                     uint32_t* n_nodes = nullptr, uint32_t* n_prims = nullptr) {
-  Hit h{__builtin_inff(), kMiss, kMiss, kMiss};
-  if (!sc.has_geometry) return h;
-  RayFrame f = make_frame(ow, dw);
-  uint32_t ref = 0, inst = 0;
-  int sp = 0, mark = -1;
-  for (uint32_t visits = 0; visits < kMaxVisits; ++visits) {
-    if ((ref & kLeafBit) == 0u) {
-      if constexpr (kCount) ++*n_nodes;
-      if (visit4<kStack, kStride>(sc.nodes + 7 * (size_t)ref, f, h.t * 1.000001f, stack, sp, ref)) continue;
-    } else if (mark < 0) {
-      // top-tree leaf: enter the instance's bottom tree in object space
-      const uint32_t k = (ref >> 3) & 0x0FFFFFFFu;
-      const float4 r0 = sc.instances[2 * (size_t)k], r1 = sc.instances[2 * (size_t)k + 1];
-      const V3 o{(ow.x - r0.x) / r0.w, (ow.y - r0.y) / r0.w, (ow.z - r0.z) / r0.w};
-      const V3 d{dw.x / r0.w, dw.y / r0.w, dw.z / r0.w};
-      f = make_frame(o, d);
-      inst = __float_as_uint(r1.y);
-      ref = __float_as_uint(r1.x);
-      mark = sp;
-      continue;
-    } else {
-      test_leaf<kCount>(sc, f, ref, inst, h, n_prims);
-    }
-    if (sp == mark) {
-      f = make_frame(ow, dw);
-      mark = -1;
-    }
-    if (sp == 0) break;
-    --sp;
-    ref = stack[sp * kStride];
+// The world ray of a two-level traversal waits in LDS (six values per lane,
+// stride kStride) rather than in registers: it is needed only when an
+// instance is entered or left.  Volatile reads keep the compiler from
+// holding a register copy across the traversal.
+template <int kStride>
+struct WorldRay {
+  float* p;
+  __device__ __forceinline__ void store(V3 o, V3 d) const {
+    p[0] = o.x; p[kStride] = o.y; p[2 * kStride] = o.z;
+    p[3 * kStride] = d.x; p[4 * kStride] = d.y; p[5 * kStride] = d.z;
   }
-  return h;
+  __device__ __forceinline__ void load(V3& o, V3& d) const {
+    const volatile float* v = p;
+    o = V3{v[0], v[kStride], v[2 * kStride]};
+    d = V3{v[3 * kStride], v[4 * kStride], v[5 * kStride]};
+  }
+};
+
+// Traversal state of one ray, advanced one node or leaf at a time so that
+// a lane can take a new ray while others in its wave still traverse.
+// Two-level scenes: mark is the stack height at which the current
+// instance's bottom tree began (-1 in the top tree), inst its id.  Top-tree
+// leaves are instances: entering one moves the ray into object space; once
+// the stack is back at the mark the world ray returns.
+struct Trav {
+  RayFrame f;
+  Hit h;
+  uint32_t ref;
+  int sp;
+  int mark;
+  uint32_t inst;
+};
+
+// Starts a traversal at the root; false when the scene has no geometry
+// (the ray then misses).  Two-level callers store (o, d) in their WorldRay.
+__device__ __forceinline__ bool trav_begin(const SceneView& sc, V3 o, V3 d, Trav& tv) {
+  tv.h = Hit{__builtin_inff(), kMiss, kMiss};
+  tv.ref = 0;
+  tv.sp = 0;
+  tv.mark = -1;
+  tv.inst = 0;
+  tv.f = make_frame(o, d);
+  return sc.has_geometry != 0;
 }
 
-template <int kWidth, int kStack, int kStride, bool kCount = false>
-__device__ __forceinline__ Hit trace_closest(const SceneView& sc, const float4* lds_nodes, uint32_t* stack, V3 o,
-                                             V3 d, uint32_t* n_nodes = nullptr, uint32_t* n_prims = nullptr) {
-  if constexpr (kWidth == kTwoLevel)
-    return closest_hit_two_level<kStack, kStride, kCount>(sc, stack, o, d, n_nodes, n_prims);
-  else if constexpr (kWidth == 4)
-    return closest_hit4<kStack, kStride, kCount>(sc, lds_nodes, stack, o, d, n_nodes, n_prims);
-  else
-    return closest_hit<kStack, kStride, kCount>(sc, lds_nodes, stack, o, d, n_nodes, n_prims);
+// One step: an inner node (entered children pushed far to near, the
+// nearest taken), an instance entered, or a leaf's primitives tested, then
+// a pop when no child was taken.  Returns false once the stack is empty.
+// kCount: also count inner-node fetches and primitive tests.
+template <int kWidth, bool kCount, class S, int kStride>
+__device__ __forceinline__ bool trav_step(const SceneView& sc, const float4* lds_nodes, S& st,
+                                          const WorldRay<kStride>& wr, Trav& tv, uint32_t& n_nodes,
+                                          uint32_t& n_prims) {
+  if ((tv.ref & kLeafBit) == 0u) {
+    if constexpr (kCount) ++n_nodes;
+    const float lim = tv.h.t * 1.000001f;
+    if constexpr (kWidth == 2) {
+      float4 n0, n1, n2, n3;
+      if (tv.ref < sc.lds_nodes) {
+        const float4* p = lds_nodes + 4 * tv.ref;
+        n0 = p[0]; n1 = p[1]; n2 = p[2]; n3 = p[3];
+      } else {
+        const float4* p = sc.nodes + 4 * (size_t)tv.ref;
+        n0 = p[0]; n1 = p[1]; n2 = p[2]; n3 = p[3];
+      }
+      float lo0, hi0, lo1, hi1;
+      slab(tv.f, n0.x, n0.y, n0.z, n0.w, n2.x, n2.y, lim, lo0, hi0);
+      slab(tv.f, n1.x, n1.y, n1.z, n1.w, n2.z, n2.w, lim, lo1, hi1);
+      const bool h0 = lo0 <= hi0, h1 = lo1 <= hi1;
+      const uint32_t r0 = __float_as_uint(n3.x), r1 = __float_as_uint(n3.y);
+      if (h0 && h1) {
+        const bool near0 = lo0 <= lo1;
+        st.push(tv.sp, near0 ? r1 : r0);
+        tv.ref = near0 ? r0 : r1;
+        return true;
+      }
+      if (h0) { tv.ref = r0; return true; }
+      if (h1) { tv.ref = r1; return true; }
+    } else {
+      const float4* p = (kWidth == 4 && tv.ref < sc.lds_nodes) ? lds_nodes + 7 * tv.ref
+                                                               : sc.nodes + 7 * (size_t)tv.ref;
+      if (visit4(p, tv.f, lim, st, tv.sp, tv.ref)) return true;
+    }
+  } else if (kWidth == kTwoLevel && tv.mark < 0) {
+    // top-tree leaf: enter the instance's bottom tree in object space
+    const uint32_t k = (tv.ref >> 3) & 0x0FFFFFFFu;
+    const float4 r0 = sc.instances[2 * (size_t)k], r1 = sc.instances[2 * (size_t)k + 1];
+    V3 ow, dw;
+    wr.load(ow, dw);
+    const V3 o{(ow.x - r0.x) / r0.w, (ow.y - r0.y) / r0.w, (ow.z - r0.z) / r0.w};
+    const V3 d{dw.x / r0.w, dw.y / r0.w, dw.z / r0.w};
+    tv.f = make_frame(o, d);
+    tv.inst = __float_as_uint(r1.y);
+    tv.ref = __float_as_uint(r1.x);
+    tv.mark = tv.sp;
+    return true;
+  } else {
+    test_leaf<kCount>(sc, tv.f, tv.ref, kWidth == kTwoLevel ? tv.inst : 0u, tv.h, &n_prims);
+  }
+  if constexpr (kWidth == kTwoLevel) {
+    if (tv.sp == tv.mark) {
+      V3 ow, dw;
+      wr.load(ow, dw);
+      tv.f = make_frame(ow, dw);
+      tv.mark = -1;
+    }
+  }
+  if (tv.sp == 0) return false;
+  tv.ref = st.pop(tv.sp);
+  return true;
+}
+
+// Closest hit of one ray, traversed to completion (the first-hit kernel).
+// A well-formed tree visits each node at most once per ray; kMaxVisits only
+// guards against a malformed upload.
+template <int kWidth, class S, int kStride>
+__device__ __forceinline__ Hit trace_closest(const SceneView& sc, const float4* lds_nodes, S& st,
+                                             const WorldRay<kStride>& wr, V3 o, V3 d) {
+  Trav tv;
+  uint32_t nn = 0, np = 0;
+  if (!trav_begin(sc, o, d, tv)) return tv.h;
+  for (uint32_t v = 0; v < kMaxVisits; ++v)
+    if (!trav_step<kWidth, false>(sc, lds_nodes, st, wr, tv, nn, np)) break;
+  return tv.h;
 }
 
 // geometric normal of a hit slot (unit for triangles; (p - c) / r for spheres)
@@ -370,49 +391,151 @@ __global__ void k_pass_init(uint32_t* cnt, uint32_t paths) {
 }
 
 // ---------------------------------------------------------------------------
-// trace: closest hit + shading of every ray entering depth `depth`.
-// Escaped rays go to the environment queue; survivors to the next queue.
+// extend: closest hit of every ray entering depth `depth`, written to
+// hits[i] = (t, slot, instance) for queue entry i.  Lanes advance their own
+// traversals one step at a time; once no more than kRefillAt lanes of a
+// wave still traverse, the idle ones take new rays from a per-wave pool of
+// 64 queue entries (one atomic per pool), so lanes whose rays finish early
+// do not wait for the slowest ray of their wave.
 // ---------------------------------------------------------------------------
 template <int kWidth, int kStack, bool kCount>
-__global__ __launch_bounds__(kTraceBlock) void k_trace(SceneView sc, PassView pv, uint32_t depth,
-                                                       RayQueue in, RayQueue out, EnvQueue env,
-                                                       float4* L, uint32_t* cnt, unsigned long long* visit_cnt) {
+__global__ __launch_bounds__(kTraceBlock) void k_extend(SceneView sc, uint32_t depth, RayQueue in, float4* hits,
+                                                        uint32_t* cnt, unsigned long long* visit_cnt) {
   extern __shared__ float4 lds_nodes[];
-#if NPT_STACK_IN_SCRATCH
-  uint32_t stack[kStack];
-  constexpr int kStride = 1;
-#else
-  __shared__ uint32_t stack_mem[kStack * kTraceBlock];
-  uint32_t* stack = stack_mem + threadIdx.x;
-  constexpr int kStride = kTraceBlock;
-#endif
+  using Stack = LaneStack<kStack, kTraceBlock>;
+  __shared__ uint32_t stack_mem[(Stack::kShort > 0 ? Stack::kShort : 1) * kTraceBlock];
+  __shared__ float world_mem[(kWidth == kTwoLevel ? 6 : 1) * kTraceBlock];
+  Stack st;
+  st.lds = stack_mem + threadIdx.x;
+  const WorldRay<kTraceBlock> wr{world_mem + threadIdx.x};
   // the grid is sized for the largest possible queue; workgroups beyond the
-  // actual ray count leave before any staging or atomic
+  // actual ray count leave before any staging or atomic (the others drain
+  // the whole queue)
   const uint32_t n = cnt[kCntRays + depth];
   if ((uint64_t)blockIdx.x * kTraceBlock >= n) return;
   stage_lds_nodes(sc, lds_nodes);
   const uint32_t lane = threadIdx.x & (kWave - 1);
-  constexpr uint32_t kWavesPerBlock = kTraceBlock / kWave;
+  uint32_t* work = &cnt[kCntWork + depth];
   uint32_t n_nodes = 0, n_prims = 0;
-  // first chunk static (one per wave of the grid), then work stealing
-  uint32_t chunk = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-  for (;; ) {
-    const uint32_t i = chunk * kWave + lane;
-    if (chunk * kWave >= n) break;
+  Trav tv;
+  uint32_t ray = 0, steps = 0;
+  bool busy = false;
+  uint32_t pool = 0, pool_end = 0;  // this wave's unclaimed queue entries
+  bool drained = false;             // the queue has no entries left
+  for (;;) {
+    // hand queued rays to the idle lanes, lowest lane first
+    uint64_t idle = __ballot(!busy);
+    while (idle != 0 && !drained) {
+      if (pool == pool_end) {
+        uint32_t b = 0;
+        if (lane == 0) b = atomicAdd(work, (uint32_t)kWave);
+        b = __shfl(b, 0);
+        if (b >= n) {
+          drained = true;
+          break;
+        }
+        pool = b;
+        pool_end = min(b + (uint32_t)kWave, n);
+      }
+      const uint32_t rank =
+          __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
+      const uint32_t take = min(pool_end - pool, (uint32_t)__popcll(idle));
+      if (!busy && rank < take) {
+        ray = pool + rank;
+        const float* qo = reinterpret_cast<const float*>(in.o + ray);
+        const float* qd = reinterpret_cast<const float*>(in.d + ray);
+        const V3 o{qo[0], qo[1], qo[2]}, d{qd[0], qd[1], qd[2]};
+        if constexpr (kWidth == kTwoLevel) wr.store(o, d);
+        busy = trav_begin(sc, o, d, tv);
+        steps = 0;
+        if (!busy) hits[ray] = make_float4(tv.h.t, __uint_as_float(kMiss), __uint_as_float(kMiss), 0.0f);
+      }
+      pool += take;
+      idle = __ballot(!busy);
+    }
+    if (__ballot(busy) == 0) break;
+    // advance until few lanes still traverse (none, once the queue is drained)
+    const uint32_t floor_busy = drained ? 0u : (uint32_t)kRefillAt;
+    for (;;) {
+      if (busy) {
+        bool more = trav_step<kWidth, kCount>(sc, lds_nodes, st, wr, tv, n_nodes, n_prims);
+        if (++steps >= kMaxVisits) more = false;
+        if (!more) {
+          hits[ray] = make_float4(tv.h.t, __uint_as_float(tv.h.slot), __uint_as_float(tv.h.inst), 0.0f);
+          busy = false;
+        }
+      }
+      if ((uint32_t)__popcll(__ballot(busy)) <= floor_busy) break;
+    }
+  }
+  if constexpr (kCount) {
+    atomicAdd(&visit_cnt[depth - 1], (unsigned long long)n_nodes);
+    atomicAdd(&visit_cnt[64 + depth - 1], (unsigned long long)n_prims);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// shade: emission, BSDF sampling and roulette for every ray of depth
+// `depth` from its hit record.  Escaped rays go to the environment queue;
+// survivors to the next queue.  Whole workgroups iterate together: queue
+// slots are reserved with one atomic per workgroup and queue.
+// ---------------------------------------------------------------------------
+constexpr int kShadeBlock = 1024;
+
+// Queue slots for two predicates at once: the wave counts meet in LDS and
+// thread 0 reserves both ranges.  Every thread of the workgroup calls it.
+__device__ __forceinline__ void block_append2(bool pa, uint32_t* ca, bool pb, uint32_t* cb, uint32_t& ia,
+                                              uint32_t& ib) {
+  constexpr int kWaves = kShadeBlock / kWave;
+  __shared__ uint32_t off_a[kWaves], off_b[kWaves];
+  const uint32_t wave = threadIdx.x / kWave;
+  const uint64_t ma = __ballot(pa), mb = __ballot(pb);
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    off_a[wave] = (uint32_t)__popcll(ma);
+    off_b[wave] = (uint32_t)__popcll(mb);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t sa = 0, sb = 0;
+    for (int w = 0; w < kWaves; ++w) {
+      const uint32_t a = off_a[w], b = off_b[w];
+      off_a[w] = sa;
+      off_b[w] = sb;
+      sa += a;
+      sb += b;
+    }
+    const uint32_t base_a = sa ? atomicAdd(ca, sa) : 0u, base_b = sb ? atomicAdd(cb, sb) : 0u;
+    for (int w = 0; w < kWaves; ++w) {
+      off_a[w] += base_a;
+      off_b[w] += base_b;
+    }
+  }
+  __syncthreads();
+  ia = off_a[wave] + __builtin_amdgcn_mbcnt_hi((uint32_t)(ma >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ma, 0u));
+  ib = off_b[wave] + __builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u));
+  __syncthreads();  // the offsets are rewritten by the next call
+}
+
+__global__ __launch_bounds__(kShadeBlock) void k_shade(SceneView sc, PassView pv, uint32_t depth, RayQueue in,
+                                               const float4* hits, RayQueue out, EnvQueue env, float4* L,
+                                               uint32_t* cnt) {
+  const uint32_t n = cnt[kCntRays + depth];
+  for (uint32_t i0 = blockIdx.x * blockDim.x; i0 < n; i0 += gridDim.x * blockDim.x) {
+    const uint32_t i = i0 + threadIdx.x;
     const bool valid = i < n;
     V3 o{0, 0, 0}, d{0, 0, 1}, beta{0, 0, 0};
     uint32_t pixel = 0, sample = 0;
+    Hit h{__builtin_inff(), kMiss, 0u};
     if (valid) {
-      const float4 qo = in.o[i], qd = in.d[i], qb = in.b[i];
+      const float4 qo = in.o[i], qd = in.d[i], qb = in.b[i], hr = hits[i];
       o = V3{qo.x, qo.y, qo.z};
       d = V3{qd.x, qd.y, qd.z};
       beta = V3{qb.x, qb.y, qb.z};
       pixel = __float_as_uint(qo.w);
       sample = __float_as_uint(qd.w);
+      h = Hit{hr.x, __float_as_uint(hr.y), __float_as_uint(hr.z)};
     }
     const uint32_t slot = (sample - pv.sample0) * pv.pixels + pixel;
-    Hit h{__builtin_inff(), kMiss, kMiss, 0u};
-    if (valid) h = trace_closest<kWidth, kStack, kStride, kCount>(sc, lds_nodes, stack, o, d, &n_nodes, &n_prims);
     const bool escaped = valid && h.slot == kMiss;
     bool alive = false;
     V3 no{0, 0, 0}, nd{0, 0, 1};
@@ -458,24 +581,17 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace(SceneView sc, PassView pv
         }
       }
     }
-    const uint32_t ei = wave_append(escaped, &cnt[kCntEnv + depth]);
+    uint32_t ei, oi;
+    block_append2(escaped, &cnt[kCntEnv + depth], alive, &cnt[kCntRays + depth + 1], ei, oi);
     if (escaped) {
       env.d[ei] = make_float4(d.x, d.y, d.z, __uint_as_float(slot));
       env.b[ei] = make_float4(beta.x, beta.y, beta.z, 0.0f);
     }
-    const uint32_t oi = wave_append(alive, &cnt[kCntRays + depth + 1]);
     if (alive) {
       out.o[oi] = make_float4(no.x, no.y, no.z, __uint_as_float(pixel));
       out.d[oi] = make_float4(nd.x, nd.y, nd.z, __uint_as_float(sample));
       out.b[oi] = make_float4(beta.x, beta.y, beta.z, 0.0f);
     }
-    uint32_t next = 0;
-    if (lane == 0) next = gridDim.x * kWavesPerBlock + atomicAdd(&cnt[kCntWork + depth], 1u);
-    chunk = __shfl(next, 0);
-  }
-  if constexpr (kCount) {
-    atomicAdd(&visit_cnt[depth - 1], (unsigned long long)n_nodes);
-    atomicAdd(&visit_cnt[64 + depth - 1], (unsigned long long)n_prims);
   }
 }
 
@@ -545,9 +661,13 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_primary(SceneView sc, Cam
                                                                uint32_t* prim, uint32_t* inst, float* tout,
                                                                float* normal) {
   extern __shared__ float4 lds_nodes[];
-  __shared__ uint32_t stack_mem[kStack * kTraceBlock];
+  using Stack = LaneStack<kStack, kTraceBlock>;
+  __shared__ uint32_t stack_mem[(Stack::kShort > 0 ? Stack::kShort : 1) * kTraceBlock];
   stage_lds_nodes(sc, lds_nodes);
-  uint32_t* stack = stack_mem + threadIdx.x;
+  __shared__ float world_mem[(kWidth == kTwoLevel ? 6 : 1) * kTraceBlock];
+  Stack st;
+  st.lds = stack_mem + threadIdx.x;
+  const WorldRay<kTraceBlock> wr{world_mem + threadIdx.x};
   const uint32_t nblocks = (pv.pixels + kTraceBlock - 1) / kTraceBlock;
   for (uint32_t b = blockIdx.x; b < nblocks; b += gridDim.x) {
     const uint32_t pixel = b * kTraceBlock + threadIdx.x;
@@ -556,13 +676,14 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_primary(SceneView sc, Cam
     const U4 r = philox(pixel, pv.sample0, 0, kRngCamera, pv.key0, pv.key1);
     const V3 d = camera_direction(cam, pv.width, pv.height, x, y, unit_float(r.x), unit_float(r.y));
     const V3 o{cam.eye[0], cam.eye[1], cam.eye[2]};
-    const Hit h = trace_closest<kWidth, kStack, kTraceBlock>(sc, lds_nodes, stack, o, d);
+    if constexpr (kWidth == kTwoLevel) wr.store(o, d);
+    const Hit h = trace_closest<kWidth>(sc, lds_nodes, st, wr, o, d);
     V3 n{0, 0, 0};
     if (h.slot != kMiss) {
       uint32_t mat;
       n = slot_normal(sc.slots, h.slot, V3{o.x + h.t * d.x, o.y + h.t * d.y, o.z + h.t * d.z}, mat);
     }
-    if (prim) prim[pixel] = h.slot == kMiss ? kMiss : h.prim;
+    if (prim) prim[pixel] = h.slot == kMiss ? kMiss : slot_prim(sc.slots, h.slot);
     if (inst) inst[pixel] = h.slot == kMiss ? kMiss : h.inst;
     if (tout) tout[pixel] = h.t;
     if (normal) {
@@ -616,39 +737,48 @@ hipError_t launch_generate(const CameraView& cam, const PassView& pv, const RayQ
   return hipGetLastError();
 }
 
-hipError_t launch_trace(int stack_depth, const SceneView& sc, const PassView& pv, uint32_t depth,
-                        uint64_t max_rays, const RayQueue& in, const RayQueue& out, const EnvQueue& env,
-                        float4* L, uint32_t* cnt, unsigned long long* visit_cnt, int num_cus, hipStream_t s) {
+hipError_t launch_extend(int stack_depth, const SceneView& sc, uint32_t depth, uint64_t max_rays,
+                         const RayQueue& in, float4* hits, uint32_t* cnt, unsigned long long* visit_cnt,
+                         int num_cus, hipStream_t s) {
   const size_t lds = (size_t)sc.lds_nodes * sc.node_float4s * sizeof(float4);
   const int grid = grid_for(max_rays, kTraceBlock, num_cus * 32);
-#define NPT_LAUNCH_TRACE(W, S, C)                                                                               \
-  hipLaunchKernelGGL((k_trace<W, S, C>), dim3(grid), dim3(kTraceBlock), lds, s, sc, pv, depth, in, out, env, L, \
-                     cnt, visit_cnt)
-#define NPT_LAUNCH_TRACE_S(W)                                                                   \
-  switch (stack_depth) {                                                                       \
-    case 16: if (c) NPT_LAUNCH_TRACE(W, 16, true); else NPT_LAUNCH_TRACE(W, 16, false); break; \
-    case 24: if (c) NPT_LAUNCH_TRACE(W, 24, true); else NPT_LAUNCH_TRACE(W, 24, false); break; \
-    case 32: if (c) NPT_LAUNCH_TRACE(W, 32, true); else NPT_LAUNCH_TRACE(W, 32, false); break; \
-    case 48: if (c) NPT_LAUNCH_TRACE(W, 48, true); else NPT_LAUNCH_TRACE(W, 48, false); break; \
-    case 64: if (c) NPT_LAUNCH_TRACE(W, 64, true); else NPT_LAUNCH_TRACE(W, 64, false); break; \
-    default: return hipErrorInvalidValue;                                                      \
+#define NPT_LAUNCH_EXTEND(W, S, C) \
+  hipLaunchKernelGGL((k_extend<W, S, C>), dim3(grid), dim3(kTraceBlock), lds, s, sc, depth, in, hits, cnt, visit_cnt)
+#define NPT_LAUNCH_EXTEND_S(W)                                                                     \
+  switch (stack_depth) {                                                                          \
+    case 16: if (c) NPT_LAUNCH_EXTEND(W, 16, true); else NPT_LAUNCH_EXTEND(W, 16, false); break;    \
+    case 24: if (c) NPT_LAUNCH_EXTEND(W, 24, true); else NPT_LAUNCH_EXTEND(W, 24, false); break;    \
+    case 32: if (c) NPT_LAUNCH_EXTEND(W, 32, true); else NPT_LAUNCH_EXTEND(W, 32, false); break;    \
+    case 48: if (c) NPT_LAUNCH_EXTEND(W, 48, true); else NPT_LAUNCH_EXTEND(W, 48, false); break;    \
+    case 64: if (c) NPT_LAUNCH_EXTEND(W, 64, true); else NPT_LAUNCH_EXTEND(W, 64, false); break;    \
+    case 96: if (c) NPT_LAUNCH_EXTEND(W, 96, true); else NPT_LAUNCH_EXTEND(W, 96, false); break;    \
+    case 128: if (c) NPT_LAUNCH_EXTEND(W, 128, true); else NPT_LAUNCH_EXTEND(W, 128, false); break; \
+    default: return hipErrorInvalidValue;                                                         \
   }
   const bool c = visit_cnt != nullptr;
   if (sc.two_level) {
-    NPT_LAUNCH_TRACE_S(kTwoLevel)
+    NPT_LAUNCH_EXTEND_S(kTwoLevel)
   } else if (sc.width == 4) {
-    NPT_LAUNCH_TRACE_S(4)
+    NPT_LAUNCH_EXTEND_S(4)
   } else {
-    NPT_LAUNCH_TRACE_S(2)
+    NPT_LAUNCH_EXTEND_S(2)
   }
-#undef NPT_LAUNCH_TRACE_S
-#undef NPT_LAUNCH_TRACE
+#undef NPT_LAUNCH_EXTEND_S
+#undef NPT_LAUNCH_EXTEND
+  return hipGetLastError();
+}
+
+hipError_t launch_shade(const SceneView& sc, const PassView& pv, uint32_t depth, uint64_t max_rays,
+                        const RayQueue& in, const float4* hits, const RayQueue& out, const EnvQueue& env,
+                        float4* L, uint32_t* cnt, int num_cus, hipStream_t s) {
+  hipLaunchKernelGGL(k_shade, dim3(grid_for(max_rays, kShadeBlock, num_cus * 4)), dim3(kShadeBlock), 0, s, sc, pv,
+                     depth, in, hits, out, env, L, cnt);
   return hipGetLastError();
 }
 
 // smallest supported traversal stack holding `entries`
 int trace_stack_size(uint32_t entries) {
-  const int sizes[] = {16, 24, 32, 48, 64};
+  const int sizes[] = {16, 24, 32, 48, 64, 96, 128};
   for (int v : sizes)
     if ((uint32_t)v >= entries) return v;
   return 0;
@@ -688,13 +818,19 @@ hipError_t launch_trace_primary(int stack_depth, const SceneView& sc, const Came
 #define NPT_LAUNCH_PRIMARY(W, S)                                                                                   \
   hipLaunchKernelGGL((k_trace_primary<W, S>), dim3(grid), dim3(kTraceBlock), lds, s, sc, cam, pv, prim, inst, t, \
                      normal)
+#define NPT_LAUNCH_PRIMARY_S(W)                  \
+  if (stack_depth <= 32) NPT_LAUNCH_PRIMARY(W, 32);      \
+  else if (stack_depth <= 64) NPT_LAUNCH_PRIMARY(W, 64); \
+  else NPT_LAUNCH_PRIMARY(W, 128);
+  if (stack_depth > 128) return hipErrorInvalidValue;
   if (sc.two_level) {
-    if (stack_depth <= 32) NPT_LAUNCH_PRIMARY(kTwoLevel, 32); else NPT_LAUNCH_PRIMARY(kTwoLevel, 64);
+    NPT_LAUNCH_PRIMARY_S(kTwoLevel)
   } else if (sc.width == 4) {
-    if (stack_depth <= 32) NPT_LAUNCH_PRIMARY(4, 32); else NPT_LAUNCH_PRIMARY(4, 64);
+    NPT_LAUNCH_PRIMARY_S(4)
   } else {
-    if (stack_depth <= 32) NPT_LAUNCH_PRIMARY(2, 32); else NPT_LAUNCH_PRIMARY(2, 64);
+    NPT_LAUNCH_PRIMARY_S(2)
   }
+#undef NPT_LAUNCH_PRIMARY_S
 #undef NPT_LAUNCH_PRIMARY
   return hipGetLastError();
 }

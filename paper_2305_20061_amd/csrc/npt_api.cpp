@@ -102,15 +102,16 @@ struct npt_ctx {
   TrainScratch train;
 
   // render scratch
-  DevBuf qa_o, qa_d, qa_b, qb_o, qb_d, qb_b, env_d, env_b, d_L, d_accum, d_cnt, d_stats;
+  DevBuf qa_o, qa_d, qa_b, qb_o, qb_d, qb_b, env_d, env_b, d_L, d_hits, d_accum, d_cnt, d_stats;
   npt_stats stats{};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  std::vector<hipEvent_t> event_pool, trace_events, env_events;
+  std::vector<hipEvent_t> event_pool, trace_events, shade_events, env_events;
   bool timing_pending = false;
 
   ~npt_ctx() {
     DevBuf* all[] = {&d_nodes, &d_slots, &d_mats, &d_inst, &d_env, &d_master, &d_adam_m, &d_adam_v, &d_frags, &d_bias,
-                     &qa_o, &qa_d, &qa_b, &qb_o, &qb_d, &qb_b, &env_d, &env_b, &d_L, &d_accum, &d_cnt, &d_stats};
+                     &qa_o, &qa_d, &qa_b, &qb_o, &qb_d, &qb_b, &env_d, &env_b, &d_L, &d_hits, &d_accum,
+                     &d_cnt, &d_stats};
     for (DevBuf* b : all) b->release();
     train.release();
     for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
@@ -426,7 +427,7 @@ extern "C" int npt_build_bvh(npt_ctx* c, const npt_bvh_params* p, void* stream) 
     if (!build_two_level(bottoms, objects, bins, b, records, stack_need, e)) return fail(c, NPT_E_INVALID_ARG, e);
   }
   if (trace_stack_size(stack_need) == 0)
-    return fail(c, NPT_E_UNSUPPORTED, "BVH deeper than the 64-entry traversal stack");
+    return fail(c, NPT_E_UNSUPPORTED, "BVH deeper than the 128-entry traversal stack");
   c->bvh = std::move(b);
   c->inst_records = std::move(records);
   c->two_level = two_level;
@@ -745,14 +746,15 @@ extern "C" int npt_render(npt_ctx* c, uint32_t W, uint32_t H, uint32_t spp, uint
 
   const uint64_t pixels = (uint64_t)W * H;
   // default pool: 2^26 paths in flight (a whole 1080p x 32 spp frame per
-  // pass; 144 B of queues per path = 9.7 GB of the 288 GB of HBM)
+  // pass; 160 B of queues per path = 10.7 GB of the 288 GB of HBM)
   const uint64_t pool = c->opt.pool_paths ? c->opt.pool_paths : (1ull << 26);
   uint64_t sp = c->opt.samples_per_pass ? c->opt.samples_per_pass : std::max<uint64_t>(1, pool / pixels);
   sp = std::min<uint64_t>(sp, spp);
   while (sp > 1 && pixels * sp >= (1ull << 31)) --sp;
   const uint64_t slots = pixels * sp;
   const size_t qb = slots * sizeof(float4);
-  DevBuf* qbufs[] = {&c->qa_o, &c->qa_d, &c->qa_b, &c->qb_o, &c->qb_d, &c->qb_b, &c->env_d, &c->env_b, &c->d_L};
+  DevBuf* qbufs[] = {&c->qa_o, &c->qa_d, &c->qa_b, &c->qb_o, &c->qb_d, &c->qb_b, &c->env_d, &c->env_b, &c->d_L,
+                     &c->d_hits};
   for (DevBuf* b : qbufs) HIP_TRY(c, b->ensure(qb));
   HIP_TRY(c, c->d_accum.ensure(pixels * sizeof(float4)));
   HIP_TRY(c, c->d_cnt.ensure(kCntWords * sizeof(uint32_t)));
@@ -762,10 +764,11 @@ extern "C" int npt_render(npt_ctx* c, uint32_t W, uint32_t H, uint32_t spp, uint
                                                       : nullptr;
   const bool timing = c->opt.kernel_timing != 0;
   c->trace_events.clear();
+  c->shade_events.clear();
   c->env_events.clear();
   auto event_pair = [&](std::vector<hipEvent_t>& v) -> hipError_t {
     // events are pooled per context and reused across renders
-    const size_t need = c->trace_events.size() + c->env_events.size() + 2;
+    const size_t need = c->trace_events.size() + c->shade_events.size() + c->env_events.size() + 2;
     while (c->event_pool.size() < need) {
       hipEvent_t e;
       hipError_t err = hipEventCreate(&e);
@@ -807,8 +810,14 @@ extern "C" int npt_render(npt_ctx* c, uint32_t W, uint32_t H, uint32_t spp, uint
         HIP_TRY(c, event_pair(c->trace_events));
         HIP_TRY(c, hipEventRecord(c->trace_events[c->trace_events.size() - 2], s));
       }
-      HIP_TRY(c, launch_trace(c->stack_depth, sv, pv, k, n, in, out, eq, L, cnt, visit_cnt, c->num_cus, s));
-      if (timing) HIP_TRY(c, hipEventRecord(c->trace_events.back(), s));
+      HIP_TRY(c, launch_extend(c->stack_depth, sv, k, n, in, c->d_hits.as<float4>(), cnt, visit_cnt, c->num_cus, s));
+      if (timing) {
+        HIP_TRY(c, hipEventRecord(c->trace_events.back(), s));
+        HIP_TRY(c, event_pair(c->shade_events));
+        HIP_TRY(c, hipEventRecord(c->shade_events[c->shade_events.size() - 2], s));
+      }
+      HIP_TRY(c, launch_shade(sv, pv, k, n, in, c->d_hits.as<float4>(), out, eq, L, cnt, c->num_cus, s));
+      if (timing) HIP_TRY(c, hipEventRecord(c->shade_events.back(), s));
       if (c->env_mode != NPT_ENV_NONE) {  // NONE: escaped paths carry no radiance
         if (timing) {
           HIP_TRY(c, event_pair(c->env_events));
@@ -887,6 +896,13 @@ extern "C" int npt_get_stats(npt_ctx* c, npt_stats* out) {
     }
     c->stats.ms_trace = sum;
     c->stats.trace_launches = (uint32_t)(c->trace_events.size() / 2);
+    sum = 0.0f;
+    for (size_t i = 0; i + 1 < c->shade_events.size(); i += 2) {
+      HIP_TRY(c, hipEventElapsedTime(&ms, c->shade_events[i], c->shade_events[i + 1]));
+      sum += ms;
+    }
+    c->stats.ms_shade = sum;
+    c->stats.shade_launches = (uint32_t)(c->shade_events.size() / 2);
     sum = 0.0f;
     for (size_t i = 0; i + 1 < c->env_events.size(); i += 2) {
       HIP_TRY(c, hipEventElapsedTime(&ms, c->env_events[i], c->env_events[i + 1]));

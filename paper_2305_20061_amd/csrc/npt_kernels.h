@@ -11,9 +11,12 @@ namespace npt {
 hipError_t launch_pass_init(uint32_t* cnt, uint32_t paths, hipStream_t s);
 hipError_t launch_generate(const CameraView& cam, const PassView& pv, const RayQueue& q, float4* L,
                            hipStream_t s);
-hipError_t launch_trace(int stack_depth, const SceneView& sc, const PassView& pv, uint32_t depth,
-                        uint64_t max_rays, const RayQueue& in, const RayQueue& out, const EnvQueue& env,
-                        float4* L, uint32_t* cnt, unsigned long long* visit_cnt, int num_cus, hipStream_t s);
+hipError_t launch_extend(int stack_depth, const SceneView& sc, uint32_t depth, uint64_t max_rays,
+                         const RayQueue& in, float4* hits, uint32_t* cnt, unsigned long long* visit_cnt,
+                         int num_cus, hipStream_t s);
+hipError_t launch_shade(const SceneView& sc, const PassView& pv, uint32_t depth, uint64_t max_rays,
+                        const RayQueue& in, const float4* hits, const RayQueue& out, const EnvQueue& env,
+                        float4* L, uint32_t* cnt, int num_cus, hipStream_t s);
 int trace_stack_size(uint32_t entries);
 hipError_t launch_env_lookup(const float4* map, int W, int H, const EnvQueue& env, float4* L,
                              const uint32_t* cnt, uint32_t depth, uint64_t max_rays, int num_cus,
