@@ -344,7 +344,7 @@ bool build_bvh(const BuildInput& in, uint32_t bins, uint32_t max_leaf, uint32_t 
     }
   }
   out.width = width;
-  out.node_float4s = width == 2 ? 4 : 7;
+  out.node_float4s = width == 2 ? 4 : kNode4Float4s;
   out.nodes.assign((size_t)next * out.node_float4s, make_float4(0, 0, 0, 0));
   for (int id : wide) {
     const std::vector<int>& ch = kids[id];
@@ -446,7 +446,7 @@ bool build_two_level(const std::vector<FlatBvh>& bottoms, const std::vector<Plac
   if (!build_bvh(tin, bins, 1, 0, 4, top, err)) return false;
 
   out.width = 4;
-  out.node_float4s = 7;
+  out.node_float4s = kNode4Float4s;
   out.nodes = top.nodes;
   out.leaves = top.leaves;
   for (int a = 0; a < 3; ++a) {
@@ -457,13 +457,13 @@ bool build_two_level(const std::vector<FlatBvh>& bottoms, const std::vector<Plac
   uint32_t deepest = 0;
   for (size_t t = 0; t < bottoms.size(); ++t) {
     const FlatBvh& b = bottoms[t];
-    const uint64_t node_off = out.nodes.size() / 7, slot_off = out.slots.size() / 3;
-    if (node_off + b.nodes.size() / 7 >= kEmptyChild || slot_off + b.slots.size() / 3 > kMaxSlots) {
+    const uint64_t node_off = out.nodes.size() / kNode4Float4s, slot_off = out.slots.size() / 3;
+    if (node_off + b.nodes.size() / kNode4Float4s >= kEmptyChild || slot_off + b.slots.size() / 3 > kMaxSlots) {
       err = "two-level layout: too many nodes or primitive slots";
       return false;
     }
     root[t] = (uint32_t)node_off;
-    for (size_t i = 0; i < b.nodes.size(); i += 7) {
+    for (size_t i = 0; i < b.nodes.size(); i += kNode4Float4s) {
       float4 rf = b.nodes[i + 6];
       float* r4[4] = {&rf.x, &rf.y, &rf.z, &rf.w};
       for (float* f : r4) {
@@ -479,6 +479,7 @@ bool build_two_level(const std::vector<FlatBvh>& bottoms, const std::vector<Plac
       }
       out.nodes.insert(out.nodes.end(), b.nodes.begin() + i, b.nodes.begin() + i + 6);
       out.nodes.push_back(rf);
+      out.nodes.insert(out.nodes.end(), b.nodes.begin() + i + 7, b.nodes.begin() + i + kNode4Float4s);
     }
     out.slots.insert(out.slots.end(), b.slots.begin(), b.slots.end());
     out.leaves += b.leaves;
@@ -494,7 +495,7 @@ bool build_two_level(const std::vector<FlatBvh>& bottoms, const std::vector<Plac
     records[2 * i + 1] = make_float4(bits(root[o.tree]), bits(o.id), 0.0f, 0.0f);
   }
   // top leaves hold one object each (leaf size 1)
-  for (size_t i = 0; i < top.nodes.size(); i += 7) {
+  for (size_t i = 0; i < top.nodes.size(); i += kNode4Float4s) {
     const float4 rf = top.nodes[i + 6];
     for (float f : {rf.x, rf.y, rf.z, rf.w}) {
       const uint32_t r = ubits(f);

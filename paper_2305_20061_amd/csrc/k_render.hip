@@ -77,6 +77,23 @@ struct LaneStack {
     }
     ++sp;
   }
+  // r3, r2, r1 in this order, each only if its flag is set; while three
+  // entries fit in LDS the stores are unconditional and only sp depends on
+  // the flags (a store above the final top is dead)
+  __device__ __forceinline__ void push3(int& sp, uint32_t r3, bool h3, uint32_t r2, bool h2, uint32_t r1, bool h1) {
+    if (sp + 3 <= kShort) {
+      lds[sp * kStride] = r3;
+      sp += h3 ? 1 : 0;
+      lds[sp * kStride] = r2;
+      sp += h2 ? 1 : 0;
+      lds[sp * kStride] = r1;
+      sp += h1 ? 1 : 0;
+    } else {
+      if (h3) push(sp, r3);
+      if (h2) push(sp, r2);
+      if (h1) push(sp, r1);
+    }
+  }
   __device__ __forceinline__ uint32_t pop(int& sp) {
     --sp;
     if (kDeep == 0 || sp < kShort) return lds[sp * kStride];
@@ -95,27 +112,32 @@ __device__ __forceinline__ float safe_inverse(float x) {
 // (plane - o) / d it errs by a part relative to the distance itself (from
 // the rounded reciprocal and the fma) and a part of up to one rounding of
 // o * ix, which does not shrink with the distance.  The second part is taken
-// out per ray: the origin term of the entry plane of each axis is moved up
-// by 4 ulp-units of |o * ix| and that of the exit plane down, so the
-// computed interval of every axis contains the exact one up to the relative
-// part, which kSlabSlack covers.  Boxes are then never missed by a ray that
-// enters them, whatever the distance between origin and box.
+// out per ray: the origin term of the entry (near) plane of each axis is
+// moved up by 4 ulp-units of |o * ix| and that of the exit (far) plane
+// down, so the computed interval of every axis contains the exact one up to
+// the relative part, which kSlabSlack covers.  Boxes are then never missed
+// by a ray that enters them, whatever the distance between origin and box.
+//
+// Which plane of an axis is the entry plane depends only on the sign of the
+// direction, so 4-wide nodes are read plane row by plane row: near_x is the
+// byte offset of the entry-plane row of x in a node (lo.x at 0 or hi.x at
+// 16; y at 32 / 48, z at 64 / 80), and no per-child min / max is needed.
 struct RayFrame {
   V3 o, d;
   Shear sh;
   float ix, iy, iz;
-  float ox_lo, oy_lo, oz_lo;  // origin terms for the low and high planes
-  float ox_hi, oy_hi, oz_hi;
+  float ox_n, oy_n, oz_n;  // origin terms of the entry planes
+  float ox_f, oy_f, oz_f;  // and of the exit planes
+  uint32_t near_x, near_y, near_z;
 };
 
 constexpr float kSlabSlack = 1.0f + 0x1p-20f;
 
-__device__ __forceinline__ void origin_terms(float o, float inv, float& lo, float& hi) {
+__device__ __forceinline__ void origin_terms(float o, float inv, float& near_t, float& far_t) {
   const float oi = o * inv;
   const float e = fabsf(oi) * 0x1p-22f;
-  const float near_t = oi + e, far_t = oi - e;  // entry plane: smaller distance
-  lo = inv >= 0.0f ? near_t : far_t;
-  hi = inv >= 0.0f ? far_t : near_t;
+  near_t = oi + e;
+  far_t = oi - e;
 }
 
 __device__ __forceinline__ RayFrame make_frame(V3 o, V3 d) {
@@ -126,18 +148,23 @@ __device__ __forceinline__ RayFrame make_frame(V3 o, V3 d) {
   f.ix = safe_inverse(d.x);
   f.iy = safe_inverse(d.y);
   f.iz = safe_inverse(d.z);
-  origin_terms(o.x, f.ix, f.ox_lo, f.ox_hi);
-  origin_terms(o.y, f.iy, f.oy_lo, f.oy_hi);
-  origin_terms(o.z, f.iz, f.oz_lo, f.oz_hi);
+  origin_terms(o.x, f.ix, f.ox_n, f.ox_f);
+  origin_terms(o.y, f.iy, f.oy_n, f.oy_f);
+  origin_terms(o.z, f.iz, f.oz_n, f.oz_f);
+  f.near_x = f.ix >= 0.0f ? 0u : 16u;
+  f.near_y = f.iy >= 0.0f ? 32u : 48u;
+  f.near_z = f.iz >= 0.0f ? 64u : 80u;
   return f;
 }
 
-// entry and exit distance of one box against [0, lim]
+// entry and exit distance of one box against [0, lim] (binary nodes, whose
+// lo / hi planes are interleaved per child)
 __device__ __forceinline__ void slab(const RayFrame& f, float lx, float hx, float ly, float hy, float lz, float hz,
                                      float lim, float& tn, float& tf) {
-  const float a0 = __builtin_fmaf(lx, f.ix, -f.ox_lo), a1 = __builtin_fmaf(hx, f.ix, -f.ox_hi);
-  const float b0 = __builtin_fmaf(ly, f.iy, -f.oy_lo), b1 = __builtin_fmaf(hy, f.iy, -f.oy_hi);
-  const float c0 = __builtin_fmaf(lz, f.iz, -f.oz_lo), c1 = __builtin_fmaf(hz, f.iz, -f.oz_hi);
+  const bool px = f.ix >= 0.0f, py = f.iy >= 0.0f, pz = f.iz >= 0.0f;
+  const float a0 = __builtin_fmaf(lx, f.ix, -(px ? f.ox_n : f.ox_f)), a1 = __builtin_fmaf(hx, f.ix, -(px ? f.ox_f : f.ox_n));
+  const float b0 = __builtin_fmaf(ly, f.iy, -(py ? f.oy_n : f.oy_f)), b1 = __builtin_fmaf(hy, f.iy, -(py ? f.oy_f : f.oy_n));
+  const float c0 = __builtin_fmaf(lz, f.iz, -(pz ? f.oz_n : f.oz_f)), c1 = __builtin_fmaf(hz, f.iz, -(pz ? f.oz_f : f.oz_n));
   tn = fmaxf(fmaxf(fminf(a0, a1), fminf(b0, b1)), fmaxf(fminf(c0, c1), 0.0f));
   tf = fminf(fminf(fmaxf(a0, a1), fmaxf(b0, b1)), fminf(fmaxf(c0, c1), lim)) * kSlabSlack;
 }
@@ -185,36 +212,47 @@ __device__ __forceinline__ void order2(float& ka, uint32_t& ra, float& kb, uint3
   ra = r;
 }
 
-// one child of a 4-wide node: entry distance, or +inf when missed or empty
-__device__ __forceinline__ float child_entry(const RayFrame& f, float lx, float hx, float ly, float hy, float lz,
-                                             float hz, float lim, uint32_t ref) {
-  float tn, tf;
-  slab(f, lx, hx, ly, hy, lz, hz, lim, tn, tf);
-  return (tn <= tf && ref != kEmptyChild) ? tn : __builtin_inff();
+// one child of a 4-wide node from its entry-plane (n) and exit-plane (f)
+// coordinates: entry distance, or +inf when missed.  An empty child (box
+// +inf / -inf) has an infinite entry distance on every axis and misses.
+__device__ __forceinline__ float child_entry(const RayFrame& f, float nx, float fx, float ny, float fy, float nz,
+                                             float fz, float lim) {
+  const float tn = fmaxf(fmaxf(__builtin_fmaf(nx, f.ix, -f.ox_n), __builtin_fmaf(ny, f.iy, -f.oy_n)),
+                         fmaxf(__builtin_fmaf(nz, f.iz, -f.oz_n), 0.0f));
+  const float tf = fminf(fminf(__builtin_fmaf(fx, f.ix, -f.ox_f), __builtin_fmaf(fy, f.iy, -f.oy_f)),
+                         fminf(__builtin_fmaf(fz, f.iz, -f.oz_f), lim)) * kSlabSlack;
+  return tn <= tf ? tn : __builtin_inff();
 }
 
-// One 4-wide node: the children the ray enters, nearest first in `ref`, the
-// others pushed far to near.  Returns false when no child is entered.
+// One 4-wide node at byte offset `off` from `base` (32-bit offsets: the
+// loads take the scalar-base + vector-offset form): the children the ray
+// enters, nearest first in `ref`, the others pushed far to near.  Returns
+// false when no child is entered.
 template <class S>
-__device__ __forceinline__ bool visit4(const float4* p, const RayFrame& f, float lim, S& st, int& sp,
+__device__ __forceinline__ bool visit4(const char* base, uint32_t off, const RayFrame& f, float lim, S& st, int& sp,
                                        uint32_t& ref) {
-  const float4 lx = p[0], hx = p[1], ly = p[2], hy = p[3], lz = p[4], hz = p[5], rf = p[6];
+  auto row = [&](uint32_t o) { return *reinterpret_cast<const float4*>(base + o); };
+  const float4 nx = row(off + f.near_x), fx = row(off + (16u - f.near_x));
+  const float4 ny = row(off + f.near_y), fy = row(off + (80u - f.near_y));
+  const float4 nz = row(off + f.near_z), fz = row(off + (144u - f.near_z));
+  const float4 rf = row(off + 96u);
   uint32_t r0 = __float_as_uint(rf.x), r1 = __float_as_uint(rf.y), r2 = __float_as_uint(rf.z),
            r3 = __float_as_uint(rf.w);
-  float k0 = child_entry(f, lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, lim, r0);
-  float k1 = child_entry(f, lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, lim, r1);
-  float k2 = child_entry(f, lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, lim, r2);
-  float k3 = child_entry(f, lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, lim, r3);
+  float k0 = child_entry(f, nx.x, fx.x, ny.x, fy.x, nz.x, fz.x, lim);
+  float k1 = child_entry(f, nx.y, fx.y, ny.y, fy.y, nz.y, fz.y, lim);
+  float k2 = child_entry(f, nx.z, fx.z, ny.z, fy.z, nz.z, fz.z, lim);
+  float k3 = child_entry(f, nx.w, fx.w, ny.w, fy.w, nz.w, fz.w, lim);
   order2(k0, r0, k1, r1);
   order2(k2, r2, k3, r3);
   order2(k0, r0, k2, r2);
   order2(k1, r1, k3, r3);
   order2(k1, r1, k2, r2);
+  // the child refs are fetched with the boxes, not after the test
+  __asm__ volatile("" : : "v"(r0), "v"(r1), "v"(r2), "v"(r3));
   const float inf = __builtin_inff();
   if (!(k0 < inf)) return false;
-  if (k3 < inf) st.push(sp, r3);
-  if (k2 < inf) st.push(sp, r2);
-  if (k1 < inf) st.push(sp, r1);
+  // the entered children are a prefix of the sorted four
+  st.push3(sp, r3, k3 < inf, r2, k2 < inf, r1, k1 < inf);
   ref = r0;
   return true;
 }
@@ -268,60 +306,11 @@ __device__ __forceinline__ bool trav_begin(const SceneView& sc, V3 o, V3 d, Trav
   return sc.has_geometry != 0;
 }
 
-// One step: an inner node (entered children pushed far to near, the
-// nearest taken), an instance entered, or a leaf's primitives tested, then
-// a pop when no child was taken.  Returns false once the stack is empty.
-// kCount: also count inner-node fetches and primitive tests.
-template <int kWidth, bool kCount, class S, int kStride>
-__device__ __forceinline__ bool trav_step(const SceneView& sc, const float4* lds_nodes, S& st,
-                                          const WorldRay<kStride>& wr, Trav& tv, uint32_t& n_nodes,
-                                          uint32_t& n_prims) {
-  if ((tv.ref & kLeafBit) == 0u) {
-    if constexpr (kCount) ++n_nodes;
-    const float lim = tv.h.t * 1.000001f;
-    if constexpr (kWidth == 2) {
-      float4 n0, n1, n2, n3;
-      if (tv.ref < sc.lds_nodes) {
-        const float4* p = lds_nodes + 4 * tv.ref;
-        n0 = p[0]; n1 = p[1]; n2 = p[2]; n3 = p[3];
-      } else {
-        const float4* p = sc.nodes + 4 * (size_t)tv.ref;
-        n0 = p[0]; n1 = p[1]; n2 = p[2]; n3 = p[3];
-      }
-      float lo0, hi0, lo1, hi1;
-      slab(tv.f, n0.x, n0.y, n0.z, n0.w, n2.x, n2.y, lim, lo0, hi0);
-      slab(tv.f, n1.x, n1.y, n1.z, n1.w, n2.z, n2.w, lim, lo1, hi1);
-      const bool h0 = lo0 <= hi0, h1 = lo1 <= hi1;
-      const uint32_t r0 = __float_as_uint(n3.x), r1 = __float_as_uint(n3.y);
-      if (h0 && h1) {
-        const bool near0 = lo0 <= lo1;
-        st.push(tv.sp, near0 ? r1 : r0);
-        tv.ref = near0 ? r0 : r1;
-        return true;
-      }
-      if (h0) { tv.ref = r0; return true; }
-      if (h1) { tv.ref = r1; return true; }
-    } else {
-      const float4* p = (kWidth == 4 && tv.ref < sc.lds_nodes) ? lds_nodes + 7 * tv.ref
-                                                               : sc.nodes + 7 * (size_t)tv.ref;
-      if (visit4(p, tv.f, lim, st, tv.sp, tv.ref)) return true;
-    }
-  } else if (kWidth == kTwoLevel && tv.mark < 0) {
-    // top-tree leaf: enter the instance's bottom tree in object space
-    const uint32_t k = (tv.ref >> 3) & 0x0FFFFFFFu;
-    const float4 r0 = sc.instances[2 * (size_t)k], r1 = sc.instances[2 * (size_t)k + 1];
-    V3 ow, dw;
-    wr.load(ow, dw);
-    const V3 o{(ow.x - r0.x) / r0.w, (ow.y - r0.y) / r0.w, (ow.z - r0.z) / r0.w};
-    const V3 d{dw.x / r0.w, dw.y / r0.w, dw.z / r0.w};
-    tv.f = make_frame(o, d);
-    tv.inst = __float_as_uint(r1.y);
-    tv.ref = __float_as_uint(r1.x);
-    tv.mark = tv.sp;
-    return true;
-  } else {
-    test_leaf<kCount>(sc, tv.f, tv.ref, kWidth == kTwoLevel ? tv.inst : 0u, tv.h, &n_prims);
-  }
+// After a node without an entered child or a tested leaf: back to the world
+// ray when a bottom tree is done, then the next deferred entry.  Returns
+// false once the stack is empty.
+template <int kWidth, class S, int kStride>
+__device__ __forceinline__ bool trav_pop(S& st, const WorldRay<kStride>& wr, Trav& tv) {
   if constexpr (kWidth == kTwoLevel) {
     if (tv.sp == tv.mark) {
       V3 ow, dw;
@@ -335,6 +324,74 @@ __device__ __forceinline__ bool trav_step(const SceneView& sc, const float4* lds
   return true;
 }
 
+// Inner node tv.ref: the children the ray enters are pushed far to near and
+// the nearest taken; with none, a pop.  Returns false once the traversal is
+// complete.  kCount: also count inner-node fetches.
+template <int kWidth, bool kCount, class S, int kStride>
+__device__ __forceinline__ bool trav_node(const SceneView& sc, const float4* lds_nodes, S& st,
+                                          const WorldRay<kStride>& wr, Trav& tv, uint32_t& n_nodes) {
+  if constexpr (kCount) ++n_nodes;
+  const float lim = tv.h.t * 1.000001f;
+  if constexpr (kWidth == 2) {
+    float4 n0, n1, n2, n3;
+    if (tv.ref < sc.lds_nodes) {
+      const float4* p = lds_nodes + 4 * tv.ref;
+      n0 = p[0]; n1 = p[1]; n2 = p[2]; n3 = p[3];
+    } else {
+      const float4* p = sc.nodes + 4 * (size_t)tv.ref;
+      n0 = p[0]; n1 = p[1]; n2 = p[2]; n3 = p[3];
+    }
+    float lo0, hi0, lo1, hi1;
+    slab(tv.f, n0.x, n0.y, n0.z, n0.w, n2.x, n2.y, lim, lo0, hi0);
+    slab(tv.f, n1.x, n1.y, n1.z, n1.w, n2.z, n2.w, lim, lo1, hi1);
+    const bool h0 = lo0 <= hi0, h1 = lo1 <= hi1;
+    const uint32_t r0 = __float_as_uint(n3.x), r1 = __float_as_uint(n3.y);
+    if (h0 && h1) {
+      const bool near0 = lo0 <= lo1;
+      st.push(tv.sp, near0 ? r1 : r0);
+      tv.ref = near0 ? r0 : r1;
+      return true;
+    }
+    if (h0 || h1) {
+      tv.ref = h0 ? r0 : r1;
+      return true;
+    }
+  } else {
+    bool entered;
+    const uint32_t off = tv.ref * (kNode4Float4s * 16u);  // node arrays stay below 4 GiB
+    if (kWidth == 4 && tv.ref < sc.lds_nodes)
+      entered = visit4(reinterpret_cast<const char*>(lds_nodes), off, tv.f, lim, st, tv.sp, tv.ref);
+    else
+      entered = visit4(reinterpret_cast<const char*>(sc.nodes), off, tv.f, lim, st, tv.sp, tv.ref);
+    if (entered) return true;
+  }
+  return trav_pop<kWidth>(st, wr, tv);
+}
+
+// Leaf tv.ref: its primitives tested, then a pop; in the top tree of a
+// two-level scene, the instance entered instead (the ray moves to object
+// space and the bottom tree's root becomes tv.ref).  Returns false once the
+// traversal is complete.  kCount: also count primitive tests.
+template <int kWidth, bool kCount, class S, int kStride>
+__device__ __forceinline__ bool trav_leaf(const SceneView& sc, S& st, const WorldRay<kStride>& wr, Trav& tv,
+                                          uint32_t& n_prims) {
+  if (kWidth == kTwoLevel && tv.mark < 0) {
+    const uint32_t k = (tv.ref >> 3) & 0x0FFFFFFFu;
+    const float4 r0 = sc.instances[2 * (size_t)k], r1 = sc.instances[2 * (size_t)k + 1];
+    V3 ow, dw;
+    wr.load(ow, dw);
+    const V3 o{(ow.x - r0.x) / r0.w, (ow.y - r0.y) / r0.w, (ow.z - r0.z) / r0.w};
+    const V3 d{dw.x / r0.w, dw.y / r0.w, dw.z / r0.w};
+    tv.f = make_frame(o, d);
+    tv.inst = __float_as_uint(r1.y);
+    tv.ref = __float_as_uint(r1.x);
+    tv.mark = tv.sp;
+    return true;
+  }
+  test_leaf<kCount>(sc, tv.f, tv.ref, kWidth == kTwoLevel ? tv.inst : 0u, tv.h, &n_prims);
+  return trav_pop<kWidth>(st, wr, tv);
+}
+
 // Closest hit of one ray, traversed to completion (the first-hit kernel).
 // A well-formed tree visits each node at most once per ray; kMaxVisits only
 // guards against a malformed upload.
@@ -344,8 +401,11 @@ __device__ __forceinline__ Hit trace_closest(const SceneView& sc, const float4* 
   Trav tv;
   uint32_t nn = 0, np = 0;
   if (!trav_begin(sc, o, d, tv)) return tv.h;
-  for (uint32_t v = 0; v < kMaxVisits; ++v)
-    if (!trav_step<kWidth, false>(sc, lds_nodes, st, wr, tv, nn, np)) break;
+  for (uint32_t v = 0; v < kMaxVisits; ++v) {
+    const bool more = (tv.ref & kLeafBit) == 0u ? trav_node<kWidth, false>(sc, lds_nodes, st, wr, tv, nn)
+                                                : trav_leaf<kWidth, false>(sc, st, wr, tv, np);
+    if (!more) break;
+  }
   return tv.h;
 }
 
@@ -369,18 +429,49 @@ __device__ __forceinline__ void stage_lds_nodes(const SceneView& sc, float4* lds
 // ---------------------------------------------------------------------------
 // generate: one camera ray per path slot of the pass
 // ---------------------------------------------------------------------------
+// Queue position -> pixel, in 8 x 8 tiles (bands of 8 rows, 8-column tiles
+// within a band; the last band and tile of a row may be narrower), so the 64
+// camera rays of a wave cover a compact block of the image.  A bijection on
+// [0, W*H); the path's identity (pixel, sample) is what the random numbers
+// and the accumulation use, so the order changes no result.
+__device__ __forceinline__ void tile_pixel(uint32_t p, uint32_t W, uint32_t H, uint32_t& x, uint32_t& y) {
+  const uint32_t full_bands = H / 8u, band_px = 8u * W;
+  uint32_t band, hb, q;
+  if (p < full_bands * band_px) {
+    band = p / band_px;
+    hb = 8u;
+    q = p - band * band_px;
+  } else {
+    band = full_bands;
+    hb = H - 8u * full_bands;
+    q = p - full_bands * band_px;
+  }
+  const uint32_t tile_px = 8u * hb, full_tiles = W / 8u;
+  if (q < full_tiles * tile_px) {
+    const uint32_t t = q / tile_px, r = q - t * tile_px;
+    x = 8u * t + (r & 7u);
+    y = 8u * band + (r >> 3);
+  } else {
+    const uint32_t wt = W - 8u * full_tiles, r = q - full_tiles * tile_px;
+    x = 8u * full_tiles + r % wt;
+    y = 8u * band + r / wt;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_generate(CameraView cam, PassView pv, RayQueue q, float4* L) {
   const uint32_t n = pv.pixels * pv.samples;
-  for (uint32_t slot = blockIdx.x * blockDim.x + threadIdx.x; slot < n; slot += gridDim.x * blockDim.x) {
-    const uint32_t pixel = slot % pv.pixels;
-    const uint32_t sample = pv.sample0 + slot / pv.pixels;
-    const uint32_t x = pixel % pv.width, y = pixel / pv.width;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const uint32_t s = i / pv.pixels;
+    uint32_t x, y;
+    tile_pixel(i - s * pv.pixels, pv.width, pv.height, x, y);
+    const uint32_t pixel = y * pv.width + x;
+    const uint32_t sample = pv.sample0 + s;
     const U4 r = philox(pixel, sample, 0, kRngCamera, pv.key0, pv.key1);
     const V3 d = camera_direction(cam, pv.width, pv.height, x, y, unit_float(r.x), unit_float(r.y));
-    q.o[slot] = make_float4(cam.eye[0], cam.eye[1], cam.eye[2], __uint_as_float(pixel));
-    q.d[slot] = make_float4(d.x, d.y, d.z, __uint_as_float(sample));
-    q.b[slot] = make_float4(1.0f, 1.0f, 1.0f, 0.0f);
-    L[slot] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    q.o[i] = make_float4(cam.eye[0], cam.eye[1], cam.eye[2], __uint_as_float(pixel));
+    q.d[i] = make_float4(d.x, d.y, d.z, __uint_as_float(sample));
+    q.b[i] = make_float4(1.0f, 1.0f, 1.0f, 0.0f);
+    L[s * pv.pixels + pixel] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   }
 }
 
@@ -454,11 +545,27 @@ __global__ __launch_bounds__(kTraceBlock) void k_extend(SceneView sc, uint32_t d
       idle = __ballot(!busy);
     }
     if (__ballot(busy) == 0) break;
-    // advance until few lanes still traverse (none, once the queue is drained)
+    // advance until few lanes still traverse (none, once the queue is
+    // drained).  Each round is a node phase (lanes at inner nodes visit
+    // them until every lane holds a leaf or is done; the others wait) and
+    // one leaf step, so that node and leaf code do not diverge within a
+    // wave step.
     const uint32_t floor_busy = drained ? 0u : (uint32_t)kRefillAt;
     for (;;) {
+      for (;;) {
+        const bool at_node = busy && (tv.ref & kLeafBit) == 0u;
+        if (__ballot(at_node) == 0) break;
+        if (at_node) {
+          bool more = trav_node<kWidth, kCount>(sc, lds_nodes, st, wr, tv, n_nodes);
+          if (++steps >= kMaxVisits) more = false;
+          if (!more) {
+            hits[ray] = make_float4(tv.h.t, __uint_as_float(tv.h.slot), __uint_as_float(tv.h.inst), 0.0f);
+            busy = false;
+          }
+        }
+      }
       if (busy) {
-        bool more = trav_step<kWidth, kCount>(sc, lds_nodes, st, wr, tv, n_nodes, n_prims);
+        bool more = trav_leaf<kWidth, kCount>(sc, st, wr, tv, n_prims);
         if (++steps >= kMaxVisits) more = false;
         if (!more) {
           hits[ray] = make_float4(tv.h.t, __uint_as_float(tv.h.slot), __uint_as_float(tv.h.inst), 0.0f);

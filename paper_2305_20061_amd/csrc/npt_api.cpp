@@ -428,6 +428,9 @@ extern "C" int npt_build_bvh(npt_ctx* c, const npt_bvh_params* p, void* stream) 
   }
   if (trace_stack_size(stack_need) == 0)
     return fail(c, NPT_E_UNSUPPORTED, "BVH deeper than the 128-entry traversal stack");
+  // the traversal addresses nodes with 32-bit byte offsets
+  if ((uint64_t)b.nodes.size() * sizeof(float4) >= (1ull << 32))
+    return fail(c, NPT_E_UNSUPPORTED, "BVH node array of 4 GiB or more (use a larger max_leaf)");
   c->bvh = std::move(b);
   c->inst_records = std::move(records);
   c->two_level = two_level;
