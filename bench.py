@@ -35,22 +35,21 @@ METRIC = "path samples/s at 1080p; NIF rays/s + MFMA util vs env-map lookup at e
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"fp16": 2500.0, "bf16": 2500.0, "fp8": 5000.0, "fp32": 157.3}
 NIF_FLOP_PER_QUERY = 2 * (64 * 96 + 4 * 96 * 96 + 96 * 3)  # 86,592
-# algorithmic bytes of the trace kernel: ray in 48 B, one node per BVH node
-# fetched (64 B two-wide, 112 B four-wide), 48 B per primitive slot tested,
-# 80 B per hit (slot re-read + material), 32 B per escaped ray (environment
-# queue), 48 B per survivor; instance records (32 B per instance entered) are
-# not counted
-B_RAY, B_PRIM, B_HIT, B_ESC, B_OUT = 48, 48, 80, 32, 48
+# algorithmic bytes of the extend kernel (closest hit): ray origin and
+# direction in (24 B), one node per BVH node fetched (64 B two-wide, 112 B
+# four-wide), 48 B per primitive slot tested, 16 B hit record out; instance
+# records (32 B per instance entered) are not counted
+B_RAY, B_PRIM, B_HITREC = 24, 48, 16
 B_NODE = {2: 64, 4: 112}
 WORKLOADS = {
     4: dict(name="large-BVH", spp=64, depth=8, prec="fp8",
             desc="large-BVH+NIF: 2048^2 terrain 8,380,418 tris + 256 instances x 81,920 tris (two-level BVH4), "
                  "{W}x{H}, {spp} spp, max depth {depth}, FP8 NIF (64-96x5-3) trained on device, seed {seed}",
-            traffic="k_trace_large_bvh_1080p_traffic.json"),
+            traffic="k_extend_large_bvh_1080p_traffic.json"),
     3: dict(name="small-BVH", spp=32, depth=6, prec="fp16",
             desc="small-BVH+NIF: displaced icosphere 81,922 tris, {W}x{H}, {spp} spp, max depth {depth}, "
                  "FP16 NIF (64-96x5-3) trained on device, seed {seed}",
-            traffic="k_trace_small_bvh_1080p_traffic.json"),
+            traffic="k_extend_small_bvh_1080p_traffic.json"),
 }
 
 
@@ -80,7 +79,7 @@ def _kernel_sha():
 
 
 def _traffic_per_launch(name):
-    """HBM bytes per trace launch from committed rocprofv3 counters, if they
+    """HBM bytes per extend launch from committed rocprofv3 counters, if they
     were taken on the current kernel source."""
     try:
         t = json.load(open(os.path.join(ROOT, "profiles", name)))
@@ -221,10 +220,8 @@ def main():
         esc = np.array(cs["escaped"], np.float64)
         visits = np.array(cs["node_visits"], np.float64)
         tests = np.array(cs["prim_tests"], np.float64)
-        survivors = np.concatenate([rays[1:], [0.0]])
-        hits = rays - esc
-        alg_bytes = float(np.sum(B_RAY * rays + B_NODE[extra["bvh"]["width"]] * visits + B_PRIM * tests
-                                 + B_HIT * hits + B_ESC * esc + B_OUT * survivors))
+        alg_bytes = float(np.sum((B_RAY + B_HITREC) * rays + B_NODE[extra["bvh"]["width"]] * visits
+                                 + B_PRIM * tests))
         extra["per_ray"] = {"node_visits": float(visits.sum() / rays.sum()),
                             "prim_tests": float(tests.sum() / rays.sum()),
                             "rays_per_path": float(rays.sum() / cs["paths"]),
@@ -248,9 +245,9 @@ def main():
                     "launches": s["env_launches"], "tflops": tf, "mfma_util": tf / MFMA_PEAK_TFLOPS[name],
                     "flop_per_query": NIF_FLOP_PER_QUERY}
 
-        extra["kernels"] = {"trace_ms_per_render": st["ms_trace"], "trace_launches": st["trace_launches"],
-                            "trace_ms_per_launch": trace_launch_ms, "nif_ms_per_render": st["ms_env"],
-                            "render_ms_device": st["ms_total"]}
+        extra["kernels"] = {"extend_ms_per_render": st["ms_trace"], "extend_launches": st["trace_launches"],
+                            "extend_ms_per_launch": trace_launch_ms, "shade_ms_per_render": st["ms_shade"],
+                            "nif_ms_per_render": st["ms_env"], "render_ms_device": st["ms_total"]}
         extra["nif"] = nif_stats(st, prec_name)
         extra["nif"]["fixed_batch_2^21_queries_per_s"] = _query_rate(npt, torch, ctx, npt.ENV_NIF)
 
@@ -292,8 +289,9 @@ def main():
             npt.npt_set_render_options(ctx, rr_start=3, kernel_timing=1)
             el, s3 = _timed_renders(npt, torch, ctx, W, H, c3["spp"], c3["depth"], seed, out, args.steps, 1)
             extra["small_bvh_fp16"] = {"path_samples_per_s": W * H * c3["spp"] * args.steps / el,
-                                       "ms_per_render": 1e3 * el / args.steps, "trace_ms_per_render": s3["ms_trace"],
-                                       "nif_ms_per_render": s3["ms_env"], "spp": c3["spp"], "max_depth": c3["depth"]}
+                                       "ms_per_render": 1e3 * el / args.steps, "extend_ms_per_render": s3["ms_trace"],
+                                       "shade_ms_per_render": s3["ms_shade"], "nif_ms_per_render": s3["ms_env"],
+                                       "spp": c3["spp"], "max_depth": c3["depth"]}
         finally:
             npt.npt_destroy(ctx)
 
@@ -305,8 +303,10 @@ def main():
                    "paths_per_step": W * H * spp},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "kernel": "k_trace (traversal + shading)",
-                     "alg_bytes_per_launch": alg_bytes / st["trace_launches"]},
+                     "traffic": traffic, "kernel": "k_extend (BVH traversal + primitive tests)",
+                     "alg_bytes_per_launch": alg_bytes / st["trace_launches"],
+                     "limiter": "VALU issue and texture addressing with an L2/MALL-resident tree "
+                                "(rocprofv3 counters); HBM carries a fraction of the algorithmic bytes"},
     }
     line.update(extra)
     if not args.no_cpu_baseline:

@@ -326,15 +326,16 @@ __device__ __forceinline__ bool trav_pop(S& st, const WorldRay<kStride>& wr, Tra
 
 // Inner node tv.ref: the children the ray enters are pushed far to near and
 // the nearest taken; with none, a pop.  Returns false once the traversal is
-// complete.  kCount: also count inner-node fetches.
-template <int kWidth, bool kCount, class S, int kStride>
+// complete.  kCount: also count inner-node fetches; kLds: the first
+// sc.lds_nodes nodes are read from the LDS copy (one-level trees only).
+template <int kWidth, bool kCount, bool kLds, class S, int kStride>
 __device__ __forceinline__ bool trav_node(const SceneView& sc, const float4* lds_nodes, S& st,
                                           const WorldRay<kStride>& wr, Trav& tv, uint32_t& n_nodes) {
   if constexpr (kCount) ++n_nodes;
   const float lim = tv.h.t * 1.000001f;
   if constexpr (kWidth == 2) {
     float4 n0, n1, n2, n3;
-    if (tv.ref < sc.lds_nodes) {
+    if (kLds && tv.ref < sc.lds_nodes) {
       const float4* p = lds_nodes + 4 * tv.ref;
       n0 = p[0]; n1 = p[1]; n2 = p[2]; n3 = p[3];
     } else {
@@ -359,7 +360,7 @@ __device__ __forceinline__ bool trav_node(const SceneView& sc, const float4* lds
   } else {
     bool entered;
     const uint32_t off = tv.ref * (kNode4Float4s * 16u);  // node arrays stay below 4 GiB
-    if (kWidth == 4 && tv.ref < sc.lds_nodes)
+    if (kLds && kWidth == 4 && tv.ref < sc.lds_nodes)
       entered = visit4(reinterpret_cast<const char*>(lds_nodes), off, tv.f, lim, st, tv.sp, tv.ref);
     else
       entered = visit4(reinterpret_cast<const char*>(sc.nodes), off, tv.f, lim, st, tv.sp, tv.ref);
@@ -402,7 +403,7 @@ __device__ __forceinline__ Hit trace_closest(const SceneView& sc, const float4* 
   uint32_t nn = 0, np = 0;
   if (!trav_begin(sc, o, d, tv)) return tv.h;
   for (uint32_t v = 0; v < kMaxVisits; ++v) {
-    const bool more = (tv.ref & kLeafBit) == 0u ? trav_node<kWidth, false>(sc, lds_nodes, st, wr, tv, nn)
+    const bool more = (tv.ref & kLeafBit) == 0u ? trav_node<kWidth, false, kWidth != kTwoLevel>(sc, lds_nodes, st, wr, tv, nn)
                                                 : trav_leaf<kWidth, false>(sc, st, wr, tv, np);
     if (!more) break;
   }
@@ -489,7 +490,7 @@ __global__ void k_pass_init(uint32_t* cnt, uint32_t paths) {
 // 64 queue entries (one atomic per pool), so lanes whose rays finish early
 // do not wait for the slowest ray of their wave.
 // ---------------------------------------------------------------------------
-template <int kWidth, int kStack, bool kCount>
+template <int kWidth, int kStack, bool kCount, bool kLds>
 __global__ __launch_bounds__(kTraceBlock) void k_extend(SceneView sc, uint32_t depth, RayQueue in, float4* hits,
                                                         uint32_t* cnt, unsigned long long* visit_cnt) {
   extern __shared__ float4 lds_nodes[];
@@ -504,7 +505,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_extend(SceneView sc, uint32_t d
   // the whole queue)
   const uint32_t n = cnt[kCntRays + depth];
   if ((uint64_t)blockIdx.x * kTraceBlock >= n) return;
-  stage_lds_nodes(sc, lds_nodes);
+  if constexpr (kLds) stage_lds_nodes(sc, lds_nodes);
   const uint32_t lane = threadIdx.x & (kWave - 1);
   uint32_t* work = &cnt[kCntWork + depth];
   uint32_t n_nodes = 0, n_prims = 0;
@@ -556,7 +557,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_extend(SceneView sc, uint32_t d
         const bool at_node = busy && (tv.ref & kLeafBit) == 0u;
         if (__ballot(at_node) == 0) break;
         if (at_node) {
-          bool more = trav_node<kWidth, kCount>(sc, lds_nodes, st, wr, tv, n_nodes);
+          bool more = trav_node<kWidth, kCount, kLds>(sc, lds_nodes, st, wr, tv, n_nodes);
           if (++steps >= kMaxVisits) more = false;
           if (!more) {
             hits[ray] = make_float4(tv.h.t, __uint_as_float(tv.h.slot), __uint_as_float(tv.h.inst), 0.0f);
@@ -849,26 +850,33 @@ hipError_t launch_extend(int stack_depth, const SceneView& sc, uint32_t depth, u
                          int num_cus, hipStream_t s) {
   const size_t lds = (size_t)sc.lds_nodes * sc.node_float4s * sizeof(float4);
   const int grid = grid_for(max_rays, kTraceBlock, num_cus * 32);
-#define NPT_LAUNCH_EXTEND(W, S, C) \
-  hipLaunchKernelGGL((k_extend<W, S, C>), dim3(grid), dim3(kTraceBlock), lds, s, sc, depth, in, hits, cnt, visit_cnt)
-#define NPT_LAUNCH_EXTEND_S(W)                                                                     \
-  switch (stack_depth) {                                                                          \
-    case 16: if (c) NPT_LAUNCH_EXTEND(W, 16, true); else NPT_LAUNCH_EXTEND(W, 16, false); break;    \
-    case 24: if (c) NPT_LAUNCH_EXTEND(W, 24, true); else NPT_LAUNCH_EXTEND(W, 24, false); break;    \
-    case 32: if (c) NPT_LAUNCH_EXTEND(W, 32, true); else NPT_LAUNCH_EXTEND(W, 32, false); break;    \
-    case 48: if (c) NPT_LAUNCH_EXTEND(W, 48, true); else NPT_LAUNCH_EXTEND(W, 48, false); break;    \
-    case 64: if (c) NPT_LAUNCH_EXTEND(W, 64, true); else NPT_LAUNCH_EXTEND(W, 64, false); break;    \
-    case 96: if (c) NPT_LAUNCH_EXTEND(W, 96, true); else NPT_LAUNCH_EXTEND(W, 96, false); break;    \
-    case 128: if (c) NPT_LAUNCH_EXTEND(W, 128, true); else NPT_LAUNCH_EXTEND(W, 128, false); break; \
-    default: return hipErrorInvalidValue;                                                         \
+#define NPT_LAUNCH_EXTEND(W, S, C, L)                                                                        \
+  hipLaunchKernelGGL((k_extend<W, S, C, L>), dim3(grid), dim3(kTraceBlock), L ? lds : 0, s, sc, depth, in, hits, cnt, \
+                     visit_cnt)
+#define NPT_LAUNCH_EXTEND_S(W, L)                                                                        \
+  switch (stack_depth) {                                                                                \
+    case 16: if (c) NPT_LAUNCH_EXTEND(W, 16, true, L); else NPT_LAUNCH_EXTEND(W, 16, false, L); break;    \
+    case 32: if (c) NPT_LAUNCH_EXTEND(W, 32, true, L); else NPT_LAUNCH_EXTEND(W, 32, false, L); break;    \
+    case 64: if (c) NPT_LAUNCH_EXTEND(W, 64, true, L); else NPT_LAUNCH_EXTEND(W, 64, false, L); break;    \
+    case 128: if (c) NPT_LAUNCH_EXTEND(W, 128, true, L); else NPT_LAUNCH_EXTEND(W, 128, false, L); break; \
+    default: return hipErrorInvalidValue;                                                               \
   }
   const bool c = visit_cnt != nullptr;
+  const bool staged = sc.lds_nodes > 0;
   if (sc.two_level) {
-    NPT_LAUNCH_EXTEND_S(kTwoLevel)
+    NPT_LAUNCH_EXTEND_S(kTwoLevel, false)
   } else if (sc.width == 4) {
-    NPT_LAUNCH_EXTEND_S(4)
+    if (staged) {
+      NPT_LAUNCH_EXTEND_S(4, true)
+    } else {
+      NPT_LAUNCH_EXTEND_S(4, false)
+    }
   } else {
-    NPT_LAUNCH_EXTEND_S(2)
+    if (staged) {
+      NPT_LAUNCH_EXTEND_S(2, true)
+    } else {
+      NPT_LAUNCH_EXTEND_S(2, false)
+    }
   }
 #undef NPT_LAUNCH_EXTEND_S
 #undef NPT_LAUNCH_EXTEND
@@ -885,7 +893,7 @@ hipError_t launch_shade(const SceneView& sc, const PassView& pv, uint32_t depth,
 
 // smallest supported traversal stack holding `entries`
 int trace_stack_size(uint32_t entries) {
-  const int sizes[] = {16, 24, 32, 48, 64, 96, 128};
+  const int sizes[] = {16, 32, 64, 128};
   for (int v : sizes)
     if ((uint32_t)v >= entries) return v;
   return 0;
