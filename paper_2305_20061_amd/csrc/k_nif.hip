@@ -8,6 +8,8 @@
 // first and last layer from L2.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "npt.h"
 #include "npt_device.h"
 #include "npt_kernels.h"
@@ -241,6 +243,13 @@ __device__ __forceinline__ void relu_to_frags(const f32x16 (&acc)[NT][kMB],
       const int mb = kb / G::kKBPerMB, r0 = (kb % G::kKBPerMB) * KPL;
       if constexpr (KPL == 1) {
         x[t][kb] = fmaxf(acc[t][mb][r0], 0.0f);
+      } else if constexpr (std::is_same_v<typename Prec<P>::Elem, _Float16>) {
+        // ReLU after the rounding, on packed halves (rounding is monotone
+        // and keeps 0, so the result is the same)
+        typename Prec<P>::Frag v;
+#pragma unroll
+        for (int e = 0; e < KPL; ++e) v[e] = (_Float16)acc[t][mb][r0 + e];
+        x[t][kb] = __builtin_elementwise_max(v, typename Prec<P>::Frag{});
       } else {
 #pragma unroll
         for (int e = 0; e < KPL; ++e) x[t][kb][e] = Prec<P>::cvt(fmaxf(acc[t][mb][r0 + e], 0.0f));
@@ -273,7 +282,7 @@ __device__ __forceinline__ void mma_layer_e4m3(const i32x8* fr, int lane, int sc
     }
 }
 
-__device__ __forceinline__ float relu448(float v) { return fminf(fmaxf(v, 0.0f), 448.0f); }
+__device__ __forceinline__ float relu448(float v) { return __builtin_amdgcn_fmed3f(v, 0.0f, 448.0f); }
 
 __device__ __forceinline__ int pack4_e4m3(const f32x16& a, int r) {
   return pack_e4m3<true>(relu448(a[r + 2]), relu448(a[r + 3]), pack_e4m3<false>(relu448(a[r]), relu448(a[r + 1]), 0));

@@ -177,33 +177,49 @@ __global__ __launch_bounds__(256) void k_train_head(const float* master, const t
 }
 
 // output-layer weight/bias gradients of one batch chunk
+// Batch reductions of the gradient run in two stages so that every CU takes
+// part and the summation order stays fixed: runs of kRun rows are summed by
+// separate workgroups into sub[run][j], then the runs of each kChunk-row
+// chunk, in order, into the chunk's partial sums.
+constexpr int kRun = 64;
+constexpr int kHeadGrads = kOut * kHidden + kOut;  // output-layer W and b, contiguous
+
+// output layer: dW = dy^T H5 and db = column sums of dy over one run
 template <int P>
-__global__ __launch_bounds__(320) void k_train_head_grad(const float* dy, const typename Prec<P>::Elem* H5,
-                                                        float* partial) {
+__global__ __launch_bounds__(320) void k_head_grad_runs(const float* dy, const typename Prec<P>::Elem* H5,
+                                                       float* sub) {
   const int j = threadIdx.x;
-  const uint32_t b0 = blockIdx.x * kChunk;
+  const uint32_t b0 = blockIdx.x * kRun;
+  float s = 0.0f;
   if (j < kOut * kHidden) {
     const int c = j / kHidden, i = j % kHidden;
-    float s = 0.0f;
-    for (uint32_t b = b0; b < b0 + kChunk; ++b) s += dy[3 * (size_t)b + c] * (float)H5[(size_t)b * kHidden + i];
-    partial[(size_t)blockIdx.x * kParams + w_offset(kLayers) + j] = s;
-  } else if (j < kOut * kHidden + kOut) {
+    for (uint32_t b = b0; b < b0 + kRun; ++b) s += dy[3 * (size_t)b + c] * (float)H5[(size_t)b * kHidden + i];
+  } else if (j < kHeadGrads) {
     const int c = j - kOut * kHidden;
-    float s = 0.0f;
-    for (uint32_t b = b0; b < b0 + kChunk; ++b) s += dy[3 * (size_t)b + c];
-    partial[(size_t)blockIdx.x * kParams + b_offset(kLayers) + c] = s;
+    for (uint32_t b = b0; b < b0 + kRun; ++b) s += dy[3 * (size_t)b + c];
   }
+  if (j < kHeadGrads) sub[(size_t)blockIdx.x * kHeadGrads + j] = s;
 }
 
-// bias gradient of a hidden layer: column sums of dP over one chunk
+// hidden-layer bias gradient: column sums of dP over one run
 template <int P>
-__global__ __launch_bounds__(128) void k_colsum(const typename Prec<P>::Elem* dP, float* partial, int boff) {
+__global__ __launch_bounds__(128) void k_colsum_runs(const typename Prec<P>::Elem* dP, float* sub) {
   const int i = threadIdx.x;
   if (i >= kHidden) return;
-  const uint32_t b0 = blockIdx.x * kChunk;
+  const uint32_t b0 = blockIdx.x * kRun;
   float s = 0.0f;
-  for (uint32_t b = b0; b < b0 + kChunk; ++b) s += (float)dP[(size_t)b * kHidden + i];
-  partial[(size_t)blockIdx.x * kParams + boff + i] = s;
+  for (uint32_t b = b0; b < b0 + kRun; ++b) s += (float)dP[(size_t)b * kHidden + i];
+  sub[(size_t)blockIdx.x * kHidden + i] = s;
+}
+
+// the runs of each chunk, in run order, into partial[chunk][off + j]
+__global__ __launch_bounds__(320) void k_chunk_sums(const float* sub, int width, float* partial, int off) {
+  const int j = threadIdx.x;
+  if (j >= width) return;
+  constexpr int kRuns = kChunk / kRun;
+  float s = 0.0f;
+  for (int r = 0; r < kRuns; ++r) s += sub[((size_t)blockIdx.x * kRuns + r) * width + j];
+  partial[(size_t)blockIdx.x * kParams + off + j] = s;
 }
 
 // gradient = (sum of chunk partials in chunk order) * scale; loss of the step
@@ -281,11 +297,11 @@ __global__ __launch_bounds__(256) void k_grid_err(const float* z, const float4* 
 // host side
 // ---------------------------------------------------------------------------
 void TrainScratch::release() {
-  void* all[] = {act, dp, wp, target, dy, partial, grad, loss_part, loss, zgrid, err_part};
+  void* all[] = {act, dp, wp, target, dy, partial, sub, grad, loss_part, loss, zgrid, err_part};
   for (void* p : all)
     if (p) (void)hipFree(p);
   act = dp = wp = nullptr;
-  target = dy = partial = grad = loss_part = loss = zgrid = err_part = nullptr;
+  target = dy = partial = sub = grad = loss_part = loss = zgrid = err_part = nullptr;
   batch_cap = elem_bytes = steps_cap = 0;
   grid_cap = 0;
 }
@@ -314,6 +330,7 @@ static hipError_t ensure_scratch(TrainScratch& s, uint32_t B, int prec, uint32_t
     if ((e = hipMalloc((void**)&s.target, (size_t)nb * 3 * 4)) != hipSuccess) return e;
     if ((e = hipMalloc((void**)&s.dy, (size_t)nb * 3 * 4)) != hipSuccess) return e;
     if ((e = hipMalloc((void**)&s.partial, (size_t)(nb / kChunk + 1) * kParams * 4)) != hipSuccess) return e;
+    if ((e = hipMalloc((void**)&s.sub, (size_t)(nb / kRun + 1) * kHeadGrads * 4)) != hipSuccess) return e;
     if ((e = hipMalloc((void**)&s.grad, (size_t)kParams * 4)) != hipSuccess) return e;
     if ((e = hipMalloc((void**)&s.loss_part, (size_t)(nb / 256 + 1) * 4)) != hipSuccess) return e;
     if ((e = hipMalloc((void**)&s.loss, (size_t)ns * 4)) != hipSuccess) return e;
@@ -372,7 +389,10 @@ static hipError_t step_gradient(TrainScratch& s, const TrainConfig& c, const Tra
                      c.loss_scale, B, s.dy, dp[0], s.loss_part);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int splits = (int)(B / kChunk);
-  hipLaunchKernelGGL(k_train_head_grad<P>, dim3(splits), dim3(320), 0, st, s.dy, acts[kLayers], s.partial);
+  const int runs = (int)(B / kRun);
+  hipLaunchKernelGGL(k_head_grad_runs<P>, dim3(runs), dim3(320), 0, st, s.dy, acts[kLayers], s.sub);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_chunk_sums, dim3(splits), dim3(320), 0, st, s.sub, kHeadGrads, s.partial, w_offset(kLayers));
   if ((e = hipGetLastError()) != hipSuccess) return e;
   int cur = 0;
   for (int l = kLayers - 1; l >= 0; --l) {
@@ -394,7 +414,9 @@ static hipError_t step_gradient(TrainScratch& s, const TrainConfig& c, const Tra
     g.ldc = layer_in(l);
     g.c_split_stride = kParams;
     if ((e = gemm<P, false, false>(g, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_colsum<P>, dim3(splits), dim3(128), 0, st, dp[cur], s.partial, b_offset(l));
+    hipLaunchKernelGGL(k_colsum_runs<P>, dim3(runs), dim3(128), 0, st, dp[cur], s.sub);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_chunk_sums, dim3(splits), dim3(128), 0, st, s.sub, kHidden, s.partial, b_offset(l));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (l == 0) break;
     // dP_{l-1} = (dP_l W_l) masked by act_l > 0

@@ -32,6 +32,7 @@ struct TrainScratch {
   float* target = nullptr;  // [B][3] log1p(bilinear) targets
   float* dy = nullptr;      // [B][3] output-layer gradients (scaled)
   float* partial = nullptr; // [splits][kParams] per-chunk gradient sums
+  float* sub = nullptr;     // [B / 64][291] per-run column sums (bias and output-layer gradients)
   float* grad = nullptr;    // [kParams]
   float* loss_part = nullptr;
   float* loss = nullptr;    // per-step losses
