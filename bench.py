@@ -41,6 +41,11 @@ NIF_FLOP_PER_QUERY = 2 * (64 * 96 + 4 * 96 * 96 + 96 * 3)  # 86,592
 # records (32 B per instance entered) are not counted
 B_RAY, B_PRIM, B_HITREC = 24, 48, 16
 B_NODE = {2: 64, 4: 112}
+# shade kernel per ray: ray and hit record in (64 B); per hit slot + material
+# (80 B); per escaped ray the environment queue entry (32 B); per survivor the
+# next queue entry (48 B).  Environment lookup per query: queue entry (32 B),
+# four texels (64 B), path radiance read-modify-write (32 B)
+B_SHADE_RAY, B_SHADE_HIT, B_SHADE_ESC, B_SHADE_OUT, B_LOOKUP = 64, 80, 32, 48, 128
 WORKLOADS = {
     4: dict(name="large-BVH", spp=64, depth=8, prec="fp8",
             desc="large-BVH+NIF: 2048^2 terrain 8,380,418 tris + 256 instances x 81,920 tris (two-level BVH4), "
@@ -115,7 +120,7 @@ def cpu_baseline(cfg, W, H, spp, depth, seed, prec, seconds):
     as one process per host core over disjoint rows."""
     cores = max(1, min(16, os.cpu_count() or 1))
     with mp.get_context("spawn").Pool(1) as pool:  # one row on one core
-        _, per_row = pool.map(_oracle_rows, [(cfg, [H // 2], W, H, spp, depth, seed, prec)])[0]
+        n1, per_row = pool.map(_oracle_rows, [(cfg, [H // 2], W, H, spp, depth, seed, prec)])[0]
     rows_total = min(H, max(cores, int(seconds * cores / max(per_row, 1e-3))))
     step = max(1, H // rows_total)
     rows = list(range(0, H, step))[:rows_total]
@@ -125,6 +130,7 @@ def cpu_baseline(cfg, W, H, spp, depth, seed, prec, seconds):
     paths = sum(r[0] for r in res)
     wall = max(r[1] for r in res)  # render time of the slowest worker (scene setup excluded)
     return {"value": paths / wall, "unit": "path samples/s", "cores": cores, "kind": "oracle",
+            "single_core_value": n1 / per_row,
             "sample": f"{len(rows)} of {H} rows (every {step}th), {W} px x {spp} spp each, depth {depth}, "
                       f"{['FP32', 'FP16', 'BF16', 'FP8'][prec]}-rounded NIF operands with FP64 sums; "
                       f"{paths} path samples, slowest worker {wall:.1f} s"}
@@ -160,6 +166,47 @@ def _query_rate(npt, torch, ctx, mode, n=1 << 21, reps=20):
 
 def _rel(a, b):
     return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b ** 2)))
+
+
+def _equal_rmse(npt, torch, ctx, W, H, spp, depth, seed, out, img, map_s, frame_s):
+    """Error of each NIF image against an env-map reference of 4x the samples
+    (another seed, so its noise is independent of the images'), turned into
+    the env-map sample count of equal error: with no light sampling the
+    env-map estimate is unbiased with squared relative error C/s, the
+    reference carries C/(4 spp) of its own, and a NIF image's remaining
+    error is its bias.  C is fitted to env-map renders at 1..spp samples.
+    The context is in env-map mode on entry."""
+    npt.npt_render(ctx, W, H, 4 * spp, depth, seed + 1000, out)
+    torch.cuda.synchronize()
+    ref = out.cpu().numpy().astype(np.float64)
+    curve = {}
+    s = 1
+    while s <= spp:
+        npt.npt_render(ctx, W, H, s, depth, seed, out)
+        torch.cuda.synchronize()
+        curve[s] = _rel(out.cpu().numpy().astype(np.float64), ref)
+        s *= 2
+    xs = np.array([1.0 / k + 1.0 / (4 * spp) for k in curve])
+    ys = np.array([v * v for v in curve.values()])
+    C = float(np.sum(xs * ys) / np.sum(xs * xs))
+    e_ref2 = C / (4 * spp)
+    res = {"reference": f"env-map render, {4 * spp} spp, seed {seed + 1000}",
+           "env_map_rel_rmse_vs_reference_by_spp": {str(k): v for k, v in curve.items()},
+           "env_map_variance_constant_C": C,
+           "model_fit_max_rel_dev": float(np.max(np.abs(np.sqrt(C * xs) / np.sqrt(ys) - 1.0))),
+           "env_map_rel_rmse_vs_truth_at_spp": float(np.sqrt(C / spp))}
+    for k, v in img.items():
+        if k == "map":
+            continue
+        e = _rel(v, ref)
+        bias = float(np.sqrt(max(e * e - e_ref2, 0.0)))
+        row = {"rel_rmse_vs_reference": e, "rel_bias_vs_truth": bias}
+        if bias > 0:
+            s_eq = C / (bias * bias)
+            row["env_map_spp_at_equal_rmse"] = s_eq
+            row["nif_cost_over_env_map_at_equal_rmse"] = frame_s[k] / (map_s * s_eq / spp)
+        res[k] = row
+    return res
 
 
 def main():
@@ -222,6 +269,9 @@ def main():
         tests = np.array(cs["prim_tests"], np.float64)
         alg_bytes = float(np.sum((B_RAY + B_HITREC) * rays + B_NODE[extra["bvh"]["width"]] * visits
                                  + B_PRIM * tests))
+        survivors = np.concatenate([rays[1:], [0.0]])
+        shade_bytes = float(np.sum(B_SHADE_RAY * rays + B_SHADE_HIT * (rays - esc) + B_SHADE_ESC * esc
+                                   + B_SHADE_OUT * survivors))
         extra["per_ray"] = {"node_visits": float(visits.sum() / rays.sum()),
                             "prim_tests": float(tests.sum() / rays.sum()),
                             "rays_per_path": float(rays.sum() / cs["paths"]),
@@ -249,13 +299,24 @@ def main():
                             "extend_ms_per_launch": trace_launch_ms, "shade_ms_per_render": st["ms_shade"],
                             "nif_ms_per_render": st["ms_env"], "render_ms_device": st["ms_total"]}
         extra["nif"] = nif_stats(st, prec_name)
+        # roofline fraction of every kernel of the step, and their time-weighted sum
+        fr = {"extend": (st["ms_trace"], alg_bytes / (st["ms_trace"] * 1e-3) / 1e9 / HBM_PEAK_GBS),
+              "shade": (st["ms_shade"], shade_bytes / (st["ms_shade"] * 1e-3) / 1e9 / HBM_PEAK_GBS),
+              "nif": (st["ms_env"], extra["nif"]["mfma_util"])}
+        tot = sum(v[0] for v in fr.values())
+        extra["kernel_roofline_fractions"] = {
+            **{k: {"ms_per_render": v[0], "frac": v[1], "peak": "MFMA " + prec_name if k == "nif" else "HBM"}
+               for k, v in fr.items()},
+            "time_weighted": sum(v[0] * v[1] for v in fr.values()) / tot}
         extra["nif"]["fixed_batch_2^21_queries_per_s"] = _query_rate(npt, torch, ctx, npt.ENV_NIF)
 
         if not args.no_envmap:
             modes = {}
+            frame_s = {prec_name: ms_step * 1e-3}
             if prec_name != "fp16":
                 npt.npt_nif_set_precision(ctx, npt.FP16)
                 el, s16 = _timed_renders(npt, torch, ctx, W, H, spp, depth, seed, out, args.steps, 1)
+                frame_s["fp16"] = el / args.steps
                 img["fp16"] = out.cpu().numpy().astype(np.float64)
                 modes["nif_fp16"] = {"path_samples_per_s": W * H * spp * args.steps / el,
                                      **nif_stats(s16, "fp16"),
@@ -266,12 +327,16 @@ def main():
             img["map"] = out.cpu().numpy().astype(np.float64)
             modes["env_map"] = {"path_samples_per_s": W * H * spp * args.steps / el,
                                 "lookup_queries_per_s": se["env_queries"] / (se["ms_env"] * 1e-3),
+                                "lookup_hbm_frac": se["env_queries"] * B_LOOKUP / (se["ms_env"] * 1e-3) / 1e9
+                                / HBM_PEAK_GBS,
                                 "lookup_ms_per_render": se["ms_env"],
                                 "fixed_batch_2^21_queries_per_s": _query_rate(npt, torch, ctx, npt.ENV_MAP)}
             # image error of each NIF precision against the map render at equal seeds
             modes["image_rel_rmse_vs_env_map"] = {k: _rel(v, img["map"]) for k, v in img.items() if k != "map"}
             if "fp16" in img and prec_name != "fp16":
                 modes["image_rel_rmse_fp8_vs_fp16"] = _rel(img[prec_name], img["fp16"])
+            modes["equal_rmse"] = _equal_rmse(npt, torch, ctx, W, H, spp, depth, seed, out, img, el / args.steps,
+                                              frame_s)
             extra["compare"] = modes
             npt.npt_set_env_mode(ctx, npt.ENV_NIF)
     finally:
