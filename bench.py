@@ -73,6 +73,9 @@ def _parse():
     p.add_argument("--calibrate-copy", action="store_true",
                    help="run one 1 GiB device copy (rocprof counter calibration)")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--spp-sweep", action="store_true",
+                   help="instead of the headline run: path rate against samples per pixel on the box scenes "
+                        "at 720x720 (one JSON line)")
     return p.parse_args()
 
 
@@ -168,45 +171,114 @@ def _rel(a, b):
     return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b ** 2)))
 
 
-def _equal_rmse(npt, torch, ctx, W, H, spp, depth, seed, out, img, map_s, frame_s):
-    """Error of each NIF image against an env-map reference of 4x the samples
-    (another seed, so its noise is independent of the images'), turned into
-    the env-map sample count of equal error: with no light sampling the
-    env-map estimate is unbiased with squared relative error C/s, the
-    reference carries C/(4 spp) of its own, and a NIF image's remaining
-    error is its bias.  C is fitted to env-map renders at 1..spp samples.
-    The context is in env-map mode on entry."""
-    npt.npt_render(ctx, W, H, 4 * spp, depth, seed + 1000, out)
-    torch.cuda.synchronize()
-    ref = out.cpu().numpy().astype(np.float64)
-    curve = {}
-    s = 1
-    while s <= spp:
-        npt.npt_render(ctx, W, H, s, depth, seed, out)
+# equal-RMSE study: image size divisor and samples of the env-map reference
+EQ_DIV, EQ_REF_SPP = 4, 16384
+
+
+def _equal_rmse(npt, torch, ctx, W, H, spp, depth, seed, precs, sample_s):
+    """NIF images against the env map at equal error.  Without light sampling
+    the env-map estimate is unbiased but carries the sun's fireflies; the NIF
+    (which has not learned the sun) is smooth but biased.  At W/EQ_DIV x
+    H/EQ_DIV (per-pixel error depends on the paths, not on the pixel count)
+    the study renders an env-map reference of EQ_REF_SPP samples with another
+    seed, the env-map image at 1..spp samples and each NIF image at spp.
+    Model: squared relative error of an env-map image at s samples is C/s
+    against the truth, r = C/EQ_REF_SPP for the reference; with independent
+    noise an image X gives e^2 = (a + r)/(1 + r), a = |X - truth|^2/|truth|^2.
+    C comes from the env-map curve, a from each NIF image, and the env-map
+    sample count of equal error is C/a.  sample_s: device seconds per path
+    sample of each mode at full size."""
+    w, h, R = W // EQ_DIV, H // EQ_DIV, EQ_REF_SPP
+    out = torch.empty(h, w, 3, dtype=torch.float32, device="cuda")
+
+    def render(s, sd):
+        npt.npt_render(ctx, w, h, s, depth, sd, out)
         torch.cuda.synchronize()
-        curve[s] = _rel(out.cpu().numpy().astype(np.float64), ref)
+        return out.cpu().numpy().astype(np.float64)
+
+    nif = {}
+    for name, code in precs.items():
+        npt.npt_nif_set_precision(ctx, code)
+        nif[name] = render(spp, seed)
+    npt.npt_set_env_mode(ctx, npt.ENV_MAP)
+    ref = render(R, seed + 1000)
+    curve, s = {}, 1
+    while s <= spp:
+        curve[s] = _rel(render(s, seed), ref)
         s *= 2
-    xs = np.array([1.0 / k + 1.0 / (4 * spp) for k in curve])
-    ys = np.array([v * v for v in curve.values()])
-    C = float(np.sum(xs * ys) / np.sum(xs * xs))
-    e_ref2 = C / (4 * spp)
-    res = {"reference": f"env-map render, {4 * spp} spp, seed {seed + 1000}",
+    # e^2 (1 + C/R) = C (1/s + 1/R)  =>  C = e^2 / (1/s + 1/R - e^2/R), one estimate per s
+    cs = np.array([e * e / (1.0 / k + 1.0 / R - e * e / R) for k, e in curve.items()])
+    C = float(np.exp(np.mean(np.log(cs))))
+    r = C / R
+    res = {"size": [w, h], "reference": f"env-map render, {R} spp, seed {seed + 1000}",
+           "reference_rel_rmse_vs_truth": float(np.sqrt(r)),
            "env_map_rel_rmse_vs_reference_by_spp": {str(k): v for k, v in curve.items()},
            "env_map_variance_constant_C": C,
-           "model_fit_max_rel_dev": float(np.max(np.abs(np.sqrt(C * xs) / np.sqrt(ys) - 1.0))),
-           "env_map_rel_rmse_vs_truth_at_spp": float(np.sqrt(C / spp))}
-    for k, v in img.items():
-        if k == "map":
-            continue
-        e = _rel(v, ref)
-        bias = float(np.sqrt(max(e * e - e_ref2, 0.0)))
-        row = {"rel_rmse_vs_reference": e, "rel_bias_vs_truth": bias}
-        if bias > 0:
-            s_eq = C / (bias * bias)
+           "C_estimates_max_rel_dev": float(np.max(np.abs(cs / C - 1.0))),
+           f"env_map_rel_rmse_vs_truth_at_{spp}_spp": float(np.sqrt(C / spp))}
+    for name, img in nif.items():
+        e = _rel(img, ref)
+        a = e * e * (1.0 + r) - r
+        row = {"rel_rmse_vs_reference": e, "rel_rmse_vs_truth": float(np.sqrt(max(a, 0.0)))}
+        if a > 0:
+            s_eq = C / a
             row["env_map_spp_at_equal_rmse"] = s_eq
-            row["nif_cost_over_env_map_at_equal_rmse"] = frame_s[k] / (map_s * s_eq / spp)
-        res[k] = row
+            row["nif_cost_over_env_map_at_equal_rmse"] = sample_s[name] * spp / (sample_s["map"] * s_eq)
+        else:
+            row["note"] = "NIF error below the reference's own noise: unresolved"
+        res[name] = row
     return res
+
+
+SWEEP_SPP = [1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024]
+
+
+def spp_sweep(args):
+    """Path rate against samples per pixel (the sample-count study of Sec. 4.5) on the
+    closed box (area light, no environment, depth 5) and the open box (FP16
+    NIF trained on the device, depth 6) at 720x720: where fixed costs per
+    render (launches, queue set-up, accumulation) stop mattering.  Device
+    time from HIP events around each render on the library's stream."""
+    import torch
+
+    from paper_2305_20061_amd import npt, synth
+
+    torch.cuda.set_device(0)
+    W = H = 720
+    res = {}
+    for name, cfg, depth in (("box", 0, 5), ("open_box_nif_fp16", 1, 6)):
+        ctx = npt.npt_create(0)
+        try:
+            npt.npt_load_scene(ctx, synth.scene_for(cfg))
+            if cfg == 0:
+                npt.npt_set_env_mode(ctx, npt.ENV_NONE)
+            else:
+                npt.npt_env_upload(ctx, synth.env_map())
+                npt.npt_nif_upload(ctx, synth.nif_init(3))
+                npt.npt_nif_train(ctx, npt.train_params(batch=65536, samples=args.train_samples, seed=1,
+                                                        grad_prec=npt.FP16))
+                npt.npt_nif_set_precision(ctx, npt.FP16)
+                npt.npt_set_env_mode(ctx, npt.ENV_NIF)
+            out = torch.empty(H, W, 3, dtype=torch.float32, device="cuda")
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            rows = {}
+            for spp in SWEEP_SPP:
+                reps = max(2, min(20, 4096 // spp))
+                npt.npt_render(ctx, W, H, spp, depth, 1, out)
+                torch.cuda.synchronize()
+                e0.record()
+                for _ in range(reps):
+                    npt.npt_render(ctx, W, H, spp, depth, 1, out)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / reps
+                st = npt.npt_get_stats(ctx)
+                rows[str(spp)] = {"ms_per_render": ms, "path_samples_per_s": W * H * spp / (ms * 1e-3),
+                                  "passes": st["passes"]}
+            res[name] = rows
+        finally:
+            npt.npt_destroy(ctx)
+    print(json.dumps({"spp_sweep": res, "size": [W, H], "unit": "path samples/s", "data": "synthetic"}))
 
 
 def main():
@@ -215,6 +287,8 @@ def main():
         print(json.dumps({"error": "one GPU only: this build measures a single MI355X; "
                                    "the multi-GPU sharding is described in DESIGN.md"}))
         sys.exit(2)
+    if args.spp_sweep:
+        return spp_sweep(args)
     import torch
 
     from paper_2305_20061_amd import npt, synth
@@ -335,8 +409,15 @@ def main():
             modes["image_rel_rmse_vs_env_map"] = {k: _rel(v, img["map"]) for k, v in img.items() if k != "map"}
             if "fp16" in img and prec_name != "fp16":
                 modes["image_rel_rmse_fp8_vs_fp16"] = _rel(img[prec_name], img["fp16"])
-            modes["equal_rmse"] = _equal_rmse(npt, torch, ctx, W, H, spp, depth, seed, out, img, el / args.steps,
-                                              frame_s)
+            paths = W * H * spp
+            sample_s = {k: v / paths for k, v in frame_s.items()}
+            sample_s["map"] = el / args.steps / paths
+            precs = {prec_name: prec}
+            if prec_name != "fp16":
+                precs["fp16"] = npt.FP16
+            npt.npt_set_env_mode(ctx, npt.ENV_NIF)
+            modes["equal_rmse"] = _equal_rmse(npt, torch, ctx, W, H, spp, depth, seed, precs, sample_s)
+            npt.npt_nif_set_precision(ctx, prec)
             extra["compare"] = modes
             npt.npt_set_env_mode(ctx, npt.ENV_NIF)
     finally:
