@@ -73,6 +73,10 @@ def _parse():
     p.add_argument("--calibrate-copy", action="store_true",
                    help="run one 1 GiB device copy (rocprof counter calibration)")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--node-format", choices=("fp32", "fp16-extent"), default="fp16-extent",
+                   help="BVH4 node encoding: FP32 boxes (112 B) or FP32 lower planes + binary16 extents (96 B)")
+    p.add_argument("--nif-study", action="store_true",
+                   help="instead of the headline run: the NIF output colour-space comparison (one JSON line)")
     p.add_argument("--spp-sweep", action="store_true",
                    help="instead of the headline run: path rate against samples per pixel on the box scenes "
                         "at 720x720 (one JSON line)")
@@ -281,6 +285,104 @@ def spp_sweep(args):
     print(json.dumps({"spp_sweep": res, "size": [W, H], "unit": "path samples/s", "data": "synthetic"}))
 
 
+def _psnr_log(nif_rgb, ref_rgb):
+    """PSNRs in the log1p domain: RGB over all channels, luminance (BT.601 Y)
+    and chrominance (BT.601 U, V) of the log1p values; the peak is the
+    reference's largest log1p value."""
+    a, b = np.log1p(np.maximum(nif_rgb, 0.0)), np.log1p(ref_rgb)
+    peak = float(b.max())
+
+    def yuv(x):
+        y = 0.299 * x[:, 0] + 0.587 * x[:, 1] + 0.114 * x[:, 2]
+        return y, np.stack([0.492 * (x[:, 2] - y), 0.877 * (x[:, 0] - y)], 1)
+
+    def psnr(x, z):
+        return float(10 * np.log10(peak * peak / np.mean((x - z) ** 2)))
+
+    ya, ca = yuv(a)
+    yb, cb = yuv(b)
+    return {"psnr_rgb": psnr(a, b), "psnr_luminance": psnr(ya, yb), "psnr_chrominance": psnr(ca, cb)}
+
+
+def nif_study(args):
+    """The output colour-space comparison of Sec. 4.3 on the synthetic sun-lit
+    sky: the network is trained on the device (Huber, Adam, 2^24 samples)
+    with its three outputs in YUV, RGB or YCoCg, at the workload's batch and
+    at a small one.  Reported: log-domain PSNRs of the NIF (FP32 inference)
+    against the map at every texel centre, its radiance at the sun's centre,
+    and the relative RMSE of an open-box render lit by it (FP16 inference)
+    against the env-map render at equal seeds.  Then the master-weight
+    precision of Sec. 3.2.1: FP32 master weights against binary16 master
+    weights with stochastically rounded updates and loss scale 16384."""
+    import torch
+
+    from paper_2305_20061_amd import npt, synth
+
+    torch.cuda.set_device(0)
+    env = synth.env_map()
+    h, w = env.shape[:2]
+    ph = 2 * np.pi * (np.arange(w) + 0.5) / w - np.pi
+    th = np.pi * (np.arange(h) + 0.5) / h
+    dirs = np.stack([np.sin(th)[:, None] * np.cos(ph)[None, :], np.cos(th)[:, None] * np.ones(w)[None, :],
+                     np.sin(th)[:, None] * np.sin(ph)[None, :]], -1).reshape(-1, 3).astype(np.float32)
+    ref = env.reshape(-1, 3).astype(np.float64)
+    d_dirs = torch.from_numpy(dirs).cuda()
+    q = torch.empty(dirs.shape[0], 3, dtype=torch.float32, device="cuda")
+    sun = torch.tensor(np.asarray(synth.sun_direction(), np.float32)[None, :]).cuda()
+    qs = torch.empty(1, 3, dtype=torch.float32, device="cuda")
+    RW, RS, RD = 512, 16, 6
+    img = torch.empty(RW, RW, 3, dtype=torch.float32, device="cuda")
+    ctx = npt.npt_create(0)
+    res = {}
+    try:
+        npt.npt_load_scene(ctx, synth.scene_for(1))
+        npt.npt_env_upload(ctx, env)
+        npt.npt_set_env_mode(ctx, npt.ENV_MAP)
+        npt.npt_render(ctx, RW, RW, RS, RD, 1, img)
+        torch.cuda.synchronize()
+        img_map = img.cpu().numpy().astype(np.float64)
+        for batch in (65536, 4096):
+            rows = {}
+            for name, colour in (("yuv", npt.COLOUR_YUV), ("rgb", npt.COLOUR_RGB), ("ycocg", npt.COLOUR_YCOCG)):
+                npt.npt_nif_upload(ctx, synth.nif_init(3), colour=colour)
+                tr = npt.npt_nif_train(ctx, npt.train_params(batch=batch, samples=args.train_samples, seed=1,
+                                                             grad_prec=npt.FP16))
+                npt.npt_nif_set_precision(ctx, npt.FP32)
+                npt.npt_env_query(ctx, npt.ENV_NIF, d_dirs, q)
+                npt.npt_env_query(ctx, npt.ENV_NIF, sun, qs)
+                torch.cuda.synchronize()
+                row = {"train_ms": tr["ms"], "steps": tr["steps"], "last_loss": tr["last_loss"],
+                       **_psnr_log(q.cpu().numpy().astype(np.float64), ref),
+                       "sun_centre_rgb": [float(x) for x in qs.cpu().numpy()[0]],
+                       "sun_true_rgb": [float(x) for x in ref.max(0)]}
+                npt.npt_nif_set_precision(ctx, npt.FP16)
+                npt.npt_set_env_mode(ctx, npt.ENV_NIF)
+                npt.npt_render(ctx, RW, RW, RS, RD, 1, img)
+                torch.cuda.synchronize()
+                row["image_rel_rmse_vs_env_map"] = _rel(img.cpu().numpy().astype(np.float64), img_map)
+                npt.npt_set_env_mode(ctx, npt.ENV_MAP)
+                rows[name] = row
+            res[f"batch_{batch}"] = rows
+        # master-weight precision (YUV, FP16 GEMMs): FP32 master against the
+        # paper's binary16 master with stochastic rounding and loss scale 16384
+        npt.npt_set_env_mode(ctx, npt.ENV_MAP)
+        for name, mp, ls in (("fp32_master", npt.FP32, 1024.0), ("fp16_master_sr_ls16384", npt.FP16, 16384.0)):
+            npt.npt_nif_upload(ctx, synth.nif_init(3))
+            tr = npt.npt_nif_train(ctx, npt.train_params(batch=65536, samples=args.train_samples, seed=1,
+                                                         grad_prec=npt.FP16, loss_scale=ls, master_prec=mp))
+            npt.npt_nif_set_precision(ctx, npt.FP32)
+            npt.npt_env_query(ctx, npt.ENV_NIF, d_dirs, q)
+            torch.cuda.synchronize()
+            res.setdefault("master_weights", {})[name] = {
+                "train_ms": tr["ms"], "last_loss": tr["last_loss"], "grid": npt.npt_nif_eval_grid(ctx, 1024, 512),
+                **_psnr_log(q.cpu().numpy().astype(np.float64), ref)}
+    finally:
+        npt.npt_destroy(ctx)
+    print(json.dumps({"nif_study": {"colour_space": res, "train_samples": args.train_samples,
+                                    "render": f"open box {RW}x{RW}, {RS} spp, depth {RD}, seed 1",
+                                    "grid": f"{w}x{h} texel centres"}, "data": "synthetic"}))
+
+
 def main():
     args = _parse()
     if args.gpus != 1:
@@ -289,6 +391,8 @@ def main():
         sys.exit(2)
     if args.spp_sweep:
         return spp_sweep(args)
+    if args.nif_study:
+        return nif_study(args)
     import torch
 
     from paper_2305_20061_amd import npt, synth
@@ -307,9 +411,12 @@ def main():
     try:
         t0 = time.perf_counter()
         # 4-wide BVH, leaf size 2, no LDS-staged levels: fastest in the sweep
-        npt.npt_load_scene(ctx, scene, max_leaf=2, lds_levels=0, width=4)
+        half = args.node_format == "fp16-extent"
+        npt.npt_load_scene(ctx, scene, max_leaf=2, lds_levels=0, width=4,
+                           node_format=npt.NODES_FP16_EXTENT if half else npt.NODES_FP32)
         extra["bvh_build_ms"] = 1e3 * (time.perf_counter() - t0)
-        extra["bvh"] = npt.npt_bvh_info(ctx)
+        extra["bvh"] = {**npt.npt_bvh_info(ctx), "node_format": args.node_format,
+                        "node_bytes": 96 if half else B_NODE[4]}
         del scene
         npt.npt_env_upload(ctx, env)
         npt.npt_nif_upload(ctx, synth.nif_init(3))
@@ -341,7 +448,7 @@ def main():
         esc = np.array(cs["escaped"], np.float64)
         visits = np.array(cs["node_visits"], np.float64)
         tests = np.array(cs["prim_tests"], np.float64)
-        alg_bytes = float(np.sum((B_RAY + B_HITREC) * rays + B_NODE[extra["bvh"]["width"]] * visits
+        alg_bytes = float(np.sum((B_RAY + B_HITREC) * rays + extra["bvh"]["node_bytes"] * visits
                                  + B_PRIM * tests))
         survivors = np.concatenate([rays[1:], [0.0]])
         shade_bytes = float(np.sum(B_SHADE_RAY * rays + B_SHADE_HIT * (rays - esc) + B_SHADE_ESC * esc
@@ -428,7 +535,8 @@ def main():
         c3 = WORKLOADS[3]
         ctx = npt.npt_create(0)
         try:
-            npt.npt_load_scene(ctx, synth.scene_for(3), max_leaf=2, lds_levels=0, width=4)
+            npt.npt_load_scene(ctx, synth.scene_for(3), max_leaf=2, lds_levels=0, width=4,
+                               node_format=npt.NODES_FP16_EXTENT if half else npt.NODES_FP32)
             npt.npt_nif_upload(ctx, trained)
             npt.npt_nif_set_precision(ctx, npt.FP16)
             npt.npt_set_env_mode(ctx, npt.ENV_NIF)

@@ -77,27 +77,47 @@ typedef struct {
  * axis (4..256, 0 = 32); max_leaf: primitives per leaf (1..8, 0 = 4);
  * lds_levels: top tree levels staged in LDS by the traversal kernel (0..8,
  * 0 = none); width: children per node, 2 (the paper's BVH2) or 4 (the
- * binary SAH tree collapsed to 4-wide nodes), 0 = 4. */
+ * binary SAH tree collapsed to 4-wide nodes), 0 = 4.  node_format
+ * (width 4, lds_levels 0): NPT_NODES_FP32 (112-byte nodes, FP32 boxes) or
+ * NPT_NODES_FP16_EXTENT (96-byte nodes: FP32 lower planes and binary16
+ * extents rounded up so that the FP32 sum lo + ext covers the box, after
+ * Sec. 3.1.4; NPT_E_UNSUPPORTED if an extent exceeds 65504). */
+#define NPT_NODES_FP32 0
+#define NPT_NODES_FP16_EXTENT 1
 typedef struct {
     uint32_t bins;
     uint32_t max_leaf;
     uint32_t lds_levels;
     uint32_t width;
+    uint32_t node_format;
 } npt_bvh_params;
 
 /* HDR-NIF shape (Sec. 3.2): 4*n_freq Fourier features -> layers x
- * [dense hidden + ReLU] -> dense 3 (YUV) -> fixed YUV->RGB matrix.
- * Supported: n_freq = 16, hidden = 96, layers = 5. */
+ * [dense hidden + ReLU] -> dense 3 -> fixed colour matrix to log-space RGB.
+ * Supported: n_freq = 16, hidden = 96, layers = 5.  colour: the space the
+ * network's three outputs live in (Sec. 4.3 compares them):
+ * NPT_COLOUR_YUV (default; BT.601 analogue, R = Y + 1.13983 V,
+ * G = Y - 0.39465 U - 0.58060 V, B = Y + 2.03211 U), NPT_COLOUR_RGB
+ * (identity), NPT_COLOUR_YCOCG (R = Y + Co - Cg, G = Y + Cg, B = Y - Co - Cg).
+ * The matrix applies to training, inference and grid evaluation alike. */
+#define NPT_COLOUR_YUV 0
+#define NPT_COLOUR_RGB 1
+#define NPT_COLOUR_YCOCG 2
 typedef struct {
     uint32_t n_freq;
     uint32_t hidden;
     uint32_t layers;
+    uint32_t colour;
 } npt_nif_desc;
 
 /* NIF training (Sec. 3.2.1): uniform (u,v) samples of the uploaded map,
- * targets log1p(bilinear), Huber loss, Adam with FP32 master weights.
+ * targets log1p(bilinear), Huber loss, Adam (FP32 moments).
  * grad_prec: NPT_FP32 / NPT_FP16 / NPT_BF16 operands of the GEMMs (FP32
- * accumulation).  Zero fields take the defaults in brackets:
+ * accumulation).  master_prec: NPT_FP32 master weights (default), or
+ * NPT_FP16 as on the paper's IPU: the master is rounded to the nearest
+ * binary16 first, and every Adam update, taken in FP32, is rounded to
+ * binary16 stochastically with u from the Philox stream (parameter index,
+ * Adam step, 0, 4) under the seed.  Zero fields take the defaults in brackets:
  * batch [65536; a multiple of 2048], samples [2^24], lr [1e-3], beta1 [0.9], beta2 [0.999],
  * eps [1e-7], huber_delta [1e-3], loss_scale [1024]. */
 typedef struct {
@@ -107,6 +127,7 @@ typedef struct {
     uint64_t seed;
     uint32_t grad_prec;
     float loss_scale;
+    uint32_t master_prec;
 } npt_train_params;
 
 typedef struct {
@@ -214,7 +235,8 @@ int npt_set_env_mode(npt_ctx *ctx, int mode);
 /* ---- HDR-NIF (Sec. 3.2) ----------------------------------------------------- */
 /* params_fp32: [W1, b1, ..., W6, b6], W row-major [out][in], n values
  * (43,779 for 16/96/5).  Becomes the FP32 master copy; Adam state is reset;
- * the inference pack of the current precision is rebuilt. */
+ * the inference pack of the current precision is rebuilt; desc->colour
+ * selects the output colour space (NPT_E_INVALID_ARG if unknown). */
 int npt_nif_upload(npt_ctx *ctx, const npt_nif_desc *desc, const float *params_fp32,
                    uint64_t n, void *stream);
 /* Copies the FP32 master parameters to host memory (synchronous). */

@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libnpt_oracle.so")
 SRC = os.path.join(HERE, "npt_oracle.c")
 
-RNG_CAM, RNG_SCATTER, RNG_TRAIN, RNG_SCENE = 0, 1, 2, 3
+RNG_CAM, RNG_SCATTER, RNG_TRAIN, RNG_SCENE, RNG_SROUND = 0, 1, 2, 3, 4
 LAMBERT, MIRROR, DIELECTRIC, EMITTER = 0, 1, 2, 3
 ENV_MAP, ENV_NIF, ENV_CONST = 0, 1, 2
 MISS = 0xFFFFFFFF
@@ -48,7 +48,7 @@ class Camera(C.Structure):
 
 
 class NifShape(C.Structure):
-    _fields_ = [("n_freq", C.c_uint32), ("hidden", C.c_uint32), ("layers", C.c_uint32)]
+    _fields_ = [("n_freq", C.c_uint32), ("hidden", C.c_uint32), ("layers", C.c_uint32), ("colour", C.c_uint32)]
 
 
 class RenderDesc(C.Structure):
@@ -94,6 +94,7 @@ def lib():
             "or_nif_frequency": (C.c_uint32, [C.c_uint32]),
             "or_nif_features": (None, [C.POINTER(NifShape), C.c_double, C.c_double, _f64p]),
             "or_yuv_to_rgb_matrix": (None, [_f64p]),
+            "or_colour_to_rgb_matrix": (None, [C.c_uint32, _f64p]),
             "or_nif_forward": (None, [C.POINTER(NifShape), _f64p, C.c_double, C.c_double, _f64p]),
             "or_nif_radiance": (None, [C.POINTER(NifShape), _f64p, C.c_double, C.c_double, _f64p]),
             "or_huber": (C.c_double, [C.c_double, C.c_double]),
@@ -107,7 +108,11 @@ def lib():
             "or_nif_train_step": (C.c_double, [C.POINTER(NifShape), _f64p, _f64p, _f64p, _f32p,
                                                C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint32,
                                                C.c_uint64, C.c_double, C.c_double, C.c_double,
-                                               C.c_double, C.c_double]),
+                                               C.c_double, C.c_double, C.c_int]),
+            "or_fp16_toward_zero": (C.c_double, [C.c_double]),
+            "or_fp16_stochastic": (C.c_double, [C.c_double, C.c_double]),
+            "or_adam_step_fp16_master": (None, [C.c_uint64, _f64p, _f64p, _f64p, _f64p, C.c_uint32, C.c_double,
+                                                C.c_double, C.c_double, C.c_double, C.c_uint64]),
             "or_scene_create": (_P, [_f32p, C.c_uint64, _u32p, C.c_uint64, _u32p, _f32p, C.c_uint64,
                                      _u32p, C.POINTER(Material), C.c_uint32, C.c_int]),
             "or_scene_add_blas": (C.c_int, [_P, _f32p, C.c_uint64, _u32p, C.c_uint64, _u32p]),
@@ -251,9 +256,13 @@ def env_bilinear(env, u, v):
 
 
 # ---------------------------------------------------------------------- NIF
-def nif_shape(n_freq=16, hidden=96, layers=5):
+# output colour spaces of the network (Sec. 4.3)
+COLOUR_YUV, COLOUR_RGB, COLOUR_YCOCG = 0, 1, 2
+
+
+def nif_shape(n_freq=16, hidden=96, layers=5, colour=COLOUR_YUV):
     s = NifShape()
-    s.n_freq, s.hidden, s.layers = n_freq, hidden, layers
+    s.n_freq, s.hidden, s.layers, s.colour = n_freq, hidden, layers, colour
     return s
 
 
@@ -274,6 +283,12 @@ def nif_features(shape, u, v):
 def yuv_to_rgb_matrix():
     m = np.zeros(9, np.float64)
     lib().or_yuv_to_rgb_matrix(_ptr(m, C.c_double))
+    return m.reshape(3, 3)
+
+
+def colour_to_rgb_matrix(colour):
+    m = np.zeros(9, np.float64)
+    lib().or_colour_to_rgb_matrix(colour, _ptr(m, C.c_double))
     return m.reshape(3, 3)
 
 
@@ -362,13 +377,27 @@ def adam_step(params, grad, m, v, step, lr, beta1, beta2, eps):
 
 
 def nif_train_step(shape, params, m, v, env, seed, step, batch, lr=1e-3, beta1=0.9,
-                   beta2=0.999, eps=1e-7, delta=1e-3):
-    """In-place training step on float64 params/m/v; returns the loss before it."""
+                   beta2=0.999, eps=1e-7, delta=1e-3, fp16_master=False):
+    """In-place training step on float64 params/m/v; returns the loss before it.
+    fp16_master: binary16 master weights with stochastically rounded updates."""
     env = f32(env)
     h, w = env.shape[:2]
     return lib().or_nif_train_step(C.byref(shape), _ptr(params, C.c_double), _ptr(m, C.c_double),
                                    _ptr(v, C.c_double), _ptr(env, C.c_float), w, h, seed, step,
-                                   batch, lr, beta1, beta2, eps, delta)
+                                   batch, lr, beta1, beta2, eps, delta, int(fp16_master))
+
+
+def fp16_toward_zero(x):
+    return lib().or_fp16_toward_zero(float(x))
+
+
+def fp16_stochastic(x, u):
+    return lib().or_fp16_stochastic(float(x), float(u))
+
+
+def adam_step_fp16_master(params, grad, m, v, step, seed, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-7):
+    lib().or_adam_step_fp16_master(params.size, _ptr(params, C.c_double), _ptr(grad, C.c_double),
+                                   _ptr(m, C.c_double), _ptr(v, C.c_double), step, lr, beta1, beta2, eps, seed)
 
 
 # ------------------------------------------------------------------- scenes

@@ -445,6 +445,22 @@ void or_yuv_to_rgb_matrix(double m[9])
     memcpy(m, k, sizeof(k));
 }
 
+/* Output colour spaces compared in Sec. 4.3: YUV (above), RGB (identity) and
+ * YCoCg (Malvar & Sullivan): R = Y + Co - Cg, G = Y + Cg, B = Y - Co - Cg,
+ * the exact inverse of Y = R/4 + G/2 + B/4, Co = (R - B)/2,
+ * Cg = -R/4 + G/2 - B/4. */
+void or_colour_to_rgb_matrix(uint32_t colour, double m[9])
+{
+    static const double rgb[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    static const double ycocg[9] = {1, 1, -1, 1, 0, 1, 1, -1, -1};
+    if (colour == OR_COLOUR_RGB)
+        memcpy(m, rgb, sizeof(rgb));
+    else if (colour == OR_COLOUR_YCOCG)
+        memcpy(m, ycocg, sizeof(ycocg));
+    else
+        or_yuv_to_rgb_matrix(m);
+}
+
 /* Forward pass keeping post-activation values: act[l] has layer_in(l) values
  * for l = 0..layers (act[0] = features); y = YUV output, z = RGB log. */
 static void nif_forward_full(const or_nif_shape *s, const double *params, double u, double v,
@@ -464,7 +480,7 @@ static void nif_forward_full(const or_nif_shape *s, const double *params, double
         p += (size_t)no * ni + no;
     }
     double m[9];
-    or_yuv_to_rgb_matrix(m);
+    or_colour_to_rgb_matrix(s->colour, m);
     for (int r = 0; r < 3; ++r) z[r] = m[3 * r] * y[0] + m[3 * r + 1] * y[1] + m[3 * r + 2] * y[2];
 }
 
@@ -605,7 +621,7 @@ void or_nif_forward_q(const or_nif_shape *s, const double *deq, int prec, double
         p += (size_t)no * ni + no;
     }
     double m[9];
-    or_yuv_to_rgb_matrix(m);
+    or_colour_to_rgb_matrix(s->colour, m);
     for (int r = 0; r < 3; ++r) z[r] = m[3 * r] * y[0] + m[3 * r + 1] * y[1] + m[3 * r + 2] * y[2];
     free(x);
     free(h);
@@ -650,7 +666,7 @@ double or_nif_loss_grad(const or_nif_shape *s, const double *params, uint64_t n,
         o += (size_t)layer_out(s, l) * layer_in(s, l) + layer_out(s, l);
     }
     double m[9];
-    or_yuv_to_rgb_matrix(m);
+    or_colour_to_rgb_matrix(s->colour, m);
     double loss = 0.0;
     double scale = 1.0 / (3.0 * (double)n);
     for (uint64_t i = 0; i < n; ++i) {
@@ -740,18 +756,83 @@ void or_adam_step(uint64_t n, double *params, const double *grad, double *m, dou
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* FP16 master weights with stochastic rounding (Sec. 3.2.1 keeps the IPU's */
+/* master weights in binary16 and rounds updates stochastically, after      */
+/* Gupta et al. 2015).  x lies between adjacent binary16 magnitudes a       */
+/* (toward zero) and a + q (away from zero), q their spacing; it becomes    */
+/* a + q with probability (|x| - a)/q, i.e. when u < (|x| - a)/q for u      */
+/* uniform in [0,1).  Magnitudes from 65504 up saturate to 65504.           */
+/* ------------------------------------------------------------------------ */
+static double fp16_spacing(double ax)
+{
+    int e;
+    (void)frexp(ax, &e); /* ax in [2^(e-1), 2^e) */
+    int lead = e - 1 < -14 ? -14 : e - 1;
+    return ldexp(1.0, lead - 10);
+}
+
+double or_fp16_toward_zero(double x)
+{
+    if (x == 0.0 || isnan(x)) return x;
+    double ax = fabs(x);
+    if (ax >= 65504.0) return copysign(65504.0, x);
+    double q = fp16_spacing(ax);
+    return copysign(floor(ax / q) * q, x);
+}
+
+double or_fp16_stochastic(double x, double u)
+{
+    if (x == 0.0 || isnan(x)) return x;
+    double ax = fabs(x);
+    if (ax >= 65504.0) return copysign(65504.0, x);
+    double q = fp16_spacing(ax);
+    double a = floor(ax / q) * q;
+    return copysign(u < (ax - a) / q ? a + q : a, x);
+}
+
+/* Adam with FP16 master weights: the master is first rounded to the nearest */
+/* binary16 (a no-op after the first step), the update is taken in FP64 and */
+/* rounded to FP32, then rounded stochastically to binary16 with u from the */
+/* Philox stream (parameter index, Adam step t, 0, OR_RNG_SROUND).          */
+void or_adam_step_fp16_master(uint64_t n, double *params, const double *grad, double *m, double *v,
+                              uint32_t step, double lr, double beta1, double beta2, double eps,
+                              uint64_t seed)
+{
+    double c1 = 1.0 - pow(beta1, (double)step);
+    double c2 = 1.0 - pow(beta2, (double)step);
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (uint64_t i = 0; i < n; ++i) {
+        double w0 = or_round_to(params[i], OR_FMT_F16);
+        m[i] = beta1 * m[i] + (1.0 - beta1) * grad[i];
+        v[i] = beta2 * v[i] + (1.0 - beta2) * grad[i] * grad[i];
+        double mh = m[i] / c1;
+        double vh = v[i] / c2;
+        double x = (double)(float)(w0 - lr * mh / (sqrt(vh) + eps));
+        const uint32_t ctr[4] = {(uint32_t)i, step, 0u, OR_RNG_SROUND};
+        uint32_t r[4];
+        or_philox4x32_10(ctr, key, r);
+        params[i] = or_fp16_stochastic(x, (double)or_u01(r[0]));
+    }
+}
+
 double or_nif_train_step(const or_nif_shape *s, double *params, double *m, double *v,
                          const float *map, uint32_t w, uint32_t h, uint64_t seed, uint32_t step,
                          uint64_t batch, double lr, double beta1, double beta2, double eps,
-                         double delta)
+                         double delta, int fp16_master)
 {
     uint64_t np = or_nif_param_count(s);
     double *uv = (double *)malloc(sizeof(double) * 2 * batch);
     double *tg = (double *)malloc(sizeof(double) * 3 * batch);
     double *g = (double *)malloc(sizeof(double) * np);
+    if (fp16_master)
+        for (uint64_t i = 0; i < np; ++i) params[i] = or_round_to(params[i], OR_FMT_F16);
     or_nif_train_batch(map, w, h, seed, step, batch, uv, tg);
     double loss = or_nif_loss_grad(s, params, batch, uv, tg, delta, g);
-    or_adam_step(np, params, g, m, v, step + 1, lr, beta1, beta2, eps);
+    if (fp16_master)
+        or_adam_step_fp16_master(np, params, g, m, v, step + 1, lr, beta1, beta2, eps, seed);
+    else
+        or_adam_step(np, params, g, m, v, step + 1, lr, beta1, beta2, eps);
     free(g);
     free(tg);
     free(uv);

@@ -36,7 +36,7 @@ extern "C" {
 #endif
 
 /* RNG purposes (the fourth counter word). */
-enum { OR_RNG_CAM = 0, OR_RNG_SCATTER = 1, OR_RNG_TRAIN = 2, OR_RNG_SCENE = 3 };
+enum { OR_RNG_CAM = 0, OR_RNG_SCATTER = 1, OR_RNG_TRAIN = 2, OR_RNG_SCENE = 3, OR_RNG_SROUND = 4 };
 
 /* Material types. */
 enum { OR_LAMBERT = 0, OR_MIRROR = 1, OR_DIELECTRIC = 2, OR_EMITTER = 3 };
@@ -65,11 +65,14 @@ typedef struct {
 } or_camera;
 
 /* NIF shape: 4*n_freq Fourier features -> `layers` x [dense `hidden` + ReLU]
- * -> dense 3 -> fixed 3x3 colour matrix (YUV->RGB). */
+ * -> dense 3 -> fixed 3x3 colour matrix to RGB.  colour: the space the
+ * network's outputs live in (Sec. 4.3): OR_COLOUR_YUV (default), RGB, YCOCG. */
+enum { OR_COLOUR_YUV = 0, OR_COLOUR_RGB = 1, OR_COLOUR_YCOCG = 2 };
 typedef struct {
     uint32_t n_freq;
     uint32_t hidden;
     uint32_t layers;
+    uint32_t colour;
 } or_nif_shape;
 
 typedef struct or_scene or_scene;
@@ -108,6 +111,8 @@ uint64_t or_nif_param_count(const or_nif_shape *s);
 uint32_t or_nif_frequency(uint32_t k);
 void or_nif_features(const or_nif_shape *s, double u, double v, double *feat);
 void or_yuv_to_rgb_matrix(double m[9]);
+/* Row-major M with RGB = M * (network output) for an OR_COLOUR_* space. */
+void or_colour_to_rgb_matrix(uint32_t colour, double m[9]);
 /* Log-space RGB output z of the network (before expm1). */
 void or_nif_forward(const or_nif_shape *s, const double *params, double u, double v, double z[3]);
 /* Radiance = max(0, expm1(z)). */
@@ -142,11 +147,22 @@ void or_nif_train_batch(const float *map, uint32_t w, uint32_t h, uint64_t seed,
 /* One Adam step (Kingma & Ba 2015, Alg. 1); step is 1-based. */
 void or_adam_step(uint64_t n, double *params, const double *grad, double *m, double *v,
                   uint32_t step, double lr, double beta1, double beta2, double eps);
-/* One full training step; returns the loss before the update. */
+/* binary16 round toward zero (saturating at 65504) and stochastic rounding
+ * with u in [0,1) (FP16 master weights, Sec. 3.2.1). */
+double or_fp16_toward_zero(double x);
+double or_fp16_stochastic(double x, double u);
+/* Adam step on FP16 master weights with stochastic rounding; step 1-based,
+ * u of parameter i from Philox (i, step, 0, OR_RNG_SROUND) under seed. */
+void or_adam_step_fp16_master(uint64_t n, double *params, const double *grad, double *m, double *v,
+                              uint32_t step, double lr, double beta1, double beta2, double eps,
+                              uint64_t seed);
+/* One full training step; returns the loss before the update.  fp16_master:
+ * master weights in binary16 (rounded to nearest first) with stochastic
+ * rounding of the update. */
 double or_nif_train_step(const or_nif_shape *s, double *params, double *m, double *v,
                          const float *map, uint32_t w, uint32_t h, uint64_t seed, uint32_t step,
                          uint64_t batch, double lr, double beta1, double beta2, double eps,
-                         double delta);
+                         double delta, int fp16_master);
 
 /* ---- scenes, closest hit and the render estimator ---------------------- */
 /* accel: 0 = brute force over all primitives, 1 = the oracle's own median-split BVH. */

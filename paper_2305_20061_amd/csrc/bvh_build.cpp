@@ -225,7 +225,93 @@ bool check_flat(const FlatBvh& b, std::string& err) {
   return true;
 }
 
+// smallest binary16 value >= v (v >= 0, finite), as bits; false beyond 65504
+bool half_up(double v, uint16_t& h) {
+  if (!(v <= 65504.0)) return false;
+  if (v <= 0.0) {
+    h = 0;
+    return true;
+  }
+  int e;
+  (void)std::frexp(v, &e);  // v in [2^(e-1), 2^e)
+  int lead = std::max(e - 1, -14);
+  double q = std::ldexp(1.0, lead - 10);
+  double m = std::ceil(v / q);  // v <= m q, m < 2^11
+  if (m >= 2048.0) {            // rounded up into the next binade
+    m = 1024.0;
+    lead += 1;
+  }
+  if (lead == -14 && m < 1024.0) {
+    h = (uint16_t)m;  // subnormal: mantissa only
+  } else {
+    h = (uint16_t)(((lead + 15) << 10) | ((uint32_t)m - 1024u));
+  }
+  return lead <= 15;
+}
+
+float half_value(uint16_t h) {
+  const int ex = (h >> 10) & 31, man = h & 1023;
+  if (ex == 0) return (float)std::ldexp((double)man, -24);
+  return (float)std::ldexp((double)(1024 + man), ex - 25);
+}
+
+uint16_t half_next(uint16_t h) { return (uint16_t)(h + 1); }  // next larger non-negative binary16
+
 }  // namespace
+
+bool compress_half_extents(FlatBvh& b, std::string& err) {
+  if (b.width != 4 || b.node_float4s != kNode4Float4s) {
+    err = "FP16 extents need 4-wide FP32 nodes";
+    return false;
+  }
+  const size_t nn = b.nodes.size() / kNode4Float4s;
+  std::vector<float4> out(nn * kNode4HalfFloat4s);
+  for (size_t i = 0; i < nn; ++i) {
+    const float4* o = &b.nodes[i * kNode4Float4s];
+    float4* h = &out[i * kNode4HalfFloat4s];
+    uint16_t ext[3][4];
+    float lo[3][4];
+    for (int a = 0; a < 3; ++a) {
+      const float l4[4] = {o[2 * a].x, o[2 * a].y, o[2 * a].z, o[2 * a].w};
+      const float h4[4] = {o[2 * a + 1].x, o[2 * a + 1].y, o[2 * a + 1].z, o[2 * a + 1].w};
+      const uint32_t r4[4] = {ubits(o[6].x), ubits(o[6].y), ubits(o[6].z), ubits(o[6].w)};
+      for (int c = 0; c < 4; ++c) {
+        if (r4[c] == kEmptyChild) {
+          lo[a][c] = INFINITY;
+          ext[a][c] = 0;
+          continue;
+        }
+        lo[a][c] = l4[c];
+        uint16_t e;
+        if (!half_up((double)h4[c] - (double)l4[c], e)) {
+          err = "FP16 extents: a box is wider than 65504";
+          return false;
+        }
+        // the traversal forms the upper plane as an FP32 sum: make sure it
+        // does not fall below the true one
+        while ((float)(l4[c] + half_value(e)) < h4[c]) {
+          e = half_next(e);
+          if (half_value(e) > 65504.0f || ((e >> 10) & 31) == 31) {
+            err = "FP16 extents: a box is wider than 65504";
+            return false;
+          }
+        }
+        ext[a][c] = e;
+      }
+    }
+    auto pack = [](uint16_t a, uint16_t b2) { return bits((uint32_t)a | ((uint32_t)b2 << 16)); };
+    h[0] = make_float4(lo[0][0], lo[0][1], lo[0][2], lo[0][3]);
+    h[1] = make_float4(lo[1][0], lo[1][1], lo[1][2], lo[1][3]);
+    h[2] = make_float4(lo[2][0], lo[2][1], lo[2][2], lo[2][3]);
+    h[3] = make_float4(pack(ext[0][0], ext[0][1]), pack(ext[0][2], ext[0][3]), pack(ext[1][0], ext[1][1]),
+                       pack(ext[1][2], ext[1][3]));
+    h[4] = make_float4(pack(ext[2][0], ext[2][1]), pack(ext[2][2], ext[2][3]), 0.0f, 0.0f);
+    h[5] = o[6];
+  }
+  b.nodes = std::move(out);
+  b.node_float4s = kNode4HalfFloat4s;
+  return true;
+}
 
 bool build_bvh(const BuildInput& in, uint32_t bins, uint32_t max_leaf, uint32_t lds_levels, uint32_t width,
                FlatBvh& out,

@@ -44,6 +44,13 @@ bool build_bvh(const BuildInput& in, uint32_t bins, uint32_t max_leaf, uint32_t 
                FlatBvh& out,
                std::string& err);
 
+// Rewrites the 7-row FP32 nodes of a 4-wide tree (one- or two-level) as
+// 6-row nodes with binary16 extents (npt_shared.h layout); node indices and
+// slots are unchanged.  Each extent is the smallest binary16 value whose
+// FP32 sum with the lower plane is >= the upper plane.  Fails for extents
+// beyond 65504.
+bool compress_half_extents(FlatBvh& b, std::string& err);
+
 // One object of a two-level scene: bottom tree `tree` placed in the world at
 // translate + scale * x (scale > 0), hits reported with instance id `id`.
 struct Placement {

@@ -187,6 +187,7 @@ struct NifIO {
   float* out;            // kSrcDirs: radiance [n][3]; kSrcGrid: log-space RGB [n][3]
   uint64_t n;            // kSrcDirs / kSrcGrid count
   uint32_t gw, gh;       // kSrcGrid
+  ColourMatrix cm;       // network output -> log-space RGB
 };
 
 template <int P, bool kAccurateSin>
@@ -431,11 +432,12 @@ __global__ __launch_bounds__(kNifBlock, 1) void k_nif_infer(const uint8_t* gpack
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         if (!valid[t]) continue;
-        const float Y = o[t][0], U = o[t][1], V = o[t][2];
-        // YUV -> RGB (BT.601 analogue), in log space
-        const float zr = Y + 1.13983f * V;
-        const float zg = (Y - 0.39465f * U) - 0.58060f * V;
-        const float zb = Y + 2.03211f * U;
+        // the fixed colour matrix, in log space
+        const float* m = io.cm.m;
+        const float y0 = o[t][0], y1 = o[t][1], y2 = o[t][2];
+        const float zr = fmaf(m[2], y2, fmaf(m[1], y1, m[0] * y0));
+        const float zg = fmaf(m[5], y2, fmaf(m[4], y1, m[3] * y0));
+        const float zb = fmaf(m[8], y2, fmaf(m[7], y1, m[6] * y0));
         const uint64_t idx = tile * kRays + t * 32 + col;
         if (io.source == kSrcGrid) {
           io.out[3 * idx] = zr;
@@ -522,9 +524,11 @@ static int nif_grid(uint64_t n, int num_cus) {
   return (int)(tiles < 1 ? 1 : (tiles > (uint64_t)num_cus ? num_cus : tiles));
 }
 
-hipError_t launch_nif_queue(int prec, const void* frags, const float* bias, const EnvQueue& env, float4* L,
-                            const uint32_t* cnt, uint32_t depth, uint64_t max_rays, int num_cus, hipStream_t s) {
+hipError_t launch_nif_queue(int prec, const void* frags, const float* bias, const ColourMatrix& cm,
+                            const EnvQueue& env, float4* L, const uint32_t* cnt, uint32_t depth, uint64_t max_rays,
+                            int num_cus, hipStream_t s) {
   NifIO io{};
+  io.cm = cm;
   io.source = kSrcQueue;
   io.env = env;
   io.L = L;
@@ -533,9 +537,10 @@ hipError_t launch_nif_queue(int prec, const void* frags, const float* bias, cons
   return launch_infer(prec, frags, bias, io, nif_grid(max_rays, num_cus), s);
 }
 
-hipError_t launch_nif_dirs(int prec, const void* frags, const float* bias, const float* dirs, uint64_t n,
-                           float* rgb, int num_cus, hipStream_t s) {
+hipError_t launch_nif_dirs(int prec, const void* frags, const float* bias, const ColourMatrix& cm, const float* dirs,
+                           uint64_t n, float* rgb, int num_cus, hipStream_t s) {
   NifIO io{};
+  io.cm = cm;
   io.source = kSrcDirs;
   io.dirs = dirs;
   io.out = rgb;
@@ -543,9 +548,10 @@ hipError_t launch_nif_dirs(int prec, const void* frags, const float* bias, const
   return launch_infer(prec, frags, bias, io, nif_grid(n, num_cus), s);
 }
 
-hipError_t launch_nif_grid(int prec, const void* frags, const float* bias, uint32_t gw, uint32_t gh,
-                           float* zout, int num_cus, hipStream_t s) {
+hipError_t launch_nif_grid(int prec, const void* frags, const float* bias, const ColourMatrix& cm, uint32_t gw,
+                           uint32_t gh, float* zout, int num_cus, hipStream_t s) {
   NifIO io{};
+  io.cm = cm;
   io.source = kSrcGrid;
   io.gw = gw;
   io.gh = gh;

@@ -257,9 +257,57 @@ __device__ __forceinline__ bool visit4(const char* base, uint32_t off, const Ray
   return true;
 }
 
-// Tree kind of the instanced (two-level, 4-wide) traversal, next to the
-// widths 2 and 4 of the one-level traversals.
+// One 4-wide node with binary16 extents (kNode4HalfFloat4s layout).  A
+// child's upper plane on an axis is the FP32 sum lo + ext, which the builder
+// made >= the true plane; it is the entry plane where the direction is
+// negative and the exit plane otherwise.  Both planes are formed as
+// fma(ext, w, lo) with per-ray weights w in {0, 1} (fma(ext, 1, lo) is that
+// rounded sum, fma(ext, 0, lo) is lo), so no per-child select is needed.
+// Empty children (lo = +inf, ext = 0) miss as in visit4.
+template <class S>
+__device__ __forceinline__ bool visit4h(const char* base, uint32_t off, const RayFrame& f, float lim, S& st,
+                                        int& sp, uint32_t& ref) {
+  const float4 lx = *reinterpret_cast<const float4*>(base + off);
+  const float4 ly = *reinterpret_cast<const float4*>(base + off + 16u);
+  const float4 lz = *reinterpret_cast<const float4*>(base + off + 32u);
+  const uint4 exy = *reinterpret_cast<const uint4*>(base + off + 48u);
+  const uint4 ezr = *reinterpret_cast<const uint4*>(base + off + 64u);
+  const float4 rf = *reinterpret_cast<const float4*>(base + off + 80u);
+  uint32_t r0 = __float_as_uint(rf.x), r1 = __float_as_uint(rf.y), r2 = __float_as_uint(rf.z),
+           r3 = __float_as_uint(rf.w);
+  const float wnx = f.ix >= 0.0f ? 0.0f : 1.0f, wny = f.iy >= 0.0f ? 0.0f : 1.0f, wnz = f.iz >= 0.0f ? 0.0f : 1.0f;
+  const float wfx = 1.0f - wnx, wfy = 1.0f - wny, wfz = 1.0f - wnz;
+  auto lo16 = [](uint32_t v) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(v & 0xFFFFu)); };
+  auto hi16 = [](uint32_t v) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(v >> 16)); };
+  auto child = [&](float lox, float ex, float loy, float ey, float loz, float ez) {
+    return child_entry(f, __builtin_fmaf(ex, wnx, lox), __builtin_fmaf(ex, wfx, lox), __builtin_fmaf(ey, wny, loy),
+                       __builtin_fmaf(ey, wfy, loy), __builtin_fmaf(ez, wnz, loz), __builtin_fmaf(ez, wfz, loz), lim);
+  };
+  float k0 = child(lx.x, lo16(exy.x), ly.x, lo16(exy.z), lz.x, lo16(ezr.x));
+  float k1 = child(lx.y, hi16(exy.x), ly.y, hi16(exy.z), lz.y, hi16(ezr.x));
+  float k2 = child(lx.z, lo16(exy.y), ly.z, lo16(exy.w), lz.z, lo16(ezr.y));
+  float k3 = child(lx.w, hi16(exy.y), ly.w, hi16(exy.w), lz.w, hi16(ezr.y));
+  order2(k0, r0, k1, r1);
+  order2(k2, r2, k3, r3);
+  order2(k0, r0, k2, r2);
+  order2(k1, r1, k3, r3);
+  order2(k1, r1, k2, r2);
+  __asm__ volatile("" : : "v"(r0), "v"(r1), "v"(r2), "v"(r3));
+  const float inf = __builtin_inff();
+  if (!(k0 < inf)) return false;
+  st.push3(sp, r3, k3 < inf, r2, k2 < inf, r1, k1 < inf);
+  ref = r0;
+  return true;
+}
+
+// Tree kinds of the traversal (the kWidth template argument): widths 2 and
+// 4 of one-level trees, the instanced (two-level, 4-wide) traversal, and
+// the 4-wide kinds with binary16-extent nodes.
 constexpr int kTwoLevel = 1;
+constexpr int kTwoLevelHalf = 3;
+constexpr int kHalf4 = 5;
+__host__ __device__ constexpr bool is_two_level(int w) { return w == kTwoLevel || w == kTwoLevelHalf; }
+__host__ __device__ constexpr bool half_nodes(int w) { return w == kHalf4 || w == kTwoLevelHalf; }
 
 // The world ray of a two-level traversal waits in LDS (six values per lane,
 // stride kStride) rather than in registers: it is needed only when an
@@ -311,7 +359,7 @@ __device__ __forceinline__ bool trav_begin(const SceneView& sc, V3 o, V3 d, Trav
 // false once the stack is empty.
 template <int kWidth, class S, int kStride>
 __device__ __forceinline__ bool trav_pop(S& st, const WorldRay<kStride>& wr, Trav& tv) {
-  if constexpr (kWidth == kTwoLevel) {
+  if constexpr (is_two_level(kWidth)) {
     if (tv.sp == tv.mark) {
       V3 ow, dw;
       wr.load(ow, dw);
@@ -357,6 +405,9 @@ __device__ __forceinline__ bool trav_node(const SceneView& sc, const float4* lds
       tv.ref = h0 ? r0 : r1;
       return true;
     }
+  } else if constexpr (half_nodes(kWidth)) {
+    const uint32_t off = tv.ref * (kNode4HalfFloat4s * 16u);  // node arrays stay below 4 GiB
+    if (visit4h(reinterpret_cast<const char*>(sc.nodes), off, tv.f, lim, st, tv.sp, tv.ref)) return true;
   } else {
     bool entered;
     const uint32_t off = tv.ref * (kNode4Float4s * 16u);  // node arrays stay below 4 GiB
@@ -376,7 +427,7 @@ __device__ __forceinline__ bool trav_node(const SceneView& sc, const float4* lds
 template <int kWidth, bool kCount, class S, int kStride>
 __device__ __forceinline__ bool trav_leaf(const SceneView& sc, S& st, const WorldRay<kStride>& wr, Trav& tv,
                                           uint32_t& n_prims) {
-  if (kWidth == kTwoLevel && tv.mark < 0) {
+  if (is_two_level(kWidth) && tv.mark < 0) {
     const uint32_t k = (tv.ref >> 3) & 0x0FFFFFFFu;
     const float4 r0 = sc.instances[2 * (size_t)k], r1 = sc.instances[2 * (size_t)k + 1];
     V3 ow, dw;
@@ -389,7 +440,7 @@ __device__ __forceinline__ bool trav_leaf(const SceneView& sc, S& st, const Worl
     tv.mark = tv.sp;
     return true;
   }
-  test_leaf<kCount>(sc, tv.f, tv.ref, kWidth == kTwoLevel ? tv.inst : 0u, tv.h, &n_prims);
+  test_leaf<kCount>(sc, tv.f, tv.ref, is_two_level(kWidth) ? tv.inst : 0u, tv.h, &n_prims);
   return trav_pop<kWidth>(st, wr, tv);
 }
 
@@ -403,7 +454,7 @@ __device__ __forceinline__ Hit trace_closest(const SceneView& sc, const float4* 
   uint32_t nn = 0, np = 0;
   if (!trav_begin(sc, o, d, tv)) return tv.h;
   for (uint32_t v = 0; v < kMaxVisits; ++v) {
-    const bool more = (tv.ref & kLeafBit) == 0u ? trav_node<kWidth, false, kWidth != kTwoLevel>(sc, lds_nodes, st, wr, tv, nn)
+    const bool more = (tv.ref & kLeafBit) == 0u ? trav_node<kWidth, false, (kWidth == 2 || kWidth == 4)>(sc, lds_nodes, st, wr, tv, nn)
                                                 : trav_leaf<kWidth, false>(sc, st, wr, tv, np);
     if (!more) break;
   }
@@ -496,7 +547,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_extend(SceneView sc, uint32_t d
   extern __shared__ float4 lds_nodes[];
   using Stack = LaneStack<kStack, kTraceBlock>;
   __shared__ uint32_t stack_mem[(Stack::kShort > 0 ? Stack::kShort : 1) * kTraceBlock];
-  __shared__ float world_mem[(kWidth == kTwoLevel ? 6 : 1) * kTraceBlock];
+  __shared__ float world_mem[(is_two_level(kWidth) ? 6 : 1) * kTraceBlock];
   Stack st;
   st.lds = stack_mem + threadIdx.x;
   const WorldRay<kTraceBlock> wr{world_mem + threadIdx.x};
@@ -537,7 +588,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_extend(SceneView sc, uint32_t d
         const float* qo = reinterpret_cast<const float*>(in.o + ray);
         const float* qd = reinterpret_cast<const float*>(in.d + ray);
         const V3 o{qo[0], qo[1], qo[2]}, d{qd[0], qd[1], qd[2]};
-        if constexpr (kWidth == kTwoLevel) wr.store(o, d);
+        if constexpr (is_two_level(kWidth)) wr.store(o, d);
         busy = trav_begin(sc, o, d, tv);
         steps = 0;
         if (!busy) hits[ray] = make_float4(tv.h.t, __uint_as_float(kMiss), __uint_as_float(kMiss), 0.0f);
@@ -772,7 +823,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_primary(SceneView sc, Cam
   using Stack = LaneStack<kStack, kTraceBlock>;
   __shared__ uint32_t stack_mem[(Stack::kShort > 0 ? Stack::kShort : 1) * kTraceBlock];
   stage_lds_nodes(sc, lds_nodes);
-  __shared__ float world_mem[(kWidth == kTwoLevel ? 6 : 1) * kTraceBlock];
+  __shared__ float world_mem[(is_two_level(kWidth) ? 6 : 1) * kTraceBlock];
   Stack st;
   st.lds = stack_mem + threadIdx.x;
   const WorldRay<kTraceBlock> wr{world_mem + threadIdx.x};
@@ -784,7 +835,7 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_primary(SceneView sc, Cam
     const U4 r = philox(pixel, pv.sample0, 0, kRngCamera, pv.key0, pv.key1);
     const V3 d = camera_direction(cam, pv.width, pv.height, x, y, unit_float(r.x), unit_float(r.y));
     const V3 o{cam.eye[0], cam.eye[1], cam.eye[2]};
-    if constexpr (kWidth == kTwoLevel) wr.store(o, d);
+    if constexpr (is_two_level(kWidth)) wr.store(o, d);
     const Hit h = trace_closest<kWidth>(sc, lds_nodes, st, wr, o, d);
     V3 n{0, 0, 0};
     if (h.slot != kMiss) {
@@ -863,8 +914,13 @@ hipError_t launch_extend(int stack_depth, const SceneView& sc, uint32_t depth, u
   }
   const bool c = visit_cnt != nullptr;
   const bool staged = sc.lds_nodes > 0;
-  if (sc.two_level) {
+  const bool half = sc.node_float4s == kNode4HalfFloat4s;
+  if (sc.two_level && half) {
+    NPT_LAUNCH_EXTEND_S(kTwoLevelHalf, false)
+  } else if (sc.two_level) {
     NPT_LAUNCH_EXTEND_S(kTwoLevel, false)
+  } else if (half) {
+    NPT_LAUNCH_EXTEND_S(kHalf4, false)
   } else if (sc.width == 4) {
     if (staged) {
       NPT_LAUNCH_EXTEND_S(4, true)
@@ -938,8 +994,13 @@ hipError_t launch_trace_primary(int stack_depth, const SceneView& sc, const Came
   else if (stack_depth <= 64) NPT_LAUNCH_PRIMARY(W, 64); \
   else NPT_LAUNCH_PRIMARY(W, 128);
   if (stack_depth > 128) return hipErrorInvalidValue;
-  if (sc.two_level) {
+  const bool half = sc.node_float4s == kNode4HalfFloat4s;
+  if (sc.two_level && half) {
+    NPT_LAUNCH_PRIMARY_S(kTwoLevelHalf)
+  } else if (sc.two_level) {
     NPT_LAUNCH_PRIMARY_S(kTwoLevel)
+  } else if (half) {
+    NPT_LAUNCH_PRIMARY_S(kHalf4)
   } else if (sc.width == 4) {
     NPT_LAUNCH_PRIMARY_S(4)
   } else {

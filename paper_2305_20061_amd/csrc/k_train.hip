@@ -128,7 +128,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
 template <int P>
 __global__ __launch_bounds__(256) void k_train_head(const float* master, const typename Prec<P>::Elem* H5,
                                                    const float* target, float delta, float scale, uint32_t B,
-                                                   float* dy_out, typename Prec<P>::Elem* dP, float* loss_part) {
+                                                   ColourMatrix cm, float* dy_out, typename Prec<P>::Elem* dP,
+                                                   float* loss_part) {
   __shared__ float w6[kOut * kHidden + kOut];
   __shared__ float red[256];
   for (int i = threadIdx.x; i < kOut * kHidden + kOut; i += blockDim.x) w6[i] = master[w_offset(kLayers) + i];
@@ -144,8 +145,10 @@ __global__ __launch_bounds__(256) void k_train_head(const float* master, const t
       y1 += w6[kHidden + i] * hv;
       y2 += w6[2 * kHidden + i] * hv;
     }
-    // YUV -> RGB (BT.601 analogue) in log space
-    const float z[3] = {y0 + 1.13983f * y2, (y0 - 0.39465f * y1) - 0.58060f * y2, y0 + 2.03211f * y1};
+    // the fixed colour matrix, in log space
+    const float* m = cm.m;
+    const float z[3] = {fmaf(m[2], y2, fmaf(m[1], y1, m[0] * y0)), fmaf(m[5], y2, fmaf(m[4], y1, m[3] * y0)),
+                        fmaf(m[8], y2, fmaf(m[7], y1, m[6] * y0))};
     float g[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -155,9 +158,9 @@ __global__ __launch_bounds__(256) void k_train_head(const float* master, const t
       g[k] = (ae <= delta ? e : copysignf(delta, e)) * scale;
     }
     // through the colour matrix: dy = M^T g
-    const float d0 = g[0] + g[1] + g[2];
-    const float d1 = -0.39465f * g[1] + 2.03211f * g[2];
-    const float d2 = 1.13983f * g[0] - 0.58060f * g[1];
+    const float d0 = fmaf(m[6], g[2], fmaf(m[3], g[1], m[0] * g[0]));
+    const float d1 = fmaf(m[7], g[2], fmaf(m[4], g[1], m[1] * g[0]));
+    const float d2 = fmaf(m[8], g[2], fmaf(m[5], g[1], m[2] * g[0]));
     dy_out[3 * (size_t)b] = d0;
     dy_out[3 * (size_t)b + 1] = d1;
     dy_out[3 * (size_t)b + 2] = d2;
@@ -238,27 +241,57 @@ __global__ __launch_bounds__(256) void k_reduce_grad(const float* partial, int s
   }
 }
 
-// Adam (Kingma & Ba, Alg. 1) on the FP32 master weights; refreshes the
-// operand-precision copy used by the next step's GEMMs
-template <int P>
+// Stochastic rounding to binary16 (FP16 master weights, Sec. 3.2.1; Gupta
+// et al. 2015): x between the binary16 magnitudes a (toward zero) and a + q
+// (q their spacing: 2^(e-10) in the binade [2^e, 2^(e+1)), 2^-24 below
+// 2^-14) goes to a + q when u < (|x| - a) / q.  Every step is exact in FP32:
+// the scalings by q are powers of two, |x| - a is exact (a <= |x| < 2a or
+// a = 0).  Magnitudes from 65504 up saturate.
+__device__ __forceinline__ float fp16_stochastic(float x, float u) {
+  const float ax = fabsf(x);
+  if (ax == 0.0f || ax != ax) return x;
+  if (ax >= 65504.0f) return copysignf(65504.0f, x);
+  const int e = max(ilogbf(ax), -14);
+  const float q = ldexpf(1.0f, e - 10);
+  const float a = floorf(ax / q) * q;
+  return copysignf(u < (ax - a) / q ? a + q : a, x);
+}
+
+// Adam (Kingma & Ba, Alg. 1) on the master weights; refreshes the
+// operand-precision copy used by the next step's GEMMs.  kSR: binary16
+// master weights (rounded to nearest on entry, a no-op after the first
+// step) whose update is rounded stochastically with u from the Philox
+// stream (parameter index, Adam step t, 0, kRngStochRound) under the seed.
+template <int P, bool kSR>
 __global__ __launch_bounds__(256) void k_adam(float* w, float* m, float* v, const float* g, float lr, float b1,
-                                             float b2, float eps, float c1, float c2, typename Prec<P>::Elem* wp) {
+                                             float b2, float eps, float c1, float c2, uint32_t t, uint32_t key0,
+                                             uint32_t key1, typename Prec<P>::Elem* wp) {
   for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < kParams; j += gridDim.x * blockDim.x) {
     const float gj = g[j];
     const float mj = b1 * m[j] + (1.0f - b1) * gj;
     const float vj = b2 * v[j] + (1.0f - b2) * gj * gj;
     m[j] = mj;
     v[j] = vj;
-    const float wj = w[j] - lr * (mj / c1) / (sqrtf(vj / c2) + eps);
+    const float w0 = kSR ? (float)(_Float16)w[j] : w[j];
+    float wj = w0 - lr * (mj / c1) / (sqrtf(vj / c2) + eps);
+    if (kSR) wj = fp16_stochastic(wj, unit_float(philox((uint32_t)j, t, 0, kRngStochRound, key0, key1).x));
     w[j] = wj;
     wp[j] = Prec<P>::cvt(wj);
   }
 }
 
-template <int P>
-__global__ __launch_bounds__(256) void k_convert(const float* w, typename Prec<P>::Elem* wp) {
-  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < kParams; j += gridDim.x * blockDim.x)
-    wp[j] = Prec<P>::cvt(w[j]);
+// operand-precision copy of the master weights; kFp16Master first rounds the
+// master itself to the nearest binary16
+template <int P, bool kFp16Master>
+__global__ __launch_bounds__(256) void k_convert(float* w, typename Prec<P>::Elem* wp) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < kParams; j += gridDim.x * blockDim.x) {
+    float x = w[j];
+    if (kFp16Master) {
+      x = (float)(_Float16)x;
+      w[j] = x;
+    }
+    wp[j] = Prec<P>::cvt(x);
+  }
 }
 
 // grid evaluation: squared log-error sums and the largest target per block
@@ -386,7 +419,7 @@ static hipError_t step_gradient(TrainScratch& s, const TrainConfig& c, const Tra
   }
   const int nblk = (int)((B + 255) / 256);
   hipLaunchKernelGGL(k_train_head<P>, dim3(nblk), dim3(256), 0, st, t.master, acts[kLayers], s.target, c.delta,
-                     c.loss_scale, B, s.dy, dp[0], s.loss_part);
+                     c.loss_scale, B, c.cm, s.dy, dp[0], s.loss_part);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int splits = (int)(B / kChunk);
   const int runs = (int)(B / kRun);
@@ -450,7 +483,11 @@ template <int P>
 static hipError_t run_p(TrainScratch& s, const TrainConfig& c, const TrainTargets& t, uint32_t step0,
                         uint32_t steps, bool update, float* grad_out, float* loss_out, hipStream_t st) {
   using Elem = typename Prec<P>::Elem;
-  hipLaunchKernelGGL(k_convert<P>, dim3(64), dim3(256), 0, st, t.master, static_cast<Elem*>(s.wp));
+  const bool fp16_master = update && c.master_prec == NPT_FP16;
+  if (fp16_master)
+    hipLaunchKernelGGL((k_convert<P, true>), dim3(64), dim3(256), 0, st, t.master, static_cast<Elem*>(s.wp));
+  else
+    hipLaunchKernelGGL((k_convert<P, false>), dim3(64), dim3(256), 0, st, t.master, static_cast<Elem*>(s.wp));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   for (uint32_t i = 0; i < steps; ++i) {
@@ -461,8 +498,13 @@ static hipError_t run_p(TrainScratch& s, const TrainConfig& c, const TrainTarget
     const double tt = (double)step + 1.0;
     const float c1 = (float)(1.0 - std::pow((double)c.beta1, tt));
     const float c2 = (float)(1.0 - std::pow((double)c.beta2, tt));
-    hipLaunchKernelGGL(k_adam<P>, dim3(64), dim3(256), 0, st, t.master, t.m, t.v, s.grad, c.lr, c.beta1, c.beta2,
-                       c.eps, c1, c2, static_cast<Elem*>(s.wp));
+    const uint32_t k0 = (uint32_t)c.seed, k1 = (uint32_t)(c.seed >> 32), tt1 = step + 1;
+    if (fp16_master)
+      hipLaunchKernelGGL((k_adam<P, true>), dim3(64), dim3(256), 0, st, t.master, t.m, t.v, s.grad, c.lr, c.beta1,
+                         c.beta2, c.eps, c1, c2, tt1, k0, k1, static_cast<Elem*>(s.wp));
+    else
+      hipLaunchKernelGGL((k_adam<P, false>), dim3(64), dim3(256), 0, st, t.master, t.m, t.v, s.grad, c.lr, c.beta1,
+                         c.beta2, c.eps, c1, c2, tt1, k0, k1, static_cast<Elem*>(s.wp));
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
@@ -499,8 +541,8 @@ hipError_t train_gradient(TrainScratch& s, const TrainConfig& c, const TrainTarg
   return dispatch(s, c, t, step, 1, false, d_grad, d_loss, st);
 }
 
-hipError_t grid_eval(TrainScratch& s, int prec, const void* frags, const float* bias, const TrainTargets& t,
-                     uint32_t gw, uint32_t gh, int num_cus, float out[2], hipStream_t st) {
+hipError_t grid_eval(TrainScratch& s, int prec, const void* frags, const float* bias, const ColourMatrix& cm,
+                     const TrainTargets& t, uint32_t gw, uint32_t gh, int num_cus, float out[2], hipStream_t st) {
   const uint64_t n = (uint64_t)gw * gh;
   hipError_t e;
   const int blocks = 256;
@@ -514,7 +556,7 @@ hipError_t grid_eval(TrainScratch& s, int prec, const void* frags, const float* 
     if ((e = hipMalloc((void**)&s.err_part, 2 * blocks * sizeof(float))) != hipSuccess) return e;
     s.grid_cap = n;
   }
-  if ((e = launch_nif_grid(prec, frags, bias, gw, gh, s.zgrid, num_cus, st)) != hipSuccess) return e;
+  if ((e = launch_nif_grid(prec, frags, bias, cm, gw, gh, s.zgrid, num_cus, st)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_grid_err, dim3(blocks), dim3(256), 0, st, s.zgrid, t.map, (int)t.w, (int)t.h, gw, gh,
                      s.err_part);
   if ((e = hipGetLastError()) != hipSuccess) return e;

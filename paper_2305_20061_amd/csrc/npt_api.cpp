@@ -99,6 +99,7 @@ struct npt_ctx {
   DevBuf d_master, d_adam_m, d_adam_v, d_frags, d_bias;
   uint32_t adam_step = 0;
   int nif_prec = NPT_FP16;
+  ColourMatrix nif_cm{};  // output colour space of the uploaded network
   TrainScratch train;
 
   // render scratch
@@ -359,7 +360,12 @@ extern "C" int npt_build_bvh(npt_ctx* c, const npt_bvh_params* p, void* stream) 
   uint32_t bins = p && p->bins ? p->bins : 32, max_leaf = p && p->max_leaf ? p->max_leaf : 4;
   uint32_t lds_levels = p ? p->lds_levels : 0;
   const uint32_t width = p && p->width ? p->width : 4;
+  const uint32_t node_format = p ? p->node_format : NPT_NODES_FP32;
   if (width != 2 && width != 4) return fail(c, NPT_E_INVALID_ARG, "BVH width must be 2 or 4");
+  if (node_format != NPT_NODES_FP32 && node_format != NPT_NODES_FP16_EXTENT)
+    return fail(c, NPT_E_INVALID_ARG, "unknown BVH node format");
+  if (node_format == NPT_NODES_FP16_EXTENT && (width != 4 || lds_levels != 0))
+    return fail(c, NPT_E_INVALID_ARG, "FP16-extent nodes need width 4 and lds_levels 0");
   if (bins < 4 || bins > 256 || max_leaf < 1 || max_leaf > kMaxLeaf || lds_levels > 8)
     return fail(c, NPT_E_INVALID_ARG, "bvh params out of range");
   const bool has_base = !c->tris.empty() || !c->spheres.empty();
@@ -426,6 +432,7 @@ extern "C" int npt_build_bvh(npt_ctx* c, const npt_bvh_params* p, void* stream) 
     }
     if (!build_two_level(bottoms, objects, bins, b, records, stack_need, e)) return fail(c, NPT_E_INVALID_ARG, e);
   }
+  if (node_format == NPT_NODES_FP16_EXTENT && !compress_half_extents(b, e)) return fail(c, NPT_E_UNSUPPORTED, e);
   if (trace_stack_size(stack_need) == 0)
     return fail(c, NPT_E_UNSUPPORTED, "BVH deeper than the 128-entry traversal stack");
   // the traversal addresses nodes with 32-bit byte offsets
@@ -534,9 +541,20 @@ static bool nif_desc_ok(const npt_nif_desc* d) {
          d->layers == (uint32_t)nif::kLayers;
 }
 
+// log-space RGB = M * network output for the colour spaces of Sec. 4.3:
+// YUV (BT.601 analogue), RGB (identity), YCoCg (Malvar & Sullivan).
+static ColourMatrix colour_matrix(uint32_t colour) {
+  switch (colour) {
+    case NPT_COLOUR_RGB: return ColourMatrix{{1, 0, 0, 0, 1, 0, 0, 0, 1}};
+    case NPT_COLOUR_YCOCG: return ColourMatrix{{1, 1, -1, 1, 0, 1, 1, -1, -1}};
+    default: return ColourMatrix{{1.0f, 0.0f, 1.13983f, 1.0f, -0.39465f, -0.58060f, 1.0f, 2.03211f, 0.0f}};
+  }
+}
+
 extern "C" int npt_nif_upload(npt_ctx* c, const npt_nif_desc* desc, const float* params, uint64_t n, void* stream) {
   if (!c) return NPT_E_INVALID_ARG;
   if (!nif_desc_ok(desc)) return fail(c, NPT_E_UNSUPPORTED, "NIF shape must be n_freq 16, hidden 96, layers 5");
+  if (desc->colour > NPT_COLOUR_YCOCG) return fail(c, NPT_E_INVALID_ARG, "unknown NIF colour space");
   if (!params || n != (uint64_t)nif::kParams) return fail(c, NPT_E_INVALID_ARG, "parameter count mismatch");
   if (!finite_all(params, n)) return fail(c, NPT_E_NAN_INPUT, "non-finite NIF parameter");
   int r = need_device(c);
@@ -551,6 +569,7 @@ extern "C" int npt_nif_upload(npt_ctx* c, const npt_nif_desc* desc, const float*
   HIP_TRY(c, hipMemsetAsync(c->d_adam_v.p, 0, bytes, s));
   c->adam_step = 0;
   c->have_nif = true;
+  c->nif_cm = colour_matrix(desc->colour);
   r = repack_nif(c, s);
   if (r) return r;
   HIP_TRY(c, hipStreamSynchronize(s));
@@ -603,7 +622,8 @@ extern "C" int npt_nif_get_dequantized(npt_ctx* c, float* params, uint64_t n) {
   return ok(c);
 }
 
-static void train_defaults(const npt_train_params* p, TrainConfig& t) {
+static void train_defaults(npt_ctx* c, const npt_train_params* p, TrainConfig& t) {
+  t.cm = c->nif_cm;
   t.batch = p && p->batch ? p->batch : 65536;
   t.samples = p && p->samples ? p->samples : (1ull << 24);
   t.lr = p && p->lr > 0 ? p->lr : 1e-3f;
@@ -614,6 +634,7 @@ static void train_defaults(const npt_train_params* p, TrainConfig& t) {
   t.seed = p ? p->seed : 0;
   t.prec = p ? (int)p->grad_prec : NPT_FP32;
   t.loss_scale = p && p->loss_scale > 0 ? p->loss_scale : 1024.0f;
+  t.master_prec = p ? (int)p->master_prec : NPT_FP32;
 }
 
 static int train_check(npt_ctx* c, const TrainConfig& t) {
@@ -623,6 +644,8 @@ static int train_check(npt_ctx* c, const TrainConfig& t) {
     return fail(c, NPT_E_INVALID_ARG, "batch must be a positive multiple of 2048, <= 2^22");
   if (t.prec != NPT_FP32 && t.prec != NPT_FP16 && t.prec != NPT_BF16)
     return fail(c, NPT_E_INVALID_ARG, "grad_prec must be FP32, FP16 or BF16");
+  if (t.master_prec != NPT_FP32 && t.master_prec != NPT_FP16)
+    return fail(c, NPT_E_INVALID_ARG, "master_prec must be FP32 or FP16");
   return NPT_OK;
 }
 
@@ -640,7 +663,7 @@ static TrainTargets train_targets(npt_ctx* c) {
 extern "C" int npt_nif_train(npt_ctx* c, const npt_train_params* p, npt_train_stats* out, void* stream) {
   if (!c) return NPT_E_INVALID_ARG;
   TrainConfig t;
-  train_defaults(p, t);
+  train_defaults(c, p, t);
   int r = train_check(c, t);
   if (r) return r;
   r = need_device(c);
@@ -674,7 +697,7 @@ extern "C" int npt_nif_train_grad(npt_ctx* c, const npt_train_params* p, uint32_
   if (!c) return NPT_E_INVALID_ARG;
   if (!d_grad || !d_loss) return fail(c, NPT_E_INVALID_ARG, "null output");
   TrainConfig t;
-  train_defaults(p, t);
+  train_defaults(c, p, t);
   int r = train_check(c, t);
   if (r) return r;
   r = need_device(c);
@@ -692,7 +715,7 @@ extern "C" int npt_nif_eval_grid(npt_ctx* c, uint32_t gw, uint32_t gh, float* ou
   if (r) return r;
   hipStream_t s = (hipStream_t)stream;
   float res[2] = {0, 0};
-  HIP_TRY(c, grid_eval(c->train, c->nif_prec, c->d_frags.p, c->d_bias.as<float>(), train_targets(c), gw, gh,
+  HIP_TRY(c, grid_eval(c->train, c->nif_prec, c->d_frags.p, c->d_bias.as<float>(), c->nif_cm, train_targets(c), gw, gh,
                        c->num_cus, res, s));
   out2[0] = res[0];
   out2[1] = res[1];
@@ -710,7 +733,8 @@ extern "C" int npt_env_query(npt_ctx* c, int mode, const float* d_dirs, uint64_t
     HIP_TRY(c, launch_env_query_map(c->d_env.as<float4>(), (int)c->env_w, (int)c->env_h, d_dirs, n, d_rgb, s));
   } else if (mode == NPT_ENV_NIF) {
     if (!c->have_nif) return fail(c, NPT_E_NO_ENV, "no NIF uploaded");
-    HIP_TRY(c, launch_nif_dirs(c->nif_prec, c->d_frags.p, c->d_bias.as<float>(), d_dirs, n, d_rgb, c->num_cus, s));
+    HIP_TRY(c, launch_nif_dirs(c->nif_prec, c->d_frags.p, c->d_bias.as<float>(), c->nif_cm, d_dirs, n, d_rgb,
+                               c->num_cus, s));
   } else {
     return fail(c, NPT_E_INVALID_ARG, "unknown env mode");
   }
@@ -830,7 +854,7 @@ extern "C" int npt_render(npt_ctx* c, uint32_t W, uint32_t H, uint32_t spp, uint
           HIP_TRY(c, launch_env_lookup(c->d_env.as<float4>(), (int)c->env_w, (int)c->env_h, eq, L, cnt, k, n,
                                        c->num_cus, s));
         } else {
-          HIP_TRY(c, launch_nif_queue(c->nif_prec, c->d_frags.p, c->d_bias.as<float>(), eq, L, cnt, k, n,
+          HIP_TRY(c, launch_nif_queue(c->nif_prec, c->d_frags.p, c->d_bias.as<float>(), c->nif_cm, eq, L, cnt, k, n,
                                       c->num_cus, s));
         }
         if (timing) HIP_TRY(c, hipEventRecord(c->env_events.back(), s));

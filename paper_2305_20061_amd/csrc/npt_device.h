@@ -16,7 +16,7 @@ namespace npt {
 // Philox4x32-10 (Salmon et al., SC'11): counter-based RNG standing in for the
 // IPU's hardware generator (Sec. 3.1.3).  Counter = (a, b, c, purpose).
 // ---------------------------------------------------------------------------
-enum : uint32_t { kRngCamera = 0, kRngScatter = 1, kRngTrain = 2 };
+enum : uint32_t { kRngCamera = 0, kRngScatter = 1, kRngTrain = 2, kRngStochRound = 4 };
 
 struct U4 {
   uint32_t x, y, z, w;

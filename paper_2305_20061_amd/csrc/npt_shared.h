@@ -24,6 +24,17 @@ constexpr uint32_t kEmptyChild = 0x7FFFFFFFu;  // unused child of a 4-wide node
 //   128-byte cache line was measured: no faster.)
 constexpr uint32_t kNode4Float4s = 7;
 
+// BVH4 node with binary16 extents (Sec. 3.1.4 proposes FP16 box extents),
+// 96 bytes (6 float4):
+//   h0 = lo.x of children 0..3, h1 = lo.y, h2 = lo.z (FP32),
+//   h3 = (ext.x of children 0,1 | 2,3, ext.y 0,1 | 2,3), h4 = (ext.z 0,1 | 2,3, -, -)
+//        as binary16 pairs (child 2k in the low half),
+//   h5 = (ref0, ref1, ref2, ref3).
+// The upper plane of a child is the FP32 sum lo + ext (rounded to nearest),
+// which the builder checks to be >= the true upper plane.  Empty children
+// have lo = +inf and ext = 0.
+constexpr uint32_t kNode4HalfFloat4s = 6;
+
 // Primitive slot, 48 bytes, leaf order:
 //   triangle: s0 = (v0, prim id), s1 = (v1, material), s2 = (v2, kPrimTriangle)
 //   sphere:   s0 = (centre, prim id), s1 = (radius, 0, 0, material), s2 = (0, 0, 0, kPrimSphere)
@@ -83,6 +94,12 @@ constexpr int kCntEnv = 80;
 constexpr int kCntWork = 160;
 constexpr int kCntEnvWork = 240;
 constexpr int kCntWords = 320;
+
+// Fixed output colour matrix of the HDR-NIF (Sec. 3.2; the spaces of
+// Sec. 4.3): log-space RGB = m (row-major 3x3) * network output.
+struct ColourMatrix {
+  float m[9];
+};
 
 struct PassView {
   uint32_t width, height, pixels;  // pixels = width * height

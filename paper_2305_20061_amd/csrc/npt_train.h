@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "npt_shared.h"
+
 namespace npt {
 
 struct TrainConfig {
@@ -14,6 +16,8 @@ struct TrainConfig {
   uint64_t seed;
   int prec;          // GEMM operand precision (NPT_FP32 / FP16 / BF16)
   float loss_scale;  // per-sample output gradient scale before low-precision GEMMs
+  ColourMatrix cm;   // fixed output colour matrix (network output -> log RGB)
+  int master_prec;   // NPT_FP32, or NPT_FP16: binary16 master weights, stochastically rounded updates
 };
 
 struct TrainTargets {
@@ -47,8 +51,8 @@ hipError_t train_run(TrainScratch& s, const TrainConfig& c, const TrainTargets& 
                      float* first_loss, float* last_loss, hipStream_t st);
 hipError_t train_gradient(TrainScratch& s, const TrainConfig& c, const TrainTargets& t, uint32_t step,
                           float* d_grad, float* d_loss, hipStream_t st);
-hipError_t grid_eval(TrainScratch& s, int prec, const void* frags, const float* bias, const TrainTargets& t,
-                     uint32_t gw, uint32_t gh, int num_cus, float out[2], hipStream_t st);
+hipError_t grid_eval(TrainScratch& s, int prec, const void* frags, const float* bias, const ColourMatrix& cm,
+                     const TrainTargets& t, uint32_t gw, uint32_t gh, int num_cus, float out[2], hipStream_t st);
 
 // counters of the render loop (k_render.hip)
 hipError_t launch_stats_clear(unsigned long long* stats, hipStream_t s);

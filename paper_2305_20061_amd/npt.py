@@ -24,6 +24,8 @@ ERRORS = {-1: "INVALID_ARG", -2: "NO_SCENE", -3: "NO_ENV", -4: "OOM", -5: "HIP",
 NPT_E = {v: k for k, v in ERRORS.items()}
 LAMBERT, MIRROR, DIELECTRIC, EMITTER = 0, 1, 2, 3
 ENV_MAP, ENV_NIF, ENV_NONE = 0, 1, 2
+NODES_FP32, NODES_FP16_EXTENT = 0, 1
+COLOUR_YUV, COLOUR_RGB, COLOUR_YCOCG = 0, 1, 2
 FP32, FP16, BF16, FP8 = 0, 1, 2, 3
 MAX_DEPTH = 64
 MISS = 0xFFFFFFFF
@@ -51,17 +53,18 @@ class npt_camera(C.Structure):
 
 
 class npt_bvh_params(C.Structure):
-    _fields_ = [("bins", C.c_uint32), ("max_leaf", C.c_uint32), ("lds_levels", C.c_uint32), ("width", C.c_uint32)]
+    _fields_ = [("bins", C.c_uint32), ("max_leaf", C.c_uint32), ("lds_levels", C.c_uint32), ("width", C.c_uint32),
+                ("node_format", C.c_uint32)]
 
 
 class npt_nif_desc(C.Structure):
-    _fields_ = [("n_freq", C.c_uint32), ("hidden", C.c_uint32), ("layers", C.c_uint32)]
+    _fields_ = [("n_freq", C.c_uint32), ("hidden", C.c_uint32), ("layers", C.c_uint32), ("colour", C.c_uint32)]
 
 
 class npt_train_params(C.Structure):
     _fields_ = [("batch", C.c_uint32), ("samples", C.c_uint64), ("lr", C.c_float), ("beta1", C.c_float),
                 ("beta2", C.c_float), ("eps", C.c_float), ("huber_delta", C.c_float), ("seed", C.c_uint64),
-                ("grad_prec", C.c_uint32), ("loss_scale", C.c_float)]
+                ("grad_prec", C.c_uint32), ("loss_scale", C.c_float), ("master_prec", C.c_uint32)]
 
 
 class npt_train_stats(C.Structure):
@@ -237,8 +240,8 @@ def npt_scene_materials(ctx, materials):
     _check(ctx, lib().npt_scene_materials(ctx, arr, len(materials)))
 
 
-def npt_build_bvh(ctx, bins=32, max_leaf=4, lds_levels=6, stream=None, width=0):
-    p = npt_bvh_params(bins, max_leaf, lds_levels, width)
+def npt_build_bvh(ctx, bins=32, max_leaf=4, lds_levels=6, stream=None, width=0, node_format=0):
+    p = npt_bvh_params(bins, max_leaf, lds_levels, width, node_format)
     _check(ctx, lib().npt_build_bvh(ctx, C.byref(p), _stream(stream)))
 
 
@@ -276,9 +279,9 @@ def npt_set_env_mode(ctx, mode):
 
 
 # ---------------------------------------------------------------------- NIF
-def npt_nif_upload(ctx, params, n_freq=16, hidden=96, layers=5, stream=None):
+def npt_nif_upload(ctx, params, n_freq=16, hidden=96, layers=5, stream=None, colour=0):
     p = _host(params, np.float32)
-    d = npt_nif_desc(n_freq, hidden, layers)
+    d = npt_nif_desc(n_freq, hidden, layers, colour)
     _check(ctx, lib().npt_nif_upload(ctx, C.byref(d), _hp(p), p.size, _stream(stream)))
 
 
@@ -299,8 +302,9 @@ def npt_nif_get_dequantized(ctx, n=43779):
 
 
 def train_params(batch=0, samples=0, lr=0.0, beta1=0.0, beta2=0.0, eps=0.0, huber_delta=0.0, seed=0,
-                 grad_prec=FP32, loss_scale=0.0):
-    return npt_train_params(batch, samples, lr, beta1, beta2, eps, huber_delta, seed, grad_prec, loss_scale)
+                 grad_prec=FP32, loss_scale=0.0, master_prec=FP32):
+    return npt_train_params(batch, samples, lr, beta1, beta2, eps, huber_delta, seed, grad_prec, loss_scale,
+                            master_prec)
 
 
 def npt_nif_train(ctx, params: npt_train_params = None, stream=None):
@@ -356,7 +360,7 @@ def npt_get_stats(ctx):
 
 
 # ------------------------------------------------------------ conveniences
-def npt_load_scene(ctx, scene: dict, bins=32, max_leaf=4, lds_levels=6, stream=None, width=0):
+def npt_load_scene(ctx, scene: dict, bins=32, max_leaf=4, lds_levels=6, stream=None, width=0, node_format=0):
     """Uploads a scene dict (paper_2305_20061_amd.synth layout) and builds its BVH."""
     npt_scene_materials(ctx, scene["materials"])
     if len(scene.get("tris", [])):
@@ -371,4 +375,6 @@ def npt_load_scene(ctx, scene: dict, bins=32, max_leaf=4, lds_levels=6, stream=N
     npt_set_camera(ctx, cam["eye"], cam["look_at"], cam["up"], cam["vfov_deg"])
     if scene.get("instances"):
         lds_levels = 0  # the two-level traversal reads every node from memory
-    npt_build_bvh(ctx, bins, max_leaf, lds_levels, stream, width)
+    if node_format:
+        lds_levels = 0  # FP16-extent nodes are read from memory
+    npt_build_bvh(ctx, bins, max_leaf, lds_levels, stream, width, node_format)

@@ -12,9 +12,9 @@ def torch_cuda():
     return torch
 
 
-def make_ctx(scene, env=None, lds_levels=6, max_leaf=4):
+def make_ctx(scene, env=None, lds_levels=6, max_leaf=4, node_format=0):
     ctx = npt.npt_create(0)
-    npt.npt_load_scene(ctx, scene, lds_levels=lds_levels, max_leaf=max_leaf)
+    npt.npt_load_scene(ctx, scene, lds_levels=lds_levels, max_leaf=max_leaf, node_format=node_format)
     if env is not None:
         npt.npt_env_upload(ctx, env)
     else:

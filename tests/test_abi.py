@@ -64,6 +64,7 @@ def test_host_only_validation(host_ctx):
     assert _code(npt.npt_nif_set_precision, c, npt.FP8) == "UNSUPPORTED"
     assert _code(npt.npt_nif_upload, c, np.zeros(10)) == "INVALID_ARG"
     assert _code(npt.npt_nif_upload, c, np.zeros(43779), hidden=128) == "UNSUPPORTED"
+    assert _code(npt.npt_nif_upload, c, np.zeros(43779), colour=3) == "INVALID_ARG"
     assert _code(npt.npt_env_upload, c, np.zeros((4, 8, 3))) == "NO_DEVICE"
     assert _code(npt.npt_env_upload, c, -np.ones((4, 8, 3))) == "NAN_INPUT"
     # render argument checks come before any device work
@@ -111,8 +112,28 @@ def test_bvh_params_validated(host_ctx):
     assert _code(npt.npt_build_bvh, c, bins=2) == "INVALID_ARG"
     assert _code(npt.npt_build_bvh, c, max_leaf=9) == "INVALID_ARG"
     assert _code(npt.npt_build_bvh, c, lds_levels=9) == "INVALID_ARG"
+    assert _code(npt.npt_build_bvh, c, node_format=2) == "INVALID_ARG"
+    assert _code(npt.npt_build_bvh, c, lds_levels=2, node_format=1) == "INVALID_ARG"
+    assert _code(npt.npt_build_bvh, c, lds_levels=0, width=2, node_format=1) == "INVALID_ARG"
     # material ids beyond the table (none uploaded -> one default material)
     assert _code(npt.npt_build_bvh, c) == "INVALID_ARG"
+
+
+def test_half_extent_nodes_build_and_guard_wide_boxes(host_ctx):
+    c = host_ctx
+    npt.npt_scene_materials(c, [{"type": npt.LAMBERT, "albedo": (0.5, 0.5, 0.5)}])
+    sc = synth.scene_for(3)
+    npt.npt_scene_triangles(c, sc["verts"], sc["tris"])
+    assert _code(npt.npt_build_bvh, c, lds_levels=0) == "NO_DEVICE"
+    a = npt.npt_bvh_info(c)
+    assert _code(npt.npt_build_bvh, c, lds_levels=0, node_format=npt.NODES_FP16_EXTENT) == "NO_DEVICE"
+    b = npt.npt_bvh_info(c)
+    assert a == b  # same tree, only the node encoding differs
+    # a triangle wider than the binary16 range cannot be encoded
+    v = np.array([[0, 0, 0], [1e5, 0, 0], [0, 1, 0]], np.float32)
+    npt.npt_scene_triangles(c, v, np.array([[0, 1, 2]]))
+    assert _code(npt.npt_build_bvh, c, lds_levels=0, node_format=npt.NODES_FP16_EXTENT) == "UNSUPPORTED"
+    assert _code(npt.npt_build_bvh, c, lds_levels=0) == "NO_DEVICE"
 
 
 def test_tiny_scenes_build(host_ctx):

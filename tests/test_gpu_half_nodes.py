@@ -1,0 +1,77 @@
+"""BVH4 nodes with binary16 extents (Sec. 3.1.4's FP16-extent proposal): the
+upper planes are FP32 sums lo + ext that the builder keeps >= the true
+boxes, so the traversal may visit more but never drops a primitive.  The
+closest hit is defined over all primitives (ties to the lowest id), so first
+hits match the oracle bit for bit and renders are identical to those of the
+FP32-node tree, one- and two-level."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2305_20061_amd import npt, synth
+
+from gpu_util import gpu_primary, gpu_render, make_ctx, oracle_scene, rel_rmse
+from test_gpu_instancing import check_primary, small_instanced_scene
+
+pytestmark = pytest.mark.gpu
+HALF = npt.NODES_FP16_EXTENT
+
+
+@pytest.mark.parametrize("cfg,W,H", [(0, 128, 128), (1, 96, 96), (2, 160, 120), (3, 192, 108)])
+def test_half_node_primary_hits_match_oracle(cfg, W, H):
+    scene = synth.scene_for(cfg)
+    ctx = make_ctx(scene, lds_levels=0, node_format=HALF)
+    try:
+        for sample in (0, 3):
+            gp, gi, gt, gn = gpu_primary(ctx, W, H, sample, seed=1)
+            osc, cam = oracle_scene(scene)
+            op, oi, ot, on = O.trace_primary(osc, cam, W, H, sample, 1)
+            agree = np.mean(gp == op)
+            print(f"FP16-extent nodes, cfg {cfg} sample {sample}: id agreement {agree:.6f}")
+            assert agree >= 0.9999
+            same = (gp == op) & (op != O.MISS)
+            assert np.array_equal(gt[same], ot[same])
+            assert np.array_equal(gn[same], on[same])
+    finally:
+        npt.npt_destroy(ctx)
+
+
+def test_half_node_instanced_primary_hits_match_oracle():
+    scene = small_instanced_scene()
+    ctx = make_ctx(scene, max_leaf=2, node_format=HALF)
+    try:
+        for sample in (0, 5):
+            oi = check_primary(scene, ctx, 192, 108, sample, 3)
+            assert np.any(oi > 0) and np.any(oi == 0)
+    finally:
+        npt.npt_destroy(ctx)
+
+
+@pytest.mark.parametrize("cfg", [2, 3, "instanced"])
+def test_half_node_renders_equal_fp32_node_renders(cfg, sky_map):
+    scene = small_instanced_scene() if cfg == "instanced" else synth.scene_for(cfg)
+    imgs = []
+    for fmt in (npt.NODES_FP32, HALF):
+        ctx = make_ctx(scene, env=sky_map, lds_levels=0, max_leaf=2, node_format=fmt)
+        try:
+            npt.npt_set_env_mode(ctx, npt.ENV_MAP)
+            imgs.append(gpu_render(ctx, 96, 64, 2, 6, 5))
+        finally:
+            npt.npt_destroy(ctx)
+    print(f"cfg {cfg}: FP16-extent vs FP32 nodes max |diff| {np.abs(imgs[0] - imgs[1]).max():.3e}")
+    assert np.array_equal(imgs[0], imgs[1])
+
+
+def test_half_node_env_render_matches_oracle(sky_map):
+    scene = synth.scene_for(2)
+    ctx = make_ctx(scene, env=sky_map, lds_levels=0, node_format=HALF)
+    try:
+        npt.npt_set_env_mode(ctx, npt.ENV_MAP)
+        g = gpu_render(ctx, 96, 72, 4, 8, 2)
+    finally:
+        npt.npt_destroy(ctx)
+    osc, cam = oracle_scene(scene)
+    o = O.render(osc, cam, O.render_desc(96, 72, 4, 8, 2, env=sky_map))
+    r = rel_rmse(g, o)
+    print(f"FP16-extent nodes env-map relRMSE {r:.3e}")
+    assert r <= 1e-3

@@ -85,13 +85,14 @@ def test_base_mesh_as_identity_instance_hits_the_same():
 
 
 @pytest.mark.timeout(600)
-def test_large_bvh_full_size_sampled_hits_match_oracle():
+@pytest.mark.parametrize("node_format", [npt.NODES_FP16_EXTENT, npt.NODES_FP32])
+def test_large_bvh_full_size_sampled_hits_match_oracle(node_format):
     # the large-BVH workload itself (2048^2 terrain, 256 instances, leaf size
-    # 2 as benchmarked) at 1920x1080: the GPU traces every pixel, the oracle a
-    # seeded sample of 4096 of them
+    # 2 and FP16-extent nodes as benchmarked) at 1920x1080: the GPU traces
+    # every pixel, the oracle a seeded sample of 4096 of them
     scene = synth.scene_for(4)
     W, H = 1920, 1080
-    ctx = make_ctx(scene, max_leaf=2, lds_levels=0)
+    ctx = make_ctx(scene, max_leaf=2, lds_levels=0, node_format=node_format)
     try:
         gp, gi, gt, gn = gpu_primary(ctx, W, H, 0, 1)
     finally:

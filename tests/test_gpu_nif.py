@@ -200,3 +200,93 @@ def test_fp8_weight_scales_follow_each_layer():
     a, b = outs
     assert np.array_equal(b[lo:lo + 96 * 96], a[lo:lo + 96 * 96] * 2.0 ** -7)
     assert np.array_equal(np.delete(a, np.s_[lo:lo + 96 * 96]), np.delete(b, np.s_[lo:lo + 96 * 96]))
+
+
+COLOURS = [npt.COLOUR_RGB, npt.COLOUR_YCOCG]
+assert (O.COLOUR_YUV, O.COLOUR_RGB, O.COLOUR_YCOCG) == (npt.COLOUR_YUV, npt.COLOUR_RGB, npt.COLOUR_YCOCG)
+
+
+@pytest.mark.parametrize("colour", COLOURS)
+@pytest.mark.parametrize("prec", [npt.FP32, npt.FP16, npt.FP8])
+def test_nif_query_other_colour_spaces(colour, prec):
+    # the output colour matrix (Sec. 4.3) is applied after the last layer:
+    # same bounds as the default YUV space
+    torch = torch_cuda()
+    shape = O.nif_shape(16, 96, 5, colour)
+    p = _weights()
+    p[-3:] = (0.6, 0.4, 0.5) if colour == npt.COLOUR_RGB else (0.6, 0.05, -0.05)
+    n = 4096 + 29
+    ctx = npt.npt_create(0)
+    try:
+        npt.npt_nif_upload(ctx, p, colour=colour)
+        npt.npt_nif_set_precision(ctx, prec)
+        d = _dirs(n, seed=4)
+        out = torch.full((n, 3), -1.0, dtype=torch.float32, device="cuda")
+        npt.npt_env_query(ctx, npt.ENV_NIF, torch.from_numpy(d).cuda(), out)
+        torch.cuda.synchronize()
+        g = out.cpu().numpy().astype(np.float64)
+    finally:
+        npt.npt_destroy(ctx)
+    ref_p = _dequant(p, prec)
+    o = np.array([O.nif_radiance_q(shape, ref_p, prec, *O.dir_to_uv(x)) for x in d])
+    r = rel_rmse(g, o)
+    print(f"colour {colour} prec {prec}: relRMSE {r:.3e}")
+    assert r <= QUERY_TOL[prec]
+
+
+@pytest.mark.parametrize("colour", COLOURS)
+def test_training_gradient_other_colour_spaces(colour, small_sky):
+    # the head's gradient goes back through M^T of the chosen colour matrix
+    torch = torch_cuda()
+    shape = O.nif_shape(16, 96, 5, colour)
+    p = synth.nif_init(11)
+    B, seed, step = 2048, 5, 2
+    ctx = npt.npt_create(0)
+    try:
+        npt.npt_env_upload(ctx, small_sky)
+        npt.npt_nif_upload(ctx, p, colour=colour)
+        grad = torch.zeros(43779, dtype=torch.float32, device="cuda")
+        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        npt.npt_nif_train_grad(ctx, npt.train_params(batch=B, seed=seed, grad_prec=npt.FP32), step, grad, loss)
+        torch.cuda.synchronize()
+        g = grad.cpu().numpy().astype(np.float64)
+        lg = float(loss.cpu()[0])
+    finally:
+        npt.npt_destroy(ctx)
+    uv, tg = O.nif_train_batch(small_sky, seed, step, B)
+    lo, go = O.nif_loss_grad(shape, p.astype(np.float64), uv, tg, 1e-3)
+    r = rel_rmse(g, go)
+    print(f"colour {colour} grad: relRMSE {r:.3e}, loss {lg:.6e} vs {lo:.6e}")
+    assert abs(lg - lo) <= LOSS_TOL[npt.FP32] * abs(lo)
+    assert r <= GRAD_TOL[npt.FP32]
+
+
+def test_fp16_master_adam_step_matches_oracle(small_sky):
+    # one Adam step with binary16 master weights and stochastically rounded
+    # updates (Sec. 3.2.1): every weight stays a binary16 value and takes the
+    # oracle's neighbour, except where the GPU's FP32 update and the oracle's
+    # FP64 update (rounded to FP32) fall on different sides of the decision;
+    # there the two differ by one binary16 step
+    p = synth.nif_init(13)
+    B, seed = 2048, 21
+    ctx = npt.npt_create(0)
+    try:
+        npt.npt_env_upload(ctx, small_sky)
+        npt.npt_nif_upload(ctx, p)
+        st = npt.npt_nif_train(ctx, npt.train_params(batch=B, samples=B, seed=seed, grad_prec=npt.FP32,
+                                                     master_prec=npt.FP16))
+        q = npt.npt_nif_download(ctx).astype(np.float64)
+    finally:
+        npt.npt_destroy(ctx)
+    ref = p.astype(np.float64).copy()
+    m, v = np.zeros_like(ref), np.zeros_like(ref)
+    lo = O.nif_train_step(SHAPE, ref, m, v, small_sky, seed, 0, B, fp16_master=True)
+    assert st["steps"] == 1 and abs(st["first_loss"] - lo) <= 1e-4 * lo
+    assert np.array_equal(q.astype(np.float16).astype(np.float64), q)
+    same = q == ref
+    print(f"FP16 master: {same.mean():.6f} of weights identical, {np.count_nonzero(~same)} differ")
+    assert same.mean() >= 0.999
+    qh, rh = q[~same].astype(np.float16), ref[~same].astype(np.float16)
+    assert np.array_equal(np.nextafter(qh, rh), rh)
+    # the update really moved the weights (not a rounding back to the start)
+    assert np.mean(q != np.float16(p).astype(np.float64)) > 0.5

@@ -64,13 +64,29 @@ def test_yuv_matrix_inverts_bt601():
     assert np.allclose(M @ [1, 0, 0], [1, 1, 1])  # pure luma is grey
 
 
-def test_zero_network_outputs_folded_bias():
-    p = np.zeros(O.nif_param_count(SHAPE))
+def test_ycocg_matrix_inverts_the_forward_transform():
+    # YCoCg (Malvar & Sullivan 2003): Y = R/4 + G/2 + B/4, Co = (R - B)/2,
+    # Cg = -R/4 + G/2 - B/4; every coefficient is dyadic, so M F = I exactly
+    F = np.array([[0.25, 0.5, 0.25], [0.5, 0.0, -0.5], [-0.25, 0.5, -0.25]])
+    M = O.colour_to_rgb_matrix(O.COLOUR_YCOCG)
+    assert np.array_equal(M @ F, np.eye(3))
+    assert np.array_equal(M @ [1, 0, 0], [1, 1, 1])  # pure luma is grey
+
+
+def test_colour_matrix_selection():
+    assert np.array_equal(O.colour_to_rgb_matrix(O.COLOUR_RGB), np.eye(3))
+    assert np.array_equal(O.colour_to_rgb_matrix(O.COLOUR_YUV), O.yuv_to_rgb_matrix())
+
+
+@pytest.mark.parametrize("colour", [O.COLOUR_YUV, O.COLOUR_RGB, O.COLOUR_YCOCG])
+def test_zero_network_outputs_folded_bias(colour):
+    shape = O.nif_shape(16, 96, 5, colour)
+    p = np.zeros(O.nif_param_count(shape))
     b = np.array([0.3, -0.2, 0.1])
     p[-3:] = b
-    z = O.nif_forward(SHAPE, p, 0.37, 0.61)
-    assert np.allclose(z, O.yuv_to_rgb_matrix() @ b, atol=1e-15)
-    rad = O.nif_radiance(SHAPE, p, 0.37, 0.61)
+    z = O.nif_forward(shape, p, 0.37, 0.61)
+    assert np.allclose(z, O.colour_to_rgb_matrix(colour) @ b, atol=1e-15)
+    rad = O.nif_radiance(shape, p, 0.37, 0.61)
     assert np.allclose(rad, np.maximum(0, np.expm1(z)), atol=1e-15)
 
 
@@ -124,7 +140,9 @@ def test_huber_closed_form():
         assert abs(fd - O.huber_grad(e, d)) < 1e-6
 
 
-def test_backward_matches_central_differences():
+@pytest.mark.parametrize("colour", [O.COLOUR_YUV, O.COLOUR_RGB, O.COLOUR_YCOCG])
+def test_backward_matches_central_differences(colour):
+    SHAPE = O.nif_shape(16, 96, 5, colour)
     rng = np.random.default_rng(1)
     p = synth.nif_init(9).astype(np.float64)
     p += rng.normal(size=p.size) * 0.01  # non-zero biases
@@ -135,7 +153,10 @@ def test_backward_matches_central_differences():
     delta = 1e3
     loss, g = O.nif_loss_grad(SHAPE, p, uv, target, delta)
     idx = np.concatenate([rng.choice(p.size, 300, replace=False), np.arange(p.size - 291, p.size)])
-    h = 1e-6
+    # step 1e-5: the roundoff of the loss difference (~eps * loss / h) stays
+    # below 1e-6 relative for the smallest gradients sampled, the truncation
+    # (~h^2) far below that
+    h = 1e-5
     worst = 0.0
     for i in idx:
         pp, pm = p.copy(), p.copy()
@@ -147,16 +168,20 @@ def test_backward_matches_central_differences():
     assert worst < 1e-5, worst
 
 
-def test_backward_linear_region_huber():
+@pytest.mark.parametrize("colour", [O.COLOUR_YUV, O.COLOUR_RGB, O.COLOUR_YCOCG])
+def test_backward_linear_region_huber(colour):
     # with errors far beyond delta the gradient w.r.t. the last bias is
     # M^T sign(e) delta / (3n), independent of the network
+    SHAPE = O.nif_shape(16, 96, 5, colour)
     rng = np.random.default_rng(2)
     p = synth.nif_init(4).astype(np.float64)
     n = 5
     uv = rng.random((n, 2))
     target = np.full((n, 3), 50.0)  # far above any output: e < 0 everywhere
     _, g = O.nif_loss_grad(SHAPE, p, uv, target, 1e-3)
-    M = O.yuv_to_rgb_matrix()
+    M = {O.COLOUR_YUV: np.array([[1, 0, 1.13983], [1, -0.39465, -0.58060], [1, 2.03211, 0]]),
+         O.COLOUR_RGB: np.eye(3),
+         O.COLOUR_YCOCG: np.array([[1, 1, -1], [1, 0, 1], [1, -1, -1]])}[colour]
     expect = M.T @ np.full(3, -1e-3 / 3)
     assert np.allclose(g[-3:], expect, atol=1e-15)
 
