@@ -75,6 +75,8 @@ def _parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--node-format", choices=("fp32", "fp16-extent"), default="fp16-extent",
                    help="BVH4 node encoding: FP32 boxes (112 B) or FP32 lower planes + binary16 extents (96 B)")
+    p.add_argument("--nif-sizes", action="store_true",
+                   help="instead of the headline run: NIF model size against path rate and PSNR (one JSON line)")
     p.add_argument("--nif-study", action="store_true",
                    help="instead of the headline run: the NIF output colour-space comparison (one JSON line)")
     p.add_argument("--spp-sweep", action="store_true",
@@ -383,6 +385,75 @@ def nif_study(args):
                                     "grid": f"{w}x{h} texel centres"}, "data": "synthetic"}))
 
 
+NIF_SIZES = [(64, 2), (96, 5), (256, 4), (1024, 8)]
+
+
+def nif_sizes(args):
+    """Model size against path rate and PSNR (Sec. 4.6): the spheres scene
+    (1024x1024, 16 spp, depth 8) lit by NIFs of several sizes, each trained
+    on the device (2^24 samples, batch 65,536, FP16 GEMMs) and run with FP16
+    operands on the layer-serial GEMM path (the 96 x 5 network also on the
+    LDS-resident kernel).  Reported per size: parameters, FLOP per query,
+    training time, log-domain PSNRs against the map (FP32 inference), path
+    samples/s, NIF time and TFLOP/s per render, and the image relRMSE
+    against the env-map render at equal seeds."""
+    import torch
+
+    from paper_2305_20061_amd import npt, synth
+
+    torch.cuda.set_device(0)
+    env = synth.env_map()
+    h, w = env.shape[:2]
+    ph = 2 * np.pi * (np.arange(w) + 0.5) / w - np.pi
+    th = np.pi * (np.arange(h) + 0.5) / h
+    dirs = np.stack([np.sin(th)[:, None] * np.cos(ph)[None, :], np.cos(th)[:, None] * np.ones(w)[None, :],
+                     np.sin(th)[:, None] * np.sin(ph)[None, :]], -1).reshape(-1, 3).astype(np.float32)
+    ref = env.reshape(-1, 3).astype(np.float64)
+    d_dirs = torch.from_numpy(dirs).cuda()
+    q = torch.empty(dirs.shape[0], 3, dtype=torch.float32, device="cuda")
+    W = H = 1024
+    spp, depth = 16, 8
+    out = torch.empty(H, W, 3, dtype=torch.float32, device="cuda")
+    ctx = npt.npt_create(0)
+    rows = []
+    try:
+        npt.npt_load_scene(ctx, synth.scene_for(2), max_leaf=2, lds_levels=0, width=4)
+        npt.npt_env_upload(ctx, env)
+        npt.npt_set_env_mode(ctx, npt.ENV_MAP)
+        npt.npt_render(ctx, W, H, spp, depth, 1, out)
+        torch.cuda.synchronize()
+        img_map = out.cpu().numpy().astype(np.float64)
+        runs = [(hd, ly, 1) for hd, ly in NIF_SIZES] + [(96, 5, 0)]
+        for hidden, layers, layered in runs:
+            npt.npt_nif_set_precision(ctx, npt.FP16)
+            npt.npt_nif_upload(ctx, synth.nif_init(3, 16, hidden, layers), hidden=hidden, layers=layers,
+                               layered=layered)
+            tr = npt.npt_nif_train(ctx, npt.train_params(batch=65536, samples=args.train_samples, seed=1,
+                                                         grad_prec=npt.FP16))
+            npt.npt_nif_set_precision(ctx, npt.FP32)
+            npt.npt_env_query(ctx, npt.ENV_NIF, d_dirs, q)
+            torch.cuda.synchronize()
+            psnr = _psnr_log(q.cpu().numpy().astype(np.float64), ref)
+            npt.npt_nif_set_precision(ctx, npt.FP16)
+            npt.npt_set_env_mode(ctx, npt.ENV_NIF)
+            npt.npt_set_render_options(ctx, rr_start=3, kernel_timing=1)
+            el, st = _timed_renders(npt, torch, ctx, W, H, spp, depth, 1, out, 2, 1)
+            npt.npt_set_render_options(ctx, rr_start=3)
+            flop = 2 * (64 * hidden + (layers - 1) * hidden * hidden + 3 * hidden)
+            rows.append({"hidden": hidden, "layers": layers, "path": "layered GEMMs" if layered else "LDS-resident",
+                         "params": npt.nif_param_count(hidden, layers), "flop_per_query": flop,
+                         "train_ms": tr["ms"], "last_loss": tr["last_loss"], **psnr,
+                         "path_samples_per_s": W * H * spp * 2 / el, "nif_ms_per_render": st["ms_env"],
+                         "nif_tflops": st["env_queries"] * flop / (st["ms_env"] * 1e-3) / 1e12,
+                         "image_rel_rmse_vs_env_map": _rel(out.cpu().numpy().astype(np.float64), img_map)})
+            npt.npt_set_env_mode(ctx, npt.ENV_MAP)
+            print(json.dumps(rows[-1]), flush=True)
+    finally:
+        npt.npt_destroy(ctx)
+    print(json.dumps({"nif_sizes": rows, "render": f"spheres {W}x{H}, {spp} spp, depth {depth}, seed 1, FP16 NIF",
+                      "train_samples": args.train_samples, "data": "synthetic"}))
+
+
 def main():
     args = _parse()
     if args.gpus != 1:
@@ -393,6 +464,8 @@ def main():
         return spp_sweep(args)
     if args.nif_study:
         return nif_study(args)
+    if args.nif_sizes:
+        return nif_sizes(args)
     import torch
 
     from paper_2305_20061_amd import npt, synth

@@ -94,7 +94,10 @@ typedef struct {
 
 /* HDR-NIF shape (Sec. 3.2): 4*n_freq Fourier features -> layers x
  * [dense hidden + ReLU] -> dense 3 -> fixed colour matrix to log-space RGB.
- * Supported: n_freq = 16, hidden = 96, layers = 5.  colour: the space the
+ * Supported: n_freq = 16; hidden 32..1024, a multiple of 32; layers 1..8.
+ * The 16/96/5 network runs on the LDS-resident MFMA kernel (FP32, FP16,
+ * BF16, FP8); every other shape, or layered = 1, on layer-serial MFMA GEMMs
+ * (FP32, FP16, BF16; Sec. 4.6 sweeps model sizes).  colour: the space the
  * network's three outputs live in (Sec. 4.3 compares them):
  * NPT_COLOUR_YUV (default; BT.601 analogue, R = Y + 1.13983 V,
  * G = Y - 0.39465 U - 0.58060 V, B = Y + 2.03211 U), NPT_COLOUR_RGB
@@ -108,6 +111,7 @@ typedef struct {
     uint32_t hidden;
     uint32_t layers;
     uint32_t colour;
+    uint32_t layered;
 } npt_nif_desc;
 
 /* NIF training (Sec. 3.2.1): uniform (u,v) samples of the uploaded map,
@@ -233,8 +237,8 @@ int npt_env_upload(npt_ctx *ctx, const float *rgb, uint32_t w, uint32_t h, void 
 int npt_set_env_mode(npt_ctx *ctx, int mode);
 
 /* ---- HDR-NIF (Sec. 3.2) ----------------------------------------------------- */
-/* params_fp32: [W1, b1, ..., W6, b6], W row-major [out][in], n values
- * (43,779 for 16/96/5).  Becomes the FP32 master copy; Adam state is reset;
+/* params_fp32: [W1, b1, ..., W_{L+1}, b_{L+1}], W row-major [out][in], n
+ * values (43,779 for 16/96/5; 64 H + H + (L - 1)(H^2 + H) + 3 H + 3).  Becomes the FP32 master copy; Adam state is reset;
  * the inference pack of the current precision is rebuilt; desc->colour
  * selects the output colour space (NPT_E_INVALID_ARG if unknown). */
 int npt_nif_upload(npt_ctx *ctx, const npt_nif_desc *desc, const float *params_fp32,

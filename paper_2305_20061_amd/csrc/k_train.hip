@@ -3,6 +3,7 @@
 // fixed order (deterministic), Adam on FP32 master weights, grid evaluation.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -126,24 +127,24 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
 // output layer, colour matrix, Huber loss and the per-sample gradient
 // ---------------------------------------------------------------------------
 template <int P>
-__global__ __launch_bounds__(256) void k_train_head(const float* master, const typename Prec<P>::Elem* H5,
+__global__ __launch_bounds__(256) void k_train_head(const float* wout, int H, const typename Prec<P>::Elem* HL,
                                                    const float* target, float delta, float scale, uint32_t B,
                                                    ColourMatrix cm, float* dy_out, typename Prec<P>::Elem* dP,
                                                    float* loss_part) {
-  __shared__ float w6[kOut * kHidden + kOut];
+  extern __shared__ float w6[];  // output layer W [3][H], then b [3]
   __shared__ float red[256];
-  for (int i = threadIdx.x; i < kOut * kHidden + kOut; i += blockDim.x) w6[i] = master[w_offset(kLayers) + i];
+  for (int i = threadIdx.x; i < kOut * H + kOut; i += blockDim.x) w6[i] = wout[i];
   __syncthreads();
   const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
   float loss = 0.0f;
   if (b < B) {
-    const typename Prec<P>::Elem* h = H5 + (size_t)b * kHidden;
-    float y0 = w6[3 * kHidden], y1 = w6[3 * kHidden + 1], y2 = w6[3 * kHidden + 2];
-    for (int i = 0; i < kHidden; ++i) {
+    const typename Prec<P>::Elem* h = HL + (size_t)b * H;
+    float y0 = w6[3 * H], y1 = w6[3 * H + 1], y2 = w6[3 * H + 2];
+    for (int i = 0; i < H; ++i) {
       const float hv = (float)h[i];
       y0 += w6[i] * hv;
-      y1 += w6[kHidden + i] * hv;
-      y2 += w6[2 * kHidden + i] * hv;
+      y1 += w6[H + i] * hv;
+      y2 += w6[2 * H + i] * hv;
     }
     // the fixed colour matrix, in log space
     const float* m = cm.m;
@@ -164,9 +165,9 @@ __global__ __launch_bounds__(256) void k_train_head(const float* master, const t
     dy_out[3 * (size_t)b] = d0;
     dy_out[3 * (size_t)b + 1] = d1;
     dy_out[3 * (size_t)b + 2] = d2;
-    typename Prec<P>::Elem* dp = dP + (size_t)b * kHidden;
-    for (int i = 0; i < kHidden; ++i) {
-      const float gv = (d0 * w6[i] + d1 * w6[kHidden + i]) + d2 * w6[2 * kHidden + i];
+    typename Prec<P>::Elem* dp = dP + (size_t)b * H;
+    for (int i = 0; i < H; ++i) {
+      const float gv = (d0 * w6[i] + d1 * w6[H + i]) + d2 * w6[2 * H + i];
       dp[i] = Prec<P>::cvt((float)h[i] > 0.0f ? gv : 0.0f);
     }
   }
@@ -185,53 +186,55 @@ __global__ __launch_bounds__(256) void k_train_head(const float* master, const t
 // separate workgroups into sub[run][j], then the runs of each kChunk-row
 // chunk, in order, into the chunk's partial sums.
 constexpr int kRun = 64;
-constexpr int kHeadGrads = kOut * kHidden + kOut;  // output-layer W and b, contiguous
 
-// output layer: dW = dy^T H5 and db = column sums of dy over one run
+// output layer: dW = dy^T HL and db = column sums of dy over one run
+// (blockIdx.x: run; blockIdx.y: 320-wide slice of the 3 H + 3 gradients)
 template <int P>
-__global__ __launch_bounds__(320) void k_head_grad_runs(const float* dy, const typename Prec<P>::Elem* H5,
+__global__ __launch_bounds__(320) void k_head_grad_runs(const float* dy, const typename Prec<P>::Elem* HL, int H,
                                                        float* sub) {
-  const int j = threadIdx.x;
+  const int heads = kOut * H + kOut;
+  const int j = blockIdx.y * 320 + threadIdx.x;
   const uint32_t b0 = blockIdx.x * kRun;
   float s = 0.0f;
-  if (j < kOut * kHidden) {
-    const int c = j / kHidden, i = j % kHidden;
-    for (uint32_t b = b0; b < b0 + kRun; ++b) s += dy[3 * (size_t)b + c] * (float)H5[(size_t)b * kHidden + i];
-  } else if (j < kHeadGrads) {
-    const int c = j - kOut * kHidden;
+  if (j < kOut * H) {
+    const int c = j / H, i = j % H;
+    for (uint32_t b = b0; b < b0 + kRun; ++b) s += dy[3 * (size_t)b + c] * (float)HL[(size_t)b * H + i];
+  } else if (j < heads) {
+    const int c = j - kOut * H;
     for (uint32_t b = b0; b < b0 + kRun; ++b) s += dy[3 * (size_t)b + c];
   }
-  if (j < kHeadGrads) sub[(size_t)blockIdx.x * kHeadGrads + j] = s;
+  if (j < heads) sub[(size_t)blockIdx.x * heads + j] = s;
 }
 
 // hidden-layer bias gradient: column sums of dP over one run
 template <int P>
-__global__ __launch_bounds__(128) void k_colsum_runs(const typename Prec<P>::Elem* dP, float* sub) {
-  const int i = threadIdx.x;
-  if (i >= kHidden) return;
+__global__ __launch_bounds__(128) void k_colsum_runs(const typename Prec<P>::Elem* dP, int H, float* sub) {
+  const int i = blockIdx.y * 128 + threadIdx.x;
+  if (i >= H) return;
   const uint32_t b0 = blockIdx.x * kRun;
   float s = 0.0f;
-  for (uint32_t b = b0; b < b0 + kRun; ++b) s += (float)dP[(size_t)b * kHidden + i];
-  sub[(size_t)blockIdx.x * kHidden + i] = s;
+  for (uint32_t b = b0; b < b0 + kRun; ++b) s += (float)dP[(size_t)b * H + i];
+  sub[(size_t)blockIdx.x * H + i] = s;
 }
 
 // the runs of each chunk, in run order, into partial[chunk][off + j]
-__global__ __launch_bounds__(320) void k_chunk_sums(const float* sub, int width, float* partial, int off) {
-  const int j = threadIdx.x;
+__global__ __launch_bounds__(320) void k_chunk_sums(const float* sub, int width, float* partial, int64_t off,
+                                                   int64_t np) {
+  const int j = blockIdx.y * blockDim.x + threadIdx.x;
   if (j >= width) return;
   constexpr int kRuns = kChunk / kRun;
   float s = 0.0f;
   for (int r = 0; r < kRuns; ++r) s += sub[((size_t)blockIdx.x * kRuns + r) * width + j];
-  partial[(size_t)blockIdx.x * kParams + off + j] = s;
+  partial[(size_t)blockIdx.x * np + off + j] = s;
 }
 
 // gradient = (sum of chunk partials in chunk order) * scale; loss of the step
 __global__ __launch_bounds__(256) void k_reduce_grad(const float* partial, int splits, float scale, float* grad,
                                                     const float* loss_part, int nloss, float loss_scale,
-                                                    float* loss_out) {
-  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < kParams; j += gridDim.x * blockDim.x) {
+                                                    float* loss_out, int64_t np) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < np; j += (int64_t)gridDim.x * blockDim.x) {
     float s = 0.0f;
-    for (int k = 0; k < splits; ++k) s += partial[(size_t)k * kParams + j];
+    for (int k = 0; k < splits; ++k) s += partial[(size_t)k * np + j];
     grad[j] = s * scale;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0 && loss_out) {
@@ -265,8 +268,8 @@ __device__ __forceinline__ float fp16_stochastic(float x, float u) {
 template <int P, bool kSR>
 __global__ __launch_bounds__(256) void k_adam(float* w, float* m, float* v, const float* g, float lr, float b1,
                                              float b2, float eps, float c1, float c2, uint32_t t, uint32_t key0,
-                                             uint32_t key1, typename Prec<P>::Elem* wp) {
-  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < kParams; j += gridDim.x * blockDim.x) {
+                                             uint32_t key1, typename Prec<P>::Elem* wp, int64_t np) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < np; j += (int64_t)gridDim.x * blockDim.x) {
     const float gj = g[j];
     const float mj = b1 * m[j] + (1.0f - b1) * gj;
     const float vj = b2 * v[j] + (1.0f - b2) * gj * gj;
@@ -283,8 +286,8 @@ __global__ __launch_bounds__(256) void k_adam(float* w, float* m, float* v, cons
 // operand-precision copy of the master weights; kFp16Master first rounds the
 // master itself to the nearest binary16
 template <int P, bool kFp16Master>
-__global__ __launch_bounds__(256) void k_convert(float* w, typename Prec<P>::Elem* wp) {
-  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < kParams; j += gridDim.x * blockDim.x) {
+__global__ __launch_bounds__(256) void k_convert(float* w, typename Prec<P>::Elem* wp, int64_t np) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < np; j += (int64_t)gridDim.x * blockDim.x) {
     float x = w[j];
     if (kFp16Master) {
       x = (float)(_Float16)x;
@@ -335,44 +338,41 @@ void TrainScratch::release() {
     if (p) (void)hipFree(p);
   act = dp = wp = nullptr;
   target = dy = partial = sub = grad = loss_part = loss = zgrid = err_part = nullptr;
-  batch_cap = elem_bytes = steps_cap = 0;
+  for (size_t& b : bytes) b = 0;
   grid_cap = 0;
 }
 
 static uint32_t elem_size(int prec) { return prec == NPT_FP32 ? 4u : 2u; }
 
-static hipError_t ensure_scratch(TrainScratch& s, uint32_t B, int prec, uint32_t steps) {
-  const uint32_t es = elem_size(prec);
-  if (B > s.batch_cap || es > s.elem_bytes || steps > s.steps_cap) {
-    const uint32_t nb = std::max(B, s.batch_cap), ne = std::max(es, s.elem_bytes);
-    const uint32_t ns = std::max(std::max(steps, s.steps_cap), 1u);
-    const uint64_t zc = s.grid_cap;
-    float* zg = s.zgrid;
-    float* ep = s.err_part;
-    s.zgrid = nullptr;
-    s.err_part = nullptr;
-    s.release();
-    s.zgrid = zg;
-    s.err_part = ep;
-    s.grid_cap = zc;
-    hipError_t e;
-    const size_t acts = (size_t)nb * (kFeat + kLayers * kHidden);
-    if ((e = hipMalloc(&s.act, acts * ne)) != hipSuccess) return e;
-    if ((e = hipMalloc(&s.dp, (size_t)2 * nb * kHidden * ne)) != hipSuccess) return e;
-    if ((e = hipMalloc(&s.wp, (size_t)kParams * 4)) != hipSuccess) return e;
-    if ((e = hipMalloc((void**)&s.target, (size_t)nb * 3 * 4)) != hipSuccess) return e;
-    if ((e = hipMalloc((void**)&s.dy, (size_t)nb * 3 * 4)) != hipSuccess) return e;
-    if ((e = hipMalloc((void**)&s.partial, (size_t)(nb / kChunk + 1) * kParams * 4)) != hipSuccess) return e;
-    if ((e = hipMalloc((void**)&s.sub, (size_t)(nb / kRun + 1) * kHeadGrads * 4)) != hipSuccess) return e;
-    if ((e = hipMalloc((void**)&s.grad, (size_t)kParams * 4)) != hipSuccess) return e;
-    if ((e = hipMalloc((void**)&s.loss_part, (size_t)(nb / 256 + 1) * 4)) != hipSuccess) return e;
-    if ((e = hipMalloc((void**)&s.loss, (size_t)ns * 4)) != hipSuccess) return e;
-    s.batch_cap = nb;
-    s.elem_bytes = ne;
-    s.steps_cap = ns;
+// grows each scratch buffer to what a step of batch B, operand precision
+// prec and shape sh needs (and the per-step loss record to `steps`)
+static hipError_t ensure_scratch(TrainScratch& s, uint32_t B, int prec, uint32_t steps, const NifShape& sh) {
+  const size_t es = elem_size(prec), np = (size_t)shape_params(sh), H = (size_t)sh.hidden;
+  const size_t need[10] = {(size_t)B * (64 + (size_t)sh.layers * H) * es,
+                           2 * (size_t)B * H * es,
+                           np * 4,
+                           (size_t)B * 3 * 4,
+                           (size_t)B * 3 * 4,
+                           ((size_t)B / kChunk + 1) * np * 4,
+                           ((size_t)B / kRun + 1) * (3 * H + 3) * 4,
+                           np * 4,
+                           ((size_t)B / 256 + 1) * 4,
+                           (size_t)std::max(steps, 1u) * 4};
+  void** ptr[10] = {&s.act, &s.dp, &s.wp, (void**)&s.target, (void**)&s.dy, (void**)&s.partial, (void**)&s.sub,
+                    (void**)&s.grad, (void**)&s.loss_part, (void**)&s.loss};
+  for (int i = 0; i < 10; ++i) {
+    if (need[i] <= s.bytes[i]) continue;
+    if (*ptr[i]) (void)hipFree(*ptr[i]);
+    *ptr[i] = nullptr;
+    s.bytes[i] = 0;
+    hipError_t e = hipMalloc(ptr[i], need[i]);
+    if (e != hipSuccess) return e;
+    s.bytes[i] = need[i];
   }
   return hipSuccess;
 }
+
+static int grid_for_params(int64_t np) { return (int)std::min<int64_t>(4096, (np + 255) / 256); }
 
 template <int P, bool AK, bool BK>
 static hipError_t gemm(const GemmDesc& g, hipStream_t st) {
@@ -387,95 +387,103 @@ template <int P>
 static hipError_t step_gradient(TrainScratch& s, const TrainConfig& c, const TrainTargets& t, uint32_t step,
                                 float* grad_out, float* loss_out, hipStream_t st) {
   using Elem = typename Prec<P>::Elem;
+  const NifShape& sh = c.shape;
+  const int H = sh.hidden, L = sh.layers;
+  const int64_t np = shape_params(sh);
   const uint32_t B = c.batch;
   Elem* act = static_cast<Elem*>(s.act);
-  Elem* acts[kLayers + 1];
+  std::vector<Elem*> acts(L + 1);
   acts[0] = act;
-  for (int l = 1; l <= kLayers; ++l) acts[l] = act + (size_t)B * kFeat + (size_t)(l - 1) * B * kHidden;
-  Elem* dp[2] = {static_cast<Elem*>(s.dp), static_cast<Elem*>(s.dp) + (size_t)B * kHidden};
+  for (int l = 1; l <= L; ++l) acts[l] = act + (size_t)B * 64 + (size_t)(l - 1) * B * H;
+  Elem* dp[2] = {static_cast<Elem*>(s.dp), static_cast<Elem*>(s.dp) + (size_t)B * H};
   const Elem* wp = static_cast<const Elem*>(s.wp);
   hipError_t e;
   hipLaunchKernelGGL(k_train_sample<P>, dim3((B + 255) / 256), dim3(256), 0, st, t, (uint32_t)c.seed,
                      (uint32_t)(c.seed >> 32), step, B, acts[0], s.target);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  for (int l = 0; l < kLayers; ++l) {
+  for (int l = 0; l < L; ++l) {
     GemmDesc g{};
     g.A = acts[l];
-    g.a_sm = layer_in(l);
+    g.a_sm = shape_in(sh, l);
     g.a_sk = 1;
-    g.B = wp + w_offset(l);
+    g.B = wp + shape_w_offset(sh, l);
     g.b_sk = 1;
-    g.b_sn = layer_in(l);
+    g.b_sn = shape_in(sh, l);
     g.M = (int)B;
-    g.N = kHidden;
-    g.K = layer_in(l);
+    g.N = H;
+    g.K = shape_in(sh, l);
     g.k_chunk = g.K;
     g.splits = 1;
     g.mode = 0;
-    g.bias = t.master + b_offset(l);
+    g.bias = t.master + shape_b_offset(sh, l);
     g.C = acts[l + 1];
-    g.ldc = kHidden;
+    g.ldc = H;
     if ((e = gemm<P, true, true>(g, st)) != hipSuccess) return e;
   }
   const int nblk = (int)((B + 255) / 256);
-  hipLaunchKernelGGL(k_train_head<P>, dim3(nblk), dim3(256), 0, st, t.master, acts[kLayers], s.target, c.delta,
-                     c.loss_scale, B, c.cm, s.dy, dp[0], s.loss_part);
+  hipLaunchKernelGGL(k_train_head<P>, dim3(nblk), dim3(256), (size_t)(kOut * H + kOut) * sizeof(float), st,
+                     t.master + shape_w_offset(sh, L), H, acts[L], s.target, c.delta, c.loss_scale, B, c.cm, s.dy,
+                     dp[0], s.loss_part);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int splits = (int)(B / kChunk);
   const int runs = (int)(B / kRun);
-  hipLaunchKernelGGL(k_head_grad_runs<P>, dim3(runs), dim3(320), 0, st, s.dy, acts[kLayers], s.sub);
+  const int heads = kOut * H + kOut;
+  hipLaunchKernelGGL(k_head_grad_runs<P>, dim3(runs, (heads + 319) / 320), dim3(320), 0, st, s.dy, acts[L], H,
+                     s.sub);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_chunk_sums, dim3(splits), dim3(320), 0, st, s.sub, kHeadGrads, s.partial, w_offset(kLayers));
+  hipLaunchKernelGGL(k_chunk_sums, dim3(splits, (heads + 319) / 320), dim3(320), 0, st, s.sub, heads, s.partial,
+                     shape_w_offset(sh, L), np);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   int cur = 0;
-  for (int l = kLayers - 1; l >= 0; --l) {
+  for (int l = L - 1; l >= 0; --l) {
     // dW_l = dP_l^T act_l, split over batch chunks
     GemmDesc g{};
     g.A = dp[cur];
     g.a_sm = 1;
-    g.a_sk = kHidden;
+    g.a_sk = H;
     g.B = acts[l];
-    g.b_sk = layer_in(l);
+    g.b_sk = shape_in(sh, l);
     g.b_sn = 1;
-    g.M = kHidden;
-    g.N = layer_in(l);
+    g.M = H;
+    g.N = shape_in(sh, l);
     g.K = (int)B;
     g.k_chunk = kChunk;
     g.splits = splits;
     g.mode = 2;
-    g.C = s.partial + w_offset(l);
-    g.ldc = layer_in(l);
-    g.c_split_stride = kParams;
+    g.C = s.partial + shape_w_offset(sh, l);
+    g.ldc = shape_in(sh, l);
+    g.c_split_stride = np;
     if ((e = gemm<P, false, false>(g, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_colsum_runs<P>, dim3(runs), dim3(128), 0, st, dp[cur], s.sub);
+    hipLaunchKernelGGL(k_colsum_runs<P>, dim3(runs, (H + 127) / 128), dim3(128), 0, st, dp[cur], H, s.sub);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_chunk_sums, dim3(splits), dim3(128), 0, st, s.sub, kHidden, s.partial, b_offset(l));
+    hipLaunchKernelGGL(k_chunk_sums, dim3(splits, (H + 127) / 128), dim3(128), 0, st, s.sub, H, s.partial,
+                       shape_b_offset(sh, l), np);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (l == 0) break;
     // dP_{l-1} = (dP_l W_l) masked by act_l > 0
     GemmDesc d{};
     d.A = dp[cur];
-    d.a_sm = kHidden;
+    d.a_sm = H;
     d.a_sk = 1;
-    d.B = wp + w_offset(l);
-    d.b_sk = layer_in(l);
+    d.B = wp + shape_w_offset(sh, l);
+    d.b_sk = shape_in(sh, l);
     d.b_sn = 1;
     d.M = (int)B;
-    d.N = layer_in(l);
-    d.K = kHidden;
-    d.k_chunk = kHidden;
+    d.N = shape_in(sh, l);
+    d.K = H;
+    d.k_chunk = H;
     d.splits = 1;
     d.mode = 1;
     d.mask = acts[l];
-    d.mask_ld = kHidden;
+    d.mask_ld = H;
     d.C = dp[cur ^ 1];
-    d.ldc = kHidden;
+    d.ldc = H;
     if ((e = gemm<P, true, false>(d, st)) != hipSuccess) return e;
     cur ^= 1;
   }
   const float scale = 1.0f / (3.0f * (float)B * c.loss_scale);
-  hipLaunchKernelGGL(k_reduce_grad, dim3(64), dim3(256), 0, st, s.partial, splits, scale, grad_out, s.loss_part,
-                     nblk, 1.0f / (3.0f * (float)B), loss_out);
+  hipLaunchKernelGGL(k_reduce_grad, dim3(grid_for_params(np)), dim3(256), 0, st, s.partial, splits, scale, grad_out,
+                     s.loss_part, nblk, 1.0f / (3.0f * (float)B), loss_out, np);
   return hipGetLastError();
 }
 
@@ -483,11 +491,13 @@ template <int P>
 static hipError_t run_p(TrainScratch& s, const TrainConfig& c, const TrainTargets& t, uint32_t step0,
                         uint32_t steps, bool update, float* grad_out, float* loss_out, hipStream_t st) {
   using Elem = typename Prec<P>::Elem;
+  const int64_t np = shape_params(c.shape);
+  const int pg = grid_for_params(np);
   const bool fp16_master = update && c.master_prec == NPT_FP16;
   if (fp16_master)
-    hipLaunchKernelGGL((k_convert<P, true>), dim3(64), dim3(256), 0, st, t.master, static_cast<Elem*>(s.wp));
+    hipLaunchKernelGGL((k_convert<P, true>), dim3(pg), dim3(256), 0, st, t.master, static_cast<Elem*>(s.wp), np);
   else
-    hipLaunchKernelGGL((k_convert<P, false>), dim3(64), dim3(256), 0, st, t.master, static_cast<Elem*>(s.wp));
+    hipLaunchKernelGGL((k_convert<P, false>), dim3(pg), dim3(256), 0, st, t.master, static_cast<Elem*>(s.wp), np);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   for (uint32_t i = 0; i < steps; ++i) {
@@ -500,11 +510,11 @@ static hipError_t run_p(TrainScratch& s, const TrainConfig& c, const TrainTarget
     const float c2 = (float)(1.0 - std::pow((double)c.beta2, tt));
     const uint32_t k0 = (uint32_t)c.seed, k1 = (uint32_t)(c.seed >> 32), tt1 = step + 1;
     if (fp16_master)
-      hipLaunchKernelGGL((k_adam<P, true>), dim3(64), dim3(256), 0, st, t.master, t.m, t.v, s.grad, c.lr, c.beta1,
-                         c.beta2, c.eps, c1, c2, tt1, k0, k1, static_cast<Elem*>(s.wp));
+      hipLaunchKernelGGL((k_adam<P, true>), dim3(pg), dim3(256), 0, st, t.master, t.m, t.v, s.grad, c.lr, c.beta1,
+                         c.beta2, c.eps, c1, c2, tt1, k0, k1, static_cast<Elem*>(s.wp), np);
     else
-      hipLaunchKernelGGL((k_adam<P, false>), dim3(64), dim3(256), 0, st, t.master, t.m, t.v, s.grad, c.lr, c.beta1,
-                         c.beta2, c.eps, c1, c2, tt1, k0, k1, static_cast<Elem*>(s.wp));
+      hipLaunchKernelGGL((k_adam<P, false>), dim3(pg), dim3(256), 0, st, t.master, t.m, t.v, s.grad, c.lr, c.beta1,
+                         c.beta2, c.eps, c1, c2, tt1, k0, k1, static_cast<Elem*>(s.wp), np);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
@@ -512,8 +522,8 @@ static hipError_t run_p(TrainScratch& s, const TrainConfig& c, const TrainTarget
 
 static hipError_t dispatch(TrainScratch& s, const TrainConfig& c, const TrainTargets& t, uint32_t step0,
                            uint32_t steps, bool update, float* grad_out, float* loss_out, hipStream_t st) {
-  if (c.batch % kChunk != 0) return hipErrorInvalidValue;
-  hipError_t e = ensure_scratch(s, c.batch, c.prec, update ? steps : 1);
+  if (c.batch % kChunk != 0 || c.shape.hidden % 32 != 0 || c.shape.layers < 1) return hipErrorInvalidValue;
+  hipError_t e = ensure_scratch(s, c.batch, c.prec, update ? steps : 1, c.shape);
   if (e != hipSuccess) return e;
   switch (c.prec) {
     case NPT_FP32: return run_p<NPT_FP32>(s, c, t, step0, steps, update, grad_out, loss_out, st);
@@ -541,8 +551,225 @@ hipError_t train_gradient(TrainScratch& s, const TrainConfig& c, const TrainTarg
   return dispatch(s, c, t, step, 1, false, d_grad, d_loss, st);
 }
 
+// ---------------------------------------------------------------------------
+// layer-serial inference (network shapes other than the LDS-resident default)
+// ---------------------------------------------------------------------------
+constexpr uint32_t kLayeredChunk = 1u << 20;  // rays per pass through the layers
+
+__device__ __forceinline__ void layered_uv(const LayeredIO& io, uint64_t idx, float& u, float& v) {
+  if (io.source == kLayeredGrid) {
+    u = ((float)(uint32_t)(idx % io.gw) + 0.5f) / (float)io.gw;
+    v = ((float)(uint32_t)(idx / io.gw) + 0.5f) / (float)io.gh;
+    return;
+  }
+  V3 d;
+  if (io.source == kLayeredQueue) {
+    const float4 ed = io.env.d[idx];
+    d = V3{ed.x, ed.y, ed.z};
+  } else {
+    d = V3{io.dirs[3 * idx], io.dirs[3 * idx + 1], io.dirs[3 * idx + 2]};
+  }
+  direction_to_uv(d, u, v);
+}
+
+// Fourier features of rows [base, base + rows) into X0 [rows][64]; rows past
+// the n source entries are zero
+template <int P>
+__global__ __launch_bounds__(256) void k_layered_features(LayeredIO io, uint64_t n, uint64_t base, uint32_t rows,
+                                                         typename Prec<P>::Elem* X0) {
+  for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += gridDim.x * blockDim.x) {
+    typename Prec<P>::Elem* x = X0 + (size_t)r * kFeat;
+    const uint64_t idx = base + r;
+    if (idx >= n) {
+      for (int k = 0; k < kFeat; ++k) x[k] = Prec<P>::cvt(0.0f);
+      continue;
+    }
+    float u, v;
+    layered_uv(io, idx, u, v);
+#pragma unroll
+    for (int k = 0; k < kFreq; ++k) {
+      const float f = (float)frequency(k);
+      float su, cu, sv, cv;
+      sincos_turns(frac_product(f, u), su, cu);
+      sincos_turns(frac_product(f, v), sv, cv);
+      x[k] = Prec<P>::cvt(su);
+      x[kFreq + k] = Prec<P>::cvt(cu);
+      x[2 * kFreq + k] = Prec<P>::cvt(sv);
+      x[3 * kFreq + k] = Prec<P>::cvt(cv);
+    }
+  }
+}
+
+// output layer (operand-precision weights, FP32 biases and sums), colour
+// matrix, then by source: log-space RGB (grid), radiance (directions), or
+// L[slot] += throughput * radiance (queue)
+template <int P>
+__global__ __launch_bounds__(256) void k_layered_head(const typename Prec<P>::Elem* wout, const float* bout, int H,
+                                                     const typename Prec<P>::Elem* XL, ColourMatrix cm, LayeredIO io,
+                                                     uint64_t n, uint64_t base, uint32_t rows) {
+  extern __shared__ float w6[];  // [3][H] weights, then 3 biases
+  for (int i = threadIdx.x; i < kOut * H; i += blockDim.x) w6[i] = (float)wout[i];
+  if (threadIdx.x < kOut) w6[kOut * H + threadIdx.x] = bout[threadIdx.x];
+  __syncthreads();
+  for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += gridDim.x * blockDim.x) {
+    const uint64_t idx = base + r;
+    if (idx >= n) continue;
+    const typename Prec<P>::Elem* h = XL + (size_t)r * H;
+    float y0 = w6[3 * H], y1 = w6[3 * H + 1], y2 = w6[3 * H + 2];
+    for (int i = 0; i < H; ++i) {
+      const float hv = (float)h[i];
+      y0 = fmaf(w6[i], hv, y0);
+      y1 = fmaf(w6[H + i], hv, y1);
+      y2 = fmaf(w6[2 * H + i], hv, y2);
+    }
+    const float* m = cm.m;
+    const float zr = fmaf(m[2], y2, fmaf(m[1], y1, m[0] * y0));
+    const float zg = fmaf(m[5], y2, fmaf(m[4], y1, m[3] * y0));
+    const float zb = fmaf(m[8], y2, fmaf(m[7], y1, m[6] * y0));
+    if (io.source == kLayeredGrid) {
+      io.out[3 * idx] = zr;
+      io.out[3 * idx + 1] = zg;
+      io.out[3 * idx + 2] = zb;
+      continue;
+    }
+    const float cr = fmaxf(expm1f(zr), 0.0f), cg = fmaxf(expm1f(zg), 0.0f), cb = fmaxf(expm1f(zb), 0.0f);
+    if (io.source == kLayeredDirs) {
+      io.out[3 * idx] = cr;
+      io.out[3 * idx + 1] = cg;
+      io.out[3 * idx + 2] = cb;
+    } else {
+      const float4 ed = io.env.d[idx], eb = io.env.b[idx];
+      const uint32_t slot = __float_as_uint(ed.w);
+      float4 l = io.L[slot];
+      l.x += eb.x * cr;
+      l.y += eb.y * cg;
+      l.z += eb.z * cb;
+      io.L[slot] = l;
+    }
+  }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_params_convert(const float* w, typename Prec<P>::Elem* wp, int64_t np) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < np; j += (int64_t)gridDim.x * blockDim.x)
+    wp[j] = Prec<P>::cvt(w[j]);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_params_dequant(NifShape sh, const float* master,
+                                                       const typename Prec<P>::Elem* wp, float* out) {
+  const int64_t np = shape_params(sh);
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < np; j += (int64_t)gridDim.x * blockDim.x) {
+    bool bias = false;
+    for (int l = 0; l <= sh.layers; ++l)
+      bias |= j >= shape_b_offset(sh, l) && j < shape_b_offset(sh, l) + shape_out(sh, l);
+    out[j] = bias ? master[j] : (float)wp[j];
+  }
+}
+
+void LayeredScratch::release() {
+  for (void*& p : x)
+    if (p) {
+      (void)hipFree(p);
+      p = nullptr;
+    }
+  cap = 0;
+}
+
+template <int P>
+static hipError_t layered_p(LayeredScratch& ls, const NifShape& sh, const void* wpv, const float* master,
+                            const ColourMatrix& cm, const LayeredIO& io, hipStream_t st) {
+  using Elem = typename Prec<P>::Elem;
+  const Elem* wp = static_cast<const Elem*>(wpv);
+  const int H = sh.hidden, L = sh.layers;
+  uint64_t n = io.n;
+  hipError_t e;
+  if (io.source == kLayeredQueue) {  // the queue length is known only on the device
+    uint32_t c = 0;
+    if ((e = hipMemcpyAsync(&c, io.cnt + kCntEnv + io.depth, sizeof(c), hipMemcpyDeviceToHost, st)) != hipSuccess)
+      return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    n = c;
+  }
+  if (n == 0) return hipSuccess;
+  const size_t width = (size_t)std::max(kFeat, H);
+  const size_t need = (size_t)kLayeredChunk * width * sizeof(Elem);
+  if (need > ls.cap) {
+    ls.release();
+    for (void*& p : ls.x)
+      if ((e = hipMalloc(&p, need)) != hipSuccess) return e;
+    ls.cap = need;
+  }
+  for (uint64_t base = 0; base < n; base += kLayeredChunk) {
+    const uint32_t rows = (uint32_t)(((std::min<uint64_t>(kLayeredChunk, n - base)) + 31) / 32 * 32);
+    Elem* x[2] = {static_cast<Elem*>(ls.x[0]), static_cast<Elem*>(ls.x[1])};
+    hipLaunchKernelGGL(k_layered_features<P>, dim3((rows + 255) / 256), dim3(256), 0, st, io, n, base, rows, x[0]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    int cur = 0;
+    for (int l = 0; l < L; ++l) {
+      GemmDesc g{};
+      g.A = x[cur];
+      g.a_sm = shape_in(sh, l);
+      g.a_sk = 1;
+      g.B = wp + shape_w_offset(sh, l);
+      g.b_sk = 1;
+      g.b_sn = shape_in(sh, l);
+      g.M = (int)rows;
+      g.N = H;
+      g.K = shape_in(sh, l);
+      g.k_chunk = g.K;
+      g.splits = 1;
+      g.mode = 0;
+      g.bias = master + shape_b_offset(sh, l);
+      g.C = x[cur ^ 1];
+      g.ldc = H;
+      if ((e = gemm<P, true, true>(g, st)) != hipSuccess) return e;
+      cur ^= 1;
+    }
+    hipLaunchKernelGGL(k_layered_head<P>, dim3((rows + 255) / 256), dim3(256), (size_t)(kOut * H + kOut) * 4, st,
+                       wp + shape_w_offset(sh, L), master + shape_b_offset(sh, L), H, x[cur], cm, io, n, base, rows);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t nif_layered(LayeredScratch& ls, int prec, const NifShape& shape, const void* wp, const float* master,
+                       const ColourMatrix& cm, const LayeredIO& io, hipStream_t st) {
+  if (shape.hidden % 32 != 0 || shape.hidden < 32 || shape.layers < 1) return hipErrorInvalidValue;
+  switch (prec) {
+    case NPT_FP32: return layered_p<NPT_FP32>(ls, shape, wp, master, cm, io, st);
+    case NPT_FP16: return layered_p<NPT_FP16>(ls, shape, wp, master, cm, io, st);
+    case NPT_BF16: return layered_p<NPT_BF16>(ls, shape, wp, master, cm, io, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_params_convert(int prec, const float* master, void* wp, int64_t n, hipStream_t st) {
+  const int g = grid_for_params(n);
+  switch (prec) {
+    case NPT_FP32: hipLaunchKernelGGL(k_params_convert<NPT_FP32>, dim3(g), dim3(256), 0, st, master, (float*)wp, n); break;
+    case NPT_FP16: hipLaunchKernelGGL(k_params_convert<NPT_FP16>, dim3(g), dim3(256), 0, st, master, (_Float16*)wp, n); break;
+    case NPT_BF16: hipLaunchKernelGGL(k_params_convert<NPT_BF16>, dim3(g), dim3(256), 0, st, master, (__bf16*)wp, n); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_params_dequant(int prec, const NifShape& shape, const float* master, const void* wp, float* out,
+                                 hipStream_t st) {
+  const int g = grid_for_params(shape_params(shape));
+  switch (prec) {
+    case NPT_FP32: hipLaunchKernelGGL(k_params_dequant<NPT_FP32>, dim3(g), dim3(256), 0, st, shape, master, (const float*)wp, out); break;
+    case NPT_FP16: hipLaunchKernelGGL(k_params_dequant<NPT_FP16>, dim3(g), dim3(256), 0, st, shape, master, (const _Float16*)wp, out); break;
+    case NPT_BF16: hipLaunchKernelGGL(k_params_dequant<NPT_BF16>, dim3(g), dim3(256), 0, st, shape, master, (const __bf16*)wp, out); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t grid_eval(TrainScratch& s, int prec, const void* frags, const float* bias, const ColourMatrix& cm,
-                     const TrainTargets& t, uint32_t gw, uint32_t gh, int num_cus, float out[2], hipStream_t st) {
+                     const TrainTargets& t, uint32_t gw, uint32_t gh, int num_cus, float out[2], hipStream_t st,
+                     LayeredScratch* layered, const NifShape* shape) {
   const uint64_t n = (uint64_t)gw * gh;
   hipError_t e;
   const int blocks = 256;
@@ -556,7 +783,18 @@ hipError_t grid_eval(TrainScratch& s, int prec, const void* frags, const float* 
     if ((e = hipMalloc((void**)&s.err_part, 2 * blocks * sizeof(float))) != hipSuccess) return e;
     s.grid_cap = n;
   }
-  if ((e = launch_nif_grid(prec, frags, bias, cm, gw, gh, s.zgrid, num_cus, st)) != hipSuccess) return e;
+  if (layered) {
+    LayeredIO io{};
+    io.source = kLayeredGrid;
+    io.gw = gw;
+    io.gh = gh;
+    io.n = n;
+    io.out = s.zgrid;
+    // frags: the operand-precision weights; bias: the FP32 master
+    if ((e = nif_layered(*layered, prec, *shape, frags, bias, cm, io, st)) != hipSuccess) return e;
+  } else if ((e = launch_nif_grid(prec, frags, bias, cm, gw, gh, s.zgrid, num_cus, st)) != hipSuccess) {
+    return e;
+  }
   hipLaunchKernelGGL(k_grid_err, dim3(blocks), dim3(256), 0, st, s.zgrid, t.map, (int)t.w, (int)t.h, gw, gh,
                      s.err_part);
   if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -100,6 +100,9 @@ struct npt_ctx {
   uint32_t adam_step = 0;
   int nif_prec = NPT_FP16;
   ColourMatrix nif_cm{};  // output colour space of the uploaded network
+  NifShape nif_shape{nif::kHidden, nif::kLayers};
+  bool nif_layered = false;  // layer-serial GEMM inference (shapes other than the default, or on request)
+  LayeredScratch layered;
   TrainScratch train;
 
   // render scratch
@@ -115,6 +118,7 @@ struct npt_ctx {
                      &d_cnt, &d_stats};
     for (DevBuf* b : all) b->release();
     train.release();
+    layered.release();
     for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
@@ -209,6 +213,13 @@ int upload_materials(npt_ctx* c, hipStream_t s) {
 
 int repack_nif(npt_ctx* c, hipStream_t s) {
   if (!c->have_nif) return NPT_OK;
+  if (c->nif_layered) {
+    // row-major operand-precision copy of the weights; biases stay in the master
+    const int64_t np = shape_params(c->nif_shape);
+    HIP_TRY(c, c->d_frags.ensure((size_t)np * (c->nif_prec == NPT_FP32 ? 4 : 2)));
+    HIP_TRY(c, launch_params_convert(c->nif_prec, c->d_master.as<float>(), c->d_frags.p, np, s));
+    return NPT_OK;
+  }
   const size_t bytes = nif_packed_bytes(c->nif_prec);
   if (bytes == 0) return fail(c, NPT_E_UNSUPPORTED, "precision not supported");
   HIP_TRY(c, c->d_frags.ensure(bytes));
@@ -537,8 +548,8 @@ extern "C" int npt_set_env_mode(npt_ctx* c, int mode) {
 // NIF
 // ===========================================================================
 static bool nif_desc_ok(const npt_nif_desc* d) {
-  return d && d->n_freq == (uint32_t)nif::kFreq && d->hidden == (uint32_t)nif::kHidden &&
-         d->layers == (uint32_t)nif::kLayers;
+  return d && d->n_freq == (uint32_t)nif::kFreq && d->hidden >= 32 && d->hidden <= 1024 && d->hidden % 32 == 0 &&
+         d->layers >= 1 && d->layers <= 8;
 }
 
 // log-space RGB = M * network output for the colour spaces of Sec. 4.3:
@@ -553,9 +564,14 @@ static ColourMatrix colour_matrix(uint32_t colour) {
 
 extern "C" int npt_nif_upload(npt_ctx* c, const npt_nif_desc* desc, const float* params, uint64_t n, void* stream) {
   if (!c) return NPT_E_INVALID_ARG;
-  if (!nif_desc_ok(desc)) return fail(c, NPT_E_UNSUPPORTED, "NIF shape must be n_freq 16, hidden 96, layers 5");
+  if (!nif_desc_ok(desc))
+    return fail(c, NPT_E_UNSUPPORTED, "NIF shape must be n_freq 16, hidden 32..1024 (a multiple of 32), layers 1..8");
   if (desc->colour > NPT_COLOUR_YCOCG) return fail(c, NPT_E_INVALID_ARG, "unknown NIF colour space");
-  if (!params || n != (uint64_t)nif::kParams) return fail(c, NPT_E_INVALID_ARG, "parameter count mismatch");
+  const NifShape shape{(int)desc->hidden, (int)desc->layers};
+  const bool layered = desc->layered != 0 || shape.hidden != nif::kHidden || shape.layers != nif::kLayers;
+  if (layered && c->nif_prec == NPT_FP8)
+    return fail(c, NPT_E_UNSUPPORTED, "FP8 inference needs the 16/96/5 network; set another precision first");
+  if (!params || n != (uint64_t)shape_params(shape)) return fail(c, NPT_E_INVALID_ARG, "parameter count mismatch");
   if (!finite_all(params, n)) return fail(c, NPT_E_NAN_INPUT, "non-finite NIF parameter");
   int r = need_device(c);
   if (r) return r;
@@ -570,6 +586,8 @@ extern "C" int npt_nif_upload(npt_ctx* c, const npt_nif_desc* desc, const float*
   c->adam_step = 0;
   c->have_nif = true;
   c->nif_cm = colour_matrix(desc->colour);
+  c->nif_shape = shape;
+  c->nif_layered = layered;
   r = repack_nif(c, s);
   if (r) return r;
   HIP_TRY(c, hipStreamSynchronize(s));
@@ -579,7 +597,8 @@ extern "C" int npt_nif_upload(npt_ctx* c, const npt_nif_desc* desc, const float*
 extern "C" int npt_nif_download(npt_ctx* c, float* params, uint64_t n) {
   if (!c) return NPT_E_INVALID_ARG;
   if (!c->have_nif) return fail(c, NPT_E_STATE, "no NIF uploaded");
-  if (!params || n != (uint64_t)nif::kParams) return fail(c, NPT_E_INVALID_ARG, "parameter count mismatch");
+  if (!params || n != (uint64_t)shape_params(c->nif_shape))
+    return fail(c, NPT_E_INVALID_ARG, "parameter count mismatch");
   int r = need_device(c);
   if (r) return r;
   HIP_TRY(c, hipDeviceSynchronize());
@@ -593,6 +612,8 @@ extern "C" int npt_nif_set_precision(npt_ctx* c, int prec) {
   if (prec == NPT_FP8 && (c->host_only || !c->fp8_capable))
     return fail(c, NPT_E_UNSUPPORTED, "FP8 NIF inference needs gfx950");
   if (nif_packed_bytes(prec) == 0) return fail(c, NPT_E_UNSUPPORTED, "precision not built");
+  if (prec == NPT_FP8 && c->have_nif && c->nif_layered)
+    return fail(c, NPT_E_UNSUPPORTED, "FP8 inference needs the 16/96/5 network on the LDS-resident path");
   const int old = c->nif_prec;
   c->nif_prec = prec;
   if (c->have_nif) {
@@ -608,13 +629,17 @@ extern "C" int npt_nif_set_precision(npt_ctx* c, int prec) {
 extern "C" int npt_nif_get_dequantized(npt_ctx* c, float* params, uint64_t n) {
   if (!c) return NPT_E_INVALID_ARG;
   if (!c->have_nif) return fail(c, NPT_E_STATE, "no NIF uploaded");
-  if (!params || n != (uint64_t)nif::kParams) return fail(c, NPT_E_INVALID_ARG, "parameter count mismatch");
+  if (!params || n != (uint64_t)shape_params(c->nif_shape))
+    return fail(c, NPT_E_INVALID_ARG, "parameter count mismatch");
   int r = need_device(c);
   if (r) return r;
   DevBuf tmp;
   HIP_TRY(c, tmp.ensure(n * sizeof(float)));
-  hipError_t e = launch_nif_dequant(c->nif_prec, c->d_master.as<float>(), c->d_bias.as<float>(), tmp.as<float>(),
-                                    (int)n, nullptr);
+  hipError_t e = c->nif_layered
+                    ? launch_params_dequant(c->nif_prec, c->nif_shape, c->d_master.as<float>(), c->d_frags.p,
+                                            tmp.as<float>(), nullptr)
+                    : launch_nif_dequant(c->nif_prec, c->d_master.as<float>(), c->d_bias.as<float>(),
+                                         tmp.as<float>(), (int)n, nullptr);
   if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
   if (e == hipSuccess) e = hipMemcpy(params, tmp.p, n * sizeof(float), hipMemcpyDeviceToHost);
   tmp.release();
@@ -624,6 +649,7 @@ extern "C" int npt_nif_get_dequantized(npt_ctx* c, float* params, uint64_t n) {
 
 static void train_defaults(npt_ctx* c, const npt_train_params* p, TrainConfig& t) {
   t.cm = c->nif_cm;
+  t.shape = c->nif_shape;
   t.batch = p && p->batch ? p->batch : 65536;
   t.samples = p && p->samples ? p->samples : (1ull << 24);
   t.lr = p && p->lr > 0 ? p->lr : 1e-3f;
@@ -715,8 +741,12 @@ extern "C" int npt_nif_eval_grid(npt_ctx* c, uint32_t gw, uint32_t gh, float* ou
   if (r) return r;
   hipStream_t s = (hipStream_t)stream;
   float res[2] = {0, 0};
-  HIP_TRY(c, grid_eval(c->train, c->nif_prec, c->d_frags.p, c->d_bias.as<float>(), c->nif_cm, train_targets(c), gw, gh,
-                       c->num_cus, res, s));
+  if (c->nif_layered)
+    HIP_TRY(c, grid_eval(c->train, c->nif_prec, c->d_frags.p, c->d_master.as<float>(), c->nif_cm, train_targets(c),
+                         gw, gh, c->num_cus, res, s, &c->layered, &c->nif_shape));
+  else
+    HIP_TRY(c, grid_eval(c->train, c->nif_prec, c->d_frags.p, c->d_bias.as<float>(), c->nif_cm, train_targets(c),
+                         gw, gh, c->num_cus, res, s));
   out2[0] = res[0];
   out2[1] = res[1];
   return ok(c);
@@ -733,8 +763,18 @@ extern "C" int npt_env_query(npt_ctx* c, int mode, const float* d_dirs, uint64_t
     HIP_TRY(c, launch_env_query_map(c->d_env.as<float4>(), (int)c->env_w, (int)c->env_h, d_dirs, n, d_rgb, s));
   } else if (mode == NPT_ENV_NIF) {
     if (!c->have_nif) return fail(c, NPT_E_NO_ENV, "no NIF uploaded");
-    HIP_TRY(c, launch_nif_dirs(c->nif_prec, c->d_frags.p, c->d_bias.as<float>(), c->nif_cm, d_dirs, n, d_rgb,
-                               c->num_cus, s));
+    if (c->nif_layered) {
+      LayeredIO io{};
+      io.source = kLayeredDirs;
+      io.dirs = d_dirs;
+      io.out = d_rgb;
+      io.n = n;
+      HIP_TRY(c, nif_layered(c->layered, c->nif_prec, c->nif_shape, c->d_frags.p, c->d_master.as<float>(), c->nif_cm,
+                             io, s));
+    } else {
+      HIP_TRY(c, launch_nif_dirs(c->nif_prec, c->d_frags.p, c->d_bias.as<float>(), c->nif_cm, d_dirs, n, d_rgb,
+                                 c->num_cus, s));
+    }
   } else {
     return fail(c, NPT_E_INVALID_ARG, "unknown env mode");
   }
@@ -853,6 +893,15 @@ extern "C" int npt_render(npt_ctx* c, uint32_t W, uint32_t H, uint32_t spp, uint
         if (c->env_mode == NPT_ENV_MAP) {
           HIP_TRY(c, launch_env_lookup(c->d_env.as<float4>(), (int)c->env_w, (int)c->env_h, eq, L, cnt, k, n,
                                        c->num_cus, s));
+        } else if (c->nif_layered) {
+          LayeredIO io{};
+          io.source = kLayeredQueue;
+          io.env = eq;
+          io.L = L;
+          io.cnt = cnt;
+          io.depth = k;
+          HIP_TRY(c, nif_layered(c->layered, c->nif_prec, c->nif_shape, c->d_frags.p, c->d_master.as<float>(),
+                                 c->nif_cm, io, s));
         } else {
           HIP_TRY(c, launch_nif_queue(c->nif_prec, c->d_frags.p, c->d_bias.as<float>(), c->nif_cm, eq, L, cnt, k, n,
                                       c->num_cus, s));

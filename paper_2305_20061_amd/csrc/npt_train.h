@@ -1,6 +1,8 @@
 // npt_train.h -- on-device HDR-NIF training (Sec. 3.2.1): uniform (u,v)
 // samples with bilinear targets, log compression, Huber loss, hand-written
-// backward pass on MFMA GEMMs, Adam with FP32 master weights.
+// backward pass on MFMA GEMMs, Adam with FP32 master weights; and the
+// layer-serial inference used for network shapes other than the
+// LDS-resident default.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -8,6 +10,26 @@
 #include "npt_shared.h"
 
 namespace npt {
+
+// Shape of the MLP at run time: 64 Fourier features -> layers x [dense
+// hidden + ReLU] -> dense 3.  hidden is a multiple of 32 (the MFMA tile).
+struct NifShape {
+  int hidden;
+  int layers;
+};
+__host__ __device__ inline int shape_in(const NifShape& s, int l) { return l == 0 ? 64 : s.hidden; }
+__host__ __device__ inline int shape_out(const NifShape& s, int l) { return l == s.layers ? 3 : s.hidden; }
+// offsets of W_l and b_l in the flat parameter vector [W_0, b_0, ..., W_L, b_L]
+__host__ __device__ inline int64_t shape_w_offset(const NifShape& s, int l) {
+  if (l == 0) return 0;
+  return (int64_t)64 * s.hidden + s.hidden + (int64_t)(l - 1) * ((int64_t)s.hidden * s.hidden + s.hidden);
+}
+__host__ __device__ inline int64_t shape_b_offset(const NifShape& s, int l) {
+  return shape_w_offset(s, l) + (int64_t)shape_out(s, l) * shape_in(s, l);
+}
+__host__ __device__ inline int64_t shape_params(const NifShape& s) {
+  return shape_w_offset(s, s.layers) + 3 * (int64_t)s.hidden + 3;
+}
 
 struct TrainConfig {
   uint32_t batch;
@@ -18,31 +40,32 @@ struct TrainConfig {
   float loss_scale;  // per-sample output gradient scale before low-precision GEMMs
   ColourMatrix cm;   // fixed output colour matrix (network output -> log RGB)
   int master_prec;   // NPT_FP32, or NPT_FP16: binary16 master weights, stochastically rounded updates
+  NifShape shape;
 };
 
 struct TrainTargets {
   const float4* map;
   uint32_t w, h;
-  float* master;  // FP32 parameters [kParams]
+  float* master;  // FP32 parameters [shape_params]
   float* m;       // Adam first moments
   float* v;       // Adam second moments
 };
 
 // Device scratch of the training step, sized on first use.
 struct TrainScratch {
-  void* act = nullptr;      // X0 [B][64] then H1..H5 [B][96], operand precision
-  void* dp = nullptr;       // two [B][96] back-propagated pre-activation gradients
+  void* act = nullptr;      // X0 [B][64] then H1..HL [B][hidden], operand precision
+  void* dp = nullptr;       // two [B][hidden] back-propagated pre-activation gradients
   void* wp = nullptr;       // parameters in operand precision
   float* target = nullptr;  // [B][3] log1p(bilinear) targets
   float* dy = nullptr;      // [B][3] output-layer gradients (scaled)
-  float* partial = nullptr; // [splits][kParams] per-chunk gradient sums
-  float* sub = nullptr;     // [B / 64][291] per-run column sums (bias and output-layer gradients)
-  float* grad = nullptr;    // [kParams]
+  float* partial = nullptr; // [splits][params] per-chunk gradient sums
+  float* sub = nullptr;     // [B / 64][3 hidden + 3] per-run column sums (bias and output-layer gradients)
+  float* grad = nullptr;    // [params]
   float* loss_part = nullptr;
   float* loss = nullptr;    // per-step losses
   float* zgrid = nullptr;   // grid evaluation outputs
   float* err_part = nullptr;
-  uint32_t batch_cap = 0, elem_bytes = 0, steps_cap = 0;
+  size_t bytes[10] = {};    // allocated bytes of act .. loss
   uint64_t grid_cap = 0;
   void release();
 };
@@ -51,8 +74,44 @@ hipError_t train_run(TrainScratch& s, const TrainConfig& c, const TrainTargets& 
                      float* first_loss, float* last_loss, hipStream_t st);
 hipError_t train_gradient(TrainScratch& s, const TrainConfig& c, const TrainTargets& t, uint32_t step,
                           float* d_grad, float* d_loss, hipStream_t st);
+
+// Layer-serial inference (any NifShape, FP32 / FP16 / BF16 operands): rays in
+// chunks; Fourier features, one GEMM (bias + ReLU epilogue) per hidden
+// layer, then the output layer, colour matrix and expm1.  The operand copy
+// wp of the weights is row-major [out][in] as the master; biases come from
+// the FP32 master.  Sources as the LDS-resident kernel: the environment
+// queue of one depth (count read back from the device), world directions,
+// or the centres of a (u,v) grid (log-space RGB out).
+enum : int { kLayeredQueue = 0, kLayeredDirs = 1, kLayeredGrid = 2 };
+struct LayeredIO {
+  int source;
+  EnvQueue env;
+  float4* L;
+  const uint32_t* cnt;
+  uint32_t depth;
+  const float* dirs;
+  float* out;
+  uint64_t n;
+  uint32_t gw, gh;
+};
+struct LayeredScratch {
+  void* x[2] = {nullptr, nullptr};  // ping-pong activations [chunk][max(64, hidden)]
+  size_t cap = 0;                   // bytes of each
+  void release();
+};
+hipError_t nif_layered(LayeredScratch& ls, int prec, const NifShape& shape, const void* wp, const float* master,
+                       const ColourMatrix& cm, const LayeredIO& io, hipStream_t st);
+// operand-precision copy of the master weights (wp, n values)
+hipError_t launch_params_convert(int prec, const float* master, void* wp, int64_t n, hipStream_t st);
+// the values the layered inference multiplies: weights from wp, biases from the master
+hipError_t launch_params_dequant(int prec, const NifShape& shape, const float* master, const void* wp, float* out,
+                                 hipStream_t st);
+
+// grid evaluation (log-MSE, log-PSNR) of whichever inference path serves
+// the context: layered when `layered` is set, else the LDS-resident kernel
 hipError_t grid_eval(TrainScratch& s, int prec, const void* frags, const float* bias, const ColourMatrix& cm,
-                     const TrainTargets& t, uint32_t gw, uint32_t gh, int num_cus, float out[2], hipStream_t st);
+                     const TrainTargets& t, uint32_t gw, uint32_t gh, int num_cus, float out[2], hipStream_t st,
+                     LayeredScratch* layered = nullptr, const NifShape* shape = nullptr);
 
 // counters of the render loop (k_render.hip)
 hipError_t launch_stats_clear(unsigned long long* stats, hipStream_t s);

@@ -58,7 +58,8 @@ class npt_bvh_params(C.Structure):
 
 
 class npt_nif_desc(C.Structure):
-    _fields_ = [("n_freq", C.c_uint32), ("hidden", C.c_uint32), ("layers", C.c_uint32), ("colour", C.c_uint32)]
+    _fields_ = [("n_freq", C.c_uint32), ("hidden", C.c_uint32), ("layers", C.c_uint32), ("colour", C.c_uint32),
+                ("layered", C.c_uint32)]
 
 
 class npt_train_params(C.Structure):
@@ -279,9 +280,13 @@ def npt_set_env_mode(ctx, mode):
 
 
 # ---------------------------------------------------------------------- NIF
-def npt_nif_upload(ctx, params, n_freq=16, hidden=96, layers=5, stream=None, colour=0):
+def nif_param_count(hidden=96, layers=5):
+    return 64 * hidden + hidden + (layers - 1) * (hidden * hidden + hidden) + 3 * hidden + 3
+
+
+def npt_nif_upload(ctx, params, n_freq=16, hidden=96, layers=5, stream=None, colour=0, layered=0):
     p = _host(params, np.float32)
-    d = npt_nif_desc(n_freq, hidden, layers, colour)
+    d = npt_nif_desc(n_freq, hidden, layers, colour, layered)
     _check(ctx, lib().npt_nif_upload(ctx, C.byref(d), _hp(p), p.size, _stream(stream)))
 
 
@@ -315,9 +320,10 @@ def npt_nif_train(ctx, params: npt_train_params = None, stream=None):
             "last_loss": st.last_loss, "ms": st.ms}
 
 
-def npt_nif_train_grad(ctx, params: npt_train_params, step, grad_out, loss_out, stream=None):
+def npt_nif_train_grad(ctx, params: npt_train_params, step, grad_out, loss_out, stream=None, n_params=43779):
+    """n_params: parameter count of the uploaded network (nif_param_count)."""
     import torch
-    _check(ctx, lib().npt_nif_train_grad(ctx, C.byref(params), step, _dev(grad_out, torch.float32, 43779),
+    _check(ctx, lib().npt_nif_train_grad(ctx, C.byref(params), step, _dev(grad_out, torch.float32, n_params),
                                          _dev(loss_out, torch.float32, 1), _stream(stream)))
 
 

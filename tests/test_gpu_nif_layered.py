@@ -1,0 +1,145 @@
+"""Layer-serial NIF inference and shape-generic training (the model sizes of
+Sec. 4.6) against the oracle, whose forward and backward passes take any
+hidden width and depth: queries with the same operand rounding, the
+dequantised weights bit for bit, gradients against the FP64 backward, a
+NIF-lit render, and the default 16/96/5 network on both inference paths."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2305_20061_amd import npt, synth
+
+from gpu_util import gpu_render, make_ctx, oracle_scene, rel_rmse, torch_cuda
+
+pytestmark = pytest.mark.gpu
+SHAPES = [(64, 2), (128, 3), (96, 5)]
+QUERY_TOL = {npt.FP32: 2e-4, npt.FP16: 2e-3, npt.BF16: 1e-2}
+
+
+def _weights(hidden, layers, seed=3):
+    p = synth.nif_init(seed, 16, hidden, layers).astype(np.float32)
+    p[-3:] = (0.6, 0.05, -0.05)
+    return p
+
+
+def _dirs(n, seed=0):
+    rng = np.random.default_rng(seed)
+    d = rng.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    return d.astype(np.float32)
+
+
+@pytest.mark.parametrize("hidden,layers", SHAPES)
+@pytest.mark.parametrize("prec", [npt.FP32, npt.FP16, npt.BF16])
+def test_layered_query_matches_oracle(hidden, layers, prec):
+    torch = torch_cuda()
+    shape = O.nif_shape(16, hidden, layers)
+    p = _weights(hidden, layers)
+    n = 2048 + 37
+    ctx = npt.npt_create(0)
+    try:
+        npt.npt_nif_set_precision(ctx, prec)
+        npt.npt_nif_upload(ctx, p, hidden=hidden, layers=layers, layered=1)
+        d = _dirs(n)
+        out = torch.full((n, 3), -1.0, dtype=torch.float32, device="cuda")
+        npt.npt_env_query(ctx, npt.ENV_NIF, torch.from_numpy(d).cuda(), out)
+        torch.cuda.synchronize()
+        g = out.cpu().numpy().astype(np.float64)
+        dq = npt.npt_nif_get_dequantized(ctx, p.size).astype(np.float64)
+    finally:
+        npt.npt_destroy(ctx)
+    ref_p = O.nif_dequantize(shape, p.astype(np.float64), prec)
+    assert np.array_equal(dq, ref_p)
+    o = np.array([O.nif_radiance_q(shape, ref_p, prec, *O.dir_to_uv(x)) for x in d])
+    r = rel_rmse(g, o)
+    print(f"layered H{hidden} L{layers} prec {prec}: relRMSE {r:.3e}")
+    assert np.all(g >= 0)
+    assert r <= QUERY_TOL[prec]
+
+
+@pytest.mark.parametrize("hidden,layers", [(64, 2), (128, 3)])
+@pytest.mark.parametrize("prec", [npt.FP32, npt.FP16])
+def test_shape_generic_training_gradient_matches_oracle(hidden, layers, prec, small_sky):
+    torch = torch_cuda()
+    shape = O.nif_shape(16, hidden, layers)
+    p = synth.nif_init(11, 16, hidden, layers)
+    B, seed, step = 2048, 5, 2
+    ctx = npt.npt_create(0)
+    try:
+        npt.npt_env_upload(ctx, small_sky)
+        npt.npt_nif_upload(ctx, p, hidden=hidden, layers=layers)
+        grad = torch.zeros(p.size, dtype=torch.float32, device="cuda")
+        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        npt.npt_nif_train_grad(ctx, npt.train_params(batch=B, seed=seed, grad_prec=prec), step, grad, loss,
+                               n_params=p.size)
+        torch.cuda.synchronize()
+        g = grad.cpu().numpy().astype(np.float64)
+        lg = float(loss.cpu()[0])
+    finally:
+        npt.npt_destroy(ctx)
+    uv, tg = O.nif_train_batch(small_sky, seed, step, B)
+    lo, go = O.nif_loss_grad(shape, p.astype(np.float64), uv, tg, 1e-3)
+    r = rel_rmse(g, go)
+    print(f"H{hidden} L{layers} grad prec {prec}: relRMSE {r:.3e}, loss {lg:.6e} vs {lo:.6e}")
+    tol = {npt.FP32: (1e-4, 1e-5), npt.FP16: (3e-2, 1e-3)}[prec]
+    assert r <= tol[0]
+    assert abs(lg - lo) <= tol[1] * abs(lo)
+
+
+def test_layered_render_matches_oracle(small_sky):
+    scene = synth.scene_for(1)
+    hidden, layers = 64, 2
+    p = _weights(hidden, layers)
+    shape = O.nif_shape(16, hidden, layers)
+    ctx = make_ctx(scene, env=small_sky)
+    try:
+        npt.npt_nif_set_precision(ctx, npt.FP16)
+        npt.npt_nif_upload(ctx, p, hidden=hidden, layers=layers)
+        npt.npt_set_env_mode(ctx, npt.ENV_NIF)
+        g = gpu_render(ctx, 48, 48, 2, 6, 9)
+        st = npt.npt_get_stats(ctx)
+    finally:
+        npt.npt_destroy(ctx)
+    osc, cam = oracle_scene(scene)
+    o = O.render(osc, cam, O.render_desc(48, 48, 2, 6, 9, nif_params=O.nif_dequantize(shape, p.astype(np.float64),
+                                                                                        O.PREC_FP16),
+                                         nif=shape, nif_prec=O.PREC_FP16))
+    r = rel_rmse(g, o)
+    print(f"layered H64 L2 FP16 render relRMSE {r:.3e}, {st['env_queries']} queries")
+    assert st["env_queries"] > 0
+    assert r <= QUERY_TOL[npt.FP16]
+
+
+def test_default_network_on_both_paths_agrees():
+    torch = torch_cuda()
+    p = _weights(96, 5)
+    d = torch.from_numpy(_dirs(4096 + 5, seed=2)).cuda()
+    outs = []
+    for layered in (0, 1):
+        ctx = npt.npt_create(0)
+        try:
+            npt.npt_nif_set_precision(ctx, npt.FP32)
+            npt.npt_nif_upload(ctx, p, layered=layered)
+            out = torch.empty(d.shape[0], 3, dtype=torch.float32, device="cuda")
+            npt.npt_env_query(ctx, npt.ENV_NIF, d, out)
+            torch.cuda.synchronize()
+            outs.append(out.cpu().numpy().astype(np.float64))
+        finally:
+            npt.npt_destroy(ctx)
+    r = rel_rmse(outs[1], outs[0])
+    print(f"default network, layered vs LDS-resident FP32: relRMSE {r:.3e}")
+    assert r <= 2e-4
+
+
+def test_layered_training_reduces_grid_error(sky_map):
+    ctx = npt.npt_create(0)
+    try:
+        npt.npt_env_upload(ctx, sky_map)
+        npt.npt_nif_upload(ctx, synth.nif_init(3, 16, 64, 2), hidden=64, layers=2)
+        before = npt.npt_nif_eval_grid(ctx, 256, 128)
+        st = npt.npt_nif_train(ctx, npt.train_params(batch=16384, samples=1 << 21, seed=1, grad_prec=npt.FP16))
+        after = npt.npt_nif_eval_grid(ctx, 256, 128)
+    finally:
+        npt.npt_destroy(ctx)
+    print(f"H64 L2: log-MSE {before['log_mse']:.4e} -> {after['log_mse']:.4e} in {st['steps']} steps")
+    assert after["log_mse"] < 0.2 * before["log_mse"]
