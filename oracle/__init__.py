@@ -48,7 +48,8 @@ class Camera(C.Structure):
 
 
 class NifShape(C.Structure):
-    _fields_ = [("n_freq", C.c_uint32), ("hidden", C.c_uint32), ("layers", C.c_uint32), ("colour", C.c_uint32)]
+    _fields_ = [("n_freq", C.c_uint32), ("hidden", C.c_uint32), ("layers", C.c_uint32), ("colour", C.c_uint32),
+                ("skip", C.c_uint32)]
 
 
 class RenderDesc(C.Structure):
@@ -260,9 +261,11 @@ def env_bilinear(env, u, v):
 COLOUR_YUV, COLOUR_RGB, COLOUR_YCOCG = 0, 1, 2
 
 
-def nif_shape(n_freq=16, hidden=96, layers=5, colour=COLOUR_YUV):
+def nif_shape(n_freq=16, hidden=96, layers=5, colour=COLOUR_YUV, skip=0):
+    """skip: 0, or the hidden layer (1..layers-1) whose input is the previous
+    layer's output followed by the features (skip-concat)."""
     s = NifShape()
-    s.n_freq, s.hidden, s.layers, s.colour = n_freq, hidden, layers, colour
+    s.n_freq, s.hidden, s.layers, s.colour, s.skip = n_freq, hidden, layers, colour, skip
     return s
 
 

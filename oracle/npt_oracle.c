@@ -412,7 +412,11 @@ void or_env_bilinear(const float *rgb, uint32_t w, uint32_t h, double u, double 
 /* ------------------------------------------------------------------------ */
 uint32_t or_nif_frequency(uint32_t k) { return (uint32_t)llround(pow(2.0, (double)(k + 1) * 0.5)); }
 
-static uint32_t layer_in(const or_nif_shape *s, uint32_t l) { return l == 0 ? 4 * s->n_freq : s->hidden; }
+static uint32_t layer_in(const or_nif_shape *s, uint32_t l)
+{
+    if (l == 0) return 4 * s->n_freq;
+    return s->skip != 0 && l == s->skip ? s->hidden + 4 * s->n_freq : s->hidden;
+}
 static uint32_t layer_out(const or_nif_shape *s, uint32_t l) { return l == s->layers ? 3 : s->hidden; }
 
 uint64_t or_nif_param_count(const or_nif_shape *s)
@@ -462,7 +466,8 @@ void or_colour_to_rgb_matrix(uint32_t colour, double m[9])
 }
 
 /* Forward pass keeping post-activation values: act[l] has layer_in(l) values
- * for l = 0..layers (act[0] = features); y = YUV output, z = RGB log. */
+ * for l = 0..layers (act[0] = features; act[skip] ends with the features
+ * again); y = network output, z = RGB log. */
 static void nif_forward_full(const or_nif_shape *s, const double *params, double u, double v,
                              double **act, double y[3], double z[3])
 {
@@ -477,6 +482,8 @@ static void nif_forward_full(const or_nif_shape *s, const double *params, double
             for (uint32_t i = 0; i < ni; ++i) acc += W[(size_t)j * ni + i] * act[l][i];
             out[j] = (l == s->layers) ? acc : (acc > 0.0 ? acc : 0.0);
         }
+        if (s->skip != 0 && l + 1 == s->skip)
+            memcpy(act[l + 1] + no, act[0], sizeof(double) * 4 * s->n_freq);
         p += (size_t)no * ni + no;
     }
     double m[9];
@@ -600,11 +607,13 @@ void or_nif_dequantize(const or_nif_shape *s, const double *params, int prec, do
 
 void or_nif_forward_q(const or_nif_shape *s, const double *deq, int prec, double u, double v, double z[3])
 {
-    uint32_t width = 4 * s->n_freq > s->hidden ? 4 * s->n_freq : s->hidden;
+    uint32_t width = 4 * s->n_freq + s->hidden;
     double *x = (double *)malloc(sizeof(double) * width);
     double *h = (double *)malloc(sizeof(double) * width);
+    double *feat = (double *)malloc(sizeof(double) * 4 * s->n_freq);
     double y[3];
-    or_nif_features(s, u, v, x);
+    or_nif_features(s, u, v, feat);
+    memcpy(x, feat, sizeof(double) * 4 * s->n_freq);
     const double *p = deq;
     for (uint32_t l = 0; l <= s->layers; ++l) {
         uint32_t ni = layer_in(s, l), no = layer_out(s, l);
@@ -618,6 +627,7 @@ void or_nif_forward_q(const or_nif_shape *s, const double *deq, int prec, double
             out[j] = (l == s->layers) ? acc : (acc > 0.0 ? acc : 0.0);
         }
         if (l < s->layers) memcpy(x, h, sizeof(double) * no);
+        if (s->skip != 0 && l + 1 == s->skip) memcpy(x + no, feat, sizeof(double) * 4 * s->n_freq);
         p += (size_t)no * ni + no;
     }
     double m[9];
@@ -625,6 +635,7 @@ void or_nif_forward_q(const or_nif_shape *s, const double *deq, int prec, double
     for (int r = 0; r < 3; ++r) z[r] = m[3 * r] * y[0] + m[3 * r + 1] * y[1] + m[3 * r + 2] * y[2];
     free(x);
     free(h);
+    free(feat);
 }
 
 void or_nif_radiance_q(const or_nif_shape *s, const double *deq, int prec, double u, double v, double rgb[3])
@@ -656,8 +667,8 @@ double or_nif_loss_grad(const or_nif_shape *s, const double *params, uint64_t n,
     uint64_t np = or_nif_param_count(s);
     if (grad) memset(grad, 0, sizeof(double) * np);
     double **act = alloc_acts(s);
-    double *da = (double *)malloc(sizeof(double) * (s->hidden > 4 * s->n_freq ? s->hidden : 4 * s->n_freq));
-    double *dprev = (double *)malloc(sizeof(double) * (s->hidden > 4 * s->n_freq ? s->hidden : 4 * s->n_freq));
+    double *da = (double *)malloc(sizeof(double) * (s->hidden + 4 * s->n_freq));
+    double *dprev = (double *)malloc(sizeof(double) * (s->hidden + 4 * s->n_freq));
     /* offsets of each layer's W in the flat parameter vector */
     size_t *off = (size_t *)malloc(sizeof(size_t) * (s->layers + 1));
     size_t o = 0;

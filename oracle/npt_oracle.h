@@ -66,13 +66,16 @@ typedef struct {
 
 /* NIF shape: 4*n_freq Fourier features -> `layers` x [dense `hidden` + ReLU]
  * -> dense 3 -> fixed 3x3 colour matrix to RGB.  colour: the space the
- * network's outputs live in (Sec. 4.3): OR_COLOUR_YUV (default), RGB, YCOCG. */
+ * network's outputs live in (Sec. 4.3): OR_COLOUR_YUV (default), RGB, YCOCG.
+ * skip: 0, or the hidden layer l (1..layers-1) whose input is the previous
+ * layer's output followed by the features again (the skip-concat of Sec. 3.2). */
 enum { OR_COLOUR_YUV = 0, OR_COLOUR_RGB = 1, OR_COLOUR_YCOCG = 2 };
 typedef struct {
     uint32_t n_freq;
     uint32_t hidden;
     uint32_t layers;
     uint32_t colour;
+    uint32_t skip;
 } or_nif_shape;
 
 typedef struct or_scene or_scene;

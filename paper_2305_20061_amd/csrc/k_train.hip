@@ -48,6 +48,18 @@ __global__ __launch_bounds__(256) void k_train_sample(TrainTargets t, uint32_t k
   }
 }
 
+// columns [col0, col0 + 64) of rows of dst (row stride ld) := the 64
+// features of each row of X0 (the skip-concat input)
+template <int P>
+__global__ __launch_bounds__(256) void k_copy_features(const typename Prec<P>::Elem* X0, uint32_t rows,
+                                                      typename Prec<P>::Elem* dst, int ld, int col0) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < (uint64_t)rows * kFeat;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t r = i / kFeat, k = i % kFeat;
+    dst[r * ld + col0 + k] = X0[i];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // GEMM on MFMA, one wave per 32x32 output tile, operands straight from
 // global memory: C(m, n) = sum_k A(m, k) B(k, n), A(m,k) = A[m*a_sm + k*a_sk],
@@ -348,7 +360,9 @@ static uint32_t elem_size(int prec) { return prec == NPT_FP32 ? 4u : 2u; }
 // prec and shape sh needs (and the per-step loss record to `steps`)
 static hipError_t ensure_scratch(TrainScratch& s, uint32_t B, int prec, uint32_t steps, const NifShape& sh) {
   const size_t es = elem_size(prec), np = (size_t)shape_params(sh), H = (size_t)sh.hidden;
-  const size_t need[10] = {(size_t)B * (64 + (size_t)sh.layers * H) * es,
+  size_t act_cols = 64;
+  for (int l = 1; l <= sh.layers; ++l) act_cols += (size_t)shape_in(sh, l);
+  const size_t need[10] = {(size_t)B * act_cols * es,
                            2 * (size_t)B * H * es,
                            np * 4,
                            (size_t)B * 3 * 4,
@@ -394,13 +408,18 @@ static hipError_t step_gradient(TrainScratch& s, const TrainConfig& c, const Tra
   Elem* act = static_cast<Elem*>(s.act);
   std::vector<Elem*> acts(L + 1);
   acts[0] = act;
-  for (int l = 1; l <= L; ++l) acts[l] = act + (size_t)B * 64 + (size_t)(l - 1) * B * H;
+  for (int l = 1; l <= L; ++l) acts[l] = acts[l - 1] + (size_t)B * shape_in(sh, l - 1);
   Elem* dp[2] = {static_cast<Elem*>(s.dp), static_cast<Elem*>(s.dp) + (size_t)B * H};
   const Elem* wp = static_cast<const Elem*>(s.wp);
   hipError_t e;
   hipLaunchKernelGGL(k_train_sample<P>, dim3((B + 255) / 256), dim3(256), 0, st, t, (uint32_t)c.seed,
                      (uint32_t)(c.seed >> 32), step, B, acts[0], s.target);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (sh.skip != 0) {
+    hipLaunchKernelGGL(k_copy_features<P>, dim3(4096), dim3(256), 0, st, acts[0], B, acts[sh.skip],
+                       shape_in(sh, sh.skip), H);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   for (int l = 0; l < L; ++l) {
     GemmDesc g{};
     g.A = acts[l];
@@ -417,7 +436,7 @@ static hipError_t step_gradient(TrainScratch& s, const TrainConfig& c, const Tra
     g.mode = 0;
     g.bias = t.master + shape_b_offset(sh, l);
     g.C = acts[l + 1];
-    g.ldc = H;
+    g.ldc = shape_in(sh, l + 1);
     if ((e = gemm<P, true, true>(g, st)) != hipSuccess) return e;
   }
   const int nblk = (int)((B + 255) / 256);
@@ -469,13 +488,13 @@ static hipError_t step_gradient(TrainScratch& s, const TrainConfig& c, const Tra
     d.b_sk = shape_in(sh, l);
     d.b_sn = 1;
     d.M = (int)B;
-    d.N = shape_in(sh, l);
+    d.N = H;  // the hidden part of layer l's input (not the features of a skip-concat)
     d.K = H;
     d.k_chunk = H;
     d.splits = 1;
     d.mode = 1;
     d.mask = acts[l];
-    d.mask_ld = H;
+    d.mask_ld = shape_in(sh, l);
     d.C = dp[cur ^ 1];
     d.ldc = H;
     if ((e = gemm<P, true, false>(d, st)) != hipSuccess) return e;
@@ -522,7 +541,9 @@ static hipError_t run_p(TrainScratch& s, const TrainConfig& c, const TrainTarget
 
 static hipError_t dispatch(TrainScratch& s, const TrainConfig& c, const TrainTargets& t, uint32_t step0,
                            uint32_t steps, bool update, float* grad_out, float* loss_out, hipStream_t st) {
-  if (c.batch % kChunk != 0 || c.shape.hidden % 32 != 0 || c.shape.layers < 1) return hipErrorInvalidValue;
+  if (c.batch % kChunk != 0 || c.shape.hidden % 32 != 0 || c.shape.layers < 1 ||
+      (c.shape.skip != 0 && (c.shape.skip < 1 || c.shape.skip >= c.shape.layers)))
+    return hipErrorInvalidValue;
   hipError_t e = ensure_scratch(s, c.batch, c.prec, update ? steps : 1, c.shape);
   if (e != hipSuccess) return e;
   switch (c.prec) {
@@ -692,8 +713,7 @@ static hipError_t layered_p(LayeredScratch& ls, const NifShape& sh, const void* 
     n = c;
   }
   if (n == 0) return hipSuccess;
-  const size_t width = (size_t)std::max(kFeat, H);
-  const size_t need = (size_t)kLayeredChunk * width * sizeof(Elem);
+  const size_t need = (size_t)kLayeredChunk * (H + kFeat) * sizeof(Elem);
   if (need > ls.cap) {
     ls.release();
     for (void*& p : ls.x)
@@ -702,10 +722,11 @@ static hipError_t layered_p(LayeredScratch& ls, const NifShape& sh, const void* 
   }
   for (uint64_t base = 0; base < n; base += kLayeredChunk) {
     const uint32_t rows = (uint32_t)(((std::min<uint64_t>(kLayeredChunk, n - base)) + 31) / 32 * 32);
-    Elem* x[2] = {static_cast<Elem*>(ls.x[0]), static_cast<Elem*>(ls.x[1])};
-    hipLaunchKernelGGL(k_layered_features<P>, dim3((rows + 255) / 256), dim3(256), 0, st, io, n, base, rows, x[0]);
+    // x[2]: the features (kept for a skip-concat); x[0] / x[1]: layer outputs
+    Elem* x[3] = {static_cast<Elem*>(ls.x[0]), static_cast<Elem*>(ls.x[1]), static_cast<Elem*>(ls.x[2])};
+    hipLaunchKernelGGL(k_layered_features<P>, dim3((rows + 255) / 256), dim3(256), 0, st, io, n, base, rows, x[2]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    int cur = 0;
+    int cur = 2, nxt = 0;
     for (int l = 0; l < L; ++l) {
       GemmDesc g{};
       g.A = x[cur];
@@ -721,10 +742,16 @@ static hipError_t layered_p(LayeredScratch& ls, const NifShape& sh, const void* 
       g.splits = 1;
       g.mode = 0;
       g.bias = master + shape_b_offset(sh, l);
-      g.C = x[cur ^ 1];
-      g.ldc = H;
+      g.C = x[nxt];
+      g.ldc = shape_in(sh, l + 1);
       if ((e = gemm<P, true, true>(g, st)) != hipSuccess) return e;
-      cur ^= 1;
+      if (sh.skip != 0 && l + 1 == sh.skip) {
+        hipLaunchKernelGGL(k_copy_features<P>, dim3(4096), dim3(256), 0, st, x[2], rows, x[nxt], shape_in(sh, l + 1),
+                           H);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+      }
+      cur = nxt;
+      nxt ^= 1;
     }
     hipLaunchKernelGGL(k_layered_head<P>, dim3((rows + 255) / 256), dim3(256), (size_t)(kOut * H + kOut) * 4, st,
                        wp + shape_w_offset(sh, L), master + shape_b_offset(sh, L), H, x[cur], cm, io, n, base, rows);
@@ -735,7 +762,9 @@ static hipError_t layered_p(LayeredScratch& ls, const NifShape& sh, const void* 
 
 hipError_t nif_layered(LayeredScratch& ls, int prec, const NifShape& shape, const void* wp, const float* master,
                        const ColourMatrix& cm, const LayeredIO& io, hipStream_t st) {
-  if (shape.hidden % 32 != 0 || shape.hidden < 32 || shape.layers < 1) return hipErrorInvalidValue;
+  if (shape.hidden % 32 != 0 || shape.hidden < 32 || shape.layers < 1 || shape.skip < 0 ||
+      (shape.skip != 0 && shape.skip >= shape.layers))
+    return hipErrorInvalidValue;
   switch (prec) {
     case NPT_FP32: return layered_p<NPT_FP32>(ls, shape, wp, master, cm, io, st);
     case NPT_FP16: return layered_p<NPT_FP16>(ls, shape, wp, master, cm, io, st);

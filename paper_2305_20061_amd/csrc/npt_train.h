@@ -13,16 +13,22 @@ namespace npt {
 
 // Shape of the MLP at run time: 64 Fourier features -> layers x [dense
 // hidden + ReLU] -> dense 3.  hidden is a multiple of 32 (the MFMA tile).
+// skip: 0, or the hidden layer (1..layers-1) whose input is the previous
+// layer's output followed by the 64 features again (skip-concat, Sec. 3.2).
 struct NifShape {
   int hidden;
   int layers;
+  int skip;
 };
-__host__ __device__ inline int shape_in(const NifShape& s, int l) { return l == 0 ? 64 : s.hidden; }
+__host__ __device__ inline int shape_in(const NifShape& s, int l) {
+  return l == 0 ? 64 : (s.skip != 0 && l == s.skip ? s.hidden + 64 : s.hidden);
+}
 __host__ __device__ inline int shape_out(const NifShape& s, int l) { return l == s.layers ? 3 : s.hidden; }
 // offsets of W_l and b_l in the flat parameter vector [W_0, b_0, ..., W_L, b_L]
 __host__ __device__ inline int64_t shape_w_offset(const NifShape& s, int l) {
-  if (l == 0) return 0;
-  return (int64_t)64 * s.hidden + s.hidden + (int64_t)(l - 1) * ((int64_t)s.hidden * s.hidden + s.hidden);
+  int64_t o = 0;
+  for (int i = 0; i < l; ++i) o += (int64_t)shape_out(s, i) * shape_in(s, i) + shape_out(s, i);
+  return o;
 }
 __host__ __device__ inline int64_t shape_b_offset(const NifShape& s, int l) {
   return shape_w_offset(s, l) + (int64_t)shape_out(s, l) * shape_in(s, l);
@@ -95,7 +101,7 @@ struct LayeredIO {
   uint32_t gw, gh;
 };
 struct LayeredScratch {
-  void* x[2] = {nullptr, nullptr};  // ping-pong activations [chunk][max(64, hidden)]
+  void* x[3] = {nullptr, nullptr, nullptr};  // ping-pong activations [chunk][hidden + 64], features [chunk][64]
   size_t cap = 0;                   // bytes of each
   void release();
 };

@@ -59,7 +59,7 @@ class npt_bvh_params(C.Structure):
 
 class npt_nif_desc(C.Structure):
     _fields_ = [("n_freq", C.c_uint32), ("hidden", C.c_uint32), ("layers", C.c_uint32), ("colour", C.c_uint32),
-                ("layered", C.c_uint32)]
+                ("layered", C.c_uint32), ("skip", C.c_uint32)]
 
 
 class npt_train_params(C.Structure):
@@ -280,13 +280,14 @@ def npt_set_env_mode(ctx, mode):
 
 
 # ---------------------------------------------------------------------- NIF
-def nif_param_count(hidden=96, layers=5):
-    return 64 * hidden + hidden + (layers - 1) * (hidden * hidden + hidden) + 3 * hidden + 3
+def nif_param_count(hidden=96, layers=5, skip=0):
+    return 64 * hidden + hidden + (layers - 1) * (hidden * hidden + hidden) + 3 * hidden + 3 + (64 * hidden if skip
+                                                                                                 else 0)
 
 
-def npt_nif_upload(ctx, params, n_freq=16, hidden=96, layers=5, stream=None, colour=0, layered=0):
+def npt_nif_upload(ctx, params, n_freq=16, hidden=96, layers=5, stream=None, colour=0, layered=0, skip=0):
     p = _host(params, np.float32)
-    d = npt_nif_desc(n_freq, hidden, layers, colour, layered)
+    d = npt_nif_desc(n_freq, hidden, layers, colour, layered, skip)
     _check(ctx, lib().npt_nif_upload(ctx, C.byref(d), _hp(p), p.size, _stream(stream)))
 
 

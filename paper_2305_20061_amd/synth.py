@@ -342,20 +342,23 @@ def uniform_env(width: int = 64, height: int = 32, value: float = 1.0):
 # --------------------------------------------------------------------------
 # NIF initial parameters (Glorot-uniform weights, zero biases)
 # --------------------------------------------------------------------------
-def nif_layer_dims(n_freq=16, hidden=96, layers=5):
+def nif_layer_dims(n_freq=16, hidden=96, layers=5, skip=0):
+    """(fan_in, fan_out) per layer; with skip > 0, hidden layer `skip` also
+    reads the 4 n_freq features (skip-concat)."""
     dims = [4 * n_freq] + [hidden] * layers + [3]
-    return [(dims[i], dims[i + 1]) for i in range(len(dims) - 1)]
+    fan_in = [dims[i] + (4 * n_freq if skip and i == skip else 0) for i in range(len(dims) - 1)]
+    return [(fan_in[i], dims[i + 1]) for i in range(len(dims) - 1)]
 
 
-def nif_param_count(n_freq=16, hidden=96, layers=5):
-    return sum(o * i + o for i, o in nif_layer_dims(n_freq, hidden, layers))
+def nif_param_count(n_freq=16, hidden=96, layers=5, skip=0):
+    return sum(o * i + o for i, o in nif_layer_dims(n_freq, hidden, layers, skip))
 
 
-def nif_init(seed: int = 3, n_freq=16, hidden=96, layers=5):
+def nif_init(seed: int = 3, n_freq=16, hidden=96, layers=5, skip=0):
     """Flat FP32 vector [W1, b1, ..., W_{L+1}, b_{L+1}], W row-major [out][in]."""
     rng = _rng(seed)
     out = []
-    for fi, fo in nif_layer_dims(n_freq, hidden, layers):
+    for fi, fo in nif_layer_dims(n_freq, hidden, layers, skip):
         a = math.sqrt(6.0 / (fi + fo))
         out.append(rng.uniform(-a, a, size=fo * fi))
         out.append(np.zeros(fo))

@@ -68,6 +68,8 @@ def test_host_only_validation(host_ctx):
     assert _code(npt.npt_nif_upload, c, np.zeros(43779), hidden=128) == "INVALID_ARG"  # count of another shape
     assert npt.nif_param_count(128, 3) == 64 * 128 + 128 + 2 * (128 * 128 + 128) + 3 * 128 + 3
     assert npt.nif_param_count() == 43779
+    assert npt.nif_param_count(128, 5, 2) == npt.nif_param_count(128, 5) + 64 * 128
+    assert _code(npt.npt_nif_upload, c, np.zeros(43779), skip=5) == "UNSUPPORTED"  # skip must be < layers
     assert _code(npt.npt_nif_upload, c, np.zeros(43779), colour=3) == "INVALID_ARG"
     assert _code(npt.npt_env_upload, c, np.zeros((4, 8, 3))) == "NO_DEVICE"
     assert _code(npt.npt_env_upload, c, -np.ones((4, 8, 3))) == "NAN_INPUT"

@@ -218,3 +218,69 @@ def test_training_reduces_loss(small_sky):
     losses = [O.nif_train_step(SHAPE, p, m, v, small_sky, seed=1, step=s, batch=256, lr=3e-3)
               for s in range(30)]
     assert np.mean(losses[-5:]) < 0.6 * np.mean(losses[:5])
+
+
+# ---- skip-concat (Sec. 3.2: the features enter again at a middle layer)
+SKIP = O.nif_shape(16, 32, 4, O.COLOUR_YUV, 2)
+
+
+def _skip_layout():
+    """(offset_W, offset_b, out, in) per layer of SKIP; layer 2 reads 32 + 64."""
+    fans = [(64, 32), (32, 32), (32 + 64, 32), (32, 32), (32, 3)]
+    out, off = [], 0
+    for fi, fo in fans:
+        out.append((off, off + fo * fi, fo, fi))
+        off += fo * fi + fo
+    return out
+
+
+def test_skip_param_count():
+    n = sum(fo * fi + fo for _, _, fo, fi in _skip_layout())
+    assert O.nif_param_count(SKIP) == n == synth.nif_param_count(16, 32, 4, 2) == synth.nif_init(1, 16, 32, 4, 2).size
+    assert n == O.nif_param_count(O.nif_shape(16, 32, 4)) + 32 * 64
+
+
+@pytest.mark.parametrize("feat", [0, 21, 63])
+def test_skip_path_closed_form(feat):
+    # every weight zero except the skip layer reading one feature into neuron
+    # 0 (bias 2), the next layer passing it on, the output reading it as Y:
+    # the features appear after the 32 hidden inputs of the skip layer
+    p = np.zeros(O.nif_param_count(SKIP))
+    lay = _skip_layout()
+    oW, ob, fo, fi = lay[2]
+    p[oW + 0 * fi + 32 + feat] = 1.0
+    p[ob + 0] = 2.0
+    oW, ob, fo, fi = lay[3]
+    p[oW + 0] = 1.0
+    oW, ob, fo, fi = lay[4]
+    p[oW + 0] = 0.5
+    k, blk = feat % 16, feat // 16
+    f = O.nif_frequency(k)
+    for u, v in ((0.1, 0.2), (0.77, 0.05)):
+        val = (np.sin if blk % 2 == 0 else np.cos)(2 * np.pi * f * (u if blk < 2 else v))
+        assert np.allclose(O.nif_forward(SKIP, p, u, v), 0.5 * (val + 2.0), atol=1e-12)
+        # the quantised forward in FP32 mode is the same function
+        assert np.allclose(O.nif_forward_q(SKIP, p, O.PREC_FP32, u, v), 0.5 * (val + 2.0), atol=1e-12)
+
+
+def test_skip_backward_matches_central_differences():
+    rng = np.random.default_rng(7)
+    p = synth.nif_init(9, 16, 32, 4, 2).astype(np.float64) + rng.normal(size=O.nif_param_count(SKIP)) * 0.01
+    uv = rng.random((5, 2))
+    target = rng.normal(size=(5, 3)) * 0.5
+    _, g = O.nif_loss_grad(SKIP, p, uv, target, 1e3)
+    lay = _skip_layout()
+    # every weight of the skip layer's feature columns, plus a random sample
+    oW, ob, fo, fi = lay[2]
+    skip_cols = [oW + j * fi + 32 + c for j in range(0, fo, 7) for c in range(0, 64, 9)]
+    idx = np.concatenate([skip_cols, rng.choice(p.size, 200, replace=False)])
+    h = 1e-5
+    worst = 0.0
+    for i in idx:
+        pp, pm = p.copy(), p.copy()
+        pp[i] += h
+        pm[i] -= h
+        fd = (O.nif_loss_grad(SKIP, pp, uv, target, 1e3, False)[0] - O.nif_loss_grad(SKIP, pm, uv, target, 1e3,
+                                                                                      False)[0]) / (2 * h)
+        worst = max(worst, abs(fd - g[i]) / max(1e-6, abs(g[i]), abs(fd)))
+    assert worst < 1e-5, worst

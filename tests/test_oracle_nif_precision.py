@@ -158,6 +158,29 @@ def _numpy_forward_q(p_deq, prec, u, v):
     return O.yuv_to_rgb_matrix() @ x
 
 
+def test_skip_quantised_forward_matches_numpy_layer_loop():
+    # skip-concat network (features again at hidden layer 2), FP16 operands:
+    # the concatenated input is rounded as one vector
+    shape = O.nif_shape(16, 32, 4, O.COLOUR_YUV, 2)
+    p = synth.nif_init(4, 16, 32, 4, 2).astype(np.float64)
+    p[-3:] = (0.6, 0.05, -0.05)
+    q = O.nif_dequantize(shape, p, O.PREC_FP16)
+    fans = [(64, 32), (32, 32), (32 + 64, 32), (32, 32), (32, 3)]
+    rnd = lambda x: x.astype(np.float16).astype(np.float64)
+    for u, v in np.random.default_rng(8).uniform(0, 1, (10, 2)):
+        feat = O.nif_features(shape, u, v)
+        x, off = feat, 0
+        for l, (fi, fo) in enumerate(fans):
+            if l == 2:
+                x = np.concatenate([x, feat])
+            W = q[off:off + fo * fi].reshape(fo, fi)
+            y = W @ rnd(x) + q[off + fo * fi:off + fo * fi + fo]
+            off += fo * fi + fo
+            x = np.maximum(y, 0.0) if l < 4 else y
+        assert np.allclose(O.nif_forward_q(shape, q, O.PREC_FP16, u, v), O.yuv_to_rgb_matrix() @ x,
+                           rtol=1e-9, atol=1e-12)
+
+
 @pytest.mark.parametrize("prec", [O.PREC_FP16, O.PREC_BF16, O.PREC_FP8])
 def test_quantised_forward_matches_numpy_layer_loop(prec):
     # BF16 via torch needs float32-exact inputs: features and activations are
