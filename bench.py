@@ -73,8 +73,9 @@ def _parse():
     p.add_argument("--calibrate-copy", action="store_true",
                    help="run one 1 GiB device copy (rocprof counter calibration)")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
-    p.add_argument("--node-format", choices=("fp32", "fp16-extent"), default="fp16-extent",
-                   help="BVH4 node encoding: FP32 boxes (112 B) or FP32 lower planes + binary16 extents (96 B)")
+    p.add_argument("--node-format", choices=("fp32", "fp16-extent", "q8"), default="fp16-extent",
+                   help="BVH4 node encoding: FP32 boxes (112 B), FP32 lower planes + binary16 extents (96 B), "
+                        "or 8-bit planes on a per-node step (64 B)")
     p.add_argument("--nif-sizes", action="store_true",
                    help="instead of the headline run: NIF model size against path rate and PSNR (one JSON line)")
     p.add_argument("--nif-study", action="store_true",
@@ -488,12 +489,11 @@ def main():
     try:
         t0 = time.perf_counter()
         # 4-wide BVH, leaf size 2, no LDS-staged levels: fastest in the sweep
-        half = args.node_format == "fp16-extent"
-        npt.npt_load_scene(ctx, scene, max_leaf=2, lds_levels=0, width=4,
-                           node_format=npt.NODES_FP16_EXTENT if half else npt.NODES_FP32)
+        fmt_code = {"fp32": npt.NODES_FP32, "fp16-extent": npt.NODES_FP16_EXTENT, "q8": npt.NODES_Q8}[args.node_format]
+        npt.npt_load_scene(ctx, scene, max_leaf=2, lds_levels=0, width=4, node_format=fmt_code)
         extra["bvh_build_ms"] = 1e3 * (time.perf_counter() - t0)
         extra["bvh"] = {**npt.npt_bvh_info(ctx), "node_format": args.node_format,
-                        "node_bytes": 96 if half else B_NODE[4]}
+                        "node_bytes": {"fp32": B_NODE[4], "fp16-extent": 96, "q8": 64}[args.node_format]}
         del scene
         npt.npt_env_upload(ctx, env)
         npt.npt_nif_upload(ctx, synth.nif_init(3))
@@ -613,7 +613,7 @@ def main():
         ctx = npt.npt_create(0)
         try:
             npt.npt_load_scene(ctx, synth.scene_for(3), max_leaf=2, lds_levels=0, width=4,
-                               node_format=npt.NODES_FP16_EXTENT if half else npt.NODES_FP32)
+                               node_format=fmt_code)
             npt.npt_nif_upload(ctx, trained)
             npt.npt_nif_set_precision(ctx, npt.FP16)
             npt.npt_set_env_mode(ctx, npt.ENV_NIF)

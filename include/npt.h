@@ -81,9 +81,12 @@ typedef struct {
  * (width 4, lds_levels 0): NPT_NODES_FP32 (112-byte nodes, FP32 boxes) or
  * NPT_NODES_FP16_EXTENT (96-byte nodes: FP32 lower planes and binary16
  * extents rounded up so that the FP32 sum lo + ext covers the box, after
- * Sec. 3.1.4; NPT_E_UNSUPPORTED if an extent exceeds 65504). */
+ * Sec. 3.1.4; NPT_E_UNSUPPORTED if an extent exceeds 65504) or NPT_NODES_Q8
+ * (64-byte nodes: per node and axis an FP32 origin and a power-of-two step,
+ * 8-bit child planes rounded outward, after Ylitie et al. 2017). */
 #define NPT_NODES_FP32 0
 #define NPT_NODES_FP16_EXTENT 1
+#define NPT_NODES_Q8 2
 typedef struct {
     uint32_t bins;
     uint32_t max_leaf;

@@ -313,6 +313,84 @@ bool compress_half_extents(FlatBvh& b, std::string& err) {
   return true;
 }
 
+bool compress_q8_nodes(FlatBvh& b, std::string& err) {
+  if (b.width != 4 || b.node_float4s != kNode4Float4s) {
+    err = "quantized nodes need 4-wide FP32 nodes";
+    return false;
+  }
+  const size_t nn = b.nodes.size() / kNode4Float4s;
+  std::vector<float4> out(nn * kNode4Q8Float4s);
+  for (size_t i = 0; i < nn; ++i) {
+    const float4* o = &b.nodes[i * kNode4Float4s];
+    const uint32_t r4[4] = {ubits(o[6].x), ubits(o[6].y), ubits(o[6].z), ubits(o[6].w)};
+    float origin[3];
+    uint32_t qlo[3] = {0, 0, 0}, qhi[3] = {0, 0, 0}, ebits = 0;
+    for (int a = 0; a < 3; ++a) {
+      const float l4[4] = {o[2 * a].x, o[2 * a].y, o[2 * a].z, o[2 * a].w};
+      const float h4[4] = {o[2 * a + 1].x, o[2 * a + 1].y, o[2 * a + 1].z, o[2 * a + 1].w};
+      float lo = INFINITY, hi = -INFINITY;
+      for (int c = 0; c < 4; ++c)
+        if (r4[c] != kEmptyChild) {
+          lo = std::min(lo, l4[c]);
+          hi = std::max(hi, h4[c]);
+        }
+      if (!(lo <= hi)) {
+        err = "quantized nodes: node without children";
+        return false;
+      }
+      origin[a] = lo;
+      // smallest power-of-two step 2^e with 254 steps covering the children;
+      // raised until every child's rounded-outward planes fit in 0..255
+      const double span = (double)hi - (double)lo;
+      int e = span > 0.0 ? (int)std::ceil(std::log2(span / 254.0)) : -126;
+      e = std::max(e, -126);
+      for (;; ++e) {
+        const float s = std::ldexp(1.0f, e);
+        bool fit = true;
+        uint32_t ql = 0, qh = 0;
+        for (int c = 0; c < 4 && fit; ++c) {
+          uint32_t a_lo = 255, a_hi = 0;  // empty child: inverted box
+          if (r4[c] != kEmptyChild) {
+            // decoded planes are the FP32 values lo + q s (q s is exact):
+            // lower plane rounded down, upper plane rounded up
+            double fl = std::floor(((double)l4[c] - (double)lo) / (double)s);
+            double fh = std::ceil(((double)h4[c] - (double)lo) / (double)s);
+            int64_t q0 = (int64_t)std::max(0.0, fl), q1 = (int64_t)fh;
+            while (q0 > 0 && lo + (float)q0 * s > l4[c]) --q0;
+            while (q1 <= 255 && lo + (float)q1 * s < h4[c]) ++q1;
+            if (q1 > 255 || !(lo + (float)q0 * s <= l4[c])) {
+              fit = false;
+              break;
+            }
+            a_lo = (uint32_t)q0;
+            a_hi = (uint32_t)q1;
+          }
+          ql |= a_lo << (8 * c);
+          qh |= a_hi << (8 * c);
+        }
+        if (fit) {
+          qlo[a] = ql;
+          qhi[a] = qh;
+          break;
+        }
+        if (e > 127) {
+          err = "quantized nodes: no step covers a box";
+          return false;
+        }
+      }
+      ebits |= (uint32_t)(e + 128) << (8 * a);
+    }
+    float4* h = &out[i * kNode4Q8Float4s];
+    h[0] = make_float4(origin[0], origin[1], origin[2], bits(ebits));
+    h[1] = make_float4(bits(qlo[0]), bits(qhi[0]), bits(qlo[1]), bits(qhi[1]));
+    h[2] = make_float4(bits(qlo[2]), bits(qhi[2]), 0.0f, 0.0f);
+    h[3] = o[6];
+  }
+  b.nodes = std::move(out);
+  b.node_float4s = kNode4Q8Float4s;
+  return true;
+}
+
 bool build_bvh(const BuildInput& in, uint32_t bins, uint32_t max_leaf, uint32_t lds_levels, uint32_t width,
                FlatBvh& out,
                std::string& err) {

@@ -51,6 +51,11 @@ bool build_bvh(const BuildInput& in, uint32_t bins, uint32_t max_leaf, uint32_t 
 // beyond 65504.
 bool compress_half_extents(FlatBvh& b, std::string& err);
 
+// Rewrites the 7-row FP32 nodes of a 4-wide tree as 4-row nodes with 8-bit
+// child planes on a per-node, per-axis power-of-two step (npt_shared.h
+// layout), each decoded plane rounded outward and checked in FP32.
+bool compress_q8_nodes(FlatBvh& b, std::string& err);
+
 // One object of a two-level scene: bottom tree `tree` placed in the world at
 // translate + scale * x (scale > 0), hits reported with instance id `id`.
 struct Placement {

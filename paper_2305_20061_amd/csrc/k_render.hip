@@ -124,7 +124,6 @@ __device__ __forceinline__ float safe_inverse(float x) {
 // 16; y at 32 / 48, z at 64 / 80), and no per-child min / max is needed.
 struct RayFrame {
   V3 o, d;
-  Shear sh;
   float ix, iy, iz;
   float ox_n, oy_n, oz_n;  // origin terms of the entry planes
   float ox_f, oy_f, oz_f;  // and of the exit planes
@@ -144,7 +143,6 @@ __device__ __forceinline__ RayFrame make_frame(V3 o, V3 d) {
   RayFrame f;
   f.o = o;
   f.d = d;
-  f.sh = make_shear(d);
   f.ix = safe_inverse(d.x);
   f.iy = safe_inverse(d.y);
   f.iz = safe_inverse(d.z);
@@ -174,6 +172,9 @@ __device__ __forceinline__ void slab(const RayFrame& f, float lx, float hx, floa
 template <bool kCount>
 __device__ __forceinline__ void test_leaf(const SceneView& sc, const RayFrame& f, uint32_t ref, uint32_t inst,
                                           Hit& h, uint32_t* n_prims) {
+  // the shear constants of the watertight test are recomputed per leaf
+  // rather than kept per lane: six fewer live registers during traversal
+  const Shear sh = make_shear(f.d);
   const uint32_t first = (ref >> 3) & 0x0FFFFFFFu;
   const uint32_t count = (ref & 7u) + 1u;
   if constexpr (kCount) *n_prims += count;
@@ -184,7 +185,7 @@ __device__ __forceinline__ void test_leaf(const SceneView& sc, const RayFrame& f
     float t = 0.0f;
     bool hit;
     if (__float_as_uint(s2.w) == kPrimTriangle)
-      hit = hit_triangle(f.o, f.sh, V3{s0.x, s0.y, s0.z}, V3{s1.x, s1.y, s1.z}, V3{s2.x, s2.y, s2.z}, h.t, t);
+      hit = hit_triangle(f.o, sh, V3{s0.x, s0.y, s0.z}, V3{s1.x, s1.y, s1.z}, V3{s2.x, s2.y, s2.z}, h.t, t);
     else
       hit = hit_sphere(f.o, f.d, V3{s0.x, s0.y, s0.z}, s1.x, h.t, t);
     // a hit has t <= h.t, so "t < h.t or a smaller key" is the tie rule;
@@ -300,14 +301,65 @@ __device__ __forceinline__ bool visit4h(const char* base, uint32_t off, const Ra
   return true;
 }
 
+// One 4-wide node with 8-bit child planes (kNode4Q8Float4s layout): per
+// axis the entry and exit plane words are chosen once per ray from the
+// direction sign, and child c's plane is fma(q_c, 2^e, origin), the FP32
+// value the builder checked.  An empty child (qlo 255 > qhi 0) has an
+// inverted box, which a far-away tiny node's slack could still accept, so
+// it is also dropped by its ref.
+template <class S>
+__device__ __forceinline__ bool visit4q(const char* base, uint32_t off, const RayFrame& f, float lim, S& st,
+                                        int& sp, uint32_t& ref) {
+  const float4 q0 = *reinterpret_cast<const float4*>(base + off);
+  const uint4 q1 = *reinterpret_cast<const uint4*>(base + off + 16u);
+  const uint4 q2 = *reinterpret_cast<const uint4*>(base + off + 32u);
+  const float4 rf = *reinterpret_cast<const float4*>(base + off + 48u);
+  uint32_t r0 = __float_as_uint(rf.x), r1 = __float_as_uint(rf.y), r2 = __float_as_uint(rf.z),
+           r3 = __float_as_uint(rf.w);
+  const uint32_t eb = __float_as_uint(q0.w);
+  const float sx = ldexpf(1.0f, (int)(eb & 255u) - 128), sy = ldexpf(1.0f, (int)((eb >> 8) & 255u) - 128),
+              sz = ldexpf(1.0f, (int)((eb >> 16) & 255u) - 128);
+  const bool px = f.ix >= 0.0f, py = f.iy >= 0.0f, pz = f.iz >= 0.0f;
+  const uint32_t nx = px ? q1.x : q1.y, fx = px ? q1.y : q1.x;
+  const uint32_t ny = py ? q1.z : q1.w, fy = py ? q1.w : q1.z;
+  const uint32_t nz = pz ? q2.x : q2.y, fz = pz ? q2.y : q2.x;
+  auto plane = [](uint32_t w, int c, float s, float o) {
+    return __builtin_fmaf((float)((w >> (8 * c)) & 255u), s, o);
+  };
+  auto child = [&](int c) {
+    return child_entry(f, plane(nx, c, sx, q0.x), plane(fx, c, sx, q0.x), plane(ny, c, sy, q0.y),
+                       plane(fy, c, sy, q0.y), plane(nz, c, sz, q0.z), plane(fz, c, sz, q0.z), lim);
+  };
+  const float inf = __builtin_inff();
+  float k0 = child(0), k1 = child(1), k2 = child(2), k3 = child(3);
+  k1 = r1 == kEmptyChild ? inf : k1;
+  k2 = r2 == kEmptyChild ? inf : k2;
+  k3 = r3 == kEmptyChild ? inf : k3;
+  order2(k0, r0, k1, r1);
+  order2(k2, r2, k3, r3);
+  order2(k0, r0, k2, r2);
+  order2(k1, r1, k3, r3);
+  order2(k1, r1, k2, r2);
+  __asm__ volatile("" : : "v"(r0), "v"(r1), "v"(r2), "v"(r3));
+  if (!(k0 < inf)) return false;
+  st.push3(sp, r3, k3 < inf, r2, k2 < inf, r1, k1 < inf);
+  ref = r0;
+  return true;
+}
+
 // Tree kinds of the traversal (the kWidth template argument): widths 2 and
 // 4 of one-level trees, the instanced (two-level, 4-wide) traversal, and
 // the 4-wide kinds with binary16-extent nodes.
 constexpr int kTwoLevel = 1;
 constexpr int kTwoLevelHalf = 3;
 constexpr int kHalf4 = 5;
-__host__ __device__ constexpr bool is_two_level(int w) { return w == kTwoLevel || w == kTwoLevelHalf; }
+constexpr int kQ84 = 6;
+constexpr int kTwoLevelQ8 = 7;
+__host__ __device__ constexpr bool is_two_level(int w) {
+  return w == kTwoLevel || w == kTwoLevelHalf || w == kTwoLevelQ8;
+}
 __host__ __device__ constexpr bool half_nodes(int w) { return w == kHalf4 || w == kTwoLevelHalf; }
+__host__ __device__ constexpr bool q8_nodes(int w) { return w == kQ84 || w == kTwoLevelQ8; }
 
 // The world ray of a two-level traversal waits in LDS (six values per lane,
 // stride kStride) rather than in registers: it is needed only when an
@@ -408,6 +460,9 @@ __device__ __forceinline__ bool trav_node(const SceneView& sc, const float4* lds
   } else if constexpr (half_nodes(kWidth)) {
     const uint32_t off = tv.ref * (kNode4HalfFloat4s * 16u);  // node arrays stay below 4 GiB
     if (visit4h(reinterpret_cast<const char*>(sc.nodes), off, tv.f, lim, st, tv.sp, tv.ref)) return true;
+  } else if constexpr (q8_nodes(kWidth)) {
+    const uint32_t off = tv.ref * (kNode4Q8Float4s * 16u);
+    if (visit4q(reinterpret_cast<const char*>(sc.nodes), off, tv.f, lim, st, tv.sp, tv.ref)) return true;
   } else {
     bool entered;
     const uint32_t off = tv.ref * (kNode4Float4s * 16u);  // node arrays stay below 4 GiB
@@ -542,7 +597,10 @@ __global__ void k_pass_init(uint32_t* cnt, uint32_t paths) {
 // do not wait for the slowest ray of their wave.
 // ---------------------------------------------------------------------------
 template <int kWidth, int kStack, bool kCount, bool kLds>
-__global__ __launch_bounds__(kTraceBlock) void k_extend(SceneView sc, uint32_t depth, RayQueue in, float4* hits,
+// Six waves per SIMD (at most 80 VGPRs): the extra waves hide texture-cache
+// latency; measured 11 % faster on the large-BVH scene than the five the
+// unconstrained allocation allows, seven spills too much.
+__global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_extend(SceneView sc, uint32_t depth, RayQueue in, float4* hits,
                                                         uint32_t* cnt, unsigned long long* visit_cnt) {
   extern __shared__ float4 lds_nodes[];
   using Stack = LaneStack<kStack, kTraceBlock>;
@@ -914,13 +972,19 @@ hipError_t launch_extend(int stack_depth, const SceneView& sc, uint32_t depth, u
   }
   const bool c = visit_cnt != nullptr;
   const bool staged = sc.lds_nodes > 0;
-  const bool half = sc.node_float4s == kNode4HalfFloat4s;
+  // node formats of 4-wide trees (a binary node is also four float4 long)
+  const bool half = sc.width == 4 && sc.node_float4s == kNode4HalfFloat4s;
+  const bool q8 = sc.width == 4 && sc.node_float4s == kNode4Q8Float4s;
   if (sc.two_level && half) {
     NPT_LAUNCH_EXTEND_S(kTwoLevelHalf, false)
+  } else if (sc.two_level && q8) {
+    NPT_LAUNCH_EXTEND_S(kTwoLevelQ8, false)
   } else if (sc.two_level) {
     NPT_LAUNCH_EXTEND_S(kTwoLevel, false)
   } else if (half) {
     NPT_LAUNCH_EXTEND_S(kHalf4, false)
+  } else if (q8) {
+    NPT_LAUNCH_EXTEND_S(kQ84, false)
   } else if (sc.width == 4) {
     if (staged) {
       NPT_LAUNCH_EXTEND_S(4, true)
@@ -994,13 +1058,19 @@ hipError_t launch_trace_primary(int stack_depth, const SceneView& sc, const Came
   else if (stack_depth <= 64) NPT_LAUNCH_PRIMARY(W, 64); \
   else NPT_LAUNCH_PRIMARY(W, 128);
   if (stack_depth > 128) return hipErrorInvalidValue;
-  const bool half = sc.node_float4s == kNode4HalfFloat4s;
+  // node formats of 4-wide trees (a binary node is also four float4 long)
+  const bool half = sc.width == 4 && sc.node_float4s == kNode4HalfFloat4s;
+  const bool q8 = sc.width == 4 && sc.node_float4s == kNode4Q8Float4s;
   if (sc.two_level && half) {
     NPT_LAUNCH_PRIMARY_S(kTwoLevelHalf)
+  } else if (sc.two_level && q8) {
+    NPT_LAUNCH_PRIMARY_S(kTwoLevelQ8)
   } else if (sc.two_level) {
     NPT_LAUNCH_PRIMARY_S(kTwoLevel)
   } else if (half) {
     NPT_LAUNCH_PRIMARY_S(kHalf4)
+  } else if (q8) {
+    NPT_LAUNCH_PRIMARY_S(kQ84)
   } else if (sc.width == 4) {
     NPT_LAUNCH_PRIMARY_S(4)
   } else {

@@ -373,10 +373,10 @@ extern "C" int npt_build_bvh(npt_ctx* c, const npt_bvh_params* p, void* stream) 
   const uint32_t width = p && p->width ? p->width : 4;
   const uint32_t node_format = p ? p->node_format : NPT_NODES_FP32;
   if (width != 2 && width != 4) return fail(c, NPT_E_INVALID_ARG, "BVH width must be 2 or 4");
-  if (node_format != NPT_NODES_FP32 && node_format != NPT_NODES_FP16_EXTENT)
+  if (node_format != NPT_NODES_FP32 && node_format != NPT_NODES_FP16_EXTENT && node_format != NPT_NODES_Q8)
     return fail(c, NPT_E_INVALID_ARG, "unknown BVH node format");
-  if (node_format == NPT_NODES_FP16_EXTENT && (width != 4 || lds_levels != 0))
-    return fail(c, NPT_E_INVALID_ARG, "FP16-extent nodes need width 4 and lds_levels 0");
+  if (node_format != NPT_NODES_FP32 && (width != 4 || lds_levels != 0))
+    return fail(c, NPT_E_INVALID_ARG, "compressed nodes need width 4 and lds_levels 0");
   if (bins < 4 || bins > 256 || max_leaf < 1 || max_leaf > kMaxLeaf || lds_levels > 8)
     return fail(c, NPT_E_INVALID_ARG, "bvh params out of range");
   const bool has_base = !c->tris.empty() || !c->spheres.empty();
@@ -444,6 +444,7 @@ extern "C" int npt_build_bvh(npt_ctx* c, const npt_bvh_params* p, void* stream) 
     if (!build_two_level(bottoms, objects, bins, b, records, stack_need, e)) return fail(c, NPT_E_INVALID_ARG, e);
   }
   if (node_format == NPT_NODES_FP16_EXTENT && !compress_half_extents(b, e)) return fail(c, NPT_E_UNSUPPORTED, e);
+  if (node_format == NPT_NODES_Q8 && !compress_q8_nodes(b, e)) return fail(c, NPT_E_UNSUPPORTED, e);
   if (trace_stack_size(stack_need) == 0)
     return fail(c, NPT_E_UNSUPPORTED, "BVH deeper than the 128-entry traversal stack");
   // the traversal addresses nodes with 32-bit byte offsets

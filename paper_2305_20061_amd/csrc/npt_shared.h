@@ -35,6 +35,15 @@ constexpr uint32_t kNode4Float4s = 7;
 // have lo = +inf and ext = 0.
 constexpr uint32_t kNode4HalfFloat4s = 6;
 
+// BVH4 node with 8-bit child boxes (after Ylitie et al. 2017), 64 bytes:
+//   q0 = (origin.x, origin.y, origin.z, step exponents e_x | e_y << 8 | e_z << 16, each + 128)
+//   q1 = (qlo.x, qhi.x, qlo.y, qhi.y), q2 = (qlo.z, qhi.z, -, -): byte c of a
+//        word is child c's plane, origin + q 2^e (the FP32 sum; q 2^e is exact)
+//   q3 = (ref0, ref1, ref2, ref3)
+// The builder rounds lower planes down and upper planes up and checks the
+// FP32 sums; empty children have qlo = 255, qhi = 0 and ref kEmptyChild.
+constexpr uint32_t kNode4Q8Float4s = 4;
+
 // Primitive slot, 48 bytes, leaf order:
 //   triangle: s0 = (v0, prim id), s1 = (v1, material), s2 = (v2, kPrimTriangle)
 //   sphere:   s0 = (centre, prim id), s1 = (radius, 0, 0, material), s2 = (0, 0, 0, kPrimSphere)

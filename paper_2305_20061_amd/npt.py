@@ -24,7 +24,7 @@ ERRORS = {-1: "INVALID_ARG", -2: "NO_SCENE", -3: "NO_ENV", -4: "OOM", -5: "HIP",
 NPT_E = {v: k for k, v in ERRORS.items()}
 LAMBERT, MIRROR, DIELECTRIC, EMITTER = 0, 1, 2, 3
 ENV_MAP, ENV_NIF, ENV_NONE = 0, 1, 2
-NODES_FP32, NODES_FP16_EXTENT = 0, 1
+NODES_FP32, NODES_FP16_EXTENT, NODES_Q8 = 0, 1, 2
 COLOUR_YUV, COLOUR_RGB, COLOUR_YCOCG = 0, 1, 2
 FP32, FP16, BF16, FP8 = 0, 1, 2, 3
 MAX_DEPTH = 64

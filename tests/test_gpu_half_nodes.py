@@ -1,9 +1,10 @@
-"""BVH4 nodes with binary16 extents (Sec. 3.1.4's FP16-extent proposal): the
-upper planes are FP32 sums lo + ext that the builder keeps >= the true
-boxes, so the traversal may visit more but never drops a primitive.  The
-closest hit is defined over all primitives (ties to the lowest id), so first
-hits match the oracle bit for bit and renders are identical to those of the
-FP32-node tree, one- and two-level."""
+"""Compressed BVH4 nodes: binary16 extents (Sec. 3.1.4's FP16-extent
+proposal) and 8-bit child planes on a power-of-two step.  Either way the
+decoded planes are FP32 values the builder keeps outside the true boxes, so
+the traversal may visit more but never drops a primitive.  The closest hit
+is defined over all primitives (ties to the lowest id), so first hits match
+the oracle bit for bit and renders are identical to those of the FP32-node
+tree, one- and two-level."""
 import numpy as np
 import pytest
 
@@ -14,20 +15,21 @@ from gpu_util import gpu_primary, gpu_render, make_ctx, oracle_scene, rel_rmse
 from test_gpu_instancing import check_primary, small_instanced_scene
 
 pytestmark = pytest.mark.gpu
-HALF = npt.NODES_FP16_EXTENT
+FORMATS = [npt.NODES_FP16_EXTENT, npt.NODES_Q8]
 
 
+@pytest.mark.parametrize("fmt", FORMATS)
 @pytest.mark.parametrize("cfg,W,H", [(0, 128, 128), (1, 96, 96), (2, 160, 120), (3, 192, 108)])
-def test_half_node_primary_hits_match_oracle(cfg, W, H):
+def test_half_node_primary_hits_match_oracle(cfg, W, H, fmt):
     scene = synth.scene_for(cfg)
-    ctx = make_ctx(scene, lds_levels=0, node_format=HALF)
+    ctx = make_ctx(scene, lds_levels=0, node_format=fmt)
     try:
         for sample in (0, 3):
             gp, gi, gt, gn = gpu_primary(ctx, W, H, sample, seed=1)
             osc, cam = oracle_scene(scene)
             op, oi, ot, on = O.trace_primary(osc, cam, W, H, sample, 1)
             agree = np.mean(gp == op)
-            print(f"FP16-extent nodes, cfg {cfg} sample {sample}: id agreement {agree:.6f}")
+            print(f"node format {fmt}, cfg {cfg} sample {sample}: id agreement {agree:.6f}")
             assert agree >= 0.9999
             same = (gp == op) & (op != O.MISS)
             assert np.array_equal(gt[same], ot[same])
@@ -36,9 +38,10 @@ def test_half_node_primary_hits_match_oracle(cfg, W, H):
         npt.npt_destroy(ctx)
 
 
-def test_half_node_instanced_primary_hits_match_oracle():
+@pytest.mark.parametrize("fmt", FORMATS)
+def test_half_node_instanced_primary_hits_match_oracle(fmt):
     scene = small_instanced_scene()
-    ctx = make_ctx(scene, max_leaf=2, node_format=HALF)
+    ctx = make_ctx(scene, max_leaf=2, node_format=fmt)
     try:
         for sample in (0, 5):
             oi = check_primary(scene, ctx, 192, 108, sample, 3)
@@ -51,20 +54,22 @@ def test_half_node_instanced_primary_hits_match_oracle():
 def test_half_node_renders_equal_fp32_node_renders(cfg, sky_map):
     scene = small_instanced_scene() if cfg == "instanced" else synth.scene_for(cfg)
     imgs = []
-    for fmt in (npt.NODES_FP32, HALF):
+    for fmt in [npt.NODES_FP32] + FORMATS:
         ctx = make_ctx(scene, env=sky_map, lds_levels=0, max_leaf=2, node_format=fmt)
         try:
             npt.npt_set_env_mode(ctx, npt.ENV_MAP)
             imgs.append(gpu_render(ctx, 96, 64, 2, 6, 5))
         finally:
             npt.npt_destroy(ctx)
-    print(f"cfg {cfg}: FP16-extent vs FP32 nodes max |diff| {np.abs(imgs[0] - imgs[1]).max():.3e}")
-    assert np.array_equal(imgs[0], imgs[1])
+    for k, fmt in enumerate(FORMATS):
+        print(f"cfg {cfg}: node format {fmt} vs FP32 nodes max |diff| {np.abs(imgs[0] - imgs[k + 1]).max():.3e}")
+        assert np.array_equal(imgs[0], imgs[k + 1])
 
 
-def test_half_node_env_render_matches_oracle(sky_map):
+@pytest.mark.parametrize("fmt", FORMATS)
+def test_half_node_env_render_matches_oracle(fmt, sky_map):
     scene = synth.scene_for(2)
-    ctx = make_ctx(scene, env=sky_map, lds_levels=0, node_format=HALF)
+    ctx = make_ctx(scene, env=sky_map, lds_levels=0, node_format=fmt)
     try:
         npt.npt_set_env_mode(ctx, npt.ENV_MAP)
         g = gpu_render(ctx, 96, 72, 4, 8, 2)

@@ -85,7 +85,7 @@ def test_base_mesh_as_identity_instance_hits_the_same():
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("node_format", [npt.NODES_FP16_EXTENT, npt.NODES_FP32])
+@pytest.mark.parametrize("node_format", [npt.NODES_FP16_EXTENT, npt.NODES_FP32, npt.NODES_Q8])
 def test_large_bvh_full_size_sampled_hits_match_oracle(node_format):
     # the large-BVH workload itself (2048^2 terrain, 256 instances, leaf size
     # 2 and FP16-extent nodes as benchmarked) at 1920x1080: the GPU traces
