@@ -630,7 +630,7 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(6))
       if (pool == pool_end) {
         uint32_t b = 0;
         if (lane == 0) b = atomicAdd(work, (uint32_t)kWave);
-        b = __shfl(b, 0);
+        b = __builtin_amdgcn_readfirstlane(b);  // wave-uniform: the pool bounds live in SGPRs
         if (b >= n) {
           drained = true;
           break;
