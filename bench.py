@@ -386,10 +386,11 @@ def nif_study(args):
                                     "grid": f"{w}x{h} texel centres"}, "data": "synthetic"}))
 
 
-# (hidden, layers, skip-concat layer): the paper's sweep sizes, the workload's
-# network, and the paper's own architecture (H128 L5, features again at the
-# middle layer)
-NIF_SIZES = [(64, 2, 0), (96, 5, 0), (128, 5, 2), (256, 4, 0), (1024, 8, 0)]
+# (hidden, layers, skip-concat layer, frequencies): the paper's sweep sizes,
+# the workload's network, and the paper's own architecture (40-d features,
+# H128 L5, features again at the middle layer) with and without its 40-d
+# features
+NIF_SIZES = [(64, 2, 0, 16), (96, 5, 0, 16), (128, 5, 2, 16), (128, 5, 2, 10), (256, 4, 0, 16), (1024, 8, 0, 16)]
 
 
 def nif_sizes(args):
@@ -427,11 +428,11 @@ def nif_sizes(args):
         npt.npt_render(ctx, W, H, spp, depth, 1, out)
         torch.cuda.synchronize()
         img_map = out.cpu().numpy().astype(np.float64)
-        runs = [(hd, ly, sk, 1) for hd, ly, sk in NIF_SIZES] + [(96, 5, 0, 0)]
-        for hidden, layers, skip, layered in runs:
+        runs = [(hd, ly, sk, nf, 1) for hd, ly, sk, nf in NIF_SIZES] + [(96, 5, 0, 16, 0)]
+        for hidden, layers, skip, nf, layered in runs:
             npt.npt_nif_set_precision(ctx, npt.FP16)
-            npt.npt_nif_upload(ctx, synth.nif_init(3, 16, hidden, layers, skip), hidden=hidden, layers=layers,
-                               layered=layered, skip=skip)
+            npt.npt_nif_upload(ctx, synth.nif_init(3, nf, hidden, layers, skip), n_freq=nf, hidden=hidden,
+                               layers=layers, layered=layered, skip=skip)
             tr = npt.npt_nif_train(ctx, npt.train_params(batch=65536, samples=args.train_samples, seed=1,
                                                          grad_prec=npt.FP16))
             npt.npt_nif_set_precision(ctx, npt.FP32)
@@ -443,10 +444,11 @@ def nif_sizes(args):
             npt.npt_set_render_options(ctx, rr_start=3, kernel_timing=1)
             el, st = _timed_renders(npt, torch, ctx, W, H, spp, depth, 1, out, 2, 1)
             npt.npt_set_render_options(ctx, rr_start=3)
-            flop = 2 * (64 * hidden + (layers - 1) * hidden * hidden + 3 * hidden + (64 * hidden if skip else 0))
-            rows.append({"hidden": hidden, "layers": layers, "skip": skip,
+            F = 4 * nf
+            flop = 2 * (F * hidden + (layers - 1) * hidden * hidden + 3 * hidden + (F * hidden if skip else 0))
+            rows.append({"hidden": hidden, "layers": layers, "skip": skip, "features": F,
                          "path": "layered GEMMs" if layered else "LDS-resident",
-                         "params": npt.nif_param_count(hidden, layers, skip), "flop_per_query": flop,
+                         "params": npt.nif_param_count(hidden, layers, skip, nf), "flop_per_query": flop,
                          "train_ms": tr["ms"], "last_loss": tr["last_loss"], **psnr,
                          "path_samples_per_s": W * H * spp * 2 / el, "nif_ms_per_render": st["ms_env"],
                          "nif_tflops": st["env_queries"] * flop / (st["ms_env"] * 1e-3) / 1e12,

@@ -97,9 +97,10 @@ typedef struct {
 
 /* HDR-NIF shape (Sec. 3.2): 4*n_freq Fourier features -> layers x
  * [dense hidden + ReLU] -> dense 3 -> fixed colour matrix to log-space RGB.
- * Supported: n_freq = 16; hidden 32..1024, a multiple of 32; layers 1..8.
- * The 16/96/5 network runs on the LDS-resident MFMA kernel (FP32, FP16,
- * BF16, FP8); every other shape, or layered = 1, on layer-serial MFMA GEMMs
+ * Supported: n_freq 1..16 (frequencies round(2^((k+1)/2)), k < n_freq);
+ * hidden 32..1024, a multiple of 32; layers 1..8.  The 16/96/5 network runs
+ * on the LDS-resident MFMA kernel (FP32, FP16, BF16, FP8); every other
+ * shape, or layered = 1, on layer-serial MFMA GEMMs
  * (FP32, FP16, BF16; Sec. 4.6 sweeps model sizes).  skip: 0, or the hidden
  * layer (1..layers-1) whose input is the previous layer's output followed by
  * the features again (the paper's skip-concat, Sec. 3.2; layered path).
@@ -245,8 +246,8 @@ int npt_set_env_mode(npt_ctx *ctx, int mode);
 
 /* ---- HDR-NIF (Sec. 3.2) ----------------------------------------------------- */
 /* params_fp32: [W1, b1, ..., W_{L+1}, b_{L+1}], W row-major [out][in], n
- * values (43,779 for 16/96/5; 64 H + H + (L - 1)(H^2 + H) + 3 H + 3, plus
- * 64 H with a skip-concat).  Becomes the FP32 master copy; Adam state is reset;
+ * values (43,779 for 16/96/5; with F = 4 n_freq: F H + H + (L - 1)(H^2 + H)
+ * + 3 H + 3, plus F H with a skip-concat).  Becomes the FP32 master copy; Adam state is reset;
  * the inference pack of the current precision is rebuilt; desc->colour
  * selects the output colour space (NPT_E_INVALID_ARG if unknown). */
 int npt_nif_upload(npt_ctx *ctx, const npt_nif_desc *desc, const float *params_fp32,

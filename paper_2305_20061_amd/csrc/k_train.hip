@@ -25,21 +25,20 @@ constexpr int kChunk = 2048;  // batch rows per split-K chunk of the weight grad
 // ---------------------------------------------------------------------------
 template <int P>
 __global__ __launch_bounds__(256) void k_train_sample(TrainTargets t, uint32_t key0, uint32_t key1, uint32_t step,
-                                                     uint32_t B, typename Prec<P>::Elem* X0, float* target) {
+                                                     uint32_t B, int nf, typename Prec<P>::Elem* X0, float* target) {
   for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < B; b += gridDim.x * blockDim.x) {
     const U4 r = philox(b, step, 0, kRngTrain, key0, key1);
     const float u = unit_float(r.x), v = unit_float(r.y);
-    typename Prec<P>::Elem* x = X0 + (size_t)b * kFeat;
-#pragma unroll
-    for (int k = 0; k < kFreq; ++k) {
+    typename Prec<P>::Elem* x = X0 + (size_t)b * 4 * nf;
+    for (int k = 0; k < nf; ++k) {
       const float f = (float)frequency(k);
       float su, cu, sv, cv;
       sincos_turns(frac_product(f, u), su, cu);
       sincos_turns(frac_product(f, v), sv, cv);
       x[k] = Prec<P>::cvt(su);
-      x[kFreq + k] = Prec<P>::cvt(cu);
-      x[2 * kFreq + k] = Prec<P>::cvt(sv);
-      x[3 * kFreq + k] = Prec<P>::cvt(cv);
+      x[nf + k] = Prec<P>::cvt(cu);
+      x[2 * nf + k] = Prec<P>::cvt(sv);
+      x[3 * nf + k] = Prec<P>::cvt(cv);
     }
     const float3 c = env_bilinear(t.map, (int)t.w, (int)t.h, u, v);
     target[3 * (size_t)b] = log1pf(c.x);
@@ -48,14 +47,14 @@ __global__ __launch_bounds__(256) void k_train_sample(TrainTargets t, uint32_t k
   }
 }
 
-// columns [col0, col0 + 64) of rows of dst (row stride ld) := the 64
+// columns [col0, col0 + F) of rows of dst (row stride ld) := the F
 // features of each row of X0 (the skip-concat input)
 template <int P>
-__global__ __launch_bounds__(256) void k_copy_features(const typename Prec<P>::Elem* X0, uint32_t rows,
+__global__ __launch_bounds__(256) void k_copy_features(const typename Prec<P>::Elem* X0, uint32_t rows, int F,
                                                       typename Prec<P>::Elem* dst, int ld, int col0) {
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < (uint64_t)rows * kFeat;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < (uint64_t)rows * F;
        i += (uint64_t)gridDim.x * blockDim.x) {
-    const uint64_t r = i / kFeat, k = i % kFeat;
+    const uint64_t r = i / F, k = i % F;
     dst[r * ld + col0 + k] = X0[i];
   }
 }
@@ -86,23 +85,28 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
   constexpr int KPL = Prec<P>::KPL;
   const int lane = threadIdx.x & 63;
   const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int mt = g.M / 32, nt = g.N / 32;
+  const int mt = g.M / 32, nt = (g.N + 31) / 32;  // M is a multiple of 32; the last column tile may be partial
   if (wave >= mt * nt * g.splits) return;
   const int split = wave / (mt * nt), rem = wave % (mt * nt);
   const int m0 = (rem / nt) * 32, n0 = (rem % nt) * 32;
   const int h = lane / 32, c = lane % 32;
+  const bool col_ok = n0 + c < g.N;
   const int kbeg = split * g.k_chunk, kend = min(g.K, kbeg + g.k_chunk);
   const Elem* A = static_cast<const Elem*>(g.A);
   const Elem* B = static_cast<const Elem*>(g.B);
   f32x16 acc;
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-  for (int k0 = kbeg; k0 < kend; k0 += 2 * KPL) {
+  const Elem zero = Prec<P>::cvt(0.0f);
+  // whole K-blocks with vector loads, then (K not a multiple of 2 KPL) one
+  // K-block with element-wise, bounds-checked loads
+  int k0 = kbeg;
+  for (; k0 + 2 * KPL <= kend; k0 += 2 * KPL) {
     const int kk = k0 + h * KPL;
     Frag a, b;
     if constexpr (KPL == 1) {
       a = A[(int64_t)(m0 + c) * g.a_sm + (int64_t)kk * g.a_sk];
-      b = B[(int64_t)kk * g.b_sk + (int64_t)(n0 + c) * g.b_sn];
+      b = col_ok ? B[(int64_t)kk * g.b_sk + (int64_t)(n0 + c) * g.b_sn] : zero;
     } else {
       if constexpr (AK) {
         a = *reinterpret_cast<const Frag*>(A + (int64_t)(m0 + c) * g.a_sm + kk);
@@ -110,7 +114,10 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
 #pragma unroll
         for (int e = 0; e < KPL; ++e) a[e] = A[(int64_t)(m0 + c) * g.a_sm + (int64_t)(kk + e) * g.a_sk];
       }
-      if constexpr (BK) {
+      if (!col_ok) {
+#pragma unroll
+        for (int e = 0; e < KPL; ++e) b[e] = zero;
+      } else if constexpr (BK) {
         b = *reinterpret_cast<const Frag*>(B + (int64_t)(n0 + c) * g.b_sn + kk);
       } else {
 #pragma unroll
@@ -119,9 +126,26 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
     }
     acc = Prec<P>::mma(a, b, acc);
   }
+  if (k0 < kend) {
+    const int kk = k0 + h * KPL;
+    Frag a, b;
+    if constexpr (KPL == 1) {
+      a = kk < kend ? A[(int64_t)(m0 + c) * g.a_sm + (int64_t)kk * g.a_sk] : zero;
+      b = (col_ok && kk < kend) ? B[(int64_t)kk * g.b_sk + (int64_t)(n0 + c) * g.b_sn] : zero;
+    } else {
+#pragma unroll
+      for (int e = 0; e < KPL; ++e) {
+        const bool in = kk + e < kend;
+        a[e] = in ? A[(int64_t)(m0 + c) * g.a_sm + (int64_t)(kk + e) * g.a_sk] : zero;
+        b[e] = (in && col_ok) ? B[(int64_t)(kk + e) * g.b_sk + (int64_t)(n0 + c) * g.b_sn] : zero;
+      }
+    }
+    acc = Prec<P>::mma(a, b, acc);
+  }
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int m = m0 + acc_row(0, h, r), n = n0 + c;
+    if (!col_ok) continue;
     float val = acc[r];
     if (g.mode == 0) {
       val = fmaxf(val + g.bias[n], 0.0f);
@@ -360,7 +384,7 @@ static uint32_t elem_size(int prec) { return prec == NPT_FP32 ? 4u : 2u; }
 // prec and shape sh needs (and the per-step loss record to `steps`)
 static hipError_t ensure_scratch(TrainScratch& s, uint32_t B, int prec, uint32_t steps, const NifShape& sh) {
   const size_t es = elem_size(prec), np = (size_t)shape_params(sh), H = (size_t)sh.hidden;
-  size_t act_cols = 64;
+  size_t act_cols = (size_t)shape_feat(sh);
   for (int l = 1; l <= sh.layers; ++l) act_cols += (size_t)shape_in(sh, l);
   const size_t need[10] = {(size_t)B * act_cols * es,
                            2 * (size_t)B * H * es,
@@ -390,7 +414,7 @@ static int grid_for_params(int64_t np) { return (int)std::min<int64_t>(4096, (np
 
 template <int P, bool AK, bool BK>
 static hipError_t gemm(const GemmDesc& g, hipStream_t st) {
-  const int waves = (g.M / 32) * (g.N / 32) * g.splits;
+  const int waves = (g.M / 32) * ((g.N + 31) / 32) * g.splits;
   hipLaunchKernelGGL((k_gemm<P, AK, BK>), dim3((waves + 3) / 4), dim3(256), 0, st, g);
   return hipGetLastError();
 }
@@ -413,10 +437,10 @@ static hipError_t step_gradient(TrainScratch& s, const TrainConfig& c, const Tra
   const Elem* wp = static_cast<const Elem*>(s.wp);
   hipError_t e;
   hipLaunchKernelGGL(k_train_sample<P>, dim3((B + 255) / 256), dim3(256), 0, st, t, (uint32_t)c.seed,
-                     (uint32_t)(c.seed >> 32), step, B, acts[0], s.target);
+                     (uint32_t)(c.seed >> 32), step, B, sh.n_freq, acts[0], s.target);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (sh.skip != 0) {
-    hipLaunchKernelGGL(k_copy_features<P>, dim3(4096), dim3(256), 0, st, acts[0], B, acts[sh.skip],
+    hipLaunchKernelGGL(k_copy_features<P>, dim3(4096), dim3(256), 0, st, acts[0], B, shape_feat(sh), acts[sh.skip],
                        shape_in(sh, sh.skip), H);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
@@ -542,7 +566,8 @@ static hipError_t run_p(TrainScratch& s, const TrainConfig& c, const TrainTarget
 static hipError_t dispatch(TrainScratch& s, const TrainConfig& c, const TrainTargets& t, uint32_t step0,
                            uint32_t steps, bool update, float* grad_out, float* loss_out, hipStream_t st) {
   if (c.batch % kChunk != 0 || c.shape.hidden % 32 != 0 || c.shape.layers < 1 ||
-      (c.shape.skip != 0 && (c.shape.skip < 1 || c.shape.skip >= c.shape.layers)))
+      (c.shape.skip != 0 && (c.shape.skip < 1 || c.shape.skip >= c.shape.layers)) || c.shape.n_freq < 1 ||
+      c.shape.n_freq > 16)
     return hipErrorInvalidValue;
   hipError_t e = ensure_scratch(s, c.batch, c.prec, update ? steps : 1, c.shape);
   if (e != hipSuccess) return e;
@@ -597,26 +622,25 @@ __device__ __forceinline__ void layered_uv(const LayeredIO& io, uint64_t idx, fl
 // the n source entries are zero
 template <int P>
 __global__ __launch_bounds__(256) void k_layered_features(LayeredIO io, uint64_t n, uint64_t base, uint32_t rows,
-                                                         typename Prec<P>::Elem* X0) {
+                                                         int nf, typename Prec<P>::Elem* X0) {
   for (uint32_t r = blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += gridDim.x * blockDim.x) {
-    typename Prec<P>::Elem* x = X0 + (size_t)r * kFeat;
+    typename Prec<P>::Elem* x = X0 + (size_t)r * 4 * nf;
     const uint64_t idx = base + r;
     if (idx >= n) {
-      for (int k = 0; k < kFeat; ++k) x[k] = Prec<P>::cvt(0.0f);
+      for (int k = 0; k < 4 * nf; ++k) x[k] = Prec<P>::cvt(0.0f);
       continue;
     }
     float u, v;
     layered_uv(io, idx, u, v);
-#pragma unroll
-    for (int k = 0; k < kFreq; ++k) {
+    for (int k = 0; k < nf; ++k) {
       const float f = (float)frequency(k);
       float su, cu, sv, cv;
       sincos_turns(frac_product(f, u), su, cu);
       sincos_turns(frac_product(f, v), sv, cv);
       x[k] = Prec<P>::cvt(su);
-      x[kFreq + k] = Prec<P>::cvt(cu);
-      x[2 * kFreq + k] = Prec<P>::cvt(sv);
-      x[3 * kFreq + k] = Prec<P>::cvt(cv);
+      x[nf + k] = Prec<P>::cvt(cu);
+      x[2 * nf + k] = Prec<P>::cvt(sv);
+      x[3 * nf + k] = Prec<P>::cvt(cv);
     }
   }
 }
@@ -713,7 +737,7 @@ static hipError_t layered_p(LayeredScratch& ls, const NifShape& sh, const void* 
     n = c;
   }
   if (n == 0) return hipSuccess;
-  const size_t need = (size_t)kLayeredChunk * (H + kFeat) * sizeof(Elem);
+  const size_t need = (size_t)kLayeredChunk * (H + shape_feat(sh)) * sizeof(Elem);
   if (need > ls.cap) {
     ls.release();
     for (void*& p : ls.x)
@@ -724,7 +748,8 @@ static hipError_t layered_p(LayeredScratch& ls, const NifShape& sh, const void* 
     const uint32_t rows = (uint32_t)(((std::min<uint64_t>(kLayeredChunk, n - base)) + 31) / 32 * 32);
     // x[2]: the features (kept for a skip-concat); x[0] / x[1]: layer outputs
     Elem* x[3] = {static_cast<Elem*>(ls.x[0]), static_cast<Elem*>(ls.x[1]), static_cast<Elem*>(ls.x[2])};
-    hipLaunchKernelGGL(k_layered_features<P>, dim3((rows + 255) / 256), dim3(256), 0, st, io, n, base, rows, x[2]);
+    hipLaunchKernelGGL(k_layered_features<P>, dim3((rows + 255) / 256), dim3(256), 0, st, io, n, base, rows,
+                       sh.n_freq, x[2]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     int cur = 2, nxt = 0;
     for (int l = 0; l < L; ++l) {
@@ -746,8 +771,8 @@ static hipError_t layered_p(LayeredScratch& ls, const NifShape& sh, const void* 
       g.ldc = shape_in(sh, l + 1);
       if ((e = gemm<P, true, true>(g, st)) != hipSuccess) return e;
       if (sh.skip != 0 && l + 1 == sh.skip) {
-        hipLaunchKernelGGL(k_copy_features<P>, dim3(4096), dim3(256), 0, st, x[2], rows, x[nxt], shape_in(sh, l + 1),
-                           H);
+        hipLaunchKernelGGL(k_copy_features<P>, dim3(4096), dim3(256), 0, st, x[2], rows, shape_feat(sh), x[nxt],
+                           shape_in(sh, l + 1), H);
         if ((e = hipGetLastError()) != hipSuccess) return e;
       }
       cur = nxt;
@@ -763,7 +788,7 @@ static hipError_t layered_p(LayeredScratch& ls, const NifShape& sh, const void* 
 hipError_t nif_layered(LayeredScratch& ls, int prec, const NifShape& shape, const void* wp, const float* master,
                        const ColourMatrix& cm, const LayeredIO& io, hipStream_t st) {
   if (shape.hidden % 32 != 0 || shape.hidden < 32 || shape.layers < 1 || shape.skip < 0 ||
-      (shape.skip != 0 && shape.skip >= shape.layers))
+      (shape.skip != 0 && shape.skip >= shape.layers) || shape.n_freq < 1 || shape.n_freq > 16)
     return hipErrorInvalidValue;
   switch (prec) {
     case NPT_FP32: return layered_p<NPT_FP32>(ls, shape, wp, master, cm, io, st);

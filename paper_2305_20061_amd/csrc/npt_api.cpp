@@ -100,7 +100,7 @@ struct npt_ctx {
   uint32_t adam_step = 0;
   int nif_prec = NPT_FP16;
   ColourMatrix nif_cm{};  // output colour space of the uploaded network
-  NifShape nif_shape{nif::kHidden, nif::kLayers, 0};
+  NifShape nif_shape{nif::kHidden, nif::kLayers, 0, nif::kFreq};
   bool nif_layered = false;  // layer-serial GEMM inference (shapes other than the default, or on request)
   LayeredScratch layered;
   TrainScratch train;
@@ -549,8 +549,8 @@ extern "C" int npt_set_env_mode(npt_ctx* c, int mode) {
 // NIF
 // ===========================================================================
 static bool nif_desc_ok(const npt_nif_desc* d) {
-  return d && d->n_freq == (uint32_t)nif::kFreq && d->hidden >= 32 && d->hidden <= 1024 && d->hidden % 32 == 0 &&
-         d->layers >= 1 && d->layers <= 8 && (d->skip == 0 || d->skip < d->layers);
+  return d && d->n_freq >= 1 && d->n_freq <= (uint32_t)nif::kFreq && d->hidden >= 32 && d->hidden <= 1024 &&
+         d->hidden % 32 == 0 && d->layers >= 1 && d->layers <= 8 && (d->skip == 0 || d->skip < d->layers);
 }
 
 // log-space RGB = M * network output for the colour spaces of Sec. 4.3:
@@ -567,11 +567,11 @@ extern "C" int npt_nif_upload(npt_ctx* c, const npt_nif_desc* desc, const float*
   if (!c) return NPT_E_INVALID_ARG;
   if (!nif_desc_ok(desc))
     return fail(c, NPT_E_UNSUPPORTED,
-                "NIF shape must be n_freq 16, hidden 32..1024 (a multiple of 32), layers 1..8, skip 0 or < layers");
+                "NIF shape must be n_freq 1..16, hidden 32..1024 (a multiple of 32), layers 1..8, skip 0 or < layers");
   if (desc->colour > NPT_COLOUR_YCOCG) return fail(c, NPT_E_INVALID_ARG, "unknown NIF colour space");
-  const NifShape shape{(int)desc->hidden, (int)desc->layers, (int)desc->skip};
-  const bool layered =
-      desc->layered != 0 || shape.hidden != nif::kHidden || shape.layers != nif::kLayers || shape.skip != 0;
+  const NifShape shape{(int)desc->hidden, (int)desc->layers, (int)desc->skip, (int)desc->n_freq};
+  const bool layered = desc->layered != 0 || shape.hidden != nif::kHidden || shape.layers != nif::kLayers ||
+                       shape.skip != 0 || shape.n_freq != nif::kFreq;
   if (layered && c->nif_prec == NPT_FP8)
     return fail(c, NPT_E_UNSUPPORTED, "FP8 inference needs the 16/96/5 network; set another precision first");
   if (!params || n != (uint64_t)shape_params(shape)) return fail(c, NPT_E_INVALID_ARG, "parameter count mismatch");

@@ -11,17 +11,20 @@
 
 namespace npt {
 
-// Shape of the MLP at run time: 64 Fourier features -> layers x [dense
-// hidden + ReLU] -> dense 3.  hidden is a multiple of 32 (the MFMA tile).
-// skip: 0, or the hidden layer (1..layers-1) whose input is the previous
-// layer's output followed by the 64 features again (skip-concat, Sec. 3.2).
+// Shape of the MLP at run time: 4 n_freq Fourier features -> layers x
+// [dense hidden + ReLU] -> dense 3.  hidden is a multiple of 32 (the MFMA
+// tile).  skip: 0, or the hidden layer (1..layers-1) whose input is the
+// previous layer's output followed by the features again (skip-concat,
+// Sec. 3.2).
 struct NifShape {
   int hidden;
   int layers;
   int skip;
+  int n_freq;
 };
+__host__ __device__ inline int shape_feat(const NifShape& s) { return 4 * s.n_freq; }
 __host__ __device__ inline int shape_in(const NifShape& s, int l) {
-  return l == 0 ? 64 : (s.skip != 0 && l == s.skip ? s.hidden + 64 : s.hidden);
+  return l == 0 ? shape_feat(s) : (s.skip != 0 && l == s.skip ? s.hidden + shape_feat(s) : s.hidden);
 }
 __host__ __device__ inline int shape_out(const NifShape& s, int l) { return l == s.layers ? 3 : s.hidden; }
 // offsets of W_l and b_l in the flat parameter vector [W_0, b_0, ..., W_L, b_L]
@@ -59,7 +62,7 @@ struct TrainTargets {
 
 // Device scratch of the training step, sized on first use.
 struct TrainScratch {
-  void* act = nullptr;      // X0 [B][64] then H1..HL [B][hidden], operand precision
+  void* act = nullptr;      // X0 [B][4 n_freq] then the inputs of layers 1..L, operand precision
   void* dp = nullptr;       // two [B][hidden] back-propagated pre-activation gradients
   void* wp = nullptr;       // parameters in operand precision
   float* target = nullptr;  // [B][3] log1p(bilinear) targets
@@ -101,7 +104,7 @@ struct LayeredIO {
   uint32_t gw, gh;
 };
 struct LayeredScratch {
-  void* x[3] = {nullptr, nullptr, nullptr};  // ping-pong activations [chunk][hidden + 64], features [chunk][64]
+  void* x[3] = {nullptr, nullptr, nullptr};  // ping-pong activations [chunk][hidden + 4 n_freq], features
   size_t cap = 0;                   // bytes of each
   void release();
 };

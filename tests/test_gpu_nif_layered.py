@@ -12,12 +12,14 @@ from paper_2305_20061_amd import npt, synth
 from gpu_util import gpu_render, make_ctx, oracle_scene, rel_rmse, torch_cuda
 
 pytestmark = pytest.mark.gpu
-SHAPES = [(64, 2, 0), (128, 3, 0), (96, 5, 0), (32, 4, 2), (128, 5, 2)]  # (hidden, layers, skip-concat layer)
+# (hidden, layers, skip-concat layer, frequencies): the last two are the
+# paper's 40-d features (10 frequencies), the last its H128 L5 architecture
+SHAPES = [(64, 2, 0, 16), (128, 3, 0, 16), (96, 5, 0, 16), (32, 4, 2, 16), (32, 3, 1, 10), (128, 5, 2, 10)]
 QUERY_TOL = {npt.FP32: 2e-4, npt.FP16: 2e-3, npt.BF16: 1e-2}
 
 
-def _weights(hidden, layers, seed=3, skip=0):
-    p = synth.nif_init(seed, 16, hidden, layers, skip).astype(np.float32)
+def _weights(hidden, layers, seed=3, skip=0, nf=16):
+    p = synth.nif_init(seed, nf, hidden, layers, skip).astype(np.float32)
     p[-3:] = (0.6, 0.05, -0.05)
     return p
 
@@ -29,17 +31,17 @@ def _dirs(n, seed=0):
     return d.astype(np.float32)
 
 
-@pytest.mark.parametrize("hidden,layers,skip", SHAPES)
+@pytest.mark.parametrize("hidden,layers,skip,nf", SHAPES)
 @pytest.mark.parametrize("prec", [npt.FP32, npt.FP16, npt.BF16])
-def test_layered_query_matches_oracle(hidden, layers, skip, prec):
+def test_layered_query_matches_oracle(hidden, layers, skip, nf, prec):
     torch = torch_cuda()
-    shape = O.nif_shape(16, hidden, layers, O.COLOUR_YUV, skip)
-    p = _weights(hidden, layers, skip=skip)
+    shape = O.nif_shape(nf, hidden, layers, O.COLOUR_YUV, skip)
+    p = _weights(hidden, layers, skip=skip, nf=nf)
     n = 2048 + 37
     ctx = npt.npt_create(0)
     try:
         npt.npt_nif_set_precision(ctx, prec)
-        npt.npt_nif_upload(ctx, p, hidden=hidden, layers=layers, layered=1, skip=skip)
+        npt.npt_nif_upload(ctx, p, n_freq=nf, hidden=hidden, layers=layers, layered=1, skip=skip)
         d = _dirs(n)
         out = torch.full((n, 3), -1.0, dtype=torch.float32, device="cuda")
         npt.npt_env_query(ctx, npt.ENV_NIF, torch.from_numpy(d).cuda(), out)
@@ -52,22 +54,22 @@ def test_layered_query_matches_oracle(hidden, layers, skip, prec):
     assert np.array_equal(dq, ref_p)
     o = np.array([O.nif_radiance_q(shape, ref_p, prec, *O.dir_to_uv(x)) for x in d])
     r = rel_rmse(g, o)
-    print(f"layered H{hidden} L{layers} skip {skip} prec {prec}: relRMSE {r:.3e}")
+    print(f"layered H{hidden} L{layers} skip {skip} freq {nf} prec {prec}: relRMSE {r:.3e}")
     assert np.all(g >= 0)
     assert r <= QUERY_TOL[prec]
 
 
-@pytest.mark.parametrize("hidden,layers,skip", [(64, 2, 0), (128, 3, 0), (32, 4, 2)])
+@pytest.mark.parametrize("hidden,layers,skip,nf", [(64, 2, 0, 16), (128, 3, 0, 16), (32, 4, 2, 16), (32, 3, 1, 10)])
 @pytest.mark.parametrize("prec", [npt.FP32, npt.FP16])
-def test_shape_generic_training_gradient_matches_oracle(hidden, layers, skip, prec, small_sky):
+def test_shape_generic_training_gradient_matches_oracle(hidden, layers, skip, nf, prec, small_sky):
     torch = torch_cuda()
-    shape = O.nif_shape(16, hidden, layers, O.COLOUR_YUV, skip)
-    p = synth.nif_init(11, 16, hidden, layers, skip)
+    shape = O.nif_shape(nf, hidden, layers, O.COLOUR_YUV, skip)
+    p = synth.nif_init(11, nf, hidden, layers, skip)
     B, seed, step = 2048, 5, 2
     ctx = npt.npt_create(0)
     try:
         npt.npt_env_upload(ctx, small_sky)
-        npt.npt_nif_upload(ctx, p, hidden=hidden, layers=layers, skip=skip)
+        npt.npt_nif_upload(ctx, p, n_freq=nf, hidden=hidden, layers=layers, skip=skip)
         grad = torch.zeros(p.size, dtype=torch.float32, device="cuda")
         loss = torch.zeros(1, dtype=torch.float32, device="cuda")
         npt.npt_nif_train_grad(ctx, npt.train_params(batch=B, seed=seed, grad_prec=prec), step, grad, loss,
@@ -80,7 +82,7 @@ def test_shape_generic_training_gradient_matches_oracle(hidden, layers, skip, pr
     uv, tg = O.nif_train_batch(small_sky, seed, step, B)
     lo, go = O.nif_loss_grad(shape, p.astype(np.float64), uv, tg, 1e-3)
     r = rel_rmse(g, go)
-    print(f"H{hidden} L{layers} skip {skip} grad prec {prec}: relRMSE {r:.3e}, loss {lg:.6e} vs {lo:.6e}")
+    print(f"H{hidden} L{layers} skip {skip} freq {nf} grad prec {prec}: relRMSE {r:.3e}, loss {lg:.6e} vs {lo:.6e}")
     tol = {npt.FP32: (1e-4, 1e-5), npt.FP16: (3e-2, 1e-3)}[prec]
     assert r <= tol[0]
     assert abs(lg - lo) <= tol[1] * abs(lo)

@@ -284,3 +284,14 @@ def test_skip_backward_matches_central_differences():
                                                                                       False)[0]) / (2 * h)
         worst = max(worst, abs(fd - g[i]) / max(1e-6, abs(g[i]), abs(fd)))
     assert worst < 1e-5, worst
+
+
+def test_fewer_frequencies_keep_the_feature_layout():
+    # 10 frequencies (the paper's 40-d features): the first 10 of each block of
+    # the 16-frequency features, blocks [sin u | cos u | sin v | cos v]
+    s10 = O.nif_shape(10, 32, 2)
+    for u, v in ((0.13, 0.71), (0.5, 0.25)):
+        f16 = O.nif_features(SHAPE, u, v).reshape(4, 16)
+        f10 = O.nif_features(s10, u, v).reshape(4, 10)
+        assert np.array_equal(f10, f16[:, :10])
+    assert O.nif_param_count(s10) == 40 * 32 + 32 + (32 * 32 + 32) + 3 * 32 + 3
