@@ -160,6 +160,87 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
 }
 
 // ---------------------------------------------------------------------------
+// LDS-tiled GEMM for the forward layers of wide networks (hidden >= 128,
+// FP16 / BF16 operands, K a multiple of 32, A and B contiguous along K):
+// 128 x 128 output tiles per 256-thread workgroup, each wave a 64 x 64
+// quarter (2 x 2 MFMA tiles), K in steps of 32 staged through LDS; rows and
+// columns beyond M and N are zero-filled on load and skipped on store.
+// Epilogue: relu(acc + bias[n]) -> C (mode 0 of GemmDesc).
+// ---------------------------------------------------------------------------
+constexpr int kTileM = 128, kTileN = 128, kTileK = 32, kTileLd = kTileK + 8;  // LDS row: 40 elements
+
+template <int P>
+__global__ __launch_bounds__(256) void k_gemm_tiled(GemmDesc g) {
+  using Elem = typename Prec<P>::Elem;
+  using Frag = typename Prec<P>::Frag;
+  static_assert(Prec<P>::KPL == 8, "16-bit operands");
+  __shared__ Elem As[kTileM * kTileLd];
+  __shared__ Elem Bs[kTileN * kTileLd];
+  const int nt = (g.N + kTileN - 1) / kTileN;
+  const int m0 = (blockIdx.x / nt) * kTileM, n0 = (blockIdx.x % nt) * kTileN;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
+  const int h = lane / 32, c = lane % 32;
+  const Elem* A = static_cast<const Elem*>(g.A);
+  const Elem* B = static_cast<const Elem*>(g.B);
+  // staging: thread t loads 16 consecutive k of row t / 2 of each tile
+  const int lr = t >> 1, lk = (t & 1) * 16;
+  const bool a_ok = m0 + lr < g.M, b_ok = n0 + lr < g.N;
+  const Elem* a_src = A + (int64_t)(m0 + lr) * g.a_sm + lk;
+  const Elem* b_src = B + (int64_t)(n0 + lr) * g.b_sn + lk;
+  Frag zf;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) zf[e] = Prec<P>::cvt(0.0f);
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+  for (int k0 = 0; k0 < g.K; k0 += kTileK) {
+    const Frag a0 = a_ok ? *reinterpret_cast<const Frag*>(a_src + k0) : zf;
+    const Frag a1 = a_ok ? *reinterpret_cast<const Frag*>(a_src + k0 + 8) : zf;
+    const Frag b0 = b_ok ? *reinterpret_cast<const Frag*>(b_src + k0) : zf;
+    const Frag b1 = b_ok ? *reinterpret_cast<const Frag*>(b_src + k0 + 8) : zf;
+    __syncthreads();  // the previous step's reads are done
+    *reinterpret_cast<Frag*>(&As[lr * kTileLd + lk]) = a0;
+    *reinterpret_cast<Frag*>(&As[lr * kTileLd + lk + 8]) = a1;
+    *reinterpret_cast<Frag*>(&Bs[lr * kTileLd + lk]) = b0;
+    *reinterpret_cast<Frag*>(&Bs[lr * kTileLd + lk + 8]) = b1;
+    __syncthreads();
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+      Frag af[2], bf[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        af[i] = *reinterpret_cast<const Frag*>(&As[(wm + i * 32 + c) * kTileLd + kb * 16 + h * 8]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        bf[j] = *reinterpret_cast<const Frag*>(&Bs[(wn + j * 32 + c) * kTileLd + kb * 16 + h * 8]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = Prec<P>::mma(af[i], bf[j], acc[i][j]);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int n = n0 + wn + j * 32 + c;
+      if (n >= g.N) continue;
+      const float bias = g.bias[n];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = m0 + wm + i * 32 + acc_row(0, h, r);
+        if (m < g.M)
+          static_cast<Elem*>(g.C)[(int64_t)m * g.ldc + n] = Prec<P>::cvt(fmaxf(acc[i][j][r] + bias, 0.0f));
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // output layer, colour matrix, Huber loss and the per-sample gradient
 // ---------------------------------------------------------------------------
 template <int P>
@@ -412,8 +493,23 @@ static hipError_t ensure_scratch(TrainScratch& s, uint32_t B, int prec, uint32_t
 
 static int grid_for_params(int64_t np) { return (int)std::min<int64_t>(4096, (np + 255) / 256); }
 
+// forward layers (mode 0, both operands contiguous along K) of networks at
+// least 128 wide with 16-bit operands take the LDS-tiled kernel
+template <int P>
+static bool tiled_ok(const GemmDesc& g) {
+  return Prec<P>::KPL == 8 && g.mode == 0 && g.splits == 1 && g.N >= 128 && g.K % kTileK == 0 && g.a_sk == 1 &&
+         g.b_sk == 1;
+}
+
 template <int P, bool AK, bool BK>
 static hipError_t gemm(const GemmDesc& g, hipStream_t st) {
+  if constexpr (AK && BK && Prec<P>::KPL == 8) {
+    if (tiled_ok<P>(g)) {
+      const int tiles = ((g.M + kTileM - 1) / kTileM) * ((g.N + kTileN - 1) / kTileN);
+      hipLaunchKernelGGL(k_gemm_tiled<P>, dim3(tiles), dim3(256), 0, st, g);
+      return hipGetLastError();
+    }
+  }
   const int waves = (g.M / 32) * ((g.N + 31) / 32) * g.splits;
   hipLaunchKernelGGL((k_gemm<P, AK, BK>), dim3((waves + 3) / 4), dim3(256), 0, st, g);
   return hipGetLastError();
