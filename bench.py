@@ -391,17 +391,19 @@ def nif_study(args):
 # H128 L5, features again at the middle layer) with and without its 40-d
 # features
 NIF_SIZES = [(64, 2, 0, 16), (96, 5, 0, 16), (128, 5, 2, 16), (128, 5, 2, 10), (256, 4, 0, 16), (1024, 8, 0, 16)]
+# shapes with an LDS-resident inference kernel (hidden, layers, skip, frequencies)
+RESIDENT = [(96, 5, 0, 16), (128, 5, 2, 10), (128, 5, 2, 16), (64, 2, 0, 16)]
 
 
 def nif_sizes(args):
     """Model size against path rate and PSNR (Sec. 4.6): the spheres scene
     (1024x1024, 16 spp, depth 8) lit by NIFs of several sizes, each trained
     on the device (2^24 samples, batch 65,536, FP16 GEMMs) and run with FP16
-    operands on the layer-serial GEMM path (the 96 x 5 network also on the
-    LDS-resident kernel).  Reported per size: parameters, FLOP per query,
+    operands on the layer-serial GEMM path.  Reported per size: parameters, FLOP per query,
     training time, log-domain PSNRs against the map (FP32 inference), path
     samples/s, NIF time and TFLOP/s per render, and the image relRMSE
-    against the env-map render at equal seeds."""
+    against the env-map render at equal seeds; shapes with an LDS-resident
+    kernel are rendered again on it, in FP16 and FP8."""
     import torch
 
     from paper_2305_20061_amd import npt, synth
@@ -428,33 +430,42 @@ def nif_sizes(args):
         npt.npt_render(ctx, W, H, spp, depth, 1, out)
         torch.cuda.synchronize()
         img_map = out.cpu().numpy().astype(np.float64)
-        runs = [(hd, ly, sk, nf, 1) for hd, ly, sk, nf in NIF_SIZES] + [(96, 5, 0, 16, 0)]
-        for hidden, layers, skip, nf, layered in runs:
+        for hidden, layers, skip, nf in NIF_SIZES:
             npt.npt_nif_set_precision(ctx, npt.FP16)
             npt.npt_nif_upload(ctx, synth.nif_init(3, nf, hidden, layers, skip), n_freq=nf, hidden=hidden,
-                               layers=layers, layered=layered, skip=skip)
+                               layers=layers, layered=1, skip=skip)
             tr = npt.npt_nif_train(ctx, npt.train_params(batch=65536, samples=args.train_samples, seed=1,
                                                          grad_prec=npt.FP16))
             npt.npt_nif_set_precision(ctx, npt.FP32)
             npt.npt_env_query(ctx, npt.ENV_NIF, d_dirs, q)
             torch.cuda.synchronize()
             psnr = _psnr_log(q.cpu().numpy().astype(np.float64), ref)
-            npt.npt_nif_set_precision(ctx, npt.FP16)
-            npt.npt_set_env_mode(ctx, npt.ENV_NIF)
-            npt.npt_set_render_options(ctx, rr_start=3, kernel_timing=1)
-            el, st = _timed_renders(npt, torch, ctx, W, H, spp, depth, 1, out, 2, 1)
-            npt.npt_set_render_options(ctx, rr_start=3)
+            n_params = npt.nif_param_count(hidden, layers, skip, nf)
+            trained = npt.npt_nif_download(ctx, n_params)
             F = 4 * nf
             flop = 2 * (F * hidden + (layers - 1) * hidden * hidden + 3 * hidden + (F * hidden if skip else 0))
-            rows.append({"hidden": hidden, "layers": layers, "skip": skip, "features": F,
-                         "path": "layered GEMMs" if layered else "LDS-resident",
-                         "params": npt.nif_param_count(hidden, layers, skip, nf), "flop_per_query": flop,
-                         "train_ms": tr["ms"], "last_loss": tr["last_loss"], **psnr,
-                         "path_samples_per_s": W * H * spp * 2 / el, "nif_ms_per_render": st["ms_env"],
-                         "nif_tflops": st["env_queries"] * flop / (st["ms_env"] * 1e-3) / 1e12,
-                         "image_rel_rmse_vs_env_map": _rel(out.cpu().numpy().astype(np.float64), img_map)})
-            npt.npt_set_env_mode(ctx, npt.ENV_MAP)
-            print(json.dumps(rows[-1]), flush=True)
+            # the layer-serial path; then, for shapes with an LDS-resident
+            # kernel, the same trained weights on it in FP16 and FP8
+            runs = [(1, npt.FP16)] + ([(0, npt.FP16), (0, npt.FP8)] if (hidden, layers, skip, nf) in RESIDENT else [])
+            for layered, prec in runs:
+                npt.npt_nif_set_precision(ctx, npt.FP16)
+                npt.npt_nif_upload(ctx, trained, n_freq=nf, hidden=hidden, layers=layers, layered=layered,
+                                   skip=skip)
+                npt.npt_nif_set_precision(ctx, prec)
+                npt.npt_set_env_mode(ctx, npt.ENV_NIF)
+                npt.npt_set_render_options(ctx, rr_start=3, kernel_timing=1)
+                el, st = _timed_renders(npt, torch, ctx, W, H, spp, depth, 1, out, 2, 1)
+                npt.npt_set_render_options(ctx, rr_start=3)
+                rows.append({"hidden": hidden, "layers": layers, "skip": skip, "features": F,
+                             "path": "layered GEMMs" if layered else "LDS-resident",
+                             "prec": {npt.FP16: "fp16", npt.FP8: "fp8"}[prec],
+                             "params": n_params, "flop_per_query": flop,
+                             "train_ms": tr["ms"], "last_loss": tr["last_loss"], **psnr,
+                             "path_samples_per_s": W * H * spp * 2 / el, "nif_ms_per_render": st["ms_env"],
+                             "nif_tflops": st["env_queries"] * flop / (st["ms_env"] * 1e-3) / 1e12,
+                             "image_rel_rmse_vs_env_map": _rel(out.cpu().numpy().astype(np.float64), img_map)})
+                npt.npt_set_env_mode(ctx, npt.ENV_MAP)
+                print(json.dumps(rows[-1]), flush=True)
     finally:
         npt.npt_destroy(ctx)
     print(json.dumps({"nif_sizes": rows, "render": f"spheres {W}x{H}, {spp} spp, depth {depth}, seed 1, FP16 NIF",

@@ -98,12 +98,15 @@ typedef struct {
 /* HDR-NIF shape (Sec. 3.2): 4*n_freq Fourier features -> layers x
  * [dense hidden + ReLU] -> dense 3 -> fixed colour matrix to log-space RGB.
  * Supported: n_freq 1..16 (frequencies round(2^((k+1)/2)), k < n_freq);
- * hidden 32..1024, a multiple of 32; layers 1..8.  The 16/96/5 network runs
- * on the LDS-resident MFMA kernel (FP32, FP16, BF16, FP8); every other
- * shape, or layered = 1, on layer-serial MFMA GEMMs
- * (FP32, FP16, BF16; Sec. 4.6 sweeps model sizes).  skip: 0, or the hidden
+ * hidden 32..1024, a multiple of 32; layers 1..8.  skip: 0, or the hidden
  * layer (1..layers-1) whose input is the previous layer's output followed by
- * the features again (the paper's skip-concat, Sec. 3.2; layered path).
+ * the features again (the paper's skip-concat, Sec. 3.2).  Four shapes
+ * (n_freq/hidden/layers/skip) run on an LDS-resident MFMA kernel in FP32,
+ * FP16, BF16 or FP8: 16/96/5/0 (the default), 10/128/5/2 (the paper's
+ * network), 16/128/5/2 and 16/64/2/0.  Every other shape, or layered = 1,
+ * runs on layer-serial MFMA GEMMs in FP32, FP16 or BF16 (Sec. 4.6 sweeps
+ * model sizes); uploading such a shape while FP8 is selected, or selecting
+ * FP8 for it, fails with NPT_E_UNSUPPORTED.
  * colour: the space the
  * network's three outputs live in (Sec. 4.3 compares them):
  * NPT_COLOUR_YUV (default; BT.601 analogue, R = Y + 1.13983 V,

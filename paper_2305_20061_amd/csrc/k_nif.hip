@@ -1,11 +1,12 @@
 // k_nif.hip -- HDR-NIF inference on MFMA (Sec. 3.2 network, Sec. 3.3 batched
 // queries of escaped rays) and the weight packing it reads.
 //
-// One workgroup per CU keeps the whole packed network in LDS (FP16/BF16:
-// 94 KB); each wave pushes 32-ray column tiles through all layers with
-// activations held in registers (see npt_nif_layout.h).  FP32 operands
-// (v_mfma_f32_32x32x2f32) keep the 4 hidden 96x96 layers in LDS and read the
-// first and last layer from L2.
+// One workgroup per CU keeps the packed network in LDS (the 16/96/5 network
+// in FP16/BF16: 87 KB; the paper's H128 L5 skip network with 40-d features:
+// 155 KB); each wave pushes 32-ray column tiles through all layers with
+// activations held in registers (see npt_nif_layout.h).  Layers that do not
+// fit (FP32 operands on v_mfma_f32_32x32x2f32, larger networks) are read
+// from L2.  Built for the shapes listed in npt_nif_layout.h.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -20,71 +21,101 @@
 namespace npt {
 using namespace nif;
 
-// Bytes of layer l's weight fragments, and their offsets in the packed
-// buffer (all layers) and in LDS (the resident layers).
-template <int P>
-__host__ __device__ constexpr size_t layer_bytes(int l) {
-  if (P == NPT_FP8 && fp8_layer(l)) return (size_t)kFp8LayerBytes;
-  return (size_t)Geometry<Prec<P>::KPL>::frags(l) * 64 * sizeof(typename Prec<P>::Frag);
-}
+// LDS of one workgroup (gfx950: 160 KiB per CU)
+constexpr size_t kLdsBudget = 160 * 1024;
 
-template <int P>
-__host__ __device__ constexpr size_t global_offset(int l) {
-  size_t o = 0;
-  for (int i = 0; i < l; ++i) o += layer_bytes<P>(i);
-  return o;
-}
-
-template <int P>
-__host__ __device__ constexpr size_t lds_offset(int l) {
-  size_t o = 0;
-  for (int i = 0; i < l; ++i)
-    if (Prec<P>::kResident[i]) o += layer_bytes<P>(i);
-  return o;
-}
-
-template <int P>
-size_t nif_lds_bytes() {
-  return lds_offset<P>(kLayers + 1) + (kBiasFloats + kScaleWords) * sizeof(float);
-}
+// Packed buffer of one network at precision P: every layer's weight
+// fragments (E4M3 for the FP8 hidden-to-hidden layers), and which of them the
+// inference kernel keeps in LDS.
+template <int P, class A>
+struct Pack {
+  using G = Geometry<Prec<P>::KPL, A>;
+  static constexpr int L = A::kLayers;
+  __host__ __device__ static constexpr size_t layer_bytes(int l) {
+    if (P == NPT_FP8 && Fp8<A>::layer(l)) return (size_t)Fp8<A>::layer_bytes(l);
+    return (size_t)G::elems(l) * sizeof(typename Prec<P>::Elem);
+  }
+  __host__ __device__ static constexpr size_t global_offset(int l) {
+    size_t o = 0;
+    for (int i = 0; i < l; ++i) o += layer_bytes(i);
+    return o;
+  }
+  static constexpr size_t kBiasBytes = (size_t)(A::kBiasFloats + kScaleWords) * sizeof(float);
+  // residency: the hidden layers first, then the first layer, then the
+  // output layer, each while it still fits beside the bias table
+  __host__ __device__ static constexpr bool resident(int l) {
+    size_t used = kBiasBytes;
+    for (int j = 0; j <= L; ++j) {
+      const int i = j < L - 1 ? j + 1 : j == L - 1 ? 0 : L;
+      const bool fits = used + layer_bytes(i) <= kLdsBudget;
+      if (fits) used += layer_bytes(i);
+      if (i == l) return fits;
+    }
+    return false;
+  }
+  __host__ __device__ static constexpr size_t lds_offset(int l) {
+    size_t o = 0;
+    for (int i = 0; i < l; ++i)
+      if (resident(i)) o += layer_bytes(i);
+    return o;
+  }
+  __host__ __device__ static constexpr bool hidden_resident() {
+    for (int l = 1; l < L; ++l)
+      if (!resident(l)) return false;
+    return true;
+  }
+  static constexpr size_t kLdsBytes = lds_offset(L + 1) + kBiasBytes;
+  static_assert(kLdsBytes <= kLdsBudget, "LDS budget");
+};
 
 // ---------------------------------------------------------------------------
 // packing: master FP32 parameters -> MFMA fragments + bias table
 // ---------------------------------------------------------------------------
+template <class A>
 __device__ __forceinline__ void fill_bias(const float* master, float* bias, int tid, int stride) {
-  for (int j = tid; j < kBiasFloats; j += stride) {
+  constexpr int H = A::kHidden, L = A::kLayers;
+  for (int j = tid; j < A::kBiasFloats; j += stride) {
     float b = 0.0f;
-    if (j < kLayers * kHidden) b = master[b_offset(j / kHidden) + j % kHidden];
-    else if (j - kLayers * kHidden < kOut) b = master[b_offset(kLayers) + (j - kLayers * kHidden)];
+    if (j < L * H) b = master[A::b_offset(j / H) + j % H];
+    else if (j - L * H < kOut) b = master[A::b_offset(L) + (j - L * H)];
     bias[j] = b;
   }
 }
 
-// FP16/BF16/FP32 fragment element i (over all layers) of the packed buffer
-template <int KPL>
-__device__ __forceinline__ float packed_weight(const float* master, int i) {
-  using G = Geometry<KPL>;
-  const int q = i / (64 * KPL);
-  const int lane = (i / KPL) % 64;
-  const int e = i % KPL;
-  int l = 0;
-  while (l < kLayers && q >= G::frag_offset(l + 1)) ++l;
-  const int local = q - G::frag_offset(l);
-  const int nkb = l == 0 ? G::kKBFeat : G::kKBHidden;
-  const int mb = local / nkb, kb = local % nkb;
-  const int row = 32 * mb + lane % 32;
-  const int col = input_index<KPL>(l, kb, lane / 32, e);
-  return row < layer_out(l) ? master[w_offset(l) + row * layer_in(l) + col] : 0.0f;
+// element j of layer l's packed fragments (FP16/BF16/FP32 layouts)
+template <int KPL, class A>
+__device__ __forceinline__ float packed_weight(const float* master, int l, int j) {
+  using G = Geometry<KPL, A>;
+  const int e = j % KPL;
+  int row, kb, h;
+  if (l == A::kLayers) {  // compact output layer: [kb][h][row 0..2][e]
+    row = (j / KPL) % 3;
+    h = (j / (3 * KPL)) % 2;
+    kb = j / (6 * KPL);
+  } else {  // [mb][kb][lane][e]
+    const int lane = (j / KPL) % 64;
+    const int q = j / (64 * KPL);
+    const int nkb = G::kb_in(l);
+    row = 32 * (q / nkb) + lane % 32;
+    kb = q % nkb;
+    h = lane / 32;
+  }
+  const int col = input_index<KPL, A>(l, kb, h, e);
+  return col < 0 ? 0.0f : master[A::w_offset(l) + row * A::layer_in(l) + col];
 }
 
-template <int P>
+template <int P, class A>
 __global__ void k_nif_pack(const float* master, typename Prec<P>::Elem* frags, float* bias) {
   constexpr int KPL = Prec<P>::KPL;
+  using G = Geometry<KPL, A>;
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-  for (int i = tid; i < Geometry<KPL>::kElems; i += gridDim.x * blockDim.x)
-    frags[i] = Prec<P>::cvt(packed_weight<KPL>(master, i));
-  fill_bias(master, bias, tid, gridDim.x * blockDim.x);
-  for (int j = tid; j < kScaleWords; j += gridDim.x * blockDim.x) reinterpret_cast<int*>(bias + kBiasFloats)[j] = 0;
+  for (int i = tid; i < G::kElems; i += gridDim.x * blockDim.x) {
+    int l = 0;
+    while (l < A::kLayers && i >= G::elem_offset(l + 1)) ++l;
+    frags[i] = Prec<P>::cvt(packed_weight<KPL, A>(master, l, i - G::elem_offset(l)));
+  }
+  fill_bias<A>(master, bias, tid, gridDim.x * blockDim.x);
+  for (int j = tid; j < kScaleWords; j += gridDim.x * blockDim.x) reinterpret_cast<int*>(bias + A::kBiasFloats)[j] = 0;
 }
 
 // FP8 weight scale: the largest s with m * 2^s <= 448 (0 for m = 0)
@@ -97,16 +128,20 @@ __device__ __forceinline__ int fp8_scale_exp(float m) {
   return s;
 }
 
-// FP8 mode: one workgroup of 256 per layer.  Layers 1..4 become E4M3
-// fragments of W * 2^s (s from the layer's largest |w|, stored after the
-// bias table); layers 0 and 5 FP16 fragments as in FP16 mode.
+// FP8 mode: one workgroup of 256 per layer.  The hidden-to-hidden layers
+// become E4M3 fragments of W * 2^s (s from the layer's largest |w|, stored
+// after the bias table); the first and output layers FP16 fragments as in
+// FP16 mode.
+template <class A>
 __global__ __launch_bounds__(256) void k_nif_pack_fp8(const float* master, uint8_t* packed, float* bias) {
+  using K = Pack<NPT_FP8, A>;
   const int l = blockIdx.x;
   __shared__ float red[256];
-  int* scales = reinterpret_cast<int*>(bias + kBiasFloats);
-  if (fp8_layer(l)) {
+  int* scales = reinterpret_cast<int*>(bias + A::kBiasFloats);
+  if (Fp8<A>::layer(l)) {
+    const int nin = A::layer_in(l), nw = A::kHidden * nin;
     float m = 0.0f;
-    for (int i = threadIdx.x; i < kHidden * kHidden; i += 256) m = fmaxf(m, fabsf(master[w_offset(l) + i]));
+    for (int i = threadIdx.x; i < nw; i += 256) m = fmaxf(m, fabsf(master[A::w_offset(l) + i]));
     red[threadIdx.x] = m;
     __syncthreads();
     for (int k = 128; k > 0; k >>= 1) {
@@ -115,45 +150,45 @@ __global__ __launch_bounds__(256) void k_nif_pack_fp8(const float* master, uint8
     }
     const int s = fp8_scale_exp(red[0]);
     if (threadIdx.x == 0) scales[l] = s;
-    int* dst = reinterpret_cast<int*>(packed + global_offset<NPT_FP8>(l));
+    int* dst = reinterpret_cast<int*>(packed + K::global_offset(l));
+    const int nkb = Fp8<A>::kb_in(l);
     // dword wd: fragment q = (M-block, K-block), lane, bytes 4 (wd % 8) .. +3
-    for (int wd = threadIdx.x; wd < kFp8LayerBytes / 4; wd += 256) {
+    for (int wd = threadIdx.x; wd < Fp8<A>::layer_bytes(l) / 4; wd += 256) {
       const int q = wd / (64 * 8), lane = (wd / 8) % 64, e0 = (wd % 8) * 4;
-      const int mb = q / kKB8, kb = q % kKB8;
+      const int mb = q / nkb, kb = q % nkb;
       const int row = 32 * mb + lane % 32;
       float v[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const int col = input_index_fp8(kb, lane / 32, e0 + k);
-        v[k] = col < 0 ? 0.0f : ldexpf(master[w_offset(l) + row * kHidden + col], s);
+        const int col = Fp8<A>::input_index(l, kb, lane / 32, e0 + k);
+        v[k] = col < 0 ? 0.0f : ldexpf(master[A::w_offset(l) + row * nin + col], s);
       }
       dst[wd] = pack_e4m3<true>(v[2], v[3], pack_e4m3<false>(v[0], v[1], 0));
     }
   } else {
-    using G = Geometry<8>;
-    _Float16* dst = reinterpret_cast<_Float16*>(packed + global_offset<NPT_FP8>(l));
-    const int base = G::frag_offset(l) * 64 * 8;
-    for (int i = threadIdx.x; i < G::frags(l) * 64 * 8; i += 256) dst[i] = (_Float16)packed_weight<8>(master, base + i);
+    _Float16* dst = reinterpret_cast<_Float16*>(packed + K::global_offset(l));
+    for (int j = threadIdx.x; j < Geometry<8, A>::elems(l); j += 256)
+      dst[j] = (_Float16)packed_weight<8, A>(master, l, j);
     if (threadIdx.x == 0) scales[l] = 0;
   }
   if (l == 0) {
-    fill_bias(master, bias, threadIdx.x, 256);
-    for (int j = kLayers + 1 + threadIdx.x; j < kScaleWords; j += 256) scales[j] = 0;
+    fill_bias<A>(master, bias, threadIdx.x, 256);
+    for (int j = A::kLayers + 1 + threadIdx.x; j < kScaleWords; j += 256) scales[j] = 0;
   }
 }
 
 // the values the kernel multiplies, back in FP32 (npt_nif_get_dequantized):
 // weights rounded as packed, biases unchanged (they are added in FP32)
-template <int P>
+template <int P, class A>
 __global__ void k_nif_dequant(const float* master, const float* bias_tab, float* out, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     int l = 0;
-    while (l < kLayers && i >= w_offset(l + 1)) ++l;
+    while (l < A::kLayers && i >= A::w_offset(l + 1)) ++l;
     const float w = master[i];
-    if (i >= b_offset(l)) {
+    if (i >= A::b_offset(l)) {
       out[i] = w;
-    } else if (P == NPT_FP8 && fp8_layer(l)) {
-      const int s = reinterpret_cast<const int*>(bias_tab + kBiasFloats)[l];
+    } else if (P == NPT_FP8 && Fp8<A>::layer(l)) {
+      const int s = reinterpret_cast<const int*>(bias_tab + A::kBiasFloats)[l];
       out[i] = ldexpf(__builtin_amdgcn_cvt_f32_fp8(pack_e4m3<false>(ldexpf(w, s), 0.0f, 0), 0), -s);
     } else {
       out[i] = (float)Prec<P>::cvt(w);
@@ -190,24 +225,37 @@ struct NifIO {
   ColourMatrix cm;       // network output -> log-space RGB
 };
 
-template <int P, bool kAccurateSin>
-__device__ __forceinline__ float feature(int f, float u, float v) {
-  const int blk = f >> 4;
-  const float arg = blk < 2 ? u : v;
-  const float ph = frac_product((float)frequency(f & 15), arg);
+// Fourier feature f (natural order: sin u, cos u, sin v, cos v blocks of NF
+// frequencies each; 0 for the padding past the last one) for lane half h,
+// which feeds feature f0 (h = 0) or f1 (h = 1): both are compile-time
+// constants once the K-block loops unroll, so the frequency, the argument and
+// sin / cos become selects between constants
+template <class A, bool kAccurateSin>
+__device__ __forceinline__ float feature(int f0, int f1, int h, float u, float v) {
+  constexpr int NF = A::kFreq;
+  const int b0 = f0 / NF, b1 = f1 / NF;
+  const float q0 = (float)frequency(f0 - b0 * NF), q1 = (float)frequency(f1 - b1 * NF);
+  const bool hi = h != 0;
+  const int blk = hi ? b1 : b0;
+  const float ph = frac_product(hi ? q1 : q0, blk < 2 ? u : v);
+  float r;
   if (kAccurateSin) {
     float s, c;
     sincos_turns(ph, s, c);
-    return (blk & 1) ? c : s;
+    r = (blk & 1) ? c : s;
+  } else if ((b0 & 1) == (b1 & 1)) {
+    r = (b0 & 1) ? __builtin_amdgcn_cosf(ph) : __builtin_amdgcn_sinf(ph);
+  } else {
+    r = (blk & 1) ? __builtin_amdgcn_cosf(ph) : __builtin_amdgcn_sinf(ph);
   }
-  return (blk & 1) ? __builtin_amdgcn_cosf(ph) : __builtin_amdgcn_sinf(ph);
+  return (hi ? f1 : f0) < A::kFeat ? r : 0.0f;
 }
 
 // bias-initialised accumulators of one layer over NT 32-ray column tiles
-template <int NT>
-__device__ __forceinline__ void init_acc(const float* lb, int h, f32x16 (&acc)[NT][kMB]) {
+template <int NT, class A>
+__device__ __forceinline__ void init_acc(const float* lb, int h, f32x16 (&acc)[NT][A::kMB]) {
 #pragma unroll
-  for (int mb = 0; mb < kMB; ++mb) {
+  for (int mb = 0; mb < A::kMB; ++mb) {
     f32x16 b;
 #pragma unroll
     for (int r = 0; r < 16; ++r) b[r] = lb[acc_row(mb, h, r)];
@@ -216,27 +264,28 @@ __device__ __forceinline__ void init_acc(const float* lb, int h, f32x16 (&acc)[N
   }
 }
 
-// acc += W x for Prec<P> operands: x holds the layer input as NKB K-blocks
-template <int P, int NT, int NKB>
+// acc += W[:, K-blocks KB0 .. KB0+NKB-1] x for Prec<P> operands; the layer's
+// fragments are [mb][NKBIN][lane]
+template <int P, class A, int NT, int NKB, int NKBIN, int KB0, int NX>
 __device__ __forceinline__ void mma_layer(const typename Prec<P>::Frag* fr, int lane,
-                                          const typename Prec<P>::Frag (&x)[NT][Geometry<Prec<P>::KPL>::kKBHidden],
-                                          f32x16 (&acc)[NT][kMB]) {
+                                          const typename Prec<P>::Frag (&x)[NT][NX], f32x16 (&acc)[NT][A::kMB]) {
 #pragma unroll
   for (int kb = 0; kb < NKB; ++kb)
 #pragma unroll
-    for (int mb = 0; mb < kMB; ++mb) {
-      const typename Prec<P>::Frag a = fr[(mb * NKB + kb) * 64 + lane];
+    for (int mb = 0; mb < A::kMB; ++mb) {
+      const typename Prec<P>::Frag a = fr[(mb * NKBIN + KB0 + kb) * 64 + lane];
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[t][mb] = Prec<P>::mma(a, x[t][kb], acc[t][mb]);
     }
 }
 
 // ReLU of the accumulators into the Prec<P> K-blocks of the next layer
-template <int P, int NT>
-__device__ __forceinline__ void relu_to_frags(const f32x16 (&acc)[NT][kMB],
-                                              typename Prec<P>::Frag (&x)[NT][Geometry<Prec<P>::KPL>::kKBHidden]) {
+template <int P, class A, int NT>
+__device__ __forceinline__ void relu_to_frags(
+    const f32x16 (&acc)[NT][A::kMB],
+    typename Prec<P>::Frag (&x)[NT][Geometry<Prec<P>::KPL, A>::kKBHidden]) {
   constexpr int KPL = Prec<P>::KPL;
-  using G = Geometry<KPL>;
+  using G = Geometry<KPL, A>;
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -258,26 +307,16 @@ __device__ __forceinline__ void relu_to_frags(const f32x16 (&acc)[NT][kMB],
     }
 }
 
-// one dense layer + ReLU: x (K-blocks of the layer input) -> x (K-blocks of
-// the next layer), weights fr, biases lb
-template <int P, int NT, int NKB>
-__device__ __forceinline__ void dense_relu(const typename Prec<P>::Frag* fr, const float* lb, int lane, int h,
-                                           typename Prec<P>::Frag (&x)[NT][Geometry<Prec<P>::KPL>::kKBHidden]) {
-  f32x16 acc[NT][kMB];
-  init_acc<NT>(lb, h, acc);
-  mma_layer<P, NT, NKB>(fr, lane, x, acc);
-  relu_to_frags<P, NT>(acc, x);
-}
-
-// FP8 hidden-to-hidden layer: acc += 2^-s (W 2^s) x with E4M3 operands
-template <int NT>
-__device__ __forceinline__ void mma_layer_e4m3(const i32x8* fr, int lane, int scale_a, const i32x8 (&x)[NT][kKB8],
-                                               f32x16 (&acc)[NT][kMB]) {
+// FP8 layer: acc += 2^-s (W 2^s) x over E4M3 K-blocks KB0 .. KB0+NKB-1 of a
+// layer with NKBIN K-blocks
+template <class A, int NT, int NKB, int NKBIN, int KB0, int NX>
+__device__ __forceinline__ void mma_layer_e4m3(const i32x8* fr, int lane, int scale_a, const i32x8 (&x)[NT][NX],
+                                               f32x16 (&acc)[NT][A::kMB]) {
 #pragma unroll
-  for (int kb = 0; kb < kKB8; ++kb)
+  for (int kb = 0; kb < NKB; ++kb)
 #pragma unroll
-    for (int mb = 0; mb < kMB; ++mb) {
-      const i32x8 a = fr[(mb * kKB8 + kb) * 64 + lane];
+    for (int mb = 0; mb < A::kMB; ++mb) {
+      const i32x8 a = fr[(mb * NKBIN + KB0 + kb) * 64 + lane];
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[t][mb] = mma_e4m3(a, x[t][kb], acc[t][mb], scale_a);
     }
@@ -289,34 +328,36 @@ __device__ __forceinline__ int pack4_e4m3(const f32x16& a, int r) {
   return pack_e4m3<true>(relu448(a[r + 2]), relu448(a[r + 3]), pack_e4m3<false>(relu448(a[r]), relu448(a[r + 1]), 0));
 }
 
-// ReLU of the accumulators, saturated at 448, into the two E4M3 K-blocks of
-// the next layer (byte e of K-block 0: M-block e / 16, register e % 16;
-// K-block 1: M-block 2, then zero padding)
-template <int NT>
-__device__ __forceinline__ void relu_to_e4m3(const f32x16 (&acc)[NT][kMB], i32x8 (&x)[NT][kKB8]) {
+// ReLU of the accumulators, saturated at 448, into the E4M3 K-blocks of the
+// next layer (byte e of K-block kb: M-block 2kb + e / 16, register e % 16;
+// zero bytes past the last M-block)
+template <class A, int NT>
+__device__ __forceinline__ void relu_to_e4m3(const f32x16 (&acc)[NT][A::kMB], i32x8 (&x)[NT][Fp8<A>::kKBHidden]) {
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
+  for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int d = 0; d < 8; ++d) x[t][0][d] = pack4_e4m3(acc[t][d / 4], 4 * (d % 4));
+    for (int kb = 0; kb < Fp8<A>::kKBHidden; ++kb)
 #pragma unroll
-    for (int d = 0; d < 4; ++d) x[t][1][d] = pack4_e4m3(acc[t][2], 4 * d);
-#pragma unroll
-    for (int d = 4; d < 8; ++d) x[t][1][d] = 0;
-  }
+      for (int d = 0; d < 8; ++d) {
+        const int mb = 2 * kb + d / 4;
+        x[t][kb][d] = mb < A::kMB ? pack4_e4m3(acc[t][mb], 4 * (d % 4)) : 0;
+      }
 }
 
-template <int P>
+template <int P, class A>
 __global__ __launch_bounds__(kNifBlock, 1) void k_nif_infer(const uint8_t* gpack, const float* gbias, NifIO io) {
   constexpr int KPL = Prec<P>::KPL;
-  using G = Geometry<KPL>;
+  using G = Geometry<KPL, A>;
+  using K = Pack<P, A>;
   using Frag = typename Prec<P>::Frag;
+  constexpr int L = A::kLayers, H = A::kHidden, MB = A::kMB;
   constexpr bool kAccurate = (P == NPT_FP32);
   constexpr int NT = (P == NPT_FP32) ? 1 : NPT_NIF_TILES;  // 32-ray column tiles per wave
   constexpr int kRays = 32 * NT;
   extern __shared__ float4 smem4[];
   uint8_t* lds = reinterpret_cast<uint8_t*>(smem4);
-  float* lbias = reinterpret_cast<float*>(lds + lds_offset<P>(kLayers + 1));
-  const int* lscale = reinterpret_cast<const int*>(lbias + kBiasFloats);
+  float* lbias = reinterpret_cast<float*>(lds + K::lds_offset(L + 1));
+  const int* lscale = reinterpret_cast<const int*>(lbias + A::kBiasFloats);
   uint64_t n;
   if (io.source == kSrcQueue) n = io.cnt[kCntEnv + io.depth];
   else n = io.n;
@@ -325,22 +366,38 @@ __global__ __launch_bounds__(kNifBlock, 1) void k_nif_infer(const uint8_t* gpack
 
   // stage the resident layers, the biases and the FP8 scale exponents
 #pragma unroll
-  for (int l = 0; l <= kLayers; ++l) {
-    if (!Prec<P>::kResident[l]) continue;
-    const uint4* src = reinterpret_cast<const uint4*>(gpack + global_offset<P>(l));
-    uint4* dst = reinterpret_cast<uint4*>(lds + lds_offset<P>(l));
-    for (int i = threadIdx.x; i < (int)(layer_bytes<P>(l) / 16); i += kNifBlock) dst[i] = src[i];
+  for (int l = 0; l <= L; ++l) {
+    if (!K::resident(l)) continue;
+    const uint4* src = reinterpret_cast<const uint4*>(gpack + K::global_offset(l));
+    uint4* dst = reinterpret_cast<uint4*>(lds + K::lds_offset(l));
+    for (int i = threadIdx.x; i < (int)(K::layer_bytes(l) / 16); i += kNifBlock) dst[i] = src[i];
   }
   {
     const uint32_t* src = reinterpret_cast<const uint32_t*>(gbias);
     uint32_t* dst = reinterpret_cast<uint32_t*>(lbias);
-    for (int i = threadIdx.x; i < kBiasFloats + kScaleWords; i += kNifBlock) dst[i] = src[i];
+    for (int i = threadIdx.x; i < A::kBiasFloats + kScaleWords; i += kNifBlock) dst[i] = src[i];
   }
   __syncthreads();
-  // weights of layer l: from LDS when resident, else from the packed buffer
-  auto frags = [&](int l) -> const Frag* {
-    return Prec<P>::kResident[l] ? reinterpret_cast<const Frag*>(lds + lds_offset<P>(l))
-                                 : reinterpret_cast<const Frag*>(gpack + global_offset<P>(l));
+  // weights of the first and output layers (compile-time residency) ...
+  const Frag* fr_first = reinterpret_cast<const Frag*>(K::resident(0) ? lds + K::lds_offset(0)
+                                                                       : gpack + K::global_offset(0));
+  const Frag* fr_out = reinterpret_cast<const Frag*>(K::resident(L) ? lds + K::lds_offset(L)
+                                                                     : gpack + K::global_offset(L));
+  // ... and of hidden layer l = 1..L-1 (wave-uniform l)
+  auto hidden = [&](int l) -> const uint8_t* {
+    if constexpr (K::hidden_resident()) {
+      uint32_t off = 0;
+#pragma unroll
+      for (int i = 1; i < L; ++i)
+        if (i == l) off = (uint32_t)K::lds_offset(i);
+      return lds + off;
+    } else {
+      const uint8_t* p = gpack;
+#pragma unroll
+      for (int i = 1; i < L; ++i)
+        if (i == l) p = K::resident(i) ? lds + K::lds_offset(i) : gpack + K::global_offset(i);
+      return p;
+    }
   };
 
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
@@ -348,6 +405,14 @@ __global__ __launch_bounds__(kNifBlock, 1) void k_nif_infer(const uint8_t* gpack
   const uint64_t waves_total = (uint64_t)gridDim.x * kNifWaves;
 
   for (uint64_t tile = (uint64_t)blockIdx.x * kNifWaves + wave; tile * kRays < n; tile += waves_total) {
+    // Wider networks: an offset of 0 that the compiler cannot see through
+    // (tiles stay far below 2^62) keeps the first- and output-layer operands
+    // inside the tile loop; hoisted out of it, they would not fit in the
+    // registers of two waves per SIMD and would spill.
+    const int z = H > 96 ? (int)(tile >> 62) : 0;
+    const Frag* fr0 = fr_first + z;
+    const Frag* fro = fr_out + z;
+    const float* lb0 = lbias + z;
     float u[NT], v[NT], bx[NT], by[NT], bz[NT];
     uint32_t slot[NT];
     bool valid[NT];
@@ -376,55 +441,93 @@ __global__ __launch_bounds__(kNifBlock, 1) void k_nif_infer(const uint8_t* gpack
       }
     }
 
-    // layer-0 operands: Fourier features
-    Frag x[NT][G::kKBHidden];
+    // Fourier features: the first layer's operands, kept for a skip layer
+    Frag xf[NT][G::kKBFeat];
+    [[maybe_unused]] i32x8 x8f[NT][1];  // FP8 skip layer: the features in E4M3
 #pragma unroll
     for (int t = 0; t < NT; ++t)
 #pragma unroll
       for (int kb = 0; kb < G::kKBFeat; ++kb) {
         if constexpr (KPL == 1) {
-          x[t][kb] = feature<P, kAccurate>(input_index<KPL>(0, kb, h, 0), u[t], v[t]);
+          xf[t][kb] = feature<A, kAccurate>(kb * G::kKB, kb * G::kKB + 1, h, u[t], v[t]);
         } else {
+          float fv[KPL];
 #pragma unroll
-          for (int e = 0; e < KPL; ++e)
-            x[t][kb][e] = Prec<P>::cvt(feature<P, kAccurate>(input_index<KPL>(0, kb, h, e), u[t], v[t]));
+          for (int e = 0; e < KPL; ++e) {
+            fv[e] = feature<A, kAccurate>(kb * G::kKB + e, kb * G::kKB + KPL + e, h, u[t], v[t]);
+            xf[t][kb][e] = Prec<P>::cvt(fv[e]);
+          }
+          if constexpr (P == NPT_FP8 && A::kSkip != 0) {
+            // byte 8 kb + e of the feature K-block, straight from FP32
+            x8f[t][0][2 * kb] = pack_e4m3<true>(fv[2], fv[3], pack_e4m3<false>(fv[0], fv[1], 0));
+            x8f[t][0][2 * kb + 1] = pack_e4m3<true>(fv[6], fv[7], pack_e4m3<false>(fv[4], fv[5], 0));
+          }
         }
       }
-
-    if constexpr (P == NPT_FP8) {
-      // layer 0 on FP16 operands, layers 1..4 on E4M3, FP16 input to the output layer
-      f32x16 acc[NT][kMB];
-      i32x8 x8[NT][kKB8];
-      init_acc<NT>(lbias, h, acc);
-      mma_layer<P, NT, G::kKBFeat>(frags(0), lane, x, acc);
-      relu_to_e4m3<NT>(acc, x8);
-#pragma unroll 1
-      for (int l = 1; l < kLayers; ++l) {
-        init_acc<NT>(lbias + l * kHidden, h, acc);
-        mma_layer_e4m3<NT>(reinterpret_cast<const i32x8*>(lds + lds_offset<P>(l)), lane, 127 - lscale[l], x8, acc);
-        if (l + 1 < kLayers) relu_to_e4m3<NT>(acc, x8);
-      }
-      relu_to_frags<P, NT>(acc, x);
-    } else {
-      // layer 0 (64 -> 96), then 1..4 (96 -> 96, all in LDS)
-      dense_relu<P, NT, G::kKBFeat>(frags(0), lbias, lane, h, x);
-#pragma unroll 1
-      for (int l = 1; l < kLayers; ++l) dense_relu<P, NT, G::kKBHidden>(frags(l), lbias + l * kHidden, lane, h, x);
+    if constexpr (P == NPT_FP8 && A::kSkip != 0) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int d = 2 * G::kKBFeat; d < 8; ++d) x8f[t][0][d] = 0;
     }
 
-    // output layer (rows 0..2 of one padded M-block) and the colour matrix
-    const Frag* fr = frags(kLayers);
+    Frag x[NT][G::kKBHidden];
+    f32x16 acc[NT][MB];
+    init_acc<NT, A>(lb0, h, acc);
+    mma_layer<P, A, NT, G::kKBFeat, G::kKBFeat, 0>(fr0, lane, xf, acc);
+    if constexpr (P == NPT_FP8) {
+      // the first layer on FP16 operands, the hidden-to-hidden layers on
+      // E4M3, FP16 input to the output layer
+      constexpr int NKB8 = Fp8<A>::kKBHidden;
+      i32x8 x8[NT][NKB8];
+      relu_to_e4m3<A, NT>(acc, x8);
+#pragma unroll 1
+      for (int l = 1; l < L; ++l) {
+        init_acc<NT, A>(lbias + l * H, h, acc);
+        const i32x8* fr = reinterpret_cast<const i32x8*>(hidden(l));
+        const int sa = 127 - lscale[l];
+        if (A::kSkip != 0 && l == A::kSkip) {
+          mma_layer_e4m3<A, NT, NKB8, NKB8 + 1, 0>(fr, lane, sa, x8, acc);
+          mma_layer_e4m3<A, NT, 1, NKB8 + 1, NKB8>(fr, lane, sa, x8f, acc);
+        } else {
+          mma_layer_e4m3<A, NT, NKB8, NKB8, 0>(fr, lane, sa, x8, acc);
+        }
+        if (l + 1 < L) relu_to_e4m3<A, NT>(acc, x8);
+      }
+      relu_to_frags<P, A, NT>(acc, x);
+    } else {
+      relu_to_frags<P, A, NT>(acc, x);
+#pragma unroll 1
+      for (int l = 1; l < L; ++l) {
+        init_acc<NT, A>(lbias + l * H, h, acc);
+        const Frag* fr = reinterpret_cast<const Frag*>(hidden(l));
+        if (A::kSkip != 0 && l == A::kSkip) {
+          constexpr int NKBIN = G::kKBHidden + G::kKBFeat;
+          mma_layer<P, A, NT, G::kKBHidden, NKBIN, 0>(fr, lane, x, acc);
+          mma_layer<P, A, NT, G::kKBFeat, NKBIN, G::kKBHidden>(fr, lane, xf, acc);
+        } else {
+          mma_layer<P, A, NT, G::kKBHidden, G::kKBHidden, 0>(fr, lane, x, acc);
+        }
+        relu_to_frags<P, A, NT>(acc, x);
+      }
+    }
+
+    // output layer: its 3 rows from the compact fragments, zero A rows for
+    // the other 29; then the colour matrix
     f32x16 o[NT];
     {
       f32x16 b;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) b[r] = lbias[kLayers * kHidden + acc_row(0, h, r)];
+      for (int r = 0; r < 16; ++r) b[r] = lb0[L * H + acc_row(0, h, r)];
 #pragma unroll
       for (int t = 0; t < NT; ++t) o[t] = b;
     }
+    const bool real_row = col < kOut;
+    const int orow = real_row ? col : 0;
 #pragma unroll
     for (int kb = 0; kb < G::kKBHidden; ++kb) {
-      const Frag a = fr[kb * 64 + lane];
+      Frag a = fro[(kb * 2 + h) * 3 + orow];
+      if (!real_row) a = Frag{};
 #pragma unroll
       for (int t = 0; t < NT; ++t) o[t] = Prec<P>::mma(a, x[t][kb], o[t]);
     }
@@ -463,60 +566,88 @@ __global__ __launch_bounds__(kNifBlock, 1) void k_nif_infer(const uint8_t* gpack
 }
 
 // ---------------------------------------------------------------------------
-// host launchers
+// host launchers: network shape by index (resident_arch), precision by code
 // ---------------------------------------------------------------------------
-size_t nif_packed_bytes(int prec) {
-  switch (prec) {
-    case NPT_FP32: return global_offset<NPT_FP32>(kLayers + 1);
-    case NPT_FP16: return global_offset<NPT_FP16>(kLayers + 1);
-    case NPT_BF16: return global_offset<NPT_BF16>(kLayers + 1);
-    case NPT_FP8: return global_offset<NPT_FP8>(kLayers + 1);
-    default: return 0;
+template <class F>
+static auto with_arch(int arch, F&& f) {
+  switch (arch) {
+    case 1: return f(ArchH128Skip40{});
+    case 2: return f(ArchH128Skip64{});
+    case 3: return f(ArchH64{});
+    default: return f(ArchDefault{});
   }
-}
-
-size_t nif_bias_bytes() { return (kBiasFloats + kScaleWords) * sizeof(float); }
-
-hipError_t launch_nif_pack(int prec, const float* master, void* frags, float* bias, hipStream_t s) {
-  switch (prec) {
-    case NPT_FP32: hipLaunchKernelGGL(k_nif_pack<NPT_FP32>, dim3(64), dim3(256), 0, s, master, (float*)frags, bias); break;
-    case NPT_FP16: hipLaunchKernelGGL(k_nif_pack<NPT_FP16>, dim3(64), dim3(256), 0, s, master, (_Float16*)frags, bias); break;
-    case NPT_BF16: hipLaunchKernelGGL(k_nif_pack<NPT_BF16>, dim3(64), dim3(256), 0, s, master, (__bf16*)frags, bias); break;
-    case NPT_FP8: hipLaunchKernelGGL(k_nif_pack_fp8, dim3(kLayers + 1), dim3(256), 0, s, master, (uint8_t*)frags, bias); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_nif_dequant(int prec, const float* master, const float* bias, float* out, int n, hipStream_t s) {
-  switch (prec) {
-    case NPT_FP32: hipLaunchKernelGGL(k_nif_dequant<NPT_FP32>, dim3(64), dim3(256), 0, s, master, bias, out, n); break;
-    case NPT_FP16: hipLaunchKernelGGL(k_nif_dequant<NPT_FP16>, dim3(64), dim3(256), 0, s, master, bias, out, n); break;
-    case NPT_BF16: hipLaunchKernelGGL(k_nif_dequant<NPT_BF16>, dim3(64), dim3(256), 0, s, master, bias, out, n); break;
-    case NPT_FP8: hipLaunchKernelGGL(k_nif_dequant<NPT_FP8>, dim3(64), dim3(256), 0, s, master, bias, out, n); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
 }
 
 template <int P>
-static hipError_t launch_infer_p(const void* frags, const float* bias, const NifIO& io, int grid, hipStream_t s) {
-  const size_t lds = nif_lds_bytes<P>();
-  hipError_t e = hipFuncSetAttribute((const void*)k_nif_infer<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_nif_infer<P>, dim3(grid), dim3(kNifBlock), lds, s, (const uint8_t*)frags, bias, io);
-  return hipGetLastError();
+using PrecTag = std::integral_constant<int, P>;
+
+static bool prec_ok(int prec) { return prec >= NPT_FP32 && prec <= NPT_FP8; }
+static bool arch_ok(int arch) { return arch >= 0 && arch < kNumArch; }
+
+template <class F>
+static auto with_prec(int prec, F&& f) {
+  switch (prec) {
+    case NPT_FP16: return f(PrecTag<NPT_FP16>{});
+    case NPT_BF16: return f(PrecTag<NPT_BF16>{});
+    case NPT_FP8: return f(PrecTag<NPT_FP8>{});
+    default: return f(PrecTag<NPT_FP32>{});
+  }
 }
 
-static hipError_t launch_infer(int prec, const void* frags, const float* bias, const NifIO& io, int grid,
+size_t nif_packed_bytes(int arch, int prec) {
+  if (!arch_ok(arch) || !prec_ok(prec)) return 0;
+  return with_arch(arch, [&](auto a) {
+    using A = decltype(a);
+    return with_prec(prec, [&](auto p) { return Pack<decltype(p)::value, A>::global_offset(A::kLayers + 1); });
+  });
+}
+
+size_t nif_bias_bytes(int arch) {
+  if (!arch_ok(arch)) return 0;
+  return with_arch(arch, [&](auto a) { return (size_t)(decltype(a)::kBiasFloats + kScaleWords) * sizeof(float); });
+}
+
+hipError_t launch_nif_pack(int arch, int prec, const float* master, void* frags, float* bias, hipStream_t s) {
+  if (!arch_ok(arch) || !prec_ok(prec)) return hipErrorInvalidValue;
+  return with_arch(arch, [&](auto a) {
+    using A = decltype(a);
+    switch (prec) {
+      case NPT_FP32: hipLaunchKernelGGL((k_nif_pack<NPT_FP32, A>), dim3(64), dim3(256), 0, s, master, (float*)frags, bias); break;
+      case NPT_FP16: hipLaunchKernelGGL((k_nif_pack<NPT_FP16, A>), dim3(64), dim3(256), 0, s, master, (_Float16*)frags, bias); break;
+      case NPT_BF16: hipLaunchKernelGGL((k_nif_pack<NPT_BF16, A>), dim3(64), dim3(256), 0, s, master, (__bf16*)frags, bias); break;
+      default: hipLaunchKernelGGL((k_nif_pack_fp8<A>), dim3(A::kLayers + 1), dim3(256), 0, s, master, (uint8_t*)frags, bias); break;
+    }
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_nif_dequant(int arch, int prec, const float* master, const float* bias, float* out, int n,
+                              hipStream_t s) {
+  if (!arch_ok(arch) || !prec_ok(prec)) return hipErrorInvalidValue;
+  return with_arch(arch, [&](auto a) {
+    using A = decltype(a);
+    return with_prec(prec, [&](auto p) {
+      hipLaunchKernelGGL((k_nif_dequant<decltype(p)::value, A>), dim3(64), dim3(256), 0, s, master, bias, out, n);
+      return hipGetLastError();
+    });
+  });
+}
+
+static hipError_t launch_infer(int arch, int prec, const void* frags, const float* bias, const NifIO& io, int grid,
                                hipStream_t s) {
-  switch (prec) {
-    case NPT_FP32: return launch_infer_p<NPT_FP32>(frags, bias, io, grid, s);
-    case NPT_FP16: return launch_infer_p<NPT_FP16>(frags, bias, io, grid, s);
-    case NPT_BF16: return launch_infer_p<NPT_BF16>(frags, bias, io, grid, s);
-    case NPT_FP8: return launch_infer_p<NPT_FP8>(frags, bias, io, grid, s);
-    default: return hipErrorInvalidValue;
-  }
+  if (!arch_ok(arch) || !prec_ok(prec)) return hipErrorInvalidValue;
+  return with_arch(arch, [&](auto a) {
+    using A = decltype(a);
+    return with_prec(prec, [&](auto p) {
+      constexpr int P = decltype(p)::value;
+      const size_t lds = Pack<P, A>::kLdsBytes;
+      hipError_t e = hipFuncSetAttribute((const void*)k_nif_infer<P, A>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((k_nif_infer<P, A>), dim3(grid), dim3(kNifBlock), lds, s, (const uint8_t*)frags, bias, io);
+      return hipGetLastError();
+    });
+  });
 }
 
 static int nif_grid(uint64_t n, int num_cus) {
@@ -524,7 +655,7 @@ static int nif_grid(uint64_t n, int num_cus) {
   return (int)(tiles < 1 ? 1 : (tiles > (uint64_t)num_cus ? num_cus : tiles));
 }
 
-hipError_t launch_nif_queue(int prec, const void* frags, const float* bias, const ColourMatrix& cm,
+hipError_t launch_nif_queue(int arch, int prec, const void* frags, const float* bias, const ColourMatrix& cm,
                             const EnvQueue& env, float4* L, const uint32_t* cnt, uint32_t depth, uint64_t max_rays,
                             int num_cus, hipStream_t s) {
   NifIO io{};
@@ -534,22 +665,22 @@ hipError_t launch_nif_queue(int prec, const void* frags, const float* bias, cons
   io.L = L;
   io.cnt = cnt;
   io.depth = depth;
-  return launch_infer(prec, frags, bias, io, nif_grid(max_rays, num_cus), s);
+  return launch_infer(arch, prec, frags, bias, io, nif_grid(max_rays, num_cus), s);
 }
 
-hipError_t launch_nif_dirs(int prec, const void* frags, const float* bias, const ColourMatrix& cm, const float* dirs,
-                           uint64_t n, float* rgb, int num_cus, hipStream_t s) {
+hipError_t launch_nif_dirs(int arch, int prec, const void* frags, const float* bias, const ColourMatrix& cm,
+                           const float* dirs, uint64_t n, float* rgb, int num_cus, hipStream_t s) {
   NifIO io{};
   io.cm = cm;
   io.source = kSrcDirs;
   io.dirs = dirs;
   io.out = rgb;
   io.n = n;
-  return launch_infer(prec, frags, bias, io, nif_grid(n, num_cus), s);
+  return launch_infer(arch, prec, frags, bias, io, nif_grid(n, num_cus), s);
 }
 
-hipError_t launch_nif_grid(int prec, const void* frags, const float* bias, const ColourMatrix& cm, uint32_t gw,
-                           uint32_t gh, float* zout, int num_cus, hipStream_t s) {
+hipError_t launch_nif_grid(int arch, int prec, const void* frags, const float* bias, const ColourMatrix& cm,
+                           uint32_t gw, uint32_t gh, float* zout, int num_cus, hipStream_t s) {
   NifIO io{};
   io.cm = cm;
   io.source = kSrcGrid;
@@ -557,7 +688,7 @@ hipError_t launch_nif_grid(int prec, const void* frags, const float* bias, const
   io.gh = gh;
   io.n = (uint64_t)gw * gh;
   io.out = zout;
-  return launch_infer(prec, frags, bias, io, nif_grid(io.n, num_cus), s);
+  return launch_infer(arch, prec, frags, bias, io, nif_grid(io.n, num_cus), s);
 }
 
 }  // namespace npt

@@ -917,9 +917,9 @@ hipError_t launch_params_dequant(int prec, const NifShape& shape, const float* m
   return hipGetLastError();
 }
 
-hipError_t grid_eval(TrainScratch& s, int prec, const void* frags, const float* bias, const ColourMatrix& cm,
-                     const TrainTargets& t, uint32_t gw, uint32_t gh, int num_cus, float out[2], hipStream_t st,
-                     LayeredScratch* layered, const NifShape* shape) {
+hipError_t grid_eval(TrainScratch& s, int prec, int arch, const void* frags, const float* bias,
+                     const ColourMatrix& cm, const TrainTargets& t, uint32_t gw, uint32_t gh, int num_cus,
+                     float out[2], hipStream_t st, LayeredScratch* layered, const NifShape* shape) {
   const uint64_t n = (uint64_t)gw * gh;
   hipError_t e;
   const int blocks = 256;
@@ -942,7 +942,7 @@ hipError_t grid_eval(TrainScratch& s, int prec, const void* frags, const float* 
     io.out = s.zgrid;
     // frags: the operand-precision weights; bias: the FP32 master
     if ((e = nif_layered(*layered, prec, *shape, frags, bias, cm, io, st)) != hipSuccess) return e;
-  } else if ((e = launch_nif_grid(prec, frags, bias, cm, gw, gh, s.zgrid, num_cus, st)) != hipSuccess) {
+  } else if ((e = launch_nif_grid(arch, prec, frags, bias, cm, gw, gh, s.zgrid, num_cus, st)) != hipSuccess) {
     return e;
   }
   hipLaunchKernelGGL(k_grid_err, dim3(blocks), dim3(256), 0, st, s.zgrid, t.map, (int)t.w, (int)t.h, gw, gh,

@@ -100,8 +100,9 @@ struct npt_ctx {
   uint32_t adam_step = 0;
   int nif_prec = NPT_FP16;
   ColourMatrix nif_cm{};  // output colour space of the uploaded network
-  NifShape nif_shape{nif::kHidden, nif::kLayers, 0, nif::kFreq};
-  bool nif_layered = false;  // layer-serial GEMM inference (shapes other than the default, or on request)
+  NifShape nif_shape{nif::ArchDefault::kHidden, nif::ArchDefault::kLayers, 0, nif::ArchDefault::kFreq};
+  int nif_arch = 0;          // LDS-resident kernel of this shape (nif::resident_arch)
+  bool nif_layered = false;  // layer-serial GEMM inference (shapes without a resident kernel, or on request)
   LayeredScratch layered;
   TrainScratch train;
 
@@ -220,11 +221,12 @@ int repack_nif(npt_ctx* c, hipStream_t s) {
     HIP_TRY(c, launch_params_convert(c->nif_prec, c->d_master.as<float>(), c->d_frags.p, np, s));
     return NPT_OK;
   }
-  const size_t bytes = nif_packed_bytes(c->nif_prec);
+  const size_t bytes = nif_packed_bytes(c->nif_arch, c->nif_prec);
   if (bytes == 0) return fail(c, NPT_E_UNSUPPORTED, "precision not supported");
   HIP_TRY(c, c->d_frags.ensure(bytes));
-  HIP_TRY(c, c->d_bias.ensure(nif_bias_bytes()));
-  HIP_TRY(c, launch_nif_pack(c->nif_prec, c->d_master.as<float>(), c->d_frags.p, c->d_bias.as<float>(), s));
+  HIP_TRY(c, c->d_bias.ensure(nif_bias_bytes(c->nif_arch)));
+  HIP_TRY(c, launch_nif_pack(c->nif_arch, c->nif_prec, c->d_master.as<float>(), c->d_frags.p,
+                             c->d_bias.as<float>(), s));
   return NPT_OK;
 }
 
@@ -549,7 +551,7 @@ extern "C" int npt_set_env_mode(npt_ctx* c, int mode) {
 // NIF
 // ===========================================================================
 static bool nif_desc_ok(const npt_nif_desc* d) {
-  return d && d->n_freq >= 1 && d->n_freq <= (uint32_t)nif::kFreq && d->hidden >= 32 && d->hidden <= 1024 &&
+  return d && d->n_freq >= 1 && d->n_freq <= (uint32_t)nif::kMaxFreq && d->hidden >= 32 && d->hidden <= 1024 &&
          d->hidden % 32 == 0 && d->layers >= 1 && d->layers <= 8 && (d->skip == 0 || d->skip < d->layers);
 }
 
@@ -570,10 +572,11 @@ extern "C" int npt_nif_upload(npt_ctx* c, const npt_nif_desc* desc, const float*
                 "NIF shape must be n_freq 1..16, hidden 32..1024 (a multiple of 32), layers 1..8, skip 0 or < layers");
   if (desc->colour > NPT_COLOUR_YCOCG) return fail(c, NPT_E_INVALID_ARG, "unknown NIF colour space");
   const NifShape shape{(int)desc->hidden, (int)desc->layers, (int)desc->skip, (int)desc->n_freq};
-  const bool layered = desc->layered != 0 || shape.hidden != nif::kHidden || shape.layers != nif::kLayers ||
-                       shape.skip != 0 || shape.n_freq != nif::kFreq;
+  const int arch = nif::resident_arch(shape.hidden, shape.layers, shape.skip, shape.n_freq);
+  const bool layered = desc->layered != 0 || arch < 0;
   if (layered && c->nif_prec == NPT_FP8)
-    return fail(c, NPT_E_UNSUPPORTED, "FP8 inference needs the 16/96/5 network; set another precision first");
+    return fail(c, NPT_E_UNSUPPORTED,
+                "FP8 inference needs a network shape with an LDS-resident kernel; set another precision first");
   if (!params || n != (uint64_t)shape_params(shape)) return fail(c, NPT_E_INVALID_ARG, "parameter count mismatch");
   if (!finite_all(params, n)) return fail(c, NPT_E_NAN_INPUT, "non-finite NIF parameter");
   int r = need_device(c);
@@ -591,6 +594,7 @@ extern "C" int npt_nif_upload(npt_ctx* c, const npt_nif_desc* desc, const float*
   c->nif_cm = colour_matrix(desc->colour);
   c->nif_shape = shape;
   c->nif_layered = layered;
+  c->nif_arch = layered ? 0 : arch;
   r = repack_nif(c, s);
   if (r) return r;
   HIP_TRY(c, hipStreamSynchronize(s));
@@ -614,9 +618,9 @@ extern "C" int npt_nif_set_precision(npt_ctx* c, int prec) {
   if (prec < NPT_FP32 || prec > NPT_FP8) return fail(c, NPT_E_INVALID_ARG, "unknown precision");
   if (prec == NPT_FP8 && (c->host_only || !c->fp8_capable))
     return fail(c, NPT_E_UNSUPPORTED, "FP8 NIF inference needs gfx950");
-  if (nif_packed_bytes(prec) == 0) return fail(c, NPT_E_UNSUPPORTED, "precision not built");
+  if (nif_packed_bytes(0, prec) == 0) return fail(c, NPT_E_UNSUPPORTED, "precision not built");
   if (prec == NPT_FP8 && c->have_nif && c->nif_layered)
-    return fail(c, NPT_E_UNSUPPORTED, "FP8 inference needs the 16/96/5 network on the LDS-resident path");
+    return fail(c, NPT_E_UNSUPPORTED, "FP8 inference needs a network shape with an LDS-resident kernel");
   const int old = c->nif_prec;
   c->nif_prec = prec;
   if (c->have_nif) {
@@ -641,7 +645,7 @@ extern "C" int npt_nif_get_dequantized(npt_ctx* c, float* params, uint64_t n) {
   hipError_t e = c->nif_layered
                     ? launch_params_dequant(c->nif_prec, c->nif_shape, c->d_master.as<float>(), c->d_frags.p,
                                             tmp.as<float>(), nullptr)
-                    : launch_nif_dequant(c->nif_prec, c->d_master.as<float>(), c->d_bias.as<float>(),
+                    : launch_nif_dequant(c->nif_arch, c->nif_prec, c->d_master.as<float>(), c->d_bias.as<float>(),
                                          tmp.as<float>(), (int)n, nullptr);
   if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
   if (e == hipSuccess) e = hipMemcpy(params, tmp.p, n * sizeof(float), hipMemcpyDeviceToHost);
@@ -745,11 +749,11 @@ extern "C" int npt_nif_eval_grid(npt_ctx* c, uint32_t gw, uint32_t gh, float* ou
   hipStream_t s = (hipStream_t)stream;
   float res[2] = {0, 0};
   if (c->nif_layered)
-    HIP_TRY(c, grid_eval(c->train, c->nif_prec, c->d_frags.p, c->d_master.as<float>(), c->nif_cm, train_targets(c),
-                         gw, gh, c->num_cus, res, s, &c->layered, &c->nif_shape));
+    HIP_TRY(c, grid_eval(c->train, c->nif_prec, 0, c->d_frags.p, c->d_master.as<float>(), c->nif_cm,
+                         train_targets(c), gw, gh, c->num_cus, res, s, &c->layered, &c->nif_shape));
   else
-    HIP_TRY(c, grid_eval(c->train, c->nif_prec, c->d_frags.p, c->d_bias.as<float>(), c->nif_cm, train_targets(c),
-                         gw, gh, c->num_cus, res, s));
+    HIP_TRY(c, grid_eval(c->train, c->nif_prec, c->nif_arch, c->d_frags.p, c->d_bias.as<float>(), c->nif_cm,
+                         train_targets(c), gw, gh, c->num_cus, res, s));
   out2[0] = res[0];
   out2[1] = res[1];
   return ok(c);
@@ -775,7 +779,7 @@ extern "C" int npt_env_query(npt_ctx* c, int mode, const float* d_dirs, uint64_t
       HIP_TRY(c, nif_layered(c->layered, c->nif_prec, c->nif_shape, c->d_frags.p, c->d_master.as<float>(), c->nif_cm,
                              io, s));
     } else {
-      HIP_TRY(c, launch_nif_dirs(c->nif_prec, c->d_frags.p, c->d_bias.as<float>(), c->nif_cm, d_dirs, n, d_rgb,
+      HIP_TRY(c, launch_nif_dirs(c->nif_arch, c->nif_prec, c->d_frags.p, c->d_bias.as<float>(), c->nif_cm, d_dirs, n, d_rgb,
                                  c->num_cus, s));
     }
   } else {
@@ -906,7 +910,7 @@ extern "C" int npt_render(npt_ctx* c, uint32_t W, uint32_t H, uint32_t spp, uint
           HIP_TRY(c, nif_layered(c->layered, c->nif_prec, c->nif_shape, c->d_frags.p, c->d_master.as<float>(),
                                  c->nif_cm, io, s));
         } else {
-          HIP_TRY(c, launch_nif_queue(c->nif_prec, c->d_frags.p, c->d_bias.as<float>(), c->nif_cm, eq, L, cnt, k, n,
+          HIP_TRY(c, launch_nif_queue(c->nif_arch, c->nif_prec, c->d_frags.p, c->d_bias.as<float>(), c->nif_cm, eq, L, cnt, k, n,
                                       c->num_cus, s));
         }
         if (timing) HIP_TRY(c, hipEventRecord(c->env_events.back(), s));

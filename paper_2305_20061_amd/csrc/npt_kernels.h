@@ -30,17 +30,18 @@ hipError_t launch_trace_primary(int stack_depth, const SceneView& sc, const Came
                                 const PassView& pv, uint32_t* prim, uint32_t* inst, float* t, float* normal,
                                 int num_cus, hipStream_t s);
 
-// k_nif.hip
-size_t nif_packed_bytes(int prec);
-hipError_t launch_nif_pack(int prec, const float* master, void* frags, float* bias, hipStream_t s);
-hipError_t launch_nif_dequant(int prec, const float* master, const float* bias, float* out, int n, hipStream_t s);
-size_t nif_bias_bytes();
-hipError_t launch_nif_queue(int prec, const void* frags, const float* bias, const ColourMatrix& cm,
+// k_nif.hip (arch: nif::resident_arch index of the network shape)
+size_t nif_packed_bytes(int arch, int prec);
+hipError_t launch_nif_pack(int arch, int prec, const float* master, void* frags, float* bias, hipStream_t s);
+hipError_t launch_nif_dequant(int arch, int prec, const float* master, const float* bias, float* out, int n,
+                              hipStream_t s);
+size_t nif_bias_bytes(int arch);
+hipError_t launch_nif_queue(int arch, int prec, const void* frags, const float* bias, const ColourMatrix& cm,
                             const EnvQueue& env, float4* L, const uint32_t* cnt, uint32_t depth, uint64_t max_rays,
                             int num_cus, hipStream_t s);
-hipError_t launch_nif_dirs(int prec, const void* frags, const float* bias, const ColourMatrix& cm, const float* dirs,
-                           uint64_t n, float* rgb, int num_cus, hipStream_t s);
-hipError_t launch_nif_grid(int prec, const void* frags, const float* bias, const ColourMatrix& cm, uint32_t gw,
-                           uint32_t gh, float* zout, int num_cus, hipStream_t s);
+hipError_t launch_nif_dirs(int arch, int prec, const void* frags, const float* bias, const ColourMatrix& cm,
+                           const float* dirs, uint64_t n, float* rgb, int num_cus, hipStream_t s);
+hipError_t launch_nif_grid(int arch, int prec, const void* frags, const float* bias, const ColourMatrix& cm,
+                           uint32_t gw, uint32_t gh, float* zout, int num_cus, hipStream_t s);
 
 }  // namespace npt

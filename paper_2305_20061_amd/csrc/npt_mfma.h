@@ -29,8 +29,6 @@ struct Prec<NPT_FP32> {
     return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
   }
   static __device__ __forceinline__ Elem cvt(float x) { return x; }
-  // inference: which layers live in LDS (FP32 weights do not all fit)
-  static constexpr bool kResident[6] = {false, true, true, true, true, false};
 };
 
 template <>
@@ -42,7 +40,6 @@ struct Prec<NPT_FP16> {
     return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
   }
   static __device__ __forceinline__ Elem cvt(float x) { return (_Float16)x; }
-  static constexpr bool kResident[6] = {true, true, true, true, true, true};
 };
 
 template <>
@@ -54,7 +51,6 @@ struct Prec<NPT_BF16> {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
   }
   static __device__ __forceinline__ Elem cvt(float x) { return (__bf16)x; }
-  static constexpr bool kResident[6] = {true, true, true, true, true, true};
 };
 
 // FP8 mode: FP16 operands for the first and output layers ...

@@ -1,8 +1,9 @@
 // npt_nif_layout.h -- register/LDS layout of the HDR-NIF MLP on MFMA
 // (shared by the inference, packing and training kernels of the library).
 //
-// Network (Sec. 3.2): 64 Fourier features -> 5 x [dense 96 + ReLU] -> dense 3
-// (YUV) -> fixed YUV->RGB matrix -> expm1.
+// Network (Sec. 3.2): 4*NF Fourier features -> L x [dense H + ReLU] -> dense
+// 3 -> fixed colour matrix -> expm1; with a skip layer S (Sec. 3.2, the
+// paper's own architecture) hidden layer S takes [h ; features].
 //
 // MFMA 32x32xK (K = 2 for FP32 operands, 16 for FP16/BF16): lane l holds,
 // per K-block, KPL = K/2 consecutive k of row/column l % 32 in lane half
@@ -19,14 +20,10 @@
 namespace npt {
 namespace nif {
 
-constexpr int kFreq = 16;
-constexpr int kFeat = 64;
-constexpr int kHidden = 96;
-constexpr int kLayers = 5;            // hidden layers
+constexpr int kMaxFreq = 16;
 constexpr int kOut = 3;
-constexpr int kMB = kHidden / 32;     // M-blocks of a hidden layer
-constexpr int kParams = kFeat * kHidden + kHidden + (kLayers - 1) * (kHidden * kHidden + kHidden) +
-                        kOut * kHidden + kOut;  // 43,779
+// FP8 weight-scale exponents stored after the bias table (one per layer)
+constexpr int kScaleWords = 16;
 
 // Frequencies round(2^((k+1)/2)), k = 0..15.
 __host__ __device__ constexpr int frequency(int k) {
@@ -35,67 +32,115 @@ __host__ __device__ constexpr int frequency(int k) {
        : k == 13 ? 128 : k == 14 ? 181 : 256;
 }
 
-// Offsets of W_l and b_l (l = 0..5) in the flat parameter vector.
-__host__ __device__ constexpr int layer_in(int l) { return l == 0 ? kFeat : kHidden; }
-__host__ __device__ constexpr int layer_out(int l) { return l == kLayers ? kOut : kHidden; }
-__host__ __device__ constexpr int w_offset(int l) {
-  int o = 0;
-  for (int i = 0; i < l; ++i) o += layer_out(i) * layer_in(i) + layer_out(i);
-  return o;
-}
-__host__ __device__ constexpr int b_offset(int l) { return w_offset(l) + layer_out(l) * layer_in(l); }
-
-// Per-precision MFMA geometry: KPL elements per lane per K-block.
-template <int KPL>
-struct Geometry {
-  static constexpr int kKB = 2 * KPL;              // K per MFMA
-  static constexpr int kRegsPerKB = KPL;           // accumulator registers feeding one K-block
-  static constexpr int kKBPerMB = 16 / KPL;        // K-blocks from one 32-row M-block
-  static constexpr int kKBFeat = kFeat / kKB;      // K-blocks of layer 0
-  static constexpr int kKBHidden = kHidden / kKB;  // K-blocks of layers 1..5
-  // fragments (64 lanes x KPL elements) per layer
-  __host__ __device__ static constexpr int frags(int l) {
-    return (l == kLayers ? 1 : kMB) * (l == 0 ? kKBFeat : kKBHidden);
-  }
-  __host__ __device__ static constexpr int frag_offset(int l) {
-    int o = 0;
-    for (int i = 0; i < l; ++i) o += frags(i);
-    return o;
-  }
-  static constexpr int kFragsTotal = frag_offset(kLayers + 1);
-  static constexpr int kElems = kFragsTotal * 64 * KPL;
-};
-
-// Input index (column of W_l) fed by element e of lane half h in K-block kb.
-template <int KPL>
-__host__ __device__ constexpr int input_index(int l, int kb, int h, int e) {
-  if (l == 0) return kb * 2 * KPL + h * KPL + e;  // features in natural order
-  const int mb = kb / Geometry<KPL>::kKBPerMB;
-  const int r = (kb % Geometry<KPL>::kKBPerMB) * KPL + e;
-  return 32 * mb + 8 * (r / 4) + 4 * h + (r % 4);
-}
-
 // Output row held in accumulator register r of lane half h, M-block mb.
 __host__ __device__ constexpr int acc_row(int mb, int h, int r) { return 32 * mb + 8 * (r / 4) + 4 * h + (r % 4); }
 
-// Bias table in LDS: 5 hidden layers x 96, then 32 for the output layer.
-// In device memory it is followed by kScaleWords words: the FP8 weight scale
-// exponent s of each layer (used by layers 1..4 in FP8 mode).
-constexpr int kBiasFloats = kLayers * kHidden + 32;
-constexpr int kScaleWords = 8;
+// One network shape: H hidden units, L hidden layers, skip layer S (0: none),
+// NF frequencies.  Parameters are [W_0, b_0, ..., W_L, b_L], W_l row-major
+// [out][in].
+template <int H, int L, int S, int NF>
+struct Arch {
+  static_assert(H >= 32 && H % 32 == 0, "hidden width is a multiple of 32");
+  static_assert(L >= 1 && L + 1 <= kScaleWords, "layer count");
+  static_assert(S == 0 || (S >= 1 && S < L), "skip layer is a hidden layer after the first");
+  static_assert(NF >= 1 && NF <= kMaxFreq, "frequency count");
+  static constexpr int kHidden = H, kLayers = L, kSkip = S, kFreq = NF;
+  static constexpr int kFeat = 4 * NF;
+  static constexpr int kMB = H / 32;  // M-blocks of a hidden layer
+  static constexpr int kBiasFloats = L * H + 32;  // bias table: L x H, then 32 for the output layer
+  __host__ __device__ static constexpr bool is_skip(int l) { return S != 0 && l == S; }
+  __host__ __device__ static constexpr int layer_in(int l) { return l == 0 ? kFeat : is_skip(l) ? H + kFeat : H; }
+  __host__ __device__ static constexpr int layer_out(int l) { return l == L ? kOut : H; }
+  __host__ __device__ static constexpr int w_offset(int l) {
+    int o = 0;
+    for (int i = 0; i < l; ++i) o += layer_out(i) * layer_in(i) + layer_out(i);
+    return o;
+  }
+  __host__ __device__ static constexpr int b_offset(int l) { return w_offset(l) + layer_out(l) * layer_in(l); }
+  __host__ __device__ static constexpr int params() { return w_offset(L + 1); }
+};
 
-// FP8 hidden-to-hidden layers (1..4) on MFMA 32x32x64: 32 E4M3 values per
-// lane per K-block; the 96 inputs pad to two K-blocks.  K-block 0 holds
-// M-blocks 0 and 1 of the previous layer's accumulator (byte e -> M-block
-// e / 16, register e % 16), K-block 1 M-block 2 (bytes 0..15) and 16 zero
-// bytes.  Input index fed by byte e of lane half h, or -1 for padding:
-constexpr int kKB8 = 2;
-constexpr int kFp8Frags = kMB * kKB8;         // A fragments per FP8 layer
-constexpr int kFp8LayerBytes = kFp8Frags * 64 * 32;
-__host__ __device__ constexpr int input_index_fp8(int kb, int h, int e) {
-  return kb == 0 ? acc_row(e / 16, h, e % 16) : (e < 16 ? acc_row(2, h, e) : -1);
+// Per-precision MFMA geometry: KPL elements per lane per K-block.  The output
+// layer is packed compactly: only its 3 real rows, [kb][h][row] fragments.
+template <int KPL, class A>
+struct Geometry {
+  static constexpr int kKB = 2 * KPL;                           // K per MFMA
+  static constexpr int kKBPerMB = 16 / KPL;                     // K-blocks from one 32-row M-block
+  static constexpr int kKBFeat = (A::kFeat + kKB - 1) / kKB;    // K-blocks of the features (zero padded)
+  static constexpr int kKBHidden = A::kHidden / kKB;            // K-blocks of a hidden activation
+  __host__ __device__ static constexpr int kb_in(int l) {
+    return l == 0 ? kKBFeat : A::is_skip(l) ? kKBHidden + kKBFeat : kKBHidden;
+  }
+  // fragments (64 lanes x KPL elements) of layer l; the output layer's
+  // 2 * 3 * kb_in compact fragments of KPL elements count as a fraction
+  __host__ __device__ static constexpr int elems(int l) {
+    return l == A::kLayers ? kb_in(l) * 2 * 3 * KPL : A::kMB * kb_in(l) * 64 * KPL;
+  }
+  __host__ __device__ static constexpr int elem_offset(int l) {
+    int o = 0;
+    for (int i = 0; i < l; ++i) o += elems(i);
+    return o;
+  }
+  static constexpr int kElems = elem_offset(A::kLayers + 1);
+};
+
+// Input index (column of W_l) fed by element e of lane half h in K-block kb,
+// or -1 for zero padding.  Features (layer 0, and the K-blocks of a skip
+// layer after its hidden input) come in natural order.
+template <int KPL, class A>
+__host__ __device__ constexpr int input_index(int l, int kb, int h, int e) {
+  using G = Geometry<KPL, A>;
+  if (l == 0 || (A::is_skip(l) && kb >= G::kKBHidden)) {
+    const int f = (l == 0 ? kb : kb - G::kKBHidden) * G::kKB + h * KPL + e;
+    return f >= A::kFeat ? -1 : l == 0 ? f : A::kHidden + f;
+  }
+  const int mb = kb / G::kKBPerMB;
+  const int r = (kb % G::kKBPerMB) * KPL + e;
+  return acc_row(mb, h, r);
 }
-__host__ __device__ constexpr bool fp8_layer(int l) { return l >= 1 && l < kLayers; }
+
+// FP8 hidden-to-hidden layers (1..L-1) on MFMA 32x32x64: 32 E4M3 values per
+// lane per K-block.  Hidden K-block kb holds M-blocks 2kb and 2kb + 1 of the
+// previous layer's accumulator (byte e -> M-block 2kb + e / 16, register
+// e % 16; zero bytes past the last M-block).  A skip layer has one more
+// K-block with the features, in the order in which the FP16 K-blocks of
+// layer 0 hold them (byte e -> FP16 K-block e / 8, element e % 8).
+template <class A>
+struct Fp8 {
+  static constexpr int kKBHidden = (A::kMB + 1) / 2;
+  __host__ __device__ static constexpr bool layer(int l) { return l >= 1 && l < A::kLayers; }
+  __host__ __device__ static constexpr int kb_in(int l) { return kKBHidden + (A::is_skip(l) ? 1 : 0); }
+  __host__ __device__ static constexpr int layer_bytes(int l) { return A::kMB * kb_in(l) * 64 * 32; }
+  __host__ __device__ static constexpr int input_index(int l, int kb, int h, int e) {
+    if (kb < kKBHidden) {
+      const int mb = 2 * kb + e / 16;
+      return mb < A::kMB ? acc_row(mb, h, e % 16) : -1;
+    }
+    const int kb16 = e / 8;
+    const int f = kb16 * 16 + h * 8 + e % 8;
+    return (kb16 < Geometry<8, A>::kKBFeat && f < A::kFeat) ? A::kHidden + f : -1;
+  }
+};
+
+// Shapes with an LDS-resident inference kernel (any other shape runs on the
+// layer-serial GEMM path): the default 16/96/5 network, the paper's H128 L5
+// network with the features concatenated at hidden layer 2 (40-d and 64-d
+// features), and the small H64 L2 network of the model-size study.
+using ArchDefault = Arch<96, 5, 0, 16>;
+using ArchH128Skip40 = Arch<128, 5, 2, 10>;
+using ArchH128Skip64 = Arch<128, 5, 2, 16>;
+using ArchH64 = Arch<64, 2, 0, 16>;
+constexpr int kNumArch = 4;
+
+// index of the LDS-resident shape (0 = the default), or -1
+inline int resident_arch(int hidden, int layers, int skip, int n_freq) {
+  auto is = [&](int H, int L, int S, int NF) { return hidden == H && layers == L && skip == S && n_freq == NF; };
+  if (is(96, 5, 0, 16)) return 0;
+  if (is(128, 5, 2, 10)) return 1;
+  if (is(128, 5, 2, 16)) return 2;
+  if (is(64, 2, 0, 16)) return 3;
+  return -1;
+}
 
 }  // namespace nif
 }  // namespace npt

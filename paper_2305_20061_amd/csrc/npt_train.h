@@ -118,9 +118,9 @@ hipError_t launch_params_dequant(int prec, const NifShape& shape, const float* m
 
 // grid evaluation (log-MSE, log-PSNR) of whichever inference path serves
 // the context: layered when `layered` is set, else the LDS-resident kernel
-hipError_t grid_eval(TrainScratch& s, int prec, const void* frags, const float* bias, const ColourMatrix& cm,
-                     const TrainTargets& t, uint32_t gw, uint32_t gh, int num_cus, float out[2], hipStream_t st,
-                     LayeredScratch* layered = nullptr, const NifShape* shape = nullptr);
+hipError_t grid_eval(TrainScratch& s, int prec, int arch, const void* frags, const float* bias,
+                     const ColourMatrix& cm, const TrainTargets& t, uint32_t gw, uint32_t gh, int num_cus,
+                     float out[2], hipStream_t st, LayeredScratch* layered = nullptr, const NifShape* shape = nullptr);
 
 // counters of the render loop (k_render.hip)
 hipError_t launch_stats_clear(unsigned long long* stats, hipStream_t s);
