@@ -128,6 +128,7 @@ struct RayFrame {
   float ox_n, oy_n, oz_n;  // origin terms of the entry planes
   float ox_f, oy_f, oz_f;  // and of the exit planes
   uint32_t near_x, near_y, near_z;
+  uint32_t wx, wy, wz;  // binary16 pair per axis: entry-plane weight (low), exit-plane weight (high)
 };
 
 constexpr float kSlabSlack = 1.0f + 0x1p-20f;
@@ -152,6 +153,9 @@ __device__ __forceinline__ RayFrame make_frame(V3 o, V3 d) {
   f.near_x = f.ix >= 0.0f ? 0u : 16u;
   f.near_y = f.iy >= 0.0f ? 32u : 48u;
   f.near_z = f.iz >= 0.0f ? 64u : 80u;
+  f.wx = f.ix >= 0.0f ? 0x3C000000u : 0x00003C00u;
+  f.wy = f.iy >= 0.0f ? 0x3C000000u : 0x00003C00u;
+  f.wz = f.iz >= 0.0f ? 0x3C000000u : 0x00003C00u;
   return f;
 }
 
@@ -263,7 +267,8 @@ __device__ __forceinline__ bool visit4(const char* base, uint32_t off, const Ray
 // made >= the true plane; it is the entry plane where the direction is
 // negative and the exit plane otherwise.  Both planes are formed as
 // fma(ext, w, lo) with per-ray weights w in {0, 1} (fma(ext, 1, lo) is that
-// rounded sum, fma(ext, 0, lo) is lo), so no per-child select is needed.
+// rounded sum, fma(ext, 0, lo) is lo), so no per-child select is needed; the
+// weights are binary16 halves of one register per axis, set once per ray.
 // Empty children (lo = +inf, ext = 0) miss as in visit4.
 template <class S>
 __device__ __forceinline__ bool visit4h(const char* base, uint32_t off, const RayFrame& f, float lim, S& st,
@@ -276,10 +281,10 @@ __device__ __forceinline__ bool visit4h(const char* base, uint32_t off, const Ra
   const float4 rf = *reinterpret_cast<const float4*>(base + off + 80u);
   uint32_t r0 = __float_as_uint(rf.x), r1 = __float_as_uint(rf.y), r2 = __float_as_uint(rf.z),
            r3 = __float_as_uint(rf.w);
-  const float wnx = f.ix >= 0.0f ? 0.0f : 1.0f, wny = f.iy >= 0.0f ? 0.0f : 1.0f, wnz = f.iz >= 0.0f ? 0.0f : 1.0f;
-  const float wfx = 1.0f - wnx, wfy = 1.0f - wny, wfz = 1.0f - wnz;
   auto lo16 = [](uint32_t v) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(v & 0xFFFFu)); };
   auto hi16 = [](uint32_t v) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(v >> 16)); };
+  const float wnx = lo16(f.wx), wny = lo16(f.wy), wnz = lo16(f.wz);
+  const float wfx = hi16(f.wx), wfy = hi16(f.wy), wfz = hi16(f.wz);
   auto child = [&](float lox, float ex, float loy, float ey, float loz, float ez) {
     return child_entry(f, __builtin_fmaf(ex, wnx, lox), __builtin_fmaf(ex, wfx, lox), __builtin_fmaf(ey, wny, loy),
                        __builtin_fmaf(ey, wfy, loy), __builtin_fmaf(ez, wnz, loz), __builtin_fmaf(ez, wfz, loz), lim);
