@@ -17,7 +17,16 @@
 namespace npt {
 using namespace nif;
 
-constexpr int kChunk = 2048;  // batch rows per split-K chunk of the weight gradients
+// batch rows per split-K chunk of the weight gradients: 2048, halved down to
+// 512 while a hidden-to-hidden layer's gradient would get fewer than 2048
+// waves of 32 x 32 tiles (narrow networks); batches are multiples of 2048
+constexpr int kChunkMax = 2048, kChunkMin = 512;
+static int grad_chunk(const NifShape& sh, uint32_t B) {
+  const int64_t tiles = (int64_t)(sh.hidden / 32) * (sh.hidden / 32);
+  int chunk = kChunkMax;
+  while (chunk > kChunkMin && tiles * (int64_t)(B / chunk) < 2048) chunk /= 2;
+  return chunk;
+}
 
 // ---------------------------------------------------------------------------
 // samples: (u, v) uniform from the TRAIN Philox stream; features; targets
@@ -71,6 +80,7 @@ struct GemmDesc {
   int64_t b_sk, b_sn;
   int M, N, K, k_chunk, splits;
   int mode;             // 0: relu(acc + bias[n]) -> C;  1: mask(m,n) > 0 ? acc : 0 -> C;  2: FP32 partial
+  float* a_rowsum;      // mode 2, optional: per split, the sums of A's rows over the split's K
   const float* bias;
   const void* mask;
   int64_t mask_ld;
@@ -98,6 +108,18 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
   const Elem zero = Prec<P>::cvt(0.0f);
+  // the waves of the first column tile also sum their rows of A (wave-uniform),
+  // as one more MFMA per K-block against a B of ones: every column of `rsum`
+  // holds the row sums
+  const bool rowsum = g.mode == 2 && g.a_rowsum != nullptr && n0 == 0;
+  f32x16 rsum = acc;
+  Frag ones;
+  if constexpr (KPL == 1) {
+    ones = 1.0f;
+  } else {
+#pragma unroll
+    for (int e = 0; e < KPL; ++e) ones[e] = Prec<P>::cvt(1.0f);
+  }
   // whole K-blocks with vector loads, then (K not a multiple of 2 KPL) one
   // K-block with element-wise, bounds-checked loads
   int k0 = kbeg;
@@ -114,6 +136,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
 #pragma unroll
         for (int e = 0; e < KPL; ++e) a[e] = A[(int64_t)(m0 + c) * g.a_sm + (int64_t)(kk + e) * g.a_sk];
       }
+
       if (!col_ok) {
 #pragma unroll
         for (int e = 0; e < KPL; ++e) b[e] = zero;
@@ -125,6 +148,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
       }
     }
     acc = Prec<P>::mma(a, b, acc);
+    if (rowsum) rsum = Prec<P>::mma(a, ones, rsum);
   }
   if (k0 < kend) {
     const int kk = k0 + h * KPL;
@@ -141,6 +165,11 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
       }
     }
     acc = Prec<P>::mma(a, b, acc);
+    if (rowsum) rsum = Prec<P>::mma(a, ones, rsum);
+  }
+  if (rowsum && c == 0) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) g.a_rowsum[(int64_t)split * g.c_split_stride + m0 + acc_row(0, h, r)] = rsum[r];
   }
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
@@ -160,7 +189,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
 }
 
 // ---------------------------------------------------------------------------
-// LDS-tiled GEMM for the forward layers of wide networks (hidden >= 128,
+// LDS-tiled GEMM for the forward layers of networks at least 64 wide (
 // FP16 / BF16 operands, K a multiple of 32, A and B contiguous along K):
 // 128 x 128 output tiles per 256-thread workgroup, each wave a 64 x 64
 // quarter (2 x 2 MFMA tiles), K in steps of 32 staged through LDS; rows and
@@ -254,14 +283,26 @@ __global__ __launch_bounds__(256) void k_train_head(const float* wout, int H, co
   __syncthreads();
   const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
   float loss = 0.0f;
+  using Elem = typename Prec<P>::Elem;
+  constexpr int V = 16 / sizeof(Elem);  // elements per 16-byte access (H is a multiple of 32)
+  union Row {
+    uint4 u;
+    Elem e[V];
+  };
   if (b < B) {
-    const typename Prec<P>::Elem* h = HL + (size_t)b * H;
+    const uint4* h4 = reinterpret_cast<const uint4*>(HL + (size_t)b * H);
     float y0 = w6[3 * H], y1 = w6[3 * H + 1], y2 = w6[3 * H + 2];
-    for (int i = 0; i < H; ++i) {
-      const float hv = (float)h[i];
-      y0 += w6[i] * hv;
-      y1 += w6[H + i] * hv;
-      y2 += w6[2 * H + i] * hv;
+    for (int i0 = 0; i0 < H; i0 += V) {
+      Row r;
+      r.u = h4[i0 / V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const int i = i0 + v;
+        const float hv = (float)r.e[v];
+        y0 += w6[i] * hv;
+        y1 += w6[H + i] * hv;
+        y2 += w6[2 * H + i] * hv;
+      }
     }
     // the fixed colour matrix, in log space
     const float* m = cm.m;
@@ -282,10 +323,17 @@ __global__ __launch_bounds__(256) void k_train_head(const float* wout, int H, co
     dy_out[3 * (size_t)b] = d0;
     dy_out[3 * (size_t)b + 1] = d1;
     dy_out[3 * (size_t)b + 2] = d2;
-    typename Prec<P>::Elem* dp = dP + (size_t)b * H;
-    for (int i = 0; i < H; ++i) {
-      const float gv = (d0 * w6[i] + d1 * w6[H + i]) + d2 * w6[2 * H + i];
-      dp[i] = Prec<P>::cvt((float)h[i] > 0.0f ? gv : 0.0f);
+    uint4* dp4 = reinterpret_cast<uint4*>(dP + (size_t)b * H);
+    for (int i0 = 0; i0 < H; i0 += V) {
+      Row r, o;
+      r.u = h4[i0 / V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const int i = i0 + v;
+        const float gv = (d0 * w6[i] + d1 * w6[H + i]) + d2 * w6[2 * H + i];
+        o.e[v] = Prec<P>::cvt((float)r.e[v] > 0.0f ? gv : 0.0f);
+      }
+      dp4[i0 / V] = o.u;
     }
   }
   red[threadIdx.x] = loss;
@@ -297,11 +345,12 @@ __global__ __launch_bounds__(256) void k_train_head(const float* wout, int H, co
   if (threadIdx.x == 0) loss_part[blockIdx.x] = red[0];
 }
 
-// output-layer weight/bias gradients of one batch chunk
-// Batch reductions of the gradient run in two stages so that every CU takes
-// part and the summation order stays fixed: runs of kRun rows are summed by
-// separate workgroups into sub[run][j], then the runs of each kChunk-row
-// chunk, in order, into the chunk's partial sums.
+// Output-layer weight/bias gradients of one batch chunk.  Their batch
+// reduction runs in two stages so that every CU takes part and the summation
+// order stays fixed: runs of kRun rows are summed by separate workgroups into
+// sub[run][j], then the runs of each chunk, in order, into the chunk's
+// partial sums.  (Hidden-layer bias gradients are summed per chunk by the
+// weight-gradient GEMM, which reads dP anyway.)
 constexpr int kRun = 64;
 
 // output layer: dW = dy^T HL and db = column sums of dy over one run
@@ -323,36 +372,34 @@ __global__ __launch_bounds__(320) void k_head_grad_runs(const float* dy, const t
   if (j < heads) sub[(size_t)blockIdx.x * heads + j] = s;
 }
 
-// hidden-layer bias gradient: column sums of dP over one run
-template <int P>
-__global__ __launch_bounds__(128) void k_colsum_runs(const typename Prec<P>::Elem* dP, int H, float* sub) {
-  const int i = blockIdx.y * 128 + threadIdx.x;
-  if (i >= H) return;
-  const uint32_t b0 = blockIdx.x * kRun;
-  float s = 0.0f;
-  for (uint32_t b = b0; b < b0 + kRun; ++b) s += (float)dP[(size_t)b * H + i];
-  sub[(size_t)blockIdx.x * H + i] = s;
-}
-
-// the runs of each chunk, in run order, into partial[chunk][off + j]
-__global__ __launch_bounds__(320) void k_chunk_sums(const float* sub, int width, float* partial, int64_t off,
-                                                   int64_t np) {
+// the runs of each chunk (runs of them), in run order, into
+// partial[chunk][off + j]
+__global__ __launch_bounds__(320) void k_chunk_sums(const float* sub, int width, int runs, float* partial,
+                                                   int64_t off, int64_t np) {
   const int j = blockIdx.y * blockDim.x + threadIdx.x;
   if (j >= width) return;
-  constexpr int kRuns = kChunk / kRun;
   float s = 0.0f;
-  for (int r = 0; r < kRuns; ++r) s += sub[((size_t)blockIdx.x * kRuns + r) * width + j];
+  for (int r = 0; r < runs; ++r) s += sub[((size_t)blockIdx.x * runs + r) * width + j];
   partial[(size_t)blockIdx.x * np + off + j] = s;
 }
 
-// gradient = (sum of chunk partials in chunk order) * scale; loss of the step
+// gradient = (sum of the chunk partials) * scale, in a fixed order: wave q
+// of a workgroup sums chunks q, q + 4, ... of 64 parameters, then the four
+// sums are added in wave order; loss of the step
 __global__ __launch_bounds__(256) void k_reduce_grad(const float* partial, int splits, float scale, float* grad,
                                                     const float* loss_part, int nloss, float loss_scale,
                                                     float* loss_out, int64_t np) {
-  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < np; j += (int64_t)gridDim.x * blockDim.x) {
+  __shared__ float part[4][64];
+  const int q = threadIdx.x >> 6, jj = threadIdx.x & 63;
+  for (int64_t j0 = (int64_t)blockIdx.x * 64; j0 < np; j0 += (int64_t)gridDim.x * 64) {
+    const int64_t j = j0 + jj;
     float s = 0.0f;
-    for (int k = 0; k < splits; ++k) s += partial[(size_t)k * np + j];
-    grad[j] = s * scale;
+    if (j < np)
+      for (int k = q; k < splits; k += 4) s += partial[(size_t)k * np + j];
+    part[q][jj] = s;
+    __syncthreads();
+    if (q == 0 && j < np) grad[j] = (((part[0][jj] + part[1][jj]) + part[2][jj]) + part[3][jj]) * scale;
+    __syncthreads();
   }
   if (blockIdx.x == 0 && threadIdx.x == 0 && loss_out) {
     float s = 0.0f;
@@ -360,6 +407,7 @@ __global__ __launch_bounds__(256) void k_reduce_grad(const float* partial, int s
     *loss_out = s * loss_scale;
   }
 }
+
 
 // Stochastic rounding to binary16 (FP16 master weights, Sec. 3.2.1; Gupta
 // et al. 2015): x between the binary16 magnitudes a (toward zero) and a + q
@@ -472,7 +520,7 @@ static hipError_t ensure_scratch(TrainScratch& s, uint32_t B, int prec, uint32_t
                            np * 4,
                            (size_t)B * 3 * 4,
                            (size_t)B * 3 * 4,
-                           ((size_t)B / kChunk + 1) * np * 4,
+                           ((size_t)B / grad_chunk(sh, B) + 1) * np * 4,
                            ((size_t)B / kRun + 1) * (3 * H + 3) * 4,
                            np * 4,
                            ((size_t)B / 256 + 1) * 4,
@@ -494,10 +542,12 @@ static hipError_t ensure_scratch(TrainScratch& s, uint32_t B, int prec, uint32_t
 static int grid_for_params(int64_t np) { return (int)std::min<int64_t>(4096, (np + 255) / 256); }
 
 // forward layers (mode 0, both operands contiguous along K) of networks at
-// least 128 wide with 16-bit operands take the LDS-tiled kernel
+// least 64 wide with 16-bit operands take the LDS-tiled kernel (a 96-wide
+// layer leaves a quarter of its one 128-column tile idle and is still several
+// times faster than one L2-fed wave per 32 x 32 tile)
 template <int P>
 static bool tiled_ok(const GemmDesc& g) {
-  return Prec<P>::KPL == 8 && g.mode == 0 && g.splits == 1 && g.N >= 128 && g.K % kTileK == 0 && g.a_sk == 1 &&
+  return Prec<P>::KPL == 8 && g.mode == 0 && g.splits == 1 && g.N >= 64 && g.K % kTileK == 0 && g.a_sk == 1 &&
          g.b_sk == 1;
 }
 
@@ -564,18 +614,19 @@ static hipError_t step_gradient(TrainScratch& s, const TrainConfig& c, const Tra
                      t.master + shape_w_offset(sh, L), H, acts[L], s.target, c.delta, c.loss_scale, B, c.cm, s.dy,
                      dp[0], s.loss_part);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const int splits = (int)(B / kChunk);
+  const int chunk = grad_chunk(sh, B);
+  const int splits = (int)(B / chunk);
   const int runs = (int)(B / kRun);
   const int heads = kOut * H + kOut;
   hipLaunchKernelGGL(k_head_grad_runs<P>, dim3(runs, (heads + 319) / 320), dim3(320), 0, st, s.dy, acts[L], H,
                      s.sub);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_chunk_sums, dim3(splits, (heads + 319) / 320), dim3(320), 0, st, s.sub, heads, s.partial,
-                     shape_w_offset(sh, L), np);
+  hipLaunchKernelGGL(k_chunk_sums, dim3(splits, (heads + 319) / 320), dim3(320), 0, st, s.sub, heads,
+                     chunk / kRun, s.partial, shape_w_offset(sh, L), np);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   int cur = 0;
   for (int l = L - 1; l >= 0; --l) {
-    // dW_l = dP_l^T act_l, split over batch chunks
+    // dW_l = dP_l^T act_l and db_l, split over batch chunks
     GemmDesc g{};
     g.A = dp[cur];
     g.a_sm = 1;
@@ -586,18 +637,14 @@ static hipError_t step_gradient(TrainScratch& s, const TrainConfig& c, const Tra
     g.M = H;
     g.N = shape_in(sh, l);
     g.K = (int)B;
-    g.k_chunk = kChunk;
+    g.k_chunk = chunk;
     g.splits = splits;
     g.mode = 2;
     g.C = s.partial + shape_w_offset(sh, l);
     g.ldc = shape_in(sh, l);
     g.c_split_stride = np;
+    g.a_rowsum = s.partial + shape_b_offset(sh, l);  // db_l: column sums of dP_l, per chunk
     if ((e = gemm<P, false, false>(g, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_colsum_runs<P>, dim3(runs, (H + 127) / 128), dim3(128), 0, st, dp[cur], H, s.sub);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_chunk_sums, dim3(splits, (H + 127) / 128), dim3(128), 0, st, s.sub, H, s.partial,
-                       shape_b_offset(sh, l), np);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     if (l == 0) break;
     // dP_{l-1} = (dP_l W_l) masked by act_l > 0
     GemmDesc d{};
@@ -621,8 +668,8 @@ static hipError_t step_gradient(TrainScratch& s, const TrainConfig& c, const Tra
     cur ^= 1;
   }
   const float scale = 1.0f / (3.0f * (float)B * c.loss_scale);
-  hipLaunchKernelGGL(k_reduce_grad, dim3(grid_for_params(np)), dim3(256), 0, st, s.partial, splits, scale, grad_out,
-                     s.loss_part, nblk, 1.0f / (3.0f * (float)B), loss_out, np);
+  hipLaunchKernelGGL(k_reduce_grad, dim3((int)std::min<int64_t>(4096, (np + 63) / 64)), dim3(256), 0, st, s.partial,
+                     splits, scale, grad_out, s.loss_part, nblk, 1.0f / (3.0f * (float)B), loss_out, np);
   return hipGetLastError();
 }
 
@@ -661,7 +708,7 @@ static hipError_t run_p(TrainScratch& s, const TrainConfig& c, const TrainTarget
 
 static hipError_t dispatch(TrainScratch& s, const TrainConfig& c, const TrainTargets& t, uint32_t step0,
                            uint32_t steps, bool update, float* grad_out, float* loss_out, hipStream_t st) {
-  if (c.batch % kChunk != 0 || c.shape.hidden % 32 != 0 || c.shape.layers < 1 ||
+  if (c.batch % kChunkMax != 0 || c.shape.hidden % 32 != 0 || c.shape.layers < 1 ||
       (c.shape.skip != 0 && (c.shape.skip < 1 || c.shape.skip >= c.shape.layers)) || c.shape.n_freq < 1 ||
       c.shape.n_freq > 16)
     return hipErrorInvalidValue;
