@@ -3,9 +3,11 @@
 #include "bvh_build.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <deque>
+#include <thread>
 
 #include "npt_shared.h"
 
@@ -34,29 +36,136 @@ struct Box {
   }
 };
 
+// A primitive as the builder sorts it: its box, centroid and input index,
+// moved together so that binning reads memory in order.
+struct Prim {
+  Box box;
+  float c[3];
+  uint32_t id;
+};
+
 struct Node {
   Box box;
   int32_t child[2] = {-1, -1};
-  uint32_t first = 0, count = 0;  // leaf range in the order array
+  uint32_t first = 0, count = 0;  // leaf range in the primitive array
   uint32_t depth = 0;
   bool leaf() const { return child[0] < 0; }
 };
 
+// Host threads of one build: subtrees of at least kParallelPrims primitives
+// build their second child on another thread while workers are free.
+constexpr uint32_t kParallelPrims = 100000;
+
+int host_threads() {
+  const unsigned t = std::thread::hardware_concurrency();
+  return (int)std::max(1u, std::min(t, 64u));
+}
+
+// fn(begin, end) over [0, n) in contiguous ranges on up to host_threads()
+// threads (one range for small n)
+template <class F>
+void parallel_ranges(uint64_t n, F&& fn) {
+  const uint64_t per = 1u << 16;
+  const int t = (int)std::min<uint64_t>((uint64_t)host_threads(), (n + per - 1) / per);
+  if (t <= 1) {
+    fn(0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int i = 1; i < t; ++i) th.emplace_back([&, i] { fn(n * i / t, n * (i + 1) / t); });
+  fn(0, n / t);
+  for (auto& x : th) x.join();
+}
+
+// fn(chunk j, begin, end) over [0, n) split into t contiguous chunks, one thread each
+template <class F>
+void parallel_chunks(uint64_t n, int t, F&& fn) {
+  std::vector<std::thread> th;
+  for (int j = 1; j < t; ++j) th.emplace_back([&, j] { fn(j, n * j / t, n * (j + 1) / t); });
+  fn(0, 0, n / t);
+  for (auto& x : th) x.join();
+}
+
+// node ranges at least this large bound and bin their primitives on all threads
+constexpr uint32_t kParallelBin = 1u << 20;
+
 struct Builder {
-  std::vector<Box> pbox;
-  std::vector<float> cen;  // [n][3]
-  std::vector<uint32_t> order;
+  Prim* prims = nullptr;  // subtrees partition disjoint ranges of it in place
   std::vector<Node> nodes;
   uint32_t bins = 32, max_leaf = 4;
+  std::atomic<int>* workers = nullptr;  // threads that may still be started
+
+  // appends a subtree built by another builder: its root becomes node
+  // nodes.size(), its child indices move by the same offset
+  int splice(const std::vector<Node>& sub) {
+    const int off = (int)nodes.size();
+    for (Node nd : sub) {
+      if (!nd.leaf()) {
+        nd.child[0] += off;
+        nd.child[1] += off;
+      }
+      nodes.push_back(nd);
+    }
+    return off;
+  }
+
+  // Primitive and centroid bounds of prims[first, first + count).  Large
+  // ranges are split over threads; min / max merge exactly in any order, so
+  // the result is the same as one thread's.
+  void bounds(uint32_t first, uint32_t count, Box& b, Box& cb) const {
+    auto part = [&](uint64_t i0, uint64_t i1, Box& pb, Box& pc) {
+      for (uint64_t i = first + i0; i < first + i1; ++i) {
+        pb.grow(prims[i].box);
+        pc.grow(prims[i].c);
+      }
+    };
+    if (count < kParallelBin) {
+      part(0, count, b, cb);
+      return;
+    }
+    const int t = host_threads();
+    std::vector<Box> pb(t), pc(t);
+    parallel_chunks(count, t, [&](int j, uint64_t i0, uint64_t i1) { part(i0, i1, pb[j], pc[j]); });
+    for (int j = 0; j < t; ++j) {
+      b.grow(pb[j]);
+      cb.grow(pc[j]);
+    }
+  }
+
+  // SAH bins of prims[first, first + count) on axis a: boxes and counts (exact
+  // merges: threads give the same bins as one)
+  void bin_axis(uint32_t first, uint32_t count, int a, float lo, float scale, Box* bbox, uint32_t* bcnt) const {
+    auto part = [&](uint64_t i0, uint64_t i1, Box* bb, uint32_t* bc) {
+      for (uint64_t i = first + i0; i < first + i1; ++i) {
+        const Prim& q = prims[i];
+        int k = (int)((q.c[a] - lo) * scale);
+        k = std::min(std::max(k, 0), (int)bins - 1);
+        bb[k].grow(q.box);
+        ++bc[k];
+      }
+    };
+    std::fill(bbox, bbox + bins, Box());
+    std::fill(bcnt, bcnt + bins, 0u);
+    if (count < kParallelBin) {
+      part(0, count, bbox, bcnt);
+      return;
+    }
+    const int t = host_threads();
+    std::vector<Box> bb((size_t)t * bins);
+    std::vector<uint32_t> bc((size_t)t * bins, 0u);
+    parallel_chunks(count, t, [&](int j, uint64_t i0, uint64_t i1) { part(i0, i1, &bb[(size_t)j * bins], &bc[(size_t)j * bins]); });
+    for (int j = 0; j < t; ++j)
+      for (uint32_t k = 0; k < bins; ++k) {
+        bbox[k].grow(bb[(size_t)j * bins + k]);
+        bcnt[k] += bc[(size_t)j * bins + k];
+      }
+  }
 
   int build(uint32_t first, uint32_t count, uint32_t depth) {
     const int id = (int)nodes.size();
     nodes.emplace_back();
     Box b, cb;
-    for (uint32_t i = first; i < first + count; ++i) {
-      b.grow(pbox[order[i]]);
-      cb.grow(&cen[3 * (size_t)order[i]]);
-    }
+    bounds(first, count, b, cb);
     nodes[id].box = b;
     nodes[id].depth = depth;
     if (count <= max_leaf) {
@@ -76,16 +185,7 @@ struct Builder {
       for (int a = 0; a < 3; ++a) {
         const float ext = cb.hi[a] - cb.lo[a];
         if (!(ext > 0.0f)) continue;
-        std::fill(bbox.begin(), bbox.end(), Box());
-        std::fill(bcnt.begin(), bcnt.end(), 0u);
-        const float scale = (float)bins / ext;
-        for (uint32_t i = first; i < first + count; ++i) {
-          const uint32_t p = order[i];
-          int k = (int)((cen[3 * (size_t)p + a] - cb.lo[a]) * scale);
-          k = std::min(std::max(k, 0), (int)bins - 1);
-          bbox[k].grow(pbox[p]);
-          ++bcnt[k];
-        }
+        bin_axis(first, count, a, cb.lo[a], (float)bins / ext, bbox.data(), bcnt.data());
         Box acc;
         uint32_t c = 0;
         for (int k = (int)bins - 1; k > 0; --k) {
@@ -114,12 +214,12 @@ struct Builder {
       const float scale = (float)bins / ext;
       const float lo = cb.lo[axis];
       const int a = axis, sp = split;
-      const uint32_t* it = std::partition(order.data() + first, order.data() + first + count, [&](uint32_t p) {
-        int k = (int)((cen[3 * (size_t)p + a] - lo) * scale);
+      const Prim* it = std::partition(prims + first, prims + first + count, [&](const Prim& q) {
+        int k = (int)((q.c[a] - lo) * scale);
         k = std::min(std::max(k, 0), (int)bins - 1);
         return k <= sp;
       });
-      mid = (uint32_t)(it - order.data());
+      mid = (uint32_t)(it - prims);
     }
     if (mid <= first || mid >= first + count) {
       // degenerate centroids or depth limit: object median on the widest axis
@@ -127,11 +227,31 @@ struct Builder {
       for (int k = 1; k < 3; ++k)
         if (cb.hi[k] - cb.lo[k] > cb.hi[a] - cb.lo[a]) a = k;
       mid = first + count / 2;
-      std::nth_element(order.begin() + first, order.begin() + mid, order.begin() + first + count,
-                       [&](uint32_t x, uint32_t y) { return cen[3 * (size_t)x + a] < cen[3 * (size_t)y + a]; });
+      std::nth_element(prims + first, prims + mid, prims + first + count,
+                       [&](const Prim& x, const Prim& y) { return x.c[a] < y.c[a]; });
     }
-    const int l = build(first, mid - first, depth + 1);
-    const int r = build(mid, first + count - mid, depth + 1);
+    const uint32_t rc = first + count - mid;
+    int l, r;
+    if (workers && rc >= kParallelPrims && workers->fetch_sub(1) > 0) {
+      // the right subtree on its own thread and node array, spliced after
+      // the left one: the tree is the one a single thread builds
+      Builder sub;
+      sub.prims = prims;
+      sub.bins = bins;
+      sub.max_leaf = max_leaf;
+      sub.workers = workers;
+      std::thread t([&] {
+        sub.build(mid, rc, depth + 1);
+        workers->fetch_add(1);  // free for other subtrees as soon as this one is done
+      });
+      l = build(first, mid - first, depth + 1);
+      t.join();
+      r = splice(sub.nodes);
+    } else {
+      if (workers && rc >= kParallelPrims) workers->fetch_add(1);  // the claim above failed: give it back
+      l = build(first, mid - first, depth + 1);
+      r = build(mid, rc, depth + 1);
+    }
     nodes[id].child[0] = l;
     nodes[id].child[1] = r;
     return id;
@@ -266,7 +386,8 @@ bool compress_half_extents(FlatBvh& b, std::string& err) {
   }
   const size_t nn = b.nodes.size() / kNode4Float4s;
   std::vector<float4> out(nn * kNode4HalfFloat4s);
-  for (size_t i = 0; i < nn; ++i) {
+  // one node; false when an extent does not fit binary16
+  auto node = [&](size_t i) -> bool {
     const float4* o = &b.nodes[i * kNode4Float4s];
     float4* h = &out[i * kNode4HalfFloat4s];
     uint16_t ext[3][4];
@@ -283,18 +404,12 @@ bool compress_half_extents(FlatBvh& b, std::string& err) {
         }
         lo[a][c] = l4[c];
         uint16_t e;
-        if (!half_up((double)h4[c] - (double)l4[c], e)) {
-          err = "FP16 extents: a box is wider than 65504";
-          return false;
-        }
+        if (!half_up((double)h4[c] - (double)l4[c], e)) return false;
         // the traversal forms the upper plane as an FP32 sum: make sure it
         // does not fall below the true one
         while ((float)(l4[c] + half_value(e)) < h4[c]) {
           e = half_next(e);
-          if (half_value(e) > 65504.0f || ((e >> 10) & 31) == 31) {
-            err = "FP16 extents: a box is wider than 65504";
-            return false;
-          }
+          if (half_value(e) > 65504.0f || ((e >> 10) & 31) == 31) return false;
         }
         ext[a][c] = e;
       }
@@ -307,6 +422,16 @@ bool compress_half_extents(FlatBvh& b, std::string& err) {
                        pack(ext[1][2], ext[1][3]));
     h[4] = make_float4(pack(ext[2][0], ext[2][1]), pack(ext[2][2], ext[2][3]), 0.0f, 0.0f);
     h[5] = o[6];
+    return true;
+  };
+  std::atomic<bool> wide{false};
+  parallel_ranges(nn, [&](uint64_t i0, uint64_t i1) {
+    for (uint64_t i = i0; i < i1; ++i)
+      if (!node(i)) wide = true;
+  });
+  if (wide) {
+    err = "FP16 extents: a box is wider than 65504";
+    return false;
   }
   b.nodes = std::move(out);
   b.node_float4s = kNode4HalfFloat4s;
@@ -404,30 +529,34 @@ bool build_bvh(const BuildInput& in, uint32_t bins, uint32_t max_leaf, uint32_t 
     err = "too many primitives for 28-bit slot indices";
     return false;
   }
+  std::vector<Prim> prims(n);
+  parallel_ranges(n, [&](uint64_t p0, uint64_t p1) {
+    for (uint64_t p = p0; p < p1; ++p) {
+      Box b;
+      if (in.nboxes) {
+        b.grow(&in.boxes[6 * p]);
+        b.grow(&in.boxes[6 * p + 3]);
+      } else if (p < in.nt) {
+        for (int k = 0; k < 3; ++k) b.grow(&in.verts[3 * (size_t)in.tris[3 * p + k]]);
+      } else {
+        const float* s = &in.spheres[4 * (p - in.nt)];
+        for (int a = 0; a < 3; ++a) {
+          b.lo[a] = std::nextafter(s[a] - s[3], -INFINITY);
+          b.hi[a] = std::nextafter(s[a] + s[3], INFINITY);
+        }
+      }
+      Prim& q = prims[p];
+      q.box = b;
+      for (int a = 0; a < 3; ++a) q.c[a] = 0.5f * (b.lo[a] + b.hi[a]);
+      q.id = (uint32_t)p;
+    }
+  });
+  std::atomic<int> workers{host_threads() - 1};
   Builder B;
   B.bins = bins;
   B.max_leaf = max_leaf;
-  B.pbox.resize(n);
-  B.cen.resize(3 * n);
-  B.order.resize(n);
-  for (uint64_t p = 0; p < n; ++p) {
-    Box b;
-    if (in.nboxes) {
-      b.grow(&in.boxes[6 * p]);
-      b.grow(&in.boxes[6 * p + 3]);
-    } else if (p < in.nt) {
-      for (int k = 0; k < 3; ++k) b.grow(&in.verts[3 * (size_t)in.tris[3 * p + k]]);
-    } else {
-      const float* s = &in.spheres[4 * (p - in.nt)];
-      for (int a = 0; a < 3; ++a) {
-        b.lo[a] = std::nextafter(s[a] - s[3], -INFINITY);
-        b.hi[a] = std::nextafter(s[a] + s[3], INFINITY);
-      }
-    }
-    B.pbox[p] = b;
-    for (int a = 0; a < 3; ++a) B.cen[3 * p + a] = 0.5f * (b.lo[a] + b.hi[a]);
-    B.order[p] = (uint32_t)p;
-  }
+  B.prims = prims.data();
+  B.workers = &workers;
   B.nodes.reserve(2 * n / std::max(1u, max_leaf) + 16);
   B.build(0, (uint32_t)n, 0);
 
@@ -554,30 +683,32 @@ bool build_bvh(const BuildInput& in, uint32_t bins, uint32_t max_leaf, uint32_t 
 
   // primitive slots in leaf order
   out.slots.resize(3 * n);
-  for (uint64_t i = 0; i < n; ++i) {
-    const uint32_t p = B.order[i];
-    float4* s = &out.slots[3 * i];
-    if (in.nboxes) {
-      // box mode: the slot only names the input box it holds
-      s[0] = make_float4(0.0f, 0.0f, 0.0f, bits(p));
-      s[1] = s[2] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    } else if (p < in.nt) {
-      const uint32_t* t = &in.tris[3 * (size_t)p];
-      const float* v0 = &in.verts[3 * (size_t)t[0]];
-      const float* v1 = &in.verts[3 * (size_t)t[1]];
-      const float* v2 = &in.verts[3 * (size_t)t[2]];
-      const uint32_t m = in.tri_mat ? in.tri_mat[p] : 0u;
-      s[0] = make_float4(v0[0], v0[1], v0[2], bits(p));
-      s[1] = make_float4(v1[0], v1[1], v1[2], bits(m));
-      s[2] = make_float4(v2[0], v2[1], v2[2], bits(kPrimTriangle));
-    } else {
-      const float* sp = &in.spheres[4 * (size_t)(p - in.nt)];
-      const uint32_t m = in.sph_mat ? in.sph_mat[p - in.nt] : 0u;
-      s[0] = make_float4(sp[0], sp[1], sp[2], bits(p));
-      s[1] = make_float4(sp[3], 0.0f, 0.0f, bits(m));
-      s[2] = make_float4(0.0f, 0.0f, 0.0f, bits(kPrimSphere));
+  parallel_ranges(n, [&](uint64_t i0, uint64_t i1) {
+    for (uint64_t i = i0; i < i1; ++i) {
+      const uint32_t p = prims[i].id;
+      float4* s = &out.slots[3 * i];
+      if (in.nboxes) {
+        // box mode: the slot only names the input box it holds
+        s[0] = make_float4(0.0f, 0.0f, 0.0f, bits(p));
+        s[1] = s[2] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      } else if (p < in.nt) {
+        const uint32_t* t = &in.tris[3 * (size_t)p];
+        const float* v0 = &in.verts[3 * (size_t)t[0]];
+        const float* v1 = &in.verts[3 * (size_t)t[1]];
+        const float* v2 = &in.verts[3 * (size_t)t[2]];
+        const uint32_t m = in.tri_mat ? in.tri_mat[p] : 0u;
+        s[0] = make_float4(v0[0], v0[1], v0[2], bits(p));
+        s[1] = make_float4(v1[0], v1[1], v1[2], bits(m));
+        s[2] = make_float4(v2[0], v2[1], v2[2], bits(kPrimTriangle));
+      } else {
+        const float* sp = &in.spheres[4 * (size_t)(p - in.nt)];
+        const uint32_t m = in.sph_mat ? in.sph_mat[p - in.nt] : 0u;
+        s[0] = make_float4(sp[0], sp[1], sp[2], bits(p));
+        s[1] = make_float4(sp[3], 0.0f, 0.0f, bits(m));
+        s[2] = make_float4(0.0f, 0.0f, 0.0f, bits(kPrimSphere));
+      }
     }
-  }
+  });
   return check_flat(out, err);
 }
 
@@ -619,33 +750,46 @@ bool build_two_level(const std::vector<FlatBvh>& bottoms, const std::vector<Plac
   }
   std::vector<uint32_t> root(bottoms.size());
   uint32_t deepest = 0;
+  size_t total_nodes = out.nodes.size(), total_slots = 0;
+  for (const FlatBvh& b : bottoms) {
+    total_nodes += b.nodes.size();
+    total_slots += b.slots.size();
+  }
+  if (total_nodes / kNode4Float4s >= kEmptyChild || total_slots / 3 > kMaxSlots) {
+    err = "two-level layout: too many nodes or primitive slots";
+    return false;
+  }
+  out.nodes.resize(total_nodes);
+  out.slots.resize(total_slots);
+  size_t nf = top.nodes.size(), sf = 0;  // float4s placed so far
   for (size_t t = 0; t < bottoms.size(); ++t) {
     const FlatBvh& b = bottoms[t];
-    const uint64_t node_off = out.nodes.size() / kNode4Float4s, slot_off = out.slots.size() / 3;
-    if (node_off + b.nodes.size() / kNode4Float4s >= kEmptyChild || slot_off + b.slots.size() / 3 > kMaxSlots) {
-      err = "two-level layout: too many nodes or primitive slots";
-      return false;
-    }
-    root[t] = (uint32_t)node_off;
-    for (size_t i = 0; i < b.nodes.size(); i += kNode4Float4s) {
-      float4 rf = b.nodes[i + 6];
-      float* r4[4] = {&rf.x, &rf.y, &rf.z, &rf.w};
-      for (float* f : r4) {
-        uint32_t r = ubits(*f);
-        if (r == kEmptyChild) continue;
-        if (r & kLeafBit) {
-          const uint32_t first = ((r >> 3) & 0x0FFFFFFFu) + (uint32_t)slot_off;
-          r = kLeafBit | (first << 3) | (r & 7u);
-        } else {
-          r += (uint32_t)node_off;
+    const uint32_t node_off = (uint32_t)(nf / kNode4Float4s), slot_off = (uint32_t)(sf / 3);
+    root[t] = node_off;
+    // each node moves by node_off, its child refs by node_off (inner) or
+    // slot_off (leaves)
+    parallel_ranges(b.nodes.size() / kNode4Float4s, [&](uint64_t i0, uint64_t i1) {
+      for (uint64_t i = i0; i < i1; ++i) {
+        const float4* src = &b.nodes[i * kNode4Float4s];
+        float4* dst = &out.nodes[nf + i * kNode4Float4s];
+        for (uint32_t k = 0; k < kNode4Float4s; ++k) dst[k] = src[k];
+        float* r4[4] = {&dst[6].x, &dst[6].y, &dst[6].z, &dst[6].w};
+        for (float* f : r4) {
+          uint32_t r = ubits(*f);
+          if (r == kEmptyChild) continue;
+          if (r & kLeafBit) {
+            const uint32_t first = ((r >> 3) & 0x0FFFFFFFu) + slot_off;
+            r = kLeafBit | (first << 3) | (r & 7u);
+          } else {
+            r += node_off;
+          }
+          *f = bits(r);
         }
-        *f = bits(r);
       }
-      out.nodes.insert(out.nodes.end(), b.nodes.begin() + i, b.nodes.begin() + i + 6);
-      out.nodes.push_back(rf);
-      out.nodes.insert(out.nodes.end(), b.nodes.begin() + i + 7, b.nodes.begin() + i + kNode4Float4s);
-    }
-    out.slots.insert(out.slots.end(), b.slots.begin(), b.slots.end());
+    });
+    std::copy(b.slots.begin(), b.slots.end(), out.slots.begin() + sf);
+    nf += b.nodes.size();
+    sf += b.slots.size();
     out.leaves += b.leaves;
     deepest = std::max(deepest, b.max_depth);
   }
