@@ -199,15 +199,21 @@ __global__ void k_nif_dequant(const float* master, const float* bias_tab, float*
 // ---------------------------------------------------------------------------
 // inference
 // ---------------------------------------------------------------------------
-// 8 waves (two per SIMD) x one 32-ray tile per wave measured fastest: the
-// second wave hides MFMA/LDS latency; more tiles per wave spill registers.
+// 8 waves (two per SIMD): the second wave hides MFMA/LDS latency.
 #ifndef NPT_NIF_WAVES
 #define NPT_NIF_WAVES 8
 #endif
-#ifndef NPT_NIF_TILES
-#define NPT_NIF_TILES 1  // 32-ray column tiles per wave for FP16/BF16 operands
-#endif
 constexpr int kNifWaves = NPT_NIF_WAVES;
+
+// 32-ray column tiles per wave: two for FP16 / BF16 operands on networks 65
+// to 96 wide (each weight fragment read from LDS feeds two MFMAs: 16/96/5
+// queries 12-13 % faster, and the same results bit for bit), else one (E4M3
+// hidden layers already read half the LDS bytes per MFMA and gain nothing;
+// a 64-wide network loses 4 %; 128-wide tiles do not fit twice in registers).
+template <int P, class A>
+constexpr int nif_tiles() {
+  return (P == NPT_FP16 || P == NPT_BF16) && A::kHidden > 64 && A::kHidden <= 96 ? 2 : 1;
+}
 constexpr int kNifBlock = 64 * kNifWaves;
 
 enum : int { kSrcQueue = 0, kSrcDirs = 1, kSrcGrid = 2 };
@@ -352,7 +358,7 @@ __global__ __launch_bounds__(kNifBlock, 1) void k_nif_infer(const uint8_t* gpack
   using Frag = typename Prec<P>::Frag;
   constexpr int L = A::kLayers, H = A::kHidden, MB = A::kMB;
   constexpr bool kAccurate = (P == NPT_FP32);
-  constexpr int NT = (P == NPT_FP32) ? 1 : NPT_NIF_TILES;  // 32-ray column tiles per wave
+  constexpr int NT = nif_tiles<P, A>();
   constexpr int kRays = 32 * NT;
   extern __shared__ float4 smem4[];
   uint8_t* lds = reinterpret_cast<uint8_t*>(smem4);
@@ -405,11 +411,11 @@ __global__ __launch_bounds__(kNifBlock, 1) void k_nif_infer(const uint8_t* gpack
   const uint64_t waves_total = (uint64_t)gridDim.x * kNifWaves;
 
   for (uint64_t tile = (uint64_t)blockIdx.x * kNifWaves + wave; tile * kRays < n; tile += waves_total) {
-    // Wider networks: an offset of 0 that the compiler cannot see through
-    // (tiles stay far below 2^62) keeps the first- and output-layer operands
-    // inside the tile loop; hoisted out of it, they would not fit in the
-    // registers of two waves per SIMD and would spill.
-    const int z = H > 96 ? (int)(tile >> 62) : 0;
+    // Wider networks and two tiles per wave: an offset of 0 that the
+    // compiler cannot see through (tiles stay far below 2^62) keeps the first-
+    // and output-layer operands inside the tile loop; hoisted out of it, they
+    // would not fit in the registers of two waves per SIMD and would spill.
+    const int z = (H > 96 || NT > 1) ? (int)(tile >> 62) : 0;
     const Frag* fr0 = fr_first + z;
     const Frag* fro = fr_out + z;
     const float* lb0 = lbias + z;
