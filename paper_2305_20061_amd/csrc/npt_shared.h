@@ -101,8 +101,7 @@ struct EnvQueue {
 constexpr int kCntRays = 0;
 constexpr int kCntEnv = 80;
 constexpr int kCntWork = 160;
-constexpr int kCntEnvWork = 240;
-constexpr int kCntWords = 320;
+constexpr int kCntWords = 240;
 
 // Fixed output colour matrix of the HDR-NIF (Sec. 3.2; the spaces of
 // Sec. 4.3): log-space RGB = m (row-major 3x3) * network output.
