@@ -561,10 +561,17 @@ def main():
 
         def nif_stats(s, name):
             tf = s["env_queries"] * NIF_FLOP_PER_QUERY / (s["ms_env"] * 1e-3) / 1e12
+            # each depth's real batch (the escaped rays of that depth, over the passes)
+            per_depth = []
+            for k, (q, ms) in enumerate(zip(s["escaped"], s["ms_env_depth"])):
+                if q > 0 and ms > 0:
+                    tfk = q * NIF_FLOP_PER_QUERY / (ms * 1e-3) / 1e12
+                    per_depth.append({"depth": k + 1, "queries": q, "ms": ms, "queries_per_s": q / (ms * 1e-3),
+                                      "mfma_util": tfk / MFMA_PEAK_TFLOPS[name]})
             return {"precision": name, "queries_per_render": s["env_queries"],
                     "queries_per_s": s["env_queries"] / (s["ms_env"] * 1e-3), "ms_per_render": s["ms_env"],
                     "launches": s["env_launches"], "tflops": tf, "mfma_util": tf / MFMA_PEAK_TFLOPS[name],
-                    "flop_per_query": NIF_FLOP_PER_QUERY}
+                    "flop_per_query": NIF_FLOP_PER_QUERY, "per_depth": per_depth}
 
         extra["kernels"] = {"extend_ms_per_render": st["ms_trace"], "extend_launches": st["trace_launches"],
                             "extend_ms_per_launch": trace_launch_ms, "shade_ms_per_render": st["ms_shade"],

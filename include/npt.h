@@ -191,6 +191,9 @@ typedef struct {
     /* kernel_timing: the shade kernel (emission, BSDF sampling, roulette) */
     float ms_shade;
     uint32_t shade_launches;
+    /* kernel_timing: environment (map or NIF) time of the queries of depth k
+     * (index k-1), summed over passes; their count is escaped[k-1] */
+    float ms_env_depth[NPT_MAX_DEPTH];
 } npt_stats;
 
 /* ---- context ------------------------------------------------------------- */

@@ -111,6 +111,7 @@ struct npt_ctx {
   npt_stats stats{};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::vector<hipEvent_t> event_pool, trace_events, shade_events, env_events;
+  std::vector<uint32_t> env_depths;  // depth of each env_events pair
   bool timing_pending = false;
 
   ~npt_ctx() {
@@ -840,6 +841,7 @@ extern "C" int npt_render(npt_ctx* c, uint32_t W, uint32_t H, uint32_t spp, uint
   c->trace_events.clear();
   c->shade_events.clear();
   c->env_events.clear();
+  c->env_depths.clear();
   auto event_pair = [&](std::vector<hipEvent_t>& v) -> hipError_t {
     // events are pooled per context and reused across renders
     const size_t need = c->trace_events.size() + c->shade_events.size() + c->env_events.size() + 2;
@@ -895,6 +897,7 @@ extern "C" int npt_render(npt_ctx* c, uint32_t W, uint32_t H, uint32_t spp, uint
       if (c->env_mode != NPT_ENV_NONE) {  // NONE: escaped paths carry no radiance
         if (timing) {
           HIP_TRY(c, event_pair(c->env_events));
+          c->env_depths.push_back(k);
           HIP_TRY(c, hipEventRecord(c->env_events[c->env_events.size() - 2], s));
         }
         if (c->env_mode == NPT_ENV_MAP) {
@@ -910,8 +913,8 @@ extern "C" int npt_render(npt_ctx* c, uint32_t W, uint32_t H, uint32_t spp, uint
           HIP_TRY(c, nif_layered(c->layered, c->nif_prec, c->nif_shape, c->d_frags.p, c->d_master.as<float>(),
                                  c->nif_cm, io, s));
         } else {
-          HIP_TRY(c, launch_nif_queue(c->nif_arch, c->nif_prec, c->d_frags.p, c->d_bias.as<float>(), c->nif_cm, eq, L, cnt, k, n,
-                                      c->num_cus, s));
+          HIP_TRY(c, launch_nif_queue(c->nif_arch, c->nif_prec, c->d_frags.p, c->d_bias.as<float>(), c->nif_cm, eq, L,
+                                      cnt, k, n, c->num_cus, s));
         }
         if (timing) HIP_TRY(c, hipEventRecord(c->env_events.back(), s));
       }
@@ -987,9 +990,12 @@ extern "C" int npt_get_stats(npt_ctx* c, npt_stats* out) {
     c->stats.ms_shade = sum;
     c->stats.shade_launches = (uint32_t)(c->shade_events.size() / 2);
     sum = 0.0f;
+    for (int k = 0; k < NPT_MAX_DEPTH; ++k) c->stats.ms_env_depth[k] = 0.0f;
     for (size_t i = 0; i + 1 < c->env_events.size(); i += 2) {
       HIP_TRY(c, hipEventElapsedTime(&ms, c->env_events[i], c->env_events[i + 1]));
       sum += ms;
+      const uint32_t k = c->env_depths[i / 2];
+      if (k >= 1 && k <= NPT_MAX_DEPTH) c->stats.ms_env_depth[k - 1] += ms;
     }
     c->stats.ms_env = sum;
     c->stats.env_launches = (uint32_t)(c->env_events.size() / 2);

@@ -84,7 +84,7 @@ class npt_stats(C.Structure):
                 ("ms_total", C.c_float), ("ms_trace", C.c_float), ("ms_env", C.c_float),
                 ("trace_launches", C.c_uint32), ("env_launches", C.c_uint32),
                 ("node_visits", C.c_uint64 * MAX_DEPTH), ("prim_tests", C.c_uint64 * MAX_DEPTH),
-                ("ms_shade", C.c_float), ("shade_launches", C.c_uint32)]
+                ("ms_shade", C.c_float), ("shade_launches", C.c_uint32), ("ms_env_depth", C.c_float * MAX_DEPTH)]
 
 
 _P = C.c_void_p
@@ -364,7 +364,7 @@ def npt_get_stats(ctx):
             "passes": s.passes, "samples_per_pass": s.samples_per_pass, "ms_total": s.ms_total,
             "ms_trace": s.ms_trace, "ms_env": s.ms_env, "trace_launches": s.trace_launches,
             "env_launches": s.env_launches, "node_visits": list(s.node_visits), "prim_tests": list(s.prim_tests),
-            "ms_shade": s.ms_shade, "shade_launches": s.shade_launches}
+            "ms_shade": s.ms_shade, "shade_launches": s.shade_launches, "ms_env_depth": list(s.ms_env_depth)}
 
 
 # ------------------------------------------------------------ conveniences
