@@ -198,13 +198,15 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
 // ---------------------------------------------------------------------------
 constexpr int kTileM = 128, kTileN = 128, kTileK = 32, kTileLd = kTileK + 8;  // LDS row: 40 elements
 
-template <int P>
+template <int P, bool BT>
 __global__ __launch_bounds__(256) void k_gemm_tiled(GemmDesc g) {
   using Elem = typename Prec<P>::Elem;
   using Frag = typename Prec<P>::Frag;
   static_assert(Prec<P>::KPL == 8, "16-bit operands");
-  __shared__ Elem As[kTileM * kTileLd];
-  __shared__ Elem Bs[kTileN * kTileLd];
+  // the operand tiles; after the K loop, half of the output tile at a time
+  __shared__ __align__(16) Elem smem[(kTileM + kTileN) * kTileLd];
+  Elem* As = smem;
+  Elem* Bs = smem + kTileM * kTileLd;
   const int nt = (g.N + kTileN - 1) / kTileN;
   const int m0 = (blockIdx.x / nt) * kTileM, n0 = (blockIdx.x % nt) * kTileN;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -217,6 +219,9 @@ __global__ __launch_bounds__(256) void k_gemm_tiled(GemmDesc g) {
   const bool a_ok = m0 + lr < g.M, b_ok = n0 + lr < g.N;
   const Elem* a_src = A + (int64_t)(m0 + lr) * g.a_sm + lk;
   const Elem* b_src = B + (int64_t)(n0 + lr) * g.b_sn + lk;
+  // BT (B contiguous along n): thread t stages 8 consecutive n at one k for
+  // each of its two chunks c = t, t + 256 (k = c % 32, n = 8 (c / 32) ..)
+  const int bt_k = t % 32, bt_n0 = (t / 32) * 8, bt_n1 = bt_n0 + 64;
   Frag zf;
 #pragma unroll
   for (int e = 0; e < 8; ++e) zf[e] = Prec<P>::cvt(0.0f);
@@ -230,13 +235,28 @@ __global__ __launch_bounds__(256) void k_gemm_tiled(GemmDesc g) {
   for (int k0 = 0; k0 < g.K; k0 += kTileK) {
     const Frag a0 = a_ok ? *reinterpret_cast<const Frag*>(a_src + k0) : zf;
     const Frag a1 = a_ok ? *reinterpret_cast<const Frag*>(a_src + k0 + 8) : zf;
-    const Frag b0 = b_ok ? *reinterpret_cast<const Frag*>(b_src + k0) : zf;
-    const Frag b1 = b_ok ? *reinterpret_cast<const Frag*>(b_src + k0 + 8) : zf;
+    Frag b0, b1;
+    if constexpr (BT) {
+      const Elem* src = B + (int64_t)(k0 + bt_k) * g.b_sk + n0;
+      b0 = n0 + bt_n0 < g.N ? *reinterpret_cast<const Frag*>(src + bt_n0) : zf;
+      b1 = n0 + bt_n1 < g.N ? *reinterpret_cast<const Frag*>(src + bt_n1) : zf;
+    } else {
+      b0 = b_ok ? *reinterpret_cast<const Frag*>(b_src + k0) : zf;
+      b1 = b_ok ? *reinterpret_cast<const Frag*>(b_src + k0 + 8) : zf;
+    }
     __syncthreads();  // the previous step's reads are done
     *reinterpret_cast<Frag*>(&As[lr * kTileLd + lk]) = a0;
     *reinterpret_cast<Frag*>(&As[lr * kTileLd + lk + 8]) = a1;
-    *reinterpret_cast<Frag*>(&Bs[lr * kTileLd + lk]) = b0;
-    *reinterpret_cast<Frag*>(&Bs[lr * kTileLd + lk + 8]) = b1;
+    if constexpr (BT) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        Bs[(bt_n0 + e) * kTileLd + bt_k] = b0[e];
+        Bs[(bt_n1 + e) * kTileLd + bt_k] = b1[e];
+      }
+    } else {
+      *reinterpret_cast<Frag*>(&Bs[lr * kTileLd + lk]) = b0;
+      *reinterpret_cast<Frag*>(&Bs[lr * kTileLd + lk + 8]) = b1;
+    }
     __syncthreads();
 #pragma unroll
     for (int kb = 0; kb < 2; ++kb) {
@@ -253,18 +273,69 @@ __global__ __launch_bounds__(256) void k_gemm_tiled(GemmDesc g) {
         for (int j = 0; j < 2; ++j) acc[i][j] = Prec<P>::mma(af[i], bf[j], acc[i][j]);
     }
   }
+  Elem* C = static_cast<Elem*>(g.C);
+  const Elem* mask = static_cast<const Elem*>(g.mask);
+  if (g.ldc % 8 == 0 && g.N % 8 == 0 && reinterpret_cast<uintptr_t>(C) % 16 == 0 &&
+      (g.mode == 0 || (g.mask_ld % 8 == 0 && reinterpret_cast<uintptr_t>(mask) % 16 == 0))) {
+    // relu(acc + bias) (mode 0) or acc (mode 1) staged through LDS, 64 rows
+    // at a time, then stored as 16-byte runs of 8 columns (mode 1 under the
+    // ReLU mask, read as 16-byte runs too)
+    constexpr int kCLd = kTileN + 8;
+    static_assert(64 * kCLd <= (kTileM + kTileN) * kTileLd, "half tile fits the operand buffers");
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      __syncthreads();  // the operand tiles, or the previous half, are no longer read
+      if ((wm >> 6) == half) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int nl = wn + j * 32 + c;
+          const float bias = g.mode == 0 && n0 + nl < g.N ? g.bias[n0 + nl] : 0.0f;
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const float v = acc[i][j][r] + bias;
+              smem[(i * 32 + acc_row(0, h, r)) * kCLd + nl] = Prec<P>::cvt(g.mode == 0 ? fmaxf(v, 0.0f) : v);
+            }
+        }
+      }
+      __syncthreads();
+      for (int q = t; q < 64 * (kTileN / 8); q += 256) {
+        const int row = q / (kTileN / 8), col = (q % (kTileN / 8)) * 8;
+        const int m = m0 + half * 64 + row, n = n0 + col;
+        if (m < g.M && n < g.N) {
+          Frag v = *reinterpret_cast<const Frag*>(&smem[row * kCLd + col]);
+          if (g.mode == 1) {
+            const Frag mk = *reinterpret_cast<const Frag*>(&mask[(int64_t)m * g.mask_ld + n]);
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+              if (!((float)mk[e] > 0.0f)) v[e] = Prec<P>::cvt(0.0f);
+          }
+          *reinterpret_cast<Frag*>(&C[(int64_t)m * g.ldc + n]) = v;
+        }
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int n = n0 + wn + j * 32 + c;
       if (n >= g.N) continue;
-      const float bias = g.bias[n];
+      const float bias = g.mode == 0 ? g.bias[n] : 0.0f;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int m = m0 + wm + i * 32 + acc_row(0, h, r);
-        if (m < g.M)
-          static_cast<Elem*>(g.C)[(int64_t)m * g.ldc + n] = Prec<P>::cvt(fmaxf(acc[i][j][r] + bias, 0.0f));
+        if (m >= g.M) continue;
+        float v;
+        if (g.mode == 0) {
+          v = fmaxf(acc[i][j][r] + bias, 0.0f);
+        } else {
+          const float mk = (float)mask[(int64_t)m * g.mask_ld + n];
+          v = mk > 0.0f ? acc[i][j][r] : 0.0f;
+        }
+        C[(int64_t)m * g.ldc + n] = Prec<P>::cvt(v);
       }
     }
 }
@@ -545,18 +616,22 @@ static int grid_for_params(int64_t np) { return (int)std::min<int64_t>(4096, (np
 // least 64 wide with 16-bit operands take the LDS-tiled kernel (a 96-wide
 // layer leaves a quarter of its one 128-column tile idle and is still several
 // times faster than one L2-fed wave per 32 x 32 tile)
-template <int P>
+// BT: B contiguous along n (rows of 16-byte aligned runs of n)
+template <int P, bool BT>
 static bool tiled_ok(const GemmDesc& g) {
-  return Prec<P>::KPL == 8 && g.mode == 0 && g.splits == 1 && g.N >= 64 && g.K % kTileK == 0 && g.a_sk == 1 &&
-         g.b_sk == 1;
+  auto aligned = [](const void* p) { return reinterpret_cast<uintptr_t>(p) % 16 == 0; };
+  const bool common = Prec<P>::KPL == 8 && (g.mode == 0 || g.mode == 1) && g.splits == 1 && g.N >= 64 &&
+                      g.K % kTileK == 0 && g.a_sk == 1 && g.a_sm % 8 == 0 && aligned(g.A) && aligned(g.B);
+  if (BT) return common && g.b_sn == 1 && g.b_sk % 8 == 0 && g.N % 8 == 0;
+  return common && g.b_sk == 1 && g.b_sn % 8 == 0;
 }
 
 template <int P, bool AK, bool BK>
 static hipError_t gemm(const GemmDesc& g, hipStream_t st) {
-  if constexpr (AK && BK && Prec<P>::KPL == 8) {
-    if (tiled_ok<P>(g)) {
+  if constexpr (AK && Prec<P>::KPL == 8) {
+    if (tiled_ok<P, !BK>(g)) {
       const int tiles = ((g.M + kTileM - 1) / kTileM) * ((g.N + kTileN - 1) / kTileN);
-      hipLaunchKernelGGL(k_gemm_tiled<P>, dim3(tiles), dim3(256), 0, st, g);
+      hipLaunchKernelGGL((k_gemm_tiled<P, !BK>), dim3(tiles), dim3(256), 0, st, g);
       return hipGetLastError();
     }
   }
