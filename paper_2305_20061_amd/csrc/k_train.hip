@@ -198,7 +198,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
 // ---------------------------------------------------------------------------
 constexpr int kTileM = 128, kTileN = 128, kTileK = 32, kTileLd = kTileK + 8;  // LDS row: 40 elements
 
-template <int P, bool BT>
+template <int P, bool AT, bool BT>
 __global__ __launch_bounds__(256) void k_gemm_tiled(GemmDesc g) {
   using Elem = typename Prec<P>::Elem;
   using Frag = typename Prec<P>::Frag;
@@ -207,8 +207,10 @@ __global__ __launch_bounds__(256) void k_gemm_tiled(GemmDesc g) {
   __shared__ __align__(16) Elem smem[(kTileM + kTileN) * kTileLd];
   Elem* As = smem;
   Elem* Bs = smem + kTileM * kTileLd;
-  const int nt = (g.N + kTileN - 1) / kTileN;
-  const int m0 = (blockIdx.x / nt) * kTileM, n0 = (blockIdx.x % nt) * kTileN;
+  const int nt = (g.N + kTileN - 1) / kTileN, tiles = ((g.M + kTileM - 1) / kTileM) * nt;
+  const int split = blockIdx.x / tiles, tile = blockIdx.x % tiles;  // split-K chunk (mode 2), output tile
+  const int m0 = (tile / nt) * kTileM, n0 = (tile % nt) * kTileN;
+  const int kbeg = split * g.k_chunk, kend = min(g.K, kbeg + g.k_chunk);
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
   const int h = lane / 32, c = lane % 32;
@@ -219,22 +221,39 @@ __global__ __launch_bounds__(256) void k_gemm_tiled(GemmDesc g) {
   const bool a_ok = m0 + lr < g.M, b_ok = n0 + lr < g.N;
   const Elem* a_src = A + (int64_t)(m0 + lr) * g.a_sm + lk;
   const Elem* b_src = B + (int64_t)(n0 + lr) * g.b_sn + lk;
-  // BT (B contiguous along n): thread t stages 8 consecutive n at one k for
-  // each of its two chunks c = t, t + 256 (k = c % 32, n = 8 (c / 32) ..)
+  // AT / BT (A contiguous along m, B along n): thread t stages 8 consecutive
+  // m (n) at one k for each of its two chunks c = t, t + 256 (k = c % 32,
+  // m = 8 (c / 32) ..)
   const int bt_k = t % 32, bt_n0 = (t / 32) * 8, bt_n1 = bt_n0 + 64;
+  // mode 2 with row sums: the waves of the first column tile also sum A's
+  // rows over the chunk, as an MFMA against a B of ones
+  const bool rowsum = g.mode == 2 && g.a_rowsum != nullptr && n0 == 0 && wn == 0;
+  Frag ones;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) ones[e] = Prec<P>::cvt(1.0f);
   Frag zf;
 #pragma unroll
   for (int e = 0; e < 8; ++e) zf[e] = Prec<P>::cvt(0.0f);
-  f32x16 acc[2][2];
+  f32x16 acc[2][2], rs[2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 2; ++i) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) rs[i][r] = 0.0f;
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
-  for (int k0 = 0; k0 < g.K; k0 += kTileK) {
-    const Frag a0 = a_ok ? *reinterpret_cast<const Frag*>(a_src + k0) : zf;
-    const Frag a1 = a_ok ? *reinterpret_cast<const Frag*>(a_src + k0 + 8) : zf;
+  }
+  for (int k0 = kbeg; k0 < kend; k0 += kTileK) {
+    Frag a0, a1;
+    if constexpr (AT) {
+      const Elem* src = A + (int64_t)(k0 + bt_k) * g.a_sk + m0;
+      a0 = m0 + bt_n0 < g.M ? *reinterpret_cast<const Frag*>(src + bt_n0) : zf;
+      a1 = m0 + bt_n1 < g.M ? *reinterpret_cast<const Frag*>(src + bt_n1) : zf;
+    } else {
+      a0 = a_ok ? *reinterpret_cast<const Frag*>(a_src + k0) : zf;
+      a1 = a_ok ? *reinterpret_cast<const Frag*>(a_src + k0 + 8) : zf;
+    }
     Frag b0, b1;
     if constexpr (BT) {
       const Elem* src = B + (int64_t)(k0 + bt_k) * g.b_sk + n0;
@@ -245,8 +264,16 @@ __global__ __launch_bounds__(256) void k_gemm_tiled(GemmDesc g) {
       b1 = b_ok ? *reinterpret_cast<const Frag*>(b_src + k0 + 8) : zf;
     }
     __syncthreads();  // the previous step's reads are done
-    *reinterpret_cast<Frag*>(&As[lr * kTileLd + lk]) = a0;
-    *reinterpret_cast<Frag*>(&As[lr * kTileLd + lk + 8]) = a1;
+    if constexpr (AT) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        As[(bt_n0 + e) * kTileLd + bt_k] = a0[e];
+        As[(bt_n1 + e) * kTileLd + bt_k] = a1[e];
+      }
+    } else {
+      *reinterpret_cast<Frag*>(&As[lr * kTileLd + lk]) = a0;
+      *reinterpret_cast<Frag*>(&As[lr * kTileLd + lk + 8]) = a1;
+    }
     if constexpr (BT) {
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
@@ -271,7 +298,38 @@ __global__ __launch_bounds__(256) void k_gemm_tiled(GemmDesc g) {
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = Prec<P>::mma(af[i], bf[j], acc[i][j]);
+      if (rowsum) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) rs[i] = Prec<P>::mma(af[i], ones, rs[i]);
+      }
     }
+  }
+  if (g.mode == 2) {
+    // FP32 partial sums of this chunk, and the row sums of A (every column
+    // of rs holds them: lanes 0 and 32 store)
+    float* Cp = static_cast<float*>(g.C) + (int64_t)split * g.c_split_stride;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int n = n0 + wn + j * 32 + c;
+        if (n >= g.N) continue;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int m = m0 + wm + i * 32 + acc_row(0, h, r);
+          if (m < g.M) Cp[(int64_t)m * g.ldc + n] = acc[i][j][r];
+        }
+      }
+    if (rowsum && c == 0) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int m = m0 + wm + i * 32 + acc_row(0, h, r);
+          if (m < g.M) g.a_rowsum[(int64_t)split * g.c_split_stride + m] = rs[i][r];
+        }
+    }
+    return;
   }
   Elem* C = static_cast<Elem*>(g.C);
   const Elem* mask = static_cast<const Elem*>(g.mask);
@@ -616,22 +674,27 @@ static int grid_for_params(int64_t np) { return (int)std::min<int64_t>(4096, (np
 // least 64 wide with 16-bit operands take the LDS-tiled kernel (a 96-wide
 // layer leaves a quarter of its one 128-column tile idle and is still several
 // times faster than one L2-fed wave per 32 x 32 tile)
-// BT: B contiguous along n (rows of 16-byte aligned runs of n)
-template <int P, bool BT>
+// AT / BT: A contiguous along m / B contiguous along n (rows of 16-byte
+// aligned runs); mode 2 (split-K FP32 partials) needs every chunk whole
+template <int P, bool AT, bool BT>
 static bool tiled_ok(const GemmDesc& g) {
   auto aligned = [](const void* p) { return reinterpret_cast<uintptr_t>(p) % 16 == 0; };
-  const bool common = Prec<P>::KPL == 8 && (g.mode == 0 || g.mode == 1) && g.splits == 1 && g.N >= 64 &&
-                      g.K % kTileK == 0 && g.a_sk == 1 && g.a_sm % 8 == 0 && aligned(g.A) && aligned(g.B);
-  if (BT) return common && g.b_sn == 1 && g.b_sk % 8 == 0 && g.N % 8 == 0;
-  return common && g.b_sk == 1 && g.b_sn % 8 == 0;
+  bool ok = Prec<P>::KPL == 8 && g.N >= 64 && aligned(g.A) && aligned(g.B);
+  if (g.mode == 2) ok = ok && g.k_chunk % kTileK == 0 && g.K % g.k_chunk == 0 && g.splits == g.K / g.k_chunk;
+  else ok = ok && (g.mode == 0 || g.mode == 1) && g.splits == 1 && g.K % kTileK == 0 && g.k_chunk == g.K;
+  if (AT) ok = ok && g.a_sm == 1 && g.a_sk % 8 == 0 && g.M % 8 == 0;
+  else ok = ok && g.a_sk == 1 && g.a_sm % 8 == 0;
+  if (BT) ok = ok && g.b_sn == 1 && g.b_sk % 8 == 0 && g.N % 8 == 0;
+  else ok = ok && g.b_sk == 1 && g.b_sn % 8 == 0;
+  return ok;
 }
 
 template <int P, bool AK, bool BK>
 static hipError_t gemm(const GemmDesc& g, hipStream_t st) {
-  if constexpr (AK && Prec<P>::KPL == 8) {
-    if (tiled_ok<P, !BK>(g)) {
+  if constexpr (Prec<P>::KPL == 8) {
+    if (tiled_ok<P, !AK, !BK>(g)) {
       const int tiles = ((g.M + kTileM - 1) / kTileM) * ((g.N + kTileN - 1) / kTileN);
-      hipLaunchKernelGGL((k_gemm_tiled<P, !BK>), dim3(tiles), dim3(256), 0, st, g);
+      hipLaunchKernelGGL((k_gemm_tiled<P, !AK, !BK>), dim3(tiles * g.splits), dim3(256), 0, st, g);
       return hipGetLastError();
     }
   }
