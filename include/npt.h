@@ -4,8 +4,9 @@
  *
  * Conventions (all calls):
  *   - Every call returns an int status: NPT_OK (0) or a negative NPT_E_* code.
- *     Nothing throws across the ABI.  npt_last_error() returns a message owned
- *     by the context, valid until the next call on that context.
+ *     Nothing throws across the ABI (a host allocation failure inside a call
+ *     returns NPT_E_OOM).  npt_last_error() returns a message owned by the
+ *     context, valid until the next call on that context.
  *   - Host input arrays are copied during the call; the caller keeps ownership.
  *   - Device output buffers are caller-owned (e.g. the data pointer of a
  *     torch.cuda tensor).  `stream` is a hipStream_t (NULL = the null stream);

@@ -139,6 +139,25 @@ int ok(npt_ctx* c) {
   return NPT_OK;
 }
 
+// Nothing throws across the C ABI: a host allocation failure or another C++
+// exception inside an entry point becomes NPT_E_OOM with a message.
+template <class F>
+int guarded(npt_ctx* c, F&& body) noexcept {
+  try {
+    return body();
+  } catch (const std::bad_alloc&) {
+    if (c) c->err = "out of memory";  // short enough to need no allocation
+  } catch (const std::exception& e) {
+    try {
+      if (c) c->err = e.what();
+    } catch (...) {
+    }
+  } catch (...) {
+    if (c) c->err = "host error";
+  }
+  return NPT_E_OOM;
+}
+
 #define HIP_TRY(ctx, expr)                                                                   \
   do {                                                                                       \
     hipError_t e_ = (expr);                                                                  \
@@ -237,36 +256,38 @@ int repack_nif(npt_ctx* c, hipStream_t s) {
 // context
 // ===========================================================================
 extern "C" int npt_create(npt_ctx** out, int device) {
-  if (!out) return NPT_E_INVALID_ARG;
-  *out = nullptr;
-  npt_ctx* c = new (std::nothrow) npt_ctx();
-  if (!c) return NPT_E_OOM;
-  if (device >= 0) {
-    int count = 0;
-    if (hipGetDeviceCount(&count) != hipSuccess || device >= count) {
-      delete c;
-      return NPT_E_NO_DEVICE;
+  return guarded(nullptr, [&]() -> int {
+    if (!out) return NPT_E_INVALID_ARG;
+    *out = nullptr;
+    npt_ctx* c = new (std::nothrow) npt_ctx();
+    if (!c) return NPT_E_OOM;
+    if (device >= 0) {
+      int count = 0;
+      if (hipGetDeviceCount(&count) != hipSuccess || device >= count) {
+        delete c;
+        return NPT_E_NO_DEVICE;
+      }
+      if (hipSetDevice(device) != hipSuccess) {
+        delete c;
+        return NPT_E_HIP;
+      }
+      hipDeviceProp_t prop;
+      if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        delete c;
+        return NPT_E_HIP;
+      }
+      c->device = device;
+      c->host_only = false;
+      c->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+      c->fp8_capable = std::strstr(prop.gcnArchName, "gfx950") != nullptr;
+      if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+        delete c;
+        return NPT_E_HIP;
+      }
     }
-    if (hipSetDevice(device) != hipSuccess) {
-      delete c;
-      return NPT_E_HIP;
-    }
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
-      delete c;
-      return NPT_E_HIP;
-    }
-    c->device = device;
-    c->host_only = false;
-    c->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-    c->fp8_capable = std::strstr(prop.gcnArchName, "gfx950") != nullptr;
-    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
-      delete c;
-      return NPT_E_HIP;
-    }
-  }
-  *out = c;
-  return NPT_OK;
+    *out = c;
+    return NPT_OK;
+  });
 }
 
 extern "C" int npt_destroy(npt_ctx* ctx) {
@@ -283,269 +304,291 @@ extern "C" const char* npt_last_error(npt_ctx* ctx) { return ctx ? ctx->err.c_st
 // ===========================================================================
 extern "C" int npt_scene_triangles(npt_ctx* c, const float* xyz, uint64_t nv, const uint32_t* tri, uint64_t nt,
                                    const uint32_t* mat_of_tri) {
-  if (!c) return NPT_E_INVALID_ARG;
-  if ((nv && !xyz) || (nt && !tri)) return fail(c, NPT_E_INVALID_ARG, "null array with nonzero size");
-  if (nv > (1ull << 32) || nt >= kMaxSlots) return fail(c, NPT_E_INVALID_ARG, "too many vertices/triangles");
-  if (!finite_all(xyz, 3 * nv)) return fail(c, NPT_E_NAN_INPUT, "non-finite vertex coordinate");
-  for (uint64_t i = 0; i < 3 * nt; ++i)
-    if (tri[i] >= nv) return fail(c, NPT_E_INVALID_ARG, "triangle index out of range");
-  c->verts.assign(xyz, xyz + 3 * nv);
-  c->tris.assign(tri, tri + 3 * nt);
-  if (mat_of_tri) c->tri_mat.assign(mat_of_tri, mat_of_tri + nt);
-  else c->tri_mat.assign(nt, 0u);
-  c->scene_dirty = true;
-  c->bvh_built = false;
-  return ok(c);
+  return guarded(c, [&]() -> int {
+    if (!c) return NPT_E_INVALID_ARG;
+    if ((nv && !xyz) || (nt && !tri)) return fail(c, NPT_E_INVALID_ARG, "null array with nonzero size");
+    if (nv > (1ull << 32) || nt >= kMaxSlots) return fail(c, NPT_E_INVALID_ARG, "too many vertices/triangles");
+    if (!finite_all(xyz, 3 * nv)) return fail(c, NPT_E_NAN_INPUT, "non-finite vertex coordinate");
+    for (uint64_t i = 0; i < 3 * nt; ++i)
+      if (tri[i] >= nv) return fail(c, NPT_E_INVALID_ARG, "triangle index out of range");
+    c->verts.assign(xyz, xyz + 3 * nv);
+    c->tris.assign(tri, tri + 3 * nt);
+    if (mat_of_tri) c->tri_mat.assign(mat_of_tri, mat_of_tri + nt);
+    else c->tri_mat.assign(nt, 0u);
+    c->scene_dirty = true;
+    c->bvh_built = false;
+    return ok(c);
+  });
 }
 
 extern "C" int npt_scene_spheres(npt_ctx* c, const float* cxyzr, uint64_t n, const uint32_t* mat) {
-  if (!c) return NPT_E_INVALID_ARG;
-  if (n && !cxyzr) return fail(c, NPT_E_INVALID_ARG, "null sphere array");
-  if (n >= kMaxSlots) return fail(c, NPT_E_INVALID_ARG, "too many spheres");
-  if (!finite_all(cxyzr, 4 * n)) return fail(c, NPT_E_NAN_INPUT, "non-finite sphere");
-  for (uint64_t i = 0; i < n; ++i)
-    if (!(cxyzr[4 * i + 3] > 0.0f)) return fail(c, NPT_E_INVALID_ARG, "sphere radius must be > 0");
-  c->spheres.assign(cxyzr, cxyzr + 4 * n);
-  if (mat) c->sph_mat.assign(mat, mat + n);
-  else c->sph_mat.assign(n, 0u);
-  c->scene_dirty = true;
-  c->bvh_built = false;
-  return ok(c);
+  return guarded(c, [&]() -> int {
+    if (!c) return NPT_E_INVALID_ARG;
+    if (n && !cxyzr) return fail(c, NPT_E_INVALID_ARG, "null sphere array");
+    if (n >= kMaxSlots) return fail(c, NPT_E_INVALID_ARG, "too many spheres");
+    if (!finite_all(cxyzr, 4 * n)) return fail(c, NPT_E_NAN_INPUT, "non-finite sphere");
+    for (uint64_t i = 0; i < n; ++i)
+      if (!(cxyzr[4 * i + 3] > 0.0f)) return fail(c, NPT_E_INVALID_ARG, "sphere radius must be > 0");
+    c->spheres.assign(cxyzr, cxyzr + 4 * n);
+    if (mat) c->sph_mat.assign(mat, mat + n);
+    else c->sph_mat.assign(n, 0u);
+    c->scene_dirty = true;
+    c->bvh_built = false;
+    return ok(c);
+  });
 }
 
 extern "C" int npt_scene_blas_triangles(npt_ctx* c, uint32_t blas_id, const float* xyz, uint64_t nv,
                                         const uint32_t* tri, uint64_t nt, const uint32_t* mat_of_tri) {
-  if (!c) return NPT_E_INVALID_ARG;
-  if (blas_id > c->blas.size()) return fail(c, NPT_E_INVALID_ARG, "blas_id must be an existing id or the next one");
-  if (nt == 0 || !xyz || !tri) return fail(c, NPT_E_INVALID_ARG, "an instanced mesh needs triangles");
-  if (nv > (1ull << 32) || nt >= kMaxSlots) return fail(c, NPT_E_INVALID_ARG, "too many vertices/triangles");
-  if (!finite_all(xyz, 3 * nv)) return fail(c, NPT_E_NAN_INPUT, "non-finite vertex coordinate");
-  for (uint64_t i = 0; i < 3 * nt; ++i)
-    if (tri[i] >= nv) return fail(c, NPT_E_INVALID_ARG, "triangle index out of range");
-  npt_ctx::Mesh m;
-  m.verts.assign(xyz, xyz + 3 * nv);
-  m.tris.assign(tri, tri + 3 * nt);
-  if (mat_of_tri) m.mat.assign(mat_of_tri, mat_of_tri + nt);
-  else m.mat.assign(nt, 0u);
-  if (blas_id == c->blas.size()) c->blas.push_back(std::move(m));
-  else c->blas[blas_id] = std::move(m);
-  c->scene_dirty = true;
-  c->bvh_built = false;
-  return ok(c);
+  return guarded(c, [&]() -> int {
+    if (!c) return NPT_E_INVALID_ARG;
+    if (blas_id > c->blas.size()) return fail(c, NPT_E_INVALID_ARG, "blas_id must be an existing id or the next one");
+    if (nt == 0 || !xyz || !tri) return fail(c, NPT_E_INVALID_ARG, "an instanced mesh needs triangles");
+    if (nv > (1ull << 32) || nt >= kMaxSlots) return fail(c, NPT_E_INVALID_ARG, "too many vertices/triangles");
+    if (!finite_all(xyz, 3 * nv)) return fail(c, NPT_E_NAN_INPUT, "non-finite vertex coordinate");
+    for (uint64_t i = 0; i < 3 * nt; ++i)
+      if (tri[i] >= nv) return fail(c, NPT_E_INVALID_ARG, "triangle index out of range");
+    npt_ctx::Mesh m;
+    m.verts.assign(xyz, xyz + 3 * nv);
+    m.tris.assign(tri, tri + 3 * nt);
+    if (mat_of_tri) m.mat.assign(mat_of_tri, mat_of_tri + nt);
+    else m.mat.assign(nt, 0u);
+    if (blas_id == c->blas.size()) c->blas.push_back(std::move(m));
+    else c->blas[blas_id] = std::move(m);
+    c->scene_dirty = true;
+    c->bvh_built = false;
+    return ok(c);
+  });
 }
 
 extern "C" int npt_scene_instances(npt_ctx* c, const npt_instance* inst, uint32_t n) {
-  if (!c) return NPT_E_INVALID_ARG;
-  if (n && !inst) return fail(c, NPT_E_INVALID_ARG, "null instance array");
-  if (n >= (1u << 24)) return fail(c, NPT_E_INVALID_ARG, "too many instances");
-  for (uint32_t i = 0; i < n; ++i) {
-    if (inst[i].blas_id >= c->blas.size()) return fail(c, NPT_E_INVALID_ARG, "instance of an unknown blas_id");
-    if (!finite_all(inst[i].translate, 3) || !std::isfinite(inst[i].scale))
-      return fail(c, NPT_E_NAN_INPUT, "non-finite instance transform");
-    if (!(inst[i].scale > 0.0f)) return fail(c, NPT_E_INVALID_ARG, "instance scale must be > 0");
-  }
-  c->instances.assign(inst, inst + n);
-  c->scene_dirty = true;
-  c->bvh_built = false;
-  return ok(c);
+  return guarded(c, [&]() -> int {
+    if (!c) return NPT_E_INVALID_ARG;
+    if (n && !inst) return fail(c, NPT_E_INVALID_ARG, "null instance array");
+    if (n >= (1u << 24)) return fail(c, NPT_E_INVALID_ARG, "too many instances");
+    for (uint32_t i = 0; i < n; ++i) {
+      if (inst[i].blas_id >= c->blas.size()) return fail(c, NPT_E_INVALID_ARG, "instance of an unknown blas_id");
+      if (!finite_all(inst[i].translate, 3) || !std::isfinite(inst[i].scale))
+        return fail(c, NPT_E_NAN_INPUT, "non-finite instance transform");
+      if (!(inst[i].scale > 0.0f)) return fail(c, NPT_E_INVALID_ARG, "instance scale must be > 0");
+    }
+    c->instances.assign(inst, inst + n);
+    c->scene_dirty = true;
+    c->bvh_built = false;
+    return ok(c);
+  });
 }
 
 extern "C" int npt_scene_materials(npt_ctx* c, const npt_material* m, uint32_t n) {
-  if (!c) return NPT_E_INVALID_ARG;
-  if (n && !m) return fail(c, NPT_E_INVALID_ARG, "null material array");
-  for (uint32_t i = 0; i < n; ++i) {
-    if (m[i].type > NPT_EMITTER) return fail(c, NPT_E_INVALID_ARG, "unknown material type");
-    if (!finite_all(m[i].albedo, 3) || !finite_all(m[i].emission, 3) || !std::isfinite(m[i].ior))
-      return fail(c, NPT_E_NAN_INPUT, "non-finite material");
-    if (m[i].type == NPT_DIELECTRIC && !(m[i].ior > 0.0f)) return fail(c, NPT_E_INVALID_ARG, "ior must be > 0");
-  }
-  c->materials.assign(m, m + n);
-  if (!c->host_only) {
-    int r = need_device(c);
-    if (r) return r;
-    r = upload_materials(c, nullptr);
-    if (r) return r;
-  }
-  return ok(c);
+  return guarded(c, [&]() -> int {
+    if (!c) return NPT_E_INVALID_ARG;
+    if (n && !m) return fail(c, NPT_E_INVALID_ARG, "null material array");
+    for (uint32_t i = 0; i < n; ++i) {
+      if (m[i].type > NPT_EMITTER) return fail(c, NPT_E_INVALID_ARG, "unknown material type");
+      if (!finite_all(m[i].albedo, 3) || !finite_all(m[i].emission, 3) || !std::isfinite(m[i].ior))
+        return fail(c, NPT_E_NAN_INPUT, "non-finite material");
+      if (m[i].type == NPT_DIELECTRIC && !(m[i].ior > 0.0f)) return fail(c, NPT_E_INVALID_ARG, "ior must be > 0");
+    }
+    c->materials.assign(m, m + n);
+    if (!c->host_only) {
+      int r = need_device(c);
+      if (r) return r;
+      r = upload_materials(c, nullptr);
+      if (r) return r;
+    }
+    return ok(c);
+  });
 }
 
 extern "C" int npt_build_bvh(npt_ctx* c, const npt_bvh_params* p, void* stream) {
-  if (!c) return NPT_E_INVALID_ARG;
-  uint32_t bins = p && p->bins ? p->bins : 32, max_leaf = p && p->max_leaf ? p->max_leaf : 4;
-  uint32_t lds_levels = p ? p->lds_levels : 0;
-  const uint32_t width = p && p->width ? p->width : 4;
-  const uint32_t node_format = p ? p->node_format : NPT_NODES_FP32;
-  if (width != 2 && width != 4) return fail(c, NPT_E_INVALID_ARG, "BVH width must be 2 or 4");
-  if (node_format != NPT_NODES_FP32 && node_format != NPT_NODES_FP16_EXTENT && node_format != NPT_NODES_Q8)
-    return fail(c, NPT_E_INVALID_ARG, "unknown BVH node format");
-  if (node_format != NPT_NODES_FP32 && (width != 4 || lds_levels != 0))
-    return fail(c, NPT_E_INVALID_ARG, "compressed nodes need width 4 and lds_levels 0");
-  if (bins < 4 || bins > 256 || max_leaf < 1 || max_leaf > kMaxLeaf || lds_levels > 8)
-    return fail(c, NPT_E_INVALID_ARG, "bvh params out of range");
-  const bool has_base = !c->tris.empty() || !c->spheres.empty();
-  const bool two_level = !c->instances.empty();
-  if (!has_base && !two_level) return fail(c, NPT_E_NO_SCENE, "no geometry uploaded");
-  if (two_level && (width != 4 || lds_levels != 0))
-    return fail(c, NPT_E_UNSUPPORTED, "instanced scenes use width 4 without LDS levels");
-  const uint32_t nmat = (uint32_t)std::max<size_t>(1, c->materials.size());
-  for (uint32_t m : c->tri_mat)
-    if (m >= nmat) return fail(c, NPT_E_INVALID_ARG, "triangle material id out of range");
-  for (uint32_t m : c->sph_mat)
-    if (m >= nmat) return fail(c, NPT_E_INVALID_ARG, "sphere material id out of range");
-  for (const npt_instance& k : c->instances) {
-    if (k.blas_id >= c->blas.size()) return fail(c, NPT_E_INVALID_ARG, "instance of an unknown blas_id");
-    for (uint32_t m : c->blas[k.blas_id].mat)
-      if (m >= nmat) return fail(c, NPT_E_INVALID_ARG, "instanced triangle material id out of range");
-  }
-  BuildInput in;
-  in.verts = c->verts.data();
-  in.nv = c->verts.size() / 3;
-  in.tris = c->tris.data();
-  in.nt = c->tris.size() / 3;
-  in.tri_mat = c->tri_mat.data();
-  in.spheres = c->spheres.data();
-  in.ns = c->spheres.size() / 4;
-  in.sph_mat = c->sph_mat.data();
-  FlatBvh b;
-  std::vector<float4> records;
-  std::string e;
-  uint32_t stack_need = 0;
-  if (!two_level) {
-    if (!build_bvh(in, bins, max_leaf, lds_levels, width, b, e)) return fail(c, NPT_E_INVALID_ARG, e);
-    // deferred children: one per level (width 2); up to three per level,
-    // plus the three of the deepest node (width 4)
-    stack_need = width == 2 ? b.max_depth + 1 : 3 * b.max_depth + 3;
-  } else {
-    // bottom trees: the base geometry (instance 0) and each instanced mesh
-    std::vector<FlatBvh> bottoms;
-    std::vector<Placement> objects;
-    if (has_base) {
-      bottoms.emplace_back();
-      if (!build_bvh(in, bins, max_leaf, 0, 4, bottoms.back(), e)) return fail(c, NPT_E_INVALID_ARG, e);
-      objects.push_back(Placement{0u, {0.0f, 0.0f, 0.0f}, 1.0f, 0u});
+  return guarded(c, [&]() -> int {
+    if (!c) return NPT_E_INVALID_ARG;
+    uint32_t bins = p && p->bins ? p->bins : 32, max_leaf = p && p->max_leaf ? p->max_leaf : 4;
+    uint32_t lds_levels = p ? p->lds_levels : 0;
+    const uint32_t width = p && p->width ? p->width : 4;
+    const uint32_t node_format = p ? p->node_format : NPT_NODES_FP32;
+    if (width != 2 && width != 4) return fail(c, NPT_E_INVALID_ARG, "BVH width must be 2 or 4");
+    if (node_format != NPT_NODES_FP32 && node_format != NPT_NODES_FP16_EXTENT && node_format != NPT_NODES_Q8)
+      return fail(c, NPT_E_INVALID_ARG, "unknown BVH node format");
+    if (node_format != NPT_NODES_FP32 && (width != 4 || lds_levels != 0))
+      return fail(c, NPT_E_INVALID_ARG, "compressed nodes need width 4 and lds_levels 0");
+    if (bins < 4 || bins > 256 || max_leaf < 1 || max_leaf > kMaxLeaf || lds_levels > 8)
+      return fail(c, NPT_E_INVALID_ARG, "bvh params out of range");
+    const bool has_base = !c->tris.empty() || !c->spheres.empty();
+    const bool two_level = !c->instances.empty();
+    if (!has_base && !two_level) return fail(c, NPT_E_NO_SCENE, "no geometry uploaded");
+    if (two_level && (width != 4 || lds_levels != 0))
+      return fail(c, NPT_E_UNSUPPORTED, "instanced scenes use width 4 without LDS levels");
+    const uint32_t nmat = (uint32_t)std::max<size_t>(1, c->materials.size());
+    for (uint32_t m : c->tri_mat)
+      if (m >= nmat) return fail(c, NPT_E_INVALID_ARG, "triangle material id out of range");
+    for (uint32_t m : c->sph_mat)
+      if (m >= nmat) return fail(c, NPT_E_INVALID_ARG, "sphere material id out of range");
+    for (const npt_instance& k : c->instances) {
+      if (k.blas_id >= c->blas.size()) return fail(c, NPT_E_INVALID_ARG, "instance of an unknown blas_id");
+      for (uint32_t m : c->blas[k.blas_id].mat)
+        if (m >= nmat) return fail(c, NPT_E_INVALID_ARG, "instanced triangle material id out of range");
     }
-    std::vector<int64_t> tree_of(c->blas.size(), -1);
-    for (size_t k = 0; k < c->instances.size(); ++k) {
-      const npt_instance& x = c->instances[k];
-      if (tree_of[x.blas_id] < 0) {
-        const npt_ctx::Mesh& m = c->blas[x.blas_id];
-        BuildInput bi;
-        bi.verts = m.verts.data();
-        bi.nv = m.verts.size() / 3;
-        bi.tris = m.tris.data();
-        bi.nt = m.tris.size() / 3;
-        bi.tri_mat = m.mat.data();
+    BuildInput in;
+    in.verts = c->verts.data();
+    in.nv = c->verts.size() / 3;
+    in.tris = c->tris.data();
+    in.nt = c->tris.size() / 3;
+    in.tri_mat = c->tri_mat.data();
+    in.spheres = c->spheres.data();
+    in.ns = c->spheres.size() / 4;
+    in.sph_mat = c->sph_mat.data();
+    FlatBvh b;
+    std::vector<float4> records;
+    std::string e;
+    uint32_t stack_need = 0;
+    if (!two_level) {
+      if (!build_bvh(in, bins, max_leaf, lds_levels, width, b, e)) return fail(c, NPT_E_INVALID_ARG, e);
+      // deferred children: one per level (width 2); up to three per level,
+      // plus the three of the deepest node (width 4)
+      stack_need = width == 2 ? b.max_depth + 1 : 3 * b.max_depth + 3;
+    } else {
+      // bottom trees: the base geometry (instance 0) and each instanced mesh
+      std::vector<FlatBvh> bottoms;
+      std::vector<Placement> objects;
+      if (has_base) {
         bottoms.emplace_back();
-        if (!build_bvh(bi, bins, max_leaf, 0, 4, bottoms.back(), e)) return fail(c, NPT_E_INVALID_ARG, e);
-        tree_of[x.blas_id] = (int64_t)bottoms.size() - 1;
+        if (!build_bvh(in, bins, max_leaf, 0, 4, bottoms.back(), e)) return fail(c, NPT_E_INVALID_ARG, e);
+        objects.push_back(Placement{0u, {0.0f, 0.0f, 0.0f}, 1.0f, 0u});
       }
-      objects.push_back(Placement{(uint32_t)tree_of[x.blas_id],
-                                  {x.translate[0], x.translate[1], x.translate[2]},
-                                  x.scale,
-                                  (uint32_t)(k + 1)});
+      std::vector<int64_t> tree_of(c->blas.size(), -1);
+      for (size_t k = 0; k < c->instances.size(); ++k) {
+        const npt_instance& x = c->instances[k];
+        if (tree_of[x.blas_id] < 0) {
+          const npt_ctx::Mesh& m = c->blas[x.blas_id];
+          BuildInput bi;
+          bi.verts = m.verts.data();
+          bi.nv = m.verts.size() / 3;
+          bi.tris = m.tris.data();
+          bi.nt = m.tris.size() / 3;
+          bi.tri_mat = m.mat.data();
+          bottoms.emplace_back();
+          if (!build_bvh(bi, bins, max_leaf, 0, 4, bottoms.back(), e)) return fail(c, NPT_E_INVALID_ARG, e);
+          tree_of[x.blas_id] = (int64_t)bottoms.size() - 1;
+        }
+        objects.push_back(Placement{(uint32_t)tree_of[x.blas_id],
+                                    {x.translate[0], x.translate[1], x.translate[2]},
+                                    x.scale,
+                                    (uint32_t)(k + 1)});
+      }
+      if (!build_two_level(bottoms, objects, bins, b, records, stack_need, e)) return fail(c, NPT_E_INVALID_ARG, e);
     }
-    if (!build_two_level(bottoms, objects, bins, b, records, stack_need, e)) return fail(c, NPT_E_INVALID_ARG, e);
-  }
-  if (node_format == NPT_NODES_FP16_EXTENT && !compress_half_extents(b, e)) return fail(c, NPT_E_UNSUPPORTED, e);
-  if (node_format == NPT_NODES_Q8 && !compress_q8_nodes(b, e)) return fail(c, NPT_E_UNSUPPORTED, e);
-  if (trace_stack_size(stack_need) == 0)
-    return fail(c, NPT_E_UNSUPPORTED, "BVH deeper than the 128-entry traversal stack");
-  // the traversal addresses nodes with 32-bit byte offsets
-  if ((uint64_t)b.nodes.size() * sizeof(float4) >= (1ull << 32))
-    return fail(c, NPT_E_UNSUPPORTED, "BVH node array of 4 GiB or more (use a larger max_leaf)");
-  c->bvh = std::move(b);
-  c->inst_records = std::move(records);
-  c->two_level = two_level;
-  c->bvh_built = false;
-  if (c->host_only) return fail(c, NPT_E_NO_DEVICE, "BVH built on the host; no device to upload to");
-  int r = need_device(c);
-  if (r) return r;
-  hipStream_t s = (hipStream_t)stream;
-  HIP_TRY(c, c->d_nodes.ensure(c->bvh.nodes.size() * sizeof(float4)));
-  HIP_TRY(c, c->d_slots.ensure(c->bvh.slots.size() * sizeof(float4)));
-  HIP_TRY(c, hipMemcpyAsync(c->d_nodes.p, c->bvh.nodes.data(), c->bvh.nodes.size() * sizeof(float4),
-                            hipMemcpyHostToDevice, s));
-  HIP_TRY(c, hipMemcpyAsync(c->d_slots.p, c->bvh.slots.data(), c->bvh.slots.size() * sizeof(float4),
-                            hipMemcpyHostToDevice, s));
-  if (two_level) {
-    HIP_TRY(c, c->d_inst.ensure(c->inst_records.size() * sizeof(float4)));
-    HIP_TRY(c, hipMemcpyAsync(c->d_inst.p, c->inst_records.data(), c->inst_records.size() * sizeof(float4),
+    if (node_format == NPT_NODES_FP16_EXTENT && !compress_half_extents(b, e)) return fail(c, NPT_E_UNSUPPORTED, e);
+    if (node_format == NPT_NODES_Q8 && !compress_q8_nodes(b, e)) return fail(c, NPT_E_UNSUPPORTED, e);
+    if (trace_stack_size(stack_need) == 0)
+      return fail(c, NPT_E_UNSUPPORTED, "BVH deeper than the 128-entry traversal stack");
+    // the traversal addresses nodes with 32-bit byte offsets
+    if ((uint64_t)b.nodes.size() * sizeof(float4) >= (1ull << 32))
+      return fail(c, NPT_E_UNSUPPORTED, "BVH node array of 4 GiB or more (use a larger max_leaf)");
+    c->bvh = std::move(b);
+    c->inst_records = std::move(records);
+    c->two_level = two_level;
+    c->bvh_built = false;
+    if (c->host_only) return fail(c, NPT_E_NO_DEVICE, "BVH built on the host; no device to upload to");
+    int r = need_device(c);
+    if (r) return r;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(c, c->d_nodes.ensure(c->bvh.nodes.size() * sizeof(float4)));
+    HIP_TRY(c, c->d_slots.ensure(c->bvh.slots.size() * sizeof(float4)));
+    HIP_TRY(c, hipMemcpyAsync(c->d_nodes.p, c->bvh.nodes.data(), c->bvh.nodes.size() * sizeof(float4),
                               hipMemcpyHostToDevice, s));
-  }
-  HIP_TRY(c, hipStreamSynchronize(s));
-  r = upload_materials(c, s);
-  if (r) return r;
-  c->stack_depth = trace_stack_size(stack_need);
-  c->bvh_built = true;
-  c->scene_dirty = false;
-  return ok(c);
+    HIP_TRY(c, hipMemcpyAsync(c->d_slots.p, c->bvh.slots.data(), c->bvh.slots.size() * sizeof(float4),
+                              hipMemcpyHostToDevice, s));
+    if (two_level) {
+      HIP_TRY(c, c->d_inst.ensure(c->inst_records.size() * sizeof(float4)));
+      HIP_TRY(c, hipMemcpyAsync(c->d_inst.p, c->inst_records.data(), c->inst_records.size() * sizeof(float4),
+                                hipMemcpyHostToDevice, s));
+    }
+    HIP_TRY(c, hipStreamSynchronize(s));
+    r = upload_materials(c, s);
+    if (r) return r;
+    c->stack_depth = trace_stack_size(stack_need);
+    c->bvh_built = true;
+    c->scene_dirty = false;
+    return ok(c);
+  });
 }
 
 extern "C" int npt_bvh_info(npt_ctx* c, uint64_t* nodes, uint64_t* leaves, uint32_t* max_depth, uint64_t* slots,
                             uint32_t* width) {
-  if (!c) return NPT_E_INVALID_ARG;
-  if (c->bvh.nodes.empty()) return fail(c, NPT_E_STATE, "no BVH built");
-  if (nodes) *nodes = c->bvh.nodes.size() / c->bvh.node_float4s;
-  if (leaves) *leaves = c->bvh.leaves;
-  if (max_depth) *max_depth = c->bvh.max_depth;
-  if (slots) *slots = c->bvh.slots.size() / 3;
-  if (width) *width = c->bvh.width;
-  return ok(c);
+  return guarded(c, [&]() -> int {
+    if (!c) return NPT_E_INVALID_ARG;
+    if (c->bvh.nodes.empty()) return fail(c, NPT_E_STATE, "no BVH built");
+    if (nodes) *nodes = c->bvh.nodes.size() / c->bvh.node_float4s;
+    if (leaves) *leaves = c->bvh.leaves;
+    if (max_depth) *max_depth = c->bvh.max_depth;
+    if (slots) *slots = c->bvh.slots.size() / 3;
+    if (width) *width = c->bvh.width;
+    return ok(c);
+  });
 }
 
 extern "C" int npt_set_camera(npt_ctx* c, const npt_camera* cam) {
-  if (!c) return NPT_E_INVALID_ARG;
-  if (!cam) return fail(c, NPT_E_INVALID_ARG, "null camera");
-  if (!finite_all(cam->eye, 3) || !finite_all(cam->look_at, 3) || !finite_all(cam->up, 3) ||
-      !std::isfinite(cam->vfov_deg))
-    return fail(c, NPT_E_NAN_INPUT, "non-finite camera");
-  if (!(cam->vfov_deg > 0.0f && cam->vfov_deg < 180.0f)) return fail(c, NPT_E_INVALID_ARG, "vfov out of (0,180)");
-  float f[3];
-  for (int i = 0; i < 3; ++i) f[i] = cam->look_at[i] - cam->eye[i];
-  const float cx = f[1] * cam->up[2] - f[2] * cam->up[1], cy = f[2] * cam->up[0] - f[0] * cam->up[2],
-              cz = f[0] * cam->up[1] - f[1] * cam->up[0];
-  if (f[0] == 0 && f[1] == 0 && f[2] == 0) return fail(c, NPT_E_INVALID_ARG, "eye == look_at");
-  if (cx == 0 && cy == 0 && cz == 0) return fail(c, NPT_E_INVALID_ARG, "up parallel to view direction");
-  c->camera = *cam;
-  c->have_camera = true;
-  return ok(c);
+  return guarded(c, [&]() -> int {
+    if (!c) return NPT_E_INVALID_ARG;
+    if (!cam) return fail(c, NPT_E_INVALID_ARG, "null camera");
+    if (!finite_all(cam->eye, 3) || !finite_all(cam->look_at, 3) || !finite_all(cam->up, 3) ||
+        !std::isfinite(cam->vfov_deg))
+      return fail(c, NPT_E_NAN_INPUT, "non-finite camera");
+    if (!(cam->vfov_deg > 0.0f && cam->vfov_deg < 180.0f)) return fail(c, NPT_E_INVALID_ARG, "vfov out of (0,180)");
+    float f[3];
+    for (int i = 0; i < 3; ++i) f[i] = cam->look_at[i] - cam->eye[i];
+    const float cx = f[1] * cam->up[2] - f[2] * cam->up[1], cy = f[2] * cam->up[0] - f[0] * cam->up[2],
+                cz = f[0] * cam->up[1] - f[1] * cam->up[0];
+    if (f[0] == 0 && f[1] == 0 && f[2] == 0) return fail(c, NPT_E_INVALID_ARG, "eye == look_at");
+    if (cx == 0 && cy == 0 && cz == 0) return fail(c, NPT_E_INVALID_ARG, "up parallel to view direction");
+    c->camera = *cam;
+    c->have_camera = true;
+    return ok(c);
+  });
 }
 
 extern "C" int npt_set_render_options(npt_ctx* c, const npt_render_options* o) {
-  if (!c) return NPT_E_INVALID_ARG;
-  if (!o) return fail(c, NPT_E_INVALID_ARG, "null options");
-  if (o->pool_paths > (1u << 30)) return fail(c, NPT_E_INVALID_ARG, "pool_paths > 2^30");
-  c->opt = *o;
-  return ok(c);
+  return guarded(c, [&]() -> int {
+    if (!c) return NPT_E_INVALID_ARG;
+    if (!o) return fail(c, NPT_E_INVALID_ARG, "null options");
+    if (o->pool_paths > (1u << 30)) return fail(c, NPT_E_INVALID_ARG, "pool_paths > 2^30");
+    c->opt = *o;
+    return ok(c);
+  });
 }
 
 // ===========================================================================
 // environment
 // ===========================================================================
 extern "C" int npt_env_upload(npt_ctx* c, const float* rgb, uint32_t w, uint32_t h, void* stream) {
-  if (!c) return NPT_E_INVALID_ARG;
-  if (!rgb || w == 0 || h == 0 || (uint64_t)w * h > (1ull << 28)) return fail(c, NPT_E_INVALID_ARG, "bad env map");
-  const uint64_t n = (uint64_t)w * h;
-  for (uint64_t i = 0; i < 3 * n; ++i)
-    if (!std::isfinite(rgb[i]) || rgb[i] < 0.0f) return fail(c, NPT_E_NAN_INPUT, "non-finite or negative radiance");
-  int r = need_device(c);
-  if (r) return r;
-  std::vector<float4> m(n);
-  for (uint64_t i = 0; i < n; ++i) m[i] = make_float4(rgb[3 * i], rgb[3 * i + 1], rgb[3 * i + 2], 0.0f);
-  HIP_TRY(c, c->d_env.ensure(n * sizeof(float4)));
-  HIP_TRY(c, hipMemcpyAsync(c->d_env.p, m.data(), n * sizeof(float4), hipMemcpyHostToDevice, (hipStream_t)stream));
-  HIP_TRY(c, hipStreamSynchronize((hipStream_t)stream));
-  c->env_w = w;
-  c->env_h = h;
-  return ok(c);
+  return guarded(c, [&]() -> int {
+    if (!c) return NPT_E_INVALID_ARG;
+    if (!rgb || w == 0 || h == 0 || (uint64_t)w * h > (1ull << 28)) return fail(c, NPT_E_INVALID_ARG, "bad env map");
+    const uint64_t n = (uint64_t)w * h;
+    for (uint64_t i = 0; i < 3 * n; ++i)
+      if (!std::isfinite(rgb[i]) || rgb[i] < 0.0f) return fail(c, NPT_E_NAN_INPUT, "non-finite or negative radiance");
+    int r = need_device(c);
+    if (r) return r;
+    std::vector<float4> m(n);
+    for (uint64_t i = 0; i < n; ++i) m[i] = make_float4(rgb[3 * i], rgb[3 * i + 1], rgb[3 * i + 2], 0.0f);
+    HIP_TRY(c, c->d_env.ensure(n * sizeof(float4)));
+    HIP_TRY(c, hipMemcpyAsync(c->d_env.p, m.data(), n * sizeof(float4), hipMemcpyHostToDevice, (hipStream_t)stream));
+    HIP_TRY(c, hipStreamSynchronize((hipStream_t)stream));
+    c->env_w = w;
+    c->env_h = h;
+    return ok(c);
+  });
 }
 
 extern "C" int npt_set_env_mode(npt_ctx* c, int mode) {
-  if (!c) return NPT_E_INVALID_ARG;
-  if (mode != NPT_ENV_MAP && mode != NPT_ENV_NIF && mode != NPT_ENV_NONE)
-    return fail(c, NPT_E_INVALID_ARG, "unknown env mode");
-  c->env_mode = mode;
-  return ok(c);
+  return guarded(c, [&]() -> int {
+    if (!c) return NPT_E_INVALID_ARG;
+    if (mode != NPT_ENV_MAP && mode != NPT_ENV_NIF && mode != NPT_ENV_NONE)
+      return fail(c, NPT_E_INVALID_ARG, "unknown env mode");
+    c->env_mode = mode;
+    return ok(c);
+  });
 }
 
 // ===========================================================================
@@ -567,92 +610,101 @@ static ColourMatrix colour_matrix(uint32_t colour) {
 }
 
 extern "C" int npt_nif_upload(npt_ctx* c, const npt_nif_desc* desc, const float* params, uint64_t n, void* stream) {
-  if (!c) return NPT_E_INVALID_ARG;
-  if (!nif_desc_ok(desc))
-    return fail(c, NPT_E_UNSUPPORTED,
-                "NIF shape must be n_freq 1..16, hidden 32..1024 (a multiple of 32), layers 1..8, skip 0 or < layers");
-  if (desc->colour > NPT_COLOUR_YCOCG) return fail(c, NPT_E_INVALID_ARG, "unknown NIF colour space");
-  const NifShape shape{(int)desc->hidden, (int)desc->layers, (int)desc->skip, (int)desc->n_freq};
-  const int arch = nif::resident_arch(shape.hidden, shape.layers, shape.skip, shape.n_freq);
-  const bool layered = desc->layered != 0 || arch < 0;
-  if (layered && c->nif_prec == NPT_FP8)
-    return fail(c, NPT_E_UNSUPPORTED,
-                "FP8 inference needs a network shape with an LDS-resident kernel; set another precision first");
-  if (!params || n != (uint64_t)shape_params(shape)) return fail(c, NPT_E_INVALID_ARG, "parameter count mismatch");
-  if (!finite_all(params, n)) return fail(c, NPT_E_NAN_INPUT, "non-finite NIF parameter");
-  int r = need_device(c);
-  if (r) return r;
-  hipStream_t s = (hipStream_t)stream;
-  const size_t bytes = n * sizeof(float);
-  HIP_TRY(c, c->d_master.ensure(bytes));
-  HIP_TRY(c, c->d_adam_m.ensure(bytes));
-  HIP_TRY(c, c->d_adam_v.ensure(bytes));
-  HIP_TRY(c, hipMemcpyAsync(c->d_master.p, params, bytes, hipMemcpyHostToDevice, s));
-  HIP_TRY(c, hipMemsetAsync(c->d_adam_m.p, 0, bytes, s));
-  HIP_TRY(c, hipMemsetAsync(c->d_adam_v.p, 0, bytes, s));
-  c->adam_step = 0;
-  c->have_nif = true;
-  c->nif_cm = colour_matrix(desc->colour);
-  c->nif_shape = shape;
-  c->nif_layered = layered;
-  c->nif_arch = layered ? 0 : arch;
-  r = repack_nif(c, s);
-  if (r) return r;
-  HIP_TRY(c, hipStreamSynchronize(s));
-  return ok(c);
+  return guarded(c, [&]() -> int {
+    if (!c) return NPT_E_INVALID_ARG;
+    if (!nif_desc_ok(desc))
+      return fail(c, NPT_E_UNSUPPORTED,
+                  "NIF shape must be n_freq 1..16, hidden 32..1024 (a multiple of 32), layers 1..8, "
+                  "skip 0 or < layers");
+    if (desc->colour > NPT_COLOUR_YCOCG) return fail(c, NPT_E_INVALID_ARG, "unknown NIF colour space");
+    const NifShape shape{(int)desc->hidden, (int)desc->layers, (int)desc->skip, (int)desc->n_freq};
+    const int arch = nif::resident_arch(shape.hidden, shape.layers, shape.skip, shape.n_freq);
+    const bool layered = desc->layered != 0 || arch < 0;
+    if (layered && c->nif_prec == NPT_FP8)
+      return fail(c, NPT_E_UNSUPPORTED,
+                  "FP8 inference needs a network shape with an LDS-resident kernel; set another precision first");
+    if (!params || n != (uint64_t)shape_params(shape)) return fail(c, NPT_E_INVALID_ARG, "parameter count mismatch");
+    if (!finite_all(params, n)) return fail(c, NPT_E_NAN_INPUT, "non-finite NIF parameter");
+    int r = need_device(c);
+    if (r) return r;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t bytes = n * sizeof(float);
+    HIP_TRY(c, c->d_master.ensure(bytes));
+    HIP_TRY(c, c->d_adam_m.ensure(bytes));
+    HIP_TRY(c, c->d_adam_v.ensure(bytes));
+    HIP_TRY(c, hipMemcpyAsync(c->d_master.p, params, bytes, hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemsetAsync(c->d_adam_m.p, 0, bytes, s));
+    HIP_TRY(c, hipMemsetAsync(c->d_adam_v.p, 0, bytes, s));
+    c->adam_step = 0;
+    c->have_nif = true;
+    c->nif_cm = colour_matrix(desc->colour);
+    c->nif_shape = shape;
+    c->nif_layered = layered;
+    c->nif_arch = layered ? 0 : arch;
+    r = repack_nif(c, s);
+    if (r) return r;
+    HIP_TRY(c, hipStreamSynchronize(s));
+    return ok(c);
+  });
 }
 
 extern "C" int npt_nif_download(npt_ctx* c, float* params, uint64_t n) {
-  if (!c) return NPT_E_INVALID_ARG;
-  if (!c->have_nif) return fail(c, NPT_E_STATE, "no NIF uploaded");
-  if (!params || n != (uint64_t)shape_params(c->nif_shape))
-    return fail(c, NPT_E_INVALID_ARG, "parameter count mismatch");
-  int r = need_device(c);
-  if (r) return r;
-  HIP_TRY(c, hipDeviceSynchronize());
-  HIP_TRY(c, hipMemcpy(params, c->d_master.p, n * sizeof(float), hipMemcpyDeviceToHost));
-  return ok(c);
+  return guarded(c, [&]() -> int {
+    if (!c) return NPT_E_INVALID_ARG;
+    if (!c->have_nif) return fail(c, NPT_E_STATE, "no NIF uploaded");
+    if (!params || n != (uint64_t)shape_params(c->nif_shape))
+      return fail(c, NPT_E_INVALID_ARG, "parameter count mismatch");
+    int r = need_device(c);
+    if (r) return r;
+    HIP_TRY(c, hipDeviceSynchronize());
+    HIP_TRY(c, hipMemcpy(params, c->d_master.p, n * sizeof(float), hipMemcpyDeviceToHost));
+    return ok(c);
+  });
 }
 
 extern "C" int npt_nif_set_precision(npt_ctx* c, int prec) {
-  if (!c) return NPT_E_INVALID_ARG;
-  if (prec < NPT_FP32 || prec > NPT_FP8) return fail(c, NPT_E_INVALID_ARG, "unknown precision");
-  if (prec == NPT_FP8 && (c->host_only || !c->fp8_capable))
-    return fail(c, NPT_E_UNSUPPORTED, "FP8 NIF inference needs gfx950");
-  if (nif_packed_bytes(0, prec) == 0) return fail(c, NPT_E_UNSUPPORTED, "precision not built");
-  if (prec == NPT_FP8 && c->have_nif && c->nif_layered)
-    return fail(c, NPT_E_UNSUPPORTED, "FP8 inference needs a network shape with an LDS-resident kernel");
-  const int old = c->nif_prec;
-  c->nif_prec = prec;
-  if (c->have_nif) {
-    int r = need_device(c);
-    if (r) { c->nif_prec = old; return r; }
-    r = repack_nif(c, nullptr);
-    if (r) { c->nif_prec = old; return r; }
-    HIP_TRY(c, hipStreamSynchronize(nullptr));
-  }
-  return ok(c);
+  return guarded(c, [&]() -> int {
+    if (!c) return NPT_E_INVALID_ARG;
+    if (prec < NPT_FP32 || prec > NPT_FP8) return fail(c, NPT_E_INVALID_ARG, "unknown precision");
+    if (prec == NPT_FP8 && (c->host_only || !c->fp8_capable))
+      return fail(c, NPT_E_UNSUPPORTED, "FP8 NIF inference needs gfx950");
+    if (nif_packed_bytes(0, prec) == 0) return fail(c, NPT_E_UNSUPPORTED, "precision not built");
+    if (prec == NPT_FP8 && c->have_nif && c->nif_layered)
+      return fail(c, NPT_E_UNSUPPORTED, "FP8 inference needs a network shape with an LDS-resident kernel");
+    const int old = c->nif_prec;
+    c->nif_prec = prec;
+    if (c->have_nif) {
+      int r = need_device(c);
+      if (r) { c->nif_prec = old; return r; }
+      r = repack_nif(c, nullptr);
+      if (r) { c->nif_prec = old; return r; }
+      HIP_TRY(c, hipStreamSynchronize(nullptr));
+    }
+    return ok(c);
+  });
 }
 
 extern "C" int npt_nif_get_dequantized(npt_ctx* c, float* params, uint64_t n) {
-  if (!c) return NPT_E_INVALID_ARG;
-  if (!c->have_nif) return fail(c, NPT_E_STATE, "no NIF uploaded");
-  if (!params || n != (uint64_t)shape_params(c->nif_shape))
-    return fail(c, NPT_E_INVALID_ARG, "parameter count mismatch");
-  int r = need_device(c);
-  if (r) return r;
-  DevBuf tmp;
-  HIP_TRY(c, tmp.ensure(n * sizeof(float)));
-  hipError_t e = c->nif_layered
-                    ? launch_params_dequant(c->nif_prec, c->nif_shape, c->d_master.as<float>(), c->d_frags.p,
-                                            tmp.as<float>(), nullptr)
-                    : launch_nif_dequant(c->nif_arch, c->nif_prec, c->d_master.as<float>(), c->d_bias.as<float>(),
-                                         tmp.as<float>(), (int)n, nullptr);
-  if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
-  if (e == hipSuccess) e = hipMemcpy(params, tmp.p, n * sizeof(float), hipMemcpyDeviceToHost);
-  tmp.release();
-  HIP_TRY(c, e);
-  return ok(c);
+  return guarded(c, [&]() -> int {
+    if (!c) return NPT_E_INVALID_ARG;
+    if (!c->have_nif) return fail(c, NPT_E_STATE, "no NIF uploaded");
+    if (!params || n != (uint64_t)shape_params(c->nif_shape))
+      return fail(c, NPT_E_INVALID_ARG, "parameter count mismatch");
+    int r = need_device(c);
+    if (r) return r;
+    DevBuf tmp;
+    HIP_TRY(c, tmp.ensure(n * sizeof(float)));
+    hipError_t e = c->nif_layered
+                      ? launch_params_dequant(c->nif_prec, c->nif_shape, c->d_master.as<float>(), c->d_frags.p,
+                                              tmp.as<float>(), nullptr)
+                      : launch_nif_dequant(c->nif_arch, c->nif_prec, c->d_master.as<float>(), c->d_bias.as<float>(),
+                                           tmp.as<float>(), (int)n, nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (e == hipSuccess) e = hipMemcpy(params, tmp.p, n * sizeof(float), hipMemcpyDeviceToHost);
+    tmp.release();
+    HIP_TRY(c, e);
+    return ok(c);
+  });
 }
 
 static void train_defaults(npt_ctx* c, const npt_train_params* p, TrainConfig& t) {
@@ -695,98 +747,106 @@ static TrainTargets train_targets(npt_ctx* c) {
 }
 
 extern "C" int npt_nif_train(npt_ctx* c, const npt_train_params* p, npt_train_stats* out, void* stream) {
-  if (!c) return NPT_E_INVALID_ARG;
-  TrainConfig t;
-  train_defaults(c, p, t);
-  int r = train_check(c, t);
-  if (r) return r;
-  r = need_device(c);
-  if (r) return r;
-  hipStream_t s = (hipStream_t)stream;
-  const uint32_t steps = (uint32_t)((t.samples + t.batch - 1) / t.batch);
-  TrainTargets tt = train_targets(c);
-  float first = 0.0f, last = 0.0f, ms = 0.0f;
-  HIP_TRY(c, hipEventRecord(c->ev0, s));
-  hipError_t e = train_run(c->train, t, tt, c->adam_step, steps, &first, &last, s);
-  HIP_TRY(c, e);
-  HIP_TRY(c, hipEventRecord(c->ev1, s));
-  HIP_TRY(c, hipEventSynchronize(c->ev1));
-  HIP_TRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
-  c->adam_step += steps;
-  r = repack_nif(c, s);
-  if (r) return r;
-  HIP_TRY(c, hipStreamSynchronize(s));
-  if (out) {
-    out->steps = steps;
-    out->step_total = c->adam_step;
-    out->first_loss = first;
-    out->last_loss = last;
-    out->ms = ms;
-  }
-  return ok(c);
+  return guarded(c, [&]() -> int {
+    if (!c) return NPT_E_INVALID_ARG;
+    TrainConfig t;
+    train_defaults(c, p, t);
+    int r = train_check(c, t);
+    if (r) return r;
+    r = need_device(c);
+    if (r) return r;
+    hipStream_t s = (hipStream_t)stream;
+    const uint32_t steps = (uint32_t)((t.samples + t.batch - 1) / t.batch);
+    TrainTargets tt = train_targets(c);
+    float first = 0.0f, last = 0.0f, ms = 0.0f;
+    HIP_TRY(c, hipEventRecord(c->ev0, s));
+    hipError_t e = train_run(c->train, t, tt, c->adam_step, steps, &first, &last, s);
+    HIP_TRY(c, e);
+    HIP_TRY(c, hipEventRecord(c->ev1, s));
+    HIP_TRY(c, hipEventSynchronize(c->ev1));
+    HIP_TRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    c->adam_step += steps;
+    r = repack_nif(c, s);
+    if (r) return r;
+    HIP_TRY(c, hipStreamSynchronize(s));
+    if (out) {
+      out->steps = steps;
+      out->step_total = c->adam_step;
+      out->first_loss = first;
+      out->last_loss = last;
+      out->ms = ms;
+    }
+    return ok(c);
+  });
 }
 
 extern "C" int npt_nif_train_grad(npt_ctx* c, const npt_train_params* p, uint32_t step, float* d_grad,
                                   float* d_loss, void* stream) {
-  if (!c) return NPT_E_INVALID_ARG;
-  if (!d_grad || !d_loss) return fail(c, NPT_E_INVALID_ARG, "null output");
-  TrainConfig t;
-  train_defaults(c, p, t);
-  int r = train_check(c, t);
-  if (r) return r;
-  r = need_device(c);
-  if (r) return r;
-  HIP_TRY(c, train_gradient(c->train, t, train_targets(c), step, d_grad, d_loss, (hipStream_t)stream));
-  return ok(c);
+  return guarded(c, [&]() -> int {
+    if (!c) return NPT_E_INVALID_ARG;
+    if (!d_grad || !d_loss) return fail(c, NPT_E_INVALID_ARG, "null output");
+    TrainConfig t;
+    train_defaults(c, p, t);
+    int r = train_check(c, t);
+    if (r) return r;
+    r = need_device(c);
+    if (r) return r;
+    HIP_TRY(c, train_gradient(c->train, t, train_targets(c), step, d_grad, d_loss, (hipStream_t)stream));
+    return ok(c);
+  });
 }
 
 extern "C" int npt_nif_eval_grid(npt_ctx* c, uint32_t gw, uint32_t gh, float* out2, void* stream) {
-  if (!c) return NPT_E_INVALID_ARG;
-  if (!out2 || gw == 0 || gh == 0 || (uint64_t)gw * gh > (1ull << 26)) return fail(c, NPT_E_INVALID_ARG, "bad grid");
-  if (!c->have_nif) return fail(c, NPT_E_STATE, "no NIF uploaded");
-  if (!c->env_w) return fail(c, NPT_E_NO_ENV, "no environment map");
-  int r = need_device(c);
-  if (r) return r;
-  hipStream_t s = (hipStream_t)stream;
-  float res[2] = {0, 0};
-  if (c->nif_layered)
-    HIP_TRY(c, grid_eval(c->train, c->nif_prec, 0, c->d_frags.p, c->d_master.as<float>(), c->nif_cm,
-                         train_targets(c), gw, gh, c->num_cus, res, s, &c->layered, &c->nif_shape));
-  else
-    HIP_TRY(c, grid_eval(c->train, c->nif_prec, c->nif_arch, c->d_frags.p, c->d_bias.as<float>(), c->nif_cm,
-                         train_targets(c), gw, gh, c->num_cus, res, s));
-  out2[0] = res[0];
-  out2[1] = res[1];
-  return ok(c);
+  return guarded(c, [&]() -> int {
+    if (!c) return NPT_E_INVALID_ARG;
+    if (!out2 || gw == 0 || gh == 0 || (uint64_t)gw * gh > (1ull << 26)) return fail(c, NPT_E_INVALID_ARG, "bad grid");
+    if (!c->have_nif) return fail(c, NPT_E_STATE, "no NIF uploaded");
+    if (!c->env_w) return fail(c, NPT_E_NO_ENV, "no environment map");
+    int r = need_device(c);
+    if (r) return r;
+    hipStream_t s = (hipStream_t)stream;
+    float res[2] = {0, 0};
+    if (c->nif_layered)
+      HIP_TRY(c, grid_eval(c->train, c->nif_prec, 0, c->d_frags.p, c->d_master.as<float>(), c->nif_cm,
+                           train_targets(c), gw, gh, c->num_cus, res, s, &c->layered, &c->nif_shape));
+    else
+      HIP_TRY(c, grid_eval(c->train, c->nif_prec, c->nif_arch, c->d_frags.p, c->d_bias.as<float>(), c->nif_cm,
+                           train_targets(c), gw, gh, c->num_cus, res, s));
+    out2[0] = res[0];
+    out2[1] = res[1];
+    return ok(c);
+  });
 }
 
 extern "C" int npt_env_query(npt_ctx* c, int mode, const float* d_dirs, uint64_t n, float* d_rgb, void* stream) {
-  if (!c) return NPT_E_INVALID_ARG;
-  if (!d_dirs || !d_rgb || n == 0) return fail(c, NPT_E_INVALID_ARG, "bad query buffers");
-  int r = need_device(c);
-  if (r) return r;
-  hipStream_t s = (hipStream_t)stream;
-  if (mode == NPT_ENV_MAP) {
-    if (!c->env_w) return fail(c, NPT_E_NO_ENV, "no environment map");
-    HIP_TRY(c, launch_env_query_map(c->d_env.as<float4>(), (int)c->env_w, (int)c->env_h, d_dirs, n, d_rgb, s));
-  } else if (mode == NPT_ENV_NIF) {
-    if (!c->have_nif) return fail(c, NPT_E_NO_ENV, "no NIF uploaded");
-    if (c->nif_layered) {
-      LayeredIO io{};
-      io.source = kLayeredDirs;
-      io.dirs = d_dirs;
-      io.out = d_rgb;
-      io.n = n;
-      HIP_TRY(c, nif_layered(c->layered, c->nif_prec, c->nif_shape, c->d_frags.p, c->d_master.as<float>(), c->nif_cm,
-                             io, s));
+  return guarded(c, [&]() -> int {
+    if (!c) return NPT_E_INVALID_ARG;
+    if (!d_dirs || !d_rgb || n == 0) return fail(c, NPT_E_INVALID_ARG, "bad query buffers");
+    int r = need_device(c);
+    if (r) return r;
+    hipStream_t s = (hipStream_t)stream;
+    if (mode == NPT_ENV_MAP) {
+      if (!c->env_w) return fail(c, NPT_E_NO_ENV, "no environment map");
+      HIP_TRY(c, launch_env_query_map(c->d_env.as<float4>(), (int)c->env_w, (int)c->env_h, d_dirs, n, d_rgb, s));
+    } else if (mode == NPT_ENV_NIF) {
+      if (!c->have_nif) return fail(c, NPT_E_NO_ENV, "no NIF uploaded");
+      if (c->nif_layered) {
+        LayeredIO io{};
+        io.source = kLayeredDirs;
+        io.dirs = d_dirs;
+        io.out = d_rgb;
+        io.n = n;
+        HIP_TRY(c, nif_layered(c->layered, c->nif_prec, c->nif_shape, c->d_frags.p, c->d_master.as<float>(), c->nif_cm,
+                               io, s));
+      } else {
+        HIP_TRY(c, launch_nif_dirs(c->nif_arch, c->nif_prec, c->d_frags.p, c->d_bias.as<float>(), c->nif_cm,
+                                   d_dirs, n, d_rgb, c->num_cus, s));
+      }
     } else {
-      HIP_TRY(c, launch_nif_dirs(c->nif_arch, c->nif_prec, c->d_frags.p, c->d_bias.as<float>(), c->nif_cm, d_dirs, n, d_rgb,
-                                 c->num_cus, s));
+      return fail(c, NPT_E_INVALID_ARG, "unknown env mode");
     }
-  } else {
-    return fail(c, NPT_E_INVALID_ARG, "unknown env mode");
-  }
-  return ok(c);
+    return ok(c);
+  });
 }
 
 // ===========================================================================
@@ -804,203 +864,209 @@ static int render_checks(npt_ctx* c, uint32_t W, uint32_t H) {
 
 extern "C" int npt_render(npt_ctx* c, uint32_t W, uint32_t H, uint32_t spp, uint32_t max_depth, uint64_t seed,
                           float* d_out, void* stream) {
-  if (!c) return NPT_E_INVALID_ARG;
-  if (!d_out) return fail(c, NPT_E_INVALID_ARG, "null output buffer");
-  if (spp == 0 || max_depth == 0 || max_depth > NPT_MAX_DEPTH)
-    return fail(c, NPT_E_INVALID_ARG, "spp must be > 0 and max_depth in 1..64");
-  if (W == 0 || H == 0 || (uint64_t)W * H * spp >= (1ull << 40))
-    return fail(c, NPT_E_INVALID_ARG, "W*H*spp must be in (0, 2^40)");
-  if (c->host_only) return fail(c, NPT_E_NO_DEVICE, "host-only context cannot render");
-  int r = render_checks(c, W, H);
-  if (r) return r;
-  if (c->env_mode == NPT_ENV_MAP && !c->env_w) return fail(c, NPT_E_NO_ENV, "env mode MAP without a map");
-  if (c->env_mode == NPT_ENV_NIF && !c->have_nif) return fail(c, NPT_E_NO_ENV, "env mode NIF without weights");
-  r = need_device(c);
-  if (r) return r;
-  hipStream_t s = (hipStream_t)stream;
+  return guarded(c, [&]() -> int {
+    if (!c) return NPT_E_INVALID_ARG;
+    if (!d_out) return fail(c, NPT_E_INVALID_ARG, "null output buffer");
+    if (spp == 0 || max_depth == 0 || max_depth > NPT_MAX_DEPTH)
+      return fail(c, NPT_E_INVALID_ARG, "spp must be > 0 and max_depth in 1..64");
+    if (W == 0 || H == 0 || (uint64_t)W * H * spp >= (1ull << 40))
+      return fail(c, NPT_E_INVALID_ARG, "W*H*spp must be in (0, 2^40)");
+    if (c->host_only) return fail(c, NPT_E_NO_DEVICE, "host-only context cannot render");
+    int r = render_checks(c, W, H);
+    if (r) return r;
+    if (c->env_mode == NPT_ENV_MAP && !c->env_w) return fail(c, NPT_E_NO_ENV, "env mode MAP without a map");
+    if (c->env_mode == NPT_ENV_NIF && !c->have_nif) return fail(c, NPT_E_NO_ENV, "env mode NIF without weights");
+    r = need_device(c);
+    if (r) return r;
+    hipStream_t s = (hipStream_t)stream;
 
-  const uint64_t pixels = (uint64_t)W * H;
-  // default pool: 2^26 paths in flight (a whole 1080p x 32 spp frame per
-  // pass; 160 B of queues per path = 10.7 GB of the 288 GB of HBM)
-  const uint64_t pool = c->opt.pool_paths ? c->opt.pool_paths : (1ull << 26);
-  uint64_t sp = c->opt.samples_per_pass ? c->opt.samples_per_pass : std::max<uint64_t>(1, pool / pixels);
-  sp = std::min<uint64_t>(sp, spp);
-  while (sp > 1 && pixels * sp >= (1ull << 31)) --sp;
-  const uint64_t slots = pixels * sp;
-  const size_t qb = slots * sizeof(float4);
-  DevBuf* qbufs[] = {&c->qa_o, &c->qa_d, &c->qa_b, &c->qb_o, &c->qb_d, &c->qb_b, &c->env_d, &c->env_b, &c->d_L,
-                     &c->d_hits};
-  for (DevBuf* b : qbufs) HIP_TRY(c, b->ensure(qb));
-  HIP_TRY(c, c->d_accum.ensure(pixels * sizeof(float4)));
-  HIP_TRY(c, c->d_cnt.ensure(kCntWords * sizeof(uint32_t)));
-  HIP_TRY(c, c->d_stats.ensure(4 * NPT_MAX_DEPTH * sizeof(unsigned long long)));
-  HIP_TRY(c, launch_stats_clear(c->d_stats.as<unsigned long long>(), s));
-  unsigned long long* visit_cnt = c->opt.count_visits ? c->d_stats.as<unsigned long long>() + 2 * NPT_MAX_DEPTH
-                                                      : nullptr;
-  const bool timing = c->opt.kernel_timing != 0;
-  c->trace_events.clear();
-  c->shade_events.clear();
-  c->env_events.clear();
-  c->env_depths.clear();
-  auto event_pair = [&](std::vector<hipEvent_t>& v) -> hipError_t {
-    // events are pooled per context and reused across renders
-    const size_t need = c->trace_events.size() + c->shade_events.size() + c->env_events.size() + 2;
-    while (c->event_pool.size() < need) {
-      hipEvent_t e;
-      hipError_t err = hipEventCreate(&e);
-      if (err != hipSuccess) return err;
-      c->event_pool.push_back(e);
-    }
-    v.push_back(c->event_pool[need - 2]);
-    v.push_back(c->event_pool[need - 1]);
-    return hipSuccess;
-  };
-
-  const SceneView sv = scene_view(c);
-  const CameraView cam = camera_view(c->camera, W, H);
-  RayQueue qa{c->qa_o.as<float4>(), c->qa_d.as<float4>(), c->qa_b.as<float4>()};
-  RayQueue qbq{c->qb_o.as<float4>(), c->qb_d.as<float4>(), c->qb_b.as<float4>()};
-  EnvQueue eq{c->env_d.as<float4>(), c->env_b.as<float4>()};
-  float4* L = c->d_L.as<float4>();
-  uint32_t* cnt = c->d_cnt.as<uint32_t>();
-
-  HIP_TRY(c, hipEventRecord(c->ev0, s));
-  uint32_t passes = 0;
-  for (uint64_t s0 = 0; s0 < spp; s0 += sp) {
-    PassView pv;
-    pv.width = W;
-    pv.height = H;
-    pv.pixels = (uint32_t)pixels;
-    pv.sample0 = (uint32_t)s0;
-    pv.samples = (uint32_t)std::min<uint64_t>(sp, spp - s0);
-    pv.max_depth = max_depth;
-    pv.rr_start = c->opt.rr_start ? c->opt.rr_start : 3;
-    pv.key0 = (uint32_t)seed;
-    pv.key1 = (uint32_t)(seed >> 32);
-    const uint64_t n = pixels * pv.samples;
-    HIP_TRY(c, launch_pass_init(cnt, (uint32_t)n, s));
-    HIP_TRY(c, launch_generate(cam, pv, qa, L, s));
-    RayQueue in = qa, out = qbq;
-    for (uint32_t k = 1; k <= max_depth; ++k) {
-      if (timing) {
-        HIP_TRY(c, event_pair(c->trace_events));
-        HIP_TRY(c, hipEventRecord(c->trace_events[c->trace_events.size() - 2], s));
+    const uint64_t pixels = (uint64_t)W * H;
+    // default pool: 2^26 paths in flight (a whole 1080p x 32 spp frame per
+    // pass; 160 B of queues per path = 10.7 GB of the 288 GB of HBM)
+    const uint64_t pool = c->opt.pool_paths ? c->opt.pool_paths : (1ull << 26);
+    uint64_t sp = c->opt.samples_per_pass ? c->opt.samples_per_pass : std::max<uint64_t>(1, pool / pixels);
+    sp = std::min<uint64_t>(sp, spp);
+    while (sp > 1 && pixels * sp >= (1ull << 31)) --sp;
+    const uint64_t slots = pixels * sp;
+    const size_t qb = slots * sizeof(float4);
+    DevBuf* qbufs[] = {&c->qa_o, &c->qa_d, &c->qa_b, &c->qb_o, &c->qb_d, &c->qb_b, &c->env_d, &c->env_b, &c->d_L,
+                       &c->d_hits};
+    for (DevBuf* b : qbufs) HIP_TRY(c, b->ensure(qb));
+    HIP_TRY(c, c->d_accum.ensure(pixels * sizeof(float4)));
+    HIP_TRY(c, c->d_cnt.ensure(kCntWords * sizeof(uint32_t)));
+    HIP_TRY(c, c->d_stats.ensure(4 * NPT_MAX_DEPTH * sizeof(unsigned long long)));
+    HIP_TRY(c, launch_stats_clear(c->d_stats.as<unsigned long long>(), s));
+    unsigned long long* visit_cnt = c->opt.count_visits ? c->d_stats.as<unsigned long long>() + 2 * NPT_MAX_DEPTH
+                                                        : nullptr;
+    const bool timing = c->opt.kernel_timing != 0;
+    c->trace_events.clear();
+    c->shade_events.clear();
+    c->env_events.clear();
+    c->env_depths.clear();
+    auto event_pair = [&](std::vector<hipEvent_t>& v) -> hipError_t {
+      // events are pooled per context and reused across renders
+      const size_t need = c->trace_events.size() + c->shade_events.size() + c->env_events.size() + 2;
+      while (c->event_pool.size() < need) {
+        hipEvent_t e;
+        hipError_t err = hipEventCreate(&e);
+        if (err != hipSuccess) return err;
+        c->event_pool.push_back(e);
       }
-      HIP_TRY(c, launch_extend(c->stack_depth, sv, k, n, in, c->d_hits.as<float4>(), cnt, visit_cnt, c->num_cus, s));
-      if (timing) {
-        HIP_TRY(c, hipEventRecord(c->trace_events.back(), s));
-        HIP_TRY(c, event_pair(c->shade_events));
-        HIP_TRY(c, hipEventRecord(c->shade_events[c->shade_events.size() - 2], s));
-      }
-      HIP_TRY(c, launch_shade(sv, pv, k, n, in, c->d_hits.as<float4>(), out, eq, L, cnt, c->num_cus, s));
-      if (timing) HIP_TRY(c, hipEventRecord(c->shade_events.back(), s));
-      if (c->env_mode != NPT_ENV_NONE) {  // NONE: escaped paths carry no radiance
+      v.push_back(c->event_pool[need - 2]);
+      v.push_back(c->event_pool[need - 1]);
+      return hipSuccess;
+    };
+
+    const SceneView sv = scene_view(c);
+    const CameraView cam = camera_view(c->camera, W, H);
+    RayQueue qa{c->qa_o.as<float4>(), c->qa_d.as<float4>(), c->qa_b.as<float4>()};
+    RayQueue qbq{c->qb_o.as<float4>(), c->qb_d.as<float4>(), c->qb_b.as<float4>()};
+    EnvQueue eq{c->env_d.as<float4>(), c->env_b.as<float4>()};
+    float4* L = c->d_L.as<float4>();
+    uint32_t* cnt = c->d_cnt.as<uint32_t>();
+
+    HIP_TRY(c, hipEventRecord(c->ev0, s));
+    uint32_t passes = 0;
+    for (uint64_t s0 = 0; s0 < spp; s0 += sp) {
+      PassView pv;
+      pv.width = W;
+      pv.height = H;
+      pv.pixels = (uint32_t)pixels;
+      pv.sample0 = (uint32_t)s0;
+      pv.samples = (uint32_t)std::min<uint64_t>(sp, spp - s0);
+      pv.max_depth = max_depth;
+      pv.rr_start = c->opt.rr_start ? c->opt.rr_start : 3;
+      pv.key0 = (uint32_t)seed;
+      pv.key1 = (uint32_t)(seed >> 32);
+      const uint64_t n = pixels * pv.samples;
+      HIP_TRY(c, launch_pass_init(cnt, (uint32_t)n, s));
+      HIP_TRY(c, launch_generate(cam, pv, qa, L, s));
+      RayQueue in = qa, out = qbq;
+      for (uint32_t k = 1; k <= max_depth; ++k) {
         if (timing) {
-          HIP_TRY(c, event_pair(c->env_events));
-          c->env_depths.push_back(k);
-          HIP_TRY(c, hipEventRecord(c->env_events[c->env_events.size() - 2], s));
+          HIP_TRY(c, event_pair(c->trace_events));
+          HIP_TRY(c, hipEventRecord(c->trace_events[c->trace_events.size() - 2], s));
         }
-        if (c->env_mode == NPT_ENV_MAP) {
-          HIP_TRY(c, launch_env_lookup(c->d_env.as<float4>(), (int)c->env_w, (int)c->env_h, eq, L, cnt, k, n,
-                                       c->num_cus, s));
-        } else if (c->nif_layered) {
-          LayeredIO io{};
-          io.source = kLayeredQueue;
-          io.env = eq;
-          io.L = L;
-          io.cnt = cnt;
-          io.depth = k;
-          HIP_TRY(c, nif_layered(c->layered, c->nif_prec, c->nif_shape, c->d_frags.p, c->d_master.as<float>(),
-                                 c->nif_cm, io, s));
-        } else {
-          HIP_TRY(c, launch_nif_queue(c->nif_arch, c->nif_prec, c->d_frags.p, c->d_bias.as<float>(), c->nif_cm, eq, L,
-                                      cnt, k, n, c->num_cus, s));
+        HIP_TRY(c, launch_extend(c->stack_depth, sv, k, n, in, c->d_hits.as<float4>(), cnt, visit_cnt, c->num_cus, s));
+        if (timing) {
+          HIP_TRY(c, hipEventRecord(c->trace_events.back(), s));
+          HIP_TRY(c, event_pair(c->shade_events));
+          HIP_TRY(c, hipEventRecord(c->shade_events[c->shade_events.size() - 2], s));
         }
-        if (timing) HIP_TRY(c, hipEventRecord(c->env_events.back(), s));
+        HIP_TRY(c, launch_shade(sv, pv, k, n, in, c->d_hits.as<float4>(), out, eq, L, cnt, c->num_cus, s));
+        if (timing) HIP_TRY(c, hipEventRecord(c->shade_events.back(), s));
+        if (c->env_mode != NPT_ENV_NONE) {  // NONE: escaped paths carry no radiance
+          if (timing) {
+            HIP_TRY(c, event_pair(c->env_events));
+            c->env_depths.push_back(k);
+            HIP_TRY(c, hipEventRecord(c->env_events[c->env_events.size() - 2], s));
+          }
+          if (c->env_mode == NPT_ENV_MAP) {
+            HIP_TRY(c, launch_env_lookup(c->d_env.as<float4>(), (int)c->env_w, (int)c->env_h, eq, L, cnt, k, n,
+                                         c->num_cus, s));
+          } else if (c->nif_layered) {
+            LayeredIO io{};
+            io.source = kLayeredQueue;
+            io.env = eq;
+            io.L = L;
+            io.cnt = cnt;
+            io.depth = k;
+            HIP_TRY(c, nif_layered(c->layered, c->nif_prec, c->nif_shape, c->d_frags.p, c->d_master.as<float>(),
+                                   c->nif_cm, io, s));
+          } else {
+            HIP_TRY(c, launch_nif_queue(c->nif_arch, c->nif_prec, c->d_frags.p, c->d_bias.as<float>(), c->nif_cm, eq, L,
+                                        cnt, k, n, c->num_cus, s));
+          }
+          if (timing) HIP_TRY(c, hipEventRecord(c->env_events.back(), s));
+        }
+        std::swap(in, out);
       }
-      std::swap(in, out);
+      HIP_TRY(c, launch_accumulate(L, c->d_accum.as<float4>(), pv, s0 == 0, s));
+      HIP_TRY(c, launch_stats_add(cnt, c->d_stats.as<unsigned long long>(), s));
+      ++passes;
     }
-    HIP_TRY(c, launch_accumulate(L, c->d_accum.as<float4>(), pv, s0 == 0, s));
-    HIP_TRY(c, launch_stats_add(cnt, c->d_stats.as<unsigned long long>(), s));
-    ++passes;
-  }
-  HIP_TRY(c, launch_finalize(c->d_accum.as<float4>(), d_out, (uint32_t)pixels, 1.0f / (float)spp, s));
-  HIP_TRY(c, hipEventRecord(c->ev1, s));
-  c->timing_pending = true;
-  c->stats = npt_stats{};
-  c->stats.paths = pixels * spp;
-  c->stats.passes = passes;
-  c->stats.samples_per_pass = (uint32_t)sp;
-  return ok(c);
+    HIP_TRY(c, launch_finalize(c->d_accum.as<float4>(), d_out, (uint32_t)pixels, 1.0f / (float)spp, s));
+    HIP_TRY(c, hipEventRecord(c->ev1, s));
+    c->timing_pending = true;
+    c->stats = npt_stats{};
+    c->stats.paths = pixels * spp;
+    c->stats.passes = passes;
+    c->stats.samples_per_pass = (uint32_t)sp;
+    return ok(c);
+  });
 }
 
 extern "C" int npt_trace_primary(npt_ctx* c, uint32_t W, uint32_t H, uint32_t sample, uint64_t seed, uint32_t* d_prim,
                                  uint32_t* d_inst, float* d_t, float* d_normal, void* stream) {
-  if (!c) return NPT_E_INVALID_ARG;
-  if (c->host_only) return fail(c, NPT_E_NO_DEVICE, "host-only context");
-  int r = render_checks(c, W, H);
-  if (r) return r;
-  r = need_device(c);
-  if (r) return r;
-  PassView pv{};
-  pv.width = W;
-  pv.height = H;
-  pv.pixels = W * H;
-  pv.sample0 = sample;
-  pv.samples = 1;
-  pv.key0 = (uint32_t)seed;
-  pv.key1 = (uint32_t)(seed >> 32);
-  HIP_TRY(c, launch_trace_primary(c->stack_depth, scene_view(c), camera_view(c->camera, W, H), pv, d_prim, d_inst,
-                                  d_t, d_normal, c->num_cus, (hipStream_t)stream));
-  return ok(c);
+  return guarded(c, [&]() -> int {
+    if (!c) return NPT_E_INVALID_ARG;
+    if (c->host_only) return fail(c, NPT_E_NO_DEVICE, "host-only context");
+    int r = render_checks(c, W, H);
+    if (r) return r;
+    r = need_device(c);
+    if (r) return r;
+    PassView pv{};
+    pv.width = W;
+    pv.height = H;
+    pv.pixels = W * H;
+    pv.sample0 = sample;
+    pv.samples = 1;
+    pv.key0 = (uint32_t)seed;
+    pv.key1 = (uint32_t)(seed >> 32);
+    HIP_TRY(c, launch_trace_primary(c->stack_depth, scene_view(c), camera_view(c->camera, W, H), pv, d_prim, d_inst,
+                                    d_t, d_normal, c->num_cus, (hipStream_t)stream));
+    return ok(c);
+  });
 }
 
 extern "C" int npt_get_stats(npt_ctx* c, npt_stats* out) {
-  if (!c) return NPT_E_INVALID_ARG;
-  if (!out) return fail(c, NPT_E_INVALID_ARG, "null stats");
-  if (c->timing_pending) {
-    int r = need_device(c);
-    if (r) return r;
-    HIP_TRY(c, hipEventSynchronize(c->ev1));
-    float ms = 0;
-    HIP_TRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
-    c->stats.ms_total = ms;
-    std::vector<unsigned long long> h(4 * NPT_MAX_DEPTH);
-    HIP_TRY(c, hipMemcpy(h.data(), c->d_stats.p, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
-    c->stats.env_queries = 0;
-    for (int k = 0; k < NPT_MAX_DEPTH; ++k) {
-      c->stats.rays[k] = h[k];
-      c->stats.escaped[k] = h[NPT_MAX_DEPTH + k];
-      c->stats.env_queries += h[NPT_MAX_DEPTH + k];
-      c->stats.node_visits[k] = h[2 * NPT_MAX_DEPTH + k];
-      c->stats.prim_tests[k] = h[3 * NPT_MAX_DEPTH + k];
+  return guarded(c, [&]() -> int {
+    if (!c) return NPT_E_INVALID_ARG;
+    if (!out) return fail(c, NPT_E_INVALID_ARG, "null stats");
+    if (c->timing_pending) {
+      int r = need_device(c);
+      if (r) return r;
+      HIP_TRY(c, hipEventSynchronize(c->ev1));
+      float ms = 0;
+      HIP_TRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+      c->stats.ms_total = ms;
+      std::vector<unsigned long long> h(4 * NPT_MAX_DEPTH);
+      HIP_TRY(c, hipMemcpy(h.data(), c->d_stats.p, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+      c->stats.env_queries = 0;
+      for (int k = 0; k < NPT_MAX_DEPTH; ++k) {
+        c->stats.rays[k] = h[k];
+        c->stats.escaped[k] = h[NPT_MAX_DEPTH + k];
+        c->stats.env_queries += h[NPT_MAX_DEPTH + k];
+        c->stats.node_visits[k] = h[2 * NPT_MAX_DEPTH + k];
+        c->stats.prim_tests[k] = h[3 * NPT_MAX_DEPTH + k];
+      }
+      float sum = 0.0f;
+      for (size_t i = 0; i + 1 < c->trace_events.size(); i += 2) {
+        HIP_TRY(c, hipEventElapsedTime(&ms, c->trace_events[i], c->trace_events[i + 1]));
+        sum += ms;
+      }
+      c->stats.ms_trace = sum;
+      c->stats.trace_launches = (uint32_t)(c->trace_events.size() / 2);
+      sum = 0.0f;
+      for (size_t i = 0; i + 1 < c->shade_events.size(); i += 2) {
+        HIP_TRY(c, hipEventElapsedTime(&ms, c->shade_events[i], c->shade_events[i + 1]));
+        sum += ms;
+      }
+      c->stats.ms_shade = sum;
+      c->stats.shade_launches = (uint32_t)(c->shade_events.size() / 2);
+      sum = 0.0f;
+      for (int k = 0; k < NPT_MAX_DEPTH; ++k) c->stats.ms_env_depth[k] = 0.0f;
+      for (size_t i = 0; i + 1 < c->env_events.size(); i += 2) {
+        HIP_TRY(c, hipEventElapsedTime(&ms, c->env_events[i], c->env_events[i + 1]));
+        sum += ms;
+        const uint32_t k = c->env_depths[i / 2];
+        if (k >= 1 && k <= NPT_MAX_DEPTH) c->stats.ms_env_depth[k - 1] += ms;
+      }
+      c->stats.ms_env = sum;
+      c->stats.env_launches = (uint32_t)(c->env_events.size() / 2);
+      c->timing_pending = false;
     }
-    float sum = 0.0f;
-    for (size_t i = 0; i + 1 < c->trace_events.size(); i += 2) {
-      HIP_TRY(c, hipEventElapsedTime(&ms, c->trace_events[i], c->trace_events[i + 1]));
-      sum += ms;
-    }
-    c->stats.ms_trace = sum;
-    c->stats.trace_launches = (uint32_t)(c->trace_events.size() / 2);
-    sum = 0.0f;
-    for (size_t i = 0; i + 1 < c->shade_events.size(); i += 2) {
-      HIP_TRY(c, hipEventElapsedTime(&ms, c->shade_events[i], c->shade_events[i + 1]));
-      sum += ms;
-    }
-    c->stats.ms_shade = sum;
-    c->stats.shade_launches = (uint32_t)(c->shade_events.size() / 2);
-    sum = 0.0f;
-    for (int k = 0; k < NPT_MAX_DEPTH; ++k) c->stats.ms_env_depth[k] = 0.0f;
-    for (size_t i = 0; i + 1 < c->env_events.size(); i += 2) {
-      HIP_TRY(c, hipEventElapsedTime(&ms, c->env_events[i], c->env_events[i + 1]));
-      sum += ms;
-      const uint32_t k = c->env_depths[i / 2];
-      if (k >= 1 && k <= NPT_MAX_DEPTH) c->stats.ms_env_depth[k - 1] += ms;
-    }
-    c->stats.ms_env = sum;
-    c->stats.env_launches = (uint32_t)(c->env_events.size() / 2);
-    c->timing_pending = false;
-  }
-  *out = c->stats;
-  return ok(c);
+    *out = c->stats;
+    return ok(c);
+  });
 }
