@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <deque>
+#include <exception>
 #include <thread>
 
 #include "npt_shared.h"
@@ -240,12 +241,23 @@ struct Builder {
       sub.bins = bins;
       sub.max_leaf = max_leaf;
       sub.workers = workers;
+      std::exception_ptr failed;  // an exception of the other thread, raised here after the join
       std::thread t([&] {
-        sub.build(mid, rc, depth + 1);
+        try {
+          sub.build(mid, rc, depth + 1);
+        } catch (...) {
+          failed = std::current_exception();
+        }
         workers->fetch_add(1);  // free for other subtrees as soon as this one is done
       });
-      l = build(first, mid - first, depth + 1);
+      try {
+        l = build(first, mid - first, depth + 1);
+      } catch (...) {
+        t.join();
+        throw;
+      }
       t.join();
+      if (failed) std::rethrow_exception(failed);
       r = splice(sub.nodes);
     } else {
       if (workers && rc >= kParallelPrims) workers->fetch_add(1);  // the claim above failed: give it back
