@@ -513,21 +513,34 @@ __global__ __launch_bounds__(320) void k_chunk_sums(const float* sub, int width,
 }
 
 // gradient = (sum of the chunk partials) * scale, in a fixed order: wave q
-// of a workgroup sums chunks q, q + 4, ... of 64 parameters, then the four
-// sums are added in wave order; loss of the step
-__global__ __launch_bounds__(256) void k_reduce_grad(const float* partial, int splits, float scale, float* grad,
-                                                    const float* loss_part, int nloss, float loss_scale,
-                                                    float* loss_out, int64_t np) {
-  __shared__ float part[4][64];
+// of a workgroup sums chunks q, q + 8, ... of 64 parameters into four
+// interleaved running sums (chunk q + 8i into sum i mod 4: independent loads
+// in flight), then the eight waves' sums are added in wave order; loss of the
+// step
+constexpr int kReduceWaves = 8;
+__global__ __launch_bounds__(64 * kReduceWaves) void k_reduce_grad(const float* partial, int splits, float scale,
+                                                                  float* grad, const float* loss_part, int nloss,
+                                                                  float loss_scale, float* loss_out, int64_t np) {
+  __shared__ float part[kReduceWaves][64];
   const int q = threadIdx.x >> 6, jj = threadIdx.x & 63;
   for (int64_t j0 = (int64_t)blockIdx.x * 64; j0 < np; j0 += (int64_t)gridDim.x * 64) {
     const int64_t j = j0 + jj;
-    float s = 0.0f;
+    constexpr int W = kReduceWaves;
+    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
     if (j < np)
-      for (int k = q; k < splits; k += 4) s += partial[(size_t)k * np + j];
-    part[q][jj] = s;
+      for (int k = q; k < splits; k += 4 * W) {
+        s0 += partial[(size_t)k * np + j];
+        if (k + W < splits) s1 += partial[(size_t)(k + W) * np + j];
+        if (k + 2 * W < splits) s2 += partial[(size_t)(k + 2 * W) * np + j];
+        if (k + 3 * W < splits) s3 += partial[(size_t)(k + 3 * W) * np + j];
+      }
+    part[q][jj] = (s0 + s1) + (s2 + s3);
     __syncthreads();
-    if (q == 0 && j < np) grad[j] = (((part[0][jj] + part[1][jj]) + part[2][jj]) + part[3][jj]) * scale;
+    if (q == 0 && j < np) {
+      float s = 0.0f;
+      for (int w = 0; w < kReduceWaves; ++w) s += part[w][jj];
+      grad[j] = s * scale;
+    }
     __syncthreads();
   }
   if (blockIdx.x == 0 && threadIdx.x == 0 && loss_out) {
@@ -806,8 +819,8 @@ static hipError_t step_gradient(TrainScratch& s, const TrainConfig& c, const Tra
     cur ^= 1;
   }
   const float scale = 1.0f / (3.0f * (float)B * c.loss_scale);
-  hipLaunchKernelGGL(k_reduce_grad, dim3((int)std::min<int64_t>(4096, (np + 63) / 64)), dim3(256), 0, st, s.partial,
-                     splits, scale, grad_out, s.loss_part, nblk, 1.0f / (3.0f * (float)B), loss_out, np);
+  hipLaunchKernelGGL(k_reduce_grad, dim3((int)std::min<int64_t>(4096, (np + 63) / 64)), dim3(64 * kReduceWaves), 0, st,
+                     s.partial, splits, scale, grad_out, s.loss_part, nblk, 1.0f / (3.0f * (float)B), loss_out, np);
   return hipGetLastError();
 }
 
