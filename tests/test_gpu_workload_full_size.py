@@ -4,7 +4,9 @@ scene (2048^2-vertex terrain plus 256 instanced displaced icospheres) at
 binary16-extent nodes and leaf size 2, lit by the HDR-NIF trained on the
 device and run with FP8 operands.  The GPU renders the whole frame in the
 benchmark's launch configuration; the oracle traces two full rows (3,840
-pixels, 245,760 path samples) with the same dequantised weights."""
+pixels, 245,760 path samples) with the same dequantised weights.  Likewise
+the spheres scene of the model-size study lit by the paper's own network on
+its LDS-resident FP8 kernel."""
 import numpy as np
 import pytest
 
@@ -48,3 +50,43 @@ def test_large_bvh_fp8_nif_full_size_rows_match_oracle():
     assert np.all(np.isfinite(g)) and np.all(g >= 0)
     assert o.mean() > 0.05  # the rows are lit: the comparison is not of zeros
     assert r <= 2e-2  # FP8 operands, as for the query and render tests
+
+
+@pytest.mark.timeout(600)
+def test_spheres_paper_network_fp8_full_size_rows_match_oracle():
+    # the spheres scene of the model-size study (1024x1024, 16 spp, depth 8)
+    # lit by the paper's network (10 frequencies, H128 L5, skip-concat at
+    # layer 2) trained on the device and run in FP8 on its LDS-resident kernel
+    W, H, spp, depth, seed = 1024, 1024, 16, 8, 1
+    hidden, layers, skip, nf = 128, 5, 2, 10
+    scene = synth.scene_for(2)
+    ctx = npt.npt_create(0)
+    try:
+        npt.npt_load_scene(ctx, scene, max_leaf=2, lds_levels=0, width=4)
+        npt.npt_env_upload(ctx, synth.env_map())
+        npt.npt_nif_upload(ctx, synth.nif_init(3, nf, hidden, layers, skip), n_freq=nf, hidden=hidden,
+                           layers=layers, skip=skip)
+        npt.npt_nif_train(ctx, npt.train_params(batch=65536, samples=1 << 22, seed=1, grad_prec=npt.FP16))
+        npt.npt_nif_set_precision(ctx, npt.FP8)
+        n = npt.nif_param_count(hidden, layers, skip, nf)
+        trained = npt.npt_nif_download(ctx, n)
+        dq = npt.npt_nif_get_dequantized(ctx, n)
+        npt.npt_set_env_mode(ctx, npt.ENV_NIF)
+        npt.npt_set_render_options(ctx, rr_start=3)
+        g = gpu_render(ctx, W, H, spp, depth, seed)
+    finally:
+        npt.npt_destroy(ctx)
+    shape = O.nif_shape(nf, hidden, layers, O.COLOUR_YUV, skip)
+    ref_p = O.nif_dequantize(shape, trained.astype(np.float64), O.PREC_FP8)
+    assert np.array_equal(dq.astype(np.float64), ref_p)
+    osc, cam = oracle_scene(scene)
+    rd = O.render_desc(W, H, spp, depth, seed, nif_params=ref_p, nif=shape, nif_prec=O.PREC_FP8)
+    rows = (300, 700)
+    o = np.stack([O.render(osc, cam, rd, y, H + 1)[y] for y in rows])
+    gr = g[list(rows)]
+    r = rel_rmse(gr, o)
+    print(f"spheres, paper network FP8, rows {rows}: mean GPU {gr.mean():.5f} oracle {o.mean():.5f}, "
+          f"relRMSE {r:.3e}")
+    assert np.all(np.isfinite(g)) and np.all(g >= 0)
+    assert o.mean() > 0.05
+    assert r <= 2e-2
