@@ -6,7 +6,8 @@ device and run with FP8 operands.  The GPU renders the whole frame in the
 benchmark's launch configuration; the oracle traces two full rows (3,840
 pixels, 245,760 path samples) with the same dequantised weights.  Likewise
 the spheres scene of the model-size study lit by the paper's own network on
-its LDS-resident FP8 kernel."""
+its LDS-resident FP8 kernel, and the open-box (FP16 NIF), spheres (BF16 NIF,
+64 spp) and small-BVH (FP16 NIF, 1080p) configurations at their full sizes."""
 import numpy as np
 import pytest
 
@@ -90,3 +91,44 @@ def test_spheres_paper_network_fp8_full_size_rows_match_oracle():
     assert np.all(np.isfinite(g)) and np.all(g >= 0)
     assert o.mean() > 0.05
     assert r <= 2e-2
+
+
+# the other configurations at their full sizes: (config, width, height, spp,
+# depth, NIF precision, two rows the oracle traces)
+CONFIGS = [(1, 512, 512, 16, 6, npt.FP16, (100, 400)),
+           (2, 1024, 1024, 64, 8, npt.BF16, (250, 750)),
+           (3, 1920, 1080, 32, 6, npt.FP16, (200, 700))]
+OPERAND_TOL = {npt.FP16: 2e-3, npt.BF16: 1e-2}  # as for the query and render tests
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("cfg,W,H,spp,depth,prec,rows", CONFIGS)
+def test_config_full_size_rows_match_oracle(cfg, W, H, spp, depth, prec, rows):
+    scene = synth.scene_for(cfg)
+    ctx = npt.npt_create(0)
+    try:
+        npt.npt_load_scene(ctx, scene, max_leaf=2, lds_levels=0, width=4)
+        npt.npt_env_upload(ctx, synth.env_map())
+        npt.npt_nif_upload(ctx, synth.nif_init(3))
+        npt.npt_nif_train(ctx, npt.train_params(batch=65536, samples=1 << 22, seed=1, grad_prec=npt.FP16))
+        npt.npt_nif_set_precision(ctx, prec)
+        trained = npt.npt_nif_download(ctx)
+        dq = npt.npt_nif_get_dequantized(ctx)
+        npt.npt_set_env_mode(ctx, npt.ENV_NIF)
+        npt.npt_set_render_options(ctx, rr_start=3)
+        g = gpu_render(ctx, W, H, spp, depth, 1)
+    finally:
+        npt.npt_destroy(ctx)
+    shape = O.nif_shape()
+    ref_p = O.nif_dequantize(shape, trained.astype(np.float64), prec)
+    assert np.array_equal(dq.astype(np.float64), ref_p)
+    osc, cam = oracle_scene(scene)
+    rd = O.render_desc(W, H, spp, depth, 1, nif_params=ref_p, nif=shape, nif_prec=prec)
+    o = np.stack([O.render(osc, cam, rd, y, H + 1)[y] for y in rows])
+    gr = g[list(rows)]
+    r = rel_rmse(gr, o)
+    print(f"config {cfg} {W}x{H} {spp} spp depth {depth} prec {prec}, rows {rows}: mean GPU {gr.mean():.5f} "
+          f"oracle {o.mean():.5f}, relRMSE {r:.3e}")
+    assert np.all(np.isfinite(g)) and np.all(g >= 0)
+    assert o.mean() > 0.01
+    assert r <= OPERAND_TOL[prec]
