@@ -25,3 +25,21 @@ def test_plain_c_client_builds_and_runs(tmp_path):
     print(r.stdout)
     assert r.returncode == 0, r.stdout + r.stderr
     assert r.stdout.strip().endswith("ok")
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
+def test_binding_structs_match_the_c_layout(tmp_path):
+    # every ctypes mirror in the binding has the size the C compiler gives the
+    # header's struct (a field added on one side only would show here)
+    import ctypes
+
+    exe = str(tmp_path / "struct_sizes")
+    cmd = ["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic", "-I", os.path.dirname(npt.HEADER),
+           os.path.join(HERE, "c", "struct_sizes.c"), "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=60).stdout.split("\n")
+    sizes = dict(line.split() for line in out if line.strip())
+    assert len(sizes) == 9
+    for name, size in sizes.items():
+        assert ctypes.sizeof(getattr(npt, name)) == int(size), name

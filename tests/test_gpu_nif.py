@@ -290,3 +290,27 @@ def test_fp16_master_adam_step_matches_oracle(small_sky):
     assert np.array_equal(np.nextafter(qh, rh), rh)
     # the update really moved the weights (not a rounding back to the start)
     assert np.mean(q != np.float16(p).astype(np.float64)) > 0.5
+
+
+def test_per_depth_environment_times_add_up(small_sky):
+    # kernel timing: the per-depth environment (NIF) times sum to the total;
+    # every depth up to the maximum has its launch (one per pass), none beyond
+    torch = torch_cuda()
+    ctx = make_ctx(synth.scene_for(1), env=small_sky)
+    try:
+        npt.npt_nif_upload(ctx, _weights())
+        npt.npt_nif_set_precision(ctx, npt.FP8)
+        npt.npt_set_env_mode(ctx, npt.ENV_NIF)
+        npt.npt_set_render_options(ctx, rr_start=3, kernel_timing=1, samples_per_pass=2)
+        out = torch.empty(64, 64, 3, device="cuda")
+        npt.npt_render(ctx, 64, 64, 4, 6, 3, out)
+        torch.cuda.synchronize()
+        st = npt.npt_get_stats(ctx)
+    finally:
+        npt.npt_destroy(ctx)
+    per_depth = np.array(st["ms_env_depth"], np.float64)
+    print(f"env ms {st['ms_env']:.4f} over {st['env_launches']} launches; per depth {per_depth[:6]}")
+    assert st["passes"] == 2 and st["env_launches"] == 2 * 6
+    assert abs(per_depth.sum() - st["ms_env"]) <= 1e-4 * st["ms_env"] + 1e-6
+    assert np.all(per_depth[:6] > 0.0) and np.all(per_depth[6:] == 0.0)
+    assert sum(st["escaped"]) == st["env_queries"] > 0
