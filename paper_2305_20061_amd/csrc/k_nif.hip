@@ -243,13 +243,20 @@ __device__ __forceinline__ float feature(int f0, int f1, int h, float u, float v
   const float q0 = (float)frequency(f0 - b0 * NF), q1 = (float)frequency(f1 - b1 * NF);
   const bool hi = h != 0;
   const int blk = hi ? b1 : b0;
-  const float ph = frac_product(hi ? q1 : q0, blk < 2 ? u : v);
+  const float q = hi ? q1 : q0, x = blk < 2 ? u : v;
   float r;
   if (kAccurateSin) {
     float s, c;
-    sincos_turns(ph, s, c);
+    sincos_turns(frac_product(q, x), s, c);
     r = (blk & 1) ? c : s;
-  } else if ((b0 & 1) == (b1 & 1)) {
+    return (hi ? f1 : f0) < A::kFeat ? r : 0.0f;
+  }
+  // The hardware sin / cos reduce their argument (in turns) themselves, so
+  // the phase needs no wrap into [0, 1): the fraction of the product plus the
+  // product's rounding error (recovered with an FMA) lies within an ulp of it.
+  const float p = q * x;
+  const float ph = __builtin_amdgcn_fractf(p) + __builtin_fmaf(q, x, -p);
+  if ((b0 & 1) == (b1 & 1)) {
     r = (b0 & 1) ? __builtin_amdgcn_cosf(ph) : __builtin_amdgcn_sinf(ph);
   } else {
     r = (blk & 1) ? __builtin_amdgcn_cosf(ph) : __builtin_amdgcn_sinf(ph);
