@@ -702,7 +702,10 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(6))
 // survivors to the next queue.  Whole workgroups iterate together: queue
 // slots are reserved with one atomic per workgroup and queue.
 // ---------------------------------------------------------------------------
-constexpr int kShadeBlock = 1024;
+// 512-thread workgroups, a grid of eight per CU (the same threads as four
+// of 1024): on the large-BVH frame 1024 threads were 9 % slower and 256
+// threads, with four times the queue-counter atomics of 1024, 53 % slower
+constexpr int kShadeBlock = 512;
 
 // Queue slots for two predicates at once: the wave counts meet in LDS and
 // thread 0 reserves both ranges.  Every thread of the workgroup calls it.
@@ -1011,7 +1014,7 @@ hipError_t launch_extend(int stack_depth, const SceneView& sc, uint32_t depth, u
 hipError_t launch_shade(const SceneView& sc, const PassView& pv, uint32_t depth, uint64_t max_rays,
                         const RayQueue& in, const float4* hits, const RayQueue& out, const EnvQueue& env,
                         float4* L, uint32_t* cnt, int num_cus, hipStream_t s) {
-  hipLaunchKernelGGL(k_shade, dim3(grid_for(max_rays, kShadeBlock, num_cus * 4)), dim3(kShadeBlock), 0, s, sc, pv,
+  hipLaunchKernelGGL(k_shade, dim3(grid_for(max_rays, kShadeBlock, num_cus * 8)), dim3(kShadeBlock), 0, s, sc, pv,
                      depth, in, hits, out, env, L, cnt);
   return hipGetLastError();
 }
