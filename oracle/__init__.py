@@ -102,6 +102,8 @@ def lib():
             "or_huber_grad": (C.c_double, [C.c_double, C.c_double]),
             "or_nif_loss_grad": (C.c_double, [C.POINTER(NifShape), _f64p, C.c_uint64, _f64p, _f64p,
                                               C.c_double, _f64p]),
+            "or_nif_loss_grad_q": (C.c_double, [C.POINTER(NifShape), _f64p, C.c_int, C.c_double, C.c_uint64,
+                                                _f64p, _f64p, C.c_double, _f64p]),
             "or_nif_train_batch": (None, [_f32p, C.c_uint32, C.c_uint32, C.c_uint64, C.c_uint32,
                                           C.c_uint64, _f64p, _f64p]),
             "or_adam_step": (None, [C.c_uint64, _f64p, _f64p, _f64p, _f64p, C.c_uint32, C.c_double,
@@ -263,7 +265,8 @@ COLOUR_YUV, COLOUR_RGB, COLOUR_YCOCG = 0, 1, 2
 
 def nif_shape(n_freq=16, hidden=96, layers=5, colour=COLOUR_YUV, skip=0):
     """skip: 0, or the hidden layer (1..layers-1) whose input is the previous
-    layer's output followed by the features (skip-concat)."""
+    layer's output followed by the features (skip-concat); that previous layer
+    has hidden - 4 n_freq outputs, so the skip layer reads hidden values."""
     s = NifShape()
     s.n_freq, s.hidden, s.layers, s.colour, s.skip = n_freq, hidden, layers, colour, skip
     return s
@@ -352,14 +355,59 @@ def huber_grad(e, delta):
     return lib().or_huber_grad(float(e), float(delta))
 
 
-def nif_loss_grad(shape, params, uv, target, delta, want_grad=True):
+def _batch_chunks(n, threads):
+    """Contiguous chunks [a, b) of a batch of n, one per thread."""
+    k = max(1, min(int(threads), n))
+    edges = [n * i // k for i in range(k + 1)]
+    return [(edges[i], edges[i + 1]) for i in range(k) if edges[i + 1] > edges[i]]
+
+
+def _chunked_mean(fn, n, want_grad, threads):
+    """fn(a, b) -> (mean loss, mean gradient) of rows [a, b).  With threads >
+    1 the chunks run on as many threads (a ctypes call releases the GIL) and
+    their means are added back weighted by chunk size, in chunk order: the
+    batch mean, summed in another order."""
+    chunks = _batch_chunks(n, threads)
+    if len(chunks) == 1:
+        return fn(0, n)
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(len(chunks)) as ex:
+        parts = list(ex.map(lambda ab: fn(*ab), chunks))
+    loss = sum(l * (b - a) for (a, b), (l, _) in zip(chunks, parts)) / n
+    grad = None
+    if want_grad:
+        grad = np.zeros_like(parts[0][1])
+        for (a, b), (_, g) in zip(chunks, parts):
+            grad += g * ((b - a) / n)
+    return loss, grad
+
+
+def nif_loss_grad(shape, params, uv, target, delta, want_grad=True, threads=1):
     p, uv, tg = f64(params), f64(uv), f64(target)
-    n = uv.shape[0]
-    g = np.zeros_like(p) if want_grad else None
-    loss = lib().or_nif_loss_grad(C.byref(shape), _ptr(p, C.c_double), n, _ptr(uv, C.c_double),
-                                  _ptr(tg, C.c_double), float(delta),
-                                  _ptr(g, C.c_double) if want_grad else None)
-    return loss, g
+
+    def run(a, b):
+        g = np.zeros_like(p) if want_grad else None
+        u, t = np.ascontiguousarray(uv[a:b]), np.ascontiguousarray(tg[a:b])
+        loss = lib().or_nif_loss_grad(C.byref(shape), _ptr(p, C.c_double), b - a, _ptr(u, C.c_double),
+                                      _ptr(t, C.c_double), float(delta),
+                                      _ptr(g, C.c_double) if want_grad else None)
+        return loss, g
+    return _chunked_mean(run, uv.shape[0], want_grad, threads)
+
+
+def nif_loss_grad_q(shape, params, prec, loss_scale, uv, target, delta, want_grad=True, threads=1):
+    """Loss and gradient with the trainer's matrix operands rounded to prec
+    (PREC_FP32: none), loss scale applied to the back-propagated gradients."""
+    p, uv, tg = f64(params), f64(uv), f64(target)
+
+    def run(a, b):
+        g = np.zeros_like(p) if want_grad else None
+        u, t = np.ascontiguousarray(uv[a:b]), np.ascontiguousarray(tg[a:b])
+        loss = lib().or_nif_loss_grad_q(C.byref(shape), _ptr(p, C.c_double), int(prec), float(loss_scale),
+                                        b - a, _ptr(u, C.c_double), _ptr(t, C.c_double), float(delta),
+                                        _ptr(g, C.c_double) if want_grad else None)
+        return loss, g
+    return _chunked_mean(run, uv.shape[0], want_grad, threads)
 
 
 def nif_train_batch(env, seed, step, n):

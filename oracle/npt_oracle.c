@@ -412,12 +412,18 @@ void or_env_bilinear(const float *rgb, uint32_t w, uint32_t h, double u, double 
 /* ------------------------------------------------------------------------ */
 uint32_t or_nif_frequency(uint32_t k) { return (uint32_t)llround(pow(2.0, (double)(k + 1) * 0.5)); }
 
-static uint32_t layer_in(const or_nif_shape *s, uint32_t l)
+/* Layer widths.  With a skip-concat (Sec. 3.2) the features join the output
+ * of the layer before hidden layer `skip`, and that layer is narrowed by the
+ * feature count so that the concatenated input of layer `skip` stays
+ * `hidden` wide: layer skip-1 has hidden - 4 n_freq outputs.  Every hidden
+ * layer after the first therefore reads `hidden` values. */
+static uint32_t layer_in(const or_nif_shape *s, uint32_t l) { return l == 0 ? 4 * s->n_freq : s->hidden; }
+static uint32_t layer_out(const or_nif_shape *s, uint32_t l)
 {
-    if (l == 0) return 4 * s->n_freq;
-    return s->skip != 0 && l == s->skip ? s->hidden + 4 * s->n_freq : s->hidden;
+    if (l == s->layers) return 3;
+    if (s->skip != 0 && l + 1 == s->skip) return s->hidden - 4 * s->n_freq;
+    return s->hidden;
 }
-static uint32_t layer_out(const or_nif_shape *s, uint32_t l) { return l == s->layers ? 3 : s->hidden; }
 
 uint64_t or_nif_param_count(const or_nif_shape *s)
 {
@@ -735,6 +741,126 @@ double or_nif_loss_grad(const or_nif_shape *s, const double *params, uint64_t n,
     free(da);
     free_acts(s, act);
     return loss * scale;
+}
+
+/* Loss and gradient of a training batch with the matrix operands of the    */
+/* on-device trainer rounded to the gradient precision (Sec. 3.2.1 trains   */
+/* in reduced precision with FP32 accumulation and a loss scale).  As in    */
+/* or_nif_forward_q, sums and products are exact; what is rounded, to the   */
+/* format of `prec` (nothing for OR_PREC_FP32):                             */
+/*   - the weights of the hidden layers 0..L-1, once (the output layer and  */
+/*     all biases are used as given: the head runs on the FP32 master);     */
+/*   - every layer input: the features, and each ReLU output;               */
+/*   - the back-propagated gradient at the output of every hidden layer,    */
+/*     after the ReLU mask and with the loss scale S applied: the output-   */
+/*     layer gradient dL/dy = M^T (Huber'(z - target) * S) is exact, its    */
+/*     product with the output weights is rounded, and so is each product   */
+/*     with a hidden layer's rounded weights.  The mask is "the rounded     */
+/*     activation is > 0".                                                  */
+/* Weight and bias gradients are the exact sums of products of these        */
+/* rounded operands, divided by 3 n S at the end; the loss is the mean      */
+/* Huber loss of the rounded forward pass.  In OR_PREC_FP32 mode this is     */
+/* the gradient of or_nif_loss_grad.                                        */
+double or_nif_loss_grad_q(const or_nif_shape *s, const double *params, int prec, double loss_scale,
+                          uint64_t n, const double *uv, const double *target, double delta, double *grad)
+{
+    const int fmt = prec == OR_PREC_FP16 ? OR_FMT_F16 : prec == OR_PREC_BF16 ? OR_FMT_BF16 : OR_FMT_NONE;
+    const uint32_t L = s->layers, F = 4 * s->n_freq;
+    const uint64_t np = or_nif_param_count(s);
+    /* offsets of W_l in the flat vector, and the rounded hidden-layer weights */
+    size_t *off = (size_t *)malloc(sizeof(size_t) * (L + 1));
+    double *wq = (double *)malloc(sizeof(double) * np);
+    size_t o = 0;
+    for (uint32_t l = 0; l <= L; ++l) {
+        const size_t nw = (size_t)layer_out(s, l) * layer_in(s, l), nb = layer_out(s, l);
+        off[l] = o;
+        for (size_t i = 0; i < nw; ++i) wq[o + i] = l < L ? or_round_to(params[o + i], fmt) : params[o + i];
+        for (size_t i = 0; i < nb; ++i) wq[o + nw + i] = params[o + nw + i];
+        o += nw + nb;
+    }
+    /* x[l]: rounded input of layer l (layer_in(l) values) */
+    double **x = (double **)malloc(sizeof(double *) * (L + 1));
+    for (uint32_t l = 0; l <= L; ++l) x[l] = (double *)malloc(sizeof(double) * layer_in(s, l));
+    double *feat = (double *)malloc(sizeof(double) * F);
+    double *g = (double *)malloc(sizeof(double) * s->hidden);  /* gradient at a layer's output */
+    double *gp = (double *)malloc(sizeof(double) * s->hidden); /* ... and at its input        */
+    double m[9];
+    or_colour_to_rgb_matrix(s->colour, m);
+    if (grad) memset(grad, 0, sizeof(double) * np);
+    double loss = 0.0;
+    for (uint64_t i = 0; i < n; ++i) {
+        or_nif_features(s, uv[2 * i], uv[2 * i + 1], feat);
+        for (uint32_t k = 0; k < F; ++k) x[0][k] = or_round_to(feat[k], fmt);
+        for (uint32_t l = 0; l < L; ++l) {
+            const uint32_t ni = layer_in(s, l), no = layer_out(s, l);
+            const double *W = wq + off[l], *b = W + (size_t)no * ni;
+            for (uint32_t j = 0; j < no; ++j) {
+                double acc = b[j];
+                for (uint32_t q = 0; q < ni; ++q) acc += W[(size_t)j * ni + q] * x[l][q];
+                x[l + 1][j] = or_round_to(acc > 0.0 ? acc : 0.0, fmt);
+            }
+            if (s->skip != 0 && l + 1 == s->skip) memcpy(x[l + 1] + no, x[0], sizeof(double) * F);
+        }
+        const uint32_t H = layer_in(s, L);
+        const double *WL = wq + off[L], *bL = WL + (size_t)3 * H;
+        double y[3], z[3], dz[3], dy[3];
+        for (uint32_t j = 0; j < 3; ++j) {
+            double acc = bL[j];
+            for (uint32_t q = 0; q < H; ++q) acc += WL[(size_t)j * H + q] * x[L][q];
+            y[j] = acc;
+        }
+        for (int r = 0; r < 3; ++r) z[r] = m[3 * r] * y[0] + m[3 * r + 1] * y[1] + m[3 * r + 2] * y[2];
+        for (int c = 0; c < 3; ++c) {
+            const double e = z[c] - target[3 * i + c];
+            loss += or_huber(e, delta);
+            dz[c] = or_huber_grad(e, delta) * loss_scale;
+        }
+        if (!grad) continue;
+        for (int k = 0; k < 3; ++k) dy[k] = m[k] * dz[0] + m[3 + k] * dz[1] + m[6 + k] * dz[2];
+        {
+            double *gW = grad + off[L], *gb = gW + (size_t)3 * H;
+            for (uint32_t j = 0; j < 3; ++j) {
+                gb[j] += dy[j];
+                for (uint32_t q = 0; q < H; ++q) gW[(size_t)j * H + q] += dy[j] * x[L][q];
+            }
+            for (uint32_t q = 0; q < H; ++q) {
+                double acc = 0.0;
+                for (uint32_t j = 0; j < 3; ++j) acc += WL[(size_t)j * H + q] * dy[j];
+                g[q] = x[L][q] > 0.0 ? or_round_to(acc, fmt) : 0.0;
+            }
+        }
+        for (int l = (int)L - 1; l >= 0; --l) {
+            const uint32_t ni = layer_in(s, (uint32_t)l), no = layer_out(s, (uint32_t)l);
+            const double *W = wq + off[l];
+            double *gW = grad + off[l], *gb = gW + (size_t)no * ni;
+            for (uint32_t j = 0; j < no; ++j) {
+                gb[j] += g[j];
+                for (uint32_t q = 0; q < ni; ++q) gW[(size_t)j * ni + q] += g[j] * x[l][q];
+            }
+            if (l == 0) break;
+            /* the gradient at the output of layer l-1: the hidden part of */
+            /* layer l's input (its first layer_out(l-1) columns)          */
+            const uint32_t nprev = layer_out(s, (uint32_t)l - 1);
+            for (uint32_t q = 0; q < nprev; ++q) {
+                double acc = 0.0;
+                for (uint32_t j = 0; j < no; ++j) acc += W[(size_t)j * ni + q] * g[j];
+                gp[q] = x[l][q] > 0.0 ? or_round_to(acc, fmt) : 0.0;
+            }
+            memcpy(g, gp, sizeof(double) * nprev);
+        }
+    }
+    if (grad) {
+        const double sc = 1.0 / (3.0 * (double)n * loss_scale);
+        for (uint64_t k = 0; k < np; ++k) grad[k] *= sc;
+    }
+    for (uint32_t l = 0; l <= L; ++l) free(x[l]);
+    free(x);
+    free(feat);
+    free(g);
+    free(gp);
+    free(wq);
+    free(off);
+    return loss / (3.0 * (double)n);
 }
 
 void or_nif_train_batch(const float *map, uint32_t w, uint32_t h, uint64_t seed, uint32_t step,

@@ -68,7 +68,9 @@ typedef struct {
  * -> dense 3 -> fixed 3x3 colour matrix to RGB.  colour: the space the
  * network's outputs live in (Sec. 4.3): OR_COLOUR_YUV (default), RGB, YCOCG.
  * skip: 0, or the hidden layer l (1..layers-1) whose input is the previous
- * layer's output followed by the features again (the skip-concat of Sec. 3.2). */
+ * layer's output followed by the features again (the skip-concat of Sec. 3.2);
+ * the previous layer is narrowed to hidden - 4 n_freq outputs so that layer
+ * l still reads `hidden` values (needs hidden > 4 n_freq). */
 enum { OR_COLOUR_YUV = 0, OR_COLOUR_RGB = 1, OR_COLOUR_YCOCG = 2 };
 typedef struct {
     uint32_t n_freq;
@@ -143,6 +145,16 @@ double or_huber_grad(double e, double delta);
  * (grad may be NULL).  uv: n x 2, target: n x 3 (log-space). */
 double or_nif_loss_grad(const or_nif_shape *s, const double *params, uint64_t n,
                         const double *uv, const double *target, double delta, double *grad);
+/* The same loss and gradient with the on-device trainer's matrix operands
+ * rounded to prec (OR_PREC_FP16 / BF16; OR_PREC_FP32 rounds nothing): hidden-
+ * layer weights, layer inputs and the back-propagated gradients at the
+ * hidden layers' outputs (after the ReLU mask, loss scale loss_scale
+ * applied); exact sums; the output layer on the given weights; gradient
+ * divided by 3 n loss_scale.  Pinned: FP32 mode = or_nif_loss_grad; FP16 /
+ * BF16 = a batched NumPy layer loop with library casts; BF16 independent of
+ * the loss scale; FP16 closer to FP64 with the paper's scale than without. */
+double or_nif_loss_grad_q(const or_nif_shape *s, const double *params, int prec, double loss_scale,
+                          uint64_t n, const double *uv, const double *target, double delta, double *grad);
 /* Training batch of Sec. 3.2.1: uniform (u,v) from the TRAIN Philox stream and
  * log1p(bilinear) targets.  uv: n x 2, target: n x 3. */
 void or_nif_train_batch(const float *map, uint32_t w, uint32_t h, uint64_t seed, uint32_t step,

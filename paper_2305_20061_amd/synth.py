@@ -343,11 +343,14 @@ def uniform_env(width: int = 64, height: int = 32, value: float = 1.0):
 # NIF initial parameters (Glorot-uniform weights, zero biases)
 # --------------------------------------------------------------------------
 def nif_layer_dims(n_freq=16, hidden=96, layers=5, skip=0):
-    """(fan_in, fan_out) per layer; with skip > 0, hidden layer `skip` also
-    reads the 4 n_freq features (skip-concat)."""
-    dims = [4 * n_freq] + [hidden] * layers + [3]
-    fan_in = [dims[i] + (4 * n_freq if skip and i == skip else 0) for i in range(len(dims) - 1)]
-    return [(fan_in[i], dims[i + 1]) for i in range(len(dims) - 1)]
+    """(fan_in, fan_out) per layer; with skip > 0, hidden layer `skip` reads
+    the previous layer's output followed by the 4 n_freq features
+    (skip-concat), and the previous layer is hidden - 4 n_freq wide so that
+    the concatenation is hidden wide."""
+    feat = 4 * n_freq
+    outs = [hidden - feat if skip and l + 1 == skip else hidden for l in range(layers)] + [3]
+    ins = [feat] + [hidden] * layers
+    return list(zip(ins, outs))
 
 
 def nif_param_count(n_freq=16, hidden=96, layers=5, skip=0):

@@ -220,13 +220,15 @@ def test_training_reduces_loss(small_sky):
     assert np.mean(losses[-5:]) < 0.6 * np.mean(losses[:5])
 
 
-# ---- skip-concat (Sec. 3.2: the features enter again at a middle layer)
-SKIP = O.nif_shape(16, 32, 4, O.COLOUR_YUV, 2)
+# ---- skip-concat (Sec. 3.2: the features enter again at a middle layer, and
+# the layer before it is narrowed so that the concatenation stays H wide)
+SKIP = O.nif_shape(4, 32, 4, O.COLOUR_YUV, 2)  # 16 features; layer 1 is 32 - 16 = 16 wide
 
 
 def _skip_layout():
-    """(offset_W, offset_b, out, in) per layer of SKIP; layer 2 reads 32 + 64."""
-    fans = [(64, 32), (32, 32), (32 + 64, 32), (32, 32), (32, 3)]
+    """(offset_W, offset_b, out, in) per layer of SKIP: layer 1 has 16
+    outputs, layer 2 reads them followed by the 16 features (32 inputs)."""
+    fans = [(16, 32), (32, 16), (16 + 16, 32), (32, 32), (32, 3)]
     out, off = [], 0
     for fi, fo in fans:
         out.append((off, off + fo * fi, fo, fi))
@@ -236,25 +238,29 @@ def _skip_layout():
 
 def test_skip_param_count():
     n = sum(fo * fi + fo for _, _, fo, fi in _skip_layout())
-    assert O.nif_param_count(SKIP) == n == synth.nif_param_count(16, 32, 4, 2) == synth.nif_init(1, 16, 32, 4, 2).size
-    assert n == O.nif_param_count(O.nif_shape(16, 32, 4)) + 32 * 64
+    assert O.nif_param_count(SKIP) == n == synth.nif_param_count(4, 32, 4, 2) == synth.nif_init(1, 4, 32, 4, 2).size
+    # the plain network minus the 16 rows (weights and biases) the narrowed layer drops
+    assert n == O.nif_param_count(O.nif_shape(4, 32, 4)) - 16 * (32 + 1)
+    # the paper's shape: 40-d features, H128 L5, concatenation at hidden layer 2
+    paper = O.nif_shape(10, 128, 5, O.COLOUR_YUV, 2)
+    assert O.nif_param_count(paper) == (40 * 128 + 128) + (128 * 88 + 88) + 3 * (128 * 128 + 128) + (3 * 128 + 3)
 
 
-@pytest.mark.parametrize("feat", [0, 21, 63])
+@pytest.mark.parametrize("feat", [0, 5, 15])
 def test_skip_path_closed_form(feat):
     # every weight zero except the skip layer reading one feature into neuron
     # 0 (bias 2), the next layer passing it on, the output reading it as Y:
-    # the features appear after the 32 hidden inputs of the skip layer
+    # the features appear after the 16 outputs of the narrowed layer
     p = np.zeros(O.nif_param_count(SKIP))
     lay = _skip_layout()
     oW, ob, fo, fi = lay[2]
-    p[oW + 0 * fi + 32 + feat] = 1.0
+    p[oW + 0 * fi + 16 + feat] = 1.0
     p[ob + 0] = 2.0
     oW, ob, fo, fi = lay[3]
     p[oW + 0] = 1.0
     oW, ob, fo, fi = lay[4]
     p[oW + 0] = 0.5
-    k, blk = feat % 16, feat // 16
+    k, blk = feat % 4, feat // 4
     f = O.nif_frequency(k)
     for u, v in ((0.1, 0.2), (0.77, 0.05)):
         val = (np.sin if blk % 2 == 0 else np.cos)(2 * np.pi * f * (u if blk < 2 else v))
@@ -263,17 +269,40 @@ def test_skip_path_closed_form(feat):
         assert np.allclose(O.nif_forward_q(SKIP, p, O.PREC_FP32, u, v), 0.5 * (val + 2.0), atol=1e-12)
 
 
+def test_skip_narrowed_layer_feeds_the_hidden_columns():
+    # a path through neuron 15 of the narrowed layer (its last output) and
+    # column 15 of the skip layer: ReLU(u-feature sin) passes through, and
+    # column 16 (the first feature) is not fed by the narrowed layer
+    p = np.zeros(O.nif_param_count(SKIP))
+    lay = _skip_layout()
+    oW, ob, fo, fi = lay[0]
+    p[oW + 15 * fi + 0] = 1.0  # neuron 15 of layer 0 reads feature 0: sin(2 pi u)
+    p[ob + 15] = 1.5
+    oW, ob, fo, fi = lay[1]
+    p[oW + 15 * fi + 15] = 1.0  # narrowed layer 1, output 15 (its last), reads it
+    oW, ob, fo, fi = lay[2]
+    p[oW + 3 * fi + 15] = 2.0  # skip layer: hidden column 15 into neuron 3
+    oW, ob, fo, fi = lay[3]
+    p[oW + 0 * fi + 3] = 1.0
+    oW, ob, fo, fi = lay[4]
+    p[oW + 0] = 1.0
+    for u, v in ((0.1, 0.2), (0.6, 0.9)):
+        assert np.allclose(O.nif_forward(SKIP, p, u, v), 2.0 * (np.sin(2 * np.pi * u) + 1.5), atol=1e-12)
+
+
 def test_skip_backward_matches_central_differences():
     rng = np.random.default_rng(7)
-    p = synth.nif_init(9, 16, 32, 4, 2).astype(np.float64) + rng.normal(size=O.nif_param_count(SKIP)) * 0.01
+    p = synth.nif_init(9, 4, 32, 4, 2).astype(np.float64) + rng.normal(size=O.nif_param_count(SKIP)) * 0.01
     uv = rng.random((5, 2))
     target = rng.normal(size=(5, 3)) * 0.5
     _, g = O.nif_loss_grad(SKIP, p, uv, target, 1e3)
     lay = _skip_layout()
-    # every weight of the skip layer's feature columns, plus a random sample
+    # every weight of the skip layer's feature columns, every weight of the
+    # narrowed layer, plus a random sample
     oW, ob, fo, fi = lay[2]
-    skip_cols = [oW + j * fi + 32 + c for j in range(0, fo, 7) for c in range(0, 64, 9)]
-    idx = np.concatenate([skip_cols, rng.choice(p.size, 200, replace=False)])
+    skip_cols = [oW + j * fi + 16 + c for j in range(0, fo, 5) for c in range(16)]
+    oW1, ob1, fo1, fi1 = lay[1]
+    idx = np.concatenate([skip_cols, np.arange(oW1, ob1 + fo1, 7), rng.choice(p.size, 200, replace=False)])
     h = 1e-5
     worst = 0.0
     for i in idx:

@@ -159,13 +159,14 @@ def _numpy_forward_q(p_deq, prec, u, v):
 
 
 def test_skip_quantised_forward_matches_numpy_layer_loop():
-    # skip-concat network (features again at hidden layer 2), FP16 operands:
-    # the concatenated input is rounded as one vector
-    shape = O.nif_shape(16, 32, 4, O.COLOUR_YUV, 2)
-    p = synth.nif_init(4, 16, 32, 4, 2).astype(np.float64)
+    # skip-concat network (features again at hidden layer 2, layer 1 narrowed
+    # to 96 - 64 = 32 outputs), FP16 operands: the concatenated input is
+    # rounded as one vector
+    shape = O.nif_shape(16, 96, 4, O.COLOUR_YUV, 2)
+    p = synth.nif_init(4, 16, 96, 4, 2).astype(np.float64)
     p[-3:] = (0.6, 0.05, -0.05)
     q = O.nif_dequantize(shape, p, O.PREC_FP16)
-    fans = [(64, 32), (32, 32), (32 + 64, 32), (32, 32), (32, 3)]
+    fans = [(64, 96), (96, 32), (32 + 64, 96), (96, 96), (96, 3)]
     rnd = lambda x: x.astype(np.float16).astype(np.float64)
     for u, v in np.random.default_rng(8).uniform(0, 1, (10, 2)):
         feat = O.nif_features(shape, u, v)
