@@ -369,7 +369,7 @@ def nif_study(args):
         # master-weight precision (YUV, FP16 GEMMs): FP32 master against the
         # paper's binary16 master with stochastic rounding and loss scale 16384
         npt.npt_set_env_mode(ctx, npt.ENV_MAP)
-        for name, mp, ls in (("fp32_master", npt.FP32, 1024.0), ("fp16_master_sr_ls16384", npt.FP16, 16384.0)):
+        for name, mp, ls in (("fp32_master_ls16384", npt.FP32, 16384.0), ("fp16_master_sr_ls16384", npt.FP16, 16384.0)):
             npt.npt_nif_upload(ctx, synth.nif_init(3))
             tr = npt.npt_nif_train(ctx, npt.train_params(batch=65536, samples=args.train_samples, seed=1,
                                                          grad_prec=npt.FP16, loss_scale=ls, master_prec=mp))
@@ -388,11 +388,11 @@ def nif_study(args):
 
 # (hidden, layers, skip-concat layer, frequencies): the paper's sweep sizes,
 # the workload's network, and the paper's own architecture (40-d features,
-# H128 L5, features again at the middle layer) with and without its 40-d
-# features
-NIF_SIZES = [(64, 2, 0, 16), (96, 5, 0, 16), (128, 5, 2, 16), (128, 5, 2, 10), (256, 4, 0, 16), (1024, 8, 0, 16)]
+# H128, four dense-ReLU layers, the features again after the narrowed second
+# one) with and without its 40-d features
+NIF_SIZES = [(64, 2, 0, 16), (96, 5, 0, 16), (128, 4, 2, 16), (128, 4, 2, 10), (256, 4, 0, 16), (1024, 8, 0, 16)]
 # shapes with an LDS-resident inference kernel (hidden, layers, skip, frequencies)
-RESIDENT = [(96, 5, 0, 16), (128, 5, 2, 10), (128, 5, 2, 16), (64, 2, 0, 16)]
+RESIDENT = [(96, 5, 0, 16), (128, 4, 2, 10), (128, 4, 2, 16), (64, 2, 0, 16)]
 
 
 def nif_sizes(args):
@@ -443,7 +443,9 @@ def nif_sizes(args):
             n_params = npt.nif_param_count(hidden, layers, skip, nf)
             trained = npt.npt_nif_download(ctx, n_params)
             F = 4 * nf
-            flop = 2 * (F * hidden + (layers - 1) * hidden * hidden + 3 * hidden + (F * hidden if skip else 0))
+            # MACs: first layer, hidden layers (the one before a skip-concat
+            # is hidden - F wide), output layer
+            flop = 2 * (F * hidden + (layers - 1) * hidden * hidden + 3 * hidden - (F * hidden if skip else 0))
             # the layer-serial path; then, for shapes with an LDS-resident
             # kernel, the same trained weights on it in FP16 and FP8
             runs = [(1, npt.FP16)] + ([(0, npt.FP16), (0, npt.FP8)] if (hidden, layers, skip, nf) in RESIDENT else [])

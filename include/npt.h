@@ -101,10 +101,14 @@ typedef struct {
  * Supported: n_freq 1..16 (frequencies round(2^((k+1)/2)), k < n_freq);
  * hidden 32..1024, a multiple of 32; layers 1..8.  skip: 0, or the hidden
  * layer (1..layers-1) whose input is the previous layer's output followed by
- * the features again (the paper's skip-concat, Sec. 3.2).  Four shapes
+ * the features again (the paper's skip-concat, Sec. 3.2); that previous
+ * layer has hidden - 4 n_freq outputs (needs hidden > 4 n_freq), so the
+ * concatenation is hidden wide.  Four shapes
  * (n_freq/hidden/layers/skip) run on an LDS-resident MFMA kernel in FP32,
- * FP16, BF16 or FP8: 16/96/5/0 (the default), 10/128/5/2 (the paper's
- * network), 16/128/5/2 and 16/64/2/0.  Every other shape, or layered = 1,
+ * FP16, BF16 or FP8: 16/96/5/0 (the default), 10/128/4/2 (the paper's
+ * network: 40-d features, four dense-ReLU layers, the second narrowed to 88
+ * outputs; with the output layer five trainable layers, 50,011 parameters =
+ * 97.7 KiB in FP16), 16/128/4/2 and 16/64/2/0.  Every other shape, or layered = 1,
  * runs on layer-serial MFMA GEMMs in FP32, FP16 or BF16 (Sec. 4.6 sweeps
  * model sizes); uploading such a shape while FP8 is selected, or selecting
  * FP8 for it, fails with NPT_E_UNSUPPORTED.
@@ -135,7 +139,11 @@ typedef struct {
  * binary16 stochastically with u from the Philox stream (parameter index,
  * Adam step, 0, 4) under the seed.  Zero fields take the defaults in brackets:
  * batch [65536; a multiple of 2048], samples [2^24], lr [1e-3], beta1 [0.9], beta2 [0.999],
- * eps [1e-7], huber_delta [1e-3], loss_scale [1024]. */
+ * eps [1e-7], huber_delta [1e-3], loss_scale [16384 with FP16 GEMM operands, the
+ * scale Sec. 3.2.1 trains with; 1 otherwise, where the range of FP32 / BF16
+ * makes a power-of-two scale cancel exactly].  The loss scale multiplies the
+ * per-sample output gradients before the backward GEMMs and is divided out
+ * of the weight gradients. */
 typedef struct {
     uint32_t batch;
     uint64_t samples;
@@ -254,7 +262,8 @@ int npt_set_env_mode(npt_ctx *ctx, int mode);
 /* ---- HDR-NIF (Sec. 3.2) ----------------------------------------------------- */
 /* params_fp32: [W1, b1, ..., W_{L+1}, b_{L+1}], W row-major [out][in], n
  * values (43,779 for 16/96/5; with F = 4 n_freq: F H + H + (L - 1)(H^2 + H)
- * + 3 H + 3, plus F H with a skip-concat).  Becomes the FP32 master copy; Adam state is reset;
+ * + 3 H + 3, less F (H + 1) with a skip-concat: 50,011 for the paper's
+ * 10/128/4 network with the features at layer 2).  Becomes the FP32 master copy; Adam state is reset;
  * the inference pack of the current precision is rebuilt; desc->colour
  * selects the output colour space (NPT_E_INVALID_ARG if unknown). */
 int npt_nif_upload(npt_ctx *ctx, const npt_nif_desc *desc, const float *params_fp32,

@@ -2,8 +2,8 @@
 // queries of escaped rays) and the weight packing it reads.
 //
 // One workgroup per CU keeps the packed network in LDS (the 16/96/5 network
-// in FP16/BF16: 87 KB; the paper's H128 L5 skip network with 40-d features:
-// 155 KB); each wave pushes 32-ray column tiles through all layers with
+// in FP16/BF16: 87 KB; the paper's H128 skip network with 40-d features:
+// 108 KB); each wave pushes 32-ray column tiles through all layers with
 // activations held in registers (see npt_nif_layout.h).  Layers that do not
 // fit (FP32 operands on v_mfma_f32_32x32x2f32, larger networks) are read
 // from L2.  Built for the shapes listed in npt_nif_layout.h.
@@ -76,8 +76,11 @@ __device__ __forceinline__ void fill_bias(const float* master, float* bias, int 
   constexpr int H = A::kHidden, L = A::kLayers;
   for (int j = tid; j < A::kBiasFloats; j += stride) {
     float b = 0.0f;
-    if (j < L * H) b = master[A::b_offset(j / H) + j % H];
-    else if (j - L * H < kOut) b = master[A::b_offset(L) + (j - L * H)];
+    if (j < L * H) {
+      if (j % H < A::layer_out(j / H)) b = master[A::b_offset(j / H) + j % H];
+    } else if (j - L * H < kOut) {
+      b = master[A::b_offset(L) + (j - L * H)];
+    }
     bias[j] = b;
   }
 }
@@ -101,7 +104,7 @@ __device__ __forceinline__ float packed_weight(const float* master, int l, int j
     h = lane / 32;
   }
   const int col = input_index<KPL, A>(l, kb, h, e);
-  return col < 0 ? 0.0f : master[A::w_offset(l) + row * A::layer_in(l) + col];
+  return col < 0 || row >= A::layer_out(l) ? 0.0f : master[A::w_offset(l) + row * A::layer_in(l) + col];
 }
 
 template <int P, class A>
@@ -139,7 +142,7 @@ __global__ __launch_bounds__(256) void k_nif_pack_fp8(const float* master, uint8
   __shared__ float red[256];
   int* scales = reinterpret_cast<int*>(bias + A::kBiasFloats);
   if (Fp8<A>::layer(l)) {
-    const int nin = A::layer_in(l), nw = A::kHidden * nin;
+    const int nin = A::layer_in(l), nout = A::layer_out(l), nw = nout * nin;
     float m = 0.0f;
     for (int i = threadIdx.x; i < nw; i += 256) m = fmaxf(m, fabsf(master[A::w_offset(l) + i]));
     red[threadIdx.x] = m;
@@ -161,7 +164,7 @@ __global__ __launch_bounds__(256) void k_nif_pack_fp8(const float* master, uint8
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int col = Fp8<A>::input_index(l, kb, lane / 32, e0 + k);
-        v[k] = col < 0 ? 0.0f : ldexpf(master[A::w_offset(l) + row * nin + col], s);
+        v[k] = col < 0 || row >= nout ? 0.0f : ldexpf(master[A::w_offset(l) + row * nin + col], s);
       }
       dst[wd] = pack_e4m3<true>(v[2], v[3], pack_e4m3<false>(v[0], v[1], 0));
     }
@@ -264,11 +267,12 @@ __device__ __forceinline__ float feature(int f0, int f1, int h, float u, float v
   return (hi ? f1 : f0) < A::kFeat ? r : 0.0f;
 }
 
-// bias-initialised accumulators of one layer over NT 32-ray column tiles
-template <int NT, class A>
+// bias-initialised accumulators (the first NMB M-blocks) of one layer over
+// NT 32-ray column tiles
+template <int NT, class A, int NMB = A::kMB>
 __device__ __forceinline__ void init_acc(const float* lb, int h, f32x16 (&acc)[NT][A::kMB]) {
 #pragma unroll
-  for (int mb = 0; mb < A::kMB; ++mb) {
+  for (int mb = 0; mb < NMB; ++mb) {
     f32x16 b;
 #pragma unroll
     for (int r = 0; r < 16; ++r) b[r] = lb[acc_row(mb, h, r)];
@@ -277,23 +281,24 @@ __device__ __forceinline__ void init_acc(const float* lb, int h, f32x16 (&acc)[N
   }
 }
 
-// acc += W[:, K-blocks KB0 .. KB0+NKB-1] x for Prec<P> operands; the layer's
-// fragments are [mb][NKBIN][lane]
-template <int P, class A, int NT, int NKB, int NKBIN, int KB0, int NX>
+// acc += W[:, K-blocks KB0 .. KB0+NKB-1] x for Prec<P> operands over the
+// first NMB M-blocks; the layer's fragments are [mb][NKBIN][lane]
+template <int P, class A, int NT, int NKB, int NKBIN, int KB0, int NMB = A::kMB, int NX>
 __device__ __forceinline__ void mma_layer(const typename Prec<P>::Frag* fr, int lane,
                                           const typename Prec<P>::Frag (&x)[NT][NX], f32x16 (&acc)[NT][A::kMB]) {
 #pragma unroll
   for (int kb = 0; kb < NKB; ++kb)
 #pragma unroll
-    for (int mb = 0; mb < A::kMB; ++mb) {
+    for (int mb = 0; mb < NMB; ++mb) {
       const typename Prec<P>::Frag a = fr[(mb * NKBIN + KB0 + kb) * 64 + lane];
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[t][mb] = Prec<P>::mma(a, x[t][kb], acc[t][mb]);
     }
 }
 
-// ReLU of the accumulators into the Prec<P> K-blocks of the next layer
-template <int P, class A, int NT>
+// ReLU of the accumulators into the first NKBX Prec<P> K-blocks of the next
+// layer
+template <int P, class A, int NT, int NKBX = Geometry<Prec<P>::KPL, A>::kKBHidden>
 __device__ __forceinline__ void relu_to_frags(
     const f32x16 (&acc)[NT][A::kMB],
     typename Prec<P>::Frag (&x)[NT][Geometry<Prec<P>::KPL, A>::kKBHidden]) {
@@ -302,7 +307,7 @@ __device__ __forceinline__ void relu_to_frags(
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int kb = 0; kb < G::kKBHidden; ++kb) {
+    for (int kb = 0; kb < NKBX; ++kb) {
       const int mb = kb / G::kKBPerMB, r0 = (kb % G::kKBPerMB) * KPL;
       if constexpr (KPL == 1) {
         x[t][kb] = fmaxf(acc[t][mb][r0], 0.0f);
@@ -321,14 +326,14 @@ __device__ __forceinline__ void relu_to_frags(
 }
 
 // FP8 layer: acc += 2^-s (W 2^s) x over E4M3 K-blocks KB0 .. KB0+NKB-1 of a
-// layer with NKBIN K-blocks
-template <class A, int NT, int NKB, int NKBIN, int KB0, int NX>
+// layer with NKBIN K-blocks, first NMB M-blocks
+template <class A, int NT, int NKB, int NKBIN, int KB0, int NMB = A::kMB, int NX>
 __device__ __forceinline__ void mma_layer_e4m3(const i32x8* fr, int lane, int scale_a, const i32x8 (&x)[NT][NX],
                                                f32x16 (&acc)[NT][A::kMB]) {
 #pragma unroll
   for (int kb = 0; kb < NKB; ++kb)
 #pragma unroll
-    for (int mb = 0; mb < A::kMB; ++mb) {
+    for (int mb = 0; mb < NMB; ++mb) {
       const i32x8 a = fr[(mb * NKBIN + KB0 + kb) * 64 + lane];
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[t][mb] = mma_e4m3(a, x[t][kb], acc[t][mb], scale_a);
@@ -341,19 +346,19 @@ __device__ __forceinline__ int pack4_e4m3(const f32x16& a, int r) {
   return pack_e4m3<true>(relu448(a[r + 2]), relu448(a[r + 3]), pack_e4m3<false>(relu448(a[r]), relu448(a[r + 1]), 0));
 }
 
-// ReLU of the accumulators, saturated at 448, into the E4M3 K-blocks of the
-// next layer (byte e of K-block kb: M-block 2kb + e / 16, register e % 16;
-// zero bytes past the last M-block)
-template <class A, int NT>
+// ReLU of the accumulators (the first NMB M-blocks), saturated at 448, into
+// the E4M3 K-blocks of the next layer (byte e of K-block kb: M-block
+// 2kb + e / 16, register e % 16; zero bytes past M-block NMB - 1)
+template <class A, int NT, int NMB = A::kMB>
 __device__ __forceinline__ void relu_to_e4m3(const f32x16 (&acc)[NT][A::kMB], i32x8 (&x)[NT][Fp8<A>::kKBHidden]) {
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int kb = 0; kb < Fp8<A>::kKBHidden; ++kb)
+    for (int kb = 0; kb < (NMB + 1) / 2; ++kb)
 #pragma unroll
       for (int d = 0; d < 8; ++d) {
         const int mb = 2 * kb + d / 4;
-        x[t][kb][d] = mb < A::kMB ? pack4_e4m3(acc[t][mb], 4 * (d % 4)) : 0;
+        x[t][kb][d] = mb < NMB ? pack4_e4m3(acc[t][mb], 4 * (d % 4)) : 0;
       }
 }
 
@@ -484,24 +489,35 @@ __global__ __launch_bounds__(kNifBlock, 1) void k_nif_infer(const uint8_t* gpack
         for (int d = 2 * G::kKBFeat; d < 8; ++d) x8f[t][0][d] = 0;
     }
 
+    // With a skip-concat, layer S - 1 computes only the M-blocks of its
+    // H - 4 NF outputs, and layer S reads only the K-blocks they fill (the
+    // weights of padding rows and columns are zero) followed by the features.
+    constexpr int S = A::kSkip, MBN = A::kMBNarrow;
+    constexpr int MB0 = A::mb_out(0);
     Frag x[NT][G::kKBHidden];
     f32x16 acc[NT][MB];
-    init_acc<NT, A>(lb0, h, acc);
-    mma_layer<P, A, NT, G::kKBFeat, G::kKBFeat, 0>(fr0, lane, xf, acc);
+    init_acc<NT, A, MB0>(lb0, h, acc);
+    mma_layer<P, A, NT, G::kKBFeat, G::kKBFeat, 0, MB0>(fr0, lane, xf, acc);
     if constexpr (P == NPT_FP8) {
       // the first layer on FP16 operands, the hidden-to-hidden layers on
       // E4M3, FP16 input to the output layer
-      constexpr int NKB8 = Fp8<A>::kKBHidden;
+      constexpr int NKB8 = Fp8<A>::kKBHidden, NKB8N = Fp8<A>::kKBNarrow;
       i32x8 x8[NT][NKB8];
-      relu_to_e4m3<A, NT>(acc, x8);
+      relu_to_e4m3<A, NT, MB0>(acc, x8);
 #pragma unroll 1
       for (int l = 1; l < L; ++l) {
-        init_acc<NT, A>(lbias + l * H, h, acc);
         const i32x8* fr = reinterpret_cast<const i32x8*>(hidden(l));
         const int sa = 127 - lscale[l];
-        if (A::kSkip != 0 && l == A::kSkip) {
-          mma_layer_e4m3<A, NT, NKB8, NKB8 + 1, 0>(fr, lane, sa, x8, acc);
-          mma_layer_e4m3<A, NT, 1, NKB8 + 1, NKB8>(fr, lane, sa, x8f, acc);
+        if (S != 0 && l + 1 == S) {
+          init_acc<NT, A, MBN>(lbias + l * H, h, acc);
+          mma_layer_e4m3<A, NT, NKB8, NKB8, 0, MBN>(fr, lane, sa, x8, acc);
+          relu_to_e4m3<A, NT, MBN>(acc, x8);
+          continue;
+        }
+        init_acc<NT, A>(lbias + l * H, h, acc);
+        if (S != 0 && l == S) {
+          mma_layer_e4m3<A, NT, NKB8N, NKB8N + 1, 0>(fr, lane, sa, x8, acc);
+          mma_layer_e4m3<A, NT, 1, NKB8N + 1, NKB8N>(fr, lane, sa, x8f, acc);
         } else {
           mma_layer_e4m3<A, NT, NKB8, NKB8, 0>(fr, lane, sa, x8, acc);
         }
@@ -509,15 +525,21 @@ __global__ __launch_bounds__(kNifBlock, 1) void k_nif_infer(const uint8_t* gpack
       }
       relu_to_frags<P, A, NT>(acc, x);
     } else {
-      relu_to_frags<P, A, NT>(acc, x);
+      relu_to_frags<P, A, NT, (S == 1 ? G::kKBNarrow : G::kKBHidden)>(acc, x);
 #pragma unroll 1
       for (int l = 1; l < L; ++l) {
-        init_acc<NT, A>(lbias + l * H, h, acc);
         const Frag* fr = reinterpret_cast<const Frag*>(hidden(l));
-        if (A::kSkip != 0 && l == A::kSkip) {
-          constexpr int NKBIN = G::kKBHidden + G::kKBFeat;
-          mma_layer<P, A, NT, G::kKBHidden, NKBIN, 0>(fr, lane, x, acc);
-          mma_layer<P, A, NT, G::kKBFeat, NKBIN, G::kKBHidden>(fr, lane, xf, acc);
+        if (S != 0 && l + 1 == S) {
+          init_acc<NT, A, MBN>(lbias + l * H, h, acc);
+          mma_layer<P, A, NT, G::kKBHidden, G::kKBHidden, 0, MBN>(fr, lane, x, acc);
+          relu_to_frags<P, A, NT, G::kKBNarrow>(acc, x);
+          continue;
+        }
+        init_acc<NT, A>(lbias + l * H, h, acc);
+        if (S != 0 && l == S) {
+          constexpr int NKBIN = G::kKBNarrow + G::kKBFeat;
+          mma_layer<P, A, NT, G::kKBNarrow, NKBIN, 0>(fr, lane, x, acc);
+          mma_layer<P, A, NT, G::kKBFeat, NKBIN, G::kKBNarrow>(fr, lane, xf, acc);
         } else {
           mma_layer<P, A, NT, G::kKBHidden, G::kKBHidden, 0>(fr, lane, x, acc);
         }

@@ -95,12 +95,12 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
   constexpr int KPL = Prec<P>::KPL;
   const int lane = threadIdx.x & 63;
   const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int mt = g.M / 32, nt = (g.N + 31) / 32;  // M is a multiple of 32; the last column tile may be partial
+  const int mt = (g.M + 31) / 32, nt = (g.N + 31) / 32;  // the last row and column tiles may be partial
   if (wave >= mt * nt * g.splits) return;
   const int split = wave / (mt * nt), rem = wave % (mt * nt);
   const int m0 = (rem / nt) * 32, n0 = (rem % nt) * 32;
   const int h = lane / 32, c = lane % 32;
-  const bool col_ok = n0 + c < g.N;
+  const bool col_ok = n0 + c < g.N, row_ok = m0 + c < g.M;
   const int kbeg = split * g.k_chunk, kend = min(g.K, kbeg + g.k_chunk);
   const Elem* A = static_cast<const Elem*>(g.A);
   const Elem* B = static_cast<const Elem*>(g.B);
@@ -127,10 +127,13 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
     const int kk = k0 + h * KPL;
     Frag a, b;
     if constexpr (KPL == 1) {
-      a = A[(int64_t)(m0 + c) * g.a_sm + (int64_t)kk * g.a_sk];
+      a = row_ok ? A[(int64_t)(m0 + c) * g.a_sm + (int64_t)kk * g.a_sk] : zero;
       b = col_ok ? B[(int64_t)kk * g.b_sk + (int64_t)(n0 + c) * g.b_sn] : zero;
     } else {
-      if constexpr (AK) {
+      if (!row_ok) {
+#pragma unroll
+        for (int e = 0; e < KPL; ++e) a[e] = zero;
+      } else if constexpr (AK) {
         a = *reinterpret_cast<const Frag*>(A + (int64_t)(m0 + c) * g.a_sm + kk);
       } else {
 #pragma unroll
@@ -154,13 +157,13 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
     const int kk = k0 + h * KPL;
     Frag a, b;
     if constexpr (KPL == 1) {
-      a = kk < kend ? A[(int64_t)(m0 + c) * g.a_sm + (int64_t)kk * g.a_sk] : zero;
+      a = (row_ok && kk < kend) ? A[(int64_t)(m0 + c) * g.a_sm + (int64_t)kk * g.a_sk] : zero;
       b = (col_ok && kk < kend) ? B[(int64_t)kk * g.b_sk + (int64_t)(n0 + c) * g.b_sn] : zero;
     } else {
 #pragma unroll
       for (int e = 0; e < KPL; ++e) {
         const bool in = kk + e < kend;
-        a[e] = in ? A[(int64_t)(m0 + c) * g.a_sm + (int64_t)(kk + e) * g.a_sk] : zero;
+        a[e] = (in && row_ok) ? A[(int64_t)(m0 + c) * g.a_sm + (int64_t)(kk + e) * g.a_sk] : zero;
         b[e] = (in && col_ok) ? B[(int64_t)(kk + e) * g.b_sk + (int64_t)(n0 + c) * g.b_sn] : zero;
       }
     }
@@ -169,12 +172,13 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc g) {
   }
   if (rowsum && c == 0) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) g.a_rowsum[(int64_t)split * g.c_split_stride + m0 + acc_row(0, h, r)] = rsum[r];
+    for (int r = 0; r < 16; ++r)
+      if (m0 + acc_row(0, h, r) < g.M) g.a_rowsum[(int64_t)split * g.c_split_stride + m0 + acc_row(0, h, r)] = rsum[r];
   }
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int m = m0 + acc_row(0, h, r), n = n0 + c;
-    if (!col_ok) continue;
+    if (!col_ok || m >= g.M) continue;
     float val = acc[r];
     if (g.mode == 0) {
       val = fmaxf(val + g.bias[n], 0.0f);
@@ -711,7 +715,7 @@ static hipError_t gemm(const GemmDesc& g, hipStream_t st) {
       return hipGetLastError();
     }
   }
-  const int waves = (g.M / 32) * ((g.N + 31) / 32) * g.splits;
+  const int waves = ((g.M + 31) / 32) * ((g.N + 31) / 32) * g.splits;
   hipLaunchKernelGGL((k_gemm<P, AK, BK>), dim3((waves + 3) / 4), dim3(256), 0, st, g);
   return hipGetLastError();
 }
@@ -738,7 +742,7 @@ static hipError_t step_gradient(TrainScratch& s, const TrainConfig& c, const Tra
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (sh.skip != 0) {
     hipLaunchKernelGGL(k_copy_features<P>, dim3(4096), dim3(256), 0, st, acts[0], B, shape_feat(sh), acts[sh.skip],
-                       shape_in(sh, sh.skip), H);
+                       shape_in(sh, sh.skip), shape_skip_col(sh));
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   for (int l = 0; l < L; ++l) {
@@ -750,7 +754,7 @@ static hipError_t step_gradient(TrainScratch& s, const TrainConfig& c, const Tra
     g.b_sk = 1;
     g.b_sn = shape_in(sh, l);
     g.M = (int)B;
-    g.N = H;
+    g.N = shape_out(sh, l);
     g.K = shape_in(sh, l);
     g.k_chunk = g.K;
     g.splits = 1;
@@ -777,7 +781,8 @@ static hipError_t step_gradient(TrainScratch& s, const TrainConfig& c, const Tra
   if ((e = hipGetLastError()) != hipSuccess) return e;
   int cur = 0;
   for (int l = L - 1; l >= 0; --l) {
-    // dW_l = dP_l^T act_l and db_l, split over batch chunks
+    // dW_l = dP_l^T act_l and db_l, split over batch chunks (dP rows are
+    // H apart; a narrowed layer uses the first shape_out(l) of them)
     GemmDesc g{};
     g.A = dp[cur];
     g.a_sm = 1;
@@ -785,7 +790,7 @@ static hipError_t step_gradient(TrainScratch& s, const TrainConfig& c, const Tra
     g.B = acts[l];
     g.b_sk = shape_in(sh, l);
     g.b_sn = 1;
-    g.M = H;
+    g.M = shape_out(sh, l);
     g.N = shape_in(sh, l);
     g.K = (int)B;
     g.k_chunk = chunk;
@@ -806,9 +811,9 @@ static hipError_t step_gradient(TrainScratch& s, const TrainConfig& c, const Tra
     d.b_sk = shape_in(sh, l);
     d.b_sn = 1;
     d.M = (int)B;
-    d.N = H;  // the hidden part of layer l's input (not the features of a skip-concat)
-    d.K = H;
-    d.k_chunk = H;
+    d.N = shape_out(sh, l - 1);  // the hidden part of layer l's input (not the features of a skip-concat)
+    d.K = shape_out(sh, l);
+    d.k_chunk = d.K;
     d.splits = 1;
     d.mode = 1;
     d.mask = acts[l];
@@ -859,10 +864,7 @@ static hipError_t run_p(TrainScratch& s, const TrainConfig& c, const TrainTarget
 
 static hipError_t dispatch(TrainScratch& s, const TrainConfig& c, const TrainTargets& t, uint32_t step0,
                            uint32_t steps, bool update, float* grad_out, float* loss_out, hipStream_t st) {
-  if (c.batch % kChunkMax != 0 || c.shape.hidden % 32 != 0 || c.shape.layers < 1 ||
-      (c.shape.skip != 0 && (c.shape.skip < 1 || c.shape.skip >= c.shape.layers)) || c.shape.n_freq < 1 ||
-      c.shape.n_freq > 16)
-    return hipErrorInvalidValue;
+  if (c.batch % kChunkMax != 0 || !shape_ok(c.shape)) return hipErrorInvalidValue;
   hipError_t e = ensure_scratch(s, c.batch, c.prec, update ? steps : 1, c.shape);
   if (e != hipSuccess) return e;
   switch (c.prec) {
@@ -1031,7 +1033,7 @@ static hipError_t layered_p(LayeredScratch& ls, const NifShape& sh, const void* 
     n = c;
   }
   if (n == 0) return hipSuccess;
-  const size_t need = (size_t)kLayeredChunk * (H + shape_feat(sh)) * sizeof(Elem);
+  const size_t need = (size_t)kLayeredChunk * std::max(H, shape_feat(sh)) * sizeof(Elem);
   if (need > ls.cap) {
     ls.release();
     for (void*& p : ls.x)
@@ -1041,6 +1043,7 @@ static hipError_t layered_p(LayeredScratch& ls, const NifShape& sh, const void* 
   for (uint64_t base = 0; base < n; base += kLayeredChunk) {
     const uint32_t rows = (uint32_t)(((std::min<uint64_t>(kLayeredChunk, n - base)) + 31) / 32 * 32);
     // x[2]: the features (kept for a skip-concat); x[0] / x[1]: layer outputs
+    // (rows hidden apart)
     Elem* x[3] = {static_cast<Elem*>(ls.x[0]), static_cast<Elem*>(ls.x[1]), static_cast<Elem*>(ls.x[2])};
     hipLaunchKernelGGL(k_layered_features<P>, dim3((rows + 255) / 256), dim3(256), 0, st, io, n, base, rows,
                        sh.n_freq, x[2]);
@@ -1055,7 +1058,7 @@ static hipError_t layered_p(LayeredScratch& ls, const NifShape& sh, const void* 
       g.b_sk = 1;
       g.b_sn = shape_in(sh, l);
       g.M = (int)rows;
-      g.N = H;
+      g.N = shape_out(sh, l);
       g.K = shape_in(sh, l);
       g.k_chunk = g.K;
       g.splits = 1;
@@ -1066,7 +1069,7 @@ static hipError_t layered_p(LayeredScratch& ls, const NifShape& sh, const void* 
       if ((e = gemm<P, true, true>(g, st)) != hipSuccess) return e;
       if (sh.skip != 0 && l + 1 == sh.skip) {
         hipLaunchKernelGGL(k_copy_features<P>, dim3(4096), dim3(256), 0, st, x[2], rows, shape_feat(sh), x[nxt],
-                           shape_in(sh, l + 1), H);
+                           shape_in(sh, l + 1), shape_skip_col(sh));
         if ((e = hipGetLastError()) != hipSuccess) return e;
       }
       cur = nxt;
@@ -1081,9 +1084,7 @@ static hipError_t layered_p(LayeredScratch& ls, const NifShape& sh, const void* 
 
 hipError_t nif_layered(LayeredScratch& ls, int prec, const NifShape& shape, const void* wp, const float* master,
                        const ColourMatrix& cm, const LayeredIO& io, hipStream_t st) {
-  if (shape.hidden % 32 != 0 || shape.hidden < 32 || shape.layers < 1 || shape.skip < 0 ||
-      (shape.skip != 0 && shape.skip >= shape.layers) || shape.n_freq < 1 || shape.n_freq > 16)
-    return hipErrorInvalidValue;
+  if (!shape_ok(shape)) return hipErrorInvalidValue;
   switch (prec) {
     case NPT_FP32: return layered_p<NPT_FP32>(ls, shape, wp, master, cm, io, st);
     case NPT_FP16: return layered_p<NPT_FP16>(ls, shape, wp, master, cm, io, st);

@@ -596,7 +596,8 @@ extern "C" int npt_set_env_mode(npt_ctx* c, int mode) {
 // ===========================================================================
 static bool nif_desc_ok(const npt_nif_desc* d) {
   return d && d->n_freq >= 1 && d->n_freq <= (uint32_t)nif::kMaxFreq && d->hidden >= 32 && d->hidden <= 1024 &&
-         d->hidden % 32 == 0 && d->layers >= 1 && d->layers <= 8 && (d->skip == 0 || d->skip < d->layers);
+         d->hidden % 32 == 0 && d->layers >= 1 && d->layers <= 8 &&
+         (d->skip == 0 || (d->skip < d->layers && d->hidden > 4 * d->n_freq));
 }
 
 // log-space RGB = M * network output for the colour spaces of Sec. 4.3:
@@ -615,7 +616,7 @@ extern "C" int npt_nif_upload(npt_ctx* c, const npt_nif_desc* desc, const float*
     if (!nif_desc_ok(desc))
       return fail(c, NPT_E_UNSUPPORTED,
                   "NIF shape must be n_freq 1..16, hidden 32..1024 (a multiple of 32), layers 1..8, "
-                  "skip 0 or < layers");
+                  "skip 0 or < layers with hidden > 4 n_freq");
     if (desc->colour > NPT_COLOUR_YCOCG) return fail(c, NPT_E_INVALID_ARG, "unknown NIF colour space");
     const NifShape shape{(int)desc->hidden, (int)desc->layers, (int)desc->skip, (int)desc->n_freq};
     const int arch = nif::resident_arch(shape.hidden, shape.layers, shape.skip, shape.n_freq);
@@ -719,7 +720,8 @@ static void train_defaults(npt_ctx* c, const npt_train_params* p, TrainConfig& t
   t.delta = p && p->huber_delta > 0 ? p->huber_delta : 1e-3f;
   t.seed = p ? p->seed : 0;
   t.prec = p ? (int)p->grad_prec : NPT_FP32;
-  t.loss_scale = p && p->loss_scale > 0 ? p->loss_scale : 1024.0f;
+  // Sec. 3.2.1 trains with FP16 gradients under a loss scale of 16384
+  t.loss_scale = p && p->loss_scale > 0 ? p->loss_scale : (t.prec == NPT_FP16 ? 16384.0f : 1.0f);
   t.master_prec = p ? (int)p->master_prec : NPT_FP32;
 }
 

@@ -3,7 +3,9 @@
 //
 // Network (Sec. 3.2): 4*NF Fourier features -> L x [dense H + ReLU] -> dense
 // 3 -> fixed colour matrix -> expm1; with a skip layer S (Sec. 3.2, the
-// paper's own architecture) hidden layer S takes [h ; features].
+// paper's own architecture) hidden layer S takes [h ; features], where h is
+// the output of layer S - 1, narrowed to H - 4 NF units so that the
+// concatenation is H wide.
 //
 // MFMA 32x32xK (K = 2 for FP32 operands, 16 for FP16/BF16): lane l holds,
 // per K-block, KPL = K/2 consecutive k of row/column l % 32 in lane half
@@ -44,13 +46,20 @@ struct Arch {
   static_assert(L >= 1 && L + 1 <= kScaleWords, "layer count");
   static_assert(S == 0 || (S >= 1 && S < L), "skip layer is a hidden layer after the first");
   static_assert(NF >= 1 && NF <= kMaxFreq, "frequency count");
+  static_assert(S == 0 || 4 * NF < H, "the layer before a skip-concat keeps some outputs");
   static constexpr int kHidden = H, kLayers = L, kSkip = S, kFreq = NF;
   static constexpr int kFeat = 4 * NF;
   static constexpr int kMB = H / 32;  // M-blocks of a hidden layer
-  static constexpr int kBiasFloats = L * H + 32;  // bias table: L x H, then 32 for the output layer
+  // outputs of the layer before the skip layer, and its M-blocks
+  static constexpr int kNarrow = S != 0 ? H - kFeat : H;
+  static constexpr int kMBNarrow = (kNarrow + 31) / 32;
+  static constexpr int kBiasFloats = L * H + 32;  // bias table: L x H (zero past a layer's outputs), then 32
   __host__ __device__ static constexpr bool is_skip(int l) { return S != 0 && l == S; }
-  __host__ __device__ static constexpr int layer_in(int l) { return l == 0 ? kFeat : is_skip(l) ? H + kFeat : H; }
-  __host__ __device__ static constexpr int layer_out(int l) { return l == L ? kOut : H; }
+  __host__ __device__ static constexpr bool is_narrow(int l) { return S != 0 && l + 1 == S; }
+  __host__ __device__ static constexpr int layer_in(int l) { return l == 0 ? kFeat : H; }
+  __host__ __device__ static constexpr int layer_out(int l) { return l == L ? kOut : is_narrow(l) ? kNarrow : H; }
+  // M-blocks a hidden layer computes
+  __host__ __device__ static constexpr int mb_out(int l) { return is_narrow(l) ? kMBNarrow : kMB; }
   __host__ __device__ static constexpr int w_offset(int l) {
     int o = 0;
     for (int i = 0; i < l; ++i) o += layer_out(i) * layer_in(i) + layer_out(i);
@@ -68,13 +77,14 @@ struct Geometry {
   static constexpr int kKBPerMB = 16 / KPL;                     // K-blocks from one 32-row M-block
   static constexpr int kKBFeat = (A::kFeat + kKB - 1) / kKB;    // K-blocks of the features (zero padded)
   static constexpr int kKBHidden = A::kHidden / kKB;            // K-blocks of a hidden activation
+  static constexpr int kKBNarrow = A::kMBNarrow * kKBPerMB;     // ... of the narrowed layer's output
   __host__ __device__ static constexpr int kb_in(int l) {
-    return l == 0 ? kKBFeat : A::is_skip(l) ? kKBHidden + kKBFeat : kKBHidden;
+    return l == 0 ? kKBFeat : A::is_skip(l) ? kKBNarrow + kKBFeat : kKBHidden;
   }
   // fragments (64 lanes x KPL elements) of layer l; the output layer's
   // 2 * 3 * kb_in compact fragments of KPL elements count as a fraction
   __host__ __device__ static constexpr int elems(int l) {
-    return l == A::kLayers ? kb_in(l) * 2 * 3 * KPL : A::kMB * kb_in(l) * 64 * KPL;
+    return l == A::kLayers ? kb_in(l) * 2 * 3 * KPL : A::mb_out(l) * kb_in(l) * 64 * KPL;
   }
   __host__ __device__ static constexpr int elem_offset(int l) {
     int o = 0;
@@ -86,17 +96,20 @@ struct Geometry {
 
 // Input index (column of W_l) fed by element e of lane half h in K-block kb,
 // or -1 for zero padding.  Features (layer 0, and the K-blocks of a skip
-// layer after its hidden input) come in natural order.
+// layer after its hidden input) come in natural order; a skip layer's hidden
+// K-blocks hold the narrowed layer's outputs (columns 0 .. kNarrow - 1, rows
+// past them padding) and its features columns kNarrow ...
 template <int KPL, class A>
 __host__ __device__ constexpr int input_index(int l, int kb, int h, int e) {
   using G = Geometry<KPL, A>;
-  if (l == 0 || (A::is_skip(l) && kb >= G::kKBHidden)) {
-    const int f = (l == 0 ? kb : kb - G::kKBHidden) * G::kKB + h * KPL + e;
-    return f >= A::kFeat ? -1 : l == 0 ? f : A::kHidden + f;
+  if (l == 0 || (A::is_skip(l) && kb >= G::kKBNarrow)) {
+    const int f = (l == 0 ? kb : kb - G::kKBNarrow) * G::kKB + h * KPL + e;
+    return f >= A::kFeat ? -1 : l == 0 ? f : A::kNarrow + f;
   }
   const int mb = kb / G::kKBPerMB;
   const int r = (kb % G::kKBPerMB) * KPL + e;
-  return acc_row(mb, h, r);
+  const int row = acc_row(mb, h, r);
+  return A::is_skip(l) && row >= A::kNarrow ? -1 : row;
 }
 
 // FP8 hidden-to-hidden layers (1..L-1) on MFMA 32x32x64: 32 E4M3 values per
@@ -108,27 +121,33 @@ __host__ __device__ constexpr int input_index(int l, int kb, int h, int e) {
 template <class A>
 struct Fp8 {
   static constexpr int kKBHidden = (A::kMB + 1) / 2;
+  static constexpr int kKBNarrow = (A::kMBNarrow + 1) / 2;  // K-blocks of the narrowed layer's output
   __host__ __device__ static constexpr bool layer(int l) { return l >= 1 && l < A::kLayers; }
-  __host__ __device__ static constexpr int kb_in(int l) { return kKBHidden + (A::is_skip(l) ? 1 : 0); }
-  __host__ __device__ static constexpr int layer_bytes(int l) { return A::kMB * kb_in(l) * 64 * 32; }
+  __host__ __device__ static constexpr int kb_in(int l) { return A::is_skip(l) ? kKBNarrow + 1 : kKBHidden; }
+  __host__ __device__ static constexpr int layer_bytes(int l) { return A::mb_out(l) * kb_in(l) * 64 * 32; }
   __host__ __device__ static constexpr int input_index(int l, int kb, int h, int e) {
-    if (kb < kKBHidden) {
+    const bool skip = A::is_skip(l);
+    if (kb < (skip ? kKBNarrow : kKBHidden)) {
       const int mb = 2 * kb + e / 16;
-      return mb < A::kMB ? acc_row(mb, h, e % 16) : -1;
+      if (mb >= (skip ? A::kMBNarrow : A::kMB)) return -1;
+      const int row = acc_row(mb, h, e % 16);
+      return skip && row >= A::kNarrow ? -1 : row;
     }
     const int kb16 = e / 8;
     const int f = kb16 * 16 + h * 8 + e % 8;
-    return (kb16 < Geometry<8, A>::kKBFeat && f < A::kFeat) ? A::kHidden + f : -1;
+    return (kb16 < Geometry<8, A>::kKBFeat && f < A::kFeat) ? A::kNarrow + f : -1;
   }
 };
 
 // Shapes with an LDS-resident inference kernel (any other shape runs on the
-// layer-serial GEMM path): the default 16/96/5 network, the paper's H128 L5
-// network with the features concatenated at hidden layer 2 (40-d and 64-d
-// features), and the small H64 L2 network of the model-size study.
+// layer-serial GEMM path): the default 16/96/5 network, the paper's network
+// (40-d features, H128, four dense-ReLU layers the second of which is
+// narrowed to 88 outputs and followed by the features: with the linear output
+// layer, five trainable layers and 97.7 KiB in FP16), the same with 64-d
+// features, and the small H64 L2 network of the model-size study.
 using ArchDefault = Arch<96, 5, 0, 16>;
-using ArchH128Skip40 = Arch<128, 5, 2, 10>;
-using ArchH128Skip64 = Arch<128, 5, 2, 16>;
+using ArchH128Skip40 = Arch<128, 4, 2, 10>;
+using ArchH128Skip64 = Arch<128, 4, 2, 16>;
 using ArchH64 = Arch<64, 2, 0, 16>;
 constexpr int kNumArch = 4;
 
@@ -136,8 +155,8 @@ constexpr int kNumArch = 4;
 inline int resident_arch(int hidden, int layers, int skip, int n_freq) {
   auto is = [&](int H, int L, int S, int NF) { return hidden == H && layers == L && skip == S && n_freq == NF; };
   if (is(96, 5, 0, 16)) return 0;
-  if (is(128, 5, 2, 10)) return 1;
-  if (is(128, 5, 2, 16)) return 2;
+  if (is(128, 4, 2, 10)) return 1;
+  if (is(128, 4, 2, 16)) return 2;
   if (is(64, 2, 0, 16)) return 3;
   return -1;
 }

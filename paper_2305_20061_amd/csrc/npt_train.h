@@ -15,7 +15,9 @@ namespace npt {
 // [dense hidden + ReLU] -> dense 3.  hidden is a multiple of 32 (the MFMA
 // tile).  skip: 0, or the hidden layer (1..layers-1) whose input is the
 // previous layer's output followed by the features again (skip-concat,
-// Sec. 3.2).
+// Sec. 3.2); that previous layer is narrowed to hidden - 4 n_freq outputs so
+// that the concatenation, and so every hidden layer's input after the first,
+// is hidden wide.
 struct NifShape {
   int hidden;
   int layers;
@@ -23,10 +25,17 @@ struct NifShape {
   int n_freq;
 };
 __host__ __device__ inline int shape_feat(const NifShape& s) { return 4 * s.n_freq; }
-__host__ __device__ inline int shape_in(const NifShape& s, int l) {
-  return l == 0 ? shape_feat(s) : (s.skip != 0 && l == s.skip ? s.hidden + shape_feat(s) : s.hidden);
+__host__ __device__ inline int shape_in(const NifShape& s, int l) { return l == 0 ? shape_feat(s) : s.hidden; }
+__host__ __device__ inline int shape_out(const NifShape& s, int l) {
+  return l == s.layers ? 3 : (s.skip != 0 && l + 1 == s.skip ? s.hidden - shape_feat(s) : s.hidden);
 }
-__host__ __device__ inline int shape_out(const NifShape& s, int l) { return l == s.layers ? 3 : s.hidden; }
+// column of layer `skip`'s input where the features start
+__host__ __device__ inline int shape_skip_col(const NifShape& s) { return s.hidden - shape_feat(s); }
+// shapes the training and layer-serial kernels accept
+__host__ __device__ inline bool shape_ok(const NifShape& s) {
+  return s.hidden >= 32 && s.hidden % 32 == 0 && s.layers >= 1 && s.n_freq >= 1 && s.n_freq <= 16 &&
+         (s.skip == 0 || (s.skip >= 1 && s.skip < s.layers && s.hidden > shape_feat(s)));
+}
 // offsets of W_l and b_l in the flat parameter vector [W_0, b_0, ..., W_L, b_L]
 __host__ __device__ inline int64_t shape_w_offset(const NifShape& s, int l) {
   int64_t o = 0;
@@ -104,7 +113,7 @@ struct LayeredIO {
   uint32_t gw, gh;
 };
 struct LayeredScratch {
-  void* x[3] = {nullptr, nullptr, nullptr};  // ping-pong activations [chunk][hidden + 4 n_freq], features
+  void* x[3] = {nullptr, nullptr, nullptr};  // ping-pong activations [chunk][hidden], features [chunk][4 n_freq]
   size_t cap = 0;                   // bytes of each
   void release();
 };

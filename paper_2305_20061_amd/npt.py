@@ -281,9 +281,10 @@ def npt_set_env_mode(ctx, mode):
 
 # ---------------------------------------------------------------------- NIF
 def nif_param_count(hidden=96, layers=5, skip=0, n_freq=16):
+    """With a skip-concat the layer before it has hidden - 4 n_freq outputs."""
     F = 4 * n_freq
-    return F * hidden + hidden + (layers - 1) * (hidden * hidden + hidden) + 3 * hidden + 3 + (F * hidden if skip
-                                                                                               else 0)
+    return (F * hidden + hidden + (layers - 1) * (hidden * hidden + hidden) + 3 * hidden + 3
+            - (F * (hidden + 1) if skip else 0))
 
 
 def npt_nif_upload(ctx, params, n_freq=16, hidden=96, layers=5, stream=None, colour=0, layered=0, skip=0):

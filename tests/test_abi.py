@@ -68,10 +68,11 @@ def test_host_only_validation(host_ctx):
     assert _code(npt.npt_nif_upload, c, np.zeros(43779), hidden=128) == "INVALID_ARG"  # count of another shape
     assert npt.nif_param_count(128, 3) == 64 * 128 + 128 + 2 * (128 * 128 + 128) + 3 * 128 + 3
     assert npt.nif_param_count() == 43779
-    assert npt.nif_param_count(128, 5, 2) == npt.nif_param_count(128, 5) + 64 * 128
+    # skip-concat: the layer before it has 128 - 64 outputs (64 fewer rows of 129)
+    assert npt.nif_param_count(128, 4, 2) == npt.nif_param_count(128, 4) - 64 * 129
     assert _code(npt.npt_nif_upload, c, np.zeros(43779), skip=5) == "UNSUPPORTED"  # skip must be < layers
     assert _code(npt.npt_nif_upload, c, np.zeros(43779), n_freq=17) == "UNSUPPORTED"
-    assert npt.nif_param_count(128, 5, 2, 10) == 40 * 128 + 128 + 4 * (128 * 128 + 128) + 3 * 128 + 3 + 40 * 128
+    assert npt.nif_param_count(128, 4, 2, 10) == (40 * 128 + 128) + (128 * 88 + 88) + 2 * (128 * 128 + 128) + 3 * 128 + 3
     assert _code(npt.npt_nif_upload, c, np.zeros(43779), colour=3) == "INVALID_ARG"
     assert _code(npt.npt_env_upload, c, np.zeros((4, 8, 3))) == "NO_DEVICE"
     assert _code(npt.npt_env_upload, c, -np.ones((4, 8, 3))) == "NAN_INPUT"

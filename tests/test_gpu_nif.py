@@ -20,8 +20,9 @@ assert (O.PREC_FP32, O.PREC_FP16, O.PREC_BF16, O.PREC_FP8) == (npt.FP32, npt.FP1
 # relative-RMSE bounds of the radiance of one query batch against the oracle
 # with the same operand rounding: what is left is FP32 accumulation order
 # and the FP32 features, which move an operand across a rounding boundary now
-# and then (one unit in its last place: 2^-11 FP16, 2^-8 BF16, 2^-4 E4M3)
-QUERY_TOL = {npt.FP32: 2e-4, npt.FP16: 2e-3, npt.BF16: 1e-2, npt.FP8: 2e-2}
+# and then (one unit in its last place: 2^-11 FP16, 2^-8 BF16, 2^-4 E4M3).
+# FP16 at 1e-3 is the image gate of the FP16-NIF configurations.
+QUERY_TOL = {npt.FP32: 5e-5, npt.FP16: 1e-3, npt.BF16: 1e-2, npt.FP8: 2e-2}
 
 
 def _weights(seed=3):
@@ -106,10 +107,18 @@ def test_nif_render_matches_oracle_low_precision(prec, small_sky):
     assert r <= QUERY_TOL[prec]
 
 
-GRAD_TOL = {npt.FP32: 1e-4, npt.FP16: 3e-2, npt.BF16: 1e-1}
-# relative loss error: FP32 rounding only; FP16 / BF16 activations carry
-# 2^-11 / 2^-8 relative rounding into the outputs
-LOSS_TOL = {npt.FP32: 1e-5, npt.FP16: 1e-3, npt.BF16: 1e-2}
+# Training gradients: against the oracle whose GEMM operands are rounded as
+# the trainer's (same loss scale; FP32 summation order and FP32 features
+# are what is left), and against the FP64 gradient without rounding; bounds
+# are the measured errors with a margin of about 3x (measured at batch 2048:
+# gradients 1.0e-6 / 1.8e-6 / 2.6e-5 against the rounded oracle, 1.0e-6 /
+# 1.2e-3 / 4.1e-3 against FP64; losses 2e-7 / 3e-7 / 4e-7 against the
+# rounded oracle, 2e-7 / 7.3e-5 / 1.1e-4 against FP64)
+LOSS_SCALE = {npt.FP32: 1.0, npt.FP16: 16384.0, npt.BF16: 1.0}  # the trainer's defaults
+GRAD_TOL_Q = {npt.FP32: 3e-6, npt.FP16: 6e-6, npt.BF16: 8e-5}
+LOSS_TOL_Q = {npt.FP32: 1e-6, npt.FP16: 1e-6, npt.BF16: 2e-6}
+GRAD_TOL = {npt.FP32: 3e-6, npt.FP16: 4e-3, npt.BF16: 1.2e-2}
+LOSS_TOL = {npt.FP32: 1e-6, npt.FP16: 2.5e-4, npt.BF16: 4e-4}
 
 
 @pytest.mark.parametrize("prec", [npt.FP32, npt.FP16, npt.BF16])
@@ -132,8 +141,12 @@ def test_training_gradient_matches_oracle(prec, small_sky):
         npt.npt_destroy(ctx)
     uv, tg = O.nif_train_batch(small_sky, seed, step, B)
     lo, go = O.nif_loss_grad(SHAPE, p.astype(np.float64), uv, tg, 1e-3)
-    r = rel_rmse(g, go)
-    print(f"grad prec {prec}: relRMSE {r:.3e}, loss {lg:.6e} vs {lo:.6e}")
+    lq, gq = O.nif_loss_grad_q(SHAPE, p.astype(np.float64), prec, LOSS_SCALE[prec], uv, tg, 1e-3)
+    r, rq = rel_rmse(g, go), rel_rmse(g, gq)
+    print(f"grad prec {prec}: relRMSE {rq:.3e} (rounded oracle), {r:.3e} (FP64); loss {lg:.7e} vs {lq:.7e} "
+          f"(rounded), {lo:.7e} (FP64)")
+    assert abs(lg - lq) <= LOSS_TOL_Q[prec] * abs(lq)
+    assert rq <= GRAD_TOL_Q[prec]
     assert abs(lg - lo) <= LOSS_TOL[prec] * abs(lo)
     assert r <= GRAD_TOL[prec]
 
@@ -153,12 +166,19 @@ def test_adam_step_matches_oracle(small_sky):
     m, v = np.zeros_like(ref), np.zeros_like(ref)
     lo = O.nif_train_step(SHAPE, ref, m, v, small_sky, seed, 0, B)
     assert st["steps"] == 1 and abs(st["first_loss"] - lo) <= 1e-4 * lo
-    dg, do = q - p, ref - p
-    # first Adam step is -lr * g / (|g| + eps): sign agreement wherever the
-    # oracle's step is not tiny, magnitudes within 1e-3 absolute of lr
-    big = np.abs(do) > 1e-4
-    assert np.mean(np.sign(dg[big]) == np.sign(do[big])) > 0.999
-    assert np.abs(dg - do).max() < 1e-3 * 1e-3 + 2e-4
+    dg, do = q - p.astype(np.float32).astype(np.float64), ref - p
+    # the first Adam step is -lr g / (|g| + eps): lr (1e-3) times the sign of
+    # g wherever |g| >> eps = 1e-7, less where |g| is near eps.  Measured: the
+    # largest difference 4.3e-5 lr over all weights (FP32 weight rounding and
+    # the FP32 gradient's error), 9.8e-6 lr among the full-size steps
+    lr = 1e-3
+    full = np.abs(do) > 0.5 * lr
+    err = np.abs(dg - do)
+    print(f"Adam step: {full.mean():.4f} of steps full size; max error there {err[full].max() / lr:.2e} lr; "
+          f"{np.count_nonzero(err > 1e-3 * lr)} weights beyond 1e-3 lr, max {err.max() / lr:.2e} lr")
+    assert full.mean() > 0.8
+    assert err[full].max() <= 3e-5 * lr
+    assert err.max() <= 1.5e-4 * lr
 
 
 def test_training_beats_untrained_network(sky_map):

@@ -1,7 +1,8 @@
 """LDS-resident NIF inference for the network shapes other than the default
-that have their own kernel (Sec. 3.2, 4.6): the paper's H128 L5 network with
-the features concatenated at hidden layer 2 (40-d and 64-d features) and the
-small H64 L2 network.  Queries in FP32/FP16/BF16/FP8 against the oracle's
+that have their own kernel (Sec. 3.2, 4.6): the paper's H128 network (four
+dense-ReLU layers, the second narrowed so that the features concatenated to
+its output make 128 inputs; 40-d and 64-d features) and the small H64 L2
+network.  Queries in FP32/FP16/BF16/FP8 against the oracle's
 forward pass with the same operand rounding, the dequantised weights bit for
 bit, a NIF-lit render, the grid evaluation against the layer-serial path, and
 which shapes accept FP8."""
@@ -15,11 +16,11 @@ from gpu_util import gpu_render, make_ctx, oracle_scene, rel_rmse, torch_cuda
 
 pytestmark = pytest.mark.gpu
 # (hidden, layers, skip-concat layer, frequencies)
-ARCHS = [(128, 5, 2, 10), (128, 5, 2, 16), (64, 2, 0, 16)]
+ARCHS = [(128, 4, 2, 10), (128, 4, 2, 16), (64, 2, 0, 16)]
 PRECS = [npt.FP32, npt.FP16, npt.BF16, npt.FP8]
 # as for the default network: accumulation order, and FP32 features that move
 # an operand across a rounding boundary now and then
-QUERY_TOL = {npt.FP32: 2e-4, npt.FP16: 2e-3, npt.BF16: 1e-2, npt.FP8: 2e-2}
+QUERY_TOL = {npt.FP32: 5e-5, npt.FP16: 1e-3, npt.BF16: 1e-2, npt.FP8: 2e-2}
 
 
 def _weights(hidden, layers, skip, nf, seed=3):

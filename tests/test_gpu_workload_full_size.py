@@ -56,10 +56,11 @@ def test_large_bvh_fp8_nif_full_size_rows_match_oracle():
 @pytest.mark.timeout(600)
 def test_spheres_paper_network_fp8_full_size_rows_match_oracle():
     # the spheres scene of the model-size study (1024x1024, 16 spp, depth 8)
-    # lit by the paper's network (10 frequencies, H128 L5, skip-concat at
-    # layer 2) trained on the device and run in FP8 on its LDS-resident kernel
+    # lit by the paper's network (10 frequencies, H128, four dense-ReLU
+    # layers, skip-concat at layer 2) trained on the device and run in FP8 on
+    # its LDS-resident kernel
     W, H, spp, depth, seed = 1024, 1024, 16, 8, 1
-    hidden, layers, skip, nf = 128, 5, 2, 10
+    hidden, layers, skip, nf = 128, 4, 2, 10
     scene = synth.scene_for(2)
     ctx = npt.npt_create(0)
     try:
@@ -98,7 +99,9 @@ def test_spheres_paper_network_fp8_full_size_rows_match_oracle():
 CONFIGS = [(1, 512, 512, 16, 6, npt.FP16, (100, 400)),
            (2, 1024, 1024, 64, 8, npt.BF16, (250, 750)),
            (3, 1920, 1080, 32, 6, npt.FP16, (200, 700))]
-OPERAND_TOL = {npt.FP16: 2e-3, npt.BF16: 1e-2}  # as for the query and render tests
+# FP16-NIF images (open box, small BVH) are held to the 1e-3 image gate; BF16
+# to the BF16 operand bound of the query and render tests
+OPERAND_TOL = {npt.FP16: 1e-3, npt.BF16: 1e-2}
 
 
 @pytest.mark.timeout(600)

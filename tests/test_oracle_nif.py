@@ -241,9 +241,10 @@ def test_skip_param_count():
     assert O.nif_param_count(SKIP) == n == synth.nif_param_count(4, 32, 4, 2) == synth.nif_init(1, 4, 32, 4, 2).size
     # the plain network minus the 16 rows (weights and biases) the narrowed layer drops
     assert n == O.nif_param_count(O.nif_shape(4, 32, 4)) - 16 * (32 + 1)
-    # the paper's shape: 40-d features, H128 L5, concatenation at hidden layer 2
-    paper = O.nif_shape(10, 128, 5, O.COLOUR_YUV, 2)
-    assert O.nif_param_count(paper) == (40 * 128 + 128) + (128 * 88 + 88) + 3 * (128 * 128 + 128) + (3 * 128 + 3)
+    # the paper's shape: 40-d features, H128, four dense-ReLU layers,
+    # concatenation at hidden layer 2
+    paper = O.nif_shape(10, 128, 4, O.COLOUR_YUV, 2)
+    assert O.nif_param_count(paper) == (40 * 128 + 128) + (128 * 88 + 88) + 2 * (128 * 128 + 128) + (3 * 128 + 3)
 
 
 @pytest.mark.parametrize("feat", [0, 5, 15])
