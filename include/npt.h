@@ -301,6 +301,27 @@ int npt_env_query(npt_ctx *ctx, int mode, const float *d_dirs, uint64_t n, float
  * NPT_E_NO_ENV: environment mode without a map or NIF weights. */
 int npt_render(npt_ctx *ctx, uint32_t width, uint32_t height, uint32_t spp, uint32_t max_depth,
                uint64_t seed, float *d_radiance, void *stream);
+
+/* ---- allocation-free rendering ------------------------------------------------ */
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * render as npt_render, bit for bit, with the path pool, accumulator and
+ * counters taken from a fixed scratch array of NPT_NOALLOC_SCRATCH_BYTES
+ * (64 MiB) that the library holds on every GPU it runs on until the process
+ * ends.  Nothing is allocated on the device, and no hipMalloc / hipFree is
+ * called.  Samples per pass are as many as fit (about 176 bytes per pixel per
+ * sample of the pass, at most npt_render_options.samples_per_pass when set);
+ * an image of more than about 380,000 pixels does not fit: NPT_E_INVALID_ARG.
+ * Environment mode NPT_ENV_NIF needs a network shape with an LDS-resident
+ * kernel (the layer-serial path allocates): NPT_E_UNSUPPORTED otherwise.
+ * Other errors as npt_render.  Every call on one GPU shares that GPU's
+ * array (the kernels clear the counters and the accumulator themselves), so
+ * calls that overlap on one GPU -- other contexts, other threads, other
+ * streams -- race and must be serialised by the caller.  No kernel timing:
+ * npt_get_stats afterwards reports paths, passes and samples per pass. */
+#define NPT_NOALLOC_SCRATCH_BYTES (64u << 20)
+int npt_render_noalloc(npt_ctx *ctx, uint32_t width, uint32_t height, uint32_t spp, uint32_t max_depth,
+                       uint64_t seed, float *d_radiance, void *stream);
 /* Primary hits of sample `sample` (Table 3-style checks): d_prim / d_inst
  * [H*W] u32 (0xFFFFFFFF on miss), d_t [H*W] FP32 (+inf on miss), d_normal
  * [H*W][3] geometric normal (0 on miss).  Any output may be NULL. */

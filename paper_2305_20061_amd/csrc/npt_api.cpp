@@ -108,6 +108,8 @@ struct npt_ctx {
 
   // render scratch
   DevBuf qa_o, qa_d, qa_b, qb_o, qb_d, qb_b, env_d, env_b, d_L, d_hits, d_accum, d_cnt, d_stats;
+  void* noalloc_scratch = nullptr;  // this device's fixed scratch (npt_render_noalloc)
+  hipError_t noalloc_status = hipErrorNotInitialized;
   npt_stats stats{};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::vector<hipEvent_t> event_pool, trace_events, shade_events, env_events;
@@ -284,6 +286,11 @@ extern "C" int npt_create(npt_ctx** out, int device) {
         delete c;
         return NPT_E_HIP;
       }
+      // the device address of the fixed scratch, looked up once per device
+      // with the device current; a failed lookup leaves only
+      // npt_render_noalloc unavailable (it reports the error)
+      c->noalloc_status = noalloc_scratch_ptr(device, &c->noalloc_scratch);
+      if (c->noalloc_status != hipSuccess) c->noalloc_scratch = nullptr;
     }
     *out = c;
     return NPT_OK;
@@ -864,24 +871,138 @@ static int render_checks(npt_ctx* c, uint32_t W, uint32_t H) {
   return NPT_OK;
 }
 
+// argument and state checks shared by the render entry points
+static int render_args(npt_ctx* c, uint32_t W, uint32_t H, uint32_t spp, uint32_t max_depth, const float* d_out) {
+  if (!d_out) return fail(c, NPT_E_INVALID_ARG, "null output buffer");
+  if (spp == 0 || max_depth == 0 || max_depth > NPT_MAX_DEPTH)
+    return fail(c, NPT_E_INVALID_ARG, "spp must be > 0 and max_depth in 1..64");
+  if (W == 0 || H == 0 || (uint64_t)W * H * spp >= (1ull << 40))
+    return fail(c, NPT_E_INVALID_ARG, "W*H*spp must be in (0, 2^40)");
+  if (c->host_only) return fail(c, NPT_E_NO_DEVICE, "host-only context cannot render");
+  int r = render_checks(c, W, H);
+  if (r) return r;
+  if (c->env_mode == NPT_ENV_MAP && !c->env_w) return fail(c, NPT_E_NO_ENV, "env mode MAP without a map");
+  if (c->env_mode == NPT_ENV_NIF && !c->have_nif) return fail(c, NPT_E_NO_ENV, "env mode NIF without weights");
+  return need_device(c);
+}
+
+// device buffers of one render: the path pool (slots = pixels x samples per
+// pass; two ray queues, the environment queue, path radiance and hit
+// records, 16 bytes per slot each), the accumulator, the queue counters and
+// the per-depth statistics
+struct RenderBufs {
+  float4 *qa_o, *qa_d, *qa_b, *qb_o, *qb_d, *qb_b, *env_d, *env_b, *L, *hits, *accum;
+  uint32_t* cnt;
+  unsigned long long* stats;
+};
+constexpr int kPoolStreams = 10;  // float4 streams per path slot
+
+// The passes of one render (samples_per_pass samples of every pixel each)
+// on the given buffers; with `timing`, HIP events around every kernel launch.
+static int render_passes(npt_ctx* c, uint32_t W, uint32_t H, uint32_t spp, uint32_t max_depth, uint64_t seed,
+                         float* d_out, hipStream_t s, const RenderBufs& b, uint64_t sp, bool timing,
+                         unsigned long long* visit_cnt) {
+  const uint64_t pixels = (uint64_t)W * H;
+  c->trace_events.clear();
+  c->shade_events.clear();
+  c->env_events.clear();
+  c->env_depths.clear();
+  auto event_pair = [&](std::vector<hipEvent_t>& v) -> hipError_t {
+    // events are pooled per context and reused across renders
+    const size_t need = c->trace_events.size() + c->shade_events.size() + c->env_events.size() + 2;
+    while (c->event_pool.size() < need) {
+      hipEvent_t e;
+      hipError_t err = hipEventCreate(&e);
+      if (err != hipSuccess) return err;
+      c->event_pool.push_back(e);
+    }
+    v.push_back(c->event_pool[need - 2]);
+    v.push_back(c->event_pool[need - 1]);
+    return hipSuccess;
+  };
+
+  const SceneView sv = scene_view(c);
+  const CameraView cam = camera_view(c->camera, W, H);
+  RayQueue qa{b.qa_o, b.qa_d, b.qa_b};
+  RayQueue qbq{b.qb_o, b.qb_d, b.qb_b};
+  EnvQueue eq{b.env_d, b.env_b};
+  float4* L = b.L;
+  uint32_t* cnt = b.cnt;
+
+  uint32_t passes = 0;
+  for (uint64_t s0 = 0; s0 < spp; s0 += sp) {
+    PassView pv;
+    pv.width = W;
+    pv.height = H;
+    pv.pixels = (uint32_t)pixels;
+    pv.sample0 = (uint32_t)s0;
+    pv.samples = (uint32_t)std::min<uint64_t>(sp, spp - s0);
+    pv.max_depth = max_depth;
+    pv.rr_start = c->opt.rr_start ? c->opt.rr_start : 3;
+    pv.key0 = (uint32_t)seed;
+    pv.key1 = (uint32_t)(seed >> 32);
+    const uint64_t n = pixels * pv.samples;
+    HIP_TRY(c, launch_pass_init(cnt, (uint32_t)n, s));
+    HIP_TRY(c, launch_generate(cam, pv, qa, L, s));
+    RayQueue in = qa, out = qbq;
+    for (uint32_t k = 1; k <= max_depth; ++k) {
+      if (timing) {
+        HIP_TRY(c, event_pair(c->trace_events));
+        HIP_TRY(c, hipEventRecord(c->trace_events[c->trace_events.size() - 2], s));
+      }
+      HIP_TRY(c, launch_extend(c->stack_depth, sv, k, n, in, b.hits, cnt, visit_cnt, c->num_cus, s));
+      if (timing) {
+        HIP_TRY(c, hipEventRecord(c->trace_events.back(), s));
+        HIP_TRY(c, event_pair(c->shade_events));
+        HIP_TRY(c, hipEventRecord(c->shade_events[c->shade_events.size() - 2], s));
+      }
+      HIP_TRY(c, launch_shade(sv, pv, k, n, in, b.hits, out, eq, L, cnt, c->num_cus, s));
+      if (timing) HIP_TRY(c, hipEventRecord(c->shade_events.back(), s));
+      if (c->env_mode != NPT_ENV_NONE) {  // NONE: escaped paths carry no radiance
+        if (timing) {
+          HIP_TRY(c, event_pair(c->env_events));
+          c->env_depths.push_back(k);
+          HIP_TRY(c, hipEventRecord(c->env_events[c->env_events.size() - 2], s));
+        }
+        if (c->env_mode == NPT_ENV_MAP) {
+          HIP_TRY(c, launch_env_lookup(c->d_env.as<float4>(), (int)c->env_w, (int)c->env_h, eq, L, cnt, k, n,
+                                       c->num_cus, s));
+        } else if (c->nif_layered) {
+          LayeredIO io{};
+          io.source = kLayeredQueue;
+          io.env = eq;
+          io.L = L;
+          io.cnt = cnt;
+          io.depth = k;
+          HIP_TRY(c, nif_layered(c->layered, c->nif_prec, c->nif_shape, c->d_frags.p, c->d_master.as<float>(),
+                                 c->nif_cm, io, s));
+        } else {
+          HIP_TRY(c, launch_nif_queue(c->nif_arch, c->nif_prec, c->d_frags.p, c->d_bias.as<float>(), c->nif_cm, eq, L,
+                                      cnt, k, n, c->num_cus, s));
+        }
+        if (timing) HIP_TRY(c, hipEventRecord(c->env_events.back(), s));
+      }
+      std::swap(in, out);
+    }
+    HIP_TRY(c, launch_accumulate(L, b.accum, pv, s0 == 0, s));
+    HIP_TRY(c, launch_stats_add(cnt, b.stats, s));
+    ++passes;
+  }
+  HIP_TRY(c, launch_finalize(b.accum, d_out, (uint32_t)pixels, 1.0f / (float)spp, s));
+  c->stats = npt_stats{};
+  c->stats.paths = pixels * spp;
+  c->stats.passes = passes;
+  c->stats.samples_per_pass = (uint32_t)sp;
+  return NPT_OK;
+}
+
 extern "C" int npt_render(npt_ctx* c, uint32_t W, uint32_t H, uint32_t spp, uint32_t max_depth, uint64_t seed,
                           float* d_out, void* stream) {
   return guarded(c, [&]() -> int {
     if (!c) return NPT_E_INVALID_ARG;
-    if (!d_out) return fail(c, NPT_E_INVALID_ARG, "null output buffer");
-    if (spp == 0 || max_depth == 0 || max_depth > NPT_MAX_DEPTH)
-      return fail(c, NPT_E_INVALID_ARG, "spp must be > 0 and max_depth in 1..64");
-    if (W == 0 || H == 0 || (uint64_t)W * H * spp >= (1ull << 40))
-      return fail(c, NPT_E_INVALID_ARG, "W*H*spp must be in (0, 2^40)");
-    if (c->host_only) return fail(c, NPT_E_NO_DEVICE, "host-only context cannot render");
-    int r = render_checks(c, W, H);
-    if (r) return r;
-    if (c->env_mode == NPT_ENV_MAP && !c->env_w) return fail(c, NPT_E_NO_ENV, "env mode MAP without a map");
-    if (c->env_mode == NPT_ENV_NIF && !c->have_nif) return fail(c, NPT_E_NO_ENV, "env mode NIF without weights");
-    r = need_device(c);
+    int r = render_args(c, W, H, spp, max_depth, d_out);
     if (r) return r;
     hipStream_t s = (hipStream_t)stream;
-
     const uint64_t pixels = (uint64_t)W * H;
     // default pool: 2^26 paths in flight (a whole 1080p x 32 spp frame per
     // pass; 160 B of queues per path = 10.7 GB of the 288 GB of HBM)
@@ -891,109 +1012,78 @@ extern "C" int npt_render(npt_ctx* c, uint32_t W, uint32_t H, uint32_t spp, uint
     while (sp > 1 && pixels * sp >= (1ull << 31)) --sp;
     const uint64_t slots = pixels * sp;
     const size_t qb = slots * sizeof(float4);
-    DevBuf* qbufs[] = {&c->qa_o, &c->qa_d, &c->qa_b, &c->qb_o, &c->qb_d, &c->qb_b, &c->env_d, &c->env_b, &c->d_L,
-                       &c->d_hits};
+    DevBuf* qbufs[kPoolStreams] = {&c->qa_o, &c->qa_d, &c->qa_b, &c->qb_o, &c->qb_d, &c->qb_b, &c->env_d, &c->env_b,
+                                   &c->d_L, &c->d_hits};
     for (DevBuf* b : qbufs) HIP_TRY(c, b->ensure(qb));
     HIP_TRY(c, c->d_accum.ensure(pixels * sizeof(float4)));
     HIP_TRY(c, c->d_cnt.ensure(kCntWords * sizeof(uint32_t)));
     HIP_TRY(c, c->d_stats.ensure(4 * NPT_MAX_DEPTH * sizeof(unsigned long long)));
-    HIP_TRY(c, launch_stats_clear(c->d_stats.as<unsigned long long>(), s));
-    unsigned long long* visit_cnt = c->opt.count_visits ? c->d_stats.as<unsigned long long>() + 2 * NPT_MAX_DEPTH
-                                                        : nullptr;
-    const bool timing = c->opt.kernel_timing != 0;
-    c->trace_events.clear();
-    c->shade_events.clear();
-    c->env_events.clear();
-    c->env_depths.clear();
-    auto event_pair = [&](std::vector<hipEvent_t>& v) -> hipError_t {
-      // events are pooled per context and reused across renders
-      const size_t need = c->trace_events.size() + c->shade_events.size() + c->env_events.size() + 2;
-      while (c->event_pool.size() < need) {
-        hipEvent_t e;
-        hipError_t err = hipEventCreate(&e);
-        if (err != hipSuccess) return err;
-        c->event_pool.push_back(e);
-      }
-      v.push_back(c->event_pool[need - 2]);
-      v.push_back(c->event_pool[need - 1]);
-      return hipSuccess;
-    };
-
-    const SceneView sv = scene_view(c);
-    const CameraView cam = camera_view(c->camera, W, H);
-    RayQueue qa{c->qa_o.as<float4>(), c->qa_d.as<float4>(), c->qa_b.as<float4>()};
-    RayQueue qbq{c->qb_o.as<float4>(), c->qb_d.as<float4>(), c->qb_b.as<float4>()};
-    EnvQueue eq{c->env_d.as<float4>(), c->env_b.as<float4>()};
-    float4* L = c->d_L.as<float4>();
-    uint32_t* cnt = c->d_cnt.as<uint32_t>();
-
+    const RenderBufs b{c->qa_o.as<float4>(), c->qa_d.as<float4>(), c->qa_b.as<float4>(), c->qb_o.as<float4>(),
+                       c->qb_d.as<float4>(), c->qb_b.as<float4>(), c->env_d.as<float4>(), c->env_b.as<float4>(),
+                       c->d_L.as<float4>(), c->d_hits.as<float4>(), c->d_accum.as<float4>(), c->d_cnt.as<uint32_t>(),
+                       c->d_stats.as<unsigned long long>()};
+    unsigned long long* visit_cnt = c->opt.count_visits ? b.stats + 2 * NPT_MAX_DEPTH : nullptr;
+    HIP_TRY(c, launch_stats_clear(b.stats, s));
     HIP_TRY(c, hipEventRecord(c->ev0, s));
-    uint32_t passes = 0;
-    for (uint64_t s0 = 0; s0 < spp; s0 += sp) {
-      PassView pv;
-      pv.width = W;
-      pv.height = H;
-      pv.pixels = (uint32_t)pixels;
-      pv.sample0 = (uint32_t)s0;
-      pv.samples = (uint32_t)std::min<uint64_t>(sp, spp - s0);
-      pv.max_depth = max_depth;
-      pv.rr_start = c->opt.rr_start ? c->opt.rr_start : 3;
-      pv.key0 = (uint32_t)seed;
-      pv.key1 = (uint32_t)(seed >> 32);
-      const uint64_t n = pixels * pv.samples;
-      HIP_TRY(c, launch_pass_init(cnt, (uint32_t)n, s));
-      HIP_TRY(c, launch_generate(cam, pv, qa, L, s));
-      RayQueue in = qa, out = qbq;
-      for (uint32_t k = 1; k <= max_depth; ++k) {
-        if (timing) {
-          HIP_TRY(c, event_pair(c->trace_events));
-          HIP_TRY(c, hipEventRecord(c->trace_events[c->trace_events.size() - 2], s));
-        }
-        HIP_TRY(c, launch_extend(c->stack_depth, sv, k, n, in, c->d_hits.as<float4>(), cnt, visit_cnt, c->num_cus, s));
-        if (timing) {
-          HIP_TRY(c, hipEventRecord(c->trace_events.back(), s));
-          HIP_TRY(c, event_pair(c->shade_events));
-          HIP_TRY(c, hipEventRecord(c->shade_events[c->shade_events.size() - 2], s));
-        }
-        HIP_TRY(c, launch_shade(sv, pv, k, n, in, c->d_hits.as<float4>(), out, eq, L, cnt, c->num_cus, s));
-        if (timing) HIP_TRY(c, hipEventRecord(c->shade_events.back(), s));
-        if (c->env_mode != NPT_ENV_NONE) {  // NONE: escaped paths carry no radiance
-          if (timing) {
-            HIP_TRY(c, event_pair(c->env_events));
-            c->env_depths.push_back(k);
-            HIP_TRY(c, hipEventRecord(c->env_events[c->env_events.size() - 2], s));
-          }
-          if (c->env_mode == NPT_ENV_MAP) {
-            HIP_TRY(c, launch_env_lookup(c->d_env.as<float4>(), (int)c->env_w, (int)c->env_h, eq, L, cnt, k, n,
-                                         c->num_cus, s));
-          } else if (c->nif_layered) {
-            LayeredIO io{};
-            io.source = kLayeredQueue;
-            io.env = eq;
-            io.L = L;
-            io.cnt = cnt;
-            io.depth = k;
-            HIP_TRY(c, nif_layered(c->layered, c->nif_prec, c->nif_shape, c->d_frags.p, c->d_master.as<float>(),
-                                   c->nif_cm, io, s));
-          } else {
-            HIP_TRY(c, launch_nif_queue(c->nif_arch, c->nif_prec, c->d_frags.p, c->d_bias.as<float>(), c->nif_cm, eq, L,
-                                        cnt, k, n, c->num_cus, s));
-          }
-          if (timing) HIP_TRY(c, hipEventRecord(c->env_events.back(), s));
-        }
-        std::swap(in, out);
-      }
-      HIP_TRY(c, launch_accumulate(L, c->d_accum.as<float4>(), pv, s0 == 0, s));
-      HIP_TRY(c, launch_stats_add(cnt, c->d_stats.as<unsigned long long>(), s));
-      ++passes;
-    }
-    HIP_TRY(c, launch_finalize(c->d_accum.as<float4>(), d_out, (uint32_t)pixels, 1.0f / (float)spp, s));
+    r = render_passes(c, W, H, spp, max_depth, seed, d_out, s, b, sp, c->opt.kernel_timing != 0, visit_cnt);
+    if (r) return r;
     HIP_TRY(c, hipEventRecord(c->ev1, s));
     c->timing_pending = true;
-    c->stats = npt_stats{};
-    c->stats.paths = pixels * spp;
-    c->stats.passes = passes;
-    c->stats.samples_per_pass = (uint32_t)sp;
+    return ok(c);
+  });
+}
+
+// Byte layout of the fixed scratch for a render of `pixels` pixels with `sp`
+// samples per pass: counters, statistics, accumulator, then the ten pool
+// streams, each 256-byte aligned.  Returns the bytes used.
+static uint64_t noalloc_layout(uint64_t pixels, uint64_t sp, uint64_t off[4 + kPoolStreams]) {
+  auto up = [](uint64_t x) { return (x + 255) & ~uint64_t(255); };
+  uint64_t o = 0;
+  off[0] = o;  // counters
+  o = up(o + kCntWords * sizeof(uint32_t));
+  off[1] = o;  // statistics
+  o = up(o + 4 * NPT_MAX_DEPTH * sizeof(unsigned long long));
+  off[2] = o;  // accumulator
+  o = up(o + pixels * sizeof(float4));
+  for (int i = 0; i < kPoolStreams; ++i) {
+    off[3 + i] = o;
+    o = up(o + pixels * sp * sizeof(float4));
+  }
+  off[3 + kPoolStreams] = o;
+  return o;
+}
+
+extern "C" int npt_render_noalloc(npt_ctx* c, uint32_t W, uint32_t H, uint32_t spp, uint32_t max_depth,
+                                  uint64_t seed, float* d_out, void* stream) {
+  return guarded(c, [&]() -> int {
+    if (!c) return NPT_E_INVALID_ARG;
+    int r = render_args(c, W, H, spp, max_depth, d_out);
+    if (r) return r;
+    if (!c->noalloc_scratch)
+      return fail(c, NPT_E_HIP, std::string("no fixed scratch on this device: ") + hipGetErrorString(c->noalloc_status));
+    if (c->env_mode == NPT_ENV_NIF && c->nif_layered)
+      return fail(c, NPT_E_UNSUPPORTED, "the layer-serial NIF allocates its activations; use a resident shape");
+    const uint64_t pixels = (uint64_t)W * H;
+    uint64_t off[4 + kPoolStreams];
+    if (noalloc_layout(pixels, 1, off) > NPT_NOALLOC_SCRATCH_BYTES)
+      return fail(c, NPT_E_INVALID_ARG, "image too large for the fixed render scratch (about 176 bytes per pixel "
+                                        "of NPT_NOALLOC_SCRATCH_BYTES)");
+    // as many samples per pass as fit (at most the requested option)
+    uint64_t sp = 1;
+    const uint64_t sp_max = std::min<uint64_t>(spp, c->opt.samples_per_pass ? c->opt.samples_per_pass : spp);
+    while (sp < sp_max && pixels * (sp + 1) < (1ull << 31) &&
+           noalloc_layout(pixels, sp + 1, off) <= NPT_NOALLOC_SCRATCH_BYTES)
+      ++sp;
+    noalloc_layout(pixels, sp, off);
+    unsigned char* base = static_cast<unsigned char*>(c->noalloc_scratch);
+    auto f4 = [&](int i) { return reinterpret_cast<float4*>(base + off[3 + i]); };
+    const RenderBufs b{f4(0), f4(1), f4(2), f4(3), f4(4), f4(5), f4(6), f4(7), f4(8), f4(9),
+                       reinterpret_cast<float4*>(base + off[2]), reinterpret_cast<uint32_t*>(base + off[0]),
+                       reinterpret_cast<unsigned long long*>(base + off[1])};
+    HIP_TRY(c, launch_stats_clear(b.stats, (hipStream_t)stream));
+    r = render_passes(c, W, H, spp, max_depth, seed, d_out, (hipStream_t)stream, b, sp, false, nullptr);
+    if (r) return r;
+    c->timing_pending = false;  // no events: the statistics hold paths and passes only
     return ok(c);
   });
 }

@@ -30,6 +30,11 @@ hipError_t launch_trace_primary(int stack_depth, const SceneView& sc, const Came
                                 const PassView& pv, uint32_t* prim, uint32_t* inst, float* t, float* normal,
                                 int num_cus, hipStream_t s);
 
+// k_scratch.hip: the device address of the fixed scratch array of
+// npt_render_noalloc (NPT_NOALLOC_SCRATCH_BYTES) on `device`, which must be
+// the current device; looked up on the first call per device
+hipError_t noalloc_scratch_ptr(int device, void** ptr);
+
 // k_nif.hip (arch: nif::resident_arch index of the network shape)
 size_t nif_packed_bytes(int arch, int prec);
 hipError_t launch_nif_pack(int arch, int prec, const float* master, void* frags, float* bias, hipStream_t s);

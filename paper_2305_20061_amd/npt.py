@@ -112,6 +112,7 @@ _SIGS = {
     "npt_nif_eval_grid": [_P, C.c_uint32, C.c_uint32, _P, _P],
     "npt_env_query": [_P, C.c_int, _P, C.c_uint64, _P, _P],
     "npt_render": [_P, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64, _P, _P],
+    "npt_render_noalloc": [_P, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64, _P, _P],
     "npt_trace_primary": [_P, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64, _P, _P, _P, _P, _P],
     "npt_get_stats": [_P, _P],
 }
@@ -348,6 +349,16 @@ def npt_render(ctx, width, height, spp, max_depth, seed, out, stream=None):
     import torch
     _check(ctx, lib().npt_render(ctx, width, height, spp, max_depth, seed,
                                  _dev(out, torch.float32, width * height * 3), _stream(stream)))
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # NPT_NOALLOC_SCRATCH_BYTES
+
+
+def npt_render_noalloc(ctx, width, height, spp, max_depth, seed, out, stream=None):
+    """npt_render on the library's fixed device scratch (no allocation)."""
+    import torch
+    _check(ctx, lib().npt_render_noalloc(ctx, width, height, spp, max_depth, seed,
+                                         _dev(out, torch.float32, width * height * 3), _stream(stream)))
 
 
 def npt_trace_primary(ctx, width, height, sample, seed, prim=None, inst=None, t=None, normal=None, stream=None):
