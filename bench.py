@@ -50,11 +50,11 @@ WORKLOADS = {
     4: dict(name="large-BVH", spp=64, depth=8, prec="fp8",
             desc="large-BVH+NIF: 2048^2 terrain 8,380,418 tris + 256 instances x 81,920 tris (two-level BVH4), "
                  "{W}x{H}, {spp} spp, max depth {depth}, FP8 NIF (64-96x5-3) trained on device, seed {seed}",
-            traffic="k_extend_large_bvh_1080p_traffic.json"),
+            traffic="k_extend_large_bvh_1080p_traffic.json", counters="counters_large_bvh_fp8_1080p.json"),
     3: dict(name="small-BVH", spp=32, depth=6, prec="fp16",
             desc="small-BVH+NIF: displaced icosphere 81,922 tris, {W}x{H}, {spp} spp, max depth {depth}, "
                  "FP16 NIF (64-96x5-3) trained on device, seed {seed}",
-            traffic="k_extend_small_bvh_1080p_traffic.json"),
+            traffic="k_extend_small_bvh_1080p_traffic.json", counters="counters_small_bvh_fp16_1080p.json"),
 }
 
 
@@ -76,6 +76,8 @@ def _parse():
     p.add_argument("--node-format", choices=("fp32", "fp16-extent", "q8"), default="fp16-extent",
                    help="BVH4 node encoding: FP32 boxes (112 B), FP32 lower planes + binary16 extents (96 B), "
                         "or 8-bit planes on a per-node step (64 B)")
+    p.add_argument("--lds-levels", type=int, default=0,
+                   help="top BVH levels staged in LDS per workgroup (of the two-level scene: of its top tree)")
     p.add_argument("--nif-sizes", action="store_true",
                    help="instead of the headline run: NIF model size against path rate and PSNR (one JSON line)")
     p.add_argument("--nif-study", action="store_true",
@@ -86,11 +88,45 @@ def _parse():
     return p.parse_args()
 
 
-def _kernel_sha():
+def _sha(files):
     h = hashlib.sha256()
-    for f in ("k_render.hip", "npt_device.h", "npt_shared.h"):
+    for f in files:
         h.update(open(os.path.join(ROOT, "paper_2305_20061_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
+
+
+def _kernel_sha():
+    return _sha(("k_render.hip", "npt_device.h", "npt_shared.h"))
+
+
+# the sources each committed counter record was taken on
+COUNTER_SOURCES = {"k_extend": ("k_render.hip", "npt_device.h", "npt_shared.h"),
+                   "nif": ("k_nif.hip", "npt_nif_layout.h", "npt_mfma.h", "npt_device.h"),
+                   "training": ("k_train.hip", "npt_train.h", "npt_mfma.h", "npt_nif_layout.h")}
+
+
+def _counters(name):
+    """Counter-derived figures of the committed rocprofv3 --pmc record
+    profiles/<name>, per kernel, where its kernel source is the current one
+    (else that kernel's entry is null)."""
+    try:
+        t = json.load(open(os.path.join(ROOT, "profiles", name)))
+    except (OSError, ValueError):
+        return None
+    keep = ("mfma_busy", "valu_insts_per_simd_cycle", "valu_per_tile", "mfma_busy_cycles_per_tile",
+            "lds_bank_conflict_share", "l2_hit_rate", "l2_request_gbs_128B", "ta_busy", "td_busy",
+            "td_stalled_on_l2", "valu_wave_insts_per_64_node_visits")
+    out = {"source": f"profiles/{name}: rocprofv3 --pmc passes over bench.py on the same kernel sources, "
+                     "not measured in this run"}
+    for k, v in t.items():
+        if not isinstance(v, dict) or "kernel_sha" not in v:
+            continue
+        group = "k_extend" if k.startswith("k_extend") else "nif" if k.startswith("k_nif") else "training"
+        if k == "training_gemm_tiled":
+            continue
+        ok = v["kernel_sha"] == _sha(COUNTER_SOURCES[group])
+        out[k] = {kk: v[kk] for kk in keep if kk in v} if ok else None
+    return out
 
 
 def _traffic_per_launch(name):
@@ -144,6 +180,11 @@ def cpu_baseline(cfg, W, H, spp, depth, seed, prec, seconds):
             "sample": f"{len(rows)} of {H} rows (every {step}th), {W} px x {spp} spp each, depth {depth}, "
                       f"{['FP32', 'FP16', 'BF16', 'FP8'][prec]}-rounded NIF operands with FP64 sums; "
                       f"{paths} path samples, slowest worker {wall:.1f} s"}
+
+
+def _stage(msg):
+    """Progress of the run's stages on stderr (the JSON line stays on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def _timed_renders(npt, torch, ctx, W, H, spp, depth, seed, out, steps, warmup):
@@ -505,9 +546,10 @@ def main():
         t0 = time.perf_counter()
         # 4-wide BVH, leaf size 2, no LDS-staged levels: fastest in the sweep
         fmt_code = {"fp32": npt.NODES_FP32, "fp16-extent": npt.NODES_FP16_EXTENT, "q8": npt.NODES_Q8}[args.node_format]
-        npt.npt_load_scene(ctx, scene, max_leaf=2, lds_levels=0, width=4, node_format=fmt_code)
+        npt.npt_load_scene(ctx, scene, max_leaf=2, lds_levels=args.lds_levels, width=4, node_format=fmt_code)
         extra["bvh_build_ms"] = 1e3 * (time.perf_counter() - t0)
-        extra["bvh"] = {**npt.npt_bvh_info(ctx), "node_format": args.node_format,
+        _stage(f"scene and BVH ready ({extra['bvh_build_ms']:.0f} ms build)")
+        extra["bvh"] = {**npt.npt_bvh_info(ctx), "node_format": args.node_format, "lds_levels": args.lds_levels,
                         "node_bytes": {"fp32": B_NODE[4], "fp16-extent": 96, "q8": 64}[args.node_format]}
         del scene
         npt.npt_env_upload(ctx, env)
@@ -515,8 +557,13 @@ def main():
         tr = npt.npt_nif_train(ctx, npt.train_params(batch=65536, samples=args.train_samples, seed=1,
                                                      grad_prec=npt.FP16))
         npt.npt_nif_set_precision(ctx, prec)
-        extra["train"] = {"ms": tr["ms"], "steps": tr["steps"], "first_loss": tr["first_loss"],
-                          "last_loss": tr["last_loss"],
+        _stage(f"NIF trained: {tr['steps']} steps in {tr['ms']:.1f} ms")
+        # training FLOP: forward, backward-data and weight-gradient products,
+        # 3 x the forward's 86,592 per sample
+        train_tflops = 3 * NIF_FLOP_PER_QUERY * tr["steps"] * 65536 / (tr["ms"] * 1e-3) / 1e12
+        extra["train"] = {"ms": tr["ms"], "steps": tr["steps"], "ms_per_step": tr["ms"] / max(1, tr["steps"]),
+                          "tflops": train_tflops, "mfma_frac": train_tflops / MFMA_PEAK_TFLOPS["fp16"],
+                          "first_loss": tr["first_loss"], "last_loss": tr["last_loss"],
                           "grid_eval": npt.npt_nif_eval_grid(ctx, 1024, 512)}
         trained = npt.npt_nif_download(ctx)
         npt.npt_set_env_mode(ctx, npt.ENV_NIF)
@@ -551,8 +598,10 @@ def main():
                             "escaped_per_path": float(esc.sum() / cs["paths"])}
 
         # the timed workload, with per-kernel events
+        _stage("counting render done; timed renders")
         npt.npt_set_render_options(ctx, rr_start=3, kernel_timing=1)
         elapsed, st = _timed_renders(npt, torch, ctx, W, H, spp, depth, seed, out, args.steps, args.warmup)
+        _stage(f"timed renders done: {1e3 * elapsed / args.steps:.2f} ms per frame")
         img = {prec_name: out.cpu().numpy().astype(np.float64)}
         ms_step = 1e3 * elapsed / args.steps
         value = W * H * spp * args.steps / elapsed
@@ -591,6 +640,7 @@ def main():
         extra["nif"]["fixed_batch_2^21_queries_per_s"] = _query_rate(npt, torch, ctx, npt.ENV_NIF)
 
         if not args.no_envmap:
+            _stage("comparison renders (FP16 NIF, env map) and the equal-RMSE study")
             modes = {}
             frame_s = {prec_name: ms_step * 1e-3}
             if prec_name != "fp16":
@@ -630,6 +680,7 @@ def main():
         npt.npt_destroy(ctx)
 
     if args.config == 4 and not args.no_small:
+        _stage("small-BVH rate")
         # the small-BVH scene with the same trained network in FP16
         c3 = WORKLOADS[3]
         ctx = npt.npt_create(0)
@@ -658,11 +709,20 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "kernel": "k_extend (BVH traversal + primitive tests)",
                      "alg_bytes_per_launch": alg_bytes / st["trace_launches"],
-                     "limiter": "VALU issue and texture addressing with an L2/MALL-resident tree "
-                                "(rocprofv3 counters); HBM carries a fraction of the algorithmic bytes"},
+                     "achieved_is": "algorithmic bytes (ray, hit record, nodes fetched, primitive slots tested) "
+                                    "per launch / launch time: what a traversal without caches would move",
+                     "traffic_source": f"profiles/{wl['traffic']}: rocprofv3 FETCH_SIZE + WRITE_SIZE of this kernel "
+                                       "source, copy-calibrated; not measured in this run",
+                     "hbm_frac_measured": (traffic / (trace_launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+                                           if traffic else None),
+                     "limiter": "VALU issue (wave64 VALU instructions at the 4-cycle issue limit) with the tree "
+                                "in L2/MALL; HBM carries about a quarter of the algorithmic bytes (rocprofv3 "
+                                "counters, see counters)"},
+        "counters": _counters(wl["counters"]),
     }
     line.update(extra)
     if not args.no_cpu_baseline:
+        _stage("CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(args.config, W, H, spp, depth, seed, prec, args.cpu_seconds)
     print(json.dumps(line), flush=True)
 

@@ -94,6 +94,8 @@ typedef struct {
     uint32_t lds_levels;
     uint32_t width;
     uint32_t node_format;
+    uint32_t threads; /* host threads of the build, 0 = all (at most 64); the
+                         tree is the same byte for byte on any number */
 } npt_bvh_params;
 
 /* HDR-NIF shape (Sec. 3.2): 4*n_freq Fourier features -> layers x
@@ -247,6 +249,14 @@ int npt_build_bvh(npt_ctx *ctx, const npt_bvh_params *p, void *stream);
  * slots, children per node.  Any output may be NULL. */
 int npt_bvh_info(npt_ctx *ctx, uint64_t *nodes, uint64_t *leaves, uint32_t *max_depth,
                  uint64_t *prim_slots, uint32_t *width);
+/* The flattened BVH as built on the host, in the device layout the traversal
+ * reads (nodes, then primitive slots, then for a two-level scene the
+ * instance records): bytes copied to host memory.  Call with NULL buffers to
+ * get the three sizes; a buffer smaller than its size is NPT_E_INVALID_ARG.
+ * NPT_E_STATE before npt_build_bvh.  The arrays depend only on the scene and
+ * the build parameters, not on the build's thread count. */
+int npt_bvh_export(npt_ctx *ctx, void *nodes, uint64_t *node_bytes, void *slots, uint64_t *slot_bytes,
+                   void *records, uint64_t *record_bytes);
 int npt_set_camera(npt_ctx *ctx, const npt_camera *cam);
 int npt_set_render_options(npt_ctx *ctx, const npt_render_options *opt);
 
@@ -270,6 +280,22 @@ int npt_nif_upload(npt_ctx *ctx, const npt_nif_desc *desc, const float *params_f
                    uint64_t n, void *stream);
 /* Copies the FP32 master parameters to host memory (synchronous). */
 int npt_nif_download(npt_ctx *ctx, float *params_fp32, uint64_t n);
+/* Training state of the uploaded network (checkpoint and resume of the
+ * training of Sec. 3.2.1): the FP32 master parameters, Adam's first and
+ * second moments (n values each, the npt_nif_upload order) and the number of
+ * Adam steps taken, copied to host memory (synchronous).  Any of params, m,
+ * v, step may be NULL.  NPT_E_STATE without an uploaded network,
+ * NPT_E_INVALID_ARG if n is not the network's parameter count. */
+int npt_nif_get_state(npt_ctx *ctx, float *params_fp32, float *m, float *v, uint64_t n, uint32_t *step);
+/* Restores a training state taken by npt_nif_get_state into the uploaded
+ * network, which must have the same shape (n parameters): master
+ * parameters, moments and step count are copied from host memory (the
+ * caller keeps them), the inference pack is rebuilt.  Training on from a
+ * restored state takes the steps an uninterrupted run would have taken,
+ * bit for bit.  NPT_E_NAN_INPUT for non-finite values or negative second
+ * moments. */
+int npt_nif_set_state(npt_ctx *ctx, const float *params_fp32, const float *m, const float *v, uint64_t n,
+                      uint32_t step, void *stream);
 /* Inference precision NPT_FP32 / FP16 / BF16 / FP8 (OCP E4M3 weights and
  * activations with power-of-two scales).  Packs the weights. */
 int npt_nif_set_precision(npt_ctx *ctx, int prec);

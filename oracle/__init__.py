@@ -70,11 +70,16 @@ _lib = None
 
 
 def lib():
+    """The oracle library; NPT_ORACLE_LIB names another build of the same
+    source to load instead (the sanitizer tests use an instrumented one)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC):
-            build_oracle()
-        L = C.CDLL(LIB_PATH)
+        path = os.environ.get("NPT_ORACLE_LIB")
+        if not path:
+            path = LIB_PATH
+            if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC):
+                build_oracle()
+        L = C.CDLL(path)
         sig = {
             "or_philox4x32_10": (None, [_u32p, _u32p, _u32p]),
             "or_u01": (C.c_float, [C.c_uint32]),

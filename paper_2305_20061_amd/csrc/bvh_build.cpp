@@ -54,19 +54,33 @@ struct Node {
 };
 
 // Host threads of one build: subtrees of at least kParallelPrims primitives
-// build their second child on another thread while workers are free.
-constexpr uint32_t kParallelPrims = 100000;
+// build their second child on another thread while workers are free.  (The
+// sanitizer tests build the builder with smaller thresholds, so that a small
+// scene reaches every threaded stage.)
+#ifndef NPT_BVH_PARALLEL_PRIMS
+#define NPT_BVH_PARALLEL_PRIMS 100000u
+#endif
+#ifndef NPT_BVH_PARALLEL_BIN
+#define NPT_BVH_PARALLEL_BIN (1u << 20)
+#endif
+#ifndef NPT_BVH_PARALLEL_RANGE
+#define NPT_BVH_PARALLEL_RANGE (1u << 16)
+#endif
+constexpr uint32_t kParallelPrims = NPT_BVH_PARALLEL_PRIMS;
+
+// the calling thread's cap on the build's threads (BuildThreads), 0 = none
+thread_local int t_thread_cap = 0;
 
 int host_threads() {
-  const unsigned t = std::thread::hardware_concurrency();
-  return (int)std::max(1u, std::min(t, 64u));
+  const unsigned hw = std::max(1u, std::min(std::thread::hardware_concurrency(), 64u));
+  return t_thread_cap > 0 ? (int)std::min<unsigned>(hw, (unsigned)t_thread_cap) : (int)hw;
 }
 
 // fn(begin, end) over [0, n) in contiguous ranges on up to host_threads()
 // threads (one range for small n)
 template <class F>
 void parallel_ranges(uint64_t n, F&& fn) {
-  const uint64_t per = 1u << 16;
+  const uint64_t per = NPT_BVH_PARALLEL_RANGE;
   const int t = (int)std::min<uint64_t>((uint64_t)host_threads(), (n + per - 1) / per);
   if (t <= 1) {
     fn(0, n);
@@ -88,12 +102,13 @@ void parallel_chunks(uint64_t n, int t, F&& fn) {
 }
 
 // node ranges at least this large bound and bin their primitives on all threads
-constexpr uint32_t kParallelBin = 1u << 20;
+constexpr uint32_t kParallelBin = NPT_BVH_PARALLEL_BIN;
 
 struct Builder {
   Prim* prims = nullptr;  // subtrees partition disjoint ranges of it in place
   std::vector<Node> nodes;
   uint32_t bins = 32, max_leaf = 4;
+  int threads = 1;                      // threads that bound and bin one large range
   std::atomic<int>* workers = nullptr;  // threads that may still be started
 
   // appends a subtree built by another builder: its root becomes node
@@ -124,7 +139,7 @@ struct Builder {
       part(0, count, b, cb);
       return;
     }
-    const int t = host_threads();
+    const int t = threads;
     std::vector<Box> pb(t), pc(t);
     parallel_chunks(count, t, [&](int j, uint64_t i0, uint64_t i1) { part(i0, i1, pb[j], pc[j]); });
     for (int j = 0; j < t; ++j) {
@@ -151,7 +166,7 @@ struct Builder {
       part(0, count, bbox, bcnt);
       return;
     }
-    const int t = host_threads();
+    const int t = threads;
     std::vector<Box> bb((size_t)t * bins);
     std::vector<uint32_t> bc((size_t)t * bins, 0u);
     parallel_chunks(count, t, [&](int j, uint64_t i0, uint64_t i1) { part(i0, i1, &bb[(size_t)j * bins], &bc[(size_t)j * bins]); });
@@ -528,6 +543,9 @@ bool compress_q8_nodes(FlatBvh& b, std::string& err) {
   return true;
 }
 
+BuildThreads::BuildThreads(int n) : prev_(t_thread_cap) { t_thread_cap = n > 0 ? n : 0; }
+BuildThreads::~BuildThreads() { t_thread_cap = prev_; }
+
 bool build_bvh(const BuildInput& in, uint32_t bins, uint32_t max_leaf, uint32_t lds_levels, uint32_t width,
                FlatBvh& out,
                std::string& err) {
@@ -565,6 +583,7 @@ bool build_bvh(const BuildInput& in, uint32_t bins, uint32_t max_leaf, uint32_t 
   });
   std::atomic<int> workers{host_threads() - 1};
   Builder B;
+  B.threads = host_threads();
   B.bins = bins;
   B.max_leaf = max_leaf;
   B.prims = prims.data();
@@ -725,7 +744,8 @@ bool build_bvh(const BuildInput& in, uint32_t bins, uint32_t max_leaf, uint32_t 
 }
 
 bool build_two_level(const std::vector<FlatBvh>& bottoms, const std::vector<Placement>& objects, uint32_t bins,
-                     FlatBvh& out, std::vector<float4>& records, uint32_t& stack_entries, std::string& err) {
+                     uint32_t lds_levels, FlatBvh& out, std::vector<float4>& records, uint32_t& stack_entries,
+                     std::string& err) {
   out = FlatBvh();
   records.clear();
   if (objects.empty()) {
@@ -750,12 +770,13 @@ bool build_two_level(const std::vector<FlatBvh>& bottoms, const std::vector<Plac
   tin.boxes = boxes.data();
   tin.nboxes = objects.size();
   FlatBvh top;
-  if (!build_bvh(tin, bins, 1, 0, 4, top, err)) return false;
+  if (!build_bvh(tin, bins, 1, lds_levels, 4, top, err)) return false;
 
   out.width = 4;
   out.node_float4s = kNode4Float4s;
   out.nodes = top.nodes;
   out.leaves = top.leaves;
+  out.lds_nodes = top.lds_nodes;  // the top tree's BFS-ordered first levels
   for (int a = 0; a < 3; ++a) {
     out.lo[a] = top.lo[a];
     out.hi[a] = top.hi[a];

@@ -36,6 +36,21 @@ struct FlatBvh {
   float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};  // bounds of all primitives
 };
 
+// Caps the host threads of the builds this thread runs while it lives (n = 0:
+// every hardware thread, at most 64).  The tree does not depend on it: a
+// build on any number of threads gives the single-threaded tree byte for
+// byte.
+class BuildThreads {
+ public:
+  explicit BuildThreads(int n);
+  ~BuildThreads();
+  BuildThreads(const BuildThreads&) = delete;
+  BuildThreads& operator=(const BuildThreads&) = delete;
+
+ private:
+  int prev_;
+};
+
 // Binned-SAH build of a binary tree (bins per axis, primitives per leaf <=
 // max_leaf), collapsed to `width` children per node (2 or 4), then
 // flattening: the nodes of the top lds_levels levels first in BFS order, the
@@ -68,9 +83,12 @@ struct Placement {
 // Two-level layout for instancing: a 4-wide top tree (one object per leaf)
 // over the world boxes of `objects`, followed in one node array and one slot
 // array by the 4-wide bottom trees with their refs moved by their offsets.
+// The top tree's first lds_levels levels come first in BFS order
+// (out.lds_nodes of them), for the traversal to stage in LDS.
 // records receives two float4 per top-tree leaf (translate, scale) and
 // (bottom root, id); stack_entries the traversal stack the layout needs.
 bool build_two_level(const std::vector<FlatBvh>& bottoms, const std::vector<Placement>& objects, uint32_t bins,
-                     FlatBvh& out, std::vector<float4>& records, uint32_t& stack_entries, std::string& err);
+                     uint32_t lds_levels, FlatBvh& out, std::vector<float4>& records, uint32_t& stack_entries,
+                     std::string& err);
 
 }  // namespace npt

@@ -432,7 +432,8 @@ __device__ __forceinline__ bool trav_pop(S& st, const WorldRay<kStride>& wr, Tra
 // Inner node tv.ref: the children the ray enters are pushed far to near and
 // the nearest taken; with none, a pop.  Returns false once the traversal is
 // complete.  kCount: also count inner-node fetches; kLds: the first
-// sc.lds_nodes nodes are read from the LDS copy (one-level trees only).
+// sc.lds_nodes nodes (the top levels in BFS order; of a two-level scene, its
+// top tree's) are read from the LDS copy (FP32 and binary16-extent nodes).
 template <int kWidth, bool kCount, bool kLds, class S, int kStride>
 __device__ __forceinline__ bool trav_node(const SceneView& sc, const float4* lds_nodes, S& st,
                                           const WorldRay<kStride>& wr, Trav& tv, uint32_t& n_nodes) {
@@ -464,7 +465,12 @@ __device__ __forceinline__ bool trav_node(const SceneView& sc, const float4* lds
     }
   } else if constexpr (half_nodes(kWidth)) {
     const uint32_t off = tv.ref * (kNode4HalfFloat4s * 16u);  // node arrays stay below 4 GiB
-    if (visit4h(reinterpret_cast<const char*>(sc.nodes), off, tv.f, lim, st, tv.sp, tv.ref)) return true;
+    bool entered;
+    if (kLds && tv.ref < sc.lds_nodes)
+      entered = visit4h(reinterpret_cast<const char*>(lds_nodes), off, tv.f, lim, st, tv.sp, tv.ref);
+    else
+      entered = visit4h(reinterpret_cast<const char*>(sc.nodes), off, tv.f, lim, st, tv.sp, tv.ref);
+    if (entered) return true;
   } else if constexpr (q8_nodes(kWidth)) {
     const uint32_t off = tv.ref * (kNode4Q8Float4s * 16u);
     if (visit4q(reinterpret_cast<const char*>(sc.nodes), off, tv.f, lim, st, tv.sp, tv.ref)) return true;
@@ -514,7 +520,8 @@ __device__ __forceinline__ Hit trace_closest(const SceneView& sc, const float4* 
   uint32_t nn = 0, np = 0;
   if (!trav_begin(sc, o, d, tv)) return tv.h;
   for (uint32_t v = 0; v < kMaxVisits; ++v) {
-    const bool more = (tv.ref & kLeafBit) == 0u ? trav_node<kWidth, false, (kWidth == 2 || kWidth == 4)>(sc, lds_nodes, st, wr, tv, nn)
+    const bool more = (tv.ref & kLeafBit) == 0u ? trav_node<kWidth, false, (kWidth == 2 || kWidth == 4 ||
+                                                                              half_nodes(kWidth))>(sc, lds_nodes, st, wr, tv, nn)
                                                 : trav_leaf<kWidth, false>(sc, st, wr, tv, np);
     if (!more) break;
   }
@@ -984,13 +991,21 @@ hipError_t launch_extend(int stack_depth, const SceneView& sc, uint32_t depth, u
   const bool half = sc.width == 4 && sc.node_float4s == kNode4HalfFloat4s;
   const bool q8 = sc.width == 4 && sc.node_float4s == kNode4Q8Float4s;
   if (sc.two_level && half) {
-    NPT_LAUNCH_EXTEND_S(kTwoLevelHalf, false)
+    if (staged) {
+      NPT_LAUNCH_EXTEND_S(kTwoLevelHalf, true)
+    } else {
+      NPT_LAUNCH_EXTEND_S(kTwoLevelHalf, false)
+    }
   } else if (sc.two_level && q8) {
     NPT_LAUNCH_EXTEND_S(kTwoLevelQ8, false)
   } else if (sc.two_level) {
     NPT_LAUNCH_EXTEND_S(kTwoLevel, false)
   } else if (half) {
-    NPT_LAUNCH_EXTEND_S(kHalf4, false)
+    if (staged) {
+      NPT_LAUNCH_EXTEND_S(kHalf4, true)
+    } else {
+      NPT_LAUNCH_EXTEND_S(kHalf4, false)
+    }
   } else if (q8) {
     NPT_LAUNCH_EXTEND_S(kQ84, false)
   } else if (sc.width == 4) {

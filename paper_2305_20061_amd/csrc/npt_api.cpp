@@ -414,18 +414,22 @@ extern "C" int npt_build_bvh(npt_ctx* c, const npt_bvh_params* p, void* stream) 
     uint32_t lds_levels = p ? p->lds_levels : 0;
     const uint32_t width = p && p->width ? p->width : 4;
     const uint32_t node_format = p ? p->node_format : NPT_NODES_FP32;
+    const BuildThreads threads(p ? (int)std::min<uint32_t>(p->threads, 64) : 0);
     if (width != 2 && width != 4) return fail(c, NPT_E_INVALID_ARG, "BVH width must be 2 or 4");
     if (node_format != NPT_NODES_FP32 && node_format != NPT_NODES_FP16_EXTENT && node_format != NPT_NODES_Q8)
       return fail(c, NPT_E_INVALID_ARG, "unknown BVH node format");
-    if (node_format != NPT_NODES_FP32 && (width != 4 || lds_levels != 0))
-      return fail(c, NPT_E_INVALID_ARG, "compressed nodes need width 4 and lds_levels 0");
+    if (node_format != NPT_NODES_FP32 && width != 4)
+      return fail(c, NPT_E_INVALID_ARG, "compressed nodes need width 4");
+    if (node_format == NPT_NODES_Q8 && lds_levels != 0)
+      return fail(c, NPT_E_INVALID_ARG, "8-bit nodes are read from memory: lds_levels must be 0");
     if (bins < 4 || bins > 256 || max_leaf < 1 || max_leaf > kMaxLeaf || lds_levels > 8)
       return fail(c, NPT_E_INVALID_ARG, "bvh params out of range");
     const bool has_base = !c->tris.empty() || !c->spheres.empty();
     const bool two_level = !c->instances.empty();
     if (!has_base && !two_level) return fail(c, NPT_E_NO_SCENE, "no geometry uploaded");
-    if (two_level && (width != 4 || lds_levels != 0))
-      return fail(c, NPT_E_UNSUPPORTED, "instanced scenes use width 4 without LDS levels");
+    if (two_level && width != 4) return fail(c, NPT_E_UNSUPPORTED, "instanced scenes use width 4");
+    if (two_level && lds_levels != 0 && node_format == NPT_NODES_FP32)
+      return fail(c, NPT_E_UNSUPPORTED, "LDS levels of an instanced scene need binary16-extent nodes");
     const uint32_t nmat = (uint32_t)std::max<size_t>(1, c->materials.size());
     for (uint32_t m : c->tri_mat)
       if (m >= nmat) return fail(c, NPT_E_INVALID_ARG, "triangle material id out of range");
@@ -483,7 +487,8 @@ extern "C" int npt_build_bvh(npt_ctx* c, const npt_bvh_params* p, void* stream) 
                                     x.scale,
                                     (uint32_t)(k + 1)});
       }
-      if (!build_two_level(bottoms, objects, bins, b, records, stack_need, e)) return fail(c, NPT_E_INVALID_ARG, e);
+      if (!build_two_level(bottoms, objects, bins, lds_levels, b, records, stack_need, e))
+        return fail(c, NPT_E_INVALID_ARG, e);
     }
     if (node_format == NPT_NODES_FP16_EXTENT && !compress_half_extents(b, e)) return fail(c, NPT_E_UNSUPPORTED, e);
     if (node_format == NPT_NODES_Q8 && !compress_q8_nodes(b, e)) return fail(c, NPT_E_UNSUPPORTED, e);
@@ -531,6 +536,27 @@ extern "C" int npt_bvh_info(npt_ctx* c, uint64_t* nodes, uint64_t* leaves, uint3
     if (max_depth) *max_depth = c->bvh.max_depth;
     if (slots) *slots = c->bvh.slots.size() / 3;
     if (width) *width = c->bvh.width;
+    return ok(c);
+  });
+}
+
+extern "C" int npt_bvh_export(npt_ctx* c, void* nodes, uint64_t* node_bytes, void* slots, uint64_t* slot_bytes,
+                              void* records, uint64_t* record_bytes) {
+  return guarded(c, [&]() -> int {
+    if (!c) return NPT_E_INVALID_ARG;
+    if (c->bvh.nodes.empty()) return fail(c, NPT_E_STATE, "no BVH built");
+    if (!node_bytes || !slot_bytes || !record_bytes) return fail(c, NPT_E_INVALID_ARG, "null size");
+    const uint64_t nb = c->bvh.nodes.size() * sizeof(float4), sb = c->bvh.slots.size() * sizeof(float4),
+                   rb = c->two_level ? c->inst_records.size() * sizeof(float4) : 0;
+    const bool copy = nodes || slots || records;
+    if (copy && ((nodes && *node_bytes < nb) || (slots && *slot_bytes < sb) || (records && *record_bytes < rb)))
+      return fail(c, NPT_E_INVALID_ARG, "export buffer too small");
+    if (nodes) std::memcpy(nodes, c->bvh.nodes.data(), nb);
+    if (slots) std::memcpy(slots, c->bvh.slots.data(), sb);
+    if (records && rb) std::memcpy(records, c->inst_records.data(), rb);
+    *node_bytes = nb;
+    *slot_bytes = sb;
+    *record_bytes = rb;
     return ok(c);
   });
 }
@@ -666,6 +692,49 @@ extern "C" int npt_nif_download(npt_ctx* c, float* params, uint64_t n) {
     if (r) return r;
     HIP_TRY(c, hipDeviceSynchronize());
     HIP_TRY(c, hipMemcpy(params, c->d_master.p, n * sizeof(float), hipMemcpyDeviceToHost));
+    return ok(c);
+  });
+}
+
+extern "C" int npt_nif_get_state(npt_ctx* c, float* params, float* m, float* v, uint64_t n, uint32_t* step) {
+  return guarded(c, [&]() -> int {
+    if (!c) return NPT_E_INVALID_ARG;
+    if (!c->have_nif) return fail(c, NPT_E_STATE, "no NIF uploaded");
+    if (n != (uint64_t)shape_params(c->nif_shape)) return fail(c, NPT_E_INVALID_ARG, "parameter count mismatch");
+    int r = need_device(c);
+    if (r) return r;
+    HIP_TRY(c, hipDeviceSynchronize());
+    const size_t bytes = n * sizeof(float);
+    if (params) HIP_TRY(c, hipMemcpy(params, c->d_master.p, bytes, hipMemcpyDeviceToHost));
+    if (m) HIP_TRY(c, hipMemcpy(m, c->d_adam_m.p, bytes, hipMemcpyDeviceToHost));
+    if (v) HIP_TRY(c, hipMemcpy(v, c->d_adam_v.p, bytes, hipMemcpyDeviceToHost));
+    if (step) *step = c->adam_step;
+    return ok(c);
+  });
+}
+
+extern "C" int npt_nif_set_state(npt_ctx* c, const float* params, const float* m, const float* v, uint64_t n,
+                                 uint32_t step, void* stream) {
+  return guarded(c, [&]() -> int {
+    if (!c) return NPT_E_INVALID_ARG;
+    if (!c->have_nif) return fail(c, NPT_E_STATE, "no NIF uploaded");
+    if (!params || !m || !v) return fail(c, NPT_E_INVALID_ARG, "null state array");
+    if (n != (uint64_t)shape_params(c->nif_shape)) return fail(c, NPT_E_INVALID_ARG, "parameter count mismatch");
+    if (!finite_all(params, n) || !finite_all(m, n) || !finite_all(v, n))
+      return fail(c, NPT_E_NAN_INPUT, "non-finite training state");
+    for (uint64_t i = 0; i < n; ++i)
+      if (v[i] < 0.0f) return fail(c, NPT_E_NAN_INPUT, "negative second moment");
+    int r = need_device(c);
+    if (r) return r;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t bytes = n * sizeof(float);
+    HIP_TRY(c, hipMemcpyAsync(c->d_master.p, params, bytes, hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(c->d_adam_m.p, m, bytes, hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(c->d_adam_v.p, v, bytes, hipMemcpyHostToDevice, s));
+    c->adam_step = step;
+    r = repack_nif(c, s);
+    if (r) return r;
+    HIP_TRY(c, hipStreamSynchronize(s));
     return ok(c);
   });
 }

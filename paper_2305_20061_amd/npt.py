@@ -54,7 +54,7 @@ class npt_camera(C.Structure):
 
 class npt_bvh_params(C.Structure):
     _fields_ = [("bins", C.c_uint32), ("max_leaf", C.c_uint32), ("lds_levels", C.c_uint32), ("width", C.c_uint32),
-                ("node_format", C.c_uint32)]
+                ("node_format", C.c_uint32), ("threads", C.c_uint32)]
 
 
 class npt_nif_desc(C.Structure):
@@ -99,12 +99,15 @@ _SIGS = {
     "npt_scene_materials": [_P, _P, C.c_uint32],
     "npt_build_bvh": [_P, _P, _P],
     "npt_bvh_info": [_P, _P, _P, _P, _P, _P],
+    "npt_bvh_export": [_P, _P, _P, _P, _P, _P, _P],
     "npt_set_camera": [_P, _P],
     "npt_set_render_options": [_P, _P],
     "npt_env_upload": [_P, _P, C.c_uint32, C.c_uint32, _P],
     "npt_set_env_mode": [_P, C.c_int],
     "npt_nif_upload": [_P, _P, _P, C.c_uint64, _P],
     "npt_nif_download": [_P, _P, C.c_uint64],
+    "npt_nif_get_state": [_P, _P, _P, _P, C.c_uint64, _P],
+    "npt_nif_set_state": [_P, _P, _P, _P, C.c_uint64, C.c_uint32, _P],
     "npt_nif_set_precision": [_P, C.c_int],
     "npt_nif_get_dequantized": [_P, _P, C.c_uint64],
     "npt_nif_train": [_P, _P, _P, _P],
@@ -242,9 +245,19 @@ def npt_scene_materials(ctx, materials):
     _check(ctx, lib().npt_scene_materials(ctx, arr, len(materials)))
 
 
-def npt_build_bvh(ctx, bins=32, max_leaf=4, lds_levels=6, stream=None, width=0, node_format=0):
-    p = npt_bvh_params(bins, max_leaf, lds_levels, width, node_format)
+def npt_build_bvh(ctx, bins=32, max_leaf=4, lds_levels=6, stream=None, width=0, node_format=0, threads=0):
+    p = npt_bvh_params(bins, max_leaf, lds_levels, width, node_format, threads)
     _check(ctx, lib().npt_build_bvh(ctx, C.byref(p), _stream(stream)))
+
+
+def npt_bvh_export(ctx):
+    """(nodes, slots, records) of the host-built BVH as byte arrays."""
+    sz = [C.c_uint64() for _ in range(3)]
+    _check(ctx, lib().npt_bvh_export(ctx, None, C.byref(sz[0]), None, C.byref(sz[1]), None, C.byref(sz[2])))
+    bufs = [np.zeros(s.value, np.uint8) for s in sz]
+    _check(ctx, lib().npt_bvh_export(ctx, _hp(bufs[0]), C.byref(sz[0]), _hp(bufs[1]), C.byref(sz[1]),
+                                     _hp(bufs[2]), C.byref(sz[2])))
+    return tuple(bufs)
 
 
 def npt_bvh_info(ctx):
@@ -298,6 +311,21 @@ def npt_nif_download(ctx, n=43779):
     out = np.zeros(n, np.float32)
     _check(ctx, lib().npt_nif_download(ctx, _hp(out), n))
     return out
+
+
+def npt_nif_get_state(ctx, n=43779):
+    """(params, m, v, step): FP32 master parameters, Adam moments, Adam steps taken."""
+    p, m, v = (np.zeros(n, np.float32) for _ in range(3))
+    step = C.c_uint32(0)
+    _check(ctx, lib().npt_nif_get_state(ctx, _hp(p), _hp(m), _hp(v), n, C.byref(step)))
+    return p, m, v, int(step.value)
+
+
+def npt_nif_set_state(ctx, params, m, v, step, stream=None):
+    p, mm, vv = (_host(a, np.float32) for a in (params, m, v))
+    if not (p.size == mm.size == vv.size):
+        raise ValueError("params, m and v must have the same length")
+    _check(ctx, lib().npt_nif_set_state(ctx, _hp(p), _hp(mm), _hp(vv), p.size, int(step), _stream(stream)))
 
 
 def npt_nif_set_precision(ctx, prec):
@@ -380,7 +408,8 @@ def npt_get_stats(ctx):
 
 
 # ------------------------------------------------------------ conveniences
-def npt_load_scene(ctx, scene: dict, bins=32, max_leaf=4, lds_levels=6, stream=None, width=0, node_format=0):
+def npt_load_scene(ctx, scene: dict, bins=32, max_leaf=4, lds_levels=6, stream=None, width=0, node_format=0,
+                   threads=0):
     """Uploads a scene dict (paper_2305_20061_amd.synth layout) and builds its BVH."""
     npt_scene_materials(ctx, scene["materials"])
     if len(scene.get("tris", [])):
@@ -393,8 +422,6 @@ def npt_load_scene(ctx, scene: dict, bins=32, max_leaf=4, lds_levels=6, stream=N
         npt_scene_instances(ctx, scene["instances"])
     cam = scene["camera"]
     npt_set_camera(ctx, cam["eye"], cam["look_at"], cam["up"], cam["vfov_deg"])
-    if scene.get("instances"):
-        lds_levels = 0  # the two-level traversal reads every node from memory
-    if node_format:
-        lds_levels = 0  # FP16-extent nodes are read from memory
-    npt_build_bvh(ctx, bins, max_leaf, lds_levels, stream, width, node_format)
+    if node_format == NODES_Q8 or (scene.get("instances") and node_format != NODES_FP16_EXTENT):
+        lds_levels = 0  # LDS staging: FP32 one-level trees and binary16-extent trees only
+    npt_build_bvh(ctx, bins, max_leaf, lds_levels, stream, width, node_format, threads)

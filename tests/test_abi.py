@@ -74,6 +74,10 @@ def test_host_only_validation(host_ctx):
     assert _code(npt.npt_nif_upload, c, np.zeros(43779), n_freq=17) == "UNSUPPORTED"
     assert npt.nif_param_count(128, 4, 2, 10) == (40 * 128 + 128) + (128 * 88 + 88) + 2 * (128 * 128 + 128) + 3 * 128 + 3
     assert _code(npt.npt_nif_upload, c, np.zeros(43779), colour=3) == "INVALID_ARG"
+    # training state: nothing uploaded yet
+    assert _code(npt.npt_nif_get_state, c) == "STATE"
+    z = np.zeros(43779, np.float32)
+    assert _code(npt.npt_nif_set_state, c, z, z, z, 0) == "STATE"
     assert _code(npt.npt_env_upload, c, np.zeros((4, 8, 3))) == "NO_DEVICE"
     assert _code(npt.npt_env_upload, c, -np.ones((4, 8, 3))) == "NAN_INPUT"
     # render argument checks come before any device work
@@ -122,7 +126,7 @@ def test_bvh_params_validated(host_ctx):
     assert _code(npt.npt_build_bvh, c, max_leaf=9) == "INVALID_ARG"
     assert _code(npt.npt_build_bvh, c, lds_levels=9) == "INVALID_ARG"
     assert _code(npt.npt_build_bvh, c, node_format=2) == "INVALID_ARG"
-    assert _code(npt.npt_build_bvh, c, lds_levels=2, node_format=1) == "INVALID_ARG"
+    assert _code(npt.npt_build_bvh, c, lds_levels=2, node_format=npt.NODES_Q8) == "INVALID_ARG"
     assert _code(npt.npt_build_bvh, c, lds_levels=0, width=2, node_format=1) == "INVALID_ARG"
     # material ids beyond the table (none uploaded -> one default material)
     assert _code(npt.npt_build_bvh, c) == "INVALID_ARG"
@@ -167,9 +171,17 @@ def test_instances_validated_and_two_level_layout_built(host_ctx):
     assert _code(npt.npt_scene_instances, c,
                  [{"blas": 0, "translate": (0, float("nan"), 0), "scale": 1.0}]) == "NAN_INPUT"
     npt.npt_scene_instances(c, sc["instances"])
-    # the two-level traversal is 4-wide and reads its nodes from memory
+    # the two-level traversal is 4-wide; it stages its top tree's first
+    # levels in LDS with binary16-extent nodes only
     assert _code(npt.npt_build_bvh, c, width=2, lds_levels=0) == "UNSUPPORTED"
     assert _code(npt.npt_build_bvh, c, width=4, lds_levels=3) == "UNSUPPORTED"
+    assert _code(npt.npt_build_bvh, c, width=4, lds_levels=2, node_format=npt.NODES_FP16_EXTENT) == "NO_DEVICE"
+    staged = npt.npt_bvh_export(c)
+    assert _code(npt.npt_build_bvh, c, width=4, lds_levels=0, node_format=npt.NODES_FP16_EXTENT) == "NO_DEVICE"
+    flat = npt.npt_bvh_export(c)
+    # the same nodes (the top tree's first levels placed first), slots and records
+    assert staged[0].size == flat[0].size and np.array_equal(staged[1], flat[1])
+    assert np.array_equal(staged[2], flat[2])
     assert _code(npt.npt_build_bvh, c, max_leaf=2, lds_levels=0) == "NO_DEVICE"
     info = npt.npt_bvh_info(c)
     nt, nb, ni = len(sc["tris"]), len(b["tris"]), len(sc["instances"])

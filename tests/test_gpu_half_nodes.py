@@ -80,3 +80,32 @@ def test_half_node_env_render_matches_oracle(fmt, sky_map):
     r = rel_rmse(g, o)
     print(f"FP16-extent nodes env-map relRMSE {r:.3e}")
     assert r <= 1e-3
+
+
+@pytest.mark.parametrize("cfg", [3, "instanced"])
+def test_lds_staged_half_nodes_match_oracle_and_unstaged(cfg, sky_map):
+    # the first levels of the tree (of an instanced scene: of its top tree),
+    # binary16-extent nodes, read from the workgroup's LDS copy: first hits
+    # bit for bit as the oracle's, and the image of the unstaged tree
+    scene = small_instanced_scene() if cfg == "instanced" else synth.scene_for(cfg)
+    imgs = []
+    for lds in (0, 2):
+        ctx = make_ctx(scene, env=sky_map, lds_levels=lds, max_leaf=2, node_format=npt.NODES_FP16_EXTENT)
+        try:
+            if lds:
+                if cfg == "instanced":
+                    oi = check_primary(scene, ctx, 192, 108, 1, 3)
+                    assert np.any(oi > 0)
+                else:
+                    gp, gi, gt, gn = gpu_primary(ctx, 192, 108, 1, seed=3)
+                    osc, cam = oracle_scene(scene)
+                    op, oi, ot, on = O.trace_primary(osc, cam, 192, 108, 1, 3)
+                    same = (gp == op) & (op != O.MISS)
+                    print(f"cfg {cfg} staged: id agreement {np.mean(gp == op):.6f}")
+                    assert np.mean(gp == op) >= 0.9999
+                    assert np.array_equal(gt[same], ot[same])
+            npt.npt_set_env_mode(ctx, npt.ENV_MAP)
+            imgs.append(gpu_render(ctx, 96, 64, 2, 6, 5))
+        finally:
+            npt.npt_destroy(ctx)
+    assert np.array_equal(imgs[0], imgs[1])

@@ -334,3 +334,46 @@ def test_per_depth_environment_times_add_up(small_sky):
     assert abs(per_depth.sum() - st["ms_env"]) <= 1e-4 * st["ms_env"] + 1e-6
     assert np.all(per_depth[:6] > 0.0) and np.all(per_depth[6:] == 0.0)
     assert sum(st["escaped"]) == st["env_queries"] > 0
+
+
+@pytest.mark.parametrize("master", [npt.FP32, npt.FP16])
+def test_training_resumes_from_saved_state(master, small_sky):
+    # four steps straight, against two steps, the training state saved,
+    # restored into a new context (whose own weights differ) and two more
+    # steps: the same master weights, moments and step count bit for bit --
+    # the batches, Adam's bias correction and the stochastic rounding all
+    # follow the restored step count
+    B = 4096
+
+    def tp(steps):
+        return npt.train_params(batch=B, samples=steps * B, seed=3, grad_prec=npt.FP16, master_prec=master)
+
+    def ctx_with(p):
+        c = npt.npt_create(0)
+        npt.npt_env_upload(c, small_sky)
+        npt.npt_nif_upload(c, p)
+        return c
+
+    p = synth.nif_init(17)
+    states = {}
+    for name, steps in (("full", 4), ("mid", 2)):
+        c = ctx_with(p)
+        try:
+            npt.npt_nif_train(c, tp(steps))
+            states[name] = npt.npt_nif_get_state(c)
+        finally:
+            npt.npt_destroy(c)
+    c = ctx_with(synth.nif_init(99))
+    try:
+        npt.npt_nif_set_state(c, *states["mid"])
+        back = npt.npt_nif_get_state(c)
+        st = npt.npt_nif_train(c, tp(2))
+        resumed = npt.npt_nif_get_state(c)
+    finally:
+        npt.npt_destroy(c)
+    assert back[3] == states["mid"][3] == 2
+    assert all(np.array_equal(x, y) for x, y in zip(back[:3], states["mid"][:3]))
+    assert st["step_total"] == resumed[3] == states["full"][3] == 4
+    for x, y in zip(resumed[:3], states["full"][:3]):
+        assert np.array_equal(x, y)
+    assert not np.array_equal(states["mid"][0], states["full"][0])  # the two later steps moved the weights
