@@ -23,6 +23,10 @@ constexpr uint32_t kMaxVisits = 1u << 22;
 #define NPT_REFILL_AT 48  // lanes still traversing at which a wave takes new rays
 #endif
 constexpr int kRefillAt = NPT_REFILL_AT;
+#ifndef NPT_LEAF_PERCENT
+#define NPT_LEAF_PERCENT 100  // leaf step once waiting leaf lanes reach this % of the lanes at inner nodes
+#endif
+constexpr uint32_t kLeafPercent = NPT_LEAF_PERCENT;
 
 // ---------------------------------------------------------------------------
 // camera (pinhole) -- same definitions as the host-side basis
@@ -668,33 +672,33 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(6))
     }
     if (__ballot(busy) == 0) break;
     // advance until few lanes still traverse (none, once the queue is
-    // drained).  Each round is a node phase (lanes at inner nodes visit
-    // them until every lane holds a leaf or is done; the others wait) and
-    // one leaf step, so that node and leaf code do not diverge within a
-    // wave step.
+    // drained).  Each wave step is either a node step (the lanes at inner
+    // nodes visit them) or a leaf step (the lanes at leaves test them or
+    // enter their instance), never both, so that node and leaf code do not
+    // diverge within a step.  A leaf step is taken once the lanes waiting at
+    // leaves reach kLeafPercent % of the lanes at inner nodes: waiting for
+    // every lane to reach a leaf would leave most lanes idle through the
+    // long node sequences of the wave's slowest rays.
     const uint32_t floor_busy = drained ? 0u : (uint32_t)kRefillAt;
     for (;;) {
-      for (;;) {
-        const bool at_node = busy && (tv.ref & kLeafBit) == 0u;
-        if (__ballot(at_node) == 0) break;
-        if (at_node) {
-          bool more = trav_node<kWidth, kCount, kLds>(sc, lds_nodes, st, wr, tv, n_nodes);
+      const bool at_node = busy && (tv.ref & kLeafBit) == 0u;
+      const uint32_t nn = (uint32_t)__popcll(__ballot(at_node));
+      const uint32_t nl = (uint32_t)__popcll(__ballot(busy && !at_node));
+      if (nn + nl <= floor_busy) break;
+      bool more = true;
+      if (100ull * nl >= (uint64_t)kLeafPercent * nn) {
+        if (busy && !at_node) {
+          more = trav_leaf<kWidth, kCount>(sc, st, wr, tv, n_prims);
           if (++steps >= kMaxVisits) more = false;
-          if (!more) {
-            hits[ray] = make_float4(tv.h.t, __uint_as_float(tv.h.slot), __uint_as_float(tv.h.inst), 0.0f);
-            busy = false;
-          }
         }
-      }
-      if (busy) {
-        bool more = trav_leaf<kWidth, kCount>(sc, st, wr, tv, n_prims);
+      } else if (at_node) {
+        more = trav_node<kWidth, kCount, kLds>(sc, lds_nodes, st, wr, tv, n_nodes);
         if (++steps >= kMaxVisits) more = false;
-        if (!more) {
-          hits[ray] = make_float4(tv.h.t, __uint_as_float(tv.h.slot), __uint_as_float(tv.h.inst), 0.0f);
-          busy = false;
-        }
       }
-      if ((uint32_t)__popcll(__ballot(busy)) <= floor_busy) break;
+      if (busy && !more) {
+        hits[ray] = make_float4(tv.h.t, __uint_as_float(tv.h.slot), __uint_as_float(tv.h.inst), 0.0f);
+        busy = false;
+      }
     }
   }
   if constexpr (kCount) {
