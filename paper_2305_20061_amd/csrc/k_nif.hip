@@ -155,9 +155,12 @@ __global__ __launch_bounds__(256) void k_nif_pack_fp8(const float* master, uint8
     if (threadIdx.x == 0) scales[l] = s;
     int* dst = reinterpret_cast<int*>(packed + K::global_offset(l));
     const int nkb = Fp8<A>::kb_in(l);
-    // dword wd: fragment q = (M-block, K-block), lane, bytes 4 (wd % 8) .. +3
+    // dword wd: fragment q = (M-block, K-block), half (bytes 0-15 / 16-31 of
+    // the lane's 32), lane, bytes 4 (wd % 4) .. +3 of the half: each half is
+    // read with a 16-byte lane stride, free of LDS bank conflicts
     for (int wd = threadIdx.x; wd < Fp8<A>::layer_bytes(l) / 4; wd += 256) {
-      const int q = wd / (64 * 8), lane = (wd / 8) % 64, e0 = (wd % 8) * 4;
+      const int q = wd / (2 * 64 * 4), half = (wd / (64 * 4)) % 2, lane = (wd / 4) % 64;
+      const int e0 = half * 16 + (wd % 4) * 4;
       const int mb = q / nkb, kb = q % nkb;
       const int row = 32 * mb + lane % 32;
       float v[4];
@@ -207,6 +210,7 @@ __global__ void k_nif_dequant(const float* master, const float* bias_tab, float*
 #define NPT_NIF_WAVES 8
 #endif
 constexpr int kNifWaves = NPT_NIF_WAVES;
+
 
 // 32-ray column tiles per wave: two for FP16 / BF16 operands on networks 65
 // to 96 wide (each weight fragment read from LDS feeds two MFMAs: 16/96/5
@@ -326,15 +330,19 @@ __device__ __forceinline__ void relu_to_frags(
 }
 
 // FP8 layer: acc += 2^-s (W 2^s) x over E4M3 K-blocks KB0 .. KB0+NKB-1 of a
-// layer with NKBIN K-blocks, first NMB M-blocks
+// layer with NKBIN K-blocks, first NMB M-blocks.  A fragment's 32 bytes per
+// lane are stored as two halves of 16, each [lane]-contiguous.
 template <class A, int NT, int NKB, int NKBIN, int KB0, int NMB = A::kMB, int NX>
 __device__ __forceinline__ void mma_layer_e4m3(const i32x8* fr, int lane, int scale_a, const i32x8 (&x)[NT][NX],
                                                f32x16 (&acc)[NT][A::kMB]) {
+  const int4* f4 = reinterpret_cast<const int4*>(fr);
 #pragma unroll
   for (int kb = 0; kb < NKB; ++kb)
 #pragma unroll
     for (int mb = 0; mb < NMB; ++mb) {
-      const i32x8 a = fr[(mb * NKBIN + KB0 + kb) * 64 + lane];
+      const int q = mb * NKBIN + KB0 + kb;
+      const int4 lo = f4[(2 * q) * 64 + lane], hi = f4[(2 * q + 1) * 64 + lane];
+      const i32x8 a = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[t][mb] = mma_e4m3(a, x[t][kb], acc[t][mb], scale_a);
     }
@@ -342,8 +350,13 @@ __device__ __forceinline__ void mma_layer_e4m3(const i32x8* fr, int lane, int sc
 
 __device__ __forceinline__ float relu448(float v) { return __builtin_amdgcn_fmed3f(v, 0.0f, 448.0f); }
 
+// four E4M3 bytes of ReLU'd accumulators; the low conversion's other half
+// is overwritten by the high one, so the word it starts from is any register
+// (here the first value's bits: no zeroing instruction)
 __device__ __forceinline__ int pack4_e4m3(const f32x16& a, int r) {
-  return pack_e4m3<true>(relu448(a[r + 2]), relu448(a[r + 3]), pack_e4m3<false>(relu448(a[r]), relu448(a[r + 1]), 0));
+  const float v0 = relu448(a[r]);
+  return pack_e4m3<true>(relu448(a[r + 2]), relu448(a[r + 3]),
+                         pack_e4m3<false>(v0, relu448(a[r + 1]), __float_as_int(v0)));
 }
 
 // ReLU of the accumulators (the first NMB M-blocks), saturated at 448, into
