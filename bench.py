@@ -76,10 +76,15 @@ def _parse():
     p.add_argument("--node-format", choices=("fp32", "fp16-extent", "q8"), default="fp16-extent",
                    help="BVH4 node encoding: FP32 boxes (112 B), FP32 lower planes + binary16 extents (96 B), "
                         "or 8-bit planes on a per-node step (64 B)")
+    p.add_argument("--max-leaf", type=int, default=2, help="primitives per BVH leaf (1..8)")
     p.add_argument("--lds-levels", type=int, default=0,
                    help="top BVH levels staged in LDS per workgroup (of the two-level scene: of its top tree)")
     p.add_argument("--nif-sizes", action="store_true",
                    help="instead of the headline run: NIF model size against path rate and PSNR (one JSON line)")
+    p.add_argument("--study-budgets", default="24,26,28,30",
+                   help="--nif-study: training budgets, log2 of the samples of one continuing run")
+    p.add_argument("--study-sun-radii", default="0.5,2,4",
+                   help="--nif-study: angular radii (degrees) of the sun disk of the synthetic sky")
     p.add_argument("--nif-study", action="store_true",
                    help="instead of the headline run: the NIF output colour-space comparison (one JSON line)")
     p.add_argument("--spp-sweep", action="store_true",
@@ -348,28 +353,67 @@ def _psnr_log(nif_rgb, ref_rgb):
     return {"psnr_rgb": psnr(a, b), "psnr_luminance": psnr(ya, yb), "psnr_chrominance": psnr(ca, cb)}
 
 
+def _hue_deg(a, b):
+    """Angle in degrees between two RGB vectors (0: the same hue and saturation)."""
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    c = float(np.dot(a, b) / max(np.linalg.norm(a) * np.linalg.norm(b), 1e-30))
+    return float(np.degrees(np.arccos(np.clip(c, -1.0, 1.0))))
+
+
+def _luma(x):
+    return float(0.299 * x[0] + 0.587 * x[1] + 0.114 * x[2])
+
+
+# networks of the colour-space study: the workload's and the paper's own
+STUDY_NETS = {"16/96/5": dict(n_freq=16, hidden=96, layers=5, skip=0),
+              "10/128/4 skip 2": dict(n_freq=10, hidden=128, layers=4, skip=2)}
+
+
 def nif_study(args):
     """The output colour-space comparison of Sec. 4.3 on the synthetic sun-lit
-    sky: the network is trained on the device (Huber, Adam, 2^24 samples)
-    with its three outputs in YUV, RGB or YCoCg, at the workload's batch and
-    at a small one.  Reported: log-domain PSNRs of the NIF (FP32 inference)
-    against the map at every texel centre, its radiance at the sun's centre,
-    and the relative RMSE of an open-box render lit by it (FP16 inference)
-    against the env-map render at equal seeds.  Then the master-weight
-    precision of Sec. 3.2.1: FP32 master weights against binary16 master
-    weights with stochastically rounded updates and loss scale 16384."""
+    sky (the workload's 0.5-degree sun disk and larger ones, same radiance),
+    over a training budget: the network (the workload's 16/96/5 and the
+    paper's 10/128/4 with the features again at layer 2) is trained on the
+    device (Huber, Adam, batch 65,536, FP16 GEMM operands) with its three
+    outputs in YUV, RGB or YCoCg, and evaluated after 2^a, 2^b, ... samples
+    of one continuing run.  Reported per point: log-domain PSNRs and MSE of
+    the NIF (FP32 inference) against the map at every texel centre; its
+    radiance at the sun's centre, the ratio of its luminance to the sun's and
+    the angle between the two RGB vectors (the hue error); and for an open-box
+    render lit by the NIF (FP16 inference) the relative RMSE against the
+    env-map render at equal seeds and the angle between the two images' mean
+    colours (the hue of the light).  Then the master-weight precision of
+    Sec. 3.2.1: FP32 master weights against binary16 master weights with
+    stochastically rounded updates and loss scale 16384."""
     import torch
 
     from paper_2305_20061_amd import npt, synth
 
     torch.cuda.set_device(0)
-    env = synth.env_map()
+    budgets = sorted(int(x) for x in args.study_budgets.split(","))
+    out = {}
+    for radius in sorted(float(x) for x in args.study_sun_radii.split(",")):
+        out[f"sun_radius_{radius:g}deg"] = _colour_study(args, budgets, synth.env_map(sun_radius_deg=radius),
+                                                         f"sun {radius:g} deg", master=radius == synth.SUN_RADIUS_DEG)
+    print(json.dumps({"nif_study": {"colour_space": out, "budgets_log2_samples": budgets, "batch": 65536,
+                                    "master_train_samples": args.train_samples,
+                                    "render": "open box 512x512, 16 spp, depth 6, seed 1",
+                                    "grid": "2048x1024 texel centres"}, "data": "synthetic"}))
+
+
+def _colour_study(args, budgets, env, tag, master):
+    import torch
+
+    from paper_2305_20061_amd import npt, synth
+
     h, w = env.shape[:2]
     ph = 2 * np.pi * (np.arange(w) + 0.5) / w - np.pi
     th = np.pi * (np.arange(h) + 0.5) / h
     dirs = np.stack([np.sin(th)[:, None] * np.cos(ph)[None, :], np.cos(th)[:, None] * np.ones(w)[None, :],
                      np.sin(th)[:, None] * np.sin(ph)[None, :]], -1).reshape(-1, 3).astype(np.float32)
     ref = env.reshape(-1, 3).astype(np.float64)
+    log_ref = np.log1p(ref)
+    sun_true = [float(x) for x in ref.max(0)]
     d_dirs = torch.from_numpy(dirs).cuda()
     q = torch.empty(dirs.shape[0], 3, dtype=torch.float32, device="cuda")
     sun = torch.tensor(np.asarray(synth.sun_direction(), np.float32)[None, :]).cuda()
@@ -385,32 +429,45 @@ def nif_study(args):
         npt.npt_render(ctx, RW, RW, RS, RD, 1, img)
         torch.cuda.synchronize()
         img_map = img.cpu().numpy().astype(np.float64)
-        for batch in (65536, 4096):
-            rows = {}
+        mean_map = img_map.reshape(-1, 3).mean(0)
+        for net, shape in STUDY_NETS.items():
             for name, colour in (("yuv", npt.COLOUR_YUV), ("rgb", npt.COLOUR_RGB), ("ycocg", npt.COLOUR_YCOCG)):
-                npt.npt_nif_upload(ctx, synth.nif_init(3), colour=colour)
-                tr = npt.npt_nif_train(ctx, npt.train_params(batch=batch, samples=args.train_samples, seed=1,
-                                                             grad_prec=npt.FP16))
-                npt.npt_nif_set_precision(ctx, npt.FP32)
-                npt.npt_env_query(ctx, npt.ENV_NIF, d_dirs, q)
-                npt.npt_env_query(ctx, npt.ENV_NIF, sun, qs)
-                torch.cuda.synchronize()
-                row = {"train_ms": tr["ms"], "steps": tr["steps"], "last_loss": tr["last_loss"],
-                       **_psnr_log(q.cpu().numpy().astype(np.float64), ref),
-                       "sun_centre_rgb": [float(x) for x in qs.cpu().numpy()[0]],
-                       "sun_true_rgb": [float(x) for x in ref.max(0)]}
-                npt.npt_nif_set_precision(ctx, npt.FP16)
-                npt.npt_set_env_mode(ctx, npt.ENV_NIF)
-                npt.npt_render(ctx, RW, RW, RS, RD, 1, img)
-                torch.cuda.synchronize()
-                row["image_rel_rmse_vs_env_map"] = _rel(img.cpu().numpy().astype(np.float64), img_map)
-                npt.npt_set_env_mode(ctx, npt.ENV_MAP)
-                rows[name] = row
-            res[f"batch_{batch}"] = rows
+                npt.npt_nif_upload(ctx, synth.nif_init(3, **shape), colour=colour, **shape)
+                done, train_ms = 0, 0.0
+                for lb in budgets:
+                    tr = npt.npt_nif_train(ctx, npt.train_params(batch=65536, samples=(1 << lb) - done, seed=1,
+                                                                 grad_prec=npt.FP16))
+                    done, train_ms = 1 << lb, train_ms + tr["ms"]
+                    npt.npt_nif_set_precision(ctx, npt.FP32)
+                    npt.npt_env_query(ctx, npt.ENV_NIF, d_dirs, q)
+                    npt.npt_env_query(ctx, npt.ENV_NIF, sun, qs)
+                    torch.cuda.synchronize()
+                    pred = q.cpu().numpy().astype(np.float64)
+                    sun_rgb = [float(x) for x in qs.cpu().numpy()[0]]
+                    row = {"train_ms": train_ms, "steps": tr["step_total"], "last_loss": tr["last_loss"],
+                           **_psnr_log(pred, ref),
+                           "log_mse": float(np.mean((np.log1p(np.maximum(pred, 0.0)) - log_ref) ** 2)),
+                           "sun_centre_rgb": sun_rgb, "sun_true_rgb": sun_true,
+                           "sun_luminance_ratio": _luma(sun_rgb) / _luma(sun_true),
+                           "sun_hue_error_deg": _hue_deg(sun_rgb, sun_true)}
+                    npt.npt_nif_set_precision(ctx, npt.FP16)
+                    npt.npt_set_env_mode(ctx, npt.ENV_NIF)
+                    npt.npt_render(ctx, RW, RW, RS, RD, 1, img)
+                    torch.cuda.synchronize()
+                    im = img.cpu().numpy().astype(np.float64)
+                    npt.npt_set_env_mode(ctx, npt.ENV_MAP)
+                    row["image_rel_rmse_vs_env_map"] = _rel(im, img_map)
+                    row["image_mean_ratio_vs_env_map"] = _luma(im.reshape(-1, 3).mean(0)) / _luma(mean_map)
+                    row["image_hue_error_deg"] = _hue_deg(im.reshape(-1, 3).mean(0), mean_map)
+                    res.setdefault(net, {}).setdefault(name, {})[f"2^{lb}"] = row
+                    _stage(f"colour study {tag} {net} {name} 2^{lb}: sun {row['sun_luminance_ratio']:.3g} of true, "
+                           f"hue {row['sun_hue_error_deg']:.1f} deg, image relRMSE "
+                           f"{row['image_rel_rmse_vs_env_map']:.3f}")
         # master-weight precision (YUV, FP16 GEMMs): FP32 master against the
         # paper's binary16 master with stochastic rounding and loss scale 16384
         npt.npt_set_env_mode(ctx, npt.ENV_MAP)
-        for name, mp, ls in (("fp32_master_ls16384", npt.FP32, 16384.0), ("fp16_master_sr_ls16384", npt.FP16, 16384.0)):
+        masters = (("fp32_master_ls16384", npt.FP32, 16384.0), ("fp16_master_sr_ls16384", npt.FP16, 16384.0))
+        for name, mp, ls in masters if master else ():
             npt.npt_nif_upload(ctx, synth.nif_init(3))
             tr = npt.npt_nif_train(ctx, npt.train_params(batch=65536, samples=args.train_samples, seed=1,
                                                          grad_prec=npt.FP16, loss_scale=ls, master_prec=mp))
@@ -422,9 +479,7 @@ def nif_study(args):
                 **_psnr_log(q.cpu().numpy().astype(np.float64), ref)}
     finally:
         npt.npt_destroy(ctx)
-    print(json.dumps({"nif_study": {"colour_space": res, "train_samples": args.train_samples,
-                                    "render": f"open box {RW}x{RW}, {RS} spp, depth {RD}, seed 1",
-                                    "grid": f"{w}x{h} texel centres"}, "data": "synthetic"}))
+    return res
 
 
 # (hidden, layers, skip-concat layer, frequencies): the paper's sweep sizes,
@@ -546,10 +601,12 @@ def main():
         t0 = time.perf_counter()
         # 4-wide BVH, leaf size 2, no LDS-staged levels: fastest in the sweep
         fmt_code = {"fp32": npt.NODES_FP32, "fp16-extent": npt.NODES_FP16_EXTENT, "q8": npt.NODES_Q8}[args.node_format]
-        npt.npt_load_scene(ctx, scene, max_leaf=2, lds_levels=args.lds_levels, width=4, node_format=fmt_code)
+        npt.npt_load_scene(ctx, scene, max_leaf=args.max_leaf, lds_levels=args.lds_levels, width=4,
+                           node_format=fmt_code)
         extra["bvh_build_ms"] = 1e3 * (time.perf_counter() - t0)
         _stage(f"scene and BVH ready ({extra['bvh_build_ms']:.0f} ms build)")
         extra["bvh"] = {**npt.npt_bvh_info(ctx), "node_format": args.node_format, "lds_levels": args.lds_levels,
+                        "max_leaf": args.max_leaf,
                         "node_bytes": {"fp32": B_NODE[4], "fp16-extent": 96, "q8": 64}[args.node_format]}
         del scene
         npt.npt_env_upload(ctx, env)

@@ -327,6 +327,23 @@ int npt_env_query(npt_ctx *ctx, int mode, const float *d_dirs, uint64_t n, float
  * NPT_E_NO_ENV: environment mode without a map or NIF weights. */
 int npt_render(npt_ctx *ctx, uint32_t width, uint32_t height, uint32_t spp, uint32_t max_depth,
                uint64_t seed, float *d_radiance, void *stream);
+/* Progressive rendering and resume by sample index (the Monte-Carlo
+ * estimate of Sec. 3.1 is a per-pixel mean over independent samples, each
+ * drawn from its own Philox stream keyed by pixel and sample index):
+ * adds samples [sample0, sample0 + samples) of every pixel to the running
+ * sums d_sum [H][W][4] FP32 (RGB sums and an unused fourth word, zeroed
+ * when sample0 == 0; device, caller-owned, 16-byte aligned), overwriting
+ * them when sample0 == 0.  When d_radiance ([H][W][3] FP32 device) is not NULL the
+ * mean over samples [0, sample0 + samples) is written there.  Each pixel's
+ * samples are added in sample order whatever the split, so renders of
+ * consecutive ranges on one d_sum give npt_render's image of
+ * sample0 + samples spp bit for bit (same seed, depth and scene); d_sum may
+ * be copied to host memory and back in between to checkpoint a render.
+ * NPT_E_INVALID_ARG: null or misaligned d_sum, sample0 + samples >= 2^32,
+ * and npt_render's argument errors with spp = samples.  Other errors and
+ * statistics (paths = W*H*samples) as npt_render. */
+int npt_render_samples(npt_ctx *ctx, uint32_t width, uint32_t height, uint32_t sample0, uint32_t samples,
+                       uint32_t max_depth, uint64_t seed, float *d_sum, float *d_radiance, void *stream);
 
 /* ---- allocation-free rendering ------------------------------------------------ */
 /* For callers that cannot allocate device memory (code under HIP graph

@@ -966,10 +966,13 @@ struct RenderBufs {
 };
 constexpr int kPoolStreams = 10;  // float4 streams per path slot
 
-// The passes of one render (samples_per_pass samples of every pixel each)
-// on the given buffers; with `timing`, HIP events around every kernel launch.
-static int render_passes(npt_ctx* c, uint32_t W, uint32_t H, uint32_t spp, uint32_t max_depth, uint64_t seed,
-                         float* d_out, hipStream_t s, const RenderBufs& b, uint64_t sp, bool timing,
+// The passes over samples [s_begin, s_end) of every pixel (samples_per_pass
+// samples each) on the given buffers.  Each pixel's radiance is added to
+// b.accum in sample order, which is cleared first when s_begin == 0; with
+// d_out, the mean over samples [0, s_end) is written there.  With `timing`,
+// HIP events around every kernel launch.
+static int render_passes(npt_ctx* c, uint32_t W, uint32_t H, uint64_t s_begin, uint64_t s_end, uint32_t max_depth,
+                         uint64_t seed, float* d_out, hipStream_t s, const RenderBufs& b, uint64_t sp, bool timing,
                          unsigned long long* visit_cnt) {
   const uint64_t pixels = (uint64_t)W * H;
   c->trace_events.clear();
@@ -999,13 +1002,13 @@ static int render_passes(npt_ctx* c, uint32_t W, uint32_t H, uint32_t spp, uint3
   uint32_t* cnt = b.cnt;
 
   uint32_t passes = 0;
-  for (uint64_t s0 = 0; s0 < spp; s0 += sp) {
+  for (uint64_t s0 = s_begin; s0 < s_end; s0 += sp) {
     PassView pv;
     pv.width = W;
     pv.height = H;
     pv.pixels = (uint32_t)pixels;
     pv.sample0 = (uint32_t)s0;
-    pv.samples = (uint32_t)std::min<uint64_t>(sp, spp - s0);
+    pv.samples = (uint32_t)std::min<uint64_t>(sp, s_end - s0);
     pv.max_depth = max_depth;
     pv.rr_start = c->opt.rr_start ? c->opt.rr_start : 3;
     pv.key0 = (uint32_t)seed;
@@ -1057,48 +1060,76 @@ static int render_passes(npt_ctx* c, uint32_t W, uint32_t H, uint32_t spp, uint3
     HIP_TRY(c, launch_stats_add(cnt, b.stats, s));
     ++passes;
   }
-  HIP_TRY(c, launch_finalize(b.accum, d_out, (uint32_t)pixels, 1.0f / (float)spp, s));
+  if (d_out) HIP_TRY(c, launch_finalize(b.accum, d_out, (uint32_t)pixels, 1.0f / (float)s_end, s));
   c->stats = npt_stats{};
-  c->stats.paths = pixels * spp;
+  c->stats.paths = pixels * (s_end - s_begin);
   c->stats.passes = passes;
   c->stats.samples_per_pass = (uint32_t)sp;
   return NPT_OK;
+}
+
+// A render of samples [s_begin, s_end) on the context's path pool, adding to
+// `accum` (the context's accumulator when null); the mean over [0, s_end) goes
+// to d_out when it is given.
+static int render_pooled(npt_ctx* c, uint32_t W, uint32_t H, uint64_t s_begin, uint64_t s_end, uint32_t max_depth,
+                         uint64_t seed, float4* accum, float* d_out, hipStream_t s) {
+  const uint64_t pixels = (uint64_t)W * H;
+  // default pool: 2^26 paths in flight (a whole 1080p x 32 spp frame per
+  // pass; 160 B of queues per path = 10.7 GB of the 288 GB of HBM)
+  const uint64_t pool = c->opt.pool_paths ? c->opt.pool_paths : (1ull << 26);
+  uint64_t sp = c->opt.samples_per_pass ? c->opt.samples_per_pass : std::max<uint64_t>(1, pool / pixels);
+  sp = std::min<uint64_t>(sp, s_end - s_begin);
+  while (sp > 1 && pixels * sp >= (1ull << 31)) --sp;
+  const uint64_t slots = pixels * sp;
+  const size_t qb = slots * sizeof(float4);
+  DevBuf* qbufs[kPoolStreams] = {&c->qa_o, &c->qa_d, &c->qa_b, &c->qb_o, &c->qb_d, &c->qb_b, &c->env_d, &c->env_b,
+                                 &c->d_L, &c->d_hits};
+  for (DevBuf* b : qbufs) HIP_TRY(c, b->ensure(qb));
+  if (!accum) {
+    HIP_TRY(c, c->d_accum.ensure(pixels * sizeof(float4)));
+    accum = c->d_accum.as<float4>();
+  }
+  HIP_TRY(c, c->d_cnt.ensure(kCntWords * sizeof(uint32_t)));
+  HIP_TRY(c, c->d_stats.ensure(4 * NPT_MAX_DEPTH * sizeof(unsigned long long)));
+  const RenderBufs b{c->qa_o.as<float4>(), c->qa_d.as<float4>(), c->qa_b.as<float4>(), c->qb_o.as<float4>(),
+                     c->qb_d.as<float4>(), c->qb_b.as<float4>(), c->env_d.as<float4>(), c->env_b.as<float4>(),
+                     c->d_L.as<float4>(), c->d_hits.as<float4>(), accum, c->d_cnt.as<uint32_t>(),
+                     c->d_stats.as<unsigned long long>()};
+  unsigned long long* visit_cnt = c->opt.count_visits ? b.stats + 2 * NPT_MAX_DEPTH : nullptr;
+  HIP_TRY(c, launch_stats_clear(b.stats, s));
+  HIP_TRY(c, hipEventRecord(c->ev0, s));
+  const int r = render_passes(c, W, H, s_begin, s_end, max_depth, seed, d_out, s, b, sp, c->opt.kernel_timing != 0,
+                              visit_cnt);
+  if (r) return r;
+  HIP_TRY(c, hipEventRecord(c->ev1, s));
+  c->timing_pending = true;
+  return ok(c);
 }
 
 extern "C" int npt_render(npt_ctx* c, uint32_t W, uint32_t H, uint32_t spp, uint32_t max_depth, uint64_t seed,
                           float* d_out, void* stream) {
   return guarded(c, [&]() -> int {
     if (!c) return NPT_E_INVALID_ARG;
-    int r = render_args(c, W, H, spp, max_depth, d_out);
+    const int r = render_args(c, W, H, spp, max_depth, d_out);
     if (r) return r;
-    hipStream_t s = (hipStream_t)stream;
-    const uint64_t pixels = (uint64_t)W * H;
-    // default pool: 2^26 paths in flight (a whole 1080p x 32 spp frame per
-    // pass; 160 B of queues per path = 10.7 GB of the 288 GB of HBM)
-    const uint64_t pool = c->opt.pool_paths ? c->opt.pool_paths : (1ull << 26);
-    uint64_t sp = c->opt.samples_per_pass ? c->opt.samples_per_pass : std::max<uint64_t>(1, pool / pixels);
-    sp = std::min<uint64_t>(sp, spp);
-    while (sp > 1 && pixels * sp >= (1ull << 31)) --sp;
-    const uint64_t slots = pixels * sp;
-    const size_t qb = slots * sizeof(float4);
-    DevBuf* qbufs[kPoolStreams] = {&c->qa_o, &c->qa_d, &c->qa_b, &c->qb_o, &c->qb_d, &c->qb_b, &c->env_d, &c->env_b,
-                                   &c->d_L, &c->d_hits};
-    for (DevBuf* b : qbufs) HIP_TRY(c, b->ensure(qb));
-    HIP_TRY(c, c->d_accum.ensure(pixels * sizeof(float4)));
-    HIP_TRY(c, c->d_cnt.ensure(kCntWords * sizeof(uint32_t)));
-    HIP_TRY(c, c->d_stats.ensure(4 * NPT_MAX_DEPTH * sizeof(unsigned long long)));
-    const RenderBufs b{c->qa_o.as<float4>(), c->qa_d.as<float4>(), c->qa_b.as<float4>(), c->qb_o.as<float4>(),
-                       c->qb_d.as<float4>(), c->qb_b.as<float4>(), c->env_d.as<float4>(), c->env_b.as<float4>(),
-                       c->d_L.as<float4>(), c->d_hits.as<float4>(), c->d_accum.as<float4>(), c->d_cnt.as<uint32_t>(),
-                       c->d_stats.as<unsigned long long>()};
-    unsigned long long* visit_cnt = c->opt.count_visits ? b.stats + 2 * NPT_MAX_DEPTH : nullptr;
-    HIP_TRY(c, launch_stats_clear(b.stats, s));
-    HIP_TRY(c, hipEventRecord(c->ev0, s));
-    r = render_passes(c, W, H, spp, max_depth, seed, d_out, s, b, sp, c->opt.kernel_timing != 0, visit_cnt);
+    return render_pooled(c, W, H, 0, spp, max_depth, seed, nullptr, d_out, (hipStream_t)stream);
+  });
+}
+
+extern "C" int npt_render_samples(npt_ctx* c, uint32_t W, uint32_t H, uint32_t sample0, uint32_t samples,
+                                  uint32_t max_depth, uint64_t seed, float* d_sum, float* d_out, void* stream) {
+  return guarded(c, [&]() -> int {
+    if (!c) return NPT_E_INVALID_ARG;
+    if (!d_sum) return fail(c, NPT_E_INVALID_ARG, "null running-sum buffer");
+    if (reinterpret_cast<uintptr_t>(d_sum) % sizeof(float4))
+      return fail(c, NPT_E_INVALID_ARG, "running-sum buffer must be 16-byte aligned");
+    if ((uint64_t)sample0 + samples > 0xFFFFFFFFull)
+      return fail(c, NPT_E_INVALID_ARG, "sample indices must stay below 2^32");
+    // the output is optional here: render_args checks the rest
+    const int r = render_args(c, W, H, samples, max_depth, d_out ? d_out : d_sum);
     if (r) return r;
-    HIP_TRY(c, hipEventRecord(c->ev1, s));
-    c->timing_pending = true;
-    return ok(c);
+    return render_pooled(c, W, H, sample0, (uint64_t)sample0 + samples, max_depth, seed,
+                         reinterpret_cast<float4*>(d_sum), d_out, (hipStream_t)stream);
   });
 }
 
@@ -1150,7 +1181,7 @@ extern "C" int npt_render_noalloc(npt_ctx* c, uint32_t W, uint32_t H, uint32_t s
                        reinterpret_cast<float4*>(base + off[2]), reinterpret_cast<uint32_t*>(base + off[0]),
                        reinterpret_cast<unsigned long long*>(base + off[1])};
     HIP_TRY(c, launch_stats_clear(b.stats, (hipStream_t)stream));
-    r = render_passes(c, W, H, spp, max_depth, seed, d_out, (hipStream_t)stream, b, sp, false, nullptr);
+    r = render_passes(c, W, H, 0, spp, max_depth, seed, d_out, (hipStream_t)stream, b, sp, false, nullptr);
     if (r) return r;
     c->timing_pending = false;  // no events: the statistics hold paths and passes only
     return ok(c);

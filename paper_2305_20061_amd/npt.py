@@ -116,6 +116,7 @@ _SIGS = {
     "npt_env_query": [_P, C.c_int, _P, C.c_uint64, _P, _P],
     "npt_render": [_P, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64, _P, _P],
     "npt_render_noalloc": [_P, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64, _P, _P],
+    "npt_render_samples": [_P, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64, _P, _P, _P],
     "npt_trace_primary": [_P, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64, _P, _P, _P, _P, _P],
     "npt_get_stats": [_P, _P],
 }
@@ -377,6 +378,16 @@ def npt_render(ctx, width, height, spp, max_depth, seed, out, stream=None):
     import torch
     _check(ctx, lib().npt_render(ctx, width, height, spp, max_depth, seed,
                                  _dev(out, torch.float32, width * height * 3), _stream(stream)))
+
+
+def npt_render_samples(ctx, width, height, sample0, samples, max_depth, seed, sums, out=None, stream=None):
+    """Adds samples [sample0, sample0 + samples) to the running sums [H, W, 4]
+    (overwritten when sample0 == 0); `out`, when given, gets the mean so far."""
+    import torch
+    n = width * height
+    _check(ctx, lib().npt_render_samples(ctx, width, height, sample0, samples, max_depth, seed,
+                                         _dev(sums, torch.float32, 4 * n), _dev(out, torch.float32, 3 * n),
+                                         _stream(stream)))
 
 
 NOALLOC_SCRATCH_BYTES = 64 << 20  # NPT_NOALLOC_SCRATCH_BYTES

@@ -302,7 +302,8 @@ def sun_direction():
     return np.array([math.cos(e) * math.cos(a), math.sin(e), math.cos(e) * math.sin(a)])
 
 
-def env_map(width: int = 2048, height: int = 1024, seed: int = 5, sun: bool = True):
+def env_map(width: int = 2048, height: int = 1024, seed: int = 5, sun: bool = True,
+            sun_radius_deg: float = SUN_RADIUS_DEG):
     """Equirectangular FP32 RGB map (height, width, 3).  Texel (i,j) centre is
     (u,v) = ((i+.5)/W, (j+.5)/H); direction phi = 2 pi u - pi, theta = pi v,
     d = (sin th cos ph, cos th, sin th sin ph) (y up)."""
@@ -330,7 +331,7 @@ def env_map(width: int = 2048, height: int = 1024, seed: int = 5, sun: bool = Tr
     if sun:
         s = sun_direction()
         cosang = dx * s[0] + dy * s[1] + dz * s[2]
-        disk = cosang >= math.cos(math.radians(SUN_RADIUS_DEG))
+        disk = cosang >= math.cos(math.radians(sun_radius_deg))
         col[disk] = SUN_RADIANCE
     return np.ascontiguousarray(col, dtype=np.float32)
 

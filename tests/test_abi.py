@@ -91,6 +91,17 @@ def test_host_only_validation(host_ctx):
     assert lib.npt_render(c, 4, 4, 1, 1, 0, C.c_void_p(1), None) == npt.NPT_E["NO_DEVICE"]
     assert "host-only" in npt.npt_last_error(c)
     assert lib.npt_render(None, 4, 4, 1, 1, 0, C.c_void_p(1), None) == npt.NPT_E["INVALID_ARG"]
+    # progressive render: running sums required and 16-byte aligned, sample
+    # indices below 2^32, then npt_render's own checks
+    rs = lib.npt_render_samples
+    assert rs(c, 4, 4, 0, 1, 1, 0, None, None, None) == npt.NPT_E["INVALID_ARG"]
+    assert rs(c, 4, 4, 0, 1, 1, 0, C.c_void_p(8), None, None) == npt.NPT_E["INVALID_ARG"]
+    assert "aligned" in npt.npt_last_error(c)
+    assert rs(c, 4, 4, 0xFFFFFFFF, 1, 1, 0, C.c_void_p(16), None, None) == npt.NPT_E["INVALID_ARG"]
+    assert rs(c, 4, 4, 0, 0, 1, 0, C.c_void_p(16), None, None) == npt.NPT_E["INVALID_ARG"]
+    assert rs(c, 4, 4, 3, 1, 65, 0, C.c_void_p(16), None, None) == npt.NPT_E["INVALID_ARG"]
+    assert rs(c, 4, 4, 3, 2, 8, 0, C.c_void_p(16), None, None) == npt.NPT_E["NO_DEVICE"]
+    assert rs(None, 4, 4, 0, 1, 1, 0, C.c_void_p(16), None, None) == npt.NPT_E["INVALID_ARG"]
 
 
 def test_host_only_bvh_build_and_state_survives_errors(host_ctx):

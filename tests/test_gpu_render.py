@@ -9,7 +9,7 @@ import pytest
 import oracle as O
 from paper_2305_20061_amd import npt, synth
 
-from gpu_util import gpu_primary, gpu_render, make_ctx, oracle_scene, rel_rmse
+from gpu_util import gpu_primary, gpu_render, make_ctx, oracle_scene, rel_rmse, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -99,6 +99,40 @@ def test_render_is_deterministic_and_pass_split_invariant(small_sky):
     assert rel_rmse(c, a) < 1e-6
     assert st["passes"] == 3 and st["paths"] == 64 * 48 * 8
     assert st["rays"][0] == 64 * 48 * 8
+
+
+def test_render_resumes_by_sample_index(small_sky):
+    """Samples [0, 13) rendered in one call, and in three pieces on one set of
+    running sums with a host round trip of the sums between pieces (a
+    checkpoint), give the same image bit for bit; so does the mean after the
+    second piece against a 9-sample render."""
+    torch = torch_cuda()
+    scene = synth.scene_for(2)
+    W, H, depth, seed = 64, 48, 8, 5
+    ctx = make_ctx(scene, env=small_sky)
+    try:
+        full13 = gpu_render(ctx, W, H, 13, depth, seed)
+        full9 = gpu_render(ctx, W, H, 9, depth, seed)
+        sums = torch.full((H, W, 4), float("nan"), dtype=torch.float32, device="cuda")
+        out = torch.empty(H, W, 3, dtype=torch.float32, device="cuda")
+        npt.npt_render_samples(ctx, W, H, 0, 4, depth, seed, sums)
+        # passes of two samples inside the second piece: the split is free
+        npt.npt_set_render_options(ctx, samples_per_pass=2)
+        npt.npt_render_samples(ctx, W, H, 4, 5, depth, seed, sums, out)
+        torch.cuda.synchronize()
+        mean9 = out.cpu().numpy().astype(np.float64)
+        saved = sums.cpu()
+        npt.npt_set_render_options(ctx)
+        resumed = saved.cuda()
+        npt.npt_render_samples(ctx, W, H, 9, 4, depth, seed, resumed, out)
+        st = npt.npt_get_stats(ctx)
+        torch.cuda.synchronize()
+        mean13 = out.cpu().numpy().astype(np.float64)
+    finally:
+        npt.npt_destroy(ctx)
+    assert np.array_equal(mean9, full9)
+    assert np.array_equal(mean13, full13)
+    assert st["paths"] == W * H * 4 and st["rays"][0] == W * H * 4
 
 
 def test_lds_levels_do_not_change_hits():
