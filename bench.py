@@ -106,8 +106,9 @@ def _kernel_sha():
 
 # the sources each committed counter record was taken on
 COUNTER_SOURCES = {"k_extend": ("k_render.hip", "npt_device.h", "npt_shared.h"),
-                   "nif": ("k_nif.hip", "npt_nif_layout.h", "npt_mfma.h", "npt_device.h"),
-                   "training": ("k_train.hip", "npt_train.h", "npt_mfma.h", "npt_nif_layout.h")}
+                   "nif": ("k_nif.hip", "npt_nif_layout.h", "npt_nif_mma.h", "npt_mfma.h", "npt_device.h"),
+                   "training": ("k_train_fused.hip", "npt_train.h", "npt_nif_mma.h", "npt_mfma.h",
+                                "npt_nif_layout.h", "npt_device.h")}
 
 
 def _counters(name):

@@ -145,7 +145,15 @@ typedef struct {
  * scale Sec. 3.2.1 trains with; 1 otherwise, where the range of FP32 / BF16
  * makes a power-of-two scale cancel exactly].  The loss scale multiplies the
  * per-sample output gradients before the backward GEMMs and is divided out
- * of the weight gradients. */
+ * of the weight gradients.  path: NPT_TRAIN_AUTO (0) takes the fused
+ * two-launch step (forward, backward and per-workgroup gradient sums in one
+ * kernel; fixed-order sums and Adam in a second) for the four LDS-resident
+ * shapes with FP16 operands, and layer-by-layer MFMA GEMMs otherwise;
+ * NPT_TRAIN_LAYERED (1) always takes the layer-by-layer GEMMs.  Both round at
+ * the same points and are deterministic; their results differ only in the
+ * order of FP32 sums. */
+#define NPT_TRAIN_AUTO 0
+#define NPT_TRAIN_LAYERED 1
 typedef struct {
     uint32_t batch;
     uint64_t samples;
@@ -154,6 +162,7 @@ typedef struct {
     uint32_t grad_prec;
     float loss_scale;
     uint32_t master_prec;
+    uint32_t path;
 } npt_train_params;
 
 typedef struct {

@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libnpt.so")
 
-SOURCES = ["npt_api.cpp", "bvh_build.cpp", "k_render.hip", "k_nif.hip", "k_train.hip", "k_scratch.hip"]
+SOURCES = ["npt_api.cpp", "bvh_build.cpp", "k_render.hip", "k_nif.hip", "k_train.hip", "k_train_fused.hip", "k_scratch.hip"]
 ARCH = os.environ.get("NPT_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-pthread", "-ffp-contract=off", "-Wall", "-Wno-unused-function",

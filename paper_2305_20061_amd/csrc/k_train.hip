@@ -651,6 +651,7 @@ void TrainScratch::release() {
   target = dy = partial = sub = grad = loss_part = loss = zgrid = err_part = nullptr;
   for (size_t& b : bytes) b = 0;
   grid_cap = 0;
+  fused.release();
 }
 
 static uint32_t elem_size(int prec) { return prec == NPT_FP32 ? 4u : 2u; }
@@ -865,6 +866,7 @@ static hipError_t run_p(TrainScratch& s, const TrainConfig& c, const TrainTarget
 static hipError_t dispatch(TrainScratch& s, const TrainConfig& c, const TrainTargets& t, uint32_t step0,
                            uint32_t steps, bool update, float* grad_out, float* loss_out, hipStream_t st) {
   if (c.batch % kChunkMax != 0 || !shape_ok(c.shape)) return hipErrorInvalidValue;
+  if (fused_train_ok(c)) return fused_train(s.fused, c, t, step0, steps, update, grad_out, loss_out, st);
   hipError_t e = ensure_scratch(s, c.batch, c.prec, update ? steps : 1, c.shape);
   if (e != hipSuccess) return e;
   switch (c.prec) {
@@ -881,7 +883,8 @@ hipError_t train_run(TrainScratch& s, const TrainConfig& c, const TrainTargets& 
   if (e != hipSuccess) return e;
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
   std::vector<float> l(steps ? steps : 1, 0.0f);
-  if (steps && (e = hipMemcpy(l.data(), s.loss, steps * sizeof(float), hipMemcpyDeviceToHost)) != hipSuccess)
+  const float* rec = fused_train_ok(c) ? s.fused.loss : s.loss;
+  if (steps && (e = hipMemcpy(l.data(), rec, steps * sizeof(float), hipMemcpyDeviceToHost)) != hipSuccess)
     return e;
   *first_loss = l.front();
   *last_loss = l[steps ? steps - 1 : 0];

@@ -799,6 +799,7 @@ static void train_defaults(npt_ctx* c, const npt_train_params* p, TrainConfig& t
   // Sec. 3.2.1 trains with FP16 gradients under a loss scale of 16384
   t.loss_scale = p && p->loss_scale > 0 ? p->loss_scale : (t.prec == NPT_FP16 ? 16384.0f : 1.0f);
   t.master_prec = p ? (int)p->master_prec : NPT_FP32;
+  t.path = p ? (int)p->path : NPT_TRAIN_AUTO;
 }
 
 static int train_check(npt_ctx* c, const TrainConfig& t) {
@@ -810,6 +811,8 @@ static int train_check(npt_ctx* c, const TrainConfig& t) {
     return fail(c, NPT_E_INVALID_ARG, "grad_prec must be FP32, FP16 or BF16");
   if (t.master_prec != NPT_FP32 && t.master_prec != NPT_FP16)
     return fail(c, NPT_E_INVALID_ARG, "master_prec must be FP32 or FP16");
+  if (t.path != NPT_TRAIN_AUTO && t.path != NPT_TRAIN_LAYERED)
+    return fail(c, NPT_E_INVALID_ARG, "path must be NPT_TRAIN_AUTO or NPT_TRAIN_LAYERED");
   return NPT_OK;
 }
 

@@ -59,6 +59,7 @@ struct TrainConfig {
   ColourMatrix cm;   // fixed output colour matrix (network output -> log RGB)
   int master_prec;   // NPT_FP32, or NPT_FP16: binary16 master weights, stochastically rounded updates
   NifShape shape;
+  int path;          // 0: the fused step where available, 1: layer-by-layer GEMMs
 };
 
 struct TrainTargets {
@@ -69,6 +70,24 @@ struct TrainTargets {
   float* v;       // Adam second moments
 };
 
+// Two-launch training step (k_train_fused.hip) for the LDS-resident shapes
+// with FP16 operands and batches of a multiple of 128: operand copies
+// of the weights as MFMA fragments (forward and transposed), per-workgroup
+// gradient sums and losses, Adam.
+struct FusedScratch {
+  void* fpack = nullptr;     // forward weight fragments of layers 0..L-1
+  void* tpack = nullptr;     // transposed fragments of layers 1..L-1
+  int32_t* fmap = nullptr;   // parameter -> position in fpack (-1: none)
+  int32_t* tmap = nullptr;   // parameter -> position in tpack (-1: none)
+  float* partial = nullptr;  // [workgroups][params]
+  float* loss = nullptr;     // per-step losses
+  float* loss_part = nullptr;  // [workgroups]
+  int32_t* bmap = nullptr;   // parameter -> position in the head table (-1: none)
+  float* head = nullptr;     // head table: hidden biases, output biases and weights (FP32)
+  size_t bytes[9] = {};
+  int arch = -1;             // shape the maps were built for
+  void release();
+};
 // Device scratch of the training step, sized on first use.
 struct TrainScratch {
   void* act = nullptr;      // X0 [B][4 n_freq] then the inputs of layers 1..L, operand precision
@@ -85,8 +104,13 @@ struct TrainScratch {
   float* err_part = nullptr;
   size_t bytes[10] = {};    // allocated bytes of act .. loss
   uint64_t grid_cap = 0;
+  FusedScratch fused;
   void release();
 };
+
+bool fused_train_ok(const TrainConfig& c);
+hipError_t fused_train(FusedScratch& s, const TrainConfig& c, const TrainTargets& t, uint32_t step0, uint32_t steps,
+                       bool update, float* grad_out, float* loss_out, hipStream_t st);
 
 hipError_t train_run(TrainScratch& s, const TrainConfig& c, const TrainTargets& t, uint32_t step0, uint32_t steps,
                      float* first_loss, float* last_loss, hipStream_t st);

@@ -65,7 +65,8 @@ class npt_nif_desc(C.Structure):
 class npt_train_params(C.Structure):
     _fields_ = [("batch", C.c_uint32), ("samples", C.c_uint64), ("lr", C.c_float), ("beta1", C.c_float),
                 ("beta2", C.c_float), ("eps", C.c_float), ("huber_delta", C.c_float), ("seed", C.c_uint64),
-                ("grad_prec", C.c_uint32), ("loss_scale", C.c_float), ("master_prec", C.c_uint32)]
+                ("grad_prec", C.c_uint32), ("loss_scale", C.c_float), ("master_prec", C.c_uint32),
+                ("path", C.c_uint32)]
 
 
 class npt_train_stats(C.Structure):
@@ -339,10 +340,13 @@ def npt_nif_get_dequantized(ctx, n=43779):
     return out
 
 
+TRAIN_AUTO, TRAIN_LAYERED = 0, 1  # npt_train_params.path
+
+
 def train_params(batch=0, samples=0, lr=0.0, beta1=0.0, beta2=0.0, eps=0.0, huber_delta=0.0, seed=0,
-                 grad_prec=FP32, loss_scale=0.0, master_prec=FP32):
+                 grad_prec=FP32, loss_scale=0.0, master_prec=FP32, path=TRAIN_AUTO):
     return npt_train_params(batch, samples, lr, beta1, beta2, eps, huber_delta, seed, grad_prec, loss_scale,
-                            master_prec)
+                            master_prec, path)
 
 
 def npt_nif_train(ctx, params: npt_train_params = None, stream=None):

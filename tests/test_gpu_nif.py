@@ -121,8 +121,10 @@ GRAD_TOL = {npt.FP32: 3e-6, npt.FP16: 4e-3, npt.BF16: 1.2e-2}
 LOSS_TOL = {npt.FP32: 1e-6, npt.FP16: 2.5e-4, npt.BF16: 4e-4}
 
 
-@pytest.mark.parametrize("prec", [npt.FP32, npt.FP16, npt.BF16])
-def test_training_gradient_matches_oracle(prec, small_sky):
+# FP16 takes the fused step by default; the layer-by-layer one is covered too
+@pytest.mark.parametrize("prec,path", [(npt.FP32, npt.TRAIN_AUTO), (npt.FP16, npt.TRAIN_AUTO),
+                                       (npt.FP16, npt.TRAIN_LAYERED), (npt.BF16, npt.TRAIN_AUTO)])
+def test_training_gradient_matches_oracle(prec, path, small_sky):
     torch = torch_cuda()
     p = synth.nif_init(11)
     B, seed, step = 2048, 5, 2
@@ -132,7 +134,7 @@ def test_training_gradient_matches_oracle(prec, small_sky):
         npt.npt_nif_upload(ctx, p)
         grad = torch.zeros(43779, dtype=torch.float32, device="cuda")
         loss = torch.zeros(1, dtype=torch.float32, device="cuda")
-        tp = npt.train_params(batch=B, seed=seed, grad_prec=prec)
+        tp = npt.train_params(batch=B, seed=seed, grad_prec=prec, path=path)
         npt.npt_nif_train_grad(ctx, tp, step, grad, loss)
         torch.cuda.synchronize()
         g = grad.cpu().numpy().astype(np.float64)
@@ -143,7 +145,7 @@ def test_training_gradient_matches_oracle(prec, small_sky):
     lo, go = O.nif_loss_grad(SHAPE, p.astype(np.float64), uv, tg, 1e-3)
     lq, gq = O.nif_loss_grad_q(SHAPE, p.astype(np.float64), prec, LOSS_SCALE[prec], uv, tg, 1e-3)
     r, rq = rel_rmse(g, go), rel_rmse(g, gq)
-    print(f"grad prec {prec}: relRMSE {rq:.3e} (rounded oracle), {r:.3e} (FP64); loss {lg:.7e} vs {lq:.7e} "
+    print(f"grad prec {prec} path {path}: relRMSE {rq:.3e} (rounded oracle), {r:.3e} (FP64); loss {lg:.7e} vs {lq:.7e} "
           f"(rounded), {lo:.7e} (FP64)")
     assert abs(lg - lq) <= LOSS_TOL_Q[prec] * abs(lq)
     assert rq <= GRAD_TOL_Q[prec]
