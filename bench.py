@@ -77,6 +77,8 @@ def _parse():
                    help="BVH4 node encoding: FP32 boxes (112 B), FP32 lower planes + binary16 extents (96 B), "
                         "or 8-bit planes on a per-node step (64 B)")
     p.add_argument("--max-leaf", type=int, default=2, help="primitives per BVH leaf (1..8)")
+    p.add_argument("--sort-rays", type=int, default=0,
+                   help="1: sort every 1024-ray chunk of the secondary queues (direction octant, origin) before tracing")
     p.add_argument("--lds-levels", type=int, default=0,
                    help="top BVH levels staged in LDS per workgroup (of the two-level scene: of its top tree)")
     p.add_argument("--nif-sizes", action="store_true",
@@ -552,9 +554,9 @@ def nif_sizes(args):
                                    skip=skip)
                 npt.npt_nif_set_precision(ctx, prec)
                 npt.npt_set_env_mode(ctx, npt.ENV_NIF)
-                npt.npt_set_render_options(ctx, rr_start=3, kernel_timing=1)
+                npt.npt_set_render_options(ctx, rr_start=3, kernel_timing=1, sort_rays=args.sort_rays)
                 el, st = _timed_renders(npt, torch, ctx, W, H, spp, depth, 1, out, 2, 1)
-                npt.npt_set_render_options(ctx, rr_start=3)
+                npt.npt_set_render_options(ctx, rr_start=3, sort_rays=args.sort_rays)
                 rows.append({"hidden": hidden, "layers": layers, "skip": skip, "features": F,
                              "path": "layered GEMMs" if layered else "LDS-resident",
                              "prec": {npt.FP16: "fp16", npt.FP8: "fp8"}[prec],
@@ -607,7 +609,7 @@ def main():
         extra["bvh_build_ms"] = 1e3 * (time.perf_counter() - t0)
         _stage(f"scene and BVH ready ({extra['bvh_build_ms']:.0f} ms build)")
         extra["bvh"] = {**npt.npt_bvh_info(ctx), "node_format": args.node_format, "lds_levels": args.lds_levels,
-                        "max_leaf": args.max_leaf,
+                        "max_leaf": args.max_leaf, "sort_rays": args.sort_rays,
                         "node_bytes": {"fp32": B_NODE[4], "fp16-extent": 96, "q8": 64}[args.node_format]}
         del scene
         npt.npt_env_upload(ctx, env)
@@ -638,7 +640,7 @@ def main():
             del a, b
 
         # counting render (outside the timed region): algorithmic bytes
-        npt.npt_set_render_options(ctx, rr_start=3, count_visits=1)
+        npt.npt_set_render_options(ctx, rr_start=3, count_visits=1, sort_rays=args.sort_rays)
         npt.npt_render(ctx, W, H, spp, depth, seed, out)
         cs = npt.npt_get_stats(ctx)
         rays = np.array(cs["rays"], np.float64)
@@ -657,7 +659,7 @@ def main():
 
         # the timed workload, with per-kernel events
         _stage("counting render done; timed renders")
-        npt.npt_set_render_options(ctx, rr_start=3, kernel_timing=1)
+        npt.npt_set_render_options(ctx, rr_start=3, kernel_timing=1, sort_rays=args.sort_rays)
         elapsed, st = _timed_renders(npt, torch, ctx, W, H, spp, depth, seed, out, args.steps, args.warmup)
         _stage(f"timed renders done: {1e3 * elapsed / args.steps:.2f} ms per frame")
         img = {prec_name: out.cpu().numpy().astype(np.float64)}
@@ -748,7 +750,7 @@ def main():
             npt.npt_nif_upload(ctx, trained)
             npt.npt_nif_set_precision(ctx, npt.FP16)
             npt.npt_set_env_mode(ctx, npt.ENV_NIF)
-            npt.npt_set_render_options(ctx, rr_start=3, kernel_timing=1)
+            npt.npt_set_render_options(ctx, rr_start=3, kernel_timing=1, sort_rays=args.sort_rays)
             el, s3 = _timed_renders(npt, torch, ctx, W, H, c3["spp"], c3["depth"], seed, out, args.steps, 1)
             extra["small_bvh_fp16"] = {"path_samples_per_s": W * H * c3["spp"] * args.steps / el,
                                        "ms_per_render": 1e3 * el / args.steps, "extend_ms_per_render": s3["ms_trace"],

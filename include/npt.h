@@ -181,13 +181,19 @@ typedef struct {
  * environment launch with HIP events on the render stream
  * (npt_stats.ms_trace / ms_shade / ms_env);
  * count_visits: 1 = use the counting variant of the extend kernel
- * (npt_stats.node_visits / prim_tests; slower, for byte accounting only). */
+ * (npt_stats.node_visits / prim_tests; slower, for byte accounting only).
+ * sort_rays: 1 = before each extend launch of depth 2 and beyond, sort every
+ * chunk of 1024 queued rays by direction octant, origin (Morton order over a
+ * 32^3 grid on the scene bounds) and direction, and trace them in that order
+ * (hits, shading and images unchanged; the sort's time counts as trace time;
+ * npt_render_noalloc ignores it). */
 typedef struct {
     uint32_t rr_start;
     uint32_t samples_per_pass;
     uint32_t pool_paths;
     uint32_t kernel_timing;
     uint32_t count_visits;
+    uint32_t sort_rays;
 } npt_render_options;
 
 #define NPT_MAX_DEPTH 64

@@ -617,7 +617,8 @@ template <int kWidth, int kStack, bool kCount, bool kLds>
 // latency; measured 11 % faster on the large-BVH scene than the five the
 // unconstrained allocation allows, seven spills too much.
 __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_extend(SceneView sc, uint32_t depth, RayQueue in, float4* hits,
-                                                        uint32_t* cnt, unsigned long long* visit_cnt) {
+                                                        uint32_t* cnt, unsigned long long* visit_cnt,
+                                                        const uint32_t* order) {
   extern __shared__ float4 lds_nodes[];
   using Stack = LaneStack<kStack, kTraceBlock>;
   __shared__ uint32_t stack_mem[(Stack::kShort > 0 ? Stack::kShort : 1) * kTraceBlock];
@@ -658,7 +659,7 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(6))
           __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
       const uint32_t take = min(pool_end - pool, (uint32_t)__popcll(idle));
       if (!busy && rank < take) {
-        ray = pool + rank;
+        ray = order ? order[pool + rank] : pool + rank;  // queue slot of the ray
         const float* qo = reinterpret_cast<const float*>(in.o + ray);
         const float* qd = reinterpret_cast<const float*>(in.d + ray);
         const V3 o{qo[0], qo[1], qo[2]}, d{qd[0], qd[1], qd[2]};
@@ -705,6 +706,75 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(6))
     atomicAdd(&visit_cnt[depth - 1], (unsigned long long)n_nodes);
     atomicAdd(&visit_cnt[64 + depth - 1], (unsigned long long)n_prims);
   }
+}
+
+// ---------------------------------------------------------------------------
+// ray order (optional): every chunk of kSortChunk queued rays is sorted by a
+// key of direction octant (3 bits), origin (Morton code of a 32^3 grid over
+// the scene bounds, 15 bits) and direction (|d.x|, |d.y| in quarters, 4
+// bits), ties by queue slot; the extend kernel then takes the chunk's rays
+// in that order through `order` and writes each hit to the ray's own slot.
+// ---------------------------------------------------------------------------
+constexpr int kSortChunk = 1024, kSortBlock = 256;
+
+__device__ __forceinline__ uint32_t spread5(uint32_t x) {  // bit i -> bit 3 i
+  uint32_t r = 0;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) r |= ((x >> i) & 1u) << (3 * i);
+  return r;
+}
+
+__device__ __forceinline__ uint32_t grid5(float x, float lo, float scale) {
+  return (uint32_t)fminf(fmaxf((x - lo) * scale, 0.0f), 31.0f);
+}
+
+__global__ __launch_bounds__(kSortBlock) void k_sort_chunks(RayQueue in, const uint32_t* cnt, uint32_t depth,
+                                                           float3 lo, float3 scale, uint32_t* order) {
+  __shared__ uint32_t key[kSortChunk];
+  const uint32_t n = cnt[kCntRays + depth];
+  const uint32_t base = blockIdx.x * kSortChunk;
+  if (base >= n) return;
+  for (int i = threadIdx.x; i < kSortChunk; i += kSortBlock) {
+    const uint32_t r = base + i;
+    uint32_t k = 0x3FFFFFu;  // past the queue's end: last (ties go by slot)
+    if (r < n) {
+      const float4 o = in.o[r], d = in.d[r];
+      const uint32_t oct = (d.x < 0.0f ? 1u : 0u) | (d.y < 0.0f ? 2u : 0u) | (d.z < 0.0f ? 4u : 0u);
+      const uint32_t m = spread5(grid5(o.x, lo.x, scale.x)) | (spread5(grid5(o.y, lo.y, scale.y)) << 1) |
+                         (spread5(grid5(o.z, lo.z, scale.z)) << 2);
+      const uint32_t dq = (min(3u, (uint32_t)(fabsf(d.x) * 4.0f)) << 2) | min(3u, (uint32_t)(fabsf(d.y) * 4.0f));
+      k = (oct << 19) | (m << 4) | dq;
+    }
+    key[i] = (k << 10) | (uint32_t)i;
+  }
+  __syncthreads();
+  // bitonic sort, ascending
+  for (int k2 = 2; k2 <= kSortChunk; k2 <<= 1)
+    for (int j = k2 >> 1; j > 0; j >>= 1) {
+      for (int t = threadIdx.x; t < kSortChunk / 2; t += kSortBlock) {
+        const int i = (t / j) * 2 * j + t % j, l = i + j;
+        const uint32_t a = key[i], b = key[l];
+        if ((a > b) == ((i & k2) == 0)) {
+          key[i] = b;
+          key[l] = a;
+        }
+      }
+      __syncthreads();
+    }
+  for (int i = threadIdx.x; i < kSortChunk; i += kSortBlock)
+    if (base + i < n) order[base + i] = base + (key[i] & (uint32_t)(kSortChunk - 1));
+}
+
+hipError_t launch_sort_chunks(const RayQueue& in, const uint32_t* cnt, uint32_t depth, uint64_t max_rays,
+                              const float lo[3], const float hi[3], uint32_t* order, hipStream_t s) {
+  float3 l3 = make_float3(lo[0], lo[1], lo[2]), sc3;
+  const float ext[3] = {hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]};
+  sc3.x = ext[0] > 0.0f ? 32.0f / ext[0] : 0.0f;
+  sc3.y = ext[1] > 0.0f ? 32.0f / ext[1] : 0.0f;
+  sc3.z = ext[2] > 0.0f ? 32.0f / ext[2] : 0.0f;
+  const uint64_t chunks = (max_rays + kSortChunk - 1) / kSortChunk;
+  hipLaunchKernelGGL(k_sort_chunks, dim3((uint32_t)chunks), dim3(kSortBlock), 0, s, in, cnt, depth, l3, sc3, order);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -975,12 +1045,12 @@ hipError_t launch_generate(const CameraView& cam, const PassView& pv, const RayQ
 
 hipError_t launch_extend(int stack_depth, const SceneView& sc, uint32_t depth, uint64_t max_rays,
                          const RayQueue& in, float4* hits, uint32_t* cnt, unsigned long long* visit_cnt,
-                         int num_cus, hipStream_t s) {
+                         const uint32_t* order, int num_cus, hipStream_t s) {
   const size_t lds = (size_t)sc.lds_nodes * sc.node_float4s * sizeof(float4);
   const int grid = grid_for(max_rays, kTraceBlock, num_cus * 32);
 #define NPT_LAUNCH_EXTEND(W, S, C, L)                                                                        \
   hipLaunchKernelGGL((k_extend<W, S, C, L>), dim3(grid), dim3(kTraceBlock), L ? lds : 0, s, sc, depth, in, hits, cnt, \
-                     visit_cnt)
+                     visit_cnt, order)
 #define NPT_LAUNCH_EXTEND_S(W, L)                                                                        \
   switch (stack_depth) {                                                                                \
     case 16: if (c) NPT_LAUNCH_EXTEND(W, 16, true, L); else NPT_LAUNCH_EXTEND(W, 16, false, L); break;    \

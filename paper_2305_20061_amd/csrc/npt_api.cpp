@@ -107,7 +107,7 @@ struct npt_ctx {
   TrainScratch train;
 
   // render scratch
-  DevBuf qa_o, qa_d, qa_b, qb_o, qb_d, qb_b, env_d, env_b, d_L, d_hits, d_accum, d_cnt, d_stats;
+  DevBuf qa_o, qa_d, qa_b, qb_o, qb_d, qb_b, env_d, env_b, d_L, d_hits, d_accum, d_cnt, d_stats, d_order;
   void* noalloc_scratch = nullptr;  // this device's fixed scratch (npt_render_noalloc)
   hipError_t noalloc_status = hipErrorNotInitialized;
   npt_stats stats{};
@@ -966,6 +966,7 @@ struct RenderBufs {
   float4 *qa_o, *qa_d, *qa_b, *qb_o, *qb_d, *qb_b, *env_d, *env_b, *L, *hits, *accum;
   uint32_t* cnt;
   unsigned long long* stats;
+  uint32_t* order = nullptr;  // trace order of sorted secondary rays (sort_rays), else null
 };
 constexpr int kPoolStreams = 10;  // float4 streams per path slot
 
@@ -1025,7 +1026,10 @@ static int render_passes(npt_ctx* c, uint32_t W, uint32_t H, uint64_t s_begin, u
         HIP_TRY(c, event_pair(c->trace_events));
         HIP_TRY(c, hipEventRecord(c->trace_events[c->trace_events.size() - 2], s));
       }
-      HIP_TRY(c, launch_extend(c->stack_depth, sv, k, n, in, b.hits, cnt, visit_cnt, c->num_cus, s));
+      const bool sorted = b.order && k >= 2;
+      if (sorted) HIP_TRY(c, launch_sort_chunks(in, cnt, k, n, c->bvh.lo, c->bvh.hi, b.order, s));
+      HIP_TRY(c, launch_extend(c->stack_depth, sv, k, n, in, b.hits, cnt, visit_cnt, sorted ? b.order : nullptr,
+                               c->num_cus, s));
       if (timing) {
         HIP_TRY(c, hipEventRecord(c->trace_events.back(), s));
         HIP_TRY(c, event_pair(c->shade_events));
@@ -1094,10 +1098,14 @@ static int render_pooled(npt_ctx* c, uint32_t W, uint32_t H, uint64_t s_begin, u
   }
   HIP_TRY(c, c->d_cnt.ensure(kCntWords * sizeof(uint32_t)));
   HIP_TRY(c, c->d_stats.ensure(4 * NPT_MAX_DEPTH * sizeof(unsigned long long)));
-  const RenderBufs b{c->qa_o.as<float4>(), c->qa_d.as<float4>(), c->qa_b.as<float4>(), c->qb_o.as<float4>(),
-                     c->qb_d.as<float4>(), c->qb_b.as<float4>(), c->env_d.as<float4>(), c->env_b.as<float4>(),
-                     c->d_L.as<float4>(), c->d_hits.as<float4>(), accum, c->d_cnt.as<uint32_t>(),
-                     c->d_stats.as<unsigned long long>()};
+  RenderBufs b{c->qa_o.as<float4>(), c->qa_d.as<float4>(), c->qa_b.as<float4>(), c->qb_o.as<float4>(),
+               c->qb_d.as<float4>(), c->qb_b.as<float4>(), c->env_d.as<float4>(), c->env_b.as<float4>(),
+               c->d_L.as<float4>(), c->d_hits.as<float4>(), accum, c->d_cnt.as<uint32_t>(),
+               c->d_stats.as<unsigned long long>()};
+  if (c->opt.sort_rays) {
+    HIP_TRY(c, c->d_order.ensure(slots * sizeof(uint32_t)));
+    b.order = c->d_order.as<uint32_t>();
+  }
   unsigned long long* visit_cnt = c->opt.count_visits ? b.stats + 2 * NPT_MAX_DEPTH : nullptr;
   HIP_TRY(c, launch_stats_clear(b.stats, s));
   HIP_TRY(c, hipEventRecord(c->ev0, s));

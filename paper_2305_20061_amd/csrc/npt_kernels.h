@@ -13,7 +13,11 @@ hipError_t launch_generate(const CameraView& cam, const PassView& pv, const RayQ
                            hipStream_t s);
 hipError_t launch_extend(int stack_depth, const SceneView& sc, uint32_t depth, uint64_t max_rays,
                          const RayQueue& in, float4* hits, uint32_t* cnt, unsigned long long* visit_cnt,
-                         int num_cus, hipStream_t s);
+                         const uint32_t* order, int num_cus, hipStream_t s);
+// every chunk of 1024 queued rays of `depth` sorted into a trace order
+// (k_extend's `order`); lo / hi: scene bounds
+hipError_t launch_sort_chunks(const RayQueue& in, const uint32_t* cnt, uint32_t depth, uint64_t max_rays,
+                              const float lo[3], const float hi[3], uint32_t* order, hipStream_t s);
 hipError_t launch_shade(const SceneView& sc, const PassView& pv, uint32_t depth, uint64_t max_rays,
                         const RayQueue& in, const float4* hits, const RayQueue& out, const EnvQueue& env,
                         float4* L, uint32_t* cnt, int num_cus, hipStream_t s);

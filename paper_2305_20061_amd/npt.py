@@ -76,7 +76,7 @@ class npt_train_stats(C.Structure):
 
 class npt_render_options(C.Structure):
     _fields_ = [("rr_start", C.c_uint32), ("samples_per_pass", C.c_uint32), ("pool_paths", C.c_uint32),
-                ("kernel_timing", C.c_uint32), ("count_visits", C.c_uint32)]
+                ("kernel_timing", C.c_uint32), ("count_visits", C.c_uint32), ("sort_rays", C.c_uint32)]
 
 
 class npt_stats(C.Structure):
@@ -279,8 +279,9 @@ def npt_set_camera(ctx, eye, look_at, up, vfov_deg):
     _check(ctx, lib().npt_set_camera(ctx, C.byref(cam)))
 
 
-def npt_set_render_options(ctx, rr_start=3, samples_per_pass=0, pool_paths=0, kernel_timing=0, count_visits=0):
-    o = npt_render_options(rr_start, samples_per_pass, pool_paths, kernel_timing, count_visits)
+def npt_set_render_options(ctx, rr_start=3, samples_per_pass=0, pool_paths=0, kernel_timing=0, count_visits=0,
+                           sort_rays=0):
+    o = npt_render_options(rr_start, samples_per_pass, pool_paths, kernel_timing, count_visits, sort_rays)
     _check(ctx, lib().npt_set_render_options(ctx, C.byref(o)))
 
 

@@ -135,6 +135,25 @@ def test_render_resumes_by_sample_index(small_sky):
     assert st["paths"] == W * H * 4 and st["rays"][0] == W * H * 4
 
 
+@pytest.mark.parametrize("cfg", [2, 3])
+def test_sorted_ray_order_does_not_change_images(cfg, small_sky):
+    """Tracing each 1024-ray chunk of the secondary queues in sorted order
+    (sort_rays) changes which lane traces which ray, not the hits: images
+    are bit-identical; the ray counts too."""
+    scene = synth.scene_for(cfg)
+    ctx = make_ctx(scene, env=small_sky)
+    try:
+        a = gpu_render(ctx, 96, 64, 6, 8, 7)
+        ra = npt.npt_get_stats(ctx)["rays"]
+        npt.npt_set_render_options(ctx, sort_rays=1)
+        b = gpu_render(ctx, 96, 64, 6, 8, 7)
+        rb = npt.npt_get_stats(ctx)["rays"]
+    finally:
+        npt.npt_destroy(ctx)
+    assert ra[1] > 0 and list(ra) == list(rb)
+    assert np.array_equal(a, b)
+
+
 def test_lds_levels_do_not_change_hits():
     scene = synth.scene_for(3)
     res = []
