@@ -130,8 +130,6 @@ def _counters(name):
         if not isinstance(v, dict) or "kernel_sha" not in v:
             continue
         group = "k_extend" if k.startswith("k_extend") else "nif" if k.startswith("k_nif") else "training"
-        if k == "training_gemm_tiled":
-            continue
         ok = v["kernel_sha"] == _sha(COUNTER_SOURCES[group])
         out[k] = {kk: v[kk] for kk in keep if kk in v} if ok else None
     return out
