@@ -35,6 +35,10 @@ METRIC = "path samples/s at 1080p; NIF rays/s + MFMA util vs env-map lookup at e
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"fp16": 2500.0, "bf16": 2500.0, "fp8": 5000.0, "fp32": 157.3}
 NIF_FLOP_PER_QUERY = 2 * (64 * 96 + 4 * 96 * 96 + 96 * 3)  # 86,592
+# FP8 mode runs the first and output layers on FP16 MFMAs: the peak of the
+# query's FLOP mix (1 / (f16 share / 2.5 + f8 share / 5.0) PFLOP/s)
+_F8_SHARE = 2 * 4 * 96 * 96 / NIF_FLOP_PER_QUERY
+MFMA_PEAK_TFLOPS_FP8_MIX = 1.0 / ((1.0 - _F8_SHARE) / 2500.0 + _F8_SHARE / 5000.0)
 # algorithmic bytes of the extend kernel (closest hit): ray origin and
 # direction in (24 B), one node per BVH node fetched (64 B two-wide, 112 B
 # four-wide), 48 B per primitive slot tested, 16 B hit record out; instance
@@ -677,10 +681,14 @@ def main():
                     tfk = q * NIF_FLOP_PER_QUERY / (ms * 1e-3) / 1e12
                     per_depth.append({"depth": k + 1, "queries": q, "ms": ms, "queries_per_s": q / (ms * 1e-3),
                                       "mfma_util": tfk / MFMA_PEAK_TFLOPS[name]})
-            return {"precision": name, "queries_per_render": s["env_queries"],
-                    "queries_per_s": s["env_queries"] / (s["ms_env"] * 1e-3), "ms_per_render": s["ms_env"],
-                    "launches": s["env_launches"], "tflops": tf, "mfma_util": tf / MFMA_PEAK_TFLOPS[name],
-                    "flop_per_query": NIF_FLOP_PER_QUERY, "per_depth": per_depth}
+            r = {"precision": name, "queries_per_render": s["env_queries"],
+                 "queries_per_s": s["env_queries"] / (s["ms_env"] * 1e-3), "ms_per_render": s["ms_env"],
+                 "launches": s["env_launches"], "tflops": tf, "mfma_util": tf / MFMA_PEAK_TFLOPS[name],
+                 "flop_per_query": NIF_FLOP_PER_QUERY, "per_depth": per_depth}
+            if name == "fp8":  # against the peak of its FP16 / E4M3 mix
+                r["mfma_util_mixed_peak"] = tf / MFMA_PEAK_TFLOPS_FP8_MIX
+                r["mixed_peak_tflops"] = MFMA_PEAK_TFLOPS_FP8_MIX
+            return r
 
         extra["kernels"] = {"extend_ms_per_render": st["ms_trace"], "extend_launches": st["trace_launches"],
                             "extend_ms_per_launch": trace_launch_ms, "shade_ms_per_render": st["ms_shade"],
