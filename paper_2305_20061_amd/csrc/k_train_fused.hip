@@ -532,8 +532,8 @@ struct FusedUpdate {
 };
 
 // The workgroups' sums of 256 parameters: wave q adds groups q, q + 8, ...
-// (16-byte loads, four parameters per lane) into four interleaved running
-// sums (group q + 8 i into sum i mod 4: independent loads in flight), the
+// (16-byte loads, four parameters per lane) into eight interleaved running
+// sums (group q + 8 i into sum i mod 8: eight loads in flight), the
 // eight waves' sums are added in wave order; then per parameter the gradient
 // (kUpdate false) or Adam (Kingma & Ba, Alg. 1) on the master weights and the
 // rewrite of both operand copies.  Workgroup 0's first wave also sums the
@@ -541,28 +541,46 @@ struct FusedUpdate {
 template <int P, bool kUpdate, bool kSR>
 __global__ __launch_bounds__(64 * kUpdateWaves) void k_fused_update(FusedUpdate u) {
   using Elem = typename Prec<P>::Elem;
-  constexpr int W = kUpdateWaves, R = 4;
+  constexpr int W = kUpdateWaves, R = 8;
   __shared__ float part[W][256];
   const int q = threadIdx.x >> 6, jj = threadIdx.x & 63;
   const int64_t j0 = (int64_t)blockIdx.x * 256;
   float4 sum[R];
 #pragma unroll
   for (int i = 0; i < R; ++i) sum[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-  if (j0 + 4 * jj < u.np)
-    for (int k = q; k < u.groups; k += R * W)
+  auto row = [&](int k) { return *reinterpret_cast<const float4*>(u.partial + (size_t)k * u.ld + j0 + 4 * jj); };
+  auto add = [](float4& a, const float4& x) {
+    a.x += x.x;
+    a.y += x.y;
+    a.z += x.z;
+    a.w += x.w;
+  };
+  if (j0 + 4 * jj < u.np) {
+    int k = q;
+    // all R loads of a round issued before any is used
+    for (; k + (R - 1) * W < u.groups; k += R * W) {
+      float4 x[R];
 #pragma unroll
-      for (int i = 0; i < R; ++i)
-        if (k + i * W < u.groups) {
-          const float4 x = *reinterpret_cast<const float4*>(u.partial + (size_t)(k + i * W) * u.ld + j0 + 4 * jj);
-          sum[i].x += x.x;
-          sum[i].y += x.y;
-          sum[i].z += x.z;
-          sum[i].w += x.w;
-        }
-  part[q][4 * jj] = (sum[0].x + sum[1].x) + (sum[2].x + sum[3].x);
-  part[q][4 * jj + 1] = (sum[0].y + sum[1].y) + (sum[2].y + sum[3].y);
-  part[q][4 * jj + 2] = (sum[0].z + sum[1].z) + (sum[2].z + sum[3].z);
-  part[q][4 * jj + 3] = (sum[0].w + sum[1].w) + (sum[2].w + sum[3].w);
+      for (int i = 0; i < R; ++i) x[i] = row(k + i * W);
+#pragma unroll
+      for (int i = 0; i < R; ++i) add(sum[i], x[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < R - 1; ++i)
+      if (k + i * W < u.groups) add(sum[i], row(k + i * W));
+  }
+  float4 t = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  {
+    const float4 a = sum[0], b = sum[1], c = sum[2], d = sum[3], e = sum[4], f = sum[5], g = sum[6], hh = sum[7];
+    t.x = ((a.x + b.x) + (c.x + d.x)) + ((e.x + f.x) + (g.x + hh.x));
+    t.y = ((a.y + b.y) + (c.y + d.y)) + ((e.y + f.y) + (g.y + hh.y));
+    t.z = ((a.z + b.z) + (c.z + d.z)) + ((e.z + f.z) + (g.z + hh.z));
+    t.w = ((a.w + b.w) + (c.w + d.w)) + ((e.w + f.w) + (g.w + hh.w));
+  }
+  part[q][4 * jj] = t.x;
+  part[q][4 * jj + 1] = t.y;
+  part[q][4 * jj + 2] = t.z;
+  part[q][4 * jj + 3] = t.w;
   __syncthreads();
   const int64_t j = j0 + threadIdx.x;
   if (threadIdx.x < 256 && j < u.np) {
