@@ -19,13 +19,17 @@
 //
 // k_fused_update: the workgroups' sums in a fixed order (deterministic),
 // then Adam on the FP32 master weights, which also rewrites both operand
-// copies of each weight (forward and transposed fragments) through
-// position maps built on the host.
+// copies of each weight (forward and transposed fragments) and the head
+// table (biases and the output layer, FP32) through position maps built on
+// the host.
 //
 // Rounding points are those of the layer-by-layer path: features, weights
 // and post-ReLU activations rounded to the operand format, FP32 sums, the
 // output layer in FP32, the loss-scaled gradients at hidden-layer outputs
-// rounded to the operand format after the ReLU mask.
+// rounded to the operand format after the ReLU mask.  The features' sin and
+// cos come from the hardware instructions, as in FP16 inference (within an
+// FP32 ulp of the accurate ones; the FP16 rounding of a feature moves
+// rarely).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
