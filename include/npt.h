@@ -77,9 +77,10 @@ typedef struct {
 /* Host BVH build (Sec. 3.1.4 builds a BVH2 on the host).  bins: SAH bins per
  * axis (4..256, 0 = 32); max_leaf: primitives per leaf (1..8, 0 = 4);
  * lds_levels: top tree levels staged in LDS by the traversal kernel (0..8,
- * 0 = none); width: children per node, 2 (the paper's BVH2) or 4 (the
- * binary SAH tree collapsed to 4-wide nodes), 0 = 4.  node_format
- * (width 4, lds_levels 0): NPT_NODES_FP32 (112-byte nodes, FP32 boxes) or
+ * 0 = none; of an instanced scene: levels of its top tree); width:
+ * children per node, 2 (the paper's BVH2) or 4 (the binary SAH tree
+ * collapsed to 4-wide nodes), 0 = 4.  node_format (width 4; Q8 with
+ * lds_levels 0): NPT_NODES_FP32 (112-byte nodes, FP32 boxes) or
  * NPT_NODES_FP16_EXTENT (96-byte nodes: FP32 lower planes and binary16
  * extents rounded up so that the FP32 sum lo + ext covers the box, after
  * Sec. 3.1.4; NPT_E_UNSUPPORTED if an extent exceeds 65504) or NPT_NODES_Q8
@@ -252,8 +253,9 @@ int npt_scene_blas_triangles(npt_ctx *ctx, uint32_t blas_id, const float *xyz, u
  * with instances is traced through a two-level BVH (4-wide top tree over
  * object boxes, one 4-wide tree per mesh; the object-space ray is
  * ((o - translate) / scale, d / scale), so t is shared by both spaces);
- * npt_build_bvh then requires width 4 (or 0) and lds_levels 0.  n = 0
- * removes all instances. */
+ * npt_build_bvh then requires width 4 (or 0), and lds_levels > 0 (top
+ * tree levels in LDS) binary16-extent nodes (NPT_E_UNSUPPORTED otherwise).
+ * n = 0 removes all instances. */
 int npt_scene_instances(npt_ctx *ctx, const npt_instance *inst, uint32_t n);
 int npt_scene_materials(npt_ctx *ctx, const npt_material *m, uint32_t n);
 /* Builds the BVH(s) on the host (binned SAH), flattens them and uploads on

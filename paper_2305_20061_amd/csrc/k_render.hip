@@ -27,6 +27,9 @@ constexpr int kRefillAt = NPT_REFILL_AT;
 #define NPT_LEAF_PERCENT 100  // leaf step once waiting leaf lanes reach this % of the lanes at inner nodes
 #endif
 constexpr uint32_t kLeafPercent = NPT_LEAF_PERCENT;
+#ifndef NPT_EXTEND_WAVES
+#define NPT_EXTEND_WAVES 6  // waves per SIMD the extend kernel's register budget is set for
+#endif
 
 // ---------------------------------------------------------------------------
 // camera (pinhole) -- same definitions as the host-side basis
@@ -60,6 +63,13 @@ __device__ __forceinline__ uint32_t slot_prim(const float4* slots, uint32_t slot
   return __float_as_uint(slots[3 * (size_t)slot].w);
 }
 
+// Pointers typed as LDS (address space 3): their loads and stores are
+// ds_read / ds_write.  Through a generic pointer the compiler may fall back
+// to flat instructions, which go through the texture address and data units
+// (the traversal's busiest path) and wait on both memory counters.
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+typedef __attribute__((address_space(3))) float lds_f32;
+
 // Per-lane traversal stack of kCap entries: the first kShort live in LDS at
 // lds[i * kStride], deeper ones in a private array that only deep
 // traversals reach.  The LDS part is what bounds the occupancy of the trace
@@ -69,7 +79,7 @@ template <int kCap, int kStride>
 struct LaneStack {
   static constexpr int kShort = kCap < NPT_SHORT_STACK ? kCap : NPT_SHORT_STACK;
   static constexpr int kDeep = kCap - kShort;
-  uint32_t* lds;
+  lds_u32* lds;
   uint32_t deep[kDeep > 0 ? kDeep : 1];
   __device__ __forceinline__ void push(int& sp, uint32_t v) {
     if (sp < kShort) {
@@ -105,22 +115,30 @@ struct LaneStack {
   }
 };
 
+// Reciprocal of a direction component for the slab tests: the hardware
+// reciprocal (within 1 ulp) of x with |x| clamped to [1e-20, 2^126], so that
+// it is finite, normal and of x's sign.  Its error is part of what
+// kSlabSlack covers (below); no hit depends on it beyond that, since the
+// slab tests only decide which boxes are opened.
 __device__ __forceinline__ float safe_inverse(float x) {
-  return 1.0f / (fabsf(x) > 1e-20f ? x : copysignf(1e-20f, x));
+  return __builtin_amdgcn_rcpf(copysignf(fminf(fmaxf(fabsf(x), 1e-20f), 0x1p126f), x));
 }
 
 // Ray in the frame a tree is traversed in: origin, direction, the shear of
 // the watertight triangle test and the slab-test terms.
 //
 // A slab distance is formed as fma(plane, ix, -o * ix).  Against the exact
-// (plane - o) / d it errs by a part relative to the distance itself (from
-// the rounded reciprocal and the fma) and a part of up to one rounding of
-// o * ix, which does not shrink with the distance.  The second part is taken
-// out per ray: the origin term of the entry (near) plane of each axis is
-// moved up by 4 ulp-units of |o * ix| and that of the exit (far) plane
-// down, so the computed interval of every axis contains the exact one up to
-// the relative part, which kSlabSlack covers.  Boxes are then never missed
-// by a ray that enters them, whatever the distance between origin and box.
+// (plane - o) / d it errs by a part relative to the distance itself (the
+// reciprocal's error, at most 1 ulp, scales plane and origin term alike,
+// plus the fma's rounding: 1.5 ulp together) and a part of up to one
+// rounding of o * ix, which does not shrink with the distance.  The second
+// part is taken out per ray: the origin term of the entry (near) plane of
+// each axis is moved up by 4 ulp-units of |o * ix| and that of the exit
+// (far) plane down, so the computed interval of every axis contains the
+// exact one up to the relative part, which kSlabSlack (8 ulp, against the
+// 3 ulp that entry and exit distance can drift apart) covers.  Boxes are
+// then never missed by a ray that enters them, whatever the distance
+// between origin and box.
 //
 // Which plane of an axis is the entry plane depends only on the sign of the
 // direction, so 4-wide nodes are read plane row by plane row: near_x is the
@@ -372,17 +390,19 @@ __host__ __device__ constexpr bool q8_nodes(int w) { return w == kQ84 || w == kT
 
 // The world ray of a two-level traversal waits in LDS (six values per lane,
 // stride kStride) rather than in registers: it is needed only when an
-// instance is entered or left.  Volatile reads keep the compiler from
-// holding a register copy across the traversal.
+// instance is entered or left.  The reads go through an address the
+// compiler cannot see through (an empty asm statement), so it neither keeps
+// a register copy across the traversal nor serialises the six reads.
 template <int kStride>
 struct WorldRay {
-  float* p;
+  lds_f32* p;
   __device__ __forceinline__ void store(V3 o, V3 d) const {
     p[0] = o.x; p[kStride] = o.y; p[2 * kStride] = o.z;
     p[3 * kStride] = d.x; p[4 * kStride] = d.y; p[5 * kStride] = d.z;
   }
   __device__ __forceinline__ void load(V3& o, V3& d) const {
-    const volatile float* v = p;
+    lds_f32* v = p;
+    __asm__ volatile("" : "+v"(v));
     o = V3{v[0], v[kStride], v[2 * kStride]};
     d = V3{v[3 * kStride], v[4 * kStride], v[5 * kStride]};
   }
@@ -616,7 +636,7 @@ template <int kWidth, int kStack, bool kCount, bool kLds>
 // Six waves per SIMD (at most 80 VGPRs): the extra waves hide texture-cache
 // latency; measured 11 % faster on the large-BVH scene than the five the
 // unconstrained allocation allows, seven spills too much.
-__global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(6))) void k_extend(SceneView sc, uint32_t depth, RayQueue in, float4* hits,
+__global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(NPT_EXTEND_WAVES))) void k_extend(SceneView sc, uint32_t depth, RayQueue in, float4* hits,
                                                         uint32_t* cnt, unsigned long long* visit_cnt,
                                                         const uint32_t* order) {
   extern __shared__ float4 lds_nodes[];
@@ -624,8 +644,8 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(6))
   __shared__ uint32_t stack_mem[(Stack::kShort > 0 ? Stack::kShort : 1) * kTraceBlock];
   __shared__ float world_mem[(is_two_level(kWidth) ? 6 : 1) * kTraceBlock];
   Stack st;
-  st.lds = stack_mem + threadIdx.x;
-  const WorldRay<kTraceBlock> wr{world_mem + threadIdx.x};
+  st.lds = (lds_u32*)(stack_mem + threadIdx.x);
+  const WorldRay<kTraceBlock> wr{(lds_f32*)(world_mem + threadIdx.x)};
   // the grid is sized for the largest possible queue; workgroups beyond the
   // actual ray count leave before any staging or atomic (the others drain
   // the whole queue)
@@ -972,8 +992,8 @@ __global__ __launch_bounds__(kTraceBlock) void k_trace_primary(SceneView sc, Cam
   stage_lds_nodes(sc, lds_nodes);
   __shared__ float world_mem[(is_two_level(kWidth) ? 6 : 1) * kTraceBlock];
   Stack st;
-  st.lds = stack_mem + threadIdx.x;
-  const WorldRay<kTraceBlock> wr{world_mem + threadIdx.x};
+  st.lds = (lds_u32*)(stack_mem + threadIdx.x);
+  const WorldRay<kTraceBlock> wr{(lds_f32*)(world_mem + threadIdx.x)};
   const uint32_t nblocks = (pv.pixels + kTraceBlock - 1) / kTraceBlock;
   for (uint32_t b = blockIdx.x; b < nblocks; b += gridDim.x) {
     const uint32_t pixel = b * kTraceBlock + threadIdx.x;
