@@ -411,9 +411,16 @@ struct WorldRay {
 // Traversal state of one ray, advanced one node or leaf at a time so that
 // a lane can take a new ray while others in its wave still traverse.
 // Two-level scenes: mark is the stack height at which the current
-// instance's bottom tree began (-1 in the top tree), inst its id.  Top-tree
-// leaves are instances: entering one moves the ray into object space; once
-// the stack is back at the mark the world ray returns.
+// instance's bottom tree began (kInTopTree in the top tree), inst its id.
+// Top-tree leaves are instances: entering one moves the ray into object
+// space; once the stack is back at the mark the world ray returns.  Both
+// frame changes happen in trav_frame, the only place that rewrites the ray
+// frame after trav_begin: node and leaf steps leave it alone (a bottom tree
+// that is done sets mark to kLeavePending), so the compiler keeps the
+// frame's twenty-odd registers in place across steps instead of copying
+// them at every join of the node and leaf paths.
+constexpr int kInTopTree = -1;
+constexpr int kLeavePending = -2;
 struct Trav {
   RayFrame f;
   Hit h;
@@ -429,28 +436,61 @@ __device__ __forceinline__ bool trav_begin(const SceneView& sc, V3 o, V3 d, Trav
   tv.h = Hit{__builtin_inff(), kMiss, kMiss};
   tv.ref = 0;
   tv.sp = 0;
-  tv.mark = -1;
+  tv.mark = kInTopTree;
   tv.inst = 0;
   tv.f = make_frame(o, d);
   return sc.has_geometry != 0;
 }
 
-// After a node without an entered child or a tested leaf: back to the world
-// ray when a bottom tree is done, then the next deferred entry.  Returns
-// false once the stack is empty.
-template <int kWidth, class S, int kStride>
-__device__ __forceinline__ bool trav_pop(S& st, const WorldRay<kStride>& wr, Trav& tv) {
+// After a node without an entered child or a tested leaf: the next
+// deferred entry (a bottom tree that is done leaves the world frame to
+// trav_frame).  Returns false once the stack is empty.
+template <int kWidth, class S>
+__device__ __forceinline__ bool trav_pop(S& st, Trav& tv) {
   if constexpr (is_two_level(kWidth)) {
-    if (tv.sp == tv.mark) {
-      V3 ow, dw;
-      wr.load(ow, dw);
-      tv.f = make_frame(ow, dw);
-      tv.mark = -1;
-    }
+    if (tv.sp == tv.mark) tv.mark = kLeavePending;
   }
   if (tv.sp == 0) return false;
   tv.ref = st.pop(tv.sp);
   return true;
+}
+
+// True when the next step of a two-level traversal is a frame change: a
+// bottom tree is done, or the ray is at a top-tree leaf.  Such lanes wait
+// with the lanes at leaves and change frames in leaf steps, so that the
+// change's code (six divisions on entry) runs for many lanes at once.
+template <int kWidth>
+__device__ __forceinline__ bool needs_frame(const Trav& tv) {
+  if constexpr (is_two_level(kWidth))
+    return tv.mark == kLeavePending || (tv.mark == kInTopTree && (tv.ref & kLeafBit) != 0u);
+  return false;
+}
+
+// The frame change needs_frame asks for: back to the world ray when a
+// bottom tree is done, and into object space when the ray is at a top-tree
+// leaf (its instance entered; the bottom tree's root becomes tv.ref).  Both
+// at once when the entry popped after a finished bottom tree is another
+// instance.
+template <int kWidth, int kStride>
+__device__ __forceinline__ void trav_frame(const SceneView& sc, const WorldRay<kStride>& wr, Trav& tv) {
+  if constexpr (is_two_level(kWidth)) {
+    if (tv.mark == kLeavePending) tv.mark = kInTopTree;
+    const bool enter = tv.mark == kInTopTree && (tv.ref & kLeafBit) != 0u;
+    {
+      V3 o, d;
+      wr.load(o, d);
+      if (enter) {
+        const uint32_t k = (tv.ref >> 3) & 0x0FFFFFFFu;
+        const float4 r0 = sc.instances[2 * (size_t)k], r1 = sc.instances[2 * (size_t)k + 1];
+        o = V3{(o.x - r0.x) / r0.w, (o.y - r0.y) / r0.w, (o.z - r0.z) / r0.w};
+        d = V3{d.x / r0.w, d.y / r0.w, d.z / r0.w};
+        tv.inst = __float_as_uint(r1.y);
+        tv.ref = __float_as_uint(r1.x);
+        tv.mark = tv.sp;
+      }
+      tv.f = make_frame(o, d);
+    }
+  }
 }
 
 // Inner node tv.ref: the children the ray enters are pushed far to near and
@@ -458,9 +498,9 @@ __device__ __forceinline__ bool trav_pop(S& st, const WorldRay<kStride>& wr, Tra
 // complete.  kCount: also count inner-node fetches; kLds: the first
 // sc.lds_nodes nodes (the top levels in BFS order; of a two-level scene, its
 // top tree's) are read from the LDS copy (FP32 and binary16-extent nodes).
-template <int kWidth, bool kCount, bool kLds, class S, int kStride>
-__device__ __forceinline__ bool trav_node(const SceneView& sc, const float4* lds_nodes, S& st,
-                                          const WorldRay<kStride>& wr, Trav& tv, uint32_t& n_nodes) {
+template <int kWidth, bool kCount, bool kLds, class S>
+__device__ __forceinline__ bool trav_node(const SceneView& sc, const float4* lds_nodes, S& st, Trav& tv,
+                                          uint32_t& n_nodes) {
   if constexpr (kCount) ++n_nodes;
   const float lim = tv.h.t * 1.000001f;
   if constexpr (kWidth == 2) {
@@ -507,31 +547,16 @@ __device__ __forceinline__ bool trav_node(const SceneView& sc, const float4* lds
       entered = visit4(reinterpret_cast<const char*>(sc.nodes), off, tv.f, lim, st, tv.sp, tv.ref);
     if (entered) return true;
   }
-  return trav_pop<kWidth>(st, wr, tv);
+  return trav_pop<kWidth>(st, tv);
 }
 
-// Leaf tv.ref: its primitives tested, then a pop; in the top tree of a
-// two-level scene, the instance entered instead (the ray moves to object
-// space and the bottom tree's root becomes tv.ref).  Returns false once the
-// traversal is complete.  kCount: also count primitive tests.
-template <int kWidth, bool kCount, class S, int kStride>
-__device__ __forceinline__ bool trav_leaf(const SceneView& sc, S& st, const WorldRay<kStride>& wr, Trav& tv,
-                                          uint32_t& n_prims) {
-  if (is_two_level(kWidth) && tv.mark < 0) {
-    const uint32_t k = (tv.ref >> 3) & 0x0FFFFFFFu;
-    const float4 r0 = sc.instances[2 * (size_t)k], r1 = sc.instances[2 * (size_t)k + 1];
-    V3 ow, dw;
-    wr.load(ow, dw);
-    const V3 o{(ow.x - r0.x) / r0.w, (ow.y - r0.y) / r0.w, (ow.z - r0.z) / r0.w};
-    const V3 d{dw.x / r0.w, dw.y / r0.w, dw.z / r0.w};
-    tv.f = make_frame(o, d);
-    tv.inst = __float_as_uint(r1.y);
-    tv.ref = __float_as_uint(r1.x);
-    tv.mark = tv.sp;
-    return true;
-  }
+// Leaf tv.ref (of a two-level scene: of a bottom tree, since trav_frame
+// enters top-tree leaves): its primitives tested, then a pop.  Returns false
+// once the traversal is complete.  kCount: also count primitive tests.
+template <int kWidth, bool kCount, class S>
+__device__ __forceinline__ bool trav_leaf(const SceneView& sc, S& st, Trav& tv, uint32_t& n_prims) {
   test_leaf<kCount>(sc, tv.f, tv.ref, is_two_level(kWidth) ? tv.inst : 0u, tv.h, &n_prims);
-  return trav_pop<kWidth>(st, wr, tv);
+  return trav_pop<kWidth>(st, tv);
 }
 
 // Closest hit of one ray, traversed to completion (the first-hit kernel).
@@ -544,9 +569,13 @@ __device__ __forceinline__ Hit trace_closest(const SceneView& sc, const float4* 
   uint32_t nn = 0, np = 0;
   if (!trav_begin(sc, o, d, tv)) return tv.h;
   for (uint32_t v = 0; v < kMaxVisits; ++v) {
+    if (needs_frame<kWidth>(tv)) {
+      trav_frame<kWidth>(sc, wr, tv);
+      continue;
+    }
     const bool more = (tv.ref & kLeafBit) == 0u ? trav_node<kWidth, false, (kWidth == 2 || kWidth == 4 ||
-                                                                              half_nodes(kWidth))>(sc, lds_nodes, st, wr, tv, nn)
-                                                : trav_leaf<kWidth, false>(sc, st, wr, tv, np);
+                                                                              half_nodes(kWidth))>(sc, lds_nodes, st, tv, nn)
+                                                : trav_leaf<kWidth, false>(sc, st, tv, np);
     if (!more) break;
   }
   return tv.h;
@@ -694,26 +723,32 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(NPT
     if (__ballot(busy) == 0) break;
     // advance until few lanes still traverse (none, once the queue is
     // drained).  Each wave step is either a node step (the lanes at inner
-    // nodes visit them) or a leaf step (the lanes at leaves test them or
-    // enter their instance), never both, so that node and leaf code do not
-    // diverge within a step.  A leaf step is taken once the lanes waiting at
-    // leaves reach kLeafPercent % of the lanes at inner nodes: waiting for
-    // every lane to reach a leaf would leave most lanes idle through the
-    // long node sequences of the wave's slowest rays.
+    // nodes visit them) or a leaf step (the lanes at leaves test them; the
+    // lanes that enter or leave an instance change frames), never both, so
+    // that node and leaf code do not diverge within a step.  A leaf step is
+    // taken once the lanes waiting at leaves or for a frame change reach
+    // kLeafPercent % of the lanes at inner nodes: waiting for every lane to
+    // reach a leaf would leave most lanes idle through the long node
+    // sequences of the wave's slowest rays.
     const uint32_t floor_busy = drained ? 0u : (uint32_t)kRefillAt;
     for (;;) {
-      const bool at_node = busy && (tv.ref & kLeafBit) == 0u;
+      const bool at_node = busy && (tv.ref & kLeafBit) == 0u && !needs_frame<kWidth>(tv);
       const uint32_t nn = (uint32_t)__popcll(__ballot(at_node));
       const uint32_t nl = (uint32_t)__popcll(__ballot(busy && !at_node));
       if (nn + nl <= floor_busy) break;
       bool more = true;
-      if (100ull * nl >= (uint64_t)kLeafPercent * nn) {
-        if (busy && !at_node) {
-          more = trav_leaf<kWidth, kCount>(sc, st, wr, tv, n_prims);
+      const bool leaf_step = 100ull * nl >= (uint64_t)kLeafPercent * nn;
+      // frame changes first, ahead of the leaf / node branch: the frame is
+      // then rewritten in one place only, which keeps its registers in place
+      const bool change = leaf_step && busy && needs_frame<kWidth>(tv);
+      if (change) trav_frame<kWidth>(sc, wr, tv);
+      if (leaf_step) {
+        if (busy && !at_node && !change) {
+          more = trav_leaf<kWidth, kCount>(sc, st, tv, n_prims);
           if (++steps >= kMaxVisits) more = false;
         }
       } else if (at_node) {
-        more = trav_node<kWidth, kCount, kLds>(sc, lds_nodes, st, wr, tv, n_nodes);
+        more = trav_node<kWidth, kCount, kLds>(sc, lds_nodes, st, tv, n_nodes);
         if (++steps >= kMaxVisits) more = false;
       }
       if (busy && !more) {
