@@ -781,9 +781,10 @@ def main():
                                        "source, copy-calibrated; not measured in this run",
                      "hbm_frac_measured": (traffic / (trace_launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
                                            if traffic else None),
-                     "limiter": "VALU issue (wave64 VALU instructions at the 4-cycle issue limit) with the tree "
-                                "in L2/MALL; HBM carries about a quarter of the algorithmic bytes (rocprofv3 "
-                                "counters, see counters)"},
+                     "limiter": "VALU issue (the SIMDs about 87 % busy with wave64 VALU instructions at half "
+                                "the lanes active: divergent traversal) and the texture data path (TD busy "
+                                "0.97), with the tree in L2/MALL; HBM carries about a quarter of the algorithmic "
+                                "bytes (rocprofv3 counters, see counters)"},
         "counters": _counters(wl["counters"]),
     }
     line.update(extra)
