@@ -252,7 +252,8 @@ int npt_scene_blas_triangles(npt_ctx *ctx, uint32_t blas_id, const float *xyz, u
  * otherwise or for an unknown blas_id; NPT_E_NAN_INPUT on NaN/Inf).  A scene
  * with instances is traced through a two-level BVH (4-wide top tree over
  * object boxes, one 4-wide tree per mesh; the object-space ray is
- * ((o - translate) / scale, d / scale), so t is shared by both spaces);
+ * ((o - translate) * r, d * r) with r = 1 / scale rounded to FP32 once, so
+ * t is shared by both spaces);
  * npt_build_bvh then requires width 4 (or 0), and lds_levels > 0 (top
  * tree levels in LDS) binary16-extent nodes (NPT_E_UNSUPPORTED otherwise).
  * n = 0 removes all instances. */

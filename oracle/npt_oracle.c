@@ -1352,10 +1352,13 @@ int or_closest_hit(const or_scene *sc, const float o[3], const float d[3], float
         pad_box(wlo, whi);
         double bt = b.hit ? (double)b.t * (1.0 + 1e-6) : INFINITY;
         if (!box_hit(wlo, whi, o, d, bt)) continue;
+        /* object ray: both terms scaled by r = 1 / scale, rounded to FP32 once
+           (instancing is not in the paper; this is the library's definition) */
+        const float r = 1.0f / in->scale;
         float oo[3], od[3];
         for (int a = 0; a < 3; ++a) {
-            oo[a] = (o[a] - in->translate[a]) / in->scale;
-            od[a] = d[a] / in->scale;
+            oo[a] = (o[a] - in->translate[a]) * r;
+            od[a] = d[a] * r;
         }
         mesh_closest(m, k + 1, oo, od, sc->accel, &b);
     }

@@ -833,7 +833,7 @@ bool build_two_level(const std::vector<FlatBvh>& bottoms, const std::vector<Plac
     const uint32_t p = ubits(top.slots[3 * i].w);
     const Placement& o = objects[p];
     records[2 * i] = make_float4(o.translate[0], o.translate[1], o.translate[2], o.scale);
-    records[2 * i + 1] = make_float4(bits(root[o.tree]), bits(o.id), 0.0f, 0.0f);
+    records[2 * i + 1] = make_float4(bits(root[o.tree]), bits(o.id), 1.0f / o.scale, 0.0f);
   }
   // top leaves hold one object each (leaf size 1)
   for (size_t i = 0; i < top.nodes.size(); i += kNode4Float4s) {

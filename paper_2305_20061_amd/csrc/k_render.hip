@@ -482,8 +482,9 @@ __device__ __forceinline__ void trav_frame(const SceneView& sc, const WorldRay<k
       if (enter) {
         const uint32_t k = (tv.ref >> 3) & 0x0FFFFFFFu;
         const float4 r0 = sc.instances[2 * (size_t)k], r1 = sc.instances[2 * (size_t)k + 1];
-        o = V3{(o.x - r0.x) / r0.w, (o.y - r0.y) / r0.w, (o.z - r0.z) / r0.w};
-        d = V3{d.x / r0.w, d.y / r0.w, d.z / r0.w};
+        const float r = r1.z;  // 1 / scale, rounded to FP32 on the host
+        o = V3{(o.x - r0.x) * r, (o.y - r0.y) * r, (o.z - r0.z) * r};
+        d = V3{d.x * r, d.y * r, d.z * r};
         tv.inst = __float_as_uint(r1.y);
         tv.ref = __float_as_uint(r1.x);
         tv.mark = tv.sp;

@@ -62,12 +62,13 @@ struct CameraView {
 
 // Two-level scenes (instancing): the top tree is a BVH4 over object boxes
 // whose leaf refs (count 1) index instance records, two float4 each:
-//   r0 = (translate.xyz, scale), r1 = (bottom root node, instance id, -, -)
-// The base geometry is the record with translate 0, scale 1 and id 0.  The
-// bottom trees follow the top tree in the node array, their primitive slots
-// share one slot array, and a bottom slot's id is the primitive index within
-// its own mesh.  An object ray is ((o - translate) / scale, d / scale): the
-// ray parameter t, and hence the order of hits, is the same in both spaces.
+//   r0 = (translate.xyz, scale), r1 = (bottom root node, instance id, r, -)
+// with r = 1 / scale rounded to FP32.  The base geometry is the record with
+// translate 0, scale 1 and id 0.  The bottom trees follow the top tree in the
+// node array, their primitive slots share one slot array, and a bottom slot's
+// id is the primitive index within its own mesh.  An object ray is
+// ((o - translate) * r, d * r): both scaled alike, so the ray parameter t,
+// and hence the order of hits, is the same in both spaces.
 struct SceneView {
   const float4* nodes;
   const float4* slots;
