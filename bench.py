@@ -127,7 +127,7 @@ def _counters(name):
         return None
     keep = ("mfma_busy", "valu_insts_per_simd_cycle", "valu_per_tile", "mfma_busy_cycles_per_tile",
             "lds_bank_conflict_share", "l2_hit_rate", "l2_request_gbs_128B", "ta_busy", "td_busy",
-            "td_stalled_on_l2", "valu_wave_insts_per_64_node_visits")
+            "td_stalled_on_l2", "valu_wave_insts_per_64_node_visits", "valu_lane_utilization")
     out = {"source": f"profiles/{name}: rocprofv3 --pmc passes over bench.py on the same kernel sources, "
                      "not measured in this run"}
     for k, v in t.items():
@@ -137,6 +137,21 @@ def _counters(name):
         ok = v["kernel_sha"] == _sha(COUNTER_SOURCES[group])
         out[k] = {kk: v[kk] for kk in keep if kk in v} if ok else None
     return out
+
+
+def _extend_limiter(counters):
+    """What holds the extend kernel, in the words of its committed counter
+    record (a wave64 FP32 VALU instruction takes 4 SIMD cycles)."""
+    k = (counters or {}).get("k_extend")
+    if not k:
+        return "no counter record for these kernel sources"
+    busy = 4.0 * k["valu_insts_per_simd_cycle"]
+    lanes = k.get("valu_lane_utilization")
+    active = f"{lanes:.2f} of the lanes active" if lanes is not None else "part of the lanes active"
+    return (f"VALU issue (the SIMDs {100 * busy:.0f} % busy with wave64 VALU instructions, {active}: "
+            f"divergent traversal) and the texture data path (TD busy {k['td_busy']:.2f}), "
+            "with the tree in L2/MALL; HBM carries about a quarter of the algorithmic bytes "
+            "(rocprofv3 counters, see counters)")
 
 
 def _traffic_per_launch(name):
@@ -765,6 +780,7 @@ def main():
         finally:
             npt.npt_destroy(ctx)
 
+    counters = _counters(wl["counters"])
     line = {
         "metric": METRIC, "value": value, "unit": "path samples/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
@@ -781,11 +797,8 @@ def main():
                                        "source, copy-calibrated; not measured in this run",
                      "hbm_frac_measured": (traffic / (trace_launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
                                            if traffic else None),
-                     "limiter": "VALU issue (the SIMDs about 87 % busy with wave64 VALU instructions at half "
-                                "the lanes active: divergent traversal) and the texture data path (TD busy "
-                                "0.97), with the tree in L2/MALL; HBM carries about a quarter of the algorithmic "
-                                "bytes (rocprofv3 counters, see counters)"},
-        "counters": _counters(wl["counters"]),
+                     "limiter": _extend_limiter(counters)},
+        "counters": counters,
     }
     line.update(extra)
     if not args.no_cpu_baseline:
