@@ -108,3 +108,55 @@ def test_large_bvh_full_size_sampled_hits_match_oracle(node_format):
     assert np.array_equal(gt[px][same & hit], ot[same & hit])
     assert np.array_equal(gn[px][same & hit], on[same & hit])
     assert np.any(oi > 0)
+
+
+def _stats_arrays(st):
+    return (np.array(st["rays"], np.int64), np.array(st["node_visits"], np.int64),
+            np.array(st["prim_tests"], np.int64))
+
+
+@pytest.mark.parametrize("node_format", [npt.NODES_FP16_EXTENT, npt.NODES_FP32])
+def test_visit_counting_build_leaves_the_image_unchanged(sky_map, node_format):
+    # the counting build of the extend kernel (count_visits) traces the same
+    # rays as the timed one: the image is bit-identical, every ray fetches at
+    # least the root, and a node visit opens at most four leaves of at most
+    # max_leaf primitives
+    scene = small_instanced_scene()
+    ctx = make_ctx(scene, env=sky_map, max_leaf=2, lds_levels=0, node_format=node_format)
+    try:
+        npt.npt_set_env_mode(ctx, npt.ENV_MAP)
+        a = gpu_render(ctx, 96, 54, 4, 6, 17)
+        npt.npt_set_render_options(ctx, count_visits=1)
+        b = gpu_render(ctx, 96, 54, 4, 6, 17)
+        rays, nv, pt = _stats_arrays(npt.npt_get_stats(ctx))
+    finally:
+        npt.npt_destroy(ctx)
+    assert np.array_equal(a, b)
+    assert rays[0] == 96 * 54 * 4
+    live = rays > 0
+    assert np.all(nv[live] >= rays[live]) and np.all(pt[live] <= 4 * 2 * nv[live])
+    assert np.all(nv[~live] == 0) and np.all(pt[~live] == 0)
+    print("node visits per ray", nv[live] / rays[live], "primitive tests per ray", pt[live] / rays[live])
+
+
+def test_visit_counts_of_a_one_triangle_scene_are_exact():
+    # one triangle under the whole view: the tree is a root with one leaf
+    # child, so every primary ray fetches exactly one node and tests exactly
+    # one primitive
+    v = np.array([[-100.0, 0.0, -100.0], [100.0, 0.0, -100.0], [0.0, 0.0, 200.0]], np.float32)
+    scene = {"verts": v, "tris": np.array([[0, 2, 1]], np.uint32), "tri_mat": np.zeros(1, np.uint32),
+             "materials": [synth._mat(synth.LAMBERT, (0.5, 0.5, 0.5))],
+             "camera": {"eye": (0.0, 2.0, 0.0), "look_at": (0.0, 0.0, 1.0), "up": (0.0, 1.0, 0.0),
+                        "vfov_deg": 40.0}}
+    for fmt in (npt.NODES_FP16_EXTENT, npt.NODES_FP32):
+        ctx = make_ctx(scene, max_leaf=2, lds_levels=0, node_format=fmt)
+        try:
+            npt.npt_set_render_options(ctx, count_visits=1)
+            gpu_render(ctx, 64, 48, 2, 1, 5)
+            rays, nv, pt = _stats_arrays(npt.npt_get_stats(ctx))
+            gp, gi, _, _ = gpu_primary(ctx, 64, 48, 0, 5)
+        finally:
+            npt.npt_destroy(ctx)
+        assert np.all(gp == 0)  # every primary ray hits the triangle
+        assert rays[0] == 64 * 48 * 2 and nv[0] == rays[0] and pt[0] == rays[0]
+        assert np.all(rays[1:] == 0)
