@@ -207,6 +207,10 @@ __device__ __forceinline__ void test_leaf(const SceneView& sc, const RayFrame& f
   for (uint32_t i = 0; i < count; ++i) {
     const float4* s = sc.slots + 3 * (size_t)(first + i);
     const float4 s0 = s[0], s1 = s[1], s2 = s[2];
+    // three whole 16-byte rows: split into the fields each primitive kind
+    // uses, they would take five loads through the texture path instead
+    __asm__ volatile("" : : "v"(s0.x), "v"(s0.y), "v"(s0.z), "v"(s0.w), "v"(s1.x), "v"(s1.y), "v"(s1.z),
+                     "v"(s1.w), "v"(s2.x), "v"(s2.y), "v"(s2.z), "v"(s2.w));
     const uint32_t prim = __float_as_uint(s0.w);
     float t = 0.0f;
     bool hit;
