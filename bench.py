@@ -77,9 +77,9 @@ def _parse():
     p.add_argument("--calibrate-copy", action="store_true",
                    help="run one 1 GiB device copy (rocprof counter calibration)")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
-    p.add_argument("--node-format", choices=("fp32", "fp16-extent", "q8"), default="fp16-extent",
+    p.add_argument("--node-format", choices=("fp32", "fp16-extent", "q8", "fp16-corner"), default="fp16-corner",
                    help="BVH4 node encoding: FP32 boxes (112 B), FP32 lower planes + binary16 extents (96 B), "
-                        "or 8-bit planes on a per-node step (64 B)")
+                        "8-bit planes on a per-node step (64 B), or binary16 planes on an FP32 node corner (80 B)")
     p.add_argument("--max-leaf", type=int, default=2, help="primitives per BVH leaf (1..8)")
     p.add_argument("--sort-rays", type=int, default=0,
                    help="1: sort every 1024-ray chunk of the secondary queues (direction octant, origin) before tracing")
@@ -620,14 +620,16 @@ def main():
     try:
         t0 = time.perf_counter()
         # 4-wide BVH, leaf size 2, no LDS-staged levels: fastest in the sweep
-        fmt_code = {"fp32": npt.NODES_FP32, "fp16-extent": npt.NODES_FP16_EXTENT, "q8": npt.NODES_Q8}[args.node_format]
+        fmt_code = {"fp32": npt.NODES_FP32, "fp16-extent": npt.NODES_FP16_EXTENT, "q8": npt.NODES_Q8,
+                    "fp16-corner": npt.NODES_FP16_CORNER}[args.node_format]
         npt.npt_load_scene(ctx, scene, max_leaf=args.max_leaf, lds_levels=args.lds_levels, width=4,
                            node_format=fmt_code)
         extra["bvh_build_ms"] = 1e3 * (time.perf_counter() - t0)
         _stage(f"scene and BVH ready ({extra['bvh_build_ms']:.0f} ms build)")
         extra["bvh"] = {**npt.npt_bvh_info(ctx), "node_format": args.node_format, "lds_levels": args.lds_levels,
                         "max_leaf": args.max_leaf, "sort_rays": args.sort_rays,
-                        "node_bytes": {"fp32": B_NODE[4], "fp16-extent": 96, "q8": 64}[args.node_format]}
+                        "node_bytes": {"fp32": B_NODE[4], "fp16-extent": 96, "q8": 64,
+                                       "fp16-corner": 80}[args.node_format]}
         del scene
         npt.npt_env_upload(ctx, env)
         npt.npt_nif_upload(ctx, synth.nif_init(3))

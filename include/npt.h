@@ -79,16 +79,23 @@ typedef struct {
  * lds_levels: top tree levels staged in LDS by the traversal kernel (0..8,
  * 0 = none; of an instanced scene: levels of its top tree); width:
  * children per node, 2 (the paper's BVH2) or 4 (the binary SAH tree
- * collapsed to 4-wide nodes), 0 = 4.  node_format (width 4; Q8 with
- * lds_levels 0): NPT_NODES_FP32 (112-byte nodes, FP32 boxes) or
+ * collapsed to 4-wide nodes), 0 = 4.  node_format (width 4; Q8 and
+ * FP16_CORNER with lds_levels 0): NPT_NODES_FP32 (112-byte nodes, FP32
+ * boxes) or
  * NPT_NODES_FP16_EXTENT (96-byte nodes: FP32 lower planes and binary16
  * extents rounded up so that the FP32 sum lo + ext covers the box, after
  * Sec. 3.1.4; NPT_E_UNSUPPORTED if an extent exceeds 65504) or NPT_NODES_Q8
  * (64-byte nodes: per node and axis an FP32 origin and a power-of-two step,
- * 8-bit child planes rounded outward, after Ylitie et al. 2017). */
+ * 8-bit child planes rounded outward, after Ylitie et al. 2017) or
+ * NPT_NODES_FP16_CORNER (80-byte nodes: per node and axis an FP32 corner,
+ * the children's lower and upper planes as binary16 offsets from it, rounded
+ * outward so that the FP32 sum corner + offset covers the box: the relative
+ * coordinates of Sec. 3.1.4 for both planes; NPT_E_UNSUPPORTED if a node
+ * spans more than 65504 on an axis). */
 #define NPT_NODES_FP32 0
 #define NPT_NODES_FP16_EXTENT 1
 #define NPT_NODES_Q8 2
+#define NPT_NODES_FP16_CORNER 3
 typedef struct {
     uint32_t bins;
     uint32_t max_leaf;

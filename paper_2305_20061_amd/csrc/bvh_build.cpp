@@ -404,6 +404,14 @@ float half_value(uint16_t h) {
 
 uint16_t half_next(uint16_t h) { return (uint16_t)(h + 1); }  // next larger non-negative binary16
 
+// largest binary16 value <= v (v >= 0, finite, at most 65504), as bits
+uint16_t half_down(double v) {
+  uint16_t h = 0;
+  if (!half_up(v, h)) return 0x7BFF;  // 65504
+  while (h > 0 && (double)half_value(h) > v) --h;
+  return h;
+}
+
 }  // namespace
 
 bool compress_half_extents(FlatBvh& b, std::string& err) {
@@ -540,6 +548,73 @@ bool compress_q8_nodes(FlatBvh& b, std::string& err) {
   }
   b.nodes = std::move(out);
   b.node_float4s = kNode4Q8Float4s;
+  return true;
+}
+
+bool compress_corner_nodes(FlatBvh& b, std::string& err) {
+  if (b.width != 4 || b.node_float4s != kNode4Float4s) {
+    err = "corner nodes need 4-wide FP32 nodes";
+    return false;
+  }
+  const size_t nn = b.nodes.size() / kNode4Float4s;
+  std::vector<float4> out(nn * kNode4CornerFloat4s);
+  // one node; false when a plane offset does not fit binary16
+  auto node = [&](size_t i) -> bool {
+    const float4* o = &b.nodes[i * kNode4Float4s];
+    float4* h = &out[i * kNode4CornerFloat4s];
+    const uint32_t r4[4] = {ubits(o[6].x), ubits(o[6].y), ubits(o[6].z), ubits(o[6].w)};
+    float corner[3];
+    uint32_t words[3][4];
+    for (int a = 0; a < 3; ++a) {
+      const float l4[4] = {o[2 * a].x, o[2 * a].y, o[2 * a].z, o[2 * a].w};
+      const float h4[4] = {o[2 * a + 1].x, o[2 * a + 1].y, o[2 * a + 1].z, o[2 * a + 1].w};
+      float c0 = INFINITY;
+      for (int c = 0; c < 4; ++c)
+        if (r4[c] != kEmptyChild) c0 = std::min(c0, l4[c]);
+      if (!(c0 < INFINITY)) return false;
+      corner[a] = c0;
+      uint16_t qlo[4], qhi[4];
+      for (int c = 0; c < 4; ++c) {
+        if (r4[c] == kEmptyChild) {
+          qlo[c] = 0x7C00;  // +inf
+          qhi[c] = 0;
+          continue;
+        }
+        // the traversal forms each plane as the FP32 sum corner + q
+        uint16_t lo = half_down((double)l4[c] - (double)c0);
+        while (lo > 0 && c0 + half_value(lo) > l4[c]) --lo;
+        if (c0 + half_value(lo) > l4[c]) return false;
+        uint16_t hi;
+        if (!half_up((double)h4[c] - (double)c0, hi)) return false;
+        while (c0 + half_value(hi) < h4[c]) {
+          hi = half_next(hi);
+          if (((hi >> 10) & 31) == 31) return false;
+        }
+        qlo[c] = lo;
+        qhi[c] = hi;
+      }
+      words[a][0] = (uint32_t)qlo[0] | ((uint32_t)qlo[1] << 16);
+      words[a][1] = (uint32_t)qlo[2] | ((uint32_t)qlo[3] << 16);
+      words[a][2] = (uint32_t)qhi[0] | ((uint32_t)qhi[1] << 16);
+      words[a][3] = (uint32_t)qhi[2] | ((uint32_t)qhi[3] << 16);
+    }
+    h[0] = make_float4(corner[0], corner[1], corner[2], 0.0f);
+    for (int a = 0; a < 3; ++a)
+      h[1 + a] = make_float4(bits(words[a][0]), bits(words[a][1]), bits(words[a][2]), bits(words[a][3]));
+    h[4] = o[6];
+    return true;
+  };
+  std::atomic<bool> bad{false};
+  parallel_ranges(nn, [&](uint64_t i0, uint64_t i1) {
+    for (uint64_t i = i0; i < i1; ++i)
+      if (!node(i)) bad = true;
+  });
+  if (bad) {
+    err = "binary16 corner nodes: a node spans more than 65504";
+    return false;
+  }
+  b.nodes = std::move(out);
+  b.node_float4s = kNode4CornerFloat4s;
   return true;
 }
 

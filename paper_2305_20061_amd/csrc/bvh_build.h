@@ -71,6 +71,13 @@ bool compress_half_extents(FlatBvh& b, std::string& err);
 // layout), each decoded plane rounded outward and checked in FP32.
 bool compress_q8_nodes(FlatBvh& b, std::string& err);
 
+// Rewrites the 7-row FP32 nodes of a 4-wide tree (one- or two-level) as
+// 5-row nodes with binary16 planes on an FP32 corner (npt_shared.h layout):
+// each lower plane the largest and each upper plane the smallest binary16
+// offset whose FP32 sum with the corner still contains the child's box.
+// Fails where a node spans more than 65504 on an axis.
+bool compress_corner_nodes(FlatBvh& b, std::string& err);
+
 // One object of a two-level scene: bottom tree `tree` placed in the world at
 // translate + scale * x (scale > 0), hits reported with instance id `id`.
 struct Placement {

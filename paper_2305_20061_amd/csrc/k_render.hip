@@ -151,6 +151,7 @@ struct RayFrame {
   float ox_f, oy_f, oz_f;  // and of the exit planes
   uint32_t near_x, near_y, near_z;
   uint32_t wx, wy, wz;  // binary16 pair per axis: entry-plane weight (low), exit-plane weight (high)
+  uint32_t mx, my, mz;  // all ones where the direction component is >= 0
 };
 
 constexpr float kSlabSlack = 1.0f + 0x1p-20f;
@@ -178,6 +179,9 @@ __device__ __forceinline__ RayFrame make_frame(V3 o, V3 d) {
   f.wx = f.ix >= 0.0f ? 0x3C000000u : 0x00003C00u;
   f.wy = f.iy >= 0.0f ? 0x3C000000u : 0x00003C00u;
   f.wz = f.iz >= 0.0f ? 0x3C000000u : 0x00003C00u;
+  f.mx = f.ix >= 0.0f ? ~0u : 0u;
+  f.my = f.iy >= 0.0f ? ~0u : 0u;
+  f.mz = f.iz >= 0.0f ? ~0u : 0u;
   return f;
 }
 
@@ -332,6 +336,58 @@ __device__ __forceinline__ bool visit4h(const char* base, uint32_t off, const Ra
   return true;
 }
 
+// One 4-wide node with binary16 planes on an FP32 corner (kNode4CornerFloat4s
+// layout): a plane is the FP32 sum corner + q, formed by one mixed-precision
+// FMA exactly as the builder checked it.  The entry-plane and exit-plane
+// words of an axis (lower planes where the direction is >= 0, else upper)
+// are picked per ray with the frame's masks, one bit-select per word.
+// Empty children (lo = +inf, hi = 0) miss on any direction.
+template <class S>
+__device__ __forceinline__ bool visit4c(const char* base, uint32_t off, const RayFrame& f, float lim, S& st,
+                                        int& sp, uint32_t& ref) {
+  const float4 cn = *reinterpret_cast<const float4*>(base + off);
+  const uint4 qx = *reinterpret_cast<const uint4*>(base + off + 16u);
+  const uint4 qy = *reinterpret_cast<const uint4*>(base + off + 32u);
+  const uint4 qz = *reinterpret_cast<const uint4*>(base + off + 48u);
+  const float4 rf = *reinterpret_cast<const float4*>(base + off + 64u);
+  uint32_t r0 = __float_as_uint(rf.x), r1 = __float_as_uint(rf.y), r2 = __float_as_uint(rf.z),
+           r3 = __float_as_uint(rf.w);
+  auto pick = [](uint32_t m, uint32_t a, uint32_t b) { return (a & m) | (b & ~m); };
+  const uint32_t nx01 = pick(f.mx, qx.x, qx.z), nx23 = pick(f.mx, qx.y, qx.w);
+  const uint32_t fx01 = pick(f.mx, qx.z, qx.x), fx23 = pick(f.mx, qx.w, qx.y);
+  const uint32_t ny01 = pick(f.my, qy.x, qy.z), ny23 = pick(f.my, qy.y, qy.w);
+  const uint32_t fy01 = pick(f.my, qy.z, qy.x), fy23 = pick(f.my, qy.w, qy.y);
+  const uint32_t nz01 = pick(f.mz, qz.x, qz.z), nz23 = pick(f.mz, qz.y, qz.w);
+  const uint32_t fz01 = pick(f.mz, qz.z, qz.x), fz23 = pick(f.mz, qz.w, qz.y);
+  auto lo16 = [](uint32_t v) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(v & 0xFFFFu)); };
+  auto hi16 = [](uint32_t v) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(v >> 16)); };
+  // 1.0 in a scalar register the compiler cannot see through: an FMA by a
+  // known 1.0 would become a conversion and an add, two instructions where
+  // v_fma_mix_f32 reads the binary16 operand directly
+  float one = 1.0f;
+  __asm__("" : "+s"(one));
+  auto plane = [one](float q, float c) { return __builtin_fmaf(q, one, c); };
+  auto child = [&](float nx, float fx, float ny, float fy, float nz, float fz) {
+    return child_entry(f, plane(nx, cn.x), plane(fx, cn.x), plane(ny, cn.y), plane(fy, cn.y), plane(nz, cn.z),
+                       plane(fz, cn.z), lim);
+  };
+  float k0 = child(lo16(nx01), lo16(fx01), lo16(ny01), lo16(fy01), lo16(nz01), lo16(fz01));
+  float k1 = child(hi16(nx01), hi16(fx01), hi16(ny01), hi16(fy01), hi16(nz01), hi16(fz01));
+  float k2 = child(lo16(nx23), lo16(fx23), lo16(ny23), lo16(fy23), lo16(nz23), lo16(fz23));
+  float k3 = child(hi16(nx23), hi16(fx23), hi16(ny23), hi16(fy23), hi16(nz23), hi16(fz23));
+  order2(k0, r0, k1, r1);
+  order2(k2, r2, k3, r3);
+  order2(k0, r0, k2, r2);
+  order2(k1, r1, k3, r3);
+  order2(k1, r1, k2, r2);
+  __asm__ volatile("" : : "v"(r0), "v"(r1), "v"(r2), "v"(r3));
+  const float inf = __builtin_inff();
+  if (!(k0 < inf)) return false;
+  st.push3(sp, r3, k3 < inf, r2, k2 < inf, r1, k1 < inf);
+  ref = r0;
+  return true;
+}
+
 // One 4-wide node with 8-bit child planes (kNode4Q8Float4s layout): per
 // axis the entry and exit plane words are chosen once per ray from the
 // direction sign, and child c's plane is fma(q_c, 2^e, origin), the FP32
@@ -380,17 +436,20 @@ __device__ __forceinline__ bool visit4q(const char* base, uint32_t off, const Ra
 
 // Tree kinds of the traversal (the kWidth template argument): widths 2 and
 // 4 of one-level trees, the instanced (two-level, 4-wide) traversal, and
-// the 4-wide kinds with binary16-extent nodes.
+// the 4-wide kinds with binary16-extent, 8-bit and binary16-corner nodes.
 constexpr int kTwoLevel = 1;
 constexpr int kTwoLevelHalf = 3;
 constexpr int kHalf4 = 5;
 constexpr int kQ84 = 6;
 constexpr int kTwoLevelQ8 = 7;
+constexpr int kCorner4 = 8;
+constexpr int kTwoLevelCorner = 9;
 __host__ __device__ constexpr bool is_two_level(int w) {
-  return w == kTwoLevel || w == kTwoLevelHalf || w == kTwoLevelQ8;
+  return w == kTwoLevel || w == kTwoLevelHalf || w == kTwoLevelQ8 || w == kTwoLevelCorner;
 }
 __host__ __device__ constexpr bool half_nodes(int w) { return w == kHalf4 || w == kTwoLevelHalf; }
 __host__ __device__ constexpr bool q8_nodes(int w) { return w == kQ84 || w == kTwoLevelQ8; }
+__host__ __device__ constexpr bool corner_nodes(int w) { return w == kCorner4 || w == kTwoLevelCorner; }
 
 // The world ray of a two-level traversal waits in LDS (six values per lane,
 // stride kStride) rather than in registers: it is needed only when an
@@ -543,6 +602,9 @@ __device__ __forceinline__ bool trav_node(const SceneView& sc, const float4* lds
   } else if constexpr (q8_nodes(kWidth)) {
     const uint32_t off = tv.ref * (kNode4Q8Float4s * 16u);
     if (visit4q(reinterpret_cast<const char*>(sc.nodes), off, tv.f, lim, st, tv.sp, tv.ref)) return true;
+  } else if constexpr (corner_nodes(kWidth)) {
+    const uint32_t off = tv.ref * (kNode4CornerFloat4s * 16u);  // node arrays stay below 4 GiB
+    if (visit4c(reinterpret_cast<const char*>(sc.nodes), off, tv.f, lim, st, tv.sp, tv.ref)) return true;
   } else {
     bool entered;
     const uint32_t off = tv.ref * (kNode4Float4s * 16u);  // node arrays stay below 4 GiB
@@ -1124,7 +1186,12 @@ hipError_t launch_extend(int stack_depth, const SceneView& sc, uint32_t depth, u
   // node formats of 4-wide trees (a binary node is also four float4 long)
   const bool half = sc.width == 4 && sc.node_float4s == kNode4HalfFloat4s;
   const bool q8 = sc.width == 4 && sc.node_float4s == kNode4Q8Float4s;
-  if (sc.two_level && half) {
+  const bool corner = sc.width == 4 && sc.node_float4s == kNode4CornerFloat4s;
+  if (sc.two_level && corner) {
+    NPT_LAUNCH_EXTEND_S(kTwoLevelCorner, false)
+  } else if (corner) {
+    NPT_LAUNCH_EXTEND_S(kCorner4, false)
+  } else if (sc.two_level && half) {
     if (staged) {
       NPT_LAUNCH_EXTEND_S(kTwoLevelHalf, true)
     } else {
@@ -1218,7 +1285,12 @@ hipError_t launch_trace_primary(int stack_depth, const SceneView& sc, const Came
   // node formats of 4-wide trees (a binary node is also four float4 long)
   const bool half = sc.width == 4 && sc.node_float4s == kNode4HalfFloat4s;
   const bool q8 = sc.width == 4 && sc.node_float4s == kNode4Q8Float4s;
-  if (sc.two_level && half) {
+  const bool corner = sc.width == 4 && sc.node_float4s == kNode4CornerFloat4s;
+  if (sc.two_level && corner) {
+    NPT_LAUNCH_PRIMARY_S(kTwoLevelCorner)
+  } else if (corner) {
+    NPT_LAUNCH_PRIMARY_S(kCorner4)
+  } else if (sc.two_level && half) {
     NPT_LAUNCH_PRIMARY_S(kTwoLevelHalf)
   } else if (sc.two_level && q8) {
     NPT_LAUNCH_PRIMARY_S(kTwoLevelQ8)

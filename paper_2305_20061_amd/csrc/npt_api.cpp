@@ -416,12 +416,13 @@ extern "C" int npt_build_bvh(npt_ctx* c, const npt_bvh_params* p, void* stream) 
     const uint32_t node_format = p ? p->node_format : NPT_NODES_FP32;
     const BuildThreads threads(p ? (int)std::min<uint32_t>(p->threads, 64) : 0);
     if (width != 2 && width != 4) return fail(c, NPT_E_INVALID_ARG, "BVH width must be 2 or 4");
-    if (node_format != NPT_NODES_FP32 && node_format != NPT_NODES_FP16_EXTENT && node_format != NPT_NODES_Q8)
+    if (node_format != NPT_NODES_FP32 && node_format != NPT_NODES_FP16_EXTENT && node_format != NPT_NODES_Q8 &&
+        node_format != NPT_NODES_FP16_CORNER)
       return fail(c, NPT_E_INVALID_ARG, "unknown BVH node format");
     if (node_format != NPT_NODES_FP32 && width != 4)
       return fail(c, NPT_E_INVALID_ARG, "compressed nodes need width 4");
-    if (node_format == NPT_NODES_Q8 && lds_levels != 0)
-      return fail(c, NPT_E_INVALID_ARG, "8-bit nodes are read from memory: lds_levels must be 0");
+    if ((node_format == NPT_NODES_Q8 || node_format == NPT_NODES_FP16_CORNER) && lds_levels != 0)
+      return fail(c, NPT_E_INVALID_ARG, "8-bit and binary16-corner nodes are read from memory: lds_levels must be 0");
     if (bins < 4 || bins > 256 || max_leaf < 1 || max_leaf > kMaxLeaf || lds_levels > 8)
       return fail(c, NPT_E_INVALID_ARG, "bvh params out of range");
     const bool has_base = !c->tris.empty() || !c->spheres.empty();
@@ -492,6 +493,7 @@ extern "C" int npt_build_bvh(npt_ctx* c, const npt_bvh_params* p, void* stream) 
     }
     if (node_format == NPT_NODES_FP16_EXTENT && !compress_half_extents(b, e)) return fail(c, NPT_E_UNSUPPORTED, e);
     if (node_format == NPT_NODES_Q8 && !compress_q8_nodes(b, e)) return fail(c, NPT_E_UNSUPPORTED, e);
+    if (node_format == NPT_NODES_FP16_CORNER && !compress_corner_nodes(b, e)) return fail(c, NPT_E_UNSUPPORTED, e);
     if (trace_stack_size(stack_need) == 0)
       return fail(c, NPT_E_UNSUPPORTED, "BVH deeper than the 128-entry traversal stack");
     // the traversal addresses nodes with 32-bit byte offsets

@@ -44,6 +44,17 @@ constexpr uint32_t kNode4HalfFloat4s = 6;
 // FP32 sums; empty children have qlo = 255, qhi = 0 and ref kEmptyChild.
 constexpr uint32_t kNode4Q8Float4s = 4;
 
+// BVH4 node with binary16 planes on an FP32 corner, 80 bytes:
+//   c0 = (corner.x, corner.y, corner.z, -): the smallest lower plane of the
+//        node's children on each axis
+//   c1 = x planes: (lo of children 0,1 | 2,3, hi of children 0,1 | 2,3) as
+//        binary16 pairs (child 2k in the low half); c2 = y, c3 = z likewise
+//   c4 = (ref0, ref1, ref2, ref3)
+// A plane is the FP32 sum corner + q (one rounding); the builder rounds q
+// down for lower and up for upper planes and checks the sums.  Empty
+// children have lo = +inf and hi = 0 (a box that no ray enters).
+constexpr uint32_t kNode4CornerFloat4s = 5;
+
 // Primitive slot, 48 bytes, leaf order:
 //   triangle: s0 = (v0, prim id), s1 = (v1, material), s2 = (v2, kPrimTriangle)
 //   sphere:   s0 = (centre, prim id), s1 = (radius, 0, 0, material), s2 = (0, 0, 0, kPrimSphere)

@@ -24,7 +24,7 @@ ERRORS = {-1: "INVALID_ARG", -2: "NO_SCENE", -3: "NO_ENV", -4: "OOM", -5: "HIP",
 NPT_E = {v: k for k, v in ERRORS.items()}
 LAMBERT, MIRROR, DIELECTRIC, EMITTER = 0, 1, 2, 3
 ENV_MAP, ENV_NIF, ENV_NONE = 0, 1, 2
-NODES_FP32, NODES_FP16_EXTENT, NODES_Q8 = 0, 1, 2
+NODES_FP32, NODES_FP16_EXTENT, NODES_Q8, NODES_FP16_CORNER = 0, 1, 2, 3
 COLOUR_YUV, COLOUR_RGB, COLOUR_YCOCG = 0, 1, 2
 FP32, FP16, BF16, FP8 = 0, 1, 2, 3
 MAX_DEPTH = 64
@@ -438,6 +438,6 @@ def npt_load_scene(ctx, scene: dict, bins=32, max_leaf=4, lds_levels=6, stream=N
         npt_scene_instances(ctx, scene["instances"])
     cam = scene["camera"]
     npt_set_camera(ctx, cam["eye"], cam["look_at"], cam["up"], cam["vfov_deg"])
-    if node_format == NODES_Q8 or (scene.get("instances") and node_format != NODES_FP16_EXTENT):
+    if node_format in (NODES_Q8, NODES_FP16_CORNER) or (scene.get("instances") and node_format != NODES_FP16_EXTENT):
         lds_levels = 0  # LDS staging: FP32 one-level trees and binary16-extent trees only
     npt_build_bvh(ctx, bins, max_leaf, lds_levels, stream, width, node_format, threads)

@@ -27,7 +27,8 @@ def _export(scene_fn, threads, **kw):
         npt.npt_destroy(c)
 
 
-@pytest.mark.parametrize("width,fmt", [(4, npt.NODES_FP32), (4, npt.NODES_FP16_EXTENT), (2, npt.NODES_FP32)])
+@pytest.mark.parametrize("width,fmt", [(4, npt.NODES_FP32), (4, npt.NODES_FP16_EXTENT), (4, npt.NODES_FP16_CORNER),
+                                       (2, npt.NODES_FP32)])
 def test_threaded_build_equals_single_threaded(width, fmt):
     v, t = _soup(300_000)  # subtrees of >= 100k primitives get their own threads
 

@@ -1,5 +1,6 @@
 """Compressed BVH4 nodes: binary16 extents (Sec. 3.1.4's FP16-extent
-proposal) and 8-bit child planes on a power-of-two step.  Either way the
+proposal), 8-bit child planes on a power-of-two step, and binary16 planes on
+an FP32 node corner.  Every way the
 decoded planes are FP32 values the builder keeps outside the true boxes, so
 the traversal may visit more but never drops a primitive.  The closest hit
 is defined over all primitives (ties to the lowest id), so first hits match
@@ -15,7 +16,7 @@ from gpu_util import gpu_primary, gpu_render, make_ctx, oracle_scene, rel_rmse
 from test_gpu_instancing import check_primary, small_instanced_scene
 
 pytestmark = pytest.mark.gpu
-FORMATS = [npt.NODES_FP16_EXTENT, npt.NODES_Q8]
+FORMATS = [npt.NODES_FP16_EXTENT, npt.NODES_Q8, npt.NODES_FP16_CORNER]
 
 
 @pytest.mark.parametrize("fmt", FORMATS)

@@ -85,7 +85,7 @@ def test_base_mesh_as_identity_instance_hits_the_same():
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("node_format", [npt.NODES_FP16_EXTENT, npt.NODES_FP32, npt.NODES_Q8])
+@pytest.mark.parametrize("node_format", [npt.NODES_FP16_EXTENT, npt.NODES_FP32, npt.NODES_Q8, npt.NODES_FP16_CORNER])
 def test_large_bvh_full_size_sampled_hits_match_oracle(node_format):
     # the large-BVH workload itself (2048^2 terrain, 256 instances, leaf size
     # 2 and FP16-extent nodes as benchmarked) at 1920x1080: the GPU traces
@@ -115,7 +115,7 @@ def _stats_arrays(st):
             np.array(st["prim_tests"], np.int64))
 
 
-@pytest.mark.parametrize("node_format", [npt.NODES_FP16_EXTENT, npt.NODES_FP32])
+@pytest.mark.parametrize("node_format", [npt.NODES_FP16_EXTENT, npt.NODES_FP32, npt.NODES_FP16_CORNER])
 def test_visit_counting_build_leaves_the_image_unchanged(sky_map, node_format):
     # the counting build of the extend kernel (count_visits) traces the same
     # rays as the timed one: the image is bit-identical, every ray fetches at
@@ -148,7 +148,7 @@ def test_visit_counts_of_a_one_triangle_scene_are_exact():
              "materials": [synth._mat(synth.LAMBERT, (0.5, 0.5, 0.5))],
              "camera": {"eye": (0.0, 2.0, 0.0), "look_at": (0.0, 0.0, 1.0), "up": (0.0, 1.0, 0.0),
                         "vfov_deg": 40.0}}
-    for fmt in (npt.NODES_FP16_EXTENT, npt.NODES_FP32):
+    for fmt in (npt.NODES_FP16_EXTENT, npt.NODES_FP32, npt.NODES_FP16_CORNER):
         ctx = make_ctx(scene, max_leaf=2, lds_levels=0, node_format=fmt)
         try:
             npt.npt_set_render_options(ctx, count_visits=1)

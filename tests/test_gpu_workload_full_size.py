@@ -1,7 +1,7 @@
 """The benchmarked workload at its full size against the oracle: the large-BVH
 scene (2048^2-vertex terrain plus 256 instanced displaced icospheres) at
 1920x1080, 64 samples per pixel, depth 8, roulette from depth 3, BVH4 with
-binary16-extent nodes and leaf size 2, lit by the HDR-NIF trained on the
+binary16-corner nodes and leaf size 2, lit by the HDR-NIF trained on the
 device and run with FP8 operands.  The GPU renders the whole frame in the
 benchmark's launch configuration; the oracle traces two full rows (3,840
 pixels, 245,760 path samples) with the same dequantised weights.  Likewise
@@ -27,7 +27,7 @@ def test_large_bvh_fp8_nif_full_size_rows_match_oracle():
     scene = synth.scene_for(4)
     ctx = npt.npt_create(0)
     try:
-        npt.npt_load_scene(ctx, scene, max_leaf=2, lds_levels=0, width=4, node_format=npt.NODES_FP16_EXTENT)
+        npt.npt_load_scene(ctx, scene, max_leaf=2, lds_levels=0, width=4, node_format=npt.NODES_FP16_CORNER)
         npt.npt_env_upload(ctx, synth.env_map())
         npt.npt_nif_upload(ctx, synth.nif_init(3))
         npt.npt_nif_train(ctx, npt.train_params(batch=65536, samples=1 << 24, seed=1, grad_prec=npt.FP16))
