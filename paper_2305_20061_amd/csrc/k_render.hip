@@ -91,17 +91,18 @@ struct LaneStack {
     }
     ++sp;
   }
-  // r3, r2, r1 in this order, each only if its flag is set; while three
-  // entries fit in LDS the stores are unconditional and only sp depends on
-  // the flags (a store above the final top is dead)
+  // r3, r2, r1 in this order, each only if its flag is set, where the
+  // flags are a prefix (h3 implies h2 implies h1: the entered children of a
+  // sorted node).  While three entries fit in LDS, slots sp, sp + 1, sp + 2
+  // are written unconditionally from one address (immediate offsets; a
+  // store above the final top is dead) and sp grows by the count.
   __device__ __forceinline__ void push3(int& sp, uint32_t r3, bool h3, uint32_t r2, bool h2, uint32_t r1, bool h1) {
     if (sp + 3 <= kShort) {
-      lds[sp * kStride] = r3;
-      sp += h3 ? 1 : 0;
-      lds[sp * kStride] = r2;
-      sp += h2 ? 1 : 0;
-      lds[sp * kStride] = r1;
-      sp += h1 ? 1 : 0;
+      lds_u32* p = lds + sp * kStride;
+      p[0] = h3 ? r3 : (h2 ? r2 : r1);
+      p[kStride] = h3 ? r2 : r1;
+      p[2 * kStride] = r1;
+      sp += (int)h1 + (int)h2 + (int)h3;
     } else {
       if (h3) push(sp, r3);
       if (h2) push(sp, r2);
@@ -603,7 +604,12 @@ __device__ __forceinline__ bool trav_node(const SceneView& sc, const float4* lds
     const uint32_t off = tv.ref * (kNode4Q8Float4s * 16u);
     if (visit4q(reinterpret_cast<const char*>(sc.nodes), off, tv.f, lim, st, tv.sp, tv.ref)) return true;
   } else if constexpr (corner_nodes(kWidth)) {
-    const uint32_t off = tv.ref * (kNode4CornerFloat4s * 16u);  // node arrays stay below 4 GiB
+    // ref * 80 (node arrays stay below 4 GiB) as ((ref << 2) + ref) << 4: two
+    // full-rate instructions instead of a quarter-rate 32-bit multiply
+    static_assert(kNode4CornerFloat4s * 16u == 80u, "binary16-corner nodes are 80 bytes");
+    uint32_t four = tv.ref << 2;
+    __asm__("" : "+v"(four));  // keeps the compiler from folding this back into a multiply
+    const uint32_t off = (four + tv.ref) << 4;
     if (visit4c(reinterpret_cast<const char*>(sc.nodes), off, tv.f, lim, st, tv.sp, tv.ref)) return true;
   } else {
     bool entered;
