@@ -658,6 +658,10 @@ __device__ __forceinline__ Hit trace_closest(const SceneView& sc, const float4* 
 __device__ __forceinline__ V3 slot_normal(const float4* slots, uint32_t slot, V3 p, uint32_t& material) {
   const float4* s = slots + 3 * (size_t)slot;
   const float4 s0 = s[0], s1 = s[1], s2 = s[2];
+  // three whole rows (split by the fields each primitive kind uses, they
+  // would take six loads)
+  __asm__ volatile("" : : "v"(s0.x), "v"(s0.y), "v"(s0.z), "v"(s0.w), "v"(s1.x), "v"(s1.y), "v"(s1.z),
+                   "v"(s1.w), "v"(s2.x), "v"(s2.y), "v"(s2.z), "v"(s2.w));
   material = __float_as_uint(s1.w);
   if (__float_as_uint(s2.w) == kPrimTriangle) {
     const V3 p0{s0.x, s0.y, s0.z};
