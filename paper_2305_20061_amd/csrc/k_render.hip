@@ -27,6 +27,12 @@ constexpr int kRefillAt = NPT_REFILL_AT;
 #define NPT_LEAF_PERCENT 100  // leaf step once waiting leaf lanes reach this % of the lanes at inner nodes
 #endif
 constexpr uint32_t kLeafPercent = NPT_LEAF_PERCENT;
+static_assert(kLeafPercent <= 100000u, "the leaf-step rule is evaluated in 32 bits");
+
+// Lanes of the wave for which b holds, straight from the lane mask the
+// compare leaves (HIP's __ballot takes an int and turns the mask into a
+// value and back: two vector instructions more).
+__device__ __forceinline__ uint64_t lanes(bool b) { return __builtin_amdgcn_ballot_w64(b); }
 #ifndef NPT_EXTEND_WAVES
 #define NPT_EXTEND_WAVES 6  // waves per SIMD the extend kernel's register budget is set for
 #endif
@@ -768,7 +774,7 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(NPT
   bool drained = false;             // the queue has no entries left
   for (;;) {
     // hand queued rays to the idle lanes, lowest lane first
-    uint64_t idle = __ballot(!busy);
+    uint64_t idle = lanes(!busy);
     while (idle != 0 && !drained) {
       if (pool == pool_end) {
         uint32_t b = 0;
@@ -795,9 +801,9 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(NPT
         if (!busy) hits[ray] = make_float4(tv.h.t, __uint_as_float(kMiss), __uint_as_float(kMiss), 0.0f);
       }
       pool += take;
-      idle = __ballot(!busy);
+      idle = lanes(!busy);
     }
-    if (__ballot(busy) == 0) break;
+    if (lanes(busy) == 0) break;
     // advance until few lanes still traverse (none, once the queue is
     // drained).  Each wave step is either a node step (the lanes at inner
     // nodes visit them) or a leaf step (the lanes at leaves test them; the
@@ -810,11 +816,16 @@ __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(NPT
     const uint32_t floor_busy = drained ? 0u : (uint32_t)kRefillAt;
     for (;;) {
       const bool at_node = busy && (tv.ref & kLeafBit) == 0u && !needs_frame<kWidth>(tv);
-      const uint32_t nn = (uint32_t)__popcll(__ballot(at_node));
-      const uint32_t nl = (uint32_t)__popcll(__ballot(busy && !at_node));
+      uint32_t nn = (uint32_t)__popcll(lanes(at_node));
+      uint32_t nl = (uint32_t)__popcll(lanes(busy && !at_node));
+      // 32-bit scalars the compiler cannot widen again: it would compare
+      // the 64-bit popcounts on the vector unit (no scalar 64-bit ordered
+      // compare), two vector instructions per use
+      __asm__("" : "+s"(nn), "+s"(nl));
       if (nn + nl <= floor_busy) break;
       bool more = true;
-      const bool leaf_step = 100ull * nl >= (uint64_t)kLeafPercent * nn;
+      // counts of at most 64 lanes: 32-bit products, a scalar compare
+      const bool leaf_step = 100u * nl >= kLeafPercent * nn;
       // frame changes first, ahead of the leaf / node branch: the frame is
       // then rewritten in one place only, which keeps its registers in place
       const bool change = leaf_step && busy && needs_frame<kWidth>(tv);
