@@ -206,12 +206,25 @@ __global__ void k_nif_dequant(const float* master, const float* bias_tab, float*
 // ---------------------------------------------------------------------------
 // inference
 // ---------------------------------------------------------------------------
-// 8 waves (two per SIMD): the second wave hides MFMA/LDS latency.
-#ifndef NPT_NIF_WAVES
-#define NPT_NIF_WAVES 8
+// Waves per workgroup (one workgroup per CU).  The FP8 kernel for networks
+// 65 to 96 wide fits in 128 registers once its first- and output-layer
+// operands are read inside the tile loop, so NPT_NIF_WAVES_FP8 waves (four
+// per SIMD) take turns at the MFMA and VALU work of their tiles: the 16/96/5
+// network's queries run 10 % faster than with two waves per SIMD (6 % with
+// three; two tiles per wave at two waves per SIMD gain nothing).  The others
+// need more registers (the 64-wide FP8 kernel would spill at four waves per
+// SIMD; FP16 with one tile per wave at four waves per SIMD is no faster than
+// two tiles at two) and run two waves per SIMD, the second one hiding MFMA /
+// LDS latency.
+#ifndef NPT_NIF_WAVES_FP8
+#define NPT_NIF_WAVES_FP8 16
 #endif
-constexpr int kNifWaves = NPT_NIF_WAVES;
-
+template <int P, class A>
+constexpr int nif_waves() {
+  return P == NPT_FP8 && A::kHidden > 64 && A::kHidden <= 96 ? NPT_NIF_WAVES_FP8 : 8;
+}
+static_assert(NPT_NIF_WAVES_FP8 % 4 == 0 && NPT_NIF_WAVES_FP8 >= 4 && NPT_NIF_WAVES_FP8 <= 16,
+              "whole waves per SIMD, at most 1024 threads");
 
 // 32-ray column tiles per wave: two for FP16 / BF16 operands on networks 65
 // to 96 wide (each weight fragment read from LDS feeds two MFMAs: 16/96/5
@@ -222,7 +235,6 @@ template <int P, class A>
 constexpr int nif_tiles() {
   return (P == NPT_FP16 || P == NPT_BF16) && A::kHidden > 64 && A::kHidden <= 96 ? 2 : 1;
 }
-constexpr int kNifBlock = 64 * kNifWaves;
 
 enum : int { kSrcQueue = 0, kSrcDirs = 1, kSrcGrid = 2 };
 
@@ -286,7 +298,8 @@ __device__ __forceinline__ void relu_to_e4m3(const f32x16 (&acc)[NT][A::kMB], i3
 }
 
 template <int P, class A>
-__global__ __launch_bounds__(kNifBlock, 1) void k_nif_infer(const uint8_t* gpack, const float* gbias, NifIO io) {
+__global__ __launch_bounds__((64 * nif_waves<P, A>()), 1) void k_nif_infer(const uint8_t* gpack, const float* gbias,
+                                                                           NifIO io) {
   constexpr int KPL = Prec<P>::KPL;
   using G = Geometry<KPL, A>;
   using K = Pack<P, A>;
@@ -295,6 +308,7 @@ __global__ __launch_bounds__(kNifBlock, 1) void k_nif_infer(const uint8_t* gpack
   constexpr bool kAccurate = (P == NPT_FP32);
   constexpr int NT = nif_tiles<P, A>();
   constexpr int kRays = 32 * NT;
+  constexpr int kNifWaves = nif_waves<P, A>(), kNifBlock = 64 * kNifWaves;
   extern __shared__ float4 smem4[];
   uint8_t* lds = reinterpret_cast<uint8_t*>(smem4);
   float* lbias = reinterpret_cast<float*>(lds + K::lds_offset(L + 1));
@@ -346,14 +360,15 @@ __global__ __launch_bounds__(kNifBlock, 1) void k_nif_infer(const uint8_t* gpack
   const uint64_t waves_total = (uint64_t)gridDim.x * kNifWaves;
 
   for (uint64_t tile = (uint64_t)blockIdx.x * kNifWaves + wave; tile * kRays < n; tile += waves_total) {
-    // Wider networks and two tiles per wave: an offset of 0 that the
-    // compiler cannot see through (tiles stay far below 2^62) keeps the first-
-    // and output-layer operands inside the tile loop; hoisted out of it, they
-    // would not fit in the registers of two waves per SIMD and would spill.
-    const int z = (H > 96 || NT > 1) ? (int)(tile >> 62) : 0;
+    // Wider networks, two tiles per wave and more than two waves per SIMD:
+    // an offset of 0 that the compiler cannot see through (tiles stay far
+    // below 2^62) keeps the first- and output-layer operands inside the tile
+    // loop; hoisted out of it, they would not fit in the registers and
+    // would spill.
+    const int z = (H > 96 || NT > 1 || kNifWaves > 8) ? (int)(tile >> 62) : 0;
     const Frag* fr0 = fr_first + z;
     const Frag* fro = fr_out + z;
-    const float* lb0 = lbias + z;
+    const float* lb0 = lbias + 4 * z;  // (4 z keeps its 16-byte alignment visible)
     float u[NT], v[NT], bx[NT], by[NT], bz[NT];
     uint32_t slot[NT];
     bool valid[NT];
@@ -591,8 +606,9 @@ hipError_t launch_nif_dequant(int arch, int prec, const float* master, const flo
   });
 }
 
-static hipError_t launch_infer(int arch, int prec, const void* frags, const float* bias, const NifIO& io, int grid,
-                               hipStream_t s) {
+// one workgroup per CU at most, and no more than the tiles of n_max rays need
+static hipError_t launch_infer(int arch, int prec, const void* frags, const float* bias, const NifIO& io,
+                               uint64_t n_max, int num_cus, hipStream_t s) {
   if (!arch_ok(arch) || !prec_ok(prec)) return hipErrorInvalidValue;
   return with_arch(arch, [&](auto a) {
     using A = decltype(a);
@@ -602,15 +618,14 @@ static hipError_t launch_infer(int arch, int prec, const void* frags, const floa
       hipError_t e = hipFuncSetAttribute((const void*)k_nif_infer<P, A>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (e != hipSuccess) return e;
-      hipLaunchKernelGGL((k_nif_infer<P, A>), dim3(grid), dim3(kNifBlock), lds, s, (const uint8_t*)frags, bias, io);
+      const uint64_t rays = (uint64_t)32 * nif_waves<P, A>() * nif_tiles<P, A>();  // per workgroup round
+      const uint64_t need = (n_max + rays - 1) / rays;
+      const int grid = (int)(need < 1 ? 1 : (need < (uint64_t)num_cus ? need : (uint64_t)num_cus));
+      hipLaunchKernelGGL((k_nif_infer<P, A>), dim3(grid), dim3(64 * nif_waves<P, A>()), lds, s,
+                         (const uint8_t*)frags, bias, io);
       return hipGetLastError();
     });
   });
-}
-
-static int nif_grid(uint64_t n, int num_cus) {
-  const uint64_t tiles = (n + 255) / 256;
-  return (int)(tiles < 1 ? 1 : (tiles > (uint64_t)num_cus ? num_cus : tiles));
 }
 
 hipError_t launch_nif_queue(int arch, int prec, const void* frags, const float* bias, const ColourMatrix& cm,
@@ -623,7 +638,7 @@ hipError_t launch_nif_queue(int arch, int prec, const void* frags, const float* 
   io.L = L;
   io.cnt = cnt;
   io.depth = depth;
-  return launch_infer(arch, prec, frags, bias, io, nif_grid(max_rays, num_cus), s);
+  return launch_infer(arch, prec, frags, bias, io, max_rays, num_cus, s);
 }
 
 hipError_t launch_nif_dirs(int arch, int prec, const void* frags, const float* bias, const ColourMatrix& cm,
@@ -634,7 +649,7 @@ hipError_t launch_nif_dirs(int arch, int prec, const void* frags, const float* b
   io.dirs = dirs;
   io.out = rgb;
   io.n = n;
-  return launch_infer(arch, prec, frags, bias, io, nif_grid(n, num_cus), s);
+  return launch_infer(arch, prec, frags, bias, io, n, num_cus, s);
 }
 
 hipError_t launch_nif_grid(int arch, int prec, const void* frags, const float* bias, const ColourMatrix& cm,
@@ -646,7 +661,7 @@ hipError_t launch_nif_grid(int arch, int prec, const void* frags, const float* b
   io.gh = gh;
   io.n = (uint64_t)gw * gh;
   io.out = zout;
-  return launch_infer(arch, prec, frags, bias, io, nif_grid(io.n, num_cus), s);
+  return launch_infer(arch, prec, frags, bias, io, io.n, num_cus, s);
 }
 
 }  // namespace npt
