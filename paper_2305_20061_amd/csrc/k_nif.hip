@@ -210,8 +210,8 @@ __global__ void k_nif_dequant(const float* master, const float* bias_tab, float*
 // 65 to 96 wide fits in 128 registers once its first- and output-layer
 // operands are read inside the tile loop, so NPT_NIF_WAVES_FP8 waves (four
 // per SIMD) take turns at the MFMA and VALU work of their tiles: the 16/96/5
-// network's queries run 10 % faster than with two waves per SIMD (6 % with
-// three; two tiles per wave at two waves per SIMD gain nothing).  The others
+// network's queries take 10 % less time than with two waves per SIMD (4-5 %
+// less with three; two tiles per wave at two waves per SIMD gain nothing).  The others
 // need more registers (the 64-wide FP8 kernel would spill at four waves per
 // SIMD; FP16 with one tile per wave at four waves per SIMD is no faster than
 // two tiles at two) and run two waves per SIMD, the second one hiding MFMA /
