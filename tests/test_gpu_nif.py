@@ -69,6 +69,42 @@ def test_nif_query_matches_oracle(prec, n):
     assert r <= QUERY_TOL[prec]
 
 
+# One more ray than 256 workgroups take in one round of the inference
+# kernel's tile loop, plus a ragged tail: 512 rays per workgroup and round in
+# FP8 (16 waves, one tile each) and FP16 / BF16 (8 waves, two tiles each),
+# 256 in FP32, so every precision wraps around the grid at least once.
+N_WRAP = 256 * 512 + 29
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_nif_query_wraps_the_grid(prec):
+    torch = torch_cuda()
+    p = _weights()
+    ctx = npt.npt_create(0)
+    try:
+        npt.npt_nif_upload(ctx, p)
+        npt.npt_nif_set_precision(ctx, prec)
+        d = _dirs(N_WRAP, seed=5)
+        dt = torch.from_numpy(d).cuda()
+        out = torch.full((N_WRAP, 3), -1.0, dtype=torch.float32, device="cuda")
+        npt.npt_env_query(ctx, npt.ENV_NIF, dt, out)
+        torch.cuda.synchronize()
+        g = out.cpu().numpy().astype(np.float64)
+    finally:
+        npt.npt_destroy(ctx)
+    assert np.all(g >= 0)  # every query written (radiance is clamped at 0; the fill is -1)
+    # sampled against the oracle: the first and last tiles, both sides of the
+    # first wrap, and a seeded spread
+    idx = np.unique(np.concatenate([np.arange(64), np.arange(N_WRAP - 96, N_WRAP),
+                                    np.arange(256 * 512 - 32, N_WRAP),
+                                    np.random.default_rng(9).integers(0, N_WRAP, 400)]))
+    ref_p = _dequant(p, prec)
+    o = np.array([O.nif_radiance_q(SHAPE, ref_p, prec, *O.dir_to_uv(d[i])) for i in idx])
+    r = rel_rmse(g[idx], o)
+    print(f"prec {prec} n {N_WRAP}: {idx.size} sampled, relRMSE {r:.3e}")
+    assert r <= QUERY_TOL[prec]
+
+
 def test_nif_render_matches_oracle_fp32(small_sky):
     scene = synth.scene_for(1)
     p = _weights()
