@@ -83,6 +83,9 @@ def _parse():
     p.add_argument("--max-leaf", type=int, default=2, help="primitives per BVH leaf (1..8)")
     p.add_argument("--sort-rays", type=int, default=0,
                    help="1: sort every 1024-ray chunk of the secondary queues (direction octant, origin) before tracing")
+    p.add_argument("--pool-paths", type=int, default=0,
+                   help="upper bound on paths in flight (0: the library default, 2^27); a frame takes "
+                        "ceil(paths / pool) passes")
     p.add_argument("--lds-levels", type=int, default=0,
                    help="top BVH levels staged in LDS per workgroup (of the two-level scene: of its top tree)")
     p.add_argument("--nif-sizes", action="store_true",
@@ -571,9 +574,10 @@ def nif_sizes(args):
                                    skip=skip)
                 npt.npt_nif_set_precision(ctx, prec)
                 npt.npt_set_env_mode(ctx, npt.ENV_NIF)
-                npt.npt_set_render_options(ctx, rr_start=3, kernel_timing=1, sort_rays=args.sort_rays)
+                npt.npt_set_render_options(ctx, rr_start=3, kernel_timing=1, sort_rays=args.sort_rays,
+                                           pool_paths=args.pool_paths)
                 el, st = _timed_renders(npt, torch, ctx, W, H, spp, depth, 1, out, 2, 1)
-                npt.npt_set_render_options(ctx, rr_start=3, sort_rays=args.sort_rays)
+                npt.npt_set_render_options(ctx, rr_start=3, sort_rays=args.sort_rays, pool_paths=args.pool_paths)
                 rows.append({"hidden": hidden, "layers": layers, "skip": skip, "features": F,
                              "path": "layered GEMMs" if layered else "LDS-resident",
                              "prec": {npt.FP16: "fp16", npt.FP8: "fp8"}[prec],
@@ -659,7 +663,8 @@ def main():
             del a, b
 
         # counting render (outside the timed region): algorithmic bytes
-        npt.npt_set_render_options(ctx, rr_start=3, count_visits=1, sort_rays=args.sort_rays)
+        npt.npt_set_render_options(ctx, rr_start=3, count_visits=1, sort_rays=args.sort_rays,
+                                   pool_paths=args.pool_paths)
         npt.npt_render(ctx, W, H, spp, depth, seed, out)
         cs = npt.npt_get_stats(ctx)
         rays = np.array(cs["rays"], np.float64)
@@ -678,7 +683,8 @@ def main():
 
         # the timed workload, with per-kernel events
         _stage("counting render done; timed renders")
-        npt.npt_set_render_options(ctx, rr_start=3, kernel_timing=1, sort_rays=args.sort_rays)
+        npt.npt_set_render_options(ctx, rr_start=3, kernel_timing=1, sort_rays=args.sort_rays,
+                                   pool_paths=args.pool_paths)
         elapsed, st = _timed_renders(npt, torch, ctx, W, H, spp, depth, seed, out, args.steps, args.warmup)
         _stage(f"timed renders done: {1e3 * elapsed / args.steps:.2f} ms per frame")
         img = {prec_name: out.cpu().numpy().astype(np.float64)}
@@ -773,7 +779,8 @@ def main():
             npt.npt_nif_upload(ctx, trained)
             npt.npt_nif_set_precision(ctx, npt.FP16)
             npt.npt_set_env_mode(ctx, npt.ENV_NIF)
-            npt.npt_set_render_options(ctx, rr_start=3, kernel_timing=1, sort_rays=args.sort_rays)
+            npt.npt_set_render_options(ctx, rr_start=3, kernel_timing=1, sort_rays=args.sort_rays,
+                                       pool_paths=args.pool_paths)
             el, s3 = _timed_renders(npt, torch, ctx, W, H, c3["spp"], c3["depth"], seed, out, args.steps, 1)
             extra["small_bvh_fp16"] = {"path_samples_per_s": W * H * c3["spp"] * args.steps / el,
                                        "ms_per_render": 1e3 * el / args.steps, "extend_ms_per_render": s3["ms_trace"],

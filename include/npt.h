@@ -183,8 +183,9 @@ typedef struct {
 
 /* Render options.  rr_start: first depth with Russian roulette (Sec. 4: 3);
  * samples_per_pass: samples traced together (0 = library default, sized
- * from the pool); pool_paths: upper bound on paths in flight (0 = 2^26,
- * 160 bytes of device queues per path);
+ * from the pool); pool_paths: upper bound on paths in flight (0 = 2^27,
+ * 160 bytes of device queues per path, allocated as far as a render needs
+ * them);
  * kernel_timing: 1 = time every extend (closest hit), shade and
  * environment launch with HIP events on the render stream
  * (npt_stats.ms_trace / ms_shade / ms_env);

